@@ -1,0 +1,374 @@
+/*
+ * oracle/sr4.c -- TEST INFRASTRUCTURE, NOT PART OF THE PRODUCT.
+ *
+ * Plain, serial, deliberately unoptimised CPU reference implementations of the
+ * integer sorts studied in Gerbessiotis, "A study of integer sorting on
+ * multicores" (arXiv 1808.10292).  Only the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg load this library; the GPU library never links
+ * it, and the two share no source, header, table or helper.
+ *
+ * Every routine is written from the paper's description, in the paper's order:
+ *
+ *   lsd_u32 / lsd_u64  Section 3.2, "Serial radix-r radix-sort: SR4": rounds of
+ *                      count-sort on lg(r)-bit digits.  Each round reads the
+ *                      input once to count digit occurrences into a count array
+ *                      of r entries, turns the counts into starting offsets,
+ *                      then reads the input a second time and writes every key
+ *                      once to its slot.  SR4 is r = 2^8 (four rounds for 32-bit
+ *                      keys); PR2's serial equivalent is r = 2^16 (two rounds).
+ *                      Readings (the paper does not state them): digits are
+ *                      taken least-significant first, and the output loop walks
+ *                      the input forward so that each round is stable -- LSD
+ *                      radix sort is only correct with stable rounds.
+ *   digit_counts_*     the counting loop of one round on its own.
+ *   gsd_u32            Section 3.3, Algorithm 1 (GSD), steps 1-5, with the
+ *                      readings listed at the function.
+ *   segmented_u32/u64  SR4 applied independently to each segment of a CSR
+ *                      segment list (the batched workload).
+ *
+ * Payloads are an addition to the paper (which sorts keys only): an optional
+ * 32-bit value travels with its key.  With a payload the stable result is
+ * unique, so every sort in this file produces exactly "the" stable sort.
+ *
+ * All functions return 0 on success and a negative value on bad arguments or
+ * allocation failure.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* One count-sort round (Section 3.2): count, exclusive prefix, stable output. */
+
+static void round_u32(const uint32_t* in, const uint32_t* vin, size_t n,
+                      int shift, int width, uint32_t* out, uint32_t* vout,
+                      uint64_t* count /* 2^width entries */)
+{
+    const uint64_t r = (uint64_t)1 << width;
+    const uint32_t mask = (uint32_t)(r - 1);
+    memset(count, 0, (size_t)r * sizeof(uint64_t));
+    for (size_t i = 0; i < n; ++i)                         /* counting pass */
+        count[(in[i] >> shift) & mask] += 1;
+    uint64_t run = 0;                                      /* starting offsets */
+    for (uint64_t v = 0; v < r; ++v) {
+        uint64_t c = count[v];
+        count[v] = run;
+        run += c;
+    }
+    for (size_t i = 0; i < n; ++i) {                       /* output pass, forward */
+        uint32_t v = (in[i] >> shift) & mask;
+        uint64_t slot = count[v]++;
+        out[slot] = in[i];
+        if (vin) vout[slot] = vin[i];
+    }
+}
+
+static void round_u64(const uint64_t* in, const uint32_t* vin, size_t n,
+                      int shift, int width, uint64_t* out, uint32_t* vout,
+                      uint64_t* count)
+{
+    const uint64_t r = (uint64_t)1 << width;
+    const uint64_t mask = r - 1;
+    memset(count, 0, (size_t)r * sizeof(uint64_t));
+    for (size_t i = 0; i < n; ++i)
+        count[(in[i] >> shift) & mask] += 1;
+    uint64_t run = 0;
+    for (uint64_t v = 0; v < r; ++v) {
+        uint64_t c = count[v];
+        count[v] = run;
+        run += c;
+    }
+    for (size_t i = 0; i < n; ++i) {
+        uint64_t v = (in[i] >> shift) & mask;
+        uint64_t slot = count[v]++;
+        out[slot] = in[i];
+        if (vin) vout[slot] = vin[i];
+    }
+}
+
+/*
+ * LSD radix sort of the key bits [begin_bit, end_bit) with digits of
+ * digit_bits bits (the last digit is narrower when the range is not a
+ * multiple).  digit_bits = 8 is SR4; 16 is the serial form of PR2's rounds.
+ * Sorting on [0, 8(d+1)) gives the array after round d of SR4.
+ * keys_out/vals_out may alias keys_in/vals_in.  vals_in == NULL: keys only.
+ */
+int lsd_u32(const uint32_t* keys_in, const uint32_t* vals_in, size_t n,
+            int digit_bits, int begin_bit, int end_bit,
+            uint32_t* keys_out, uint32_t* vals_out)
+{
+    if (digit_bits < 1 || digit_bits > 16 || begin_bit < 0 || end_bit > 32 ||
+        begin_bit > end_bit || (n && (!keys_in || !keys_out)) ||
+        (vals_in && !vals_out))
+        return -1;
+    uint32_t* a = (uint32_t*)malloc((n ? n : 1) * sizeof(uint32_t));
+    uint32_t* b = (uint32_t*)malloc((n ? n : 1) * sizeof(uint32_t));
+    uint32_t* va = vals_in ? (uint32_t*)malloc((n ? n : 1) * sizeof(uint32_t)) : NULL;
+    uint32_t* vb = vals_in ? (uint32_t*)malloc((n ? n : 1) * sizeof(uint32_t)) : NULL;
+    uint64_t* count = (uint64_t*)malloc(((size_t)1 << digit_bits) * sizeof(uint64_t));
+    if (!a || !b || !count || (vals_in && (!va || !vb))) {
+        free(a); free(b); free(va); free(vb); free(count);
+        return -2;
+    }
+    if (n) memcpy(a, keys_in, n * sizeof(uint32_t));
+    if (vals_in && n) memcpy(va, vals_in, n * sizeof(uint32_t));
+    for (int lo = begin_bit; lo < end_bit; lo += digit_bits) {
+        int width = end_bit - lo < digit_bits ? end_bit - lo : digit_bits;
+        round_u32(a, va, n, lo, width, b, vb, count);
+        uint32_t* t = a; a = b; b = t;
+        t = va; va = vb; vb = t;
+    }
+    if (n) memcpy(keys_out, a, n * sizeof(uint32_t));
+    if (vals_in && n) memcpy(vals_out, va, n * sizeof(uint32_t));
+    free(a); free(b); free(va); free(vb); free(count);
+    return 0;
+}
+
+int lsd_u64(const uint64_t* keys_in, const uint32_t* vals_in, size_t n,
+            int digit_bits, int begin_bit, int end_bit,
+            uint64_t* keys_out, uint32_t* vals_out)
+{
+    if (digit_bits < 1 || digit_bits > 16 || begin_bit < 0 || end_bit > 64 ||
+        begin_bit > end_bit || (n && (!keys_in || !keys_out)) ||
+        (vals_in && !vals_out))
+        return -1;
+    uint64_t* a = (uint64_t*)malloc((n ? n : 1) * sizeof(uint64_t));
+    uint64_t* b = (uint64_t*)malloc((n ? n : 1) * sizeof(uint64_t));
+    uint32_t* va = vals_in ? (uint32_t*)malloc((n ? n : 1) * sizeof(uint32_t)) : NULL;
+    uint32_t* vb = vals_in ? (uint32_t*)malloc((n ? n : 1) * sizeof(uint32_t)) : NULL;
+    uint64_t* count = (uint64_t*)malloc(((size_t)1 << digit_bits) * sizeof(uint64_t));
+    if (!a || !b || !count || (vals_in && (!va || !vb))) {
+        free(a); free(b); free(va); free(vb); free(count);
+        return -2;
+    }
+    if (n) memcpy(a, keys_in, n * sizeof(uint64_t));
+    if (vals_in && n) memcpy(va, vals_in, n * sizeof(uint32_t));
+    for (int lo = begin_bit; lo < end_bit; lo += digit_bits) {
+        int width = end_bit - lo < digit_bits ? end_bit - lo : digit_bits;
+        round_u64(a, va, n, lo, width, b, vb, count);
+        uint64_t* t = a; a = b; b = t;
+        uint32_t* tv = va; va = vb; vb = tv;
+    }
+    if (n) memcpy(keys_out, a, n * sizeof(uint64_t));
+    if (vals_in && n) memcpy(vals_out, va, n * sizeof(uint32_t));
+    free(a); free(b); free(va); free(vb); free(count);
+    return 0;
+}
+
+/* The counting loop of one round (Section 3.2): counts[v] = #{i : digit(x_i) = v}. */
+int digit_counts_u32(const uint32_t* keys, size_t n, int shift, int width,
+                     uint64_t* counts)
+{
+    if (width < 1 || width > 16 || shift < 0 || shift + width > 32) return -1;
+    const uint32_t mask = (uint32_t)(((uint64_t)1 << width) - 1);
+    memset(counts, 0, ((size_t)1 << width) * sizeof(uint64_t));
+    for (size_t i = 0; i < n; ++i) counts[(keys[i] >> shift) & mask] += 1;
+    return 0;
+}
+
+int digit_counts_u64(const uint64_t* keys, size_t n, int shift, int width,
+                     uint64_t* counts)
+{
+    if (width < 1 || width > 16 || shift < 0 || shift + width > 64) return -1;
+    const uint64_t mask = ((uint64_t)1 << width) - 1;
+    memset(counts, 0, ((size_t)1 << width) * sizeof(uint64_t));
+    for (size_t i = 0; i < n; ++i) counts[(keys[i] >> shift) & mask] += 1;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Segmented: SR4 on every segment [off[s], off[s+1]) independently.          */
+
+int segmented_u32(const uint32_t* keys_in, const uint32_t* vals_in,
+                  const uint64_t* offsets, size_t num_segs,
+                  uint32_t* keys_out, uint32_t* vals_out)
+{
+    for (size_t s = 0; s < num_segs; ++s) {
+        uint64_t lo = offsets[s], hi = offsets[s + 1];
+        if (hi < lo) return -1;
+        int rc = lsd_u32(keys_in + lo, vals_in ? vals_in + lo : NULL, hi - lo,
+                         8, 0, 32, keys_out + lo, vals_in ? vals_out + lo : NULL);
+        if (rc) return rc;
+    }
+    return 0;
+}
+
+int segmented_u64(const uint64_t* keys_in, const uint32_t* vals_in,
+                  const uint64_t* offsets, size_t num_segs,
+                  uint64_t* keys_out, uint32_t* vals_out)
+{
+    for (size_t s = 0; s < num_segs; ++s) {
+        uint64_t lo = offsets[s], hi = offsets[s + 1];
+        if (hi < lo) return -1;
+        int rc = lsd_u64(keys_in + lo, vals_in ? vals_in + lo : NULL, hi - lo,
+                         8, 0, 64, keys_out + lo, vals_in ? vals_out + lo : NULL);
+        if (rc) return rc;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* GSD, Algorithm 1 (Section 3.3).
+ *
+ * Readings where the paper is silent:
+ *  - Block k of step 1 is [floor(k n / p), floor((k+1) n / p)); p is clamped
+ *    to n so that no block is empty.
+ *  - Step 2 takes, from block k of N_k sorted keys, the s = r p keys at
+ *    positions ceil(j N_k / s) - 1 for j = 1..s: the last key of each of s
+ *    near-equal segments, the final one being the block maximum.
+ *  - Keys are compared as composites (key, g), g being the key's position in
+ *    the concatenation X of the locally sorted blocks.  Because every block is
+ *    sorted stably, g-order among equal keys is input order, so duplicates
+ *    (which the paper defers to a discussion it does not include) are split
+ *    deterministically and the result is the stable sort.
+ *  - Step 3 splitter i (1 <= i <= p-1) is the (i s)-th smallest composite of
+ *    the sample, 1-based.  The sample is sorted with SR4 instead of BTN; any
+ *    correct sort gives the same sequence.
+ *  - Step 4: X_{k,j} holds the keys e of block k with S_j < e <= S_{j+1}
+ *    (S_0 = -inf, S_p = +inf): a splitter, the largest key of its sample
+ *    segment, stays with the keys below it.  Its end is found by binary
+ *    search.
+ *  - Step 5 merges the runs X_{0,j}, ..., X_{p-1,j} with a heap, equal keys
+ *    taken from the lower run first (stable).
+ *
+ * Outputs besides the sorted keys/values: cnt[k*p + j] = |X_{k,j}|, the
+ * splitters (key, g) and, through cnt, the bucket sizes |Y_j|.
+ */
+
+static int comp_less(uint32_t ka, uint64_t ga, uint32_t kb, uint64_t gb)
+{
+    return ka < kb || (ka == kb && ga < gb);
+}
+
+/* heap of run heads for step 5, ordered by (key, run index) */
+typedef struct { uint32_t key; uint32_t run; } head;
+
+static int head_less(head a, head b)
+{
+    return a.key < b.key || (a.key == b.key && a.run < b.run);
+}
+
+static void heap_sift_down(head* h, size_t m, size_t i)
+{
+    for (;;) {
+        size_t l = 2 * i + 1, r = l + 1, best = i;
+        if (l < m && head_less(h[l], h[best])) best = l;
+        if (r < m && head_less(h[r], h[best])) best = r;
+        if (best == i) return;
+        head t = h[i]; h[i] = h[best]; h[best] = t;
+        i = best;
+    }
+}
+
+int gsd_u32(const uint32_t* keys_in, const uint32_t* vals_in, size_t n,
+            int p_req, int r,
+            uint32_t* keys_out, uint32_t* vals_out,
+            uint64_t* cnt /* p*p */, uint32_t* split_key /* p-1 */,
+            uint64_t* split_g /* p-1 */, int* p_used)
+{
+    if (p_req < 1 || r < 1 || n == 0 || n >= ((uint64_t)1 << 32) ||
+        !keys_in || !keys_out || (vals_in && !vals_out))
+        return -1;
+    size_t p = (size_t)p_req < n ? (size_t)p_req : n;
+    *p_used = (int)p;
+    const size_t s = (size_t)r * p;
+
+    /* step 1: local sorting of p near-equal blocks */
+    uint32_t* X = (uint32_t*)malloc(n * sizeof(uint32_t));
+    uint32_t* XV = vals_in ? (uint32_t*)malloc(n * sizeof(uint32_t)) : NULL;
+    uint64_t* lo = (uint64_t*)malloc((p + 1) * sizeof(uint64_t));
+    uint32_t* Tk = (uint32_t*)malloc(p * s * sizeof(uint32_t));
+    uint32_t* Tg = (uint32_t*)malloc(p * s * sizeof(uint32_t));
+    uint32_t* Sk = (uint32_t*)malloc(p * s * sizeof(uint32_t));
+    uint32_t* Sg = (uint32_t*)malloc(p * s * sizeof(uint32_t));
+    uint64_t* b = (uint64_t*)malloc(p * (p + 1) * sizeof(uint64_t));
+    head* heap = (head*)malloc(p * sizeof(head));
+    uint64_t* cur = (uint64_t*)malloc(p * sizeof(uint64_t));
+    int rc = 0;
+    if (!X || (vals_in && !XV) || !lo || !Tk || !Tg || !Sk || !Sg || !b || !heap || !cur) {
+        rc = -2;
+        goto done;
+    }
+    for (size_t k = 0; k <= p; ++k) lo[k] = (uint64_t)((k * (unsigned __int128)n) / p);
+    for (size_t k = 0; k < p; ++k) {
+        rc = lsd_u32(keys_in + lo[k], vals_in ? vals_in + lo[k] : NULL, lo[k + 1] - lo[k],
+                     8, 0, 32, X + lo[k], vals_in ? XV + lo[k] : NULL);
+        if (rc) goto done;
+    }
+
+    /* step 2: regular sample of s keys per block, the last one the block maximum */
+    for (size_t k = 0; k < p; ++k) {
+        uint64_t Nk = lo[k + 1] - lo[k];
+        for (size_t j = 1; j <= s; ++j) {
+            uint64_t q = (j * Nk + s - 1) / s - 1;          /* ceil(j Nk / s) - 1 */
+            Tk[k * s + j - 1] = X[lo[k] + q];
+            Tg[k * s + j - 1] = (uint32_t)(lo[k] + q);
+        }
+    }
+    /* sort the sample by (key, g): T is laid out in block order, so g already
+       increases along equal keys and a stable sort by key suffices */
+    rc = lsd_u32(Tk, Tg, p * s, 8, 0, 32, Sk, Sg);
+    if (rc) goto done;
+
+    /* step 3: splitters = the (i s)-th smallest sample composites */
+    for (size_t i = 1; i < p; ++i) {
+        split_key[i - 1] = Sk[i * s - 1];
+        split_g[i - 1] = Sg[i * s - 1];
+    }
+
+    /* step 4: split every sorted block around the splitters by binary search:
+       b[k][i] = #{q in block k : (X[q], q) <= S_i}, b[k][0] = 0, b[k][p] = N_k */
+    for (size_t k = 0; k < p; ++k) {
+        uint64_t Nk = lo[k + 1] - lo[k];
+        b[k * (p + 1) + 0] = 0;
+        b[k * (p + 1) + p] = Nk;
+        for (size_t i = 1; i < p; ++i) {
+            uint64_t a = 0, e = Nk;                       /* first q with S_i < X_q */
+            while (a < e) {
+                uint64_t mid = a + (e - a) / 2;
+                if (!comp_less(split_key[i - 1], split_g[i - 1], X[lo[k] + mid], lo[k] + mid))
+                    a = mid + 1;
+                else
+                    e = mid;
+            }
+            b[k * (p + 1) + i] = a;
+        }
+        for (size_t j = 0; j < p; ++j)
+            cnt[k * p + j] = b[k * (p + 1) + j + 1] - b[k * (p + 1) + j];
+    }
+
+    /* step 5: Y_j = p-way merge of X_{0,j} .. X_{p-1,j}; Y = Y_0 Y_1 ... */
+    uint64_t o = 0;
+    for (size_t j = 0; j < p; ++j) {
+        size_t m = 0;
+        for (size_t k = 0; k < p; ++k) {
+            cur[k] = b[k * (p + 1) + j];
+            if (cur[k] < b[k * (p + 1) + j + 1]) {
+                heap[m].key = X[lo[k] + cur[k]];
+                heap[m].run = (uint32_t)k;
+                ++m;
+            }
+        }
+        for (size_t i = m; i-- > 0;) heap_sift_down(heap, m, i);
+        while (m) {
+            uint32_t k = heap[0].run;
+            if (o >= n) { rc = -3; goto done; }          /* runs overlap: split is broken */
+            keys_out[o] = X[lo[k] + cur[k]];
+            if (vals_in) vals_out[o] = XV[lo[k] + cur[k]];
+            ++o;
+            ++cur[k];
+            if (cur[k] < b[(size_t)k * (p + 1) + j + 1]) {
+                heap[0].key = X[lo[k] + cur[k]];
+            } else {
+                heap[0] = heap[--m];
+            }
+            if (m) heap_sift_down(heap, m, 0);
+        }
+    }
+    if (o != n) rc = -3;
+
+done:
+    free(X); free(XV); free(lo); free(Tk); free(Tg); free(Sk); free(Sg);
+    free(b); free(heap); free(cur);
+    return rc;
+}
