@@ -1,0 +1,197 @@
+#!/usr/bin/env python3
+"""Throughput of the integer-sort hot path on one MI355X.
+
+Workload: one stable sort of n = 2^27 uint32 keys drawn uniformly over the full
+32-bit range (SplitMix64, seed 0x18081029202), keys only, with the radix-2^8
+LSD sort (PR4 of arXiv 1808.10292, Section 3.2): one digit-count kernel and four
+count-sort round kernels.  A step is one whole sort; inputs are resident in HBM
+before timing starts and the output buffer is reused.
+
+Printed as one JSON line:
+  value        whole-sort Gkeys/s (n / seconds per step)
+  roofline     the dominant kernel (a count-sort round): algorithmic bytes per
+               launch (read + write of every key, 2 n 4 B) over its average
+               duration from HIP events recorded on its stream during the timed
+               steps, against MI355X's 8 TB/s; traffic = HBM bytes per launch
+               from rocprofv3 FETCH_SIZE/WRITE_SIZE when the committed counter
+               summary matches the current kernel source, else null
+  cpu_baseline the CPU oracle (serial SR4 in C, one thread) on the same keys
+  variants     other algorithms on the same keys (reported, not in value)
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBPS = 8000.0
+METRIC = "Gkeys/s + % HBM roofline, 2^27 uint32; batched vs plain; p50/p99 latency"
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_round_u32_keys_2p27_counters.md")
+ROUND_SOURCE = os.path.join(ROOT, "paper_1808_10292_amd", "csrc", "lsd_r8.hip")
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def source_sha():
+    h = hashlib.sha256()
+    for p in (ROUND_SOURCE, os.path.join(ROOT, "paper_1808_10292_amd", "csrc", "device_common.h")):
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic():
+    """HBM bytes per round launch measured with rocprofv3 counters, if the
+    summary was taken on the current kernel source."""
+    if not os.path.exists(COUNTERS_FILE):
+        return None
+    fields = {}
+    for line in open(COUNTERS_FILE):
+        if "=" in line and line.strip().startswith("- "):
+            k, v = line.strip()[2:].split("=", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    if fields.get("source_sha256_16") != source_sha():
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def time_steps(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--log2n", type=int, default=27)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="minimum CPU time spent timing the oracle (0 disables)")
+    ap.add_argument("--no-variants", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import keygen
+    from paper_1808_10292_amd import rsort
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    rsort.load_library()
+    n = 1 << args.log2n
+    log("generating %d keys" % n)
+    keys = keygen.uniform_u32(n, keygen.SEED_LARGE)
+    dk = torch.from_numpy(keys).cuda()
+    out = torch.empty_like(dk)
+    torch.cuda.synchronize()
+
+    def step():
+        rsort.rsort_sort(dk, out, algo="lsd8")
+
+    log("timing %d steps after %d warm-up" % (args.steps, args.warmup))
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    rsort.rsort_profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    launches, round_ms = rsort.rsort_profile_read(rsort.RSORT_KERNEL_ROUND)
+    hl, hist_ms = rsort.rsort_profile_read(rsort.RSORT_KERNEL_HIST)
+    rsort.rsort_profile_enable(False)
+    rsort.rsort_synchronize()
+
+    # sanity: sorted, same multiset fingerprint as the input
+    got = out.cpu().numpy()
+    ok = bool(np.all(got[1:] >= got[:-1])) and \
+        int(got.astype(np.uint64).sum()) == int(keys.astype(np.uint64).sum()) and \
+        int(np.bitwise_xor.reduce(got)) == int(np.bitwise_xor.reduce(keys))
+    if not ok:
+        log("OUTPUT CHECK FAILED")
+
+    round_avg_ms = round_ms / max(launches, 1)
+    bytes_per_round = 2 * n * 4
+    achieved = bytes_per_round / (round_avg_ms * 1e-3) / 1e9
+    gkeys = n / sec / 1e9
+    traffic = committed_traffic()
+    result = {
+        "metric": METRIC,
+        "value": round(gkeys, 3),
+        "unit": "Gkeys/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(sec * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic: uniform 32-bit keys from SplitMix64 (no dataset in the paper)",
+        "config": {"workload": "lsd-r8 (PR4) stable sort of 2^%d uniform uint32 keys, keys only"
+                               % args.log2n, "n": n, "key": "uint32", "payload": None,
+                   "algo": "lsd_r8", "rounds": 4},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBPS, 4),
+                     "traffic": traffic,
+                     "kernel": "k_round<uint32,keys-only> (one count-sort round)",
+                     "algorithmic_bytes_per_launch": bytes_per_round,
+                     "avg_launch_ms": round(round_avg_ms, 5), "timed_launches": launches},
+        "whole_sort": {"algorithmic_bytes": n * 4 + 4 * bytes_per_round,
+                       "gbps": round((n * 4 + 4 * bytes_per_round) / sec / 1e9, 1),
+                       "hist_kernel_ms": round(hist_ms / max(hl, 1), 5)},
+        "output_check": "sorted+fingerprint " + ("ok" if ok else "FAILED"),
+    }
+
+    if not args.no_variants:
+        variants = {}
+        for algo in ("lsd16", "sample"):
+            try:
+                rsort.rsort_sort(dk, out, algo=algo)
+            except rsort.RsortError as e:
+                variants[algo] = "unavailable: %s" % e.status
+                continue
+            s = time_steps(lambda: rsort.rsort_sort(dk, out, algo=algo), max(3, args.steps // 4), 1, torch)
+            variants[algo] = {"gkeys_per_s": round(n / s / 1e9, 3), "ms": round(s * 1e3, 3)}
+        result["variants"] = variants
+
+    if args.cpu_seconds > 0:
+        import oracle
+        log("timing the CPU oracle for >= %.0f s" % args.cpu_seconds)
+        runs, t = 0, 0.0
+        while t < args.cpu_seconds or runs == 0:
+            t0 = time.perf_counter()
+            oracle.sr4(keys)
+            t += time.perf_counter() - t0
+            runs += 1
+        result["cpu_baseline"] = {"value": round(n * runs / t / 1e9, 4), "unit": "Gkeys/s",
+                                  "cores": 1, "kind": "oracle",
+                                  "sample": "%d full runs of serial SR4 (C, one thread) on the "
+                                            "same 2^%d keys, %.1f s" % (runs, args.log2n, t)}
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

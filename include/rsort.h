@@ -1,0 +1,147 @@
+/*
+ * rsort.h -- C ABI of the MI355X (gfx950) integer-sorting library.
+ *
+ * The library sorts n integer keys, optionally carrying a 32-bit payload, on
+ * one AMD Instinct GPU.  It implements the data-parallel sorts studied in
+ * Gerbessiotis, "A study of integer sorting on multicores" (arXiv 1808.10292):
+ *
+ *   RSORT_LSD_R8          PR4: LSD radix sort with radix r = 2^8, one stable
+ *                         count-sort round per 8-bit digit (Section 3.2, PR4,
+ *                         equations Tp and Tp4);
+ *   RSORT_LSD_R16         PR2: the same with r = 2^16 (Section 3.2, eq. Tp2);
+ *   RSORT_SAMPLE_REGULAR  GSD: local sort of p blocks, regular oversampling,
+ *                         splitter selection, split by binary search and
+ *                         routing to p buckets (Section 3.3, Algorithm 1).
+ *
+ * Every algorithm returns the same, unique result: the stable sort.  Keys come
+ * out nondecreasing (as unsigned integers), equal keys keep their input order,
+ * and each payload moves with its key.
+ *
+ * Conventions shared by every entry point
+ *   - Return value: RSORT_OK (0) or a negative rsort_status.  No entry point
+ *     aborts or throws.  Argument errors are detected before anything is
+ *     enqueued.  Device-side failures are reported by rsort_synchronize.
+ *   - Data pointers are HIP device pointers owned by the caller; the library
+ *     never frees them.  Host pointers are rejected with RSORT_EINVAL.
+ *   - "stream" is a hipStream_t passed as void* (NULL = the null stream).  Work
+ *     is enqueued asynchronously on it and is stream-ordered; the call returns
+ *     before the GPU finishes.
+ *   - An rsort_ctx is used by one host thread at a time.
+ *   - n < 2^30 (RSORT_EUNSUPPORTED otherwise).
+ */
+#ifndef RSORT_H
+#define RSORT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rsort_ctx rsort_ctx;
+
+enum rsort_status {
+    RSORT_OK = 0,
+    RSORT_EINVAL = -1,        /* bad argument (NULL, host pointer, overlap, range) */
+    RSORT_ENOMEM = -2,        /* device allocation failed                          */
+    RSORT_EDEVICE = -3,       /* a HIP call or a kernel failed                     */
+    RSORT_EBUSY = -4,         /* resource in use                                   */
+    RSORT_EUNSUPPORTED = -5   /* valid request outside this build's limits         */
+};
+
+enum rsort_key_type { RSORT_U32 = 0, RSORT_U64 = 1 };
+
+enum rsort_algo {
+    RSORT_AUTO = 0,            /* currently RSORT_LSD_R8                           */
+    RSORT_LSD_R8 = 1,          /* PR4                                              */
+    RSORT_LSD_R16 = 2,         /* PR2                                              */
+    RSORT_SAMPLE_REGULAR = 3   /* GSD skeleton (uint32 keys)                        */
+};
+
+/* Create a context bound to HIP device `hip_device`.  The context owns a
+ * growable cached workspace and small device-side state (error word, the
+ * statistics of the last sample sort).  *out receives the handle. */
+int rsort_create(int hip_device, rsort_ctx** out);
+
+/* Release the context and everything it allocated.  Waits for the device. */
+int rsort_destroy(rsort_ctx* ctx);
+
+/* Static description of a status code. */
+const char* rsort_status_string(int status);
+
+/* Detail message for the last failure seen on ctx ("" if none).  The pointer
+ * stays valid until the next call on ctx. */
+const char* rsort_last_error(const rsort_ctx* ctx);
+
+/* Bytes of workspace rsort_sort needs for this request (algo as in rsort_sort;
+ * for RSORT_SAMPLE_REGULAR the default p and r).  Monotone in n. */
+int rsort_workspace_bytes(rsort_ctx* ctx, int key_type, int has_vals, size_t n,
+                          int algo, size_t* bytes);
+
+/*
+ * Stable sort of n keys on the key bits [begin_bit, end_bit).
+ *
+ *   key_type   RSORT_U32 (keys are uint32_t) or RSORT_U64 (uint64_t).
+ *   keys_in    device array of n keys; read only unless it equals keys_out.
+ *   keys_out   device array of n keys receiving the sorted keys.  keys_in ==
+ *              keys_out sorts in place; any other overlap is RSORT_EINVAL.
+ *   vals_in, vals_out
+ *              both NULL (keys only) or both device arrays of n uint32_t
+ *              payloads; vals_out[i] is the payload of the key now at i.
+ *              Same aliasing rule as the keys.
+ *   begin_bit, end_bit
+ *              0 <= begin_bit <= end_bit <= key width.  Only these bits are
+ *              compared; (0, 32) or (0, 64) sorts whole keys.  Sorting on
+ *              [0, 8(d+1)) reproduces the array after round d of PR4.
+ *   algo       an rsort_algo.  RSORT_SAMPLE_REGULAR requires whole uint32 keys
+ *              and uses p = 256 buckets and oversampling factor r = 32 (see
+ *              rsort_sample_sort for other values).
+ *   workspace, ws_bytes
+ *              NULL and 0 to use the context's cached workspace (grown with
+ *              hipMalloc when needed), or a device buffer of at least
+ *              rsort_workspace_bytes() bytes that stays untouched by others
+ *              until the sort completes on `stream`.
+ */
+int rsort_sort(rsort_ctx* ctx, int key_type,
+               const void* keys_in, void* keys_out,
+               const uint32_t* vals_in, uint32_t* vals_out,
+               size_t n, int begin_bit, int end_bit, int algo,
+               void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * The counting step of every count-sort round, for all rounds at once
+ * (Section 3.2: each round first counts digit occurrences): one read of the
+ * keys produces, for every digit d of the key bits [begin_bit, end_bit) taken
+ * digit_bits (8 or 16) at a time from the least significant end,
+ *   hist_out[d * 2^digit_bits + v] = #{ i : digit d of keys[i] == v }.
+ * hist_out is a device array of ceil((end_bit - begin_bit) / digit_bits) *
+ * 2^digit_bits uint32_t that the call overwrites.
+ */
+int rsort_histogram(rsort_ctx* ctx, int key_type, const void* keys, size_t n,
+                    int digit_bits, int begin_bit, int end_bit,
+                    uint32_t* hist_out, void* stream);
+
+/* Wait for `stream`, then report any device-side failure recorded by this
+ * context's kernels since the last call (RSORT_EDEVICE) and clear it. */
+int rsort_synchronize(rsort_ctx* ctx, void* stream);
+
+/* Kernel timing for measurement.  While enabled, every sort on ctx records a
+ * HIP event on its stream immediately before and after each kernel of the
+ * kinds below; enabling (or disabling) resets the totals. */
+enum rsort_kernel_kind {
+    RSORT_KERNEL_ROUND = 0,   /* one count-sort round (rank, look-back, scatter) */
+    RSORT_KERNEL_HIST = 1     /* the digit-counting kernel                        */
+};
+int rsort_profile_enable(rsort_ctx* ctx, int enable);
+
+/* Waits for the recorded events and returns, for one rsort_kernel_kind, how
+ * many launches were timed since profiling was enabled and their summed
+ * durations in milliseconds. */
+int rsort_profile_read(rsort_ctx* ctx, int kind, uint64_t* launches, double* total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RSORT_H */

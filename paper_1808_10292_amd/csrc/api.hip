@@ -1,0 +1,386 @@
+// C ABI of the library (declarations and contracts in include/rsort.h):
+// argument validation, workspace management and dispatch to the kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/rsort.h"
+#include "rsort_internal.h"
+
+namespace rsort {
+
+// Event pairs recorded around kernels of each kind; totals are folded in when
+// read.  Events are pooled so steady-state recording creates none.
+struct Profiler {
+    struct Pair {
+        int kind;
+        hipEvent_t start, stop;
+    };
+    std::vector<hipEvent_t> pool;
+    std::vector<Pair> pending;
+    hipEvent_t open_start[kNumKinds] = {};
+    uint64_t launches[kNumKinds] = {};
+    double total_ms[kNumKinds] = {};
+
+    hipEvent_t get()
+    {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    void fold()
+    {
+        for (Pair& p : pending) {
+            float ms = 0.f;
+            if (hipEventSynchronize(p.stop) == hipSuccess &&
+                hipEventElapsedTime(&ms, p.start, p.stop) == hipSuccess) {
+                launches[p.kind] += 1;
+                total_ms[p.kind] += ms;
+            }
+            pool.push_back(p.start);
+            pool.push_back(p.stop);
+        }
+        pending.clear();
+    }
+    ~Profiler()
+    {
+        fold();
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    }
+};
+
+void profiler_mark(Profiler* p, hipStream_t s, int kind, bool begin)
+{
+    hipEvent_t e = p->get();
+    if (!e) return;
+    (void)hipEventRecord(e, s);
+    if (begin) {
+        p->open_start[kind] = e;
+    } else if (p->open_start[kind]) {
+        p->pending.push_back({kind, p->open_start[kind], e});
+        p->open_start[kind] = nullptr;
+        if (p->pending.size() > 4096) p->fold();
+    }
+}
+
+}  // namespace rsort
+
+struct rsort_ctx {
+    int device = 0;
+    void* ws = nullptr;          // cached workspace (grown on demand)
+    size_t ws_bytes = 0;
+    uint32_t* dev_err = nullptr; // device-side failure bits (DeviceError)
+    rsort::Profiler* prof = nullptr;
+    std::string last_error;
+};
+
+namespace {
+
+constexpr size_t kMaxN = (size_t)1 << 30;
+
+int fail(rsort_ctx* ctx, int status, const char* fmt, ...)
+{
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        ctx->last_error = buf;
+    }
+    return status;
+}
+
+int hip_fail(rsort_ctx* ctx, hipError_t e, const char* where)
+{
+    return fail(ctx, e == hipErrorOutOfMemory ? RSORT_ENOMEM : RSORT_EDEVICE, "%s: %s", where,
+                hipGetErrorString(e));
+}
+
+// True if p is memory the GPU `device` can address as device memory.
+bool is_device_pointer(const void* p, int device)
+{
+    hipPointerAttribute_t attr;
+    hipError_t e = hipPointerGetAttributes(&attr, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return attr.type == hipMemoryTypeDevice && attr.device == device;
+}
+
+bool overlap_partial(const void* a, size_t abytes, const void* b, size_t bbytes)
+{
+    if (a == b) return false;
+    const char* x = (const char*)a;
+    const char* y = (const char*)b;
+    return x < y + bbytes && y < x + abytes;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        int cur;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+int ensure_workspace(rsort_ctx* ctx, size_t need, void** ws)
+{
+    if (need <= ctx->ws_bytes) {
+        *ws = ctx->ws;
+        return RSORT_OK;
+    }
+    if (ctx->ws) {
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipDeviceSynchronize");
+        (void)hipFree(ctx->ws);
+        ctx->ws = nullptr;
+        ctx->ws_bytes = 0;
+    }
+    size_t grow = std::max(need, (size_t)1 << 20);
+    hipError_t e = hipMalloc(&ctx->ws, grow);
+    if (e != hipSuccess) {
+        ctx->ws = nullptr;
+        return hip_fail(ctx, e, "hipMalloc(workspace)");
+    }
+    ctx->ws_bytes = grow;
+    *ws = ctx->ws;
+    return RSORT_OK;
+}
+
+int key_bytes_of(int key_type)
+{
+    return key_type == RSORT_U32 ? 4 : (key_type == RSORT_U64 ? 8 : 0);
+}
+
+int validate_bits(rsort_ctx* ctx, int key_type, int begin_bit, int end_bit)
+{
+    const int width = key_bytes_of(key_type) * 8;
+    if (begin_bit < 0 || end_bit > width || begin_bit > end_bit)
+        return fail(ctx, RSORT_EINVAL, "bit range [%d, %d) outside [0, %d]", begin_bit, end_bit, width);
+    return RSORT_OK;
+}
+
+size_t sort_ws_bytes(int key_type, bool has_vals, size_t n, int algo, int begin_bit, int end_bit)
+{
+    (void)algo;
+    return rsort::lsd_r8_layout(key_bytes_of(key_type), has_vals, n, begin_bit, end_bit).bytes;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rsort_create(int hip_device, rsort_ctx** out)
+{
+    if (!out) return RSORT_EINVAL;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || hip_device < 0 || hip_device >= count)
+        return RSORT_EINVAL;
+    rsort_ctx* ctx = new (std::nothrow) rsort_ctx;
+    if (!ctx) return RSORT_ENOMEM;
+    ctx->device = hip_device;
+    DeviceGuard g(hip_device);
+    if (hipMalloc(&ctx->dev_err, 256) != hipSuccess ||
+        hipMemset(ctx->dev_err, 0, 256) != hipSuccess) {
+        if (ctx->dev_err) (void)hipFree(ctx->dev_err);
+        delete ctx;
+        return RSORT_ENOMEM;
+    }
+    *out = ctx;
+    return RSORT_OK;
+}
+
+int rsort_destroy(rsort_ctx* ctx)
+{
+    if (!ctx) return RSORT_EINVAL;
+    {
+        DeviceGuard g(ctx->device);
+        (void)hipDeviceSynchronize();
+        delete ctx->prof;
+        if (ctx->ws) (void)hipFree(ctx->ws);
+        if (ctx->dev_err) (void)hipFree(ctx->dev_err);
+    }
+    delete ctx;
+    return RSORT_OK;
+}
+
+const char* rsort_status_string(int status)
+{
+    switch (status) {
+    case RSORT_OK: return "success";
+    case RSORT_EINVAL: return "invalid argument";
+    case RSORT_ENOMEM: return "out of device memory";
+    case RSORT_EDEVICE: return "device error";
+    case RSORT_EBUSY: return "resource busy";
+    case RSORT_EUNSUPPORTED: return "unsupported request";
+    default: return "unknown status";
+    }
+}
+
+const char* rsort_last_error(const rsort_ctx* ctx)
+{
+    return ctx ? ctx->last_error.c_str() : "";
+}
+
+int rsort_workspace_bytes(rsort_ctx* ctx, int key_type, int has_vals, size_t n, int algo,
+                          size_t* bytes)
+{
+    if (!ctx || !bytes) return RSORT_EINVAL;
+    if (!key_bytes_of(key_type)) return fail(ctx, RSORT_EINVAL, "unknown key type %d", key_type);
+    if (n >= kMaxN) return fail(ctx, RSORT_EUNSUPPORTED, "n = %zu >= 2^30", n);
+    *bytes = sort_ws_bytes(key_type, has_vals != 0, n, algo, 0, key_bytes_of(key_type) * 8);
+    return RSORT_OK;
+}
+
+int rsort_sort(rsort_ctx* ctx, int key_type, const void* keys_in, void* keys_out,
+               const uint32_t* vals_in, uint32_t* vals_out, size_t n, int begin_bit,
+               int end_bit, int algo, void* workspace, size_t ws_bytes, void* stream)
+{
+    if (!ctx) return RSORT_EINVAL;
+    ctx->last_error.clear();
+    const int kb = key_bytes_of(key_type);
+    if (!kb) return fail(ctx, RSORT_EINVAL, "unknown key type %d", key_type);
+    if (algo != RSORT_AUTO && algo != RSORT_LSD_R8)
+        return fail(ctx, RSORT_EUNSUPPORTED, "algorithm %d not available", algo);
+    int rc = validate_bits(ctx, key_type, begin_bit, end_bit);
+    if (rc) return rc;
+    if ((vals_in == nullptr) != (vals_out == nullptr))
+        return fail(ctx, RSORT_EINVAL, "vals_in and vals_out must both be NULL or both be set");
+    if (n == 0) return RSORT_OK;
+    if (n >= kMaxN) return fail(ctx, RSORT_EUNSUPPORTED, "n = %zu >= 2^30", n);
+    if (!keys_in || !keys_out) return fail(ctx, RSORT_EINVAL, "NULL key pointer with n > 0");
+    if ((workspace == nullptr) != (ws_bytes == 0))
+        return fail(ctx, RSORT_EINVAL, "workspace and ws_bytes must both be 0 or both be set");
+
+    DeviceGuard g(ctx->device);
+    if (!is_device_pointer(keys_in, ctx->device) || !is_device_pointer(keys_out, ctx->device))
+        return fail(ctx, RSORT_EINVAL, "key arrays must be device memory of device %d", ctx->device);
+    if (vals_in && (!is_device_pointer(vals_in, ctx->device) || !is_device_pointer(vals_out, ctx->device)))
+        return fail(ctx, RSORT_EINVAL, "payload arrays must be device memory of device %d", ctx->device);
+    const size_t kbytes = n * kb, vbytes = n * 4;
+    if (overlap_partial(keys_in, kbytes, keys_out, kbytes))
+        return fail(ctx, RSORT_EINVAL, "keys_in and keys_out overlap without being equal");
+    if (vals_in) {
+        if (overlap_partial(vals_in, vbytes, vals_out, vbytes))
+            return fail(ctx, RSORT_EINVAL, "vals_in and vals_out overlap without being equal");
+        if (overlap_partial(keys_in, kbytes, vals_in, vbytes) || keys_in == (const void*)vals_in ||
+            overlap_partial(keys_out, kbytes, vals_out, vbytes) || keys_out == (void*)vals_out ||
+            overlap_partial(keys_out, kbytes, vals_in, vbytes) || keys_out == (const void*)vals_in ||
+            overlap_partial(keys_in, kbytes, vals_out, vbytes) || keys_in == (const void*)vals_out)
+            return fail(ctx, RSORT_EINVAL, "key and payload arrays overlap");
+    }
+    hipStream_t s = (hipStream_t)stream;
+
+    if (end_bit == begin_bit) {  // nothing to compare: the stable sort is the identity
+        hipError_t e = rsort::copy_bytes(keys_out, keys_in, kbytes, s);
+        if (e == hipSuccess && vals_in) e = rsort::copy_bytes(vals_out, vals_in, vbytes, s);
+        return e == hipSuccess ? RSORT_OK : hip_fail(ctx, e, "copy");
+    }
+
+    const rsort::LsdR8Layout L = rsort::lsd_r8_layout(kb, vals_in != nullptr, n, begin_bit, end_bit);
+    void* ws = workspace;
+    if (ws) {
+        if (ws_bytes < L.bytes)
+            return fail(ctx, RSORT_EINVAL, "workspace of %zu bytes < %zu needed", ws_bytes, L.bytes);
+        if (!is_device_pointer(ws, ctx->device))
+            return fail(ctx, RSORT_EINVAL, "workspace must be device memory");
+    } else {
+        rc = ensure_workspace(ctx, L.bytes, &ws);
+        if (rc) return rc;
+    }
+    hipError_t e = rsort::lsd_r8_sort(kb, keys_in, keys_out, vals_in, vals_out, n, begin_bit,
+                                      end_bit, ws, L, ctx->dev_err, s, ctx->prof);
+    if (e != hipSuccess) return hip_fail(ctx, e, "kernel launch");
+    return RSORT_OK;
+}
+
+int rsort_histogram(rsort_ctx* ctx, int key_type, const void* keys, size_t n, int digit_bits,
+                    int begin_bit, int end_bit, uint32_t* hist_out, void* stream)
+{
+    if (!ctx) return RSORT_EINVAL;
+    ctx->last_error.clear();
+    const int kb = key_bytes_of(key_type);
+    if (!kb) return fail(ctx, RSORT_EINVAL, "unknown key type %d", key_type);
+    if (digit_bits != 8 && digit_bits != 16)
+        return fail(ctx, RSORT_EINVAL, "digit_bits must be 8 or 16");
+    int rc = validate_bits(ctx, key_type, begin_bit, end_bit);
+    if (rc) return rc;
+    if (n >= kMaxN) return fail(ctx, RSORT_EUNSUPPORTED, "n = %zu >= 2^30", n);
+    if (end_bit == begin_bit) return RSORT_OK;
+    DeviceGuard g(ctx->device);
+    if (!hist_out || !is_device_pointer(hist_out, ctx->device))
+        return fail(ctx, RSORT_EINVAL, "hist_out must be device memory");
+    if (n && (!keys || !is_device_pointer(keys, ctx->device)))
+        return fail(ctx, RSORT_EINVAL, "keys must be device memory");
+    void* ws = nullptr;
+    size_t need = rsort::histogram_ws_bytes(digit_bits, begin_bit, end_bit);
+    if (need) {
+        rc = ensure_workspace(ctx, need, &ws);
+        if (rc) return rc;
+    }
+    hipError_t e = rsort::histogram(kb, keys, n, digit_bits, begin_bit, end_bit, hist_out, ws,
+                                    (hipStream_t)stream);
+    return e == hipSuccess ? RSORT_OK : hip_fail(ctx, e, "kernel launch");
+}
+
+int rsort_profile_enable(rsort_ctx* ctx, int enable)
+{
+    if (!ctx) return RSORT_EINVAL;
+    DeviceGuard g(ctx->device);
+    delete ctx->prof;
+    ctx->prof = nullptr;
+    if (enable) {
+        ctx->prof = new (std::nothrow) rsort::Profiler;
+        if (!ctx->prof) return fail(ctx, RSORT_ENOMEM, "profiler");
+    }
+    return RSORT_OK;
+}
+
+int rsort_profile_read(rsort_ctx* ctx, int kind, uint64_t* launches, double* total_ms)
+{
+    if (!ctx || !launches || !total_ms || kind < 0 || kind >= rsort::kNumKinds) return RSORT_EINVAL;
+    if (!ctx->prof) return fail(ctx, RSORT_EINVAL, "profiling is not enabled");
+    DeviceGuard g(ctx->device);
+    ctx->prof->fold();
+    *launches = ctx->prof->launches[kind];
+    *total_ms = ctx->prof->total_ms[kind];
+    return RSORT_OK;
+}
+
+int rsort_synchronize(rsort_ctx* ctx, void* stream)
+{
+    if (!ctx) return RSORT_EINVAL;
+    DeviceGuard g(ctx->device);
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamSynchronize");
+    uint32_t err = 0;
+    e = hipMemcpy(&err, ctx->dev_err, 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpy(error word)");
+    if (err) {
+        (void)hipMemset(ctx->dev_err, 0, 4);
+        return fail(ctx, RSORT_EDEVICE, "device-side failure bits 0x%x%s", err,
+                    (err & 1u) ? " (look-back wait timed out)" : "");
+    }
+    return RSORT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,63 @@
+// Host-side interfaces between the C ABI (api.hip) and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace rsort {
+
+constexpr size_t kAlign = 256;
+
+inline size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
+
+// One entry per count-sort round, written on the device by the scan kernel:
+// whether the round runs (it is skipped when one digit value holds every key,
+// which makes the round the identity), its ordinal among the rounds that run,
+// and where it reads and writes: 0 = caller input, 1 = caller output,
+// 2 = workspace temporary.
+struct RoundPlan {
+    int32_t exec;
+    int32_t ord;
+    int32_t src;
+    int32_t dst;
+};
+
+constexpr int kMaxRounds = 8;      // 64-bit keys, 8-bit digits
+constexpr int kHistReplicas = 8;   // global histogram copies, picked by block index
+
+// Optional kernel timing: HIP events recorded on the launch stream around the
+// kernels of one kind (implemented in api.hip).  nullptr disables it.
+enum KernelKind { kKindRound = 0, kKindHist = 1, kKindOther = 2, kNumKinds = 3 };
+struct Profiler;
+void profiler_mark(Profiler* p, hipStream_t s, int kind, bool begin);
+
+// ---------------------------------------------------------------------------
+// Radix 2^8 LSD (PR4) with one-sweep rounds.
+struct LsdR8Layout {
+    uint32_t rounds;     // number of 8-bit (or narrower, last) digits
+    uint32_t tile;       // keys per tile in a round
+    uint32_t ntiles;
+    size_t off_tmp_keys, off_tmp_vals, off_state0, off_state1;
+    size_t off_hist, off_bases, off_plan, off_tickets;
+    size_t bytes;
+};
+
+LsdR8Layout lsd_r8_layout(int key_bytes, bool has_vals, size_t n, int begin_bit, int end_bit);
+
+// Enqueue the whole sort on `stream`.  ws must hold layout.bytes bytes.
+hipError_t lsd_r8_sort(int key_bytes, const void* keys_in, void* keys_out,
+                       const uint32_t* vals_in, uint32_t* vals_out, size_t n,
+                       int begin_bit, int end_bit, void* ws, const LsdR8Layout& L,
+                       uint32_t* dev_err, hipStream_t stream, Profiler* prof);
+
+// Digit histograms of every digit (8- or 16-bit) of [begin_bit, end_bit).
+size_t histogram_ws_bytes(int digit_bits, int begin_bit, int end_bit);
+hipError_t histogram(int key_bytes, const void* keys, size_t n, int digit_bits,
+                     int begin_bit, int end_bit, uint32_t* hist_out, void* ws,
+                     hipStream_t stream);
+
+// Plain device copy used when a sort moves nothing (empty bit range).
+hipError_t copy_bytes(void* dst, const void* src, size_t bytes, hipStream_t stream);
+
+}  // namespace rsort

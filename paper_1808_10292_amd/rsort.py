@@ -1,0 +1,265 @@
+"""Python binding of the C ABI in include/rsort.h (ctypes; marshalling only).
+
+Every function here converts torch tensors to device pointers and calls the
+entry point of the same name in ``librsort.so``; all sorting work runs in the
+library's HIP kernels.  If the library is missing the import-time loader raises
+instead of falling back to anything else.
+
+torch is imported before the library is loaded so that the library binds to
+the HIP runtime torch already mapped (both carry the same soname), which makes
+torch's device pointers and streams valid handles for the library.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librsort.so")
+
+RSORT_OK = 0
+RSORT_EINVAL = -1
+RSORT_ENOMEM = -2
+RSORT_EDEVICE = -3
+RSORT_EBUSY = -4
+RSORT_EUNSUPPORTED = -5
+
+RSORT_U32 = 0
+RSORT_U64 = 1
+
+RSORT_AUTO = 0
+RSORT_LSD_R8 = 1
+RSORT_LSD_R16 = 2
+RSORT_SAMPLE_REGULAR = 3
+
+ALGOS = {"auto": RSORT_AUTO, "lsd8": RSORT_LSD_R8, "pr4": RSORT_LSD_R8,
+         "lsd16": RSORT_LSD_R16, "pr2": RSORT_LSD_R16,
+         "sample": RSORT_SAMPLE_REGULAR, "gsd": RSORT_SAMPLE_REGULAR}
+
+# Every symbol include/rsort.h declares; the loader checks they all exist.
+EXPORTED = ("rsort_create", "rsort_destroy", "rsort_status_string", "rsort_last_error",
+            "rsort_workspace_bytes", "rsort_sort", "rsort_histogram", "rsort_synchronize",
+            "rsort_profile_enable", "rsort_profile_read")
+
+RSORT_KERNEL_ROUND = 0
+RSORT_KERNEL_HIST = 1
+
+
+class RsortError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str = ""):
+        self.status = status
+        msg = "%s failed: %s (%d)" % (where, _status_string(status), status)
+        if detail:
+            msg += ": " + detail
+        super().__init__(msg)
+
+
+_lib = None
+_lib_lock = threading.Lock()
+
+
+def load_library():
+    """Load librsort.so and declare the C signatures.  Raises if it is absent."""
+    global _lib
+    with _lib_lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("HIP library %s is not built; run "
+                              "`python -m paper_1808_10292_amd.build`" % LIB_PATH)
+        lib = ctypes.CDLL(LIB_PATH)
+        vp, sz, i, u32p = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p
+        for name in EXPORTED:
+            getattr(lib, name)  # AttributeError if a declared symbol is missing
+        lib.rsort_create.argtypes = [i, ctypes.POINTER(vp)]
+        lib.rsort_destroy.argtypes = [vp]
+        lib.rsort_status_string.argtypes = [i]
+        lib.rsort_status_string.restype = ctypes.c_char_p
+        lib.rsort_last_error.argtypes = [vp]
+        lib.rsort_last_error.restype = ctypes.c_char_p
+        lib.rsort_workspace_bytes.argtypes = [vp, i, i, sz, i, ctypes.POINTER(sz)]
+        lib.rsort_sort.argtypes = [vp, i, vp, vp, u32p, u32p, sz, i, i, i, vp, sz, vp]
+        lib.rsort_histogram.argtypes = [vp, i, vp, sz, i, i, i, u32p, vp]
+        lib.rsort_synchronize.argtypes = [vp, vp]
+        lib.rsort_profile_enable.argtypes = [vp, i]
+        lib.rsort_profile_read.argtypes = [vp, i, ctypes.POINTER(ctypes.c_uint64),
+                                           ctypes.POINTER(ctypes.c_double)]
+        for name in EXPORTED:
+            f = getattr(lib, name)
+            if f.restype is ctypes.c_int or f.restype is None:
+                f.restype = i
+        lib.rsort_status_string.restype = ctypes.c_char_p
+        lib.rsort_last_error.restype = ctypes.c_char_p
+        _lib = lib
+        return lib
+
+
+def _status_string(status: int) -> str:
+    try:
+        return load_library().rsort_status_string(status).decode()
+    except Exception:  # noqa: BLE001 - only used to format an error
+        return "status"
+
+
+class Context:
+    """An rsort_ctx bound to one HIP device."""
+
+    def __init__(self, device: int = 0):
+        lib = load_library()
+        h = ctypes.c_void_p()
+        rc = lib.rsort_create(int(device), ctypes.byref(h))
+        if rc != RSORT_OK:
+            raise RsortError(rc, "rsort_create")
+        self.handle = h
+        self.device = int(device)
+        self._lib = lib
+
+    def check(self, rc: int, where: str):
+        if rc != RSORT_OK:
+            detail = self._lib.rsort_last_error(self.handle).decode()
+            raise RsortError(rc, where, detail)
+
+    def close(self):
+        if self.handle:
+            self._lib.rsort_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
+
+
+_contexts: dict = {}
+
+
+def context(device=None) -> Context:
+    if device is None:
+        device = torch.cuda.current_device()
+    if isinstance(device, torch.device):
+        device = device.index if device.index is not None else torch.cuda.current_device()
+    ctx = _contexts.get(device)
+    if ctx is None:
+        ctx = _contexts[device] = Context(device)
+    return ctx
+
+
+def _key_type(t: torch.Tensor) -> int:
+    if t.dtype in (torch.int32, torch.uint32):
+        return RSORT_U32
+    if t.dtype in (torch.int64, torch.uint64):
+        return RSORT_U64
+    raise TypeError("keys must be a 32- or 64-bit integer tensor (bit pattern sorted as "
+                    "unsigned), got %s" % t.dtype)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _check_tensor(t, n, name):
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    if not t.is_contiguous() or t.numel() != n:
+        raise ValueError("%s must be contiguous with %d elements" % (name, n))
+
+
+# ---------------------------------------------------------------------------
+# Entry points under their C names.
+
+def rsort_workspace_bytes(key_dtype, has_vals: bool, n: int, algo="auto", device=None) -> int:
+    ctx = context(device)
+    kt = _key_type(torch.empty(0, dtype=key_dtype))
+    out = ctypes.c_size_t()
+    ctx.check(ctx._lib.rsort_workspace_bytes(ctx.handle, kt, int(bool(has_vals)), int(n),
+                                             ALGOS[algo] if isinstance(algo, str) else int(algo),
+                                             ctypes.byref(out)), "rsort_workspace_bytes")
+    return out.value
+
+
+def rsort_sort(keys_in, keys_out, vals_in=None, vals_out=None, begin_bit=0, end_bit=None,
+               algo="auto", workspace=None, stream=None):
+    """Stable sort of keys_in into keys_out (may be the same tensor)."""
+    kt = _key_type(keys_in)
+    n = keys_in.numel()
+    if keys_out.dtype != keys_in.dtype:
+        raise TypeError("keys_out must have the dtype of keys_in")
+    _check_tensor(keys_in, n, "keys_in")
+    _check_tensor(keys_out, n, "keys_out")
+    if (vals_in is None) != (vals_out is None):
+        raise ValueError("vals_in and vals_out must both be given or both be None")
+    if vals_in is not None:
+        for t, name in ((vals_in, "vals_in"), (vals_out, "vals_out")):
+            if t.dtype not in (torch.int32, torch.uint32):
+                raise TypeError("%s must be a 32-bit integer tensor" % name)
+            _check_tensor(t, n, name)
+    if end_bit is None:
+        end_bit = 32 if kt == RSORT_U32 else 64
+    ctx = context(keys_in.device)
+    ws_ptr, ws_bytes = None, 0
+    if workspace is not None:
+        ws_ptr, ws_bytes = _ptr(workspace), workspace.numel() * workspace.element_size()
+    rc = ctx._lib.rsort_sort(ctx.handle, kt, _ptr(keys_in), _ptr(keys_out), _ptr(vals_in),
+                             _ptr(vals_out), n, int(begin_bit), int(end_bit),
+                             ALGOS[algo] if isinstance(algo, str) else int(algo),
+                             ws_ptr, ws_bytes, _stream_handle(stream))
+    ctx.check(rc, "rsort_sort")
+    return keys_out, vals_out
+
+
+def rsort_histogram(keys, digit_bits=8, begin_bit=0, end_bit=None, out=None, stream=None):
+    """Counts of every digit of every count-sort round, shape (rounds, 2^digit_bits)."""
+    kt = _key_type(keys)
+    if end_bit is None:
+        end_bit = 32 if kt == RSORT_U32 else 64
+    rounds = (end_bit - begin_bit + digit_bits - 1) // digit_bits if end_bit > begin_bit else 0
+    if out is None:
+        out = torch.zeros((rounds, 1 << digit_bits), dtype=torch.int32, device=keys.device)
+    ctx = context(keys.device)
+    rc = ctx._lib.rsort_histogram(ctx.handle, kt, _ptr(keys), keys.numel(), int(digit_bits),
+                                  int(begin_bit), int(end_bit), _ptr(out), _stream_handle(stream))
+    ctx.check(rc, "rsort_histogram")
+    return out
+
+
+def rsort_synchronize(stream=None, device=None):
+    ctx = context(device)
+    ctx.check(ctx._lib.rsort_synchronize(ctx.handle, _stream_handle(stream)),
+              "rsort_synchronize")
+
+
+def rsort_profile_enable(enable=True, device=None):
+    ctx = context(device)
+    ctx.check(ctx._lib.rsort_profile_enable(ctx.handle, int(bool(enable))),
+              "rsort_profile_enable")
+
+
+def rsort_profile_read(kind=RSORT_KERNEL_ROUND, device=None):
+    """(timed launches, summed milliseconds) for one kernel kind."""
+    ctx = context(device)
+    launches = ctypes.c_uint64()
+    ms = ctypes.c_double()
+    ctx.check(ctx._lib.rsort_profile_read(ctx.handle, int(kind), ctypes.byref(launches),
+                                          ctypes.byref(ms)), "rsort_profile_read")
+    return launches.value, ms.value
+
+
+# ---------------------------------------------------------------------------
+# Convenience wrapper.
+
+def sort(keys, values=None, algo="auto", begin_bit=0, end_bit=None, stream=None):
+    """Return (sorted_keys, moved_values or None) as new tensors."""
+    ko = torch.empty_like(keys)
+    vo = None if values is None else torch.empty_like(values)
+    rsort_sort(keys, ko, values, vo, begin_bit, end_bit, algo, stream=stream)
+    return ko, vo

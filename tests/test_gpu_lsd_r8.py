@@ -1,0 +1,192 @@
+"""GPU parity of the radix-2^8 LSD path (PR4) against the CPU oracle.
+
+Every comparison is bit-exact: the stable sort is unique, and so are the digit
+counts.  Sizes span one to many tiles with ragged tails (a tile is 8192 uint32
+or 4096 uint64 keys), all six key distributions, keys-only and key-value,
+in-place and out-of-place, partial bit ranges and repeated runs.
+"""
+import numpy as np
+import pytest
+
+import keygen
+import oracle
+from tests.gpu_util import announce, check_kv_invariants, dev, host
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [1, 2, 63, 64, 65, 1000, 8191, 8192, 8193, 3 * 8192 + 17, 100003, 1 << 20]
+
+
+@pytest.fixture(scope="module")
+def rs():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1808_10292_amd import rsort
+    rsort.load_library()
+    return rsort
+
+
+@pytest.mark.parametrize("dist", keygen.KV_DISTRIBUTIONS)
+def test_histogram_8bit_matches_oracle(rs, dist):
+    for n in (1, 8193, 300001):
+        announce("hist8", dist, n)
+        keys = keygen.kv_keys(dist, n)
+        got = host(rs.rsort_histogram(dev(keys), 8)).astype(np.uint64)
+        for d in range(4):
+            assert np.array_equal(got[d], oracle.digit_counts(keys, 8 * d, 8)), (dist, n, d)
+
+
+def test_histogram_16bit_and_ranges(rs):
+    keys = keygen.zipf_keys(250001, 3)
+    announce("hist16")
+    got = host(rs.rsort_histogram(dev(keys), 16)).astype(np.uint64)
+    for d in range(2):
+        assert np.array_equal(got[d], oracle.digit_counts(keys, 16 * d, 16))
+    got = host(rs.rsort_histogram(dev(keys), 8, 5, 27)).astype(np.uint64)
+    assert got.shape[0] == 3
+    assert np.array_equal(got[0], oracle.digit_counts(keys, 5, 8))
+    assert np.array_equal(got[2][:64], oracle.digit_counts(keys, 21, 6))
+    k64 = keygen.uniform_u64(70001, 4)
+    got = host(rs.rsort_histogram(dev(k64), 8)).astype(np.uint64)
+    for d in range(8):
+        assert np.array_equal(got[d], oracle.digit_counts(k64, 8 * d, 8))
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_keys_only_sizes(rs, n):
+    announce("keys u32", n)
+    keys = keygen.uniform_u32(n, 100 + n)
+    ko, _ = rs.sort(dev(keys))
+    want, _ = oracle.sr4(keys)
+    assert np.array_equal(host(ko), want)
+
+
+@pytest.mark.parametrize("dist", keygen.KV_DISTRIBUTIONS)
+def test_kv_distributions(rs, dist):
+    n = 200003
+    announce("kv u32", dist, n)
+    keys = keygen.kv_keys(dist, n)
+    vals = np.arange(n, dtype=np.uint32)
+    ko, vo = rs.sort(dev(keys), dev(vals))
+    ko, vo = host(ko), host(vo)
+    wk, wv = oracle.sr4(keys, vals)
+    assert np.array_equal(ko, wk) and np.array_equal(vo, wv)
+    check_kv_invariants(keys, ko, vo)
+
+
+@pytest.mark.parametrize("n", [5, 4096, 4097, 77777])
+def test_u64_keys(rs, n):
+    announce("u64", n)
+    keys = keygen.uniform_u64(n, 7 + n)
+    keys[::5] = keys[1]
+    vals = np.arange(n, dtype=np.uint32)
+    ko, vo = rs.sort(dev(keys), dev(vals))
+    wk, wv = oracle.sr4(keys, vals)
+    assert np.array_equal(host(ko), wk) and np.array_equal(host(vo), wv)
+    ko, _ = rs.sort(dev(keys))
+    assert np.array_equal(host(ko), wk)
+
+
+@pytest.mark.parametrize("d", [0, 1, 2, 3])
+def test_state_after_each_round(rs, d):
+    """Sorting on [0, 8(d+1)) is the array after round d (oracle's round-d state)."""
+    n = 50001
+    announce("round", d)
+    keys = keygen.uniform_u32(n, 55)
+    vals = np.arange(n, dtype=np.uint32)
+    ko, vo = rs.sort(dev(keys), dev(vals), end_bit=8 * (d + 1))
+    wk, wv = oracle.lsd_sort(keys, vals, 8, 0, 8 * (d + 1))
+    assert np.array_equal(host(ko), wk) and np.array_equal(host(vo), wv)
+
+
+@pytest.mark.parametrize("lo,hi", [(0, 24), (4, 28), (3, 10), (16, 32), (0, 0), (31, 32)])
+def test_bit_ranges_in_and_out_of_place(rs, lo, hi):
+    import torch
+    n = 30011
+    announce("bits", lo, hi)
+    keys = keygen.zipf_keys(n, 5)
+    vals = np.arange(n, dtype=np.uint32)
+    wk, wv = oracle.lsd_sort(keys, vals, 8, lo, hi)
+    ko, vo = rs.sort(dev(keys), dev(vals), begin_bit=lo, end_bit=hi)
+    assert np.array_equal(host(ko), wk) and np.array_equal(host(vo), wv)
+    k, v = dev(keys), dev(vals)
+    rs.rsort_sort(k, k, v, v, lo, hi)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(k), wk) and np.array_equal(host(v), wv)
+
+
+@pytest.mark.parametrize("dist", ["low16", "equal", "presorted", "reverse"])
+def test_in_place_with_identity_rounds(rs, dist):
+    """Identity rounds are skipped; in place the running count is made even."""
+    n = 65537
+    announce("inplace", dist)
+    keys = keygen.kv_keys(dist, n)
+    vals = np.arange(n, dtype=np.uint32)
+    wk, wv = oracle.sr4(keys, vals)
+    k, v = dev(keys), dev(vals)
+    rs.rsort_sort(k, k, v, v)
+    assert np.array_equal(host(k), wk) and np.array_equal(host(v), wv)
+    k = dev(keys)
+    rs.rsort_sort(k, k)
+    assert np.array_equal(host(k), wk)
+
+
+def test_repeatable(rs):
+    n = (1 << 20) + 3
+    keys = keygen.zipf_keys(n, 77)
+    vals = np.arange(n, dtype=np.uint32)
+    announce("repeat")
+    dk, dv = dev(keys), dev(vals)
+    first = None
+    for _ in range(5):
+        ko, vo = rs.sort(dk, dv)
+        cur = (host(ko), host(vo))
+        if first is None:
+            first = cur
+            wk, wv = oracle.sr4(keys, vals)
+            assert np.array_equal(cur[0], wk) and np.array_equal(cur[1], wv)
+        else:
+            assert np.array_equal(cur[0], first[0]) and np.array_equal(cur[1], first[1])
+    rs.rsort_synchronize()
+
+
+def test_caller_workspace(rs):
+    import torch
+    n = 123457
+    keys = keygen.uniform_u32(n, 9)
+    need = rs.rsort_workspace_bytes(torch.uint32, False, n)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    announce("caller workspace", need)
+    ko = torch.empty(n, dtype=torch.uint32, device="cuda")
+    rs.rsort_sort(dev(keys), ko, workspace=ws)
+    assert np.array_equal(host(ko), oracle.sr4(keys)[0])
+    with pytest.raises(rs.RsortError):
+        rs.rsort_sort(dev(keys), ko, workspace=ws[: need // 2])
+
+
+def test_argument_errors(rs):
+    import torch
+    k = dev(keygen.uniform_u32(1000, 1))
+    with pytest.raises(rs.RsortError):
+        rs.rsort_sort(k, torch.empty(1000, dtype=torch.uint32, device="cuda"), begin_bit=4, end_bit=40)
+    # partial overlap of input and output
+    big = torch.zeros(2000, dtype=torch.uint32, device="cuda")
+    with pytest.raises(rs.RsortError):
+        rs.rsort_sort(big[:1000], big[500:1500])
+    # n = 0 is a no-op
+    e = torch.empty(0, dtype=torch.uint32, device="cuda")
+    rs.rsort_sort(e, e)
+    rs.rsort_synchronize()
+
+
+@pytest.mark.slow
+def test_full_size_2p27_keys_only(rs):
+    """The benchmark workload itself: 2^27 uniform 32-bit keys, bit-exact."""
+    n = 1 << 27
+    announce("2^27 keys")
+    keys = keygen.uniform_u32(n, keygen.SEED_LARGE)
+    ko, _ = rs.sort(dev(keys))
+    got = host(ko)
+    want, _ = oracle.sr4(keys)
+    assert np.array_equal(got, want)
+    rs.rsort_synchronize()
