@@ -23,14 +23,34 @@ namespace {
 
 constexpr uint32_t R = 256;  // radix
 
+// Tile shape: WG threads, ITEMS keys per thread (tile = WG * ITEMS keys), and
+// the number of predecessor words a look-back step reads at once.
+#ifndef RSORT_R8_WG32
+#define RSORT_R8_WG32 512
+#endif
+#ifndef RSORT_R8_ITEMS32
+#define RSORT_R8_ITEMS32 16
+#endif
+#ifndef RSORT_R8_WG64
+#define RSORT_R8_WG64 512
+#endif
+#ifndef RSORT_R8_ITEMS64
+#define RSORT_R8_ITEMS64 8
+#endif
+#ifndef LB_WINDOW
+#define LB_WINDOW 4
+#endif
+#ifndef RSORT_R8_WAVES_PER_EU
+#define RSORT_R8_WAVES_PER_EU 6
+#endif
 template <typename K> struct R8Config;
 template <> struct R8Config<uint32_t> {
-    static constexpr int WG = 512;
-    static constexpr int ITEMS = 16;
+    static constexpr int WG = RSORT_R8_WG32;
+    static constexpr int ITEMS = RSORT_R8_ITEMS32;
 };
 template <> struct R8Config<uint64_t> {
-    static constexpr int WG = 512;
-    static constexpr int ITEMS = 8;
+    static constexpr int WG = RSORT_R8_WG64;
+    static constexpr int ITEMS = RSORT_R8_ITEMS64;
 };
 
 constexpr int kHistWG = 256;
@@ -213,19 +233,42 @@ __global__ void k_precopy(const RoundPlan* plan, const K* keys, K* keys_tmp,
 }
 
 // One stable count-sort round over all tiles (see the file comment).
+//
+// Layout: the tile is split among half-waves (32 lanes); half-wave h owns the
+// contiguous keys [h*ITEMS*32, (h+1)*ITEMS*32) of the tile, row i lane l at
+// h*ITEMS*32 + i*32 + (l & 31), so "earlier in the input" is lexicographic
+// (h, i, l) -- the order the ranking below preserves.
+//
+// Phases of a tile:
+//   count   each half-wave counts its digits into its own LDS row;
+//   publish digit thread v sums the rows, publishes the tile's count of v
+//           (aggregate) for later tiles, turns the rows into per-half-wave
+//           slot bases, and issues the first look-back loads;
+//   rank    each half-wave ranks its keys in row order: lanes OR their bit
+//           into the slot of their digit, the set of lanes below with the same
+//           digit gives the rank, and the digit's base advances by the set size;
+//   lookback digit threads finish folding predecessor words into the number of
+//           keys of v in all earlier tiles, and publish the inclusive prefix;
+//   scatter the tile is staged in digit order and written out, consecutive
+//           threads writing consecutive slots of a digit's run (payloads in a
+//           second staging pass through the same LDS).
 template <typename K, bool KV, int WG, int ITEMS>
-__global__ __launch_bounds__(WG) void k_round(RoundArgs a)
+__global__ __launch_bounds__(WG, RSORT_R8_WAVES_PER_EU) void k_round(RoundArgs a)
 {
-    constexpr int WAVES = WG / 64;
+    constexpr int HW = WG / 32;                 // half-waves
     constexpr uint32_t TILE = (uint32_t)WG * ITEMS;
+    constexpr uint32_t STAGE_WORDS = TILE * sizeof(K) / 4;
+    constexpr uint32_t TABLE_WORDS = HW * R;
+    static_assert(STAGE_WORDS >= TABLE_WORDS, "staging must cover the count table");
+    static_assert(TILE <= 65536, "16-bit slot bases");
     struct Smem {
         union {
-            uint64_t bits[WAVES][R];   // ranking: lanes of this wave per digit value
-            K keys[TILE];              // staging: the tile in digit order
+            uint32_t table[HW][R];   // counts, then lane sets of the ranking
+            K keys[TILE];            // staging: the tile in digit order
+            uint32_t vals[TILE];     // staging of the payloads (second pass)
         } u;
-        uint32_t cnt[WAVES][R];        // per-wave digit counts, then slot bases
-        uint32_t vals[KV ? TILE : 1];
-        uint32_t goff[R];              // output index of tile slot 0 of each digit
+        uint16_t base[HW][R];        // next slot of digit v for half-wave h
+        uint32_t goff[R];            // output index of tile slot 0 of each digit
         uint32_t wsum[4];
         uint32_t tile;
     };
@@ -237,106 +280,131 @@ __global__ __launch_bounds__(WG) void k_round(RoundArgs a)
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63;
     const uint32_t wave = tid >> 6;
+    const uint32_t hw = tid >> 5;
+    const uint32_t hl = tid & 31;
 
-    for (uint32_t i = tid; i < WAVES * R; i += WG) {
-        (&sm.u.bits[0][0])[i] = 0;
-        (&sm.cnt[0][0])[i] = 0;
-    }
+    for (uint32_t i = tid; i < TABLE_WORDS; i += WG) (&sm.u.table[0][0])[i] = 0;
     if (tid == 0) sm.tile = atomicAdd(&a.tickets[a.round], 1u);
     __syncthreads();
 
     const uint32_t tile = sm.tile;
     const uint32_t base = tile * TILE;
     const uint32_t lim = a.n - base;   // keys in this tile (>= TILE except the last)
-
     const K* src = pick<K>(pl.src, (const K*)a.keys_in, (K*)a.keys_out, (K*)a.keys_tmp);
     const uint32_t* vsrc = KV ? pick<uint32_t>(pl.src, a.vals_in, a.vals_out, a.vals_tmp) : nullptr;
 
-    // Load: wave w owns keys [w*ITEMS*64, (w+1)*ITEMS*64) of the tile, one
-    // coalesced 64-key row per item.
-    const uint32_t wofs = wave * ITEMS * 64 + lane;
+    const uint32_t hofs = hw * ITEMS * 32 + hl;
     K k[ITEMS];
     uint32_t v[ITEMS];
-    uint32_t rk[ITEMS];
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
-        const uint32_t o = wofs + i * 64;
+        const uint32_t o = hofs + i * 32;
         k[i] = o < lim ? src[base + o] : K(0);
         if (KV) v[i] = o < lim ? vsrc[base + o] : 0u;
     }
 
-    // Stable rank inside the wave.  For each row, every lane ORs its lane bit
-    // into the slot of its digit; reading the slot back gives the set of lanes
-    // holding the same digit, and the number of those below this lane plus the
-    // wave's running count of the digit is the key's rank among equal digits.
-    uint64_t* bits = sm.u.bits[wave];
-    uint32_t* cnt = sm.cnt[wave];
-    const uint64_t lbit = 1ull << lane;
+    // count
+    uint32_t* row = sm.u.table[hw];
 #pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        const bool ok = wofs + i * 64 < lim;
-        const uint32_t d = digit_of(k[i], a.shift, a.mask);
-        if (ok) __hip_atomic_fetch_or(&bits[d], lbit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        wave_lds_order();
-        const uint64_t peers = ok ? __hip_atomic_load(&bits[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : 0ull;
-        const uint32_t before = __hip_atomic_load(&cnt[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        rk[i] = mbcnt64(peers, before);
-        wave_lds_order();
-        if (ok) {
-            __hip_atomic_fetch_add(&cnt[d], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            __hip_atomic_store(&bits[d], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        }
-        wave_lds_order();
-    }
+    for (int i = 0; i < ITEMS; ++i)
+        if (hofs + i * 32 < lim) atomicAdd(&row[digit_of(k[i], a.shift, a.mask)], 1u);
     __syncthreads();
 
-    // Digit threads: prefix over waves, publish the tile's counts, prefix over
-    // digits (where each digit starts inside the tile).
+    // publish
     uint32_t* region = (pl.ord & 1) ? a.state1 : a.state0;
     uint32_t* next_region = (pl.ord & 1) ? a.state0 : a.state1;
     uint32_t total = 0, tstart = 0;
+    uint32_t lb[LB_WINDOW];
     if (tid < R) {
 #pragma unroll
-        for (int w = 0; w < WAVES; ++w) {
-            uint32_t c = sm.cnt[w][tid];
-            sm.cnt[w][tid] = total;
+        for (int h = 0; h < HW; ++h) {
+            const uint32_t c = sm.u.table[h][tid];
+            sm.u.table[h][tid] = 0;          // the same rows hold the lane sets next
+            sm.base[h][tid] = (uint16_t)total;
             total += c;
         }
         st_agent(&region[(size_t)tile * R + tid], (tile == 0 ? kFlagPrefix : kFlagAggregate) | total);
-    }
-    if (tid < R) {
-        uint32_t incl = wave_inclusive_sum(total);
+        const uint32_t incl = wave_inclusive_sum(total);
         if (lane == 63) sm.wsum[wave] = incl;
         tstart = incl - total;
+#pragma unroll
+        for (int q = 0; q < LB_WINDOW; ++q)
+            lb[q] = (uint32_t)q < tile ? ld_agent(&region[(size_t)(tile - 1 - q) * R + tid]) : kFlagPrefix;
     }
     __syncthreads();
     if (tid < R) {
         for (uint32_t w = 0; w < wave; ++w) tstart += sm.wsum[w];
 #pragma unroll
-        for (int w = 0; w < WAVES; ++w) sm.cnt[w][tid] += tstart;
+        for (int h = 0; h < HW; ++h) sm.base[h][tid] = (uint16_t)(sm.base[h][tid] + tstart);
     }
     __syncthreads();
 
-    // Stage the tile in digit order.
+    // rank
+    uint32_t pos[ITEMS];
+    {
+        uint32_t* lanes = sm.u.table[hw];
+        uint16_t* hb = sm.base[hw];
+        const uint32_t bit = 1u << hl;
+        const uint32_t lowsel = lane < 32 ? ~0u : 0u;
 #pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        if (wofs + i * 64 < lim) {
-            const uint32_t pos = sm.cnt[wave][digit_of(k[i], a.shift, a.mask)] + rk[i];
-            sm.u.keys[pos] = k[i];
-            if (KV) sm.vals[pos] = v[i];
+        for (int i = 0; i < ITEMS; ++i) {
+            const bool ok = hofs + i * 32 < lim;
+            const uint32_t d = digit_of(k[i], a.shift, a.mask);
+            if (ok) __hip_atomic_fetch_or(&lanes[d], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            wave_lds_order();
+            const uint32_t m = ok ? __hip_atomic_load(&lanes[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : 0u;
+            const uint32_t b = hb[d];
+            pos[i] = __builtin_amdgcn_mbcnt_hi(m, __builtin_amdgcn_mbcnt_lo(m & lowsel, b));
+            wave_lds_order();
+            if (ok) {
+                hb[d] = (uint16_t)(b + __builtin_popcount(m));
+                __hip_atomic_store(&lanes[d], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+            wave_lds_order();
         }
     }
 
-    // Decoupled look-back: keys of this digit in all earlier tiles.
+    // lookback: fold predecessor words nearest first -- aggregates are added
+    // and passed over, the first inclusive prefix ends the walk, a word not
+    // yet published is polled again.  The first window was loaded before the
+    // ranking.
     if (tid < R) {
         uint32_t excl = 0;
         if (tile > 0) {
-            uint32_t j = tile - 1;
+            uint32_t j = tile;   // entries j-1, j-2, ... are still to be folded
             uint32_t spins = 0;
             for (;;) {
-                const uint32_t w = ld_agent(&region[(size_t)j * R + tid]);
-                const uint32_t f = w >> kFlagShift;
-                if (f == 0) {
+                uint32_t used = 0, pval = 0;
+                bool done = false;
+#pragma unroll
+                for (int q = 0; q < LB_WINDOW; ++q) {
+                    if (!done && used == (uint32_t)q) {
+                        const uint32_t f = lb[q] >> kFlagShift;
+                        if (f != 0) {
+                            excl += lb[q] & kCountMask;
+                            used = q + 1;
+                            done = f == (kFlagPrefix >> kFlagShift);
+                            pval = lb[q] & kCountMask;
+                        }
+                    }
+                }
+                if (done) {
+                    // Help: the aggregate-only tiles folded in this window now
+                    // have known inclusive prefixes; publish them so later
+                    // tiles stop their walks here.  The value is unique, so a
+                    // race with the owner's own store of it is harmless.
+                    uint32_t run = pval;
+#pragma unroll
+                    for (int q = LB_WINDOW - 2; q >= 0; --q) {
+                        if ((uint32_t)q + 1 < used) {
+                            run += lb[q] & kCountMask;
+                            st_agent(&region[(size_t)(j - 1 - q) * R + tid], kFlagPrefix | (run & kCountMask));
+                        }
+                    }
+                    break;
+                }
+                j -= used;
+                if (used == 0) {
                     // Give up after kSpinLimit polls, or at once if another
                     // tile already gave up, so the grid always drains.
                     if (++spins > kSpinLimit ||
@@ -345,11 +413,10 @@ __global__ __launch_bounds__(WG) void k_round(RoundArgs a)
                         break;
                     }
                     __builtin_amdgcn_s_sleep(1);
-                    continue;
                 }
-                excl += w & kCountMask;
-                if (f == (kFlagPrefix >> kFlagShift) || j == 0) break;
-                --j;
+#pragma unroll
+                for (int q = 0; q < LB_WINDOW; ++q)
+                    lb[q] = (uint32_t)q < j ? ld_agent(&region[(size_t)(j - 1 - q) * R + tid]) : kFlagPrefix;
             }
             st_agent(&region[(size_t)tile * R + tid], kFlagPrefix | ((excl + total) & kCountMask));
         }
@@ -358,19 +425,35 @@ __global__ __launch_bounds__(WG) void k_round(RoundArgs a)
     }
     __syncthreads();
 
-    // Scatter: consecutive threads write consecutive slots of a digit's run.
+    // scatter
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i)
+        if (hofs + i * 32 < lim) sm.u.keys[pos[i]] = k[i];
+    __syncthreads();
     K* dst = pick<K>(pl.dst, (const K*)a.keys_in, (K*)a.keys_out, (K*)a.keys_tmp);
-    uint32_t* vdst = KV ? pick<uint32_t>(pl.dst, a.vals_in, a.vals_out, a.vals_tmp) : nullptr;
+    uint32_t outi[KV ? ITEMS : 1];
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const uint32_t p = i * WG + tid;
+        uint32_t o = a.n;
         if (p < lim) {
             const K key = sm.u.keys[p];
-            const uint32_t o = sm.goff[digit_of(key, a.shift, a.mask)] + p;
-            if (o < a.n) {  // always true unless a look-back wait was abandoned
-                dst[o] = key;
-                if (KV) vdst[o] = sm.vals[p];
-            }
+            o = sm.goff[digit_of(key, a.shift, a.mask)] + p;
+            if (o < a.n) dst[o] = key;   // always true unless a look-back wait was abandoned
+        }
+        if (KV) outi[i] = o;
+    }
+    if (KV) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i)
+            if (hofs + i * 32 < lim) sm.u.vals[pos[i]] = v[i];
+        __syncthreads();
+        uint32_t* vdst = pick<uint32_t>(pl.dst, a.vals_in, a.vals_out, a.vals_tmp);
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t p = i * WG + tid;
+            if (p < lim && outi[i] < a.n) vdst[outi[i]] = sm.u.vals[p];
         }
     }
 }
@@ -419,8 +502,10 @@ hipError_t run(const void* keys_in, void* keys_out, const uint32_t* vals_in, uin
                        (uint32_t)(kHistReplicas * nr * R), tickets, nr, state0,
                        (size_t)L.ntiles * R);
     if (prof) profiler_mark(prof, stream, kKindHist, true);
+    if (prof) profiler_mark(prof, stream, kKindHist, true);
     hipLaunchKernelGGL(k_hist<K>, dim3(hist_grid(n)), dim3(kHistWG), 0, stream,
                        (const K*)keys_in, (uint32_t)n, (uint32_t)begin_bit, (uint32_t)end_bit, nr, hist);
+    if (prof) profiler_mark(prof, stream, kKindHist, false);
     if (prof) profiler_mark(prof, stream, kKindHist, false);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(R), 0, stream, (const uint32_t*)hist, nr,
                        (uint32_t)n, (int)in_place, bases, plan);
@@ -448,7 +533,9 @@ hipError_t run(const void* keys_in, void* keys_out, const uint32_t* vals_in, uin
         a.state1 = state1;
         a.err = dev_err;
         if (prof) profiler_mark(prof, stream, kKindRound, true);
+        if (prof) profiler_mark(prof, stream, kKindRound, true);
         hipLaunchKernelGGL((k_round<K, KV, WG, ITEMS>), dim3(L.ntiles), dim3(WG), 0, stream, a);
+        if (prof) profiler_mark(prof, stream, kKindRound, false);
         if (prof) profiler_mark(prof, stream, kKindRound, false);
     }
     return hipGetLastError();
