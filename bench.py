@@ -3,14 +3,16 @@
 
 Workload: one stable sort of n = 2^27 uint32 keys drawn uniformly over the full
 32-bit range (SplitMix64, seed 0x18081029202), keys only, with the radix-2^8
-LSD sort (PR4 of arXiv 1808.10292, Section 3.2): one digit-count kernel and four
-count-sort round kernels.  A step is one whole sort; inputs are resident in HBM
+LSD sort (PR4 of arXiv 1808.10292, Section 3.2): one all-digit count kernel,
+then per count-sort round a tile-count kernel, a tile-offset scan and a
+rank-and-scatter kernel.  A step is one whole sort; inputs are resident in HBM
 before timing starts and the output buffer is reused.
 
 Printed as one JSON line:
   value        whole-sort Gkeys/s (n / seconds per step)
-  roofline     the dominant kernel (a count-sort round): algorithmic bytes per
-               launch (read + write of every key, 2 n 4 B) over its average
+  roofline     the dominant kernel (the rank-and-scatter kernel of a round):
+               algorithmic bytes per launch (read + write of every key,
+               2 n 4 B) over its average
                duration from HIP events recorded on its stream during the timed
                steps, against MI355X's 8 TB/s; traffic = HBM bytes per launch
                from rocprofv3 FETCH_SIZE/WRITE_SIZE when the committed counter
@@ -30,7 +32,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBPS = 8000.0
 METRIC = "Gkeys/s + % HBM roofline, 2^27 uint32; batched vs plain; p50/p99 latency"
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_round_u32_keys_2p27_counters.md")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_scatter_u32_keys_2p27_counters.md")
 ROUND_SOURCE = os.path.join(ROOT, "paper_1808_10292_amd", "csrc", "lsd_r8.hip")
 
 
@@ -84,6 +86,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="minimum CPU time spent timing the oracle (0 disables)")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--mode", choices=("sort", "copy"), default="sort",
+                    help="copy: time the library's plain device copy of the same bytes "
+                         "(calibrates rocprofv3 byte counters against a known transfer)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -105,6 +110,14 @@ def main():
     out = torch.empty_like(dk)
     torch.cuda.synchronize()
 
+    if args.mode == "copy":
+        # begin_bit == end_bit: nothing to compare, the sort is a plain copy
+        sec = time_steps(lambda: rsort.rsort_sort(dk, out, begin_bit=0, end_bit=0),
+                         args.steps, args.warmup, torch)
+        print(json.dumps({"mode": "copy", "bytes_moved": 2 * n * 4, "ms": round(sec * 1e3, 4),
+                          "gbps": round(2 * n * 4 / sec / 1e9, 1)}), flush=True)
+        return
+
     def step():
         rsort.rsort_sort(dk, out, algo="lsd8")
 
@@ -121,6 +134,8 @@ def main():
     sec = (time.perf_counter() - t0) / args.steps
     launches, round_ms = rsort.rsort_profile_read(rsort.RSORT_KERNEL_ROUND)
     hl, hist_ms = rsort.rsort_profile_read(rsort.RSORT_KERNEL_HIST)
+    cl, count_ms = rsort.rsort_profile_read(rsort.RSORT_KERNEL_COUNT)
+    sl, scan_ms = rsort.rsort_profile_read(rsort.RSORT_KERNEL_TILESCAN)
     rsort.rsort_profile_enable(False)
     rsort.rsort_synchronize()
 
@@ -156,9 +171,12 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBPS, 4),
                      "traffic": traffic,
-                     "kernel": "k_round<uint32,keys-only> (one count-sort round)",
+                     "kernel": "k_scatter<uint32, keys-only> (rank and route of one count-sort round)",
                      "algorithmic_bytes_per_launch": bytes_per_round,
                      "avg_launch_ms": round(round_avg_ms, 5), "timed_launches": launches},
+        "per_round_ms": {"count": round(count_ms / max(cl, 1), 5),
+                         "tilescan": round(scan_ms / max(sl, 1), 5),
+                         "scatter": round(round_avg_ms, 5)},
         "whole_sort": {"algorithmic_bytes": n * 4 + 4 * bytes_per_round,
                        "gbps": round((n * 4 + 4 * bytes_per_round) / sec / 1e9, 1),
                        "hist_kernel_ms": round(hist_ms / max(hl, 1), 5)},

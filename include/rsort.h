@@ -130,8 +130,10 @@ int rsort_synchronize(rsort_ctx* ctx, void* stream);
  * HIP event on its stream immediately before and after each kernel of the
  * kinds below; enabling (or disabling) resets the totals. */
 enum rsort_kernel_kind {
-    RSORT_KERNEL_ROUND = 0,   /* one count-sort round (rank, look-back, scatter) */
-    RSORT_KERNEL_HIST = 1     /* the digit-counting kernel                        */
+    RSORT_KERNEL_ROUND = 0,     /* rank-and-scatter kernel of a count-sort round  */
+    RSORT_KERNEL_HIST = 1,      /* all-rounds digit counting before the rounds    */
+    RSORT_KERNEL_COUNT = 2,     /* per-tile digit counts of a round               */
+    RSORT_KERNEL_TILESCAN = 3   /* exclusive scan of the tile counts of a round   */
 };
 int rsort_profile_enable(rsort_ctx* ctx, int enable);
 

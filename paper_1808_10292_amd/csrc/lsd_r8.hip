@@ -1,20 +1,32 @@
 // PR4 on gfx950: LSD radix sort with radix 2^8, one stable count-sort round
-// per 8-bit digit (arXiv 1808.10292, Section 3.2, PR4 / eq. Tp4).
+// per 8-bit digit (arXiv 1808.10292, Section 3.2, PR4 and eq. Tp / Tp4).
 //
-// The paper's round (count digits, exchange the p x r counts, route keys) maps
-// onto one MI355X like this:
-//   k_hist   one read of the keys counts every digit of every round at once
-//            (the count loops of all rounds; LDS histograms, 8 global copies);
-//   k_scan   exclusive prefix of each round's 256 counts = where each digit's
-//            bucket starts in the output, plus the round plan (identity rounds,
-//            i.e. one digit value holding all n keys, are skipped);
-//   k_round  one launch per round.  Each workgroup takes one tile of keys in
-//            ticket order, ranks them stably by digit in LDS, learns how many
-//            keys of each digit all earlier tiles hold through a decoupled
-//            look-back over per-(tile, digit) words (the paper's count
-//            exchange), stages the tile in digit order in LDS and writes every
-//            key (and payload) once to its final slot (the routing).
-// Keys and payloads are read once and written once per round.
+// The paper's parallel round has three steps: every processor counts the
+// digits of its block of keys, the p x r counts are exchanged so that each
+// processor knows where its keys of each digit go, and the keys are routed
+// there.  On one MI355X a "processor" is a tile of keys handled by one
+// workgroup, and a round is three kernels:
+//
+//   k_count    per-tile digit counts (the count loop; one read of the keys);
+//   k_tilescan the count exchange: for every tile t and digit v, the output
+//              index of the tile's first key of digit v, i.e. the digit's
+//              global start plus the keys of v in tiles before t (a scan over
+//              tiles per digit, blocks of tiles chained by a decoupled
+//              look-back);
+//   k_scatter  the output loop: the tile is ranked stably by digit in LDS,
+//              staged in digit order and written out -- consecutive threads
+//              write consecutive slots of each digit's run -- with the payload
+//              moved alongside.
+//
+// Before the first round, k_hist counts every digit of every round in a single
+// read of the keys and k_plan turns those counts into the digit starts of
+// each round and the round plan: a round whose digit is the same for all n
+// keys is the identity and is skipped.
+//
+// No tile of a round waits for another tile: the dependencies are kernel
+// boundaries, except the chain of tile blocks inside k_tilescan.
+#include <algorithm>
+
 #include "device_common.h"
 #include "rsort_internal.h"
 
@@ -23,8 +35,8 @@ namespace {
 
 constexpr uint32_t R = 256;  // radix
 
-// Tile shape: WG threads, ITEMS keys per thread (tile = WG * ITEMS keys), and
-// the number of predecessor words a look-back step reads at once.
+// Tile shape of the count and scatter kernels: WG threads, ITEMS keys per
+// thread (tile = WG * ITEMS keys).
 #ifndef RSORT_R8_WG32
 #define RSORT_R8_WG32 512
 #endif
@@ -37,12 +49,31 @@ constexpr uint32_t R = 256;  // radix
 #ifndef RSORT_R8_ITEMS64
 #define RSORT_R8_ITEMS64 8
 #endif
+// Scatter grid: 1 = persistent (resident workgroups loop over the tiles and
+// prefetch the next tile), 0 = one workgroup per tile.
+#ifndef RSORT_SCATTER_PERSIST
+#define RSORT_SCATTER_PERSIST 0
+#endif
+// Scatter ranking order: 1 = rank, then bases; 0 = count, bases, then rank;
+// -1 = rank first with payloads, count first without (the faster of each).
+#ifndef RSORT_RANK_FIRST
+#define RSORT_RANK_FIRST -1
+#endif
+// Waves per SIMD the scatter kernel is compiled for (bounds its registers).
+#ifndef RSORT_R8_WAVES_PER_EU
+#define RSORT_R8_WAVES_PER_EU 8
+#endif
+#ifndef RSORT_R8_WAVES_PER_EU_KV
+#define RSORT_R8_WAVES_PER_EU_KV 5
+#endif
+// Tiles per block of the tile scan, and predecessor blocks read per look-back step.
+#ifndef RSORT_SCAN_BLOCK
+#define RSORT_SCAN_BLOCK 32
+#endif
 #ifndef LB_WINDOW
 #define LB_WINDOW 4
 #endif
-#ifndef RSORT_R8_WAVES_PER_EU
-#define RSORT_R8_WAVES_PER_EU 6
-#endif
+
 template <typename K> struct R8Config;
 template <> struct R8Config<uint32_t> {
     static constexpr int WG = RSORT_R8_WG32;
@@ -55,6 +86,7 @@ template <> struct R8Config<uint64_t> {
 
 constexpr int kHistWG = 256;
 constexpr int kHistUnroll = 8;
+constexpr uint32_t kScanBlock = RSORT_SCAN_BLOCK;
 
 struct RoundArgs {
     const void* keys_in;
@@ -67,13 +99,25 @@ struct RoundArgs {
     uint32_t shift;
     uint32_t mask;
     uint32_t round;
-    const uint32_t* bases;   // [round][256]
+    uint32_t ntiles;
+    const uint32_t* bases;   // [round][256] start of each digit's bucket
     const RoundPlan* plan;
-    uint32_t* tickets;       // [round]
-    uint32_t* state0;        // [ntiles][256], rounds with even ordinal
-    uint32_t* state1;        // [ntiles][256], rounds with odd ordinal
+    uint32_t* counts;        // [ntiles][256] tile counts, then tile output starts
+    uint32_t* blk_state;     // [round][nblocks][256] look-back words of k_tilescan
+    uint32_t* tickets;       // [round] block tickets of k_tilescan
     uint32_t* err;
 };
+
+// Output stores of the scatter: streaming (non-temporal) when RSORT_NT_STORES.
+#ifndef RSORT_NT_STORES
+#define RSORT_NT_STORES 0
+#endif
+template <typename T>
+__device__ __forceinline__ void store_out(T* p, T v)
+{
+    if (RSORT_NT_STORES) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
 
 template <typename T>
 __device__ __forceinline__ T* pick(int sel, const T* in, T* out, T* tmp)
@@ -81,16 +125,27 @@ __device__ __forceinline__ T* pick(int sel, const T* in, T* out, T* tmp)
     return sel == 0 ? const_cast<T*>(in) : (sel == 1 ? out : tmp);
 }
 
-// Zero the global histogram copies, the tile tickets and the look-back words
-// of the first round.
+// Tile handled by this workgroup.  Workgroups are dealt to the 8 XCDs in turn,
+// so with ntiles a multiple of 8, tile = (block mod 8) * (ntiles / 8) + block / 8
+// gives every XCD a contiguous run of tiles: neighbouring tiles, whose output
+// runs share cache lines, then sit behind the same L2.  Other grids keep the
+// plain order.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t ntiles)
+{
+    const uint32_t b = blockIdx.x;
+    if ((ntiles & 7) != 0) return b;
+    return (b & 7) * (ntiles >> 3) + (b >> 3);
+}
+
+// Zero the global histogram copies, the block tickets and the tile-scan words.
 __global__ void k_init(uint32_t* hist, uint32_t hist_words, uint32_t* tickets,
-                       uint32_t nrounds, uint32_t* state0, size_t state_words)
+                       uint32_t nrounds, uint32_t* blk_state, size_t state_words)
 {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (size_t i = g; i < hist_words; i += stride) hist[i] = 0;
     for (size_t i = g; i < nrounds; i += stride) tickets[i] = 0;
-    for (size_t i = g; i < state_words; i += stride) state0[i] = 0;
+    for (size_t i = g; i < state_words; i += stride) blk_state[i] = 0;
 }
 
 // Counts of every 8-bit digit of [begin_bit, end_bit) in one pass over the
@@ -158,7 +213,7 @@ __device__ __forceinline__ uint32_t block256_inclusive_sum(uint32_t x, uint32_t*
 
 // Round bases (exclusive prefix of each round's counts) and the round plan.
 // One workgroup of 256 threads, thread t owns digit value t.
-__global__ __launch_bounds__(R) void k_scan(const uint32_t* hist, uint32_t nrounds, uint32_t n,
+__global__ __launch_bounds__(R) void k_plan(const uint32_t* hist, uint32_t nrounds, uint32_t n,
                                             int in_place, uint32_t* bases, RoundPlan* plan)
 {
     __shared__ uint32_t wsum[4];
@@ -232,45 +287,159 @@ __global__ void k_precopy(const RoundPlan* plan, const K* keys, K* keys_tmp,
     }
 }
 
-// One stable count-sort round over all tiles (see the file comment).
+// ---------------------------------------------------------------------------
+// k_count: counts[tile][v] = keys of digit v in the tile.
+//
+// Every lane counts into its own column of a [256][32] table (lane l of every
+// wave uses column l mod 32), so the 32 lanes of a half-wave always hit 32
+// different LDS banks; the columns are summed at the end.
+template <typename K, int WG, int ITEMS>
+__global__ __launch_bounds__(WG) void k_count(RoundArgs a)
+{
+    constexpr uint32_t TILE = (uint32_t)WG * ITEMS;
+    __shared__ uint32_t h[R * 32];
+    const RoundPlan pl = a.plan[a.round];
+    if (!pl.exec) return;
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t i = tid; i < R * 32 / 4; i += WG) ((uint4*)h)[i] = make_uint4(0, 0, 0, 0);
+    __syncthreads();
+    const uint32_t tile = xcd_tile(a.ntiles);
+    const uint32_t base = tile * TILE;
+    const uint32_t lim = min(TILE, a.n - base);
+    const K* src = pick<K>(pl.src, (const K*)a.keys_in, (K*)a.keys_out, (K*)a.keys_tmp) + base;
+    K k[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t o = i * WG + tid;
+        k[i] = o < lim ? src[o] : K(0);
+    }
+    const uint32_t col = tid & 31;
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i)
+        if (i * WG + tid < lim) atomicAdd(&h[digit_of(k[i], a.shift, a.mask) * 32 + col], 1u);
+    __syncthreads();
+    for (uint32_t v = tid; v < R; v += WG) {
+        const uint4* r4 = (const uint4*)&h[v * 32];
+        uint32_t s = 0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const uint4 x = r4[(q + v) & 7];   // rotate the start so threads spread over banks
+            s += x.x + x.y + x.z + x.w;
+        }
+        a.counts[(size_t)tile * R + v] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_tilescan: replaces counts[t][v] by bases[v] + sum of counts[t'][v] over
+// t' < t.  Workgroup = block of kScanBlock tiles taken in ticket order; thread
+// v sums its digit over the block, publishes the block total, folds the totals
+// of earlier blocks by decoupled look-back (a packed flag+count word per block
+// and digit), publishes the inclusive prefix and rewrites its column.
+__global__ __launch_bounds__(R) void k_tilescan(RoundArgs a)
+{
+    __shared__ uint32_t blk_s;
+    const RoundPlan pl = a.plan[a.round];
+    if (!pl.exec) return;
+    const uint32_t v = threadIdx.x;
+    if (v == 0) blk_s = atomicAdd(&a.tickets[a.round], 1u);
+    __syncthreads();
+    const uint32_t blk = blk_s;
+    const uint32_t nblocks = (a.ntiles + kScanBlock - 1) / kScanBlock;
+    uint32_t* state = a.blk_state + (size_t)a.round * nblocks * R;
+    const uint32_t t0 = blk * kScanBlock;
+    const uint32_t t1 = min(a.ntiles, t0 + kScanBlock);
+    uint32_t* col = a.counts + v;
+
+    uint32_t c[kScanBlock];
+    uint32_t total = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < kScanBlock; ++i) {
+        c[i] = t0 + i < t1 ? col[(size_t)(t0 + i) * R] : 0u;
+        total += c[i];
+    }
+    st_agent(&state[(size_t)blk * R + v], (blk == 0 ? kFlagPrefix : kFlagAggregate) | total);
+
+    uint32_t excl = 0;
+    if (blk > 0) {
+        uint32_t j = blk;   // entries j-1, j-2, ... are still to be folded
+        uint32_t spins = 0;
+        for (;;) {
+            uint32_t lb[LB_WINDOW];
+#pragma unroll
+            for (int q = 0; q < LB_WINDOW; ++q)
+                lb[q] = (uint32_t)q < j ? ld_agent(&state[(size_t)(j - 1 - q) * R + v]) : kFlagPrefix;
+            uint32_t used = 0;
+            bool done = false;
+#pragma unroll
+            for (int q = 0; q < LB_WINDOW; ++q) {
+                if (!done && used == (uint32_t)q) {
+                    const uint32_t f = lb[q] >> kFlagShift;
+                    if (f != 0) {
+                        excl += lb[q] & kCountMask;
+                        used = q + 1;
+                        done = f == (kFlagPrefix >> kFlagShift);
+                    }
+                }
+            }
+            if (done) break;
+            j -= used;
+            if (used == 0) {
+                // Give up after kSpinLimit polls, or at once if another
+                // workgroup already gave up, so the grid always drains.
+                if (++spins > kSpinLimit ||
+                    ((spins & 255u) == 0 && (ld_agent(a.err) & kErrLookbackTimeout))) {
+                    atomicOr(a.err, (uint32_t)kErrLookbackTimeout);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        st_agent(&state[(size_t)blk * R + v], kFlagPrefix | ((excl + total) & kCountMask));
+    }
+    uint32_t run = a.bases[a.round * R + v] + excl;
+#pragma unroll
+    for (uint32_t i = 0; i < kScanBlock; ++i) {
+        if (t0 + i < t1) col[(size_t)(t0 + i) * R] = run;
+        run += c[i];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_scatter: one stable count-sort round of one tile.
 //
 // Layout: the tile is split among half-waves (32 lanes); half-wave h owns the
 // contiguous keys [h*ITEMS*32, (h+1)*ITEMS*32) of the tile, row i lane l at
 // h*ITEMS*32 + i*32 + (l & 31), so "earlier in the input" is lexicographic
-// (h, i, l) -- the order the ranking below preserves.
-//
-// Phases of a tile:
-//   count   each half-wave counts its digits into its own LDS row;
-//   publish digit thread v sums the rows, publishes the tile's count of v
-//           (aggregate) for later tiles, turns the rows into per-half-wave
-//           slot bases, and issues the first look-back loads;
-//   rank    each half-wave ranks its keys in row order: lanes OR their bit
-//           into the slot of their digit, the set of lanes below with the same
-//           digit gives the rank, and the digit's base advances by the set size;
-//   lookback digit threads finish folding predecessor words into the number of
-//           keys of v in all earlier tiles, and publish the inclusive prefix;
-//   scatter the tile is staged in digit order and written out, consecutive
-//           threads writing consecutive slots of a digit's run (payloads in a
-//           second staging pass through the same LDS).
+// (h, i, l) -- the order the ranking preserves.
+// Each half-wave has one 64-bit slot per digit value: the set of its lanes
+// holding that digit in the current row (low word) and the number of its keys
+// of that digit in earlier rows (high word).
+//   rank   row by row, lanes OR their bit into the slot of their digit, read
+//          the slot back -- the lanes below with the same digit plus the count
+//          give the key's rank among the half-wave's keys of that digit -- and
+//          write the slot back as {no lanes, count + lanes in the set};
+//   bases  digit thread v turns the counts of all half-waves into slot bases
+//          inside the tile (prefix over half-waves plus the tile's prefix over
+//          digits), written over the counts;
+//   stage  each key goes to LDS at base + rank, the tile now in digit order;
+//   scatter consecutive threads write consecutive slots of a digit's run; the
+//          payloads follow in a second staging pass through the same LDS.
 template <typename K, bool KV, int WG, int ITEMS>
-__global__ __launch_bounds__(WG, RSORT_R8_WAVES_PER_EU) void k_round(RoundArgs a)
+__global__ __launch_bounds__(WG, KV ? RSORT_R8_WAVES_PER_EU_KV : RSORT_R8_WAVES_PER_EU) void k_scatter(RoundArgs a)
 {
     constexpr int HW = WG / 32;                 // half-waves
     constexpr uint32_t TILE = (uint32_t)WG * ITEMS;
-    constexpr uint32_t STAGE_WORDS = TILE * sizeof(K) / 4;
-    constexpr uint32_t TABLE_WORDS = HW * R;
-    static_assert(STAGE_WORDS >= TABLE_WORDS, "staging must cover the count table");
-    static_assert(TILE <= 65536, "16-bit slot bases");
+    constexpr bool rank_first = RSORT_RANK_FIRST < 0 ? KV : RSORT_RANK_FIRST != 0;
+    static_assert(TILE * sizeof(K) >= HW * R * sizeof(uint2), "staging must cover the slots");
     struct Smem {
         union {
-            uint32_t table[HW][R];   // counts, then lane sets of the ranking
-            K keys[TILE];            // staging: the tile in digit order
-            uint32_t vals[TILE];     // staging of the payloads (second pass)
+            uint2 slot[HW][R];           // {lane set, count}, then {-, slot base}
+            K keys[TILE];                // staging: the tile in digit order
+            uint32_t vals[TILE];         // staging of the payloads (second pass)
         } u;
-        uint16_t base[HW][R];        // next slot of digit v for half-wave h
-        uint32_t goff[R];            // output index of tile slot 0 of each digit
+        uint32_t goff[R];                // output index of tile slot 0 of each digit
         uint32_t wsum[4];
-        uint32_t tile;
     };
     __shared__ Smem sm;
 
@@ -282,187 +451,193 @@ __global__ __launch_bounds__(WG, RSORT_R8_WAVES_PER_EU) void k_round(RoundArgs a
     const uint32_t wave = tid >> 6;
     const uint32_t hw = tid >> 5;
     const uint32_t hl = tid & 31;
-
-    for (uint32_t i = tid; i < TABLE_WORDS; i += WG) (&sm.u.table[0][0])[i] = 0;
-    if (tid == 0) sm.tile = atomicAdd(&a.tickets[a.round], 1u);
-    __syncthreads();
-
-    const uint32_t tile = sm.tile;
-    const uint32_t base = tile * TILE;
-    const uint32_t lim = a.n - base;   // keys in this tile (>= TILE except the last)
+    const uint32_t hofs = hw * ITEMS * 32 + hl;
     const K* src = pick<K>(pl.src, (const K*)a.keys_in, (K*)a.keys_out, (K*)a.keys_tmp);
     const uint32_t* vsrc = KV ? pick<uint32_t>(pl.src, a.vals_in, a.vals_out, a.vals_tmp) : nullptr;
+    K* dst = pick<K>(pl.dst, (const K*)a.keys_in, (K*)a.keys_out, (K*)a.keys_tmp);
+    uint32_t* vdst = KV ? pick<uint32_t>(pl.dst, a.vals_in, a.vals_out, a.vals_tmp) : nullptr;
 
-    const uint32_t hofs = hw * ITEMS * 32 + hl;
-    K k[ITEMS];
-    uint32_t v[ITEMS];
-#pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        const uint32_t o = hofs + i * 32;
-        k[i] = o < lim ? src[base + o] : K(0);
-        if (KV) v[i] = o < lim ? vsrc[base + o] : 0u;
-    }
-
-    // count
-    uint32_t* row = sm.u.table[hw];
-#pragma unroll
-    for (int i = 0; i < ITEMS; ++i)
-        if (hofs + i * 32 < lim) atomicAdd(&row[digit_of(k[i], a.shift, a.mask)], 1u);
-    __syncthreads();
-
-    // publish
-    uint32_t* region = (pl.ord & 1) ? a.state1 : a.state0;
-    uint32_t* next_region = (pl.ord & 1) ? a.state0 : a.state1;
-    uint32_t total = 0, tstart = 0;
-    uint32_t lb[LB_WINDOW];
-    if (tid < R) {
-#pragma unroll
-        for (int h = 0; h < HW; ++h) {
-            const uint32_t c = sm.u.table[h][tid];
-            sm.u.table[h][tid] = 0;          // the same rows hold the lane sets next
-            sm.base[h][tid] = (uint16_t)total;
-            total += c;
-        }
-        st_agent(&region[(size_t)tile * R + tid], (tile == 0 ? kFlagPrefix : kFlagAggregate) | total);
-        const uint32_t incl = wave_inclusive_sum(total);
-        if (lane == 63) sm.wsum[wave] = incl;
-        tstart = incl - total;
-#pragma unroll
-        for (int q = 0; q < LB_WINDOW; ++q)
-            lb[q] = (uint32_t)q < tile ? ld_agent(&region[(size_t)(tile - 1 - q) * R + tid]) : kFlagPrefix;
-    }
-    __syncthreads();
-    if (tid < R) {
-        for (uint32_t w = 0; w < wave; ++w) tstart += sm.wsum[w];
-#pragma unroll
-        for (int h = 0; h < HW; ++h) sm.base[h][tid] = (uint16_t)(sm.base[h][tid] + tstart);
-    }
-    __syncthreads();
-
-    // rank
-    uint32_t pos[ITEMS];
-    {
-        uint32_t* lanes = sm.u.table[hw];
-        uint16_t* hb = sm.base[hw];
-        const uint32_t bit = 1u << hl;
-        const uint32_t lowsel = lane < 32 ? ~0u : 0u;
+    auto load = [&](uint32_t t, K (&kk)[ITEMS], uint32_t (&vv)[ITEMS]) {
+        const uint32_t base = t * TILE;
+        const uint32_t lim = a.n - base;
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
-            const bool ok = hofs + i * 32 < lim;
-            const uint32_t d = digit_of(k[i], a.shift, a.mask);
-            if (ok) __hip_atomic_fetch_or(&lanes[d], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            wave_lds_order();
-            const uint32_t m = ok ? __hip_atomic_load(&lanes[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : 0u;
-            const uint32_t b = hb[d];
-            pos[i] = __builtin_amdgcn_mbcnt_hi(m, __builtin_amdgcn_mbcnt_lo(m & lowsel, b));
-            wave_lds_order();
-            if (ok) {
-                hb[d] = (uint16_t)(b + __builtin_popcount(m));
-                __hip_atomic_store(&lanes[d], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            }
-            wave_lds_order();
+            const uint32_t o = hofs + i * 32;
+            kk[i] = o < lim ? src[base + o] : K(0);
+            if (KV) vv[i] = o < lim ? vsrc[base + o] : 0u;
         }
-    }
+    };
 
-    // lookback: fold predecessor words nearest first -- aggregates are added
-    // and passed over, the first inclusive prefix ends the walk, a word not
-    // yet published is polled again.  The first window was loaded before the
-    // ranking.
-    if (tid < R) {
-        uint32_t excl = 0;
-        if (tile > 0) {
-            uint32_t j = tile;   // entries j-1, j-2, ... are still to be folded
-            uint32_t spins = 0;
-            for (;;) {
-                uint32_t used = 0, pval = 0;
-                bool done = false;
-#pragma unroll
-                for (int q = 0; q < LB_WINDOW; ++q) {
-                    if (!done && used == (uint32_t)q) {
-                        const uint32_t f = lb[q] >> kFlagShift;
-                        if (f != 0) {
-                            excl += lb[q] & kCountMask;
-                            used = q + 1;
-                            done = f == (kFlagPrefix >> kFlagShift);
-                            pval = lb[q] & kCountMask;
-                        }
-                    }
-                }
-                if (done) {
-                    // Help: the aggregate-only tiles folded in this window now
-                    // have known inclusive prefixes; publish them so later
-                    // tiles stop their walks here.  The value is unique, so a
-                    // race with the owner's own store of it is harmless.
-                    uint32_t run = pval;
-#pragma unroll
-                    for (int q = LB_WINDOW - 2; q >= 0; --q) {
-                        if ((uint32_t)q + 1 < used) {
-                            run += lb[q] & kCountMask;
-                            st_agent(&region[(size_t)(j - 1 - q) * R + tid], kFlagPrefix | (run & kCountMask));
-                        }
-                    }
-                    break;
-                }
-                j -= used;
-                if (used == 0) {
-                    // Give up after kSpinLimit polls, or at once if another
-                    // tile already gave up, so the grid always drains.
-                    if (++spins > kSpinLimit ||
-                        ((spins & 255u) == 0 && (ld_agent(a.err) & kErrLookbackTimeout))) {
-                        atomicOr(a.err, (uint32_t)kErrLookbackTimeout);
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
-                }
-#pragma unroll
-                for (int q = 0; q < LB_WINDOW; ++q)
-                    lb[q] = (uint32_t)q < j ? ld_agent(&region[(size_t)(j - 1 - q) * R + tid]) : kFlagPrefix;
-            }
-            st_agent(&region[(size_t)tile * R + tid], kFlagPrefix | ((excl + total) & kCountMask));
-        }
-        next_region[(size_t)tile * R + tid] = 0u;
-        sm.goff[tid] = a.bases[a.round * R + tid] + excl - tstart;
-    }
-    __syncthreads();
-
-    // scatter
-#pragma unroll
-    for (int i = 0; i < ITEMS; ++i)
-        if (hofs + i * 32 < lim) sm.u.keys[pos[i]] = k[i];
-    __syncthreads();
-    K* dst = pick<K>(pl.dst, (const K*)a.keys_in, (K*)a.keys_out, (K*)a.keys_tmp);
-    uint32_t outi[KV ? ITEMS : 1];
-#pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        const uint32_t p = i * WG + tid;
-        uint32_t o = a.n;
-        if (p < lim) {
-            const K key = sm.u.keys[p];
-            o = sm.goff[digit_of(key, a.shift, a.mask)] + p;
-            if (o < a.n) dst[o] = key;   // always true unless a look-back wait was abandoned
-        }
-        if (KV) outi[i] = o;
-    }
-    if (KV) {
+    // One tile whose keys are in k/v; the keys of tile tn (if any) are loaded
+    // into kn/vn once k has been counted, so that those loads are in flight
+    // while this tile is ranked, staged and written.
+    auto process = [&](uint32_t tile, K (&k)[ITEMS], uint32_t (&v)[ITEMS], uint32_t tn,
+                       K (&kn)[ITEMS], uint32_t (&vn)[ITEMS]) {
+        const uint32_t base = tile * TILE;
+        const uint32_t lim = a.n - base;   // keys in this tile (>= TILE except the last)
+        for (uint32_t i = tid; i < HW * R / 2; i += WG)
+            ((uint4*)&sm.u.slot[0][0])[i] = make_uint4(0, 0, 0, 0);
+        uint32_t toff = 0;
+        if (tid < R) toff = a.counts[(size_t)tile * R + tid];
         __syncthreads();
+
+        // Rank row by row; the high word of a slot is advanced by the lanes of
+        // the row that hold its digit.  Gives each key's rank plus the word's
+        // value before the key's row.
+        uint32_t pos[ITEMS];
+        auto rank = [&]() {
+            uint2* sl = sm.u.slot[hw];
+            const uint32_t bit = 1u << hl;
+            const uint32_t lowsel = lane < 32 ? ~0u : 0u;
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                const bool ok = hofs + i * 32 < lim;
+                const uint32_t d = digit_of(k[i], a.shift, a.mask);
+                if (ok) __hip_atomic_fetch_or(&sl[d].x, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                wave_lds_order();
+                const uint64_t s = ok ? __hip_atomic_load((uint64_t*)&sl[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : 0ull;
+                const uint32_t m = (uint32_t)s, c = (uint32_t)(s >> 32);
+                pos[i] = __builtin_amdgcn_mbcnt_hi(m, __builtin_amdgcn_mbcnt_lo(m & lowsel, c));
+                wave_lds_order();
+                if (ok)
+                    __hip_atomic_store((uint64_t*)&sl[d], (uint64_t)(c + __builtin_popcount(m)) << 32,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                wave_lds_order();
+            }
+        };
+
+        if (rank_first) {
+            // rank with counts starting at zero; the counts end up in the slots
+            rank();
+        } else {
+            // count first: the slots' high words get the per-half-wave counts
+            uint2* sl = sm.u.slot[hw];
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i)
+                if (hofs + i * 32 < lim) atomicAdd(&sl[digit_of(k[i], a.shift, a.mask)].y, 1u);
+        }
+        if (RSORT_SCATTER_PERSIST && tn < a.ntiles) load(tn, kn, vn);
+        __syncthreads();
+
+        // bases
+        uint32_t run = 0;
+        if (tid < R) {
+            uint32_t total = 0;
+#pragma unroll
+            for (int h = 0; h < HW; ++h) total += sm.u.slot[h][tid].y;
+            const uint32_t incl = wave_inclusive_sum(total);
+            if (lane == 63) sm.wsum[wave] = incl;
+            run = incl - total;
+        }
+        __syncthreads();
+        if (tid < R) {
+            for (uint32_t w = 0; w < wave; ++w) run += sm.wsum[w];
+            sm.goff[tid] = toff - run;
+#pragma unroll
+            for (int h = 0; h < HW; ++h) {
+                const uint32_t c = sm.u.slot[h][tid].y;
+                sm.u.slot[h][tid].y = run;
+                run += c;
+            }
+        }
+        __syncthreads();
+        if (rank_first) {
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                // Recompute the digit here rather than keep 16 slot addresses
+                // alive across the bases phase (registers limit occupancy).
+                __asm__ volatile("" : "+v"(k[i]));
+                pos[i] += sm.u.slot[hw][digit_of(k[i], a.shift, a.mask)].y;
+            }
+        } else {
+            rank();   // the high words now start at the slot bases
+        }
+        __syncthreads();
+
+        // scatter
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i)
-            if (hofs + i * 32 < lim) sm.u.vals[pos[i]] = v[i];
+            if (hofs + i * 32 < lim) sm.u.keys[pos[i]] = k[i];
         __syncthreads();
-        uint32_t* vdst = pick<uint32_t>(pl.dst, a.vals_in, a.vals_out, a.vals_tmp);
+        uint32_t outi[KV ? ITEMS : 1];
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
             const uint32_t p = i * WG + tid;
-            if (p < lim && outi[i] < a.n) vdst[outi[i]] = sm.u.vals[p];
+            uint32_t o = a.n;
+            if (p < lim) {
+                const K key = sm.u.keys[p];
+                o = sm.goff[digit_of(key, a.shift, a.mask)] + p;
+                if (o < a.n) store_out(&dst[o], key);   // always true unless a tile-scan wait was abandoned
+            }
+            if (KV) outi[i] = o;
         }
+        if (KV) {
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i)
+                if (hofs + i * 32 < lim) sm.u.vals[pos[i]] = v[i];
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                const uint32_t p = i * WG + tid;
+                if (p < lim && outi[i] < a.n) store_out(&vdst[outi[i]], sm.u.vals[p]);
+            }
+        }
+        __syncthreads();   // staging and goff are free for the next tile
+    };
+
+    // Tile sequence of this workgroup: with a grid smaller than the tile count
+    // each workgroup loops.  When both counts are multiples of 8 every XCD owns
+    // a contiguous eighth of the tiles (blocks are dealt to XCDs in turn), so
+    // neighbouring tiles write their shared cache lines through the same L2.
+    const uint32_t b = blockIdx.x, G = gridDim.x;
+    const bool xcd = (a.ntiles & 7) == 0 && (G & 7) == 0;
+    const uint32_t per = a.ntiles >> 3, g8 = G >> 3, x = b & 7;
+    uint32_t tile = xcd ? x * per + (b >> 3) : b;
+    auto next_of = [&](uint32_t t) -> uint32_t {
+        if (xcd) {
+            const uint32_t l = t - x * per + g8;
+            return l < per ? x * per + l : a.ntiles;
+        }
+        return t + G < a.ntiles ? t + G : a.ntiles;
+    };
+    if (tile >= a.ntiles) return;
+
+    K ka[ITEMS];
+    uint32_t va[ITEMS];
+    load(tile, ka, va);
+    if constexpr (!RSORT_SCATTER_PERSIST) {
+        process(tile, ka, va, a.ntiles, ka, va);
+        return;
+    }
+    K kb[ITEMS];
+    uint32_t vb[ITEMS];
+    for (;;) {
+        uint32_t tn = next_of(tile);
+        process(tile, ka, va, tn, kb, vb);
+        tile = tn;
+        if (tile >= a.ntiles) break;
+        tn = next_of(tile);
+        process(tile, kb, vb, tn, ka, va);
+        tile = tn;
+        if (tile >= a.ntiles) break;
     }
 }
 
+// Plain copy: 16-byte words when both pointers are 16-byte aligned, bytes otherwise.
 __global__ void k_copy_bytes(const uint8_t* src, uint8_t* dst, size_t bytes)
 {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < bytes; i += stride)
-        dst[i] = src[i];
+    const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t head = 0;
+    if ((((uintptr_t)src | (uintptr_t)dst) & 15) == 0) {
+        const size_t words = bytes / 16;
+        const uint4* s4 = (const uint4*)src;
+        uint4* d4 = (uint4*)dst;
+        for (size_t i = g; i < words; i += stride) d4[i] = s4[i];
+        head = words * 16;
+    }
+    for (size_t i = head + g; i < bytes; i += stride) dst[i] = src[i];
 }
 
 uint32_t rounds_of(int begin_bit, int end_bit, int digit_bits)
@@ -479,6 +654,31 @@ uint32_t hist_grid(size_t n)
     return (uint32_t)g;
 }
 
+uint32_t nblocks_of(uint32_t ntiles) { return (ntiles + kScanBlock - 1) / kScanBlock; }
+
+// Workgroups that fit on the device at once for a kernel (cached per kernel).
+uint32_t persistent_blocks(const void* kernel, int wg)
+{
+    static const void* cached_kernel[16];
+    static uint32_t cached_value[16];
+    for (int i = 0; i < 16; ++i)
+        if (cached_kernel[i] == kernel) return cached_value[i];
+    int dev = 0, cus = 0, per_cu = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, wg, 0) != hipSuccess || per_cu <= 0)
+        per_cu = 1;
+    const uint32_t v = (uint32_t)(cus * per_cu);
+    for (int i = 0; i < 16; ++i)
+        if (!cached_kernel[i]) {
+            cached_kernel[i] = kernel;
+            cached_value[i] = v;
+            break;
+        }
+    return v;
+}
+
 template <typename K, bool KV>
 hipError_t run(const void* keys_in, void* keys_out, const uint32_t* vals_in, uint32_t* vals_out,
                size_t n, int begin_bit, int end_bit, void* ws, const LsdR8Layout& L,
@@ -491,28 +691,34 @@ hipError_t run(const void* keys_in, void* keys_out, const uint32_t* vals_in, uin
     uint32_t* bases = (uint32_t*)(w + L.off_bases);
     RoundPlan* plan = (RoundPlan*)(w + L.off_plan);
     uint32_t* tickets = (uint32_t*)(w + L.off_tickets);
-    uint32_t* state0 = (uint32_t*)(w + L.off_state0);
-    uint32_t* state1 = (uint32_t*)(w + L.off_state1);
+    uint32_t* counts = (uint32_t*)(w + L.off_counts);
+    uint32_t* blk_state = (uint32_t*)(w + L.off_blk_state);
     K* keys_tmp = (K*)(w + L.off_tmp_keys);
     uint32_t* vals_tmp = KV ? (uint32_t*)(w + L.off_tmp_vals) : nullptr;
     const uint32_t nr = L.rounds;
     const bool in_place = keys_in == keys_out || (KV && vals_in == vals_out);
+    const uint32_t nblk = nblocks_of(L.ntiles);
 
     hipLaunchKernelGGL(k_init, dim3(256), dim3(256), 0, stream, hist,
-                       (uint32_t)(kHistReplicas * nr * R), tickets, nr, state0,
-                       (size_t)L.ntiles * R);
-    if (prof) profiler_mark(prof, stream, kKindHist, true);
+                       (uint32_t)(kHistReplicas * nr * R), tickets, nr, blk_state,
+                       (size_t)nr * nblk * R);
     if (prof) profiler_mark(prof, stream, kKindHist, true);
     hipLaunchKernelGGL(k_hist<K>, dim3(hist_grid(n)), dim3(kHistWG), 0, stream,
                        (const K*)keys_in, (uint32_t)n, (uint32_t)begin_bit, (uint32_t)end_bit, nr, hist);
     if (prof) profiler_mark(prof, stream, kKindHist, false);
-    if (prof) profiler_mark(prof, stream, kKindHist, false);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(R), 0, stream, (const uint32_t*)hist, nr,
+    hipLaunchKernelGGL(k_plan, dim3(1), dim3(R), 0, stream, (const uint32_t*)hist, nr,
                        (uint32_t)n, (int)in_place, bases, plan);
     if (in_place && (nr & 1)) {
         uint32_t g = (uint32_t)std::min<size_t>((n + 255) / 256, 2048);
         hipLaunchKernelGGL(k_precopy<K>, dim3(g), dim3(256), 0, stream, (const RoundPlan*)plan,
                            (const K*)keys_in, keys_tmp, KV ? vals_in : nullptr, vals_tmp, (uint32_t)n);
+    }
+    // Scatter grid: one workgroup per tile, or RSORT_SCATTER_WAVES resident
+    // workgroups per CU looping over the tiles.
+    uint32_t sgrid = L.ntiles;
+    if (RSORT_SCATTER_PERSIST) {
+        const uint32_t resident = persistent_blocks((const void*)k_scatter<K, KV, WG, ITEMS>, WG);
+        sgrid = std::min<uint32_t>(L.ntiles, resident & ~7u ? resident & ~7u : resident);
     }
     for (uint32_t d = 0; d < nr; ++d) {
         RoundArgs a;
@@ -526,16 +732,21 @@ hipError_t run(const void* keys_in, void* keys_out, const uint32_t* vals_in, uin
         a.shift = (uint32_t)begin_bit + 8u * d;
         a.mask = (1u << std::min(8u, (uint32_t)end_bit - a.shift)) - 1u;
         a.round = d;
+        a.ntiles = L.ntiles;
         a.bases = bases;
         a.plan = plan;
+        a.counts = counts;
+        a.blk_state = blk_state;
         a.tickets = tickets;
-        a.state0 = state0;
-        a.state1 = state1;
         a.err = dev_err;
+        if (prof) profiler_mark(prof, stream, kKindCount, true);
+        hipLaunchKernelGGL((k_count<K, WG, ITEMS>), dim3(L.ntiles), dim3(WG), 0, stream, a);
+        if (prof) profiler_mark(prof, stream, kKindCount, false);
+        if (prof) profiler_mark(prof, stream, kKindTileScan, true);
+        hipLaunchKernelGGL(k_tilescan, dim3(nblk), dim3(R), 0, stream, a);
+        if (prof) profiler_mark(prof, stream, kKindTileScan, false);
         if (prof) profiler_mark(prof, stream, kKindRound, true);
-        if (prof) profiler_mark(prof, stream, kKindRound, true);
-        hipLaunchKernelGGL((k_round<K, KV, WG, ITEMS>), dim3(L.ntiles), dim3(WG), 0, stream, a);
-        if (prof) profiler_mark(prof, stream, kKindRound, false);
+        hipLaunchKernelGGL((k_scatter<K, KV, WG, ITEMS>), dim3(sgrid), dim3(WG), 0, stream, a);
         if (prof) profiler_mark(prof, stream, kKindRound, false);
     }
     return hipGetLastError();
@@ -550,15 +761,16 @@ LsdR8Layout lsd_r8_layout(int key_bytes, bool has_vals, size_t n, int begin_bit,
     L.tile = key_bytes == 8 ? R8Config<uint64_t>::WG * R8Config<uint64_t>::ITEMS
                             : R8Config<uint32_t>::WG * R8Config<uint32_t>::ITEMS;
     L.ntiles = (uint32_t)((n + L.tile - 1) / L.tile);
+    const uint32_t nblk = nblocks_of(L.ntiles);
     size_t o = 0;
-    L.off_tmp_keys = o; o = align_up(o + n * key_bytes);
-    L.off_tmp_vals = o; o = align_up(o + (has_vals ? n * 4 : 0));
-    L.off_state0 = o;   o = align_up(o + (size_t)L.ntiles * R * 4);
-    L.off_state1 = o;   o = align_up(o + (size_t)L.ntiles * R * 4);
-    L.off_hist = o;     o = align_up(o + (size_t)kHistReplicas * kMaxRounds * R * 4);
-    L.off_bases = o;    o = align_up(o + (size_t)kMaxRounds * R * 4);
-    L.off_plan = o;     o = align_up(o + (kMaxRounds + 1) * sizeof(RoundPlan));
-    L.off_tickets = o;  o = align_up(o + kMaxRounds * 4);
+    L.off_tmp_keys = o;  o = align_up(o + n * key_bytes);
+    L.off_tmp_vals = o;  o = align_up(o + (has_vals ? n * 4 : 0));
+    L.off_counts = o;    o = align_up(o + (size_t)L.ntiles * R * 4);
+    L.off_blk_state = o; o = align_up(o + (size_t)std::max(1u, L.rounds) * nblk * R * 4);
+    L.off_hist = o;      o = align_up(o + (size_t)kHistReplicas * kMaxRounds * R * 4);
+    L.off_bases = o;     o = align_up(o + (size_t)kMaxRounds * R * 4);
+    L.off_plan = o;      o = align_up(o + (kMaxRounds + 1) * sizeof(RoundPlan));
+    L.off_tickets = o;   o = align_up(o + kMaxRounds * 4);
     L.bytes = o;
     return L;
 }
@@ -579,7 +791,7 @@ hipError_t lsd_r8_sort(int key_bytes, const void* keys_in, void* keys_out,
 hipError_t copy_bytes(void* dst, const void* src, size_t bytes, hipStream_t stream)
 {
     if (!bytes || dst == src) return hipSuccess;
-    uint32_t g = (uint32_t)std::min<size_t>((bytes + 255) / 256, 4096);
+    uint32_t g = (uint32_t)std::min<size_t>((bytes + 4095) / 4096, 8192);
     hipLaunchKernelGGL(k_copy_bytes, dim3(g), dim3(256), 0, stream, (const uint8_t*)src,
                        (uint8_t*)dst, bytes);
     return hipGetLastError();
@@ -641,6 +853,8 @@ __global__ __launch_bounds__(kH16WG) void k_hist16(const K* __restrict__ keys, u
 
 size_t histogram_ws_bytes(int digit_bits, int begin_bit, int end_bit)
 {
+    (void)begin_bit;
+    (void)end_bit;
     if (digit_bits == 8) return (size_t)kHistReplicas * kMaxRounds * R * 4;
     return 0;
 }

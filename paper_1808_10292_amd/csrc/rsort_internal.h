@@ -28,7 +28,7 @@ constexpr int kHistReplicas = 8;   // global histogram copies, picked by block i
 
 // Optional kernel timing: HIP events recorded on the launch stream around the
 // kernels of one kind (implemented in api.hip).  nullptr disables it.
-enum KernelKind { kKindRound = 0, kKindHist = 1, kKindOther = 2, kNumKinds = 3 };
+enum KernelKind { kKindRound = 0, kKindHist = 1, kKindCount = 2, kKindTileScan = 3, kNumKinds = 4 };
 struct Profiler;
 void profiler_mark(Profiler* p, hipStream_t s, int kind, bool begin);
 
@@ -38,7 +38,7 @@ struct LsdR8Layout {
     uint32_t rounds;     // number of 8-bit (or narrower, last) digits
     uint32_t tile;       // keys per tile in a round
     uint32_t ntiles;
-    size_t off_tmp_keys, off_tmp_vals, off_state0, off_state1;
+    size_t off_tmp_keys, off_tmp_vals, off_counts, off_blk_state;
     size_t off_hist, off_bases, off_plan, off_tickets;
     size_t bytes;
 };

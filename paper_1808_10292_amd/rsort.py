@@ -46,6 +46,8 @@ EXPORTED = ("rsort_create", "rsort_destroy", "rsort_status_string", "rsort_last_
 
 RSORT_KERNEL_ROUND = 0
 RSORT_KERNEL_HIST = 1
+RSORT_KERNEL_COUNT = 2
+RSORT_KERNEL_TILESCAN = 3
 
 
 class RsortError(RuntimeError):
