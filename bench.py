@@ -42,7 +42,8 @@ def log(msg):
 
 def source_sha():
     h = hashlib.sha256()
-    for p in (ROUND_SOURCE, os.path.join(ROOT, "paper_1808_10292_amd", "csrc", "device_common.h")):
+    for p in (ROUND_SOURCE, os.path.join(ROOT, "paper_1808_10292_amd", "csrc", "lsd_kernels.h"),
+              os.path.join(ROOT, "paper_1808_10292_amd", "csrc", "device_common.h")):
         with open(p, "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -75,6 +76,62 @@ def time_steps(fn, steps, warmup, torch):
         fn()
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / steps
+
+
+def bench_batched(rsort, torch, np, keygen, args):
+    """Batched segmented sort vs one plain sort per array: 4096 arrays with
+    lognormal sizes (median 2^12, sigma 1.5, clipped to [16, 2^20]), uniform
+    32-bit keys, keys only."""
+    sizes = keygen.lognormal_sizes(4096)
+    off = keygen.offsets_from_sizes(sizes)
+    total = int(off[-1])
+    log("batched: %d arrays, %d keys" % (sizes.size, total))
+    keys = keygen.uniform_u32(total, keygen.SEED_SEGMENTS)
+    dk = torch.from_numpy(keys).cuda()
+    out = torch.empty_like(dk)
+    split, tune_ms = rsort.rsort_segmented_tune(dk, out, off, reps=3)
+    reps = max(5, args.steps // 2)
+    # per-call latency: submit -> completion, one call at a time
+    lat = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rsort.rsort_segmented_sort(dk, out, off)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+    got = out.cpu().numpy()
+    ok = all(bool(np.all(got[a:b][1:] >= got[a:b][:-1])) for a, b in zip(off[:-1:97], off[1::97]))
+    batched = time_steps(lambda: rsort.rsort_segmented_sort(dk, out, off), reps, 2, torch)
+    # the same call replayed from a HIP graph
+    need = rsort.rsort_segmented_workspace_bytes(torch.uint32, False, off)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    rsort.rsort_segmented_sort(dk, out, off, workspace=ws)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        rsort.rsort_segmented_sort(dk, out, off, workspace=ws)
+    graph = time_steps(g.replay, reps, 2, torch)
+    # one plain sort call per array, same stream
+    bounds = [(int(a), int(b)) for a, b in zip(off[:-1], off[1:])]
+    views = [(dk[a:b], out[a:b]) for a, b in bounds]
+
+    def plain():
+        for ki, ko in views:
+            rsort.rsort_sort(ki, ko)
+    plain_s = time_steps(plain, 2, 1, torch)
+    lat_us = np.array(lat) * 1e6
+    return {"workload": "4096 arrays, lognormal sizes (median 4096, sigma 1.5, clip [16, 2^20]), "
+                        "uniform u32 keys, keys only",
+            "keys": total, "split_small_max": split,
+            "batched_ms": round(batched * 1e3, 3), "batched_gkeys_per_s": round(total / batched / 1e9, 3),
+            "graph_replay_ms": round(graph * 1e3, 3),
+            "graph_gkeys_per_s": round(total / graph / 1e9, 3),
+            "plain_per_array_ms": round(plain_s * 1e3, 3),
+            "plain_gkeys_per_s": round(total / plain_s / 1e9, 3),
+            "speedup_batched_vs_plain": round(plain_s / batched, 2),
+            "latency_us_p50": round(float(np.percentile(lat_us, 50)), 1),
+            "latency_us_p99": round(float(np.percentile(lat_us, 99)), 1),
+            "check": "segments sorted (sampled)" if ok else "FAILED"}
 
 
 def main():
@@ -194,6 +251,9 @@ def main():
             s = time_steps(lambda: rsort.rsort_sort(dk, out, algo=algo), max(3, args.steps // 4), 1, torch)
             variants[algo] = {"gkeys_per_s": round(n / s / 1e9, 3), "ms": round(s * 1e3, 3)}
         result["variants"] = variants
+
+    if not args.no_variants:
+        result["batched"] = bench_batched(rsort, torch, np, keygen, args)
 
     if args.cpu_seconds > 0:
         import oracle

@@ -122,6 +122,44 @@ int rsort_histogram(rsort_ctx* ctx, int key_type, const void* keys, size_t n,
                     int digit_bits, int begin_bit, int end_bit,
                     uint32_t* hist_out, void* stream);
 
+/*
+ * Batched segmented sort: num_segs independent arrays stored back to back,
+ * segment s being elements [seg_offsets[s], seg_offsets[s+1]) of the key (and
+ * payload) arrays, each sorted stably on its own (the paper's SR4 applied per
+ * segment, Section 3.2).  seg_offsets is a HOST array of num_segs + 1
+ * nondecreasing values; elements outside [seg_offsets[0], seg_offsets[num_segs])
+ * are not touched.  Keys are whole (32 or 64 bits).  Segments of at most the
+ * small/large split (rsort_segmented_set_split) are sorted inside one
+ * workgroup's LDS; longer ones through the tiled round kernels.  Other
+ * arguments as in rsort_sort; the call reads seg_offsets before returning.
+ * The call may be captured into a HIP graph: make one identical call (same
+ * offsets, key type, payload presence and workspace) outside the capture
+ * first; it leaves the segment plan in the workspace, which the captured
+ * kernels then read at every replay.  Use a caller-owned workspace for
+ * captured calls (the context's cached one is reused by later calls).
+ */
+int rsort_segmented_sort(rsort_ctx* ctx, int key_type, const void* keys_in, void* keys_out,
+                         const uint32_t* vals_in, uint32_t* vals_out,
+                         const uint64_t* seg_offsets, size_t num_segs,
+                         void* workspace, size_t ws_bytes, void* stream);
+
+/* Workspace rsort_segmented_sort needs for these segments (host offsets). */
+int rsort_segmented_workspace_bytes(rsort_ctx* ctx, int key_type, int has_vals,
+                                    const uint64_t* seg_offsets, size_t num_segs, size_t* bytes);
+
+/* Largest segment sorted whole in LDS (<= 8192; 0 sends every segment through
+ * the tiled path).  Chosen by the tuner; applies to later calls on ctx. */
+int rsort_segmented_set_split(rsort_ctx* ctx, uint32_t small_max);
+
+/* Tuner for the small/large split: sorts the given batch (into keys_out /
+ * vals_out) reps times with each candidate split (0, 1024, 4096, 8192 keys),
+ * keeps the fastest on ctx and returns it, with its time per sort in ms.
+ * Synchronises the stream. */
+int rsort_segmented_tune(rsort_ctx* ctx, int key_type, const void* keys_in, void* keys_out,
+                         const uint32_t* vals_in, uint32_t* vals_out,
+                         const uint64_t* seg_offsets, size_t num_segs, int reps, void* stream,
+                         uint32_t* best_split, double* best_ms);
+
 /* Wait for `stream`, then report any device-side failure recorded by this
  * context's kernels since the last call (RSORT_EDEVICE) and clear it. */
 int rsort_synchronize(rsort_ctx* ctx, void* stream);
@@ -133,7 +171,8 @@ enum rsort_kernel_kind {
     RSORT_KERNEL_ROUND = 0,     /* rank-and-scatter kernel of a count-sort round  */
     RSORT_KERNEL_HIST = 1,      /* all-rounds digit counting before the rounds    */
     RSORT_KERNEL_COUNT = 2,     /* per-tile digit counts of a round               */
-    RSORT_KERNEL_TILESCAN = 3   /* exclusive scan of the tile counts of a round   */
+    RSORT_KERNEL_TILESCAN = 3,  /* exclusive scan of the tile counts of a round   */
+    RSORT_KERNEL_SMALL = 4      /* whole-segment in-LDS sorts (segmented sort)    */
 };
 int rsort_profile_enable(rsort_ctx* ctx, int enable);
 

@@ -81,6 +81,16 @@ struct rsort_ctx {
     size_t ws_bytes = 0;
     uint32_t* dev_err = nullptr; // device-side failure bits (DeviceError)
     rsort::Profiler* prof = nullptr;
+    // pinned host staging of the segmented sort's plan, and the event that
+    // marks the end of its last upload (the buffer is reused only after it)
+    void* meta_host = nullptr;
+    size_t meta_bytes = 0;
+    hipEvent_t meta_done = nullptr;
+    bool meta_pending = false;
+    uint32_t small_max = rsort::kSmallMaxDefault;
+    rsort::SegPlan plan;
+    uint64_t upload_sig = 0;         // plan last uploaded into upload_ws
+    void* upload_ws = nullptr;
     std::string last_error;
 };
 
@@ -151,6 +161,7 @@ int ensure_workspace(rsort_ctx* ctx, size_t need, void** ws)
         hipError_t e = hipDeviceSynchronize();
         if (e != hipSuccess) return hip_fail(ctx, e, "hipDeviceSynchronize");
         (void)hipFree(ctx->ws);
+        if (ctx->upload_ws == ctx->ws) ctx->upload_ws = nullptr;
         ctx->ws = nullptr;
         ctx->ws_bytes = 0;
     }
@@ -216,6 +227,8 @@ int rsort_destroy(rsort_ctx* ctx)
         DeviceGuard g(ctx->device);
         (void)hipDeviceSynchronize();
         delete ctx->prof;
+        if (ctx->meta_host) (void)hipHostFree(ctx->meta_host);
+        if (ctx->meta_done) (void)hipEventDestroy(ctx->meta_done);
         if (ctx->ws) (void)hipFree(ctx->ws);
         if (ctx->dev_err) (void)hipFree(ctx->dev_err);
     }
@@ -363,6 +376,189 @@ int rsort_profile_read(rsort_ctx* ctx, int kind, uint64_t* launches, double* tot
     ctx->prof->fold();
     *launches = ctx->prof->launches[kind];
     *total_ms = ctx->prof->total_ms[kind];
+    return RSORT_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Validate host CSR offsets; total key count in *total.
+int check_offsets(rsort_ctx* ctx, const uint64_t* off, size_t num_segs, size_t* total)
+{
+    if (num_segs && !off) return fail(ctx, RSORT_EINVAL, "seg_offsets is NULL");
+    *total = num_segs ? (size_t)off[num_segs] : 0;
+    for (size_t s = 0; s < num_segs; ++s)
+        if (off[s + 1] < off[s])
+            return fail(ctx, RSORT_EINVAL, "seg_offsets decreases at segment %zu", s);
+    if (*total >= kMaxN) return fail(ctx, RSORT_EUNSUPPORTED, "total = %zu >= 2^30", *total);
+    return RSORT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rsort_segmented_workspace_bytes(rsort_ctx* ctx, int key_type, int has_vals,
+                                    const uint64_t* seg_offsets, size_t num_segs, size_t* bytes)
+{
+    if (!ctx || !bytes) return RSORT_EINVAL;
+    const int kb = key_bytes_of(key_type);
+    if (!kb) return fail(ctx, RSORT_EINVAL, "unknown key type %d", key_type);
+    size_t total = 0;
+    int rc = check_offsets(ctx, seg_offsets, num_segs, &total);
+    if (rc) return rc;
+    rsort::SegPlan P;
+    rsort::segmented_plan(seg_offsets, num_segs, ctx->small_max, kb, P);
+    *bytes = rsort::segmented_ws_bytes(kb, has_vals != 0, total, P);
+    return RSORT_OK;
+}
+
+int rsort_segmented_set_split(rsort_ctx* ctx, uint32_t small_max)
+{
+    if (!ctx) return RSORT_EINVAL;
+    if (small_max > rsort::kSmallMaxDefault)
+        return fail(ctx, RSORT_EINVAL, "small_max %u above the in-LDS capacity %u", small_max,
+                    rsort::kSmallMaxDefault);
+    ctx->small_max = small_max;
+    return RSORT_OK;
+}
+
+int rsort_segmented_sort(rsort_ctx* ctx, int key_type, const void* keys_in, void* keys_out,
+                         const uint32_t* vals_in, uint32_t* vals_out, const uint64_t* seg_offsets,
+                         size_t num_segs, void* workspace, size_t ws_bytes, void* stream)
+{
+    if (!ctx) return RSORT_EINVAL;
+    ctx->last_error.clear();
+    const int kb = key_bytes_of(key_type);
+    if (!kb) return fail(ctx, RSORT_EINVAL, "unknown key type %d", key_type);
+    if ((vals_in == nullptr) != (vals_out == nullptr))
+        return fail(ctx, RSORT_EINVAL, "vals_in and vals_out must both be NULL or both be set");
+    if ((workspace == nullptr) != (ws_bytes == 0))
+        return fail(ctx, RSORT_EINVAL, "workspace and ws_bytes must both be 0 or both be set");
+    size_t total = 0;
+    int rc = check_offsets(ctx, seg_offsets, num_segs, &total);
+    if (rc) return rc;
+    if (total == 0) return RSORT_OK;
+    if (!keys_in || !keys_out) return fail(ctx, RSORT_EINVAL, "NULL key pointer");
+
+    DeviceGuard g(ctx->device);
+    if (!is_device_pointer(keys_in, ctx->device) || !is_device_pointer(keys_out, ctx->device))
+        return fail(ctx, RSORT_EINVAL, "key arrays must be device memory of device %d", ctx->device);
+    if (vals_in && (!is_device_pointer(vals_in, ctx->device) || !is_device_pointer(vals_out, ctx->device)))
+        return fail(ctx, RSORT_EINVAL, "payload arrays must be device memory of device %d", ctx->device);
+    const size_t kbytes = total * kb, vbytes = total * 4;
+    if (overlap_partial(keys_in, kbytes, keys_out, kbytes))
+        return fail(ctx, RSORT_EINVAL, "keys_in and keys_out overlap without being equal");
+    if (vals_in && overlap_partial(vals_in, vbytes, vals_out, vbytes))
+        return fail(ctx, RSORT_EINVAL, "vals_in and vals_out overlap without being equal");
+
+    rsort::SegPlan& P = ctx->plan;
+    rsort::segmented_plan(seg_offsets, num_segs, ctx->small_max, kb, P);
+    const size_t need = rsort::segmented_ws_bytes(kb, vals_in != nullptr, total, P);
+    void* ws = workspace;
+    if (ws) {
+        if (ws_bytes < need)
+            return fail(ctx, RSORT_EINVAL, "workspace of %zu bytes < %zu needed", ws_bytes, need);
+    } else {
+        rc = ensure_workspace(ctx, need, &ws);
+        if (rc) return rc;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const size_t mb = rsort::segmented_meta_bytes(P);
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cap) != hipSuccess) cap = hipStreamCaptureStatusNone;
+    // The plan signature: what the kernels read from the workspace's plan area.
+    uint64_t sig = 1469598103934665603ull;
+    auto mix = [&sig](uint64_t x) { sig = (sig ^ x) * 1099511628211ull; };
+    mix((uint64_t)kb);
+    mix(vals_in != nullptr);
+    mix(ctx->small_max);
+    mix(num_segs);
+    for (size_t i = 0; i <= num_segs; ++i) mix(seg_offsets[i]);
+    if (cap == hipStreamCaptureStatusActive) {
+        // No host traffic inside a graph: the plan must already sit in this
+        // workspace from an identical call made outside the capture.
+        if (sig != ctx->upload_sig || ws != ctx->upload_ws)
+            return fail(ctx, RSORT_EINVAL, "capturing a segmented sort needs one identical call "
+                                           "with the same workspace outside the capture first");
+        hipError_t e = rsort::segmented_sort(kb, keys_in, keys_out, vals_in, vals_out, total, P,
+                                             nullptr, ws, ctx->dev_err, s, nullptr);
+        return e == hipSuccess ? RSORT_OK : hip_fail(ctx, e, "segmented sort capture");
+    }
+    // pinned staging of the plan: wait until its previous upload has completed
+    if (ctx->meta_pending) {
+        hipError_t e = hipEventSynchronize(ctx->meta_done);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipEventSynchronize");
+        ctx->meta_pending = false;
+    }
+    if (mb > ctx->meta_bytes) {
+        if (ctx->meta_host) (void)hipHostFree(ctx->meta_host);
+        ctx->meta_host = nullptr;
+        ctx->meta_bytes = 0;
+        size_t grow = std::max(mb, (size_t)1 << 16);
+        hipError_t e = hipHostMalloc(&ctx->meta_host, grow, hipHostMallocDefault);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipHostMalloc(plan staging)");
+        ctx->meta_bytes = grow;
+    }
+    if (!ctx->meta_done && hipEventCreateWithFlags(&ctx->meta_done, hipEventDisableTiming) != hipSuccess)
+        return fail(ctx, RSORT_EDEVICE, "hipEventCreate");
+    rsort::segmented_pack(P, kb, ctx->meta_host);
+    hipError_t e = rsort::segmented_sort(kb, keys_in, keys_out, vals_in, vals_out, total, P,
+                                         ctx->meta_host, ws, ctx->dev_err, s, ctx->prof);
+    if (e != hipSuccess) return hip_fail(ctx, e, "segmented sort launch");
+    if (hipEventRecord(ctx->meta_done, s) == hipSuccess) ctx->meta_pending = true;
+    ctx->upload_sig = sig;
+    ctx->upload_ws = ws;
+    return RSORT_OK;
+}
+
+int rsort_segmented_tune(rsort_ctx* ctx, int key_type, const void* keys_in, void* keys_out,
+                         const uint32_t* vals_in, uint32_t* vals_out, const uint64_t* seg_offsets,
+                         size_t num_segs, int reps, void* stream, uint32_t* best_split,
+                         double* best_ms)
+{
+    if (!ctx || !best_split) return RSORT_EINVAL;
+    static const uint32_t cands[] = {0, 1024, 4096, 8192};
+    if (reps < 1) reps = 3;
+    hipStream_t s = (hipStream_t)stream;
+    DeviceGuard g(ctx->device);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return fail(ctx, RSORT_EDEVICE, "hipEventCreate");
+    }
+    const uint32_t saved = ctx->small_max;
+    double best = 1e30;
+    uint32_t pick = saved;
+    int rc = RSORT_OK;
+    for (uint32_t c : cands) {
+        ctx->small_max = c;
+        rc = rsort_segmented_sort(ctx, key_type, keys_in, keys_out, vals_in, vals_out, seg_offsets,
+                                  num_segs, nullptr, 0, stream);   // warm-up, sizes the workspace
+        if (rc) break;
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < reps && !rc; ++r)
+            rc = rsort_segmented_sort(ctx, key_type, keys_in, keys_out, vals_in, vals_out,
+                                      seg_offsets, num_segs, nullptr, 0, stream);
+        (void)hipEventRecord(e1, s);
+        if (rc) break;
+        float ms = 0.f;
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            rc = fail(ctx, RSORT_EDEVICE, "timing");
+            break;
+        }
+        if (ms / reps < best) {
+            best = ms / reps;
+            pick = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->small_max = rc ? saved : pick;
+    if (rc) return rc;
+    *best_split = pick;
+    if (best_ms) *best_ms = best;
     return RSORT_OK;
 }
 

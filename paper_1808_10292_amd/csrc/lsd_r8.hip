@@ -25,604 +25,10 @@
 //
 // No tile of a round waits for another tile: the dependencies are kernel
 // boundaries, except the chain of tile blocks inside k_tilescan.
-#include <algorithm>
-
-#include "device_common.h"
-#include "rsort_internal.h"
+#include "lsd_kernels.h"
 
 namespace rsort {
 namespace {
-
-constexpr uint32_t R = 256;  // radix
-
-// Tile shape of the count and scatter kernels: WG threads, ITEMS keys per
-// thread (tile = WG * ITEMS keys).
-#ifndef RSORT_R8_WG32
-#define RSORT_R8_WG32 512
-#endif
-#ifndef RSORT_R8_ITEMS32
-#define RSORT_R8_ITEMS32 16
-#endif
-#ifndef RSORT_R8_WG64
-#define RSORT_R8_WG64 512
-#endif
-#ifndef RSORT_R8_ITEMS64
-#define RSORT_R8_ITEMS64 8
-#endif
-// Scatter grid: 1 = persistent (resident workgroups loop over the tiles and
-// prefetch the next tile), 0 = one workgroup per tile.
-#ifndef RSORT_SCATTER_PERSIST
-#define RSORT_SCATTER_PERSIST 0
-#endif
-// Scatter ranking order: 1 = rank, then bases; 0 = count, bases, then rank;
-// -1 = rank first with payloads, count first without (the faster of each).
-#ifndef RSORT_RANK_FIRST
-#define RSORT_RANK_FIRST -1
-#endif
-// Waves per SIMD the scatter kernel is compiled for (bounds its registers).
-#ifndef RSORT_R8_WAVES_PER_EU
-#define RSORT_R8_WAVES_PER_EU 8
-#endif
-#ifndef RSORT_R8_WAVES_PER_EU_KV
-#define RSORT_R8_WAVES_PER_EU_KV 5
-#endif
-// Tiles per block of the tile scan, and predecessor blocks read per look-back step.
-#ifndef RSORT_SCAN_BLOCK
-#define RSORT_SCAN_BLOCK 32
-#endif
-#ifndef LB_WINDOW
-#define LB_WINDOW 4
-#endif
-
-template <typename K> struct R8Config;
-template <> struct R8Config<uint32_t> {
-    static constexpr int WG = RSORT_R8_WG32;
-    static constexpr int ITEMS = RSORT_R8_ITEMS32;
-};
-template <> struct R8Config<uint64_t> {
-    static constexpr int WG = RSORT_R8_WG64;
-    static constexpr int ITEMS = RSORT_R8_ITEMS64;
-};
-
-constexpr int kHistWG = 256;
-constexpr int kHistUnroll = 8;
-constexpr uint32_t kScanBlock = RSORT_SCAN_BLOCK;
-
-struct RoundArgs {
-    const void* keys_in;
-    void* keys_out;
-    void* keys_tmp;
-    const uint32_t* vals_in;
-    uint32_t* vals_out;
-    uint32_t* vals_tmp;
-    uint32_t n;
-    uint32_t shift;
-    uint32_t mask;
-    uint32_t round;
-    uint32_t ntiles;
-    const uint32_t* bases;   // [round][256] start of each digit's bucket
-    const RoundPlan* plan;
-    uint32_t* counts;        // [ntiles][256] tile counts, then tile output starts
-    uint32_t* blk_state;     // [round][nblocks][256] look-back words of k_tilescan
-    uint32_t* tickets;       // [round] block tickets of k_tilescan
-    uint32_t* err;
-};
-
-// Output stores of the scatter: streaming (non-temporal) when RSORT_NT_STORES.
-#ifndef RSORT_NT_STORES
-#define RSORT_NT_STORES 0
-#endif
-template <typename T>
-__device__ __forceinline__ void store_out(T* p, T v)
-{
-    if (RSORT_NT_STORES) __builtin_nontemporal_store(v, p);
-    else *p = v;
-}
-
-template <typename T>
-__device__ __forceinline__ T* pick(int sel, const T* in, T* out, T* tmp)
-{
-    return sel == 0 ? const_cast<T*>(in) : (sel == 1 ? out : tmp);
-}
-
-// Tile handled by this workgroup.  Workgroups are dealt to the 8 XCDs in turn,
-// so with ntiles a multiple of 8, tile = (block mod 8) * (ntiles / 8) + block / 8
-// gives every XCD a contiguous run of tiles: neighbouring tiles, whose output
-// runs share cache lines, then sit behind the same L2.  Other grids keep the
-// plain order.
-__device__ __forceinline__ uint32_t xcd_tile(uint32_t ntiles)
-{
-    const uint32_t b = blockIdx.x;
-    if ((ntiles & 7) != 0) return b;
-    return (b & 7) * (ntiles >> 3) + (b >> 3);
-}
-
-// Zero the global histogram copies, the block tickets and the tile-scan words.
-__global__ void k_init(uint32_t* hist, uint32_t hist_words, uint32_t* tickets,
-                       uint32_t nrounds, uint32_t* blk_state, size_t state_words)
-{
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (size_t i = g; i < hist_words; i += stride) hist[i] = 0;
-    for (size_t i = g; i < nrounds; i += stride) tickets[i] = 0;
-    for (size_t i = g; i < state_words; i += stride) blk_state[i] = 0;
-}
-
-// Counts of every 8-bit digit of [begin_bit, end_bit) in one pass over the
-// keys: LDS histograms per workgroup, then one global atomic per nonzero bin
-// into copy (block index mod 8), which spreads contention across the XCDs.
-template <typename K>
-__global__ __launch_bounds__(kHistWG) void k_hist(const K* __restrict__ keys, uint32_t n,
-                                                  uint32_t begin_bit, uint32_t end_bit,
-                                                  uint32_t nrounds, uint32_t* hist)
-{
-    __shared__ uint32_t h[kMaxRounds * R];
-    for (uint32_t i = threadIdx.x; i < nrounds * R; i += kHistWG) h[i] = 0;
-    __syncthreads();
-
-    uint32_t shift[kMaxRounds], mask[kMaxRounds];
-#pragma unroll
-    for (int d = 0; d < kMaxRounds; ++d) {
-        uint32_t lo = begin_bit + 8u * d;
-        uint32_t w = lo < end_bit ? min(8u, end_bit - lo) : 0u;
-        shift[d] = lo < end_bit ? lo : 0u;
-        mask[d] = (1u << w) - 1u;
-    }
-
-    const uint32_t stride = gridDim.x * kHistWG;
-    uint32_t i = blockIdx.x * kHistWG + threadIdx.x;
-    for (; i + (kHistUnroll - 1) * stride < n; i += kHistUnroll * stride) {
-        K k[kHistUnroll];
-#pragma unroll
-        for (int u = 0; u < kHistUnroll; ++u) k[u] = keys[i + u * stride];
-#pragma unroll
-        for (int u = 0; u < kHistUnroll; ++u) {
-#pragma unroll
-            for (int d = 0; d < kMaxRounds; ++d) {
-                if ((uint32_t)d < nrounds)
-                    atomicAdd(&h[d * R + digit_of(k[u], shift[d], mask[d])], 1u);
-            }
-        }
-    }
-    for (; i < n; i += stride) {
-        K key = keys[i];
-#pragma unroll
-        for (int d = 0; d < kMaxRounds; ++d)
-            if ((uint32_t)d < nrounds) atomicAdd(&h[d * R + digit_of(key, shift[d], mask[d])], 1u);
-    }
-    __syncthreads();
-    uint32_t* dst = hist + (blockIdx.x % kHistReplicas) * nrounds * R;
-    for (uint32_t b = threadIdx.x; b < nrounds * R; b += kHistWG) {
-        uint32_t c = h[b];
-        if (c) atomicAdd(&dst[b], c);
-    }
-}
-
-// Block-wide (256 threads) inclusive sum; wsum is 4 words of LDS.
-__device__ __forceinline__ uint32_t block256_inclusive_sum(uint32_t x, uint32_t* wsum)
-{
-    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    uint32_t incl = wave_inclusive_sum(x);
-    if (lane == 63) wsum[wave] = incl;
-    __syncthreads();
-    uint32_t pre = 0;
-    for (uint32_t w = 0; w < wave; ++w) pre += wsum[w];
-    __syncthreads();
-    return pre + incl;
-}
-
-// Round bases (exclusive prefix of each round's counts) and the round plan.
-// One workgroup of 256 threads, thread t owns digit value t.
-__global__ __launch_bounds__(R) void k_plan(const uint32_t* hist, uint32_t nrounds, uint32_t n,
-                                            int in_place, uint32_t* bases, RoundPlan* plan)
-{
-    __shared__ uint32_t wsum[4];
-    __shared__ int identity[kMaxRounds];
-    const uint32_t t = threadIdx.x;
-    if (t < kMaxRounds) identity[t] = 0;
-    __syncthreads();
-    for (uint32_t d = 0; d < nrounds; ++d) {
-        uint32_t c = 0;
-        for (int rep = 0; rep < kHistReplicas; ++rep) c += hist[(rep * nrounds + d) * R + t];
-        uint32_t incl = block256_inclusive_sum(c, wsum);
-        bases[d * R + t] = incl - c;
-        if (c == n) identity[d] = 1;
-    }
-    __syncthreads();
-    if (t == 0) {
-        int exec[kMaxRounds];
-        int m = 0;
-        for (uint32_t d = 0; d < nrounds; ++d) {
-            exec[d] = !identity[d];
-            m += exec[d];
-        }
-        // The last round must land in the caller's output and no round may
-        // read and write the same buffer.  Rounds alternate between output and
-        // temporary backwards from the last one, so: without aliasing at least
-        // one round must run; in place, an even number must (re-enable an
-        // identity round, or copy the input to the temporary first).
-        int precopy = 0;
-        if (!in_place && m == 0) {
-            exec[nrounds - 1] = 1;
-            m = 1;
-        } else if (in_place && (m & 1)) {
-            int added = 0;
-            for (int d = (int)nrounds - 1; d >= 0 && !added; --d)
-                if (!exec[d]) { exec[d] = 1; added = 1; }
-            if (added) ++m; else precopy = 1;
-        }
-        int ord = 0;
-        int src = precopy ? 2 : 0;
-        for (uint32_t d = 0; d < nrounds; ++d) {
-            RoundPlan p;
-            p.exec = exec[d];
-            p.ord = exec[d] ? ord : -1;
-            p.src = src;
-            p.dst = exec[d] ? (((m - 1 - ord) & 1) ? 2 : 1) : -1;
-            if (exec[d]) {
-                src = p.dst;
-                ++ord;
-            }
-            plan[d] = p;
-        }
-        RoundPlan pc;
-        pc.exec = precopy;
-        pc.ord = m;
-        pc.src = 0;
-        pc.dst = 2;
-        plan[kMaxRounds] = pc;
-    }
-}
-
-// In-place sorts with an odd number of running rounds: copy input -> temporary.
-template <typename K>
-__global__ void k_precopy(const RoundPlan* plan, const K* keys, K* keys_tmp,
-                          const uint32_t* vals, uint32_t* vals_tmp, uint32_t n)
-{
-    if (!plan[kMaxRounds].exec) return;
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        keys_tmp[i] = keys[i];
-        if (vals) vals_tmp[i] = vals[i];
-    }
-}
-
-// ---------------------------------------------------------------------------
-// k_count: counts[tile][v] = keys of digit v in the tile.
-//
-// Every lane counts into its own column of a [256][32] table (lane l of every
-// wave uses column l mod 32), so the 32 lanes of a half-wave always hit 32
-// different LDS banks; the columns are summed at the end.
-template <typename K, int WG, int ITEMS>
-__global__ __launch_bounds__(WG) void k_count(RoundArgs a)
-{
-    constexpr uint32_t TILE = (uint32_t)WG * ITEMS;
-    __shared__ uint32_t h[R * 32];
-    const RoundPlan pl = a.plan[a.round];
-    if (!pl.exec) return;
-    const uint32_t tid = threadIdx.x;
-    for (uint32_t i = tid; i < R * 32 / 4; i += WG) ((uint4*)h)[i] = make_uint4(0, 0, 0, 0);
-    __syncthreads();
-    const uint32_t tile = xcd_tile(a.ntiles);
-    const uint32_t base = tile * TILE;
-    const uint32_t lim = min(TILE, a.n - base);
-    const K* src = pick<K>(pl.src, (const K*)a.keys_in, (K*)a.keys_out, (K*)a.keys_tmp) + base;
-    K k[ITEMS];
-#pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        const uint32_t o = i * WG + tid;
-        k[i] = o < lim ? src[o] : K(0);
-    }
-    const uint32_t col = tid & 31;
-#pragma unroll
-    for (int i = 0; i < ITEMS; ++i)
-        if (i * WG + tid < lim) atomicAdd(&h[digit_of(k[i], a.shift, a.mask) * 32 + col], 1u);
-    __syncthreads();
-    for (uint32_t v = tid; v < R; v += WG) {
-        const uint4* r4 = (const uint4*)&h[v * 32];
-        uint32_t s = 0;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const uint4 x = r4[(q + v) & 7];   // rotate the start so threads spread over banks
-            s += x.x + x.y + x.z + x.w;
-        }
-        a.counts[(size_t)tile * R + v] = s;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// k_tilescan: replaces counts[t][v] by bases[v] + sum of counts[t'][v] over
-// t' < t.  Workgroup = block of kScanBlock tiles taken in ticket order; thread
-// v sums its digit over the block, publishes the block total, folds the totals
-// of earlier blocks by decoupled look-back (a packed flag+count word per block
-// and digit), publishes the inclusive prefix and rewrites its column.
-__global__ __launch_bounds__(R) void k_tilescan(RoundArgs a)
-{
-    __shared__ uint32_t blk_s;
-    const RoundPlan pl = a.plan[a.round];
-    if (!pl.exec) return;
-    const uint32_t v = threadIdx.x;
-    if (v == 0) blk_s = atomicAdd(&a.tickets[a.round], 1u);
-    __syncthreads();
-    const uint32_t blk = blk_s;
-    const uint32_t nblocks = (a.ntiles + kScanBlock - 1) / kScanBlock;
-    uint32_t* state = a.blk_state + (size_t)a.round * nblocks * R;
-    const uint32_t t0 = blk * kScanBlock;
-    const uint32_t t1 = min(a.ntiles, t0 + kScanBlock);
-    uint32_t* col = a.counts + v;
-
-    uint32_t c[kScanBlock];
-    uint32_t total = 0;
-#pragma unroll
-    for (uint32_t i = 0; i < kScanBlock; ++i) {
-        c[i] = t0 + i < t1 ? col[(size_t)(t0 + i) * R] : 0u;
-        total += c[i];
-    }
-    st_agent(&state[(size_t)blk * R + v], (blk == 0 ? kFlagPrefix : kFlagAggregate) | total);
-
-    uint32_t excl = 0;
-    if (blk > 0) {
-        uint32_t j = blk;   // entries j-1, j-2, ... are still to be folded
-        uint32_t spins = 0;
-        for (;;) {
-            uint32_t lb[LB_WINDOW];
-#pragma unroll
-            for (int q = 0; q < LB_WINDOW; ++q)
-                lb[q] = (uint32_t)q < j ? ld_agent(&state[(size_t)(j - 1 - q) * R + v]) : kFlagPrefix;
-            uint32_t used = 0;
-            bool done = false;
-#pragma unroll
-            for (int q = 0; q < LB_WINDOW; ++q) {
-                if (!done && used == (uint32_t)q) {
-                    const uint32_t f = lb[q] >> kFlagShift;
-                    if (f != 0) {
-                        excl += lb[q] & kCountMask;
-                        used = q + 1;
-                        done = f == (kFlagPrefix >> kFlagShift);
-                    }
-                }
-            }
-            if (done) break;
-            j -= used;
-            if (used == 0) {
-                // Give up after kSpinLimit polls, or at once if another
-                // workgroup already gave up, so the grid always drains.
-                if (++spins > kSpinLimit ||
-                    ((spins & 255u) == 0 && (ld_agent(a.err) & kErrLookbackTimeout))) {
-                    atomicOr(a.err, (uint32_t)kErrLookbackTimeout);
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-            }
-        }
-        st_agent(&state[(size_t)blk * R + v], kFlagPrefix | ((excl + total) & kCountMask));
-    }
-    uint32_t run = a.bases[a.round * R + v] + excl;
-#pragma unroll
-    for (uint32_t i = 0; i < kScanBlock; ++i) {
-        if (t0 + i < t1) col[(size_t)(t0 + i) * R] = run;
-        run += c[i];
-    }
-}
-
-// ---------------------------------------------------------------------------
-// k_scatter: one stable count-sort round of one tile.
-//
-// Layout: the tile is split among half-waves (32 lanes); half-wave h owns the
-// contiguous keys [h*ITEMS*32, (h+1)*ITEMS*32) of the tile, row i lane l at
-// h*ITEMS*32 + i*32 + (l & 31), so "earlier in the input" is lexicographic
-// (h, i, l) -- the order the ranking preserves.
-// Each half-wave has one 64-bit slot per digit value: the set of its lanes
-// holding that digit in the current row (low word) and the number of its keys
-// of that digit in earlier rows (high word).
-//   rank   row by row, lanes OR their bit into the slot of their digit, read
-//          the slot back -- the lanes below with the same digit plus the count
-//          give the key's rank among the half-wave's keys of that digit -- and
-//          write the slot back as {no lanes, count + lanes in the set};
-//   bases  digit thread v turns the counts of all half-waves into slot bases
-//          inside the tile (prefix over half-waves plus the tile's prefix over
-//          digits), written over the counts;
-//   stage  each key goes to LDS at base + rank, the tile now in digit order;
-//   scatter consecutive threads write consecutive slots of a digit's run; the
-//          payloads follow in a second staging pass through the same LDS.
-template <typename K, bool KV, int WG, int ITEMS>
-__global__ __launch_bounds__(WG, KV ? RSORT_R8_WAVES_PER_EU_KV : RSORT_R8_WAVES_PER_EU) void k_scatter(RoundArgs a)
-{
-    constexpr int HW = WG / 32;                 // half-waves
-    constexpr uint32_t TILE = (uint32_t)WG * ITEMS;
-    constexpr bool rank_first = RSORT_RANK_FIRST < 0 ? KV : RSORT_RANK_FIRST != 0;
-    static_assert(TILE * sizeof(K) >= HW * R * sizeof(uint2), "staging must cover the slots");
-    struct Smem {
-        union {
-            uint2 slot[HW][R];           // {lane set, count}, then {-, slot base}
-            K keys[TILE];                // staging: the tile in digit order
-            uint32_t vals[TILE];         // staging of the payloads (second pass)
-        } u;
-        uint32_t goff[R];                // output index of tile slot 0 of each digit
-        uint32_t wsum[4];
-    };
-    __shared__ Smem sm;
-
-    const RoundPlan pl = a.plan[a.round];
-    if (!pl.exec) return;
-
-    const uint32_t tid = threadIdx.x;
-    const uint32_t lane = tid & 63;
-    const uint32_t wave = tid >> 6;
-    const uint32_t hw = tid >> 5;
-    const uint32_t hl = tid & 31;
-    const uint32_t hofs = hw * ITEMS * 32 + hl;
-    const K* src = pick<K>(pl.src, (const K*)a.keys_in, (K*)a.keys_out, (K*)a.keys_tmp);
-    const uint32_t* vsrc = KV ? pick<uint32_t>(pl.src, a.vals_in, a.vals_out, a.vals_tmp) : nullptr;
-    K* dst = pick<K>(pl.dst, (const K*)a.keys_in, (K*)a.keys_out, (K*)a.keys_tmp);
-    uint32_t* vdst = KV ? pick<uint32_t>(pl.dst, a.vals_in, a.vals_out, a.vals_tmp) : nullptr;
-
-    auto load = [&](uint32_t t, K (&kk)[ITEMS], uint32_t (&vv)[ITEMS]) {
-        const uint32_t base = t * TILE;
-        const uint32_t lim = a.n - base;
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i) {
-            const uint32_t o = hofs + i * 32;
-            kk[i] = o < lim ? src[base + o] : K(0);
-            if (KV) vv[i] = o < lim ? vsrc[base + o] : 0u;
-        }
-    };
-
-    // One tile whose keys are in k/v; the keys of tile tn (if any) are loaded
-    // into kn/vn once k has been counted, so that those loads are in flight
-    // while this tile is ranked, staged and written.
-    auto process = [&](uint32_t tile, K (&k)[ITEMS], uint32_t (&v)[ITEMS], uint32_t tn,
-                       K (&kn)[ITEMS], uint32_t (&vn)[ITEMS]) {
-        const uint32_t base = tile * TILE;
-        const uint32_t lim = a.n - base;   // keys in this tile (>= TILE except the last)
-        for (uint32_t i = tid; i < HW * R / 2; i += WG)
-            ((uint4*)&sm.u.slot[0][0])[i] = make_uint4(0, 0, 0, 0);
-        uint32_t toff = 0;
-        if (tid < R) toff = a.counts[(size_t)tile * R + tid];
-        __syncthreads();
-
-        // Rank row by row; the high word of a slot is advanced by the lanes of
-        // the row that hold its digit.  Gives each key's rank plus the word's
-        // value before the key's row.
-        uint32_t pos[ITEMS];
-        auto rank = [&]() {
-            uint2* sl = sm.u.slot[hw];
-            const uint32_t bit = 1u << hl;
-            const uint32_t lowsel = lane < 32 ? ~0u : 0u;
-#pragma unroll
-            for (int i = 0; i < ITEMS; ++i) {
-                const bool ok = hofs + i * 32 < lim;
-                const uint32_t d = digit_of(k[i], a.shift, a.mask);
-                if (ok) __hip_atomic_fetch_or(&sl[d].x, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                wave_lds_order();
-                const uint64_t s = ok ? __hip_atomic_load((uint64_t*)&sl[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : 0ull;
-                const uint32_t m = (uint32_t)s, c = (uint32_t)(s >> 32);
-                pos[i] = __builtin_amdgcn_mbcnt_hi(m, __builtin_amdgcn_mbcnt_lo(m & lowsel, c));
-                wave_lds_order();
-                if (ok)
-                    __hip_atomic_store((uint64_t*)&sl[d], (uint64_t)(c + __builtin_popcount(m)) << 32,
-                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                wave_lds_order();
-            }
-        };
-
-        if (rank_first) {
-            // rank with counts starting at zero; the counts end up in the slots
-            rank();
-        } else {
-            // count first: the slots' high words get the per-half-wave counts
-            uint2* sl = sm.u.slot[hw];
-#pragma unroll
-            for (int i = 0; i < ITEMS; ++i)
-                if (hofs + i * 32 < lim) atomicAdd(&sl[digit_of(k[i], a.shift, a.mask)].y, 1u);
-        }
-        if (RSORT_SCATTER_PERSIST && tn < a.ntiles) load(tn, kn, vn);
-        __syncthreads();
-
-        // bases
-        uint32_t run = 0;
-        if (tid < R) {
-            uint32_t total = 0;
-#pragma unroll
-            for (int h = 0; h < HW; ++h) total += sm.u.slot[h][tid].y;
-            const uint32_t incl = wave_inclusive_sum(total);
-            if (lane == 63) sm.wsum[wave] = incl;
-            run = incl - total;
-        }
-        __syncthreads();
-        if (tid < R) {
-            for (uint32_t w = 0; w < wave; ++w) run += sm.wsum[w];
-            sm.goff[tid] = toff - run;
-#pragma unroll
-            for (int h = 0; h < HW; ++h) {
-                const uint32_t c = sm.u.slot[h][tid].y;
-                sm.u.slot[h][tid].y = run;
-                run += c;
-            }
-        }
-        __syncthreads();
-        if (rank_first) {
-#pragma unroll
-            for (int i = 0; i < ITEMS; ++i) {
-                // Recompute the digit here rather than keep 16 slot addresses
-                // alive across the bases phase (registers limit occupancy).
-                __asm__ volatile("" : "+v"(k[i]));
-                pos[i] += sm.u.slot[hw][digit_of(k[i], a.shift, a.mask)].y;
-            }
-        } else {
-            rank();   // the high words now start at the slot bases
-        }
-        __syncthreads();
-
-        // scatter
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i)
-            if (hofs + i * 32 < lim) sm.u.keys[pos[i]] = k[i];
-        __syncthreads();
-        uint32_t outi[KV ? ITEMS : 1];
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i) {
-            const uint32_t p = i * WG + tid;
-            uint32_t o = a.n;
-            if (p < lim) {
-                const K key = sm.u.keys[p];
-                o = sm.goff[digit_of(key, a.shift, a.mask)] + p;
-                if (o < a.n) store_out(&dst[o], key);   // always true unless a tile-scan wait was abandoned
-            }
-            if (KV) outi[i] = o;
-        }
-        if (KV) {
-            __syncthreads();
-#pragma unroll
-            for (int i = 0; i < ITEMS; ++i)
-                if (hofs + i * 32 < lim) sm.u.vals[pos[i]] = v[i];
-            __syncthreads();
-#pragma unroll
-            for (int i = 0; i < ITEMS; ++i) {
-                const uint32_t p = i * WG + tid;
-                if (p < lim && outi[i] < a.n) store_out(&vdst[outi[i]], sm.u.vals[p]);
-            }
-        }
-        __syncthreads();   // staging and goff are free for the next tile
-    };
-
-    // Tile sequence of this workgroup: with a grid smaller than the tile count
-    // each workgroup loops.  When both counts are multiples of 8 every XCD owns
-    // a contiguous eighth of the tiles (blocks are dealt to XCDs in turn), so
-    // neighbouring tiles write their shared cache lines through the same L2.
-    const uint32_t b = blockIdx.x, G = gridDim.x;
-    const bool xcd = (a.ntiles & 7) == 0 && (G & 7) == 0;
-    const uint32_t per = a.ntiles >> 3, g8 = G >> 3, x = b & 7;
-    uint32_t tile = xcd ? x * per + (b >> 3) : b;
-    auto next_of = [&](uint32_t t) -> uint32_t {
-        if (xcd) {
-            const uint32_t l = t - x * per + g8;
-            return l < per ? x * per + l : a.ntiles;
-        }
-        return t + G < a.ntiles ? t + G : a.ntiles;
-    };
-    if (tile >= a.ntiles) return;
-
-    K ka[ITEMS];
-    uint32_t va[ITEMS];
-    load(tile, ka, va);
-    if constexpr (!RSORT_SCATTER_PERSIST) {
-        process(tile, ka, va, a.ntiles, ka, va);
-        return;
-    }
-    K kb[ITEMS];
-    uint32_t vb[ITEMS];
-    for (;;) {
-        uint32_t tn = next_of(tile);
-        process(tile, ka, va, tn, kb, vb);
-        tile = tn;
-        if (tile >= a.ntiles) break;
-        tn = next_of(tile);
-        process(tile, kb, vb, tn, ka, va);
-        tile = tn;
-        if (tile >= a.ntiles) break;
-    }
-}
 
 // Plain copy: 16-byte words when both pointers are 16-byte aligned, bytes otherwise.
 __global__ void k_copy_bytes(const uint8_t* src, uint8_t* dst, size_t bytes)
@@ -739,6 +145,7 @@ hipError_t run(const void* keys_in, void* keys_out, const uint32_t* vals_in, uin
         a.blk_state = blk_state;
         a.tickets = tickets;
         a.err = dev_err;
+        a.tiles = nullptr;
         if (prof) profiler_mark(prof, stream, kKindCount, true);
         hipLaunchKernelGGL((k_count<K, WG, ITEMS>), dim3(L.ntiles), dim3(WG), 0, stream, a);
         if (prof) profiler_mark(prof, stream, kKindCount, false);

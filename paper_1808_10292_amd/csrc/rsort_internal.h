@@ -5,6 +5,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace rsort {
 
 constexpr size_t kAlign = 256;
@@ -28,7 +30,7 @@ constexpr int kHistReplicas = 8;   // global histogram copies, picked by block i
 
 // Optional kernel timing: HIP events recorded on the launch stream around the
 // kernels of one kind (implemented in api.hip).  nullptr disables it.
-enum KernelKind { kKindRound = 0, kKindHist = 1, kKindCount = 2, kKindTileScan = 3, kNumKinds = 4 };
+enum KernelKind { kKindRound = 0, kKindHist = 1, kKindCount = 2, kKindTileScan = 3, kKindSmall = 4, kNumKinds = 5 };
 struct Profiler;
 void profiler_mark(Profiler* p, hipStream_t s, int kind, bool begin);
 
@@ -56,6 +58,26 @@ size_t histogram_ws_bytes(int digit_bits, int begin_bit, int end_bit);
 hipError_t histogram(int key_bytes, const void* keys, size_t n, int digit_bits,
                      int begin_bit, int end_bit, uint32_t* hist_out, void* ws,
                      hipStream_t stream);
+
+// ---------------------------------------------------------------------------
+// Batched segmented sort (segmented.hip).  Segments of at most small_max keys
+// are sorted whole in LDS by one workgroup (three capacity classes); larger
+// ones are cut into tiles for the round kernels.
+struct SegPlan {
+    std::vector<uint2> small[3];   // {first key, end} per small segment, by class
+    std::vector<uint2> tiles;      // {first key, end} per tile of the large segments
+    std::vector<uint4> lsegs;      // {first tile, end tile, first key, 0} per large segment
+};
+constexpr uint32_t kSmallMaxDefault = 8192;
+void segmented_plan(const uint64_t* offsets, size_t num_segs, uint32_t small_max, int key_bytes,
+                    SegPlan& P);
+size_t segmented_meta_bytes(const SegPlan& P);
+size_t segmented_ws_bytes(int key_bytes, bool has_vals, size_t total, const SegPlan& P);
+void segmented_pack(const SegPlan& P, int key_bytes, void* host);
+hipError_t segmented_sort(int key_bytes, const void* keys_in, void* keys_out,
+                          const uint32_t* vals_in, uint32_t* vals_out, size_t total,
+                          const SegPlan& P, const void* host_meta, void* ws, uint32_t* dev_err,
+                          hipStream_t stream, Profiler* prof);
 
 // Plain device copy used when a sort moves nothing (empty bit range).
 hipError_t copy_bytes(void* dst, const void* src, size_t bytes, hipStream_t stream);

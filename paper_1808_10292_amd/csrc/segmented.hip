@@ -1,0 +1,387 @@
+// Batched segmented sorting: many independent arrays (CSR segments of one key
+// array) sorted in one call, each by the stable LSD radix-2^8 sort of
+// arXiv 1808.10292 Section 3.2 (SR4 applied per segment).
+//
+// Segments are split by size on the host:
+//   small (<= 8192 keys): one workgroup sorts the whole segment in LDS --
+//           every round is count, bases, rank and restage inside the
+//           workgroup, so the segment is read from HBM once and written once
+//           (k_seg_small, three tile capacities: 1024, 4096, 8192 keys);
+//   large:  split into tiles of 8192 keys that never cross a segment; each
+//           round is the plain sort's k_count and k_scatter over the tile list,
+//           with k_segscan turning the tile counts of every segment into output
+//           starts (one workgroup per segment).
+// The size split is a parameter the tuner (rsort_segmented_tune) chooses.
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "lsd_kernels.h"
+
+namespace rsort {
+namespace {
+
+// ---------------------------------------------------------------------------
+// k_seg_small: one workgroup sorts segment blockIdx.x of the list in LDS.
+// Layout as in k_scatter: half-wave h owns positions [h*ITEMS*32, ...) of the
+// segment, row i lane l at h*ITEMS*32 + 32*i + l.  Each round reads the keys
+// in that layout from the staging array, counts into 64-bit slots, converts the
+// counts to slot bases, ranks (lane sets), and writes keys (and payloads) back
+// to the staging array at their new positions.  A round in which one digit
+// value holds every key of the segment moves nothing and is skipped.
+template <typename K, bool KV, int WG, int ITEMS>
+__global__ __launch_bounds__(WG) void k_seg_small(const K* __restrict__ keys_in, K* keys_out,
+                                                  const uint32_t* __restrict__ vals_in,
+                                                  uint32_t* vals_out, const uint2* segs,
+                                                  uint32_t nrounds)
+{
+    constexpr int HW = WG / 32;
+    constexpr uint32_t TILE = (uint32_t)WG * ITEMS;
+    struct Smem {
+        K keys[TILE];
+        uint32_t vals[KV ? TILE : 1];
+        uint2 slot[HW][R];
+        uint32_t wsum[4];
+    };
+    __shared__ Smem sm;
+
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & 63;
+    const uint32_t wave = tid >> 6;
+    const uint32_t hw = tid >> 5;
+    const uint32_t hl = tid & 31;
+    const uint32_t hofs = hw * ITEMS * 32 + hl;
+    const uint2 seg = segs[blockIdx.x];
+    const uint32_t base = seg.x;
+    const uint32_t len = seg.y - seg.x;
+
+    K k[ITEMS];
+    uint32_t v[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t o = hofs + i * 32;
+        k[i] = o < len ? keys_in[base + o] : K(0);
+        if (KV) v[i] = o < len ? vals_in[base + o] : 0u;
+    }
+
+    for (uint32_t r = 0; r < nrounds; ++r) {
+        const uint32_t shift = 8u * r;
+        for (uint32_t i = tid; i < HW * R / 2; i += WG)
+            ((uint4*)&sm.slot[0][0])[i] = make_uint4(0, 0, 0, 0);
+        __syncthreads();
+        // count
+        uint2* sl = sm.slot[hw];
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i)
+            if (hofs + i * 32 < len) atomicAdd(&sl[digit_of(k[i], shift, 0xFFu)].y, 1u);
+        __syncthreads();
+        // bases
+        uint32_t run = 0, total = 0;
+        if (tid < R) {
+#pragma unroll
+            for (int h = 0; h < HW; ++h) total += sm.slot[h][tid].y;
+            const uint32_t incl = wave_inclusive_sum(total);
+            if (lane == 63) sm.wsum[wave] = incl;
+            run = incl - total;
+        }
+        // barrier + "some digit value holds every key": the round is the identity
+        if (__syncthreads_or(tid < R && total == len)) continue;
+        if (tid < R) {
+            for (uint32_t w = 0; w < wave; ++w) run += sm.wsum[w];
+#pragma unroll
+            for (int h = 0; h < HW; ++h) {
+                const uint32_t c = sm.slot[h][tid].y;
+                sm.slot[h][tid].y = run;
+                run += c;
+            }
+        }
+        __syncthreads();
+        // rank
+        uint32_t pos[ITEMS];
+        {
+            const uint32_t bit = 1u << hl;
+            const uint32_t lowsel = lane < 32 ? ~0u : 0u;
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                const bool ok = hofs + i * 32 < len;
+                const uint32_t d = digit_of(k[i], shift, 0xFFu);
+                if (ok) __hip_atomic_fetch_or(&sl[d].x, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                wave_lds_order();
+                const uint64_t s = ok ? __hip_atomic_load((uint64_t*)&sl[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : 0ull;
+                const uint32_t m = (uint32_t)s, c = (uint32_t)(s >> 32);
+                pos[i] = __builtin_amdgcn_mbcnt_hi(m, __builtin_amdgcn_mbcnt_lo(m & lowsel, c));
+                wave_lds_order();
+                if (ok)
+                    __hip_atomic_store((uint64_t*)&sl[d], (uint64_t)(c + __builtin_popcount(m)) << 32,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                wave_lds_order();
+            }
+        }
+        // restage in the new order and reload in the ranking layout
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            if (hofs + i * 32 < len) {
+                sm.keys[pos[i]] = k[i];
+                if (KV) sm.vals[pos[i]] = v[i];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t o = hofs + i * 32;
+            if (o < len) {
+                k[i] = sm.keys[o];
+                if (KV) v[i] = sm.vals[o];
+            }
+        }
+        __syncthreads();
+    }
+    // write out: each thread holds positions hofs + 32 i in the final order
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t o = hofs + i * 32;
+        if (o < len) {
+            keys_out[base + o] = k[i];
+            if (KV) vals_out[base + o] = v[i];
+        }
+    }
+}
+
+// k_segscan: one workgroup per large segment {first tile, end tile, first key}.
+// Thread v sums its digit over the segment's tiles, the 256 totals are scanned
+// into the digit starts inside the segment, and every tile count is replaced
+// by the output index of the tile's first key of digit v.
+__global__ __launch_bounds__(R) void k_segscan(RoundArgs a, const uint4* lsegs)
+{
+    __shared__ uint32_t wsum[4];
+    const RoundPlan pl = a.plan[a.round];
+    if (!pl.exec) return;
+    const uint4 sg = lsegs[blockIdx.x];
+    const uint32_t v = threadIdx.x;
+    uint32_t* col = a.counts + v;
+    uint32_t total = 0;
+    uint32_t t = sg.x;
+    for (; t + 4 <= sg.y; t += 4) {
+        const uint32_t c0 = col[(size_t)t * R], c1 = col[(size_t)(t + 1) * R];
+        const uint32_t c2 = col[(size_t)(t + 2) * R], c3 = col[(size_t)(t + 3) * R];
+        total += c0 + c1 + c2 + c3;
+    }
+    for (; t < sg.y; ++t) total += col[(size_t)t * R];
+    const uint32_t lane = v & 63, wave = v >> 6;
+    const uint32_t incl = wave_inclusive_sum(total);
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    uint32_t run = sg.z + incl - total;
+    for (uint32_t w = 0; w < wave; ++w) run += wsum[w];
+    for (t = sg.x; t < sg.y; ++t) {
+        const uint32_t c = col[(size_t)t * R];
+        col[(size_t)t * R] = run;
+        run += c;
+    }
+}
+
+// Small-segment kernel classes: capacity = WG * ITEMS keys.
+struct SmallClass {
+    int wg, items;
+};
+constexpr SmallClass kSmallClasses[3] = {{256, 4}, {512, 8}, {512, 16}};
+// Keys per tile of the large path: the tile of the plain sort's round kernels.
+uint32_t large_tile(int key_bytes)
+{
+    return key_bytes == 8 ? R8Config<uint64_t>::WG * R8Config<uint64_t>::ITEMS
+                          : R8Config<uint32_t>::WG * R8Config<uint32_t>::ITEMS;
+}
+
+template <typename K, bool KV>
+void launch_small(int cls, const void* ki, void* ko, const uint32_t* vi, uint32_t* vo,
+                  const uint2* segs, uint32_t nsegs, uint32_t nrounds, hipStream_t s)
+{
+    if (!nsegs) return;
+    switch (cls) {
+    case 0:
+        hipLaunchKernelGGL((k_seg_small<K, KV, 256, 4>), dim3(nsegs), dim3(256), 0, s,
+                           (const K*)ki, (K*)ko, vi, vo, segs, nrounds);
+        break;
+    case 1:
+        hipLaunchKernelGGL((k_seg_small<K, KV, 512, 8>), dim3(nsegs), dim3(512), 0, s,
+                           (const K*)ki, (K*)ko, vi, vo, segs, nrounds);
+        break;
+    default:
+        hipLaunchKernelGGL((k_seg_small<K, KV, 512, 16>), dim3(nsegs), dim3(512), 0, s,
+                           (const K*)ki, (K*)ko, vi, vo, segs, nrounds);
+        break;
+    }
+}
+
+}  // namespace
+
+// Host-side plan: which segments go to which small class, the large tiles and
+// the large segments.  Built from host CSR offsets.
+void segmented_plan(const uint64_t* off, size_t nsegs, uint32_t small_max, int key_bytes,
+                    SegPlan& P)
+{
+    P.small[0].clear();
+    P.small[1].clear();
+    P.small[2].clear();
+    P.tiles.clear();
+    P.lsegs.clear();
+    const uint32_t tile = large_tile(key_bytes);
+    for (size_t s = 0; s < nsegs; ++s) {
+        const uint32_t lo = (uint32_t)off[s], hi = (uint32_t)off[s + 1];
+        const uint32_t len = hi - lo;
+        if (len == 0) continue;
+        if (len <= small_max) {
+            int cls = 2;
+            for (int c = 0; c < 3; ++c)
+                if (len <= (uint32_t)(kSmallClasses[c].wg * kSmallClasses[c].items)) { cls = c; break; }
+            P.small[cls].push_back(make_uint2(lo, hi));
+        } else {
+            const uint32_t t0 = (uint32_t)P.tiles.size();
+            for (uint32_t b = lo; b < hi; b += tile) P.tiles.push_back(make_uint2(b, std::min(hi, b + tile)));
+            P.lsegs.push_back(make_uint4(t0, (uint32_t)P.tiles.size(), lo, 0));
+        }
+    }
+}
+
+size_t segmented_ws_bytes(int key_bytes, bool has_vals, size_t total, const SegPlan& P)
+{
+    const size_t nt = P.tiles.size();
+    size_t o = 0;
+    o = align_up(o + (P.tiles.empty() ? 0 : total * key_bytes));          // tmp keys
+    o = align_up(o + (P.tiles.empty() || !has_vals ? 0 : total * 4));      // tmp vals
+    o = align_up(o + nt * R * 4);                                          // tile counts
+    o = align_up(o + segmented_meta_bytes(P));                             // plan + lists
+    return o;
+}
+
+size_t segmented_meta_bytes(const SegPlan& P)
+{
+    return align_up((kMaxRounds + 1) * sizeof(RoundPlan), 16) +
+           (P.small[0].size() + P.small[1].size() + P.small[2].size() + P.tiles.size()) * sizeof(uint2) +
+           P.lsegs.size() * sizeof(uint4);
+}
+
+// Pack the round plan and the lists into `host` (pinned): plan, small[0..2],
+// tiles, lsegs.  Large segments run every round (no identity skipping), so the
+// plan is static; the key width gives an even number of rounds, which ends in
+// the output whether or not the sort is in place.
+void segmented_pack(const SegPlan& P, int key_bytes, void* host)
+{
+    uint8_t* h = (uint8_t*)host;
+    RoundPlan* plan = (RoundPlan*)h;
+    const int rounds = key_bytes;
+    int src = 0;
+    for (int d = 0; d < kMaxRounds; ++d) {
+        RoundPlan r{0, -1, 0, -1};
+        if (d < rounds) {
+            r.exec = 1;
+            r.ord = d;
+            r.src = src;
+            r.dst = ((rounds - 1 - d) & 1) ? 2 : 1;
+            src = r.dst;
+        }
+        plan[d] = r;
+    }
+    plan[kMaxRounds] = RoundPlan{0, 0, 0, 2};
+    h += align_up((kMaxRounds + 1) * sizeof(RoundPlan), 16);
+    for (int c = 0; c < 3; ++c) {
+        memcpy(h, P.small[c].data(), P.small[c].size() * sizeof(uint2));
+        h += P.small[c].size() * sizeof(uint2);
+    }
+    memcpy(h, P.tiles.data(), P.tiles.size() * sizeof(uint2));
+    h += P.tiles.size() * sizeof(uint2);
+    memcpy(h, P.lsegs.data(), P.lsegs.size() * sizeof(uint4));
+}
+
+namespace {
+
+template <typename K, bool KV>
+hipError_t run_segmented(const void* keys_in, void* keys_out, const uint32_t* vals_in,
+                         uint32_t* vals_out, size_t total, const SegPlan& P, const void* host_meta,
+                         void* ws, uint32_t* dev_err, hipStream_t stream, Profiler* prof)
+{
+    const uint32_t nrounds = sizeof(K);   // 8-bit digits over the whole key
+    const size_t nt = P.tiles.size();
+    uint8_t* w = (uint8_t*)ws;
+    size_t o = 0;
+    K* keys_tmp = (K*)(w + o);          o = align_up(o + (nt ? total * sizeof(K) : 0));
+    uint32_t* vals_tmp = (uint32_t*)(w + o); o = align_up(o + (nt && KV ? total * 4 : 0));
+    uint32_t* counts = (uint32_t*)(w + o);   o = align_up(o + nt * R * 4);
+    uint8_t* meta = w + o;
+    const size_t meta_bytes = segmented_meta_bytes(P);
+    hipError_t e = hipSuccess;
+    if (meta_bytes && host_meta) {   // null: the plan is already in the workspace
+        e = hipMemcpyAsync(meta, host_meta, meta_bytes, hipMemcpyHostToDevice, stream);
+        if (e != hipSuccess) return e;
+    }
+    const RoundPlan* plan = (const RoundPlan*)meta;
+    const uint2* small[3];
+    uint8_t* m = meta + align_up((kMaxRounds + 1) * sizeof(RoundPlan), 16);
+    for (int c = 0; c < 3; ++c) {
+        small[c] = (const uint2*)m;
+        m += P.small[c].size() * sizeof(uint2);
+    }
+    const uint2* tiles = (const uint2*)m;
+    m += nt * sizeof(uint2);
+    const uint4* lsegs = (const uint4*)m;
+
+    if (prof) profiler_mark(prof, stream, kKindSmall, true);
+    for (int c = 0; c < 3; ++c)
+        launch_small<K, KV>(c, keys_in, keys_out, KV ? vals_in : nullptr, KV ? vals_out : nullptr,
+                            small[c], (uint32_t)P.small[c].size(), nrounds, stream);
+    if (prof) profiler_mark(prof, stream, kKindSmall, false);
+    if (!nt) return hipGetLastError();
+
+    // Large segments: every round runs; the plan arrived with the lists.
+    constexpr int WG = R8Config<K>::WG;
+    constexpr int ITEMS = R8Config<K>::ITEMS;
+    const int rounds = (int)nrounds;
+    for (int d = 0; d < rounds; ++d) {
+        RoundArgs a;
+        a.keys_in = keys_in;
+        a.keys_out = keys_out;
+        a.keys_tmp = keys_tmp;
+        a.vals_in = vals_in;
+        a.vals_out = vals_out;
+        a.vals_tmp = vals_tmp;
+        a.n = (uint32_t)total;
+        a.shift = 8u * d;
+        a.mask = 0xFFu;
+        a.round = d;
+        a.ntiles = (uint32_t)nt;
+        a.bases = nullptr;
+        a.plan = plan;
+        a.counts = counts;
+        a.blk_state = nullptr;
+        a.tickets = nullptr;
+        a.err = dev_err;
+        a.tiles = tiles;
+        if (prof) profiler_mark(prof, stream, kKindCount, true);
+        hipLaunchKernelGGL((k_count<K, WG, ITEMS>), dim3(nt), dim3(WG), 0, stream, a);
+        if (prof) profiler_mark(prof, stream, kKindCount, false);
+        if (prof) profiler_mark(prof, stream, kKindTileScan, true);
+        hipLaunchKernelGGL(k_segscan, dim3((uint32_t)P.lsegs.size()), dim3(R), 0, stream, a, lsegs);
+        if (prof) profiler_mark(prof, stream, kKindTileScan, false);
+        if (prof) profiler_mark(prof, stream, kKindRound, true);
+        hipLaunchKernelGGL((k_scatter<K, KV, WG, ITEMS>), dim3(nt), dim3(WG), 0, stream, a);
+        if (prof) profiler_mark(prof, stream, kKindRound, false);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t segmented_sort(int key_bytes, const void* keys_in, void* keys_out,
+                          const uint32_t* vals_in, uint32_t* vals_out, size_t total,
+                          const SegPlan& P, const void* host_meta, void* ws, uint32_t* dev_err,
+                          hipStream_t stream, Profiler* prof)
+{
+    const bool kv = vals_in != nullptr;
+    if (key_bytes == 4)
+        return kv ? run_segmented<uint32_t, true>(keys_in, keys_out, vals_in, vals_out, total, P, host_meta, ws, dev_err, stream, prof)
+                  : run_segmented<uint32_t, false>(keys_in, keys_out, vals_in, vals_out, total, P, host_meta, ws, dev_err, stream, prof);
+    return kv ? run_segmented<uint64_t, true>(keys_in, keys_out, vals_in, vals_out, total, P, host_meta, ws, dev_err, stream, prof)
+              : run_segmented<uint64_t, false>(keys_in, keys_out, vals_in, vals_out, total, P, host_meta, ws, dev_err, stream, prof);
+}
+
+}  // namespace rsort

@@ -42,12 +42,15 @@ ALGOS = {"auto": RSORT_AUTO, "lsd8": RSORT_LSD_R8, "pr4": RSORT_LSD_R8,
 # Every symbol include/rsort.h declares; the loader checks they all exist.
 EXPORTED = ("rsort_create", "rsort_destroy", "rsort_status_string", "rsort_last_error",
             "rsort_workspace_bytes", "rsort_sort", "rsort_histogram", "rsort_synchronize",
-            "rsort_profile_enable", "rsort_profile_read")
+            "rsort_profile_enable", "rsort_profile_read", "rsort_segmented_sort",
+            "rsort_segmented_workspace_bytes", "rsort_segmented_set_split",
+            "rsort_segmented_tune")
 
 RSORT_KERNEL_ROUND = 0
 RSORT_KERNEL_HIST = 1
 RSORT_KERNEL_COUNT = 2
 RSORT_KERNEL_TILESCAN = 3
+RSORT_KERNEL_SMALL = 4
 
 
 class RsortError(RuntimeError):
@@ -87,6 +90,12 @@ def load_library():
         lib.rsort_histogram.argtypes = [vp, i, vp, sz, i, i, i, u32p, vp]
         lib.rsort_synchronize.argtypes = [vp, vp]
         lib.rsort_profile_enable.argtypes = [vp, i]
+        lib.rsort_segmented_sort.argtypes = [vp, i, vp, vp, u32p, u32p, vp, sz, vp, sz, vp]
+        lib.rsort_segmented_workspace_bytes.argtypes = [vp, i, i, vp, sz, ctypes.POINTER(sz)]
+        lib.rsort_segmented_set_split.argtypes = [vp, ctypes.c_uint32]
+        lib.rsort_segmented_tune.argtypes = [vp, i, vp, vp, u32p, u32p, vp, sz, i, vp,
+                                             ctypes.POINTER(ctypes.c_uint32),
+                                             ctypes.POINTER(ctypes.c_double)]
         lib.rsort_profile_read.argtypes = [vp, i, ctypes.POINTER(ctypes.c_uint64),
                                            ctypes.POINTER(ctypes.c_double)]
         for name in EXPORTED:
@@ -254,6 +263,77 @@ def rsort_profile_read(kind=RSORT_KERNEL_ROUND, device=None):
     ctx.check(ctx._lib.rsort_profile_read(ctx.handle, int(kind), ctypes.byref(launches),
                                           ctypes.byref(ms)), "rsort_profile_read")
     return launches.value, ms.value
+
+
+def _host_offsets(seg_offsets):
+    import numpy as np
+    off = np.ascontiguousarray(np.asarray(seg_offsets, dtype=np.uint64))
+    if off.ndim != 1 or off.size < 1:
+        raise ValueError("seg_offsets must be a 1-D array of num_segs + 1 offsets")
+    return off
+
+
+def rsort_segmented_sort(keys_in, keys_out, seg_offsets, vals_in=None, vals_out=None,
+                         workspace=None, stream=None):
+    """Sort every segment [off[s], off[s+1]) of keys_in independently into keys_out.
+    seg_offsets: host sequence (numpy/list) of num_segs + 1 offsets."""
+    kt = _key_type(keys_in)
+    off = _host_offsets(seg_offsets)
+    n = keys_in.numel()
+    if int(off[-1]) > n:
+        raise ValueError("seg_offsets end beyond the key array")
+    _check_tensor(keys_in, n, "keys_in")
+    _check_tensor(keys_out, n, "keys_out")
+    if (vals_in is None) != (vals_out is None):
+        raise ValueError("vals_in and vals_out must both be given or both be None")
+    if vals_in is not None:
+        _check_tensor(vals_in, n, "vals_in")
+        _check_tensor(vals_out, n, "vals_out")
+    ctx = context(keys_in.device)
+    ws_ptr, ws_bytes = None, 0
+    if workspace is not None:
+        ws_ptr, ws_bytes = _ptr(workspace), workspace.numel() * workspace.element_size()
+    rc = ctx._lib.rsort_segmented_sort(ctx.handle, kt, _ptr(keys_in), _ptr(keys_out),
+                                       _ptr(vals_in), _ptr(vals_out),
+                                       ctypes.c_void_p(off.ctypes.data), off.size - 1,
+                                       ws_ptr, ws_bytes, _stream_handle(stream))
+    ctx.check(rc, "rsort_segmented_sort")
+    return keys_out, vals_out
+
+
+def rsort_segmented_workspace_bytes(key_dtype, has_vals, seg_offsets, device=None):
+    ctx = context(device)
+    kt = _key_type(torch.empty(0, dtype=key_dtype))
+    off = _host_offsets(seg_offsets)
+    out = ctypes.c_size_t()
+    ctx.check(ctx._lib.rsort_segmented_workspace_bytes(ctx.handle, kt, int(bool(has_vals)),
+                                                       ctypes.c_void_p(off.ctypes.data),
+                                                       off.size - 1, ctypes.byref(out)),
+              "rsort_segmented_workspace_bytes")
+    return out.value
+
+
+def rsort_segmented_set_split(small_max, device=None):
+    ctx = context(device)
+    ctx.check(ctx._lib.rsort_segmented_set_split(ctx.handle, int(small_max)),
+              "rsort_segmented_set_split")
+
+
+def rsort_segmented_tune(keys_in, keys_out, seg_offsets, vals_in=None, vals_out=None, reps=3,
+                         stream=None):
+    """Pick the fastest small/large split for this batch; returns (split, ms)."""
+    kt = _key_type(keys_in)
+    off = _host_offsets(seg_offsets)
+    ctx = context(keys_in.device)
+    split = ctypes.c_uint32()
+    ms = ctypes.c_double()
+    rc = ctx._lib.rsort_segmented_tune(ctx.handle, kt, _ptr(keys_in), _ptr(keys_out),
+                                       _ptr(vals_in), _ptr(vals_out),
+                                       ctypes.c_void_p(off.ctypes.data), off.size - 1, int(reps),
+                                       _stream_handle(stream), ctypes.byref(split),
+                                       ctypes.byref(ms))
+    ctx.check(rc, "rsort_segmented_tune")
+    return split.value, ms.value
 
 
 # ---------------------------------------------------------------------------

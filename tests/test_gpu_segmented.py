@@ -1,0 +1,180 @@
+"""GPU parity of the batched segmented sort against the oracle's per-segment SR4.
+
+Segments cover every size class boundary of the in-LDS path (1024 / 4096 /
+8192 keys), the tiled path (longer segments, ragged last tiles), empty and
+one-key segments, constant segments (identity rounds), u64 keys, payloads,
+in-place sorting, the all-tiled split, and the lognormal 4096-segment batch.
+Every comparison is bit-exact.
+"""
+import numpy as np
+import pytest
+
+import keygen
+import oracle
+from tests.gpu_util import announce, dev, host
+
+pytestmark = pytest.mark.gpu
+
+BOUNDARY_SIZES = [0, 1, 2, 31, 32, 33, 1023, 1024, 1025, 4095, 4096, 4097, 8191, 8192,
+                  8193, 16384, 16385, 100001, 0, 7]
+
+
+@pytest.fixture(scope="module")
+def rs():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1808_10292_amd import rsort
+    rsort.load_library()
+    yield rsort
+    rsort.rsort_segmented_set_split(8192)
+
+
+def run_case(rs, keys, sizes, with_vals, in_place=False):
+    off = keygen.offsets_from_sizes(np.asarray(sizes))
+    n = keys.size
+    vals = np.arange(n, dtype=np.uint32)
+    wk, wv = oracle.segmented(keys, vals if with_vals else None, off)
+    dk = dev(keys)
+    dv = dev(vals) if with_vals else None
+    if in_place:
+        rs.rsort_segmented_sort(dk, dk, off, dv, dv)
+        ko, vo = dk, dv
+    else:
+        import torch
+        ko = torch.empty_like(dk)
+        vo = torch.empty_like(dv) if with_vals else None
+        rs.rsort_segmented_sort(dk, ko, off, dv, vo)
+    rs.rsort_synchronize()
+    assert np.array_equal(host(ko), wk)
+    if with_vals:
+        assert np.array_equal(host(vo), wv)
+
+
+@pytest.mark.parametrize("with_vals", [False, True])
+def test_boundary_sizes_u32(rs, with_vals):
+    n = int(sum(BOUNDARY_SIZES))
+    announce("seg boundaries u32", with_vals)
+    keys = keygen.uniform_u32(n, 31)
+    run_case(rs, keys, BOUNDARY_SIZES, with_vals)
+
+
+@pytest.mark.parametrize("with_vals", [False, True])
+def test_boundary_sizes_u64(rs, with_vals):
+    n = int(sum(BOUNDARY_SIZES))
+    announce("seg boundaries u64", with_vals)
+    keys = keygen.uniform_u64(n, 32)
+    keys[::3] = keys[5]
+    run_case(rs, keys, BOUNDARY_SIZES, with_vals)
+
+
+@pytest.mark.parametrize("dist", keygen.KV_DISTRIBUTIONS)
+def test_distributions(rs, dist):
+    sizes = [3000, 9000, 700, 20000, 8192, 1]
+    announce("seg dist", dist)
+    keys = keygen.kv_keys(dist, int(sum(sizes)))
+    run_case(rs, keys, sizes, True)
+
+
+def test_in_place(rs):
+    sizes = [5000, 50000, 100, 9000]
+    announce("seg in place")
+    keys = keygen.zipf_keys(int(sum(sizes)), 8)
+    run_case(rs, keys, sizes, True, in_place=True)
+    run_case(rs, keys, sizes, False, in_place=True)
+
+
+def test_all_tiled_split(rs):
+    sizes = [1, 100, 5000, 8192, 30000]
+    announce("seg split 0")
+    keys = keygen.uniform_u32(int(sum(sizes)), 9)
+    rs.rsort_segmented_set_split(0)
+    try:
+        run_case(rs, keys, sizes, True)
+    finally:
+        rs.rsort_segmented_set_split(8192)
+
+
+def test_lognormal_batch(rs):
+    """The batched workload: 4096 lognormal segments (median 2^12, sigma 1.5,
+    clipped to [16, 2^20]), uniform 32-bit keys."""
+    sizes = keygen.lognormal_sizes(4096)
+    n = int(sizes.sum())
+    announce("seg lognormal", n)
+    keys = keygen.uniform_u32(n, keygen.SEED_SEGMENTS)
+    run_case(rs, keys, sizes, False)
+
+
+def test_offsets_not_starting_at_zero_and_errors(rs):
+    import torch
+    keys = keygen.uniform_u32(1000, 3)
+    off = np.array([100, 300, 300, 900], dtype=np.uint64)
+    dk = dev(keys)
+    ko = dev(keys.copy())
+    rs.rsort_segmented_sort(dk, ko, off)
+    got = host(ko)
+    want = keys.copy()
+    for a, b in zip(off[:-1], off[1:]):
+        want[a:b] = np.sort(keys[a:b], kind="stable")
+    assert np.array_equal(got, want)
+    with pytest.raises(rs.RsortError):
+        rs.rsort_segmented_sort(dk, ko, np.array([0, 500, 400], dtype=np.uint64))
+    e = torch.empty(0, dtype=torch.uint32, device="cuda")
+    rs.rsort_segmented_sort(e, e, np.array([0], dtype=np.uint64))
+
+
+def test_tuner_picks_a_split_and_stays_exact(rs):
+    import torch
+    sizes = keygen.lognormal_sizes(512, seed=77)
+    off = keygen.offsets_from_sizes(sizes)
+    n = int(off[-1])
+    announce("seg tune", n)
+    keys = keygen.uniform_u32(n, 78)
+    dk = dev(keys)
+    ko = torch.empty_like(dk)
+    split, ms = rs.rsort_segmented_tune(dk, ko, off, reps=2)
+    assert split in (0, 1024, 4096, 8192) and ms > 0
+    rs.rsort_segmented_sort(dk, ko, off)
+    want, _ = oracle.segmented(keys, None, off)
+    assert np.array_equal(host(ko), want)
+    rs.rsort_segmented_set_split(8192)
+
+
+def test_graph_capture_replays(rs):
+    """The segmented sort captured into a HIP graph: every replay, with eager
+    work in between, equals the eager result, and follows new input data."""
+    import torch
+    sizes = keygen.lognormal_sizes(300, seed=5)
+    off = keygen.offsets_from_sizes(sizes)
+    n = int(off[-1])
+    announce("seg graph", n)
+    keys = keygen.uniform_u32(n, 6)
+    vals = np.arange(n, dtype=np.uint32)
+    dk, dv = dev(keys), dev(vals)
+    ko, vo = torch.empty_like(dk), torch.empty_like(dv)
+    need = rs.rsort_segmented_workspace_bytes(torch.uint32, True, off)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    rs.rsort_segmented_sort(dk, ko, off, dv, vo, workspace=ws)
+    torch.cuda.synchronize()
+    wk, wv = oracle.segmented(keys, vals, off)
+    assert np.array_equal(host(ko), wk) and np.array_equal(host(vo), wv)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        rs.rsort_segmented_sort(dk, ko, off, dv, vo, workspace=ws)
+    for rep in range(3):
+        ko.view(torch.int32).fill_(rep)
+        vo.view(torch.int32).fill_(rep)
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(ko), wk), rep
+        assert np.array_equal(host(vo), wv), rep
+    keys2 = keygen.uniform_u32(n, 7)
+    dk.copy_(torch.from_numpy(keys2).cuda())
+    g.replay()
+    torch.cuda.synchronize()
+    assert np.array_equal(host(ko), oracle.segmented(keys2, vals, off)[0])
+    # a capture without the preceding identical eager call is refused
+    off2 = keygen.offsets_from_sizes(sizes[::-1].copy())
+    g2 = torch.cuda.CUDAGraph()
+    with pytest.raises(rs.RsortError):
+        with torch.cuda.graph(g2):
+            rs.rsort_segmented_sort(dk, ko, off2, dv, vo, workspace=ws)
