@@ -10,8 +10,9 @@
  *                         equations Tp and Tp4);
  *   RSORT_LSD_R16         PR2: the same with r = 2^16 (Section 3.2, eq. Tp2);
  *   RSORT_SAMPLE_REGULAR  GSD: local sort of p blocks, regular oversampling,
- *                         splitter selection, split by binary search and
- *                         routing to p buckets (Section 3.3, Algorithm 1).
+ *                         splitter selection, split by binary search,
+ *                         routing to p buckets and a stable sort of every
+ *                         bucket (Section 3.3, Algorithm 1).
  *
  * Every algorithm returns the same, unique result: the stable sort.  Keys come
  * out nondecreasing (as unsigned integers), equal keys keep their input order,
@@ -159,6 +160,50 @@ int rsort_segmented_tune(rsort_ctx* ctx, int key_type, const void* keys_in, void
                          const uint32_t* vals_in, uint32_t* vals_out,
                          const uint64_t* seg_offsets, size_t num_segs, int reps, void* stream,
                          uint32_t* best_split, double* best_ms);
+
+/*
+ * Deterministic regular-oversampling sample sort, GSD (Section 3.3,
+ * Algorithm 1), of n uint32 keys (key_type must be RSORT_U32), stable, with
+ * an optional payload.
+ *
+ *   p   number of blocks and of buckets, 1 <= p <= 1024 (clamped to n).  The
+ *       keys are cut into blocks k = [floor(kn/p), floor((k+1)n/p)), each
+ *       block is stable-sorted, and s = r p keys at positions
+ *       ceil(j N_k / s) - 1 (j = 1..s, N_k the block length) form its regular
+ *       sample.  The p s sample keys, ordered as composites (key, input index),
+ *       give the splitters S_i = sample element i s - 1 (i = 1..p-1); block k
+ *       is split at bnd[k][i] = #{q in block k : (key_q, index_q) <= S_i} and
+ *       bucket j collects the runs [bnd[k][j], bnd[k][j+1]) of all blocks in
+ *       block order.  Buckets are then stable-sorted, which yields the same
+ *       array as the paper's p-way merge of each bucket.
+ *   r   oversampling factor, r >= 1, with r p^2 <= 2^26.
+ * Comparing composites makes the bucket bound of Lemma 1,
+ * |bucket| <= (1 + 1/r) n/p + r p, hold for any keys, duplicates included.
+ * Other arguments as in rsort_sort (whole keys only).  The split of the last
+ * run is kept on the context for rsort_sample_sort_stats.  No host traffic
+ * is enqueued, so the call can be captured in a HIP graph once an eager call
+ * on the same context has run (it allocates the statistics area).
+ */
+int rsort_sample_sort(rsort_ctx* ctx, int key_type, const void* keys_in, void* keys_out,
+                      const uint32_t* vals_in, uint32_t* vals_out, size_t n, int p, int r,
+                      void* workspace, size_t ws_bytes, void* stream);
+
+/* Workspace rsort_sample_sort needs for (n, p, r, payload). */
+int rsort_sample_sort_workspace_bytes(rsort_ctx* ctx, int key_type, int has_vals, size_t n,
+                                      int p, int r, size_t* bytes);
+
+/*
+ * Split statistics of the last sample sort on ctx (waits for the device).
+ * *p_used receives the number of buckets; each non-NULL HOST array must hold
+ * p_cap >= *p_used (or p_cap^2 for cnt) entries:
+ *   cnt[k * p_used + j]  |X_{k,j}|, keys of block k routed to bucket j;
+ *   bucket[j]            |Y_j|, the size of bucket j;
+ *   split_key[i - 1], split_index[i - 1]
+ *                        the splitter S_i as (key, input index), i = 1..p_used-1.
+ * RSORT_EINVAL if no sample sort has run on ctx or p_cap is too small.
+ */
+int rsort_sample_sort_stats(rsort_ctx* ctx, int p_cap, int* p_used, uint32_t* cnt,
+                            uint32_t* bucket, uint32_t* split_key, uint32_t* split_index);
 
 /* Wait for `stream`, then report any device-side failure recorded by this
  * context's kernels since the last call (RSORT_EDEVICE) and clear it. */

@@ -91,12 +91,18 @@ struct rsort_ctx {
     rsort::SegPlan plan;
     uint64_t upload_sig = 0;         // plan last uploaded into upload_ws
     void* upload_ws = nullptr;
+    // split statistics of the last sample sort (device), sized for p = kMaxP
+    uint32_t* gsd_stats = nullptr;
+    uint32_t gsd_p = 0;
     std::string last_error;
 };
 
 namespace {
 
 constexpr size_t kMaxN = (size_t)1 << 30;
+constexpr int kMaxP = 1024;                       // sample sort buckets
+constexpr uint64_t kMaxSample = (uint64_t)1 << 26; // r p^2
+constexpr int kDefaultP = 256, kDefaultR = 32;
 
 int fail(rsort_ctx* ctx, int status, const char* fmt, ...)
 {
@@ -191,8 +197,45 @@ int validate_bits(rsort_ctx* ctx, int key_type, int begin_bit, int end_bit)
 
 size_t sort_ws_bytes(int key_type, bool has_vals, size_t n, int algo, int begin_bit, int end_bit)
 {
-    (void)algo;
+    if (algo == RSORT_SAMPLE_REGULAR)
+        return rsort::gsd_layout(has_vals, n, kDefaultP, kDefaultR).bytes;
     return rsort::lsd_r8_layout(key_bytes_of(key_type), has_vals, n, begin_bit, end_bit).bytes;
+}
+
+// Device residency and aliasing of the key / payload arrays of a sort of n
+// keys (the caller has checked n > 0 and the NULL rules).
+int check_arrays(rsort_ctx* ctx, int kb, const void* keys_in, const void* keys_out,
+                 const uint32_t* vals_in, const uint32_t* vals_out, size_t n)
+{
+    if (!is_device_pointer(keys_in, ctx->device) || !is_device_pointer(keys_out, ctx->device))
+        return fail(ctx, RSORT_EINVAL, "key arrays must be device memory of device %d", ctx->device);
+    if (vals_in && (!is_device_pointer(vals_in, ctx->device) || !is_device_pointer(vals_out, ctx->device)))
+        return fail(ctx, RSORT_EINVAL, "payload arrays must be device memory of device %d", ctx->device);
+    const size_t kbytes = n * kb, vbytes = n * 4;
+    if (overlap_partial(keys_in, kbytes, keys_out, kbytes))
+        return fail(ctx, RSORT_EINVAL, "keys_in and keys_out overlap without being equal");
+    if (vals_in) {
+        if (overlap_partial(vals_in, vbytes, vals_out, vbytes))
+            return fail(ctx, RSORT_EINVAL, "vals_in and vals_out overlap without being equal");
+        if (overlap_partial(keys_in, kbytes, vals_in, vbytes) || keys_in == (const void*)vals_in ||
+            overlap_partial(keys_out, kbytes, vals_out, vbytes) || keys_out == (const void*)vals_out ||
+            overlap_partial(keys_out, kbytes, vals_in, vbytes) || keys_out == (const void*)vals_in ||
+            overlap_partial(keys_in, kbytes, vals_out, vbytes) || keys_in == (const void*)vals_out)
+            return fail(ctx, RSORT_EINVAL, "key and payload arrays overlap");
+    }
+    return RSORT_OK;
+}
+
+int check_gsd_params(rsort_ctx* ctx, int key_type, int p, int r)
+{
+    if (key_type != RSORT_U32)
+        return fail(ctx, RSORT_EUNSUPPORTED, "the sample sort takes uint32 keys only");
+    if (p < 1 || p > kMaxP) return fail(ctx, RSORT_EINVAL, "p = %d outside [1, %d]", p, kMaxP);
+    if (r < 1) return fail(ctx, RSORT_EINVAL, "r = %d < 1", r);
+    if ((uint64_t)r * p * p > kMaxSample)
+        return fail(ctx, RSORT_EUNSUPPORTED, "sample r p^2 = %llu above 2^26",
+                    (unsigned long long)r * p * p);
+    return RSORT_OK;
 }
 
 }  // namespace
@@ -231,6 +274,7 @@ int rsort_destroy(rsort_ctx* ctx)
         if (ctx->meta_done) (void)hipEventDestroy(ctx->meta_done);
         if (ctx->ws) (void)hipFree(ctx->ws);
         if (ctx->dev_err) (void)hipFree(ctx->dev_err);
+        if (ctx->gsd_stats) (void)hipFree(ctx->gsd_stats);
     }
     delete ctx;
     return RSORT_OK;
@@ -260,7 +304,100 @@ int rsort_workspace_bytes(rsort_ctx* ctx, int key_type, int has_vals, size_t n, 
     if (!ctx || !bytes) return RSORT_EINVAL;
     if (!key_bytes_of(key_type)) return fail(ctx, RSORT_EINVAL, "unknown key type %d", key_type);
     if (n >= kMaxN) return fail(ctx, RSORT_EUNSUPPORTED, "n = %zu >= 2^30", n);
+    if (algo == RSORT_SAMPLE_REGULAR)
+        return rsort_sample_sort_workspace_bytes(ctx, key_type, has_vals, n, kDefaultP, kDefaultR,
+                                                 bytes);
     *bytes = sort_ws_bytes(key_type, has_vals != 0, n, algo, 0, key_bytes_of(key_type) * 8);
+    return RSORT_OK;
+}
+
+int rsort_sample_sort_workspace_bytes(rsort_ctx* ctx, int key_type, int has_vals, size_t n,
+                                      int p, int r, size_t* bytes)
+{
+    if (!ctx || !bytes) return RSORT_EINVAL;
+    int rc = check_gsd_params(ctx, key_type, p, r);
+    if (rc) return rc;
+    if (n >= kMaxN) return fail(ctx, RSORT_EUNSUPPORTED, "n = %zu >= 2^30", n);
+    *bytes = n ? rsort::gsd_layout(has_vals != 0, n, (uint32_t)p, (uint32_t)r).bytes : 0;
+    return RSORT_OK;
+}
+
+int rsort_sample_sort(rsort_ctx* ctx, int key_type, const void* keys_in, void* keys_out,
+                      const uint32_t* vals_in, uint32_t* vals_out, size_t n, int p, int r,
+                      void* workspace, size_t ws_bytes, void* stream)
+{
+    if (!ctx) return RSORT_EINVAL;
+    ctx->last_error.clear();
+    int rc = check_gsd_params(ctx, key_type, p, r);
+    if (rc) return rc;
+    if ((vals_in == nullptr) != (vals_out == nullptr))
+        return fail(ctx, RSORT_EINVAL, "vals_in and vals_out must both be NULL or both be set");
+    if ((workspace == nullptr) != (ws_bytes == 0))
+        return fail(ctx, RSORT_EINVAL, "workspace and ws_bytes must both be 0 or both be set");
+    if (n == 0) return RSORT_OK;
+    if (n >= kMaxN) return fail(ctx, RSORT_EUNSUPPORTED, "n = %zu >= 2^30", n);
+    if (!keys_in || !keys_out) return fail(ctx, RSORT_EINVAL, "NULL key pointer with n > 0");
+    DeviceGuard g(ctx->device);
+    rc = check_arrays(ctx, 4, keys_in, keys_out, vals_in, vals_out, n);
+    if (rc) return rc;
+    const rsort::GsdLayout L = rsort::gsd_layout(vals_in != nullptr, n, (uint32_t)p, (uint32_t)r);
+    hipStream_t s = (hipStream_t)stream;
+    if (!ctx->gsd_stats) {
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(s, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone)
+            return fail(ctx, RSORT_EINVAL,
+                        "first sample sort on a context cannot be captured (it allocates)");
+        hipError_t e = hipMalloc(&ctx->gsd_stats, rsort::gsd_stats_words(kMaxP) * 4);
+        if (e != hipSuccess) {
+            ctx->gsd_stats = nullptr;
+            return hip_fail(ctx, e, "hipMalloc(sample sort statistics)");
+        }
+    }
+    void* ws = workspace;
+    if (ws) {
+        if (ws_bytes < L.bytes)
+            return fail(ctx, RSORT_EINVAL, "workspace of %zu bytes < %zu needed", ws_bytes, L.bytes);
+        if (!is_device_pointer(ws, ctx->device))
+            return fail(ctx, RSORT_EINVAL, "workspace must be device memory");
+    } else {
+        rc = ensure_workspace(ctx, L.bytes, &ws);
+        if (rc) return rc;
+    }
+    hipError_t e = rsort::gsd_sort((const uint32_t*)keys_in, (uint32_t*)keys_out, vals_in, vals_out,
+                                   n, L, ws, ctx->gsd_stats, ctx->dev_err, s, ctx->prof);
+    if (e != hipSuccess) return hip_fail(ctx, e, "kernel launch");
+    ctx->gsd_p = L.p;
+    return RSORT_OK;
+}
+
+int rsort_sample_sort_stats(rsort_ctx* ctx, int p_cap, int* p_used, uint32_t* cnt,
+                            uint32_t* bucket, uint32_t* split_key, uint32_t* split_index)
+{
+    if (!ctx || !p_used) return RSORT_EINVAL;
+    if (!ctx->gsd_p) return fail(ctx, RSORT_EINVAL, "no sample sort has run on this context");
+    const uint32_t p = ctx->gsd_p;
+    *p_used = (int)p;
+    if (p_cap < (int)p) return fail(ctx, RSORT_EINVAL, "p_cap %d < p %u", p_cap, p);
+    DeviceGuard g(ctx->device);
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipDeviceSynchronize");
+    std::vector<uint32_t> h(rsort::gsd_stats_words(p));
+    e = hipMemcpy(h.data(), ctx->gsd_stats, h.size() * 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpy(statistics)");
+    const uint32_t* bnd = h.data();
+    for (uint32_t j = 0; j < p; ++j) {
+        uint32_t tot = 0;
+        for (uint32_t k = 0; k < p; ++k) {
+            const uint32_t c = bnd[(size_t)k * (p + 1) + j + 1] - bnd[(size_t)k * (p + 1) + j];
+            if (cnt) cnt[(size_t)k * p + j] = c;
+            tot += c;
+        }
+        if (bucket) bucket[j] = tot;
+    }
+    for (uint32_t i = 0; i + 1 < p; ++i) {
+        if (split_key) split_key[i] = h[(size_t)p * (p + 1) + i];
+        if (split_index) split_index[i] = h[(size_t)p * (p + 1) + p + i];
+    }
     return RSORT_OK;
 }
 
@@ -272,10 +409,16 @@ int rsort_sort(rsort_ctx* ctx, int key_type, const void* keys_in, void* keys_out
     ctx->last_error.clear();
     const int kb = key_bytes_of(key_type);
     if (!kb) return fail(ctx, RSORT_EINVAL, "unknown key type %d", key_type);
-    if (algo != RSORT_AUTO && algo != RSORT_LSD_R8)
+    if (algo != RSORT_AUTO && algo != RSORT_LSD_R8 && algo != RSORT_SAMPLE_REGULAR)
         return fail(ctx, RSORT_EUNSUPPORTED, "algorithm %d not available", algo);
     int rc = validate_bits(ctx, key_type, begin_bit, end_bit);
     if (rc) return rc;
+    if (algo == RSORT_SAMPLE_REGULAR) {
+        if (begin_bit != 0 || end_bit != kb * 8)
+            return fail(ctx, RSORT_EUNSUPPORTED, "the sample sort compares whole keys");
+        return rsort_sample_sort(ctx, key_type, keys_in, keys_out, vals_in, vals_out, n, kDefaultP,
+                                 kDefaultR, workspace, ws_bytes, stream);
+    }
     if ((vals_in == nullptr) != (vals_out == nullptr))
         return fail(ctx, RSORT_EINVAL, "vals_in and vals_out must both be NULL or both be set");
     if (n == 0) return RSORT_OK;
@@ -285,22 +428,9 @@ int rsort_sort(rsort_ctx* ctx, int key_type, const void* keys_in, void* keys_out
         return fail(ctx, RSORT_EINVAL, "workspace and ws_bytes must both be 0 or both be set");
 
     DeviceGuard g(ctx->device);
-    if (!is_device_pointer(keys_in, ctx->device) || !is_device_pointer(keys_out, ctx->device))
-        return fail(ctx, RSORT_EINVAL, "key arrays must be device memory of device %d", ctx->device);
-    if (vals_in && (!is_device_pointer(vals_in, ctx->device) || !is_device_pointer(vals_out, ctx->device)))
-        return fail(ctx, RSORT_EINVAL, "payload arrays must be device memory of device %d", ctx->device);
+    rc = check_arrays(ctx, kb, keys_in, keys_out, vals_in, vals_out, n);
+    if (rc) return rc;
     const size_t kbytes = n * kb, vbytes = n * 4;
-    if (overlap_partial(keys_in, kbytes, keys_out, kbytes))
-        return fail(ctx, RSORT_EINVAL, "keys_in and keys_out overlap without being equal");
-    if (vals_in) {
-        if (overlap_partial(vals_in, vbytes, vals_out, vbytes))
-            return fail(ctx, RSORT_EINVAL, "vals_in and vals_out overlap without being equal");
-        if (overlap_partial(keys_in, kbytes, vals_in, vbytes) || keys_in == (const void*)vals_in ||
-            overlap_partial(keys_out, kbytes, vals_out, vbytes) || keys_out == (void*)vals_out ||
-            overlap_partial(keys_out, kbytes, vals_in, vbytes) || keys_out == (const void*)vals_in ||
-            overlap_partial(keys_in, kbytes, vals_out, vbytes) || keys_in == (const void*)vals_out)
-            return fail(ctx, RSORT_EINVAL, "key and payload arrays overlap");
-    }
     hipStream_t s = (hipStream_t)stream;
 
     if (end_bit == begin_bit) {  // nothing to compare: the stable sort is the identity

@@ -17,6 +17,7 @@ namespace {
 
 
 constexpr uint32_t R = 256;  // radix
+constexpr uint32_t kNoTile = 0xFFFFFFFFu;
 
 // Tile shape of the count and scatter kernels: WG threads, ITEMS keys per
 // thread (tile = WG * ITEMS keys).
@@ -90,6 +91,8 @@ struct RoundArgs {
     uint32_t* tickets;       // [round] block tickets of k_tilescan
     uint32_t* err;
     const uint2* tiles;      // tile list {first key, end} (segmented), or null
+    const uint32_t* ntiles_dev;  // tile count known only on the device (grid is an
+                                 // upper bound; surplus workgroups exit), or null
 };
 
 // First key and key count of tile t (at most TILE keys).
@@ -298,7 +301,13 @@ __global__ __launch_bounds__(WG) void k_count(RoundArgs a)
     const uint32_t tid = threadIdx.x;
     for (uint32_t i = tid; i < R * 32 / 4; i += WG) ((uint4*)h)[i] = make_uint4(0, 0, 0, 0);
     __syncthreads();
-    const uint32_t tile = xcd_tile(a.ntiles);
+    uint32_t tile;
+    if (a.ntiles_dev) {
+        tile = blockIdx.x;
+        if (tile >= *a.ntiles_dev) return;
+    } else {
+        tile = xcd_tile(a.ntiles);
+    }
     const uint2 tr = tile_range(a, tile, TILE);
     const uint32_t base = tr.x;
     const uint32_t lim = tr.y;
@@ -512,7 +521,7 @@ __global__ __launch_bounds__(WG, KV ? RSORT_R8_WAVES_PER_EU_KV : RSORT_R8_WAVES_
             for (int i = 0; i < ITEMS; ++i)
                 if (hofs + i * 32 < lim) atomicAdd(&sl[digit_of(k[i], a.shift, a.mask)].y, 1u);
         }
-        if (RSORT_SCATTER_PERSIST && tn < a.ntiles) load(tn, kn, vn);
+        if (RSORT_SCATTER_PERSIST && tn != kNoTile) load(tn, kn, vn);
         __syncthreads();
 
         // bases
@@ -587,23 +596,24 @@ __global__ __launch_bounds__(WG, KV ? RSORT_R8_WAVES_PER_EU_KV : RSORT_R8_WAVES_
     // a contiguous eighth of the tiles (blocks are dealt to XCDs in turn), so
     // neighbouring tiles write their shared cache lines through the same L2.
     const uint32_t b = blockIdx.x, G = gridDim.x;
-    const bool xcd = (a.ntiles & 7) == 0 && (G & 7) == 0;
+    const uint32_t ntiles = a.ntiles_dev ? *a.ntiles_dev : a.ntiles;
+    const bool xcd = !a.ntiles_dev && (a.ntiles & 7) == 0 && (G & 7) == 0;
     const uint32_t per = a.ntiles >> 3, g8 = G >> 3, x = b & 7;
     uint32_t tile = xcd ? x * per + (b >> 3) : b;
     auto next_of = [&](uint32_t t) -> uint32_t {
         if (xcd) {
             const uint32_t l = t - x * per + g8;
-            return l < per ? x * per + l : a.ntiles;
+            return l < per ? x * per + l : kNoTile;
         }
-        return t + G < a.ntiles ? t + G : a.ntiles;
+        return t + G < ntiles ? t + G : kNoTile;
     };
-    if (tile >= a.ntiles) return;
+    if (tile >= ntiles) return;
 
     K ka[ITEMS];
     uint32_t va[ITEMS];
     load(tile, ka, va);
     if constexpr (!RSORT_SCATTER_PERSIST) {
-        process(tile, ka, va, a.ntiles, ka, va);
+        process(tile, ka, va, kNoTile, ka, va);
         return;
     }
     K kb[ITEMS];
@@ -612,11 +622,11 @@ __global__ __launch_bounds__(WG, KV ? RSORT_R8_WAVES_PER_EU_KV : RSORT_R8_WAVES_
         uint32_t tn = next_of(tile);
         process(tile, ka, va, tn, kb, vb);
         tile = tn;
-        if (tile >= a.ntiles) break;
+        if (tile == kNoTile) break;
         tn = next_of(tile);
         process(tile, kb, vb, tn, ka, va);
         tile = tn;
-        if (tile >= a.ntiles) break;
+        if (tile == kNoTile) break;
     }
 }
 

@@ -146,6 +146,7 @@ hipError_t run(const void* keys_in, void* keys_out, const uint32_t* vals_in, uin
         a.tickets = tickets;
         a.err = dev_err;
         a.tiles = nullptr;
+        a.ntiles_dev = nullptr;
         if (prof) profiler_mark(prof, stream, kKindCount, true);
         hipLaunchKernelGGL((k_count<K, WG, ITEMS>), dim3(L.ntiles), dim3(WG), 0, stream, a);
         if (prof) profiler_mark(prof, stream, kKindCount, false);

@@ -79,6 +79,41 @@ hipError_t segmented_sort(int key_bytes, const void* keys_in, void* keys_out,
                           const SegPlan& P, const void* host_meta, void* ws, uint32_t* dev_err,
                           hipStream_t stream, Profiler* prof);
 
+// Device-planned segmented sort: offsets (nseg + 1 u32, nondecreasing) live in
+// device memory.  ws must hold devseg_layout(...).bytes bytes.
+struct DevSegLayout {
+    uint32_t max_tiles;   // upper bound of the tile count: ceil(n / tile) + nseg
+    size_t off_tmp_keys, off_tmp_vals, off_counts, off_plan, off_small, off_tiles, off_lsegs,
+        off_ntiles;
+    size_t bytes;
+};
+DevSegLayout devseg_layout(int key_bytes, bool has_vals, size_t n, uint32_t nseg);
+hipError_t devseg_sort(int key_bytes, const void* keys_in, void* keys_out, const uint32_t* vals_in,
+                       uint32_t* vals_out, size_t n, const uint32_t* off, uint32_t nseg,
+                       uint32_t small_max, void* ws, const DevSegLayout& L, uint32_t* dev_err,
+                       hipStream_t stream, Profiler* prof);
+
+// ---------------------------------------------------------------------------
+// Regular-oversampling sample sort, GSD (sample_sort.hip), 32-bit keys.
+struct GsdLayout {
+    uint32_t p;                 // blocks = buckets (the request clamped to n)
+    uint32_t s;                 // samples per block, r p
+    uint32_t tiles_per_block;   // route workgroups per block
+    size_t nT;                  // sample size p s
+    LsdR8Layout LT;             // the sample's sort
+    DevSegLayout LS;            // local sort and bucket finish
+    size_t off_lo, off_boff, off_bsize, off_coloff, off_Tk, off_Tg, off_Sk, off_Sg, off_lsd,
+        off_Y, off_YV, off_seg;
+    size_t bytes;
+};
+GsdLayout gsd_layout(bool has_vals, size_t n, uint32_t p, uint32_t r);
+// Statistics area (device, u32): split bounds p x (p+1), splitter keys (p),
+// splitter indexes (p).
+size_t gsd_stats_words(uint32_t p);
+hipError_t gsd_sort(const uint32_t* keys_in, uint32_t* keys_out, const uint32_t* vals_in,
+                    uint32_t* vals_out, size_t n, const GsdLayout& L, void* ws, uint32_t* stats,
+                    uint32_t* dev_err, hipStream_t stream, Profiler* prof);
+
 // Plain device copy used when a sort moves nothing (empty bit range).
 hipError_t copy_bytes(void* dst, const void* src, size_t bytes, hipStream_t stream);
 

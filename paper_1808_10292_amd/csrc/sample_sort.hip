@@ -1,0 +1,306 @@
+// Deterministic regular-oversampling sample sort (GSD, arXiv 1808.10292
+// Section 3.3, Algorithm 1) for 32-bit keys with an optional 32-bit payload.
+//
+//   1. local sort     the n keys are cut into p near-equal blocks
+//                     (block k = [floor(kn/p), floor((k+1)n/p))) and every block
+//                     is stable-sorted: the device-planned segmented radix sort;
+//   2. sample         s = r p keys per sorted block at positions ceil(j N_k/s)-1,
+//                     j = 1..s (the last one is the block maximum), each kept as
+//                     the composite (key, global index);
+//   3. sort sample    the p s composites by key with the stable LSD sort; the
+//                     sample is laid out in block order, so equal keys already
+//                     sit in index order and the result is sorted by composite;
+//   4. splitters      S_i = sorted sample element i s - 1, i = 1..p-1;
+//   5. split          every block is split around the splitters by binary search:
+//                     bnd[k][i] = #{q in block k : (X_q, index) <= S_i};
+//   6. route          runs X_{k,j} = block k between bnd[k][j] and bnd[k][j+1]
+//                     are copied to bucket j, buckets in order, runs of one
+//                     bucket in block order;
+//   7. finish         every bucket is stable-sorted (device-planned segmented
+//                     sort).  Bucket j holds exactly the keys between S_j and
+//                     S_{j+1} as composites, so the concatenation is the stable
+//                     sort of the input; the paper merges the p sorted runs of
+//                     a bucket, which gives the same array.
+// Duplicate keys: comparing composites (key, index) instead of keys keeps the
+// bucket bound of Lemma 1 for any key distribution, and the split of equal
+// keys by index keeps the result stable.
+#include <algorithm>
+
+#include "lsd_kernels.h"
+
+namespace rsort {
+namespace {
+
+constexpr uint32_t kRouteWG = 256;
+constexpr uint32_t kRouteItems = 16;
+constexpr uint32_t kRouteTile = kRouteWG * kRouteItems;   // keys per route workgroup
+constexpr uint32_t kScanCols = 64;                        // bucket columns per scan workgroup
+constexpr uint32_t kScanGroups = 16;                      // block groups per column
+
+// lo[k] = floor(k n / p), k = 0..p.
+__global__ void k_gsd_blocks(uint32_t* lo, uint32_t n, uint32_t p)
+{
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k <= p) lo[k] = (uint32_t)(((uint64_t)k * n) / p);
+}
+
+// Regular sample of the sorted blocks: element t = k s + j - 1.
+__global__ void k_gsd_sample(const uint32_t* __restrict__ X, const uint32_t* lo, uint32_t p,
+                             uint32_t s, uint32_t* Tk, uint32_t* Tg)
+{
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (size_t)p * s) return;
+    const uint32_t k = (uint32_t)(t / s);
+    const uint64_t j = t - (size_t)k * s + 1;
+    const uint32_t b = lo[k];
+    const uint64_t nk = lo[k + 1] - b;
+    const uint32_t q = (uint32_t)((j * nk + s - 1) / s - 1);
+    Tk[t] = X[b + q];
+    Tg[t] = b + q;
+}
+
+// Composite order (key, index).
+__device__ __forceinline__ bool comp_less(uint32_t ak, uint32_t ag, uint32_t bk, uint32_t bg)
+{
+    return ak < bk || (ak == bk && ag < bg);
+}
+
+// bnd[k][i] for k < p, i <= p; splitter copies for the statistics.
+__global__ void k_gsd_split(const uint32_t* __restrict__ X, const uint32_t* lo, uint32_t p,
+                            uint32_t s, const uint32_t* Sk, const uint32_t* Sg, uint32_t* bnd,
+                            uint32_t* split_key, uint32_t* split_g)
+{
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= p * (p + 1)) return;
+    const uint32_t k = t / (p + 1), i = t - k * (p + 1);
+    const uint32_t b = lo[k], nk = lo[k + 1] - b;
+    uint32_t res;
+    if (i == 0) {
+        res = 0;
+    } else if (i == p) {
+        res = nk;
+    } else {
+        const uint32_t sk = Sk[(size_t)i * s - 1], sg = Sg[(size_t)i * s - 1];
+        if (k == 0) {
+            split_key[i - 1] = sk;
+            split_g[i - 1] = sg;
+        }
+        uint32_t a = 0, e = nk;   // first q with S_i < (X_q, b + q)
+        while (a < e) {
+            const uint32_t mid = a + ((e - a) >> 1);
+            if (comp_less(sk, sg, X[b + mid], b + mid))
+                e = mid;
+            else
+                a = mid + 1;
+        }
+        res = a;
+    }
+    bnd[t] = res;
+}
+
+// Within-bucket offsets: off[k][j] = sum over k' < k of |X_{k',j}|, and the
+// bucket sizes.  Workgroup c covers columns [64c, 64c+64); thread (g, col)
+// sums the run lengths of its block group, the 16 group sums of a column are
+// scanned in LDS, and each thread writes the offsets of its group.
+__global__ __launch_bounds__(kScanCols * kScanGroups) void k_gsd_colscan(const uint32_t* bnd,
+                                                                         uint32_t p, uint32_t* off,
+                                                                         uint32_t* bsize)
+{
+    __shared__ uint32_t part[kScanGroups][kScanCols];
+    const uint32_t col = threadIdx.x % kScanCols, g = threadIdx.x / kScanCols;
+    const uint32_t j = blockIdx.x * kScanCols + col;
+    const uint32_t per = (p + kScanGroups - 1) / kScanGroups;
+    const uint32_t k0 = min(p, g * per), k1 = min(p, k0 + per);
+    uint32_t sum = 0;
+    if (j < p)
+        for (uint32_t k = k0; k < k1; ++k) {
+            const uint32_t* row = bnd + (size_t)k * (p + 1);
+            sum += row[j + 1] - row[j];
+        }
+    part[g][col] = sum;
+    __syncthreads();
+    uint32_t run = 0, total = 0;
+    for (uint32_t h = 0; h < kScanGroups; ++h) {
+        const uint32_t v = part[h][col];
+        run += h < g ? v : 0u;
+        total += v;
+    }
+    if (j >= p) return;
+    if (g == 0) bsize[j] = total;
+    for (uint32_t k = k0; k < k1; ++k) {
+        const uint32_t* row = bnd + (size_t)k * (p + 1);
+        off[(size_t)k * p + j] = run;
+        run += row[j + 1] - row[j];
+    }
+}
+
+// Bucket starts boff[j] = sum of bucket sizes before j, boff[p] = n.
+__global__ __launch_bounds__(1024) void k_gsd_bucket_starts(const uint32_t* bsize, uint32_t p,
+                                                            uint32_t* boff)
+{
+    __shared__ uint32_t wsum[16];
+    __shared__ uint32_t carry;
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid == 0) carry = 0;
+    __syncthreads();
+    for (uint32_t c = 0; c < p; c += 1024) {
+        const uint32_t j = c + tid;
+        const uint32_t x = j < p ? bsize[j] : 0u;
+        const uint32_t incl = wave_inclusive_sum(x);
+        if (lane == 63) wsum[wave] = incl;
+        __syncthreads();
+        uint32_t before = carry, all = 0;
+        for (uint32_t w = 0; w < 16; ++w) {
+            before += w < wave ? wsum[w] : 0u;
+            all += wsum[w];
+        }
+        if (j < p) boff[j] = before + incl - x;
+        __syncthreads();
+        if (tid == 0) carry += all;
+        __syncthreads();
+    }
+    if (tid == 0) boff[p] = carry;
+}
+
+// Route: workgroup (k, t) copies keys [t T, (t+1) T) of sorted block k.  The
+// key at block offset u belongs to the run j with bnd[k][j] <= u < bnd[k][j+1]
+// and lands at boff[j] + off[k][j] + u - bnd[k][j].  The runs met by the
+// workgroup's range are found once, each key searches only among them.
+template <bool KV>
+__global__ __launch_bounds__(kRouteWG) void k_gsd_route(const uint32_t* __restrict__ X,
+                                                        const uint32_t* __restrict__ XV,
+                                                        const uint32_t* lo, uint32_t p,
+                                                        uint32_t tiles_per_block,
+                                                        const uint32_t* bnd, const uint32_t* off,
+                                                        const uint32_t* boff, uint32_t* Y,
+                                                        uint32_t* YV)
+{
+    __shared__ uint32_t sb[1025];
+    __shared__ uint32_t sd[1024];
+    __shared__ uint32_t jr[2];
+    const uint32_t k = blockIdx.x / tiles_per_block;
+    const uint32_t t = blockIdx.x - k * tiles_per_block;
+    const uint32_t b = lo[k], nk = lo[k + 1] - b;
+    const uint32_t u0 = t * kRouteTile;
+    if (u0 >= nk) return;
+    const uint32_t u1 = min(nk, u0 + kRouteTile);
+    const uint32_t* row = bnd + (size_t)k * (p + 1);
+    // the run of the first and of the last key: last j with bnd[j] <= u
+    if (threadIdx.x < 2) {
+        const uint32_t u = threadIdx.x == 0 ? u0 : u1 - 1;
+        uint32_t a = 0, e = p;   // search j in [0, p): bnd[0] = 0 <= u always
+        while (e - a > 1) {
+            const uint32_t mid = (a + e) >> 1;
+            if (row[mid] <= u) a = mid; else e = mid;
+        }
+        jr[threadIdx.x] = a;
+    }
+    __syncthreads();
+    const uint32_t j0 = jr[0], j1 = jr[1];
+    for (uint32_t j = j0 + threadIdx.x; j <= j1 + 1; j += kRouteWG) sb[j - j0] = row[j];
+    for (uint32_t j = j0 + threadIdx.x; j <= j1; j += kRouteWG)
+        sd[j - j0] = boff[j] + off[(size_t)k * p + j] - row[j];
+    __syncthreads();
+    const uint32_t nr = j1 - j0 + 1;
+#pragma unroll 4
+    for (uint32_t i = 0; i < kRouteItems; ++i) {
+        const uint32_t u = u0 + i * kRouteWG + threadIdx.x;
+        if (u >= u1) break;
+        uint32_t a = 0, e = nr;   // last local run with sb[a] <= u
+        while (e - a > 1) {
+            const uint32_t mid = (a + e) >> 1;
+            if (sb[mid] <= u) a = mid; else e = mid;
+        }
+        const uint32_t d = sd[a] + u;
+        Y[d] = X[b + u];
+        if (KV) YV[d] = XV[b + u];
+    }
+}
+
+}  // namespace
+
+GsdLayout gsd_layout(bool has_vals, size_t n, uint32_t p_req, uint32_t r)
+{
+    GsdLayout L{};
+    const uint32_t p = (uint32_t)std::min<size_t>(p_req, n ? n : 1);
+    L.p = p;
+    L.s = r * p;
+    L.nT = (size_t)p * L.s;
+    L.tiles_per_block = (uint32_t)((n / p + 1 + kRouteTile - 1) / kRouteTile);
+    L.LT = lsd_r8_layout(4, true, L.nT, 0, 32);
+    L.LS = devseg_layout(4, has_vals, n, p);
+    size_t o = 0;
+    L.off_lo = o;    o = align_up(o + (size_t)(p + 1) * 4);
+    L.off_boff = o;  o = align_up(o + (size_t)(p + 1) * 4);
+    L.off_bsize = o; o = align_up(o + (size_t)p * 4);
+    L.off_coloff = o; o = align_up(o + (size_t)p * p * 4);
+    L.off_Tk = o;    o = align_up(o + L.nT * 4);
+    L.off_Tg = o;    o = align_up(o + L.nT * 4);
+    L.off_Sk = o;    o = align_up(o + L.nT * 4);
+    L.off_Sg = o;    o = align_up(o + L.nT * 4);
+    L.off_lsd = o;   o = align_up(o + L.LT.bytes);
+    L.off_Y = o;     o = align_up(o + n * 4);
+    L.off_YV = o;    o = align_up(o + (has_vals ? n * 4 : 0));
+    L.off_seg = o;   o = align_up(o + L.LS.bytes);
+    L.bytes = o;
+    return L;
+}
+
+size_t gsd_stats_words(uint32_t p) { return (size_t)p * (p + 1) + 2 * (size_t)p; }
+
+hipError_t gsd_sort(const uint32_t* keys_in, uint32_t* keys_out, const uint32_t* vals_in,
+                    uint32_t* vals_out, size_t n, const GsdLayout& L, void* ws, uint32_t* stats,
+                    uint32_t* dev_err, hipStream_t stream, Profiler* prof)
+{
+    if (!n) return hipSuccess;
+    const uint32_t p = L.p, s = L.s;
+    uint8_t* w = (uint8_t*)ws;
+    uint32_t* lo = (uint32_t*)(w + L.off_lo);
+    uint32_t* boff = (uint32_t*)(w + L.off_boff);
+    uint32_t* bsize = (uint32_t*)(w + L.off_bsize);
+    uint32_t* coloff = (uint32_t*)(w + L.off_coloff);
+    uint32_t* Tk = (uint32_t*)(w + L.off_Tk);
+    uint32_t* Tg = (uint32_t*)(w + L.off_Tg);
+    uint32_t* Sk = (uint32_t*)(w + L.off_Sk);
+    uint32_t* Sg = (uint32_t*)(w + L.off_Sg);
+    uint32_t* Y = (uint32_t*)(w + L.off_Y);
+    uint32_t* YV = vals_in ? (uint32_t*)(w + L.off_YV) : nullptr;
+    void* seg_ws = w + L.off_seg;
+    uint32_t* bnd = stats;                                   // p x (p+1)
+    uint32_t* split_key = stats + (size_t)p * (p + 1);       // p - 1
+    uint32_t* split_g = split_key + p;                       // p - 1
+    const uint32_t small_max = kSmallMaxDefault;
+
+    hipLaunchKernelGGL(k_gsd_blocks, dim3((p + 256) / 256), dim3(256), 0, stream, lo, (uint32_t)n, p);
+    // 1. local sort of the blocks into the output arrays
+    hipError_t e = devseg_sort(4, keys_in, keys_out, vals_in, vals_out, n, lo, p, small_max,
+                               seg_ws, L.LS, dev_err, stream, prof);
+    if (e != hipSuccess) return e;
+    // 2-3. regular sample, sorted by composite
+    hipLaunchKernelGGL(k_gsd_sample, dim3((uint32_t)((L.nT + 255) / 256)), dim3(256), 0, stream,
+                       keys_out, lo, p, s, Tk, Tg);
+    e = lsd_r8_sort(4, Tk, Sk, Tg, Sg, L.nT, 0, 32, w + L.off_lsd, L.LT, dev_err, stream, nullptr);
+    if (e != hipSuccess) return e;
+    // 4-5. splitters and split
+    const uint32_t nb = p * (p + 1);
+    hipLaunchKernelGGL(k_gsd_split, dim3((nb + 255) / 256), dim3(256), 0, stream, keys_out, lo, p,
+                       s, Sk, Sg, bnd, split_key, split_g);
+    // 6. route
+    hipLaunchKernelGGL(k_gsd_colscan, dim3((p + kScanCols - 1) / kScanCols),
+                       dim3(kScanCols * kScanGroups), 0, stream, bnd, p, coloff, bsize);
+    hipLaunchKernelGGL(k_gsd_bucket_starts, dim3(1), dim3(1024), 0, stream, bsize, p, boff);
+    const dim3 rg(p * L.tiles_per_block);
+    if (vals_in)
+        hipLaunchKernelGGL(k_gsd_route<true>, rg, dim3(kRouteWG), 0, stream, keys_out, vals_out,
+                           lo, p, L.tiles_per_block, bnd, coloff, boff, Y, YV);
+    else
+        hipLaunchKernelGGL(k_gsd_route<false>, rg, dim3(kRouteWG), 0, stream, keys_out, nullptr,
+                           lo, p, L.tiles_per_block, bnd, coloff, boff, Y, nullptr);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // 7. finish: every bucket stable-sorted into the output
+    return devseg_sort(4, Y, keys_out, YV, vals_out, n, boff, p, small_max, seg_ws, L.LS, dev_err,
+                       stream, prof);
+}
+
+}  // namespace rsort

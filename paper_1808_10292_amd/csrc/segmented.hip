@@ -356,6 +356,7 @@ hipError_t run_segmented(const void* keys_in, void* keys_out, const uint32_t* va
         a.tickets = nullptr;
         a.err = dev_err;
         a.tiles = tiles;
+        a.ntiles_dev = nullptr;
         if (prof) profiler_mark(prof, stream, kKindCount, true);
         hipLaunchKernelGGL((k_count<K, WG, ITEMS>), dim3(nt), dim3(WG), 0, stream, a);
         if (prof) profiler_mark(prof, stream, kKindCount, false);
@@ -382,6 +383,180 @@ hipError_t segmented_sort(int key_bytes, const void* keys_in, void* keys_out,
                   : run_segmented<uint32_t, false>(keys_in, keys_out, vals_in, vals_out, total, P, host_meta, ws, dev_err, stream, prof);
     return kv ? run_segmented<uint64_t, true>(keys_in, keys_out, vals_in, vals_out, total, P, host_meta, ws, dev_err, stream, prof)
               : run_segmented<uint64_t, false>(keys_in, keys_out, vals_in, vals_out, total, P, host_meta, ws, dev_err, stream, prof);
+}
+
+
+// ---------------------------------------------------------------------------
+// Device-planned segmented sort: the segment offsets live in device memory
+// and are known to no host code (the sample sort's blocks and buckets).  One
+// planning workgroup classifies the segments and writes the small-segment
+// lists, the tile list, the per-segment tile ranges, the tile count and the
+// round plan into the workspace; the round kernels are launched over an upper
+// bound of the tile count and surplus workgroups exit at once.  No host
+// traffic, so the sequence can be captured in a graph.
+namespace {
+
+constexpr int kPlanWG = 1024;
+
+// Block-wide exclusive sum over kPlanWG threads; *total receives the sum.
+__device__ uint32_t plan_exclusive_sum(uint32_t x, uint32_t* wsum, uint32_t* total)
+{
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t incl = wave_inclusive_sum(x);
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+    for (uint32_t w = 0; w < kPlanWG / 64; ++w) {
+        const uint32_t v = wsum[w];
+        before += w < wave ? v : 0u;
+        all += v;
+    }
+    __syncthreads();
+    *total = all;
+    return before + incl - x;
+}
+
+__global__ __launch_bounds__(kPlanWG) void k_devseg_plan(const uint32_t* off, uint32_t nseg,
+                                                         uint32_t small_max, uint32_t tile,
+                                                         uint32_t rounds, RoundPlan* plan,
+                                                         uint2* small, uint2* tiles, uint4* lsegs,
+                                                         uint32_t* ntiles)
+{
+    __shared__ uint32_t wsum[kPlanWG / 64];
+    const uint32_t tid = threadIdx.x;
+    if (tid <= (uint32_t)kMaxRounds) {
+        RoundPlan r{0, -1, 0, -1};
+        if (tid < rounds) {
+            r.exec = 1;
+            r.ord = (int32_t)tid;
+            r.src = tid == 0 ? 0 : (((rounds - tid) & 1) ? 2 : 1);
+            r.dst = ((rounds - 1 - tid) & 1) ? 2 : 1;
+        }
+        if (tid == (uint32_t)kMaxRounds) r = RoundPlan{0, 0, 0, 2};
+        plan[tid] = r;
+    }
+    uint32_t base = 0;
+    for (uint32_t c = 0; c < nseg; c += kPlanWG) {
+        const uint32_t j = c + tid;
+        uint32_t lo = 0, hi = 0, nt = 0;
+        if (j < nseg) {
+            lo = off[j];
+            hi = off[j + 1];
+            const uint32_t len = hi - lo;
+            nt = len > small_max ? (len + tile - 1) / tile : 0u;
+            // class c takes len in (cap[c-1], cap[c]]; other classes see an empty segment
+            uint32_t cls = 3;
+            if (len && len <= small_max)
+                for (uint32_t k = 0; k < 3; ++k)
+                    if (len <= (uint32_t)(kSmallClasses[k].wg * kSmallClasses[k].items)) { cls = k; break; }
+            for (uint32_t k = 0; k < 3; ++k)
+                small[(size_t)k * nseg + j] = make_uint2(lo, k == cls ? hi : lo);
+        }
+        uint32_t total;
+        const uint32_t t0 = base + plan_exclusive_sum(nt, wsum, &total);
+        if (j < nseg) {
+            lsegs[j] = make_uint4(t0, t0 + nt, lo, 0);
+            for (uint32_t b = 0; b < nt; ++b) {
+                const uint32_t first = lo + b * tile;
+                tiles[t0 + b] = make_uint2(first, min(hi, first + tile));
+            }
+        }
+        base += total;
+    }
+    if (tid == 0) *ntiles = base;
+}
+
+template <typename K, bool KV>
+hipError_t run_devseg(const void* keys_in, void* keys_out, const uint32_t* vals_in,
+                      uint32_t* vals_out, size_t n, const uint32_t* off, uint32_t nseg,
+                      uint32_t small_max, void* ws, const DevSegLayout& L, uint32_t* dev_err,
+                      hipStream_t stream, Profiler* prof)
+{
+    uint8_t* w = (uint8_t*)ws;
+    K* keys_tmp = (K*)(w + L.off_tmp_keys);
+    uint32_t* vals_tmp = KV ? (uint32_t*)(w + L.off_tmp_vals) : nullptr;
+    uint32_t* counts = (uint32_t*)(w + L.off_counts);
+    RoundPlan* plan = (RoundPlan*)(w + L.off_plan);
+    uint2* small = (uint2*)(w + L.off_small);
+    uint2* tiles = (uint2*)(w + L.off_tiles);
+    uint4* lsegs = (uint4*)(w + L.off_lsegs);
+    uint32_t* ntiles = (uint32_t*)(w + L.off_ntiles);
+    const uint32_t rounds = sizeof(K);
+    hipLaunchKernelGGL(k_devseg_plan, dim3(1), dim3(kPlanWG), 0, stream, off, nseg, small_max,
+                       large_tile(sizeof(K)), rounds, plan, small, tiles, lsegs, ntiles);
+    if (prof) profiler_mark(prof, stream, kKindSmall, true);
+    for (int c = 0; c < 3; ++c)
+        launch_small<K, KV>(c, keys_in, keys_out, KV ? vals_in : nullptr, KV ? vals_out : nullptr,
+                            small + (size_t)c * nseg, nseg, rounds, stream);
+    if (prof) profiler_mark(prof, stream, kKindSmall, false);
+    constexpr int WG = R8Config<K>::WG;
+    constexpr int ITEMS = R8Config<K>::ITEMS;
+    for (uint32_t d = 0; d < rounds; ++d) {
+        RoundArgs a;
+        a.keys_in = keys_in;
+        a.keys_out = keys_out;
+        a.keys_tmp = keys_tmp;
+        a.vals_in = vals_in;
+        a.vals_out = vals_out;
+        a.vals_tmp = vals_tmp;
+        a.n = (uint32_t)n;
+        a.shift = 8u * d;
+        a.mask = 0xFFu;
+        a.round = (int)d;
+        a.ntiles = L.max_tiles;
+        a.bases = nullptr;
+        a.plan = plan;
+        a.counts = counts;
+        a.blk_state = nullptr;
+        a.tickets = nullptr;
+        a.err = dev_err;
+        a.tiles = tiles;
+        a.ntiles_dev = ntiles;
+        if (prof) profiler_mark(prof, stream, kKindCount, true);
+        hipLaunchKernelGGL((k_count<K, WG, ITEMS>), dim3(L.max_tiles), dim3(WG), 0, stream, a);
+        if (prof) profiler_mark(prof, stream, kKindCount, false);
+        if (prof) profiler_mark(prof, stream, kKindTileScan, true);
+        hipLaunchKernelGGL(k_segscan, dim3(nseg), dim3(R), 0, stream, a, (const uint4*)lsegs);
+        if (prof) profiler_mark(prof, stream, kKindTileScan, false);
+        if (prof) profiler_mark(prof, stream, kKindRound, true);
+        hipLaunchKernelGGL((k_scatter<K, KV, WG, ITEMS>), dim3(L.max_tiles), dim3(WG), 0, stream, a);
+        if (prof) profiler_mark(prof, stream, kKindRound, false);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+DevSegLayout devseg_layout(int key_bytes, bool has_vals, size_t n, uint32_t nseg)
+{
+    DevSegLayout L;
+    const uint32_t tile = large_tile(key_bytes);
+    L.max_tiles = (uint32_t)((n + tile - 1) / tile) + nseg;
+    size_t o = 0;
+    L.off_tmp_keys = o;  o = align_up(o + n * key_bytes);
+    L.off_tmp_vals = o;  o = align_up(o + (has_vals ? n * 4 : 0));
+    L.off_counts = o;    o = align_up(o + (size_t)L.max_tiles * R * 4);
+    L.off_plan = o;      o = align_up(o + (kMaxRounds + 1) * sizeof(RoundPlan));
+    L.off_small = o;     o = align_up(o + (size_t)3 * nseg * sizeof(uint2));
+    L.off_tiles = o;     o = align_up(o + (size_t)L.max_tiles * sizeof(uint2));
+    L.off_lsegs = o;     o = align_up(o + (size_t)nseg * sizeof(uint4));
+    L.off_ntiles = o;    o = align_up(o + 4);
+    L.bytes = o;
+    return L;
+}
+
+hipError_t devseg_sort(int key_bytes, const void* keys_in, void* keys_out, const uint32_t* vals_in,
+                       uint32_t* vals_out, size_t n, const uint32_t* off, uint32_t nseg,
+                       uint32_t small_max, void* ws, const DevSegLayout& L, uint32_t* dev_err,
+                       hipStream_t stream, Profiler* prof)
+{
+    if (!nseg || !n) return hipSuccess;
+    const bool kv = vals_in != nullptr;
+    if (key_bytes == 4)
+        return kv ? run_devseg<uint32_t, true>(keys_in, keys_out, vals_in, vals_out, n, off, nseg, small_max, ws, L, dev_err, stream, prof)
+                  : run_devseg<uint32_t, false>(keys_in, keys_out, vals_in, vals_out, n, off, nseg, small_max, ws, L, dev_err, stream, prof);
+    return kv ? run_devseg<uint64_t, true>(keys_in, keys_out, vals_in, vals_out, n, off, nseg, small_max, ws, L, dev_err, stream, prof)
+              : run_devseg<uint64_t, false>(keys_in, keys_out, vals_in, vals_out, n, off, nseg, small_max, ws, L, dev_err, stream, prof);
 }
 
 }  // namespace rsort

@@ -44,7 +44,8 @@ EXPORTED = ("rsort_create", "rsort_destroy", "rsort_status_string", "rsort_last_
             "rsort_workspace_bytes", "rsort_sort", "rsort_histogram", "rsort_synchronize",
             "rsort_profile_enable", "rsort_profile_read", "rsort_segmented_sort",
             "rsort_segmented_workspace_bytes", "rsort_segmented_set_split",
-            "rsort_segmented_tune")
+            "rsort_segmented_tune", "rsort_sample_sort", "rsort_sample_sort_workspace_bytes",
+            "rsort_sample_sort_stats")
 
 RSORT_KERNEL_ROUND = 0
 RSORT_KERNEL_HIST = 1
@@ -96,6 +97,9 @@ def load_library():
         lib.rsort_segmented_tune.argtypes = [vp, i, vp, vp, u32p, u32p, vp, sz, i, vp,
                                              ctypes.POINTER(ctypes.c_uint32),
                                              ctypes.POINTER(ctypes.c_double)]
+        lib.rsort_sample_sort.argtypes = [vp, i, vp, vp, u32p, u32p, sz, i, i, vp, sz, vp]
+        lib.rsort_sample_sort_workspace_bytes.argtypes = [vp, i, i, sz, i, i, ctypes.POINTER(sz)]
+        lib.rsort_sample_sort_stats.argtypes = [vp, i, ctypes.POINTER(i), vp, vp, vp, vp]
         lib.rsort_profile_read.argtypes = [vp, i, ctypes.POINTER(ctypes.c_uint64),
                                            ctypes.POINTER(ctypes.c_double)]
         for name in EXPORTED:
@@ -334,6 +338,70 @@ def rsort_segmented_tune(keys_in, keys_out, seg_offsets, vals_in=None, vals_out=
                                        ctypes.byref(ms))
     ctx.check(rc, "rsort_segmented_tune")
     return split.value, ms.value
+
+
+def _check_kv(keys_in, keys_out, vals_in, vals_out):
+    n = keys_in.numel()
+    if keys_out.dtype != keys_in.dtype:
+        raise TypeError("keys_out must have the dtype of keys_in")
+    _check_tensor(keys_in, n, "keys_in")
+    _check_tensor(keys_out, n, "keys_out")
+    if (vals_in is None) != (vals_out is None):
+        raise ValueError("vals_in and vals_out must both be given or both be None")
+    if vals_in is not None:
+        for t, name in ((vals_in, "vals_in"), (vals_out, "vals_out")):
+            if t.dtype not in (torch.int32, torch.uint32):
+                raise TypeError("%s must be a 32-bit integer tensor" % name)
+            _check_tensor(t, n, name)
+    return n
+
+
+def rsort_sample_sort(keys_in, keys_out, vals_in=None, vals_out=None, p=256, r=32,
+                      workspace=None, stream=None):
+    """GSD sample sort (p buckets, oversampling factor r) of 32-bit keys."""
+    kt = _key_type(keys_in)
+    n = _check_kv(keys_in, keys_out, vals_in, vals_out)
+    ctx = context(keys_in.device)
+    ws_ptr, ws_bytes = None, 0
+    if workspace is not None:
+        ws_ptr, ws_bytes = _ptr(workspace), workspace.numel() * workspace.element_size()
+    rc = ctx._lib.rsort_sample_sort(ctx.handle, kt, _ptr(keys_in), _ptr(keys_out), _ptr(vals_in),
+                                    _ptr(vals_out), n, int(p), int(r), ws_ptr, ws_bytes,
+                                    _stream_handle(stream))
+    ctx.check(rc, "rsort_sample_sort")
+    return keys_out, vals_out
+
+
+def rsort_sample_sort_workspace_bytes(key_dtype, has_vals, n, p=256, r=32, device=None):
+    ctx = context(device)
+    kt = _key_type(torch.empty(0, dtype=key_dtype))
+    out = ctypes.c_size_t()
+    ctx.check(ctx._lib.rsort_sample_sort_workspace_bytes(ctx.handle, kt, int(bool(has_vals)),
+                                                         int(n), int(p), int(r),
+                                                         ctypes.byref(out)),
+              "rsort_sample_sort_workspace_bytes")
+    return out.value
+
+
+def rsort_sample_sort_stats(p_cap=1024, device=None):
+    """Split of the last sample sort: dict with p, cnt (p x p), bucket (p),
+    split_key and split_index (p - 1), as numpy uint32 arrays."""
+    import numpy as np
+    ctx = context(device)
+    used = ctypes.c_int()
+    cnt = np.zeros(p_cap * p_cap, dtype=np.uint32)
+    bucket = np.zeros(p_cap, dtype=np.uint32)
+    sk = np.zeros(p_cap, dtype=np.uint32)
+    si = np.zeros(p_cap, dtype=np.uint32)
+    rc = ctx._lib.rsort_sample_sort_stats(ctx.handle, int(p_cap), ctypes.byref(used),
+                                          ctypes.c_void_p(cnt.ctypes.data),
+                                          ctypes.c_void_p(bucket.ctypes.data),
+                                          ctypes.c_void_p(sk.ctypes.data),
+                                          ctypes.c_void_p(si.ctypes.data))
+    ctx.check(rc, "rsort_sample_sort_stats")
+    p = used.value
+    return {"p": p, "cnt": cnt[:p * p].reshape(p, p), "bucket": bucket[:p],
+            "split_key": sk[:max(p - 1, 0)], "split_index": si[:max(p - 1, 0)]}
 
 
 # ---------------------------------------------------------------------------

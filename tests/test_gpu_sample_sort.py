@@ -1,0 +1,187 @@
+"""GPU parity of the regular-oversampling sample sort (GSD, Algorithm 1)
+against the oracle's GSD.
+
+Compared bit-exactly: the sorted keys and payloads, the p x p split matrix
+cnt[k][j] = |X_{k,j}|, the bucket sizes and the p - 1 splitter composites
+(key, input index).  Also checked: the bucket bound of Lemma 1 on every
+distribution (duplicates included), the clamp p = n for tiny inputs, small
+blocks (whole-block LDS sorts) and large ones (tiled rounds), in-place sorting,
+keys only, rsort_sort's default p = 256, r = 32, and argument errors.
+"""
+import numpy as np
+import pytest
+
+import keygen
+import oracle
+from tests.gpu_util import announce, check_kv_invariants, dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rs():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1808_10292_amd import rsort
+    rsort.load_library()
+    return rsort
+
+
+def lemma1_bound(n, p, r):
+    return (1.0 + 1.0 / r) * n / p + r * p
+
+
+def run_case(rs, keys, p, r, with_vals=True, in_place=False):
+    import torch
+    n = keys.size
+    vals = np.arange(n, dtype=np.uint32)
+    want = oracle.gsd(keys, vals if with_vals else None, p, r)
+    dk = dev(keys)
+    dv = dev(vals) if with_vals else None
+    if in_place:
+        ko, vo = dk, dv
+    else:
+        ko = torch.empty_like(dk)
+        vo = torch.empty_like(dv) if with_vals else None
+    rs.rsort_sample_sort(dk, ko, dv, vo, p=p, r=r)
+    rs.rsort_synchronize()
+    got_k = host(ko)
+    assert np.array_equal(got_k, want["keys"])
+    if with_vals:
+        assert np.array_equal(host(vo), want["vals"])
+    st = rs.rsort_sample_sort_stats()
+    pu = want["p"]
+    assert st["p"] == pu
+    assert np.array_equal(st["cnt"].astype(np.uint64), want["cnt"])
+    assert np.array_equal(st["bucket"].astype(np.uint64), want["bucket"])
+    assert np.array_equal(st["split_key"], want["split_key"])
+    assert np.array_equal(st["split_index"].astype(np.uint64), want["split_g"])
+    assert int(st["bucket"].max()) <= lemma1_bound(n, pu, r)
+    return st
+
+
+@pytest.mark.parametrize("dist", keygen.KV_DISTRIBUTIONS)
+def test_distributions_small_blocks(rs, dist):
+    """n = 300007, p = 256: blocks of ~1172 keys (in-LDS local sorts)."""
+    n = 300007
+    announce("gsd small blocks", dist, n)
+    run_case(rs, keygen.kv_keys(dist, n), 256, 32)
+
+
+@pytest.mark.parametrize("dist", keygen.KV_DISTRIBUTIONS)
+def test_distributions_large_blocks(rs, dist):
+    """n = 3000017, p = 256: blocks of ~11719 keys (tiled rounds, ragged tiles)."""
+    n = 3000017
+    announce("gsd large blocks", dist, n)
+    run_case(rs, keygen.kv_keys(dist, n), 256, 32)
+
+
+@pytest.mark.parametrize("n,p,r", [(1, 256, 32), (2, 256, 32), (299, 300, 2), (1000, 1, 1),
+                                   (50000, 7, 3), (65536, 1024, 4), (123457, 100, 1),
+                                   (200000, 64, 64)])
+def test_shapes(rs, n, p, r):
+    announce("gsd shape", n, p, r)
+    keys = keygen.zipf_keys(n, 40 + p)
+    run_case(rs, keys, p, r)
+
+
+def test_keys_only_and_in_place(rs):
+    n = 1000003
+    announce("gsd keys only / in place", n)
+    keys = keygen.uniform_u32(n, 17)
+    run_case(rs, keys, 256, 32, with_vals=False)
+    run_case(rs, keys, 256, 32, with_vals=True, in_place=True)
+    run_case(rs, keys, 128, 8, with_vals=False, in_place=True)
+
+
+def test_rsort_sort_default_parameters(rs):
+    """rsort_sort with the sample-sort algorithm: p = 256, r = 32."""
+    n = 1 << 22
+    announce("gsd via rsort_sort", n)
+    keys = keygen.uniform_u32(n, 21)
+    vals = np.arange(n, dtype=np.uint32)
+    ko, vo = rs.sort(dev(keys), dev(vals), algo="sample")
+    rs.rsort_synchronize()
+    want = oracle.gsd(keys, vals, 256, 32)
+    assert np.array_equal(host(ko), want["keys"])
+    assert np.array_equal(host(vo), want["vals"])
+    st = rs.rsort_sample_sort_stats()
+    assert st["p"] == 256
+    assert np.array_equal(st["bucket"].astype(np.uint64), want["bucket"])
+
+
+def test_errors(rs):
+    import torch
+    k32 = dev(keygen.uniform_u32(1000, 3))
+    o32 = torch.empty_like(k32)
+    for p, r in ((0, 4), (1025, 1), (256, 0)):
+        with pytest.raises(rs.RsortError) as e:
+            rs.rsort_sample_sort(k32, o32, p=p, r=r)
+        assert e.value.status == rs.RSORT_EINVAL
+    with pytest.raises(rs.RsortError) as e:
+        rs.rsort_sample_sort(k32, o32, p=1024, r=128)      # sample 2^27 > 2^26
+    assert e.value.status == rs.RSORT_EUNSUPPORTED
+    k64 = dev(keygen.uniform_u64(1000, 3))
+    with pytest.raises(rs.RsortError) as e:
+        rs.rsort_sample_sort(k64, torch.empty_like(k64))
+    assert e.value.status == rs.RSORT_EUNSUPPORTED
+    with pytest.raises(rs.RsortError):
+        rs.sort(k32, algo="sample", begin_bit=0, end_bit=16)
+    e0 = torch.empty(0, dtype=torch.uint32, device="cuda")
+    rs.rsort_sample_sort(e0, e0)
+
+
+def test_graph_capture_replays(rs):
+    """The sample sort needs no host traffic: captured once, every replay
+    (with eager work between) equals the eager result and follows new data."""
+    import torch
+    n = 500009
+    announce("gsd graph", n)
+    keys = keygen.zipf_keys(n, 91)
+    vals = np.arange(n, dtype=np.uint32)
+    dk, dv = dev(keys), dev(vals)
+    ko, vo = torch.empty_like(dk), torch.empty_like(dv)
+    need = rs.rsort_sample_sort_workspace_bytes(torch.uint32, True, n, 256, 32)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    rs.rsort_sample_sort(dk, ko, dv, vo, workspace=ws)
+    torch.cuda.synchronize()
+    want = oracle.gsd(keys, vals, 256, 32)
+    assert np.array_equal(host(ko), want["keys"]) and np.array_equal(host(vo), want["vals"])
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        rs.rsort_sample_sort(dk, ko, dv, vo, workspace=ws)
+    for rep in range(3):
+        ko.view(torch.int32).fill_(rep)
+        vo.view(torch.int32).fill_(rep)
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(ko), want["keys"]), rep
+        assert np.array_equal(host(vo), want["vals"]), rep
+    keys2 = keygen.uniform_u32(n, 92)
+    dk.copy_(dev(keys2))
+    g.replay()
+    torch.cuda.synchronize()
+    assert np.array_equal(host(ko), oracle.gsd(keys2, vals, 256, 32)["keys"])
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("dist", keygen.KV_DISTRIBUTIONS)
+def test_full_size_kv(rs, dist):
+    """The key-value workload at full size: 2^28 pairs, payload = input index,
+    p = 256, r = 32.  The four invariants of check_kv_invariants determine the
+    stable sort uniquely; the bucket sizes obey Lemma 1 and sum to n."""
+    import torch
+    n = 1 << 28
+    announce("gsd full", dist, n)
+    keys = keygen.kv_keys(dist, n)
+    dk = dev(keys)
+    dv = torch.arange(n, dtype=torch.int32, device="cuda")
+    ko, vo = torch.empty_like(dk), torch.empty_like(dv)
+    rs.rsort_sample_sort(dk, ko, dv, vo, p=256, r=32)
+    rs.rsort_synchronize()
+    del dk
+    st = rs.rsort_sample_sort_stats()
+    assert int(st["bucket"].astype(np.uint64).sum()) == n
+    assert int(st["bucket"].max()) <= lemma1_bound(n, 256, 32)
+    assert np.all(st["cnt"].astype(np.uint64).sum(axis=1) == n // 256)   # block sizes
+    check_kv_invariants(keys, host(ko), host(vo).view(np.uint32))
