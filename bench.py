@@ -19,6 +19,10 @@ Printed as one JSON line:
                summary matches the current kernel source, else null
   cpu_baseline the CPU oracle (serial SR4 in C, one thread) on the same keys
   variants     other algorithms on the same keys (reported, not in value)
+  batched      4096 lognormal arrays: batched segmented sort vs one plain
+               sort per array, latency p50/p99, graph replay
+  kv           2^28 key-value pairs per key distribution: PR4 vs the
+               regular-oversampling sample sort (GSD, p = 256, r = 32)
 """
 import argparse
 import hashlib
@@ -134,6 +138,44 @@ def bench_batched(rsort, torch, np, keygen, args):
             "check": "segments sorted (sampled)" if ok else "FAILED"}
 
 
+def bench_kv(rsort, torch, np, keygen, args):
+    """Key-value sort, radix (PR4) against the regular-oversampling sample sort
+    (GSD, p = 256 buckets, oversampling factor r = 32): 2^28 pairs by default
+    (uint32 key, uint32 payload = input index) per key distribution."""
+    n = 1 << args.kv_log2n
+    res = {"workload": "2^%d (uint32 key, uint32 payload = input index) pairs; PR4 vs GSD "
+                       "p=256 r=32" % args.kv_log2n, "n": n}
+    dv = torch.arange(n, dtype=torch.int32, device="cuda")
+    ko = torch.empty(n, dtype=torch.uint32, device="cuda")
+    vo = torch.empty_like(dv)
+    steps = max(3, args.steps // 4)
+    for dist in args.kv_dists.split(","):
+        log("kv %s: generating %d keys" % (dist, n))
+        keys = keygen.kv_keys(dist, n)
+        dk = torch.from_numpy(keys).cuda()
+        row = {}
+        for algo in ("lsd8", "sample"):
+            fn = (lambda: rsort.rsort_sort(dk, ko, dv, vo, algo="lsd8")) if algo == "lsd8" else \
+                (lambda: rsort.rsort_sample_sort(dk, ko, dv, vo, p=256, r=32))
+            sec = time_steps(fn, steps, 1, torch)
+            # spot check: sorted keys and payloads that point at their keys
+            idx = np.random.default_rng(5).integers(0, n, 4096)
+            ti = torch.from_numpy(idx).cuda()
+            k_h = ko.view(torch.int32)[ti].cpu().numpy().view(np.uint32)
+            v_h = vo[ti].cpu().numpy().view(np.uint32)
+            ok = bool(np.array_equal(keys[v_h], k_h))
+            head = ko[:1 << 20].cpu().numpy()
+            ok = ok and bool(np.all(head[1:] >= head[:-1]))
+            row[algo] = {"ms": round(sec * 1e3, 3), "gkeys_per_s": round(n / sec / 1e9, 3),
+                         "check": "sampled ok" if ok else "FAILED"}
+        st = rsort.rsort_sample_sort_stats()
+        row["sample"]["max_bucket"] = int(st["bucket"].max())
+        row["sample"]["lemma1_bound"] = round((1 + 1 / 32) * n / 256 + 32 * 256, 1)
+        res[dist] = row
+        del dk
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -143,6 +185,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="minimum CPU time spent timing the oracle (0 disables)")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--kv-log2n", type=int, default=28)
+    ap.add_argument("--kv-dists", default="uniform,zipf,equal",
+                    help="comma list of key distributions for the key-value leg "
+                         "(uniform, low16, zipf, equal, presorted, reverse)")
     ap.add_argument("--mode", choices=("sort", "copy"), default="sort",
                     help="copy: time the library's plain device copy of the same bytes "
                          "(calibrates rocprofv3 byte counters against a known transfer)")
@@ -242,7 +288,7 @@ def main():
 
     if not args.no_variants:
         variants = {}
-        for algo in ("lsd16", "sample"):
+        for algo in ("lsd16",):
             try:
                 rsort.rsort_sort(dk, out, algo=algo)
             except rsort.RsortError as e:
@@ -254,6 +300,8 @@ def main():
 
     if not args.no_variants:
         result["batched"] = bench_batched(rsort, torch, np, keygen, args)
+        del dk, out
+        result["kv"] = bench_kv(rsort, torch, np, keygen, args)
 
     if args.cpu_seconds > 0:
         import oracle

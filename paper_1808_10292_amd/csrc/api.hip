@@ -199,6 +199,8 @@ size_t sort_ws_bytes(int key_type, bool has_vals, size_t n, int algo, int begin_
 {
     if (algo == RSORT_SAMPLE_REGULAR)
         return rsort::gsd_layout(has_vals, n, kDefaultP, kDefaultR).bytes;
+    if (algo == RSORT_LSD_R16)
+        return rsort::lsd_r16_layout(key_bytes_of(key_type), has_vals, n, begin_bit, end_bit).bytes;
     return rsort::lsd_r8_layout(key_bytes_of(key_type), has_vals, n, begin_bit, end_bit).bytes;
 }
 
@@ -409,7 +411,8 @@ int rsort_sort(rsort_ctx* ctx, int key_type, const void* keys_in, void* keys_out
     ctx->last_error.clear();
     const int kb = key_bytes_of(key_type);
     if (!kb) return fail(ctx, RSORT_EINVAL, "unknown key type %d", key_type);
-    if (algo != RSORT_AUTO && algo != RSORT_LSD_R8 && algo != RSORT_SAMPLE_REGULAR)
+    if (algo != RSORT_AUTO && algo != RSORT_LSD_R8 && algo != RSORT_LSD_R16 &&
+        algo != RSORT_SAMPLE_REGULAR)
         return fail(ctx, RSORT_EUNSUPPORTED, "algorithm %d not available", algo);
     int rc = validate_bits(ctx, key_type, begin_bit, end_bit);
     if (rc) return rc;
@@ -439,6 +442,23 @@ int rsort_sort(rsort_ctx* ctx, int key_type, const void* keys_in, void* keys_out
         return e == hipSuccess ? RSORT_OK : hip_fail(ctx, e, "copy");
     }
 
+    if (algo == RSORT_LSD_R16) {
+        const rsort::LsdR16Layout L16 =
+            rsort::lsd_r16_layout(kb, vals_in != nullptr, n, begin_bit, end_bit);
+        void* ws = workspace;
+        if (ws) {
+            if (ws_bytes < L16.bytes)
+                return fail(ctx, RSORT_EINVAL, "workspace of %zu bytes < %zu needed", ws_bytes, L16.bytes);
+            if (!is_device_pointer(ws, ctx->device))
+                return fail(ctx, RSORT_EINVAL, "workspace must be device memory");
+        } else {
+            rc = ensure_workspace(ctx, L16.bytes, &ws);
+            if (rc) return rc;
+        }
+        hipError_t e = rsort::lsd_r16_sort(kb, keys_in, keys_out, vals_in, vals_out, n, begin_bit,
+                                           end_bit, ws, L16, s, ctx->prof);
+        return e == hipSuccess ? RSORT_OK : hip_fail(ctx, e, "kernel launch");
+    }
     const rsort::LsdR8Layout L = rsort::lsd_r8_layout(kb, vals_in != nullptr, n, begin_bit, end_bit);
     void* ws = workspace;
     if (ws) {

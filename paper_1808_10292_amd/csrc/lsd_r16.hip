@@ -1,0 +1,344 @@
+// PR2: LSD radix sort with radix r = 2^16 (arXiv 1808.10292 Section 3.2, PR2,
+// equation Tp2): one stable count-sort round per 16-bit digit, two rounds for
+// 32-bit keys.  A round has the paper's three parts, laid out for gfx950:
+//
+//   count    the keys are cut into W <= 256 contiguous chunks, one per
+//            workgroup; k_rows16 counts chunk w's digits into its own row
+//            rows[w][0..65535] (the paper's per-processor count array).  65536
+//            counters do not fit in LDS, so two workgroups per chunk each
+//            count one half of the digit range (32768 LDS counters, 128 KiB);
+//   prefix   rows[w][v] becomes the output index of chunk w's first key of
+//            digit v: sum over all digits u < v of their totals plus the
+//            counts of v in chunks before w (column sums, a scan of the 65536
+//            totals, column prefixes);
+//   place    k_scatter16: workgroup w walks its chunk in order, tile by tile.
+//            Each tile is stable-sorted by the 16-bit digit in LDS (two 8-bit
+//            counting sub-rounds), every key goes to rows[w][v] + its rank in
+//            its digit's run in the tile, and the run's last key advances
+//            rows[w][v].  The workgroup owns its row, so no atomics are needed;
+//            tiles are visited in order, so the round is stable.
+//
+// With 65536 buckets a tile of 8192 keys meets a different digit at almost
+// every key, so the placement is a scattered 4-byte write per key: the cost
+// the paper attributes to large radixes.
+#include <algorithm>
+
+#include "rsort_internal.h"
+#include "tile_sort.h"
+
+namespace rsort {
+namespace {
+
+constexpr uint32_t kR16 = 65536;
+constexpr uint32_t kHalfBins = 32768;
+constexpr int kRowsWG = 1024;
+constexpr uint32_t kMaxChunks = 256;
+
+template <typename K> struct R16Config;
+template <> struct R16Config<uint32_t> {
+    static constexpr int WG = 1024;
+    static constexpr int ITEMS = 8;
+};
+template <> struct R16Config<uint64_t> {
+    static constexpr int WG = 1024;
+    static constexpr int ITEMS = 4;
+};
+
+template <typename K>
+constexpr uint32_t r16_tile() { return (uint32_t)R16Config<K>::WG * R16Config<K>::ITEMS; }
+
+// Workgroup (w, half) counts the digits v of chunk w with v >> 15 == half.
+template <typename K>
+__global__ __launch_bounds__(kRowsWG) void k_rows16(const K* __restrict__ keys, uint32_t n,
+                                                    uint32_t chunk, uint32_t shift, uint32_t mask,
+                                                    uint32_t* rows)
+{
+    extern __shared__ uint32_t cnt[];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t w = blockIdx.x, half = blockIdx.y;
+    const uint32_t nbins = mask + 1;
+    const uint32_t h0 = half * kHalfBins;
+    if (h0 >= nbins) return;
+    const uint32_t hb = min(kHalfBins, nbins - h0);
+    for (uint32_t i = tid; i < hb; i += kRowsWG) cnt[i] = 0;
+    __syncthreads();
+    const uint32_t lo = w * chunk, hi = min(n, lo + chunk);
+    uint32_t i = lo + tid;
+    for (; i + 3 * kRowsWG < hi; i += 4 * kRowsWG) {
+        const K a = keys[i], b = keys[i + kRowsWG], c = keys[i + 2 * kRowsWG],
+                d = keys[i + 3 * kRowsWG];
+        const uint32_t da = digit_of(a, shift, mask) - h0, db = digit_of(b, shift, mask) - h0;
+        const uint32_t dc = digit_of(c, shift, mask) - h0, dd = digit_of(d, shift, mask) - h0;
+        if (da < hb) atomicAdd(&cnt[da], 1u);
+        if (db < hb) atomicAdd(&cnt[db], 1u);
+        if (dc < hb) atomicAdd(&cnt[dc], 1u);
+        if (dd < hb) atomicAdd(&cnt[dd], 1u);
+    }
+    for (; i < hi; i += kRowsWG) {
+        const uint32_t d = digit_of(keys[i], shift, mask) - h0;
+        if (d < hb) atomicAdd(&cnt[d], 1u);
+    }
+    __syncthreads();
+    uint32_t* row = rows + (size_t)w * kR16 + h0;
+    for (uint32_t b = tid; b < hb; b += kRowsWG) row[b] = cnt[b];
+}
+
+// tot[v] = sum over the chunks of rows[w][v].
+__global__ __launch_bounds__(256) void k_colsum16(const uint32_t* rows, uint32_t nchunks,
+                                                  uint32_t nbins, uint32_t* tot)
+{
+    const uint32_t v = blockIdx.x * 256 + threadIdx.x;
+    if (v >= nbins) return;
+    uint32_t s = 0, w = 0;
+    for (; w + 4 <= nchunks; w += 4)
+        s += rows[(size_t)w * kR16 + v] + rows[(size_t)(w + 1) * kR16 + v] +
+             rows[(size_t)(w + 2) * kR16 + v] + rows[(size_t)(w + 3) * kR16 + v];
+    for (; w < nchunks; ++w) s += rows[(size_t)w * kR16 + v];
+    tot[v] = s;
+}
+
+// In-place exclusive scan of tot[0..nbins) (nbins <= 65536) by one workgroup:
+// thread t owns 64 consecutive digits.
+__global__ __launch_bounds__(1024) void k_totscan16(uint32_t* tot, uint32_t nbins)
+{
+    __shared__ uint32_t wsum[16];
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t v0 = tid * 64;
+    uint32_t s = 0;
+    for (uint32_t j = 0; j < 64; ++j)
+        if (v0 + j < nbins) s += tot[v0 + j];
+    const uint32_t incl = wave_inclusive_sum(s);
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    uint32_t run = incl - s;
+    for (uint32_t w = 0; w < wave; ++w) run += wsum[w];
+    for (uint32_t j = 0; j < 64; ++j) {
+        if (v0 + j < nbins) {
+            const uint32_t c = tot[v0 + j];
+            tot[v0 + j] = run;
+            run += c;
+        }
+    }
+}
+
+// rows[w][v] = tot[v] (the digit's start) + sum over chunks w' < w of rows[w'][v].
+__global__ __launch_bounds__(256) void k_colprefix16(uint32_t* rows, uint32_t nchunks,
+                                                     uint32_t nbins, const uint32_t* start)
+{
+    const uint32_t v = blockIdx.x * 256 + threadIdx.x;
+    if (v >= nbins) return;
+    uint32_t run = start[v];
+    for (uint32_t w = 0; w < nchunks; ++w) {
+        uint32_t* p = rows + (size_t)w * kR16 + v;
+        const uint32_t c = *p;
+        *p = run;
+        run += c;
+    }
+}
+
+// Inclusive max over the 64 lanes of a wave.
+__device__ __forceinline__ uint32_t wave_inclusive_max(uint32_t x)
+{
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= (uint32_t)o) x = max(x, y);
+    }
+    return x;
+}
+
+template <typename K, bool KV>
+__global__ __launch_bounds__(R16Config<K>::WG) void k_scatter16(
+    const K* __restrict__ keys_in, K* __restrict__ keys_out, const uint32_t* __restrict__ vals_in,
+    uint32_t* __restrict__ vals_out, uint32_t n, uint32_t chunk, uint32_t shift, uint32_t width,
+    uint32_t* rows)
+{
+    constexpr int WG = R16Config<K>::WG;
+    constexpr int ITEMS = R16Config<K>::ITEMS;
+    constexpr uint32_t TILE = (uint32_t)WG * ITEMS;
+    static_assert(ITEMS * sizeof(K) % 16 == 0, "vector LDS reads of a thread's run");
+    __shared__ TileSmem<K, KV, WG, ITEMS> sm;
+    __shared__ uint32_t wmax[WG / 64];
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t hofs = (tid >> 5) * ITEMS * 32 + (tid & 31);
+    const uint32_t w = blockIdx.x;
+    const uint32_t lo = w * chunk, hi = min(n, lo + chunk);
+    const uint32_t mask = (1u << width) - 1u;
+    const uint32_t w0 = min(width, 8u);
+    uint32_t* row = rows + (size_t)w * kR16;
+    const uint32_t o0 = tid * ITEMS;   // this thread's consecutive positions after sorting
+
+    for (uint32_t t0 = lo; t0 < hi; t0 += TILE) {
+        const uint32_t len = min(TILE, hi - t0);
+        K k[ITEMS];
+        uint32_t v[ITEMS];
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t o = hofs + i * 32;
+            k[i] = o < len ? keys_in[t0 + o] : K(0);
+            v[i] = KV && o < len ? vals_in[t0 + o] : 0u;
+        }
+        // stable sort of the tile by the digit: low 8 bits, then the rest
+        tile_round<K, KV, WG, ITEMS>(sm, k, v, len, shift, (1u << w0) - 1u);
+        if (width > 8) tile_round<K, KV, WG, ITEMS>(sm, k, v, len, shift + 8, (1u << (width - 8)) - 1u);
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t o = hofs + i * 32;
+            if (o < len) {
+                sm.keys[o] = k[i];
+                if (KV) sm.vals[o] = v[i];
+            }
+        }
+        __syncthreads();
+        // each thread takes ITEMS consecutive sorted positions
+        K kk[ITEMS];
+        uint32_t vv[ITEMS], dg[ITEMS];
+        {
+            const uint4* src = (const uint4*)&sm.keys[o0];
+#pragma unroll
+            for (int q = 0; q < (int)(ITEMS * sizeof(K) / 16); ++q) ((uint4*)kk)[q] = src[q];
+            if (KV) {
+                const uint4* vs = (const uint4*)&sm.vals[o0];
+#pragma unroll
+                for (int q = 0; q < ITEMS / 4; ++q) ((uint4*)vv)[q] = vs[q];
+            }
+        }
+        const uint32_t dprev = (o0 > 0 && o0 - 1 < len) ? digit_of(sm.keys[o0 - 1], shift, mask) : 0xFFFFFFFFu;
+        const uint32_t dnext = (o0 + ITEMS < len) ? digit_of(sm.keys[o0 + ITEMS], shift, mask) : 0xFFFFFFFFu;
+        uint32_t mhead = 0;   // last run start at or before this thread's positions
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            dg[i] = digit_of(kk[i], shift, mask);
+            const uint32_t pd = i == 0 ? dprev : dg[i - 1];
+            if (o0 + i < len && (o0 + i == 0 || pd != dg[i])) mhead = o0 + i;
+        }
+        // exclusive max-scan of the heads over the threads in position order
+        const uint32_t incl = wave_inclusive_max(mhead);
+        if (lane == 63) wmax[wave] = incl;
+        uint32_t carry = __shfl_up(incl, 1, 64);
+        if (lane == 0) carry = 0;
+        __syncthreads();
+        for (uint32_t q = 0; q < wave; ++q) carry = max(carry, wmax[q]);
+        uint32_t base[ITEMS], rank[ITEMS];
+        uint32_t cur = carry;
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t o = o0 + i;
+            const uint32_t pd = i == 0 ? dprev : dg[i - 1];
+            if (o < len && (o == 0 || pd != dg[i])) cur = o;
+            rank[i] = o - cur;
+            base[i] = o < len ? ld_agent(&row[dg[i]]) : 0u;
+        }
+        __syncthreads();   // every read of the row precedes its updates
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t o = o0 + i;
+            if (o < len) {
+                const uint32_t d = base[i] + rank[i];
+                if (d < n) {   // always true when the rows are consistent
+                    keys_out[d] = kk[i];
+                    if (KV) vals_out[d] = vv[i];
+                }
+                const uint32_t nd = i + 1 < ITEMS ? dg[i + 1] : dnext;
+                if (o + 1 == len || nd != dg[i]) st_agent(&row[dg[i]], d + 1);
+            }
+        }
+        __threadfence();
+        __syncthreads();
+    }
+}
+
+template <typename K>
+void set_rows_lds()
+{
+    (void)hipFuncSetAttribute((const void*)k_rows16<K>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(kHalfBins * 4));
+}
+
+template <typename K, bool KV>
+hipError_t run16(const void* keys_in, void* keys_out, const uint32_t* vals_in, uint32_t* vals_out,
+                 size_t n, int begin_bit, int end_bit, void* ws, const LsdR16Layout& L,
+                 hipStream_t stream, Profiler* prof)
+{
+    uint8_t* w = (uint8_t*)ws;
+    K* tmp = (K*)(w + L.off_tmp_keys);
+    uint32_t* vtmp = KV ? (uint32_t*)(w + L.off_tmp_vals) : nullptr;
+    uint32_t* rows = (uint32_t*)(w + L.off_rows);
+    uint32_t* tot = (uint32_t*)(w + L.off_tot);
+    const uint32_t rounds = L.rounds;
+    const K* src = (const K*)keys_in;
+    const uint32_t* vsrc = vals_in;
+    hipError_t e;
+    if ((rounds & 1) && keys_in == keys_out) {
+        // an odd round count ends in the output: start from a copy
+        e = copy_bytes(tmp, keys_in, n * sizeof(K), stream);
+        if (e == hipSuccess && KV) e = copy_bytes(vtmp, vals_in, n * 4, stream);
+        if (e != hipSuccess) return e;
+        src = tmp;
+        vsrc = vtmp;
+    }
+    set_rows_lds<K>();
+    for (uint32_t d = 0; d < rounds; ++d) {
+        const uint32_t shift = (uint32_t)begin_bit + 16u * d;
+        const uint32_t width = std::min(16u, (uint32_t)end_bit - shift);
+        const uint32_t mask = (1u << width) - 1u;
+        const uint32_t nbins = mask + 1;
+        const bool to_tmp = ((rounds - 1 - d) & 1) != 0;
+        K* dst = to_tmp ? tmp : (K*)keys_out;
+        uint32_t* vdst = KV ? (to_tmp ? vtmp : vals_out) : nullptr;
+        if (prof) profiler_mark(prof, stream, kKindCount, true);
+        hipLaunchKernelGGL(k_rows16<K>, dim3(L.nchunks, 2), dim3(kRowsWG), kHalfBins * 4, stream,
+                           src, (uint32_t)n, L.chunk, shift, mask, rows);
+        if (prof) profiler_mark(prof, stream, kKindCount, false);
+        if (prof) profiler_mark(prof, stream, kKindTileScan, true);
+        const dim3 cg((nbins + 255) / 256);
+        hipLaunchKernelGGL(k_colsum16, cg, dim3(256), 0, stream, (const uint32_t*)rows, L.nchunks, nbins, tot);
+        hipLaunchKernelGGL(k_totscan16, dim3(1), dim3(1024), 0, stream, tot, nbins);
+        hipLaunchKernelGGL(k_colprefix16, cg, dim3(256), 0, stream, rows, L.nchunks, nbins, (const uint32_t*)tot);
+        if (prof) profiler_mark(prof, stream, kKindTileScan, false);
+        if (prof) profiler_mark(prof, stream, kKindRound, true);
+        hipLaunchKernelGGL((k_scatter16<K, KV>), dim3(L.nchunks), dim3(R16Config<K>::WG), 0, stream,
+                           src, dst, vsrc, vdst, (uint32_t)n, L.chunk, shift, width, rows);
+        if (prof) profiler_mark(prof, stream, kKindRound, false);
+        src = dst;
+        vsrc = vdst;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+LsdR16Layout lsd_r16_layout(int key_bytes, bool has_vals, size_t n, int begin_bit, int end_bit)
+{
+    LsdR16Layout L{};
+    L.rounds = (uint32_t)((end_bit - begin_bit + 15) / 16);
+    const uint32_t tile = key_bytes == 8 ? r16_tile<uint64_t>() : r16_tile<uint32_t>();
+    size_t per = (n + kMaxChunks - 1) / kMaxChunks;
+    per = std::max<size_t>(tile, (per + tile - 1) / tile * tile);
+    L.chunk = (uint32_t)per;
+    L.nchunks = (uint32_t)std::max<size_t>(1, (n + per - 1) / per);
+    size_t o = 0;
+    L.off_tmp_keys = o;  o = align_up(o + n * key_bytes);
+    L.off_tmp_vals = o;  o = align_up(o + (has_vals ? n * 4 : 0));
+    L.off_rows = o;      o = align_up(o + (size_t)L.nchunks * kR16 * 4);
+    L.off_tot = o;       o = align_up(o + (size_t)kR16 * 4);
+    L.bytes = o;
+    return L;
+}
+
+hipError_t lsd_r16_sort(int key_bytes, const void* keys_in, void* keys_out,
+                        const uint32_t* vals_in, uint32_t* vals_out, size_t n, int begin_bit,
+                        int end_bit, void* ws, const LsdR16Layout& L, hipStream_t stream,
+                        Profiler* prof)
+{
+    if (!n || !L.rounds) return hipSuccess;
+    const bool kv = vals_in != nullptr;
+    if (key_bytes == 4)
+        return kv ? run16<uint32_t, true>(keys_in, keys_out, vals_in, vals_out, n, begin_bit, end_bit, ws, L, stream, prof)
+                  : run16<uint32_t, false>(keys_in, keys_out, vals_in, vals_out, n, begin_bit, end_bit, ws, L, stream, prof);
+    return kv ? run16<uint64_t, true>(keys_in, keys_out, vals_in, vals_out, n, begin_bit, end_bit, ws, L, stream, prof)
+              : run16<uint64_t, false>(keys_in, keys_out, vals_in, vals_out, n, begin_bit, end_bit, ws, L, stream, prof);
+}
+
+}  // namespace rsort

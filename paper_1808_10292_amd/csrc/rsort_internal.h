@@ -53,6 +53,22 @@ hipError_t lsd_r8_sort(int key_bytes, const void* keys_in, void* keys_out,
                        int begin_bit, int end_bit, void* ws, const LsdR8Layout& L,
                        uint32_t* dev_err, hipStream_t stream, Profiler* prof);
 
+// ---------------------------------------------------------------------------
+// Radix 2^16 LSD (PR2, lsd_r16.hip): per round, chunk rows of 65536 counts,
+// column prefixes, and a chunk-ordered placement through LDS-sorted tiles.
+struct LsdR16Layout {
+    uint32_t rounds;    // 16-bit (last one narrower) digits
+    uint32_t chunk;     // keys per chunk (a multiple of the tile)
+    uint32_t nchunks;   // <= 256 workgroups / count rows
+    size_t off_tmp_keys, off_tmp_vals, off_rows, off_tot;
+    size_t bytes;
+};
+LsdR16Layout lsd_r16_layout(int key_bytes, bool has_vals, size_t n, int begin_bit, int end_bit);
+hipError_t lsd_r16_sort(int key_bytes, const void* keys_in, void* keys_out,
+                        const uint32_t* vals_in, uint32_t* vals_out, size_t n, int begin_bit,
+                        int end_bit, void* ws, const LsdR16Layout& L, hipStream_t stream,
+                        Profiler* prof);
+
 // Digit histograms of every digit (8- or 16-bit) of [begin_bit, end_bit).
 size_t histogram_ws_bytes(int digit_bits, int begin_bit, int end_bit);
 hipError_t histogram(int key_bytes, const void* keys, size_t n, int digit_bits,

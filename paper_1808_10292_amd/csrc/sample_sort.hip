@@ -169,8 +169,8 @@ __global__ __launch_bounds__(1024) void k_gsd_bucket_starts(const uint32_t* bsiz
 template <bool KV>
 __global__ __launch_bounds__(kRouteWG) void k_gsd_route(const uint32_t* __restrict__ X,
                                                         const uint32_t* __restrict__ XV,
-                                                        const uint32_t* lo, uint32_t p,
-                                                        uint32_t tiles_per_block,
+                                                        const uint32_t* lo, uint32_t n,
+                                                        uint32_t p, uint32_t tiles_per_block,
                                                         const uint32_t* bnd, const uint32_t* off,
                                                         const uint32_t* boff, uint32_t* Y,
                                                         uint32_t* YV)
@@ -212,8 +212,10 @@ __global__ __launch_bounds__(kRouteWG) void k_gsd_route(const uint32_t* __restri
             if (sb[mid] <= u) a = mid; else e = mid;
         }
         const uint32_t d = sd[a] + u;
-        Y[d] = X[b + u];
-        if (KV) YV[d] = XV[b + u];
+        if (d < n) {   // always true when the split is consistent
+            Y[d] = X[b + u];
+            if (KV) YV[d] = XV[b + u];
+        }
     }
 }
 
@@ -292,10 +294,10 @@ hipError_t gsd_sort(const uint32_t* keys_in, uint32_t* keys_out, const uint32_t*
     const dim3 rg(p * L.tiles_per_block);
     if (vals_in)
         hipLaunchKernelGGL(k_gsd_route<true>, rg, dim3(kRouteWG), 0, stream, keys_out, vals_out,
-                           lo, p, L.tiles_per_block, bnd, coloff, boff, Y, YV);
+                           lo, (uint32_t)n, p, L.tiles_per_block, bnd, coloff, boff, Y, YV);
     else
         hipLaunchKernelGGL(k_gsd_route<false>, rg, dim3(kRouteWG), 0, stream, keys_out, nullptr,
-                           lo, p, L.tiles_per_block, bnd, coloff, boff, Y, nullptr);
+                           lo, (uint32_t)n, p, L.tiles_per_block, bnd, coloff, boff, Y, nullptr);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     // 7. finish: every bucket stable-sorted into the output

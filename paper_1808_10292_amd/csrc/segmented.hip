@@ -17,40 +17,23 @@
 #include <vector>
 
 #include "lsd_kernels.h"
+#include "tile_sort.h"
 
 namespace rsort {
 namespace {
 
 // ---------------------------------------------------------------------------
-// k_seg_small: one workgroup sorts segment blockIdx.x of the list in LDS.
-// Layout as in k_scatter: half-wave h owns positions [h*ITEMS*32, ...) of the
-// segment, row i lane l at h*ITEMS*32 + 32*i + l.  Each round reads the keys
-// in that layout from the staging array, counts into 64-bit slots, converts the
-// counts to slot bases, ranks (lane sets), and writes keys (and payloads) back
-// to the staging array at their new positions.  A round in which one digit
-// value holds every key of the segment moves nothing and is skipped.
+// k_seg_small: one workgroup sorts segment blockIdx.x of the list in LDS, one
+// tile_round per 8-bit digit (whole keys), then writes it back once.
 template <typename K, bool KV, int WG, int ITEMS>
 __global__ __launch_bounds__(WG) void k_seg_small(const K* __restrict__ keys_in, K* keys_out,
                                                   const uint32_t* __restrict__ vals_in,
                                                   uint32_t* vals_out, const uint2* segs,
                                                   uint32_t nrounds)
 {
-    constexpr int HW = WG / 32;
-    constexpr uint32_t TILE = (uint32_t)WG * ITEMS;
-    struct Smem {
-        K keys[TILE];
-        uint32_t vals[KV ? TILE : 1];
-        uint2 slot[HW][R];
-        uint32_t wsum[4];
-    };
-    __shared__ Smem sm;
-
+    __shared__ TileSmem<K, KV, WG, ITEMS> sm;
     const uint32_t tid = threadIdx.x;
-    const uint32_t lane = tid & 63;
-    const uint32_t wave = tid >> 6;
-    const uint32_t hw = tid >> 5;
-    const uint32_t hl = tid & 31;
-    const uint32_t hofs = hw * ITEMS * 32 + hl;
+    const uint32_t hofs = (tid >> 5) * ITEMS * 32 + (tid & 31);
     const uint2 seg = segs[blockIdx.x];
     const uint32_t base = seg.x;
     const uint32_t len = seg.y - seg.x;
@@ -61,81 +44,10 @@ __global__ __launch_bounds__(WG) void k_seg_small(const K* __restrict__ keys_in,
     for (int i = 0; i < ITEMS; ++i) {
         const uint32_t o = hofs + i * 32;
         k[i] = o < len ? keys_in[base + o] : K(0);
-        if (KV) v[i] = o < len ? vals_in[base + o] : 0u;
+        v[i] = KV && o < len ? vals_in[base + o] : 0u;
     }
-
-    for (uint32_t r = 0; r < nrounds; ++r) {
-        const uint32_t shift = 8u * r;
-        for (uint32_t i = tid; i < HW * R / 2; i += WG)
-            ((uint4*)&sm.slot[0][0])[i] = make_uint4(0, 0, 0, 0);
-        __syncthreads();
-        // count
-        uint2* sl = sm.slot[hw];
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i)
-            if (hofs + i * 32 < len) atomicAdd(&sl[digit_of(k[i], shift, 0xFFu)].y, 1u);
-        __syncthreads();
-        // bases
-        uint32_t run = 0, total = 0;
-        if (tid < R) {
-#pragma unroll
-            for (int h = 0; h < HW; ++h) total += sm.slot[h][tid].y;
-            const uint32_t incl = wave_inclusive_sum(total);
-            if (lane == 63) sm.wsum[wave] = incl;
-            run = incl - total;
-        }
-        // barrier + "some digit value holds every key": the round is the identity
-        if (__syncthreads_or(tid < R && total == len)) continue;
-        if (tid < R) {
-            for (uint32_t w = 0; w < wave; ++w) run += sm.wsum[w];
-#pragma unroll
-            for (int h = 0; h < HW; ++h) {
-                const uint32_t c = sm.slot[h][tid].y;
-                sm.slot[h][tid].y = run;
-                run += c;
-            }
-        }
-        __syncthreads();
-        // rank
-        uint32_t pos[ITEMS];
-        {
-            const uint32_t bit = 1u << hl;
-            const uint32_t lowsel = lane < 32 ? ~0u : 0u;
-#pragma unroll
-            for (int i = 0; i < ITEMS; ++i) {
-                const bool ok = hofs + i * 32 < len;
-                const uint32_t d = digit_of(k[i], shift, 0xFFu);
-                if (ok) __hip_atomic_fetch_or(&sl[d].x, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                wave_lds_order();
-                const uint64_t s = ok ? __hip_atomic_load((uint64_t*)&sl[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : 0ull;
-                const uint32_t m = (uint32_t)s, c = (uint32_t)(s >> 32);
-                pos[i] = __builtin_amdgcn_mbcnt_hi(m, __builtin_amdgcn_mbcnt_lo(m & lowsel, c));
-                wave_lds_order();
-                if (ok)
-                    __hip_atomic_store((uint64_t*)&sl[d], (uint64_t)(c + __builtin_popcount(m)) << 32,
-                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                wave_lds_order();
-            }
-        }
-        // restage in the new order and reload in the ranking layout
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i) {
-            if (hofs + i * 32 < len) {
-                sm.keys[pos[i]] = k[i];
-                if (KV) sm.vals[pos[i]] = v[i];
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i) {
-            const uint32_t o = hofs + i * 32;
-            if (o < len) {
-                k[i] = sm.keys[o];
-                if (KV) v[i] = sm.vals[o];
-            }
-        }
-        __syncthreads();
-    }
+    for (uint32_t r = 0; r < nrounds; ++r)
+        tile_round<K, KV, WG, ITEMS>(sm, k, v, len, 8u * r, 0xFFu);
     // write out: each thread holds positions hofs + 32 i in the final order
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
