@@ -23,6 +23,8 @@ Printed as one JSON line:
                sort per array, latency p50/p99, graph replay
   kv           2^28 key-value pairs per key distribution: PR4 vs the
                regular-oversampling sample sort (GSD, p = 256, r = 32)
+  serve        Poisson stream of mixed-size uint32/uint64 requests through
+               the continuous-batching server: p50/p99 latency, keys/s
 """
 import argparse
 import hashlib
@@ -176,6 +178,66 @@ def bench_kv(rsort, torch, np, keygen, args):
     return res
 
 
+def bench_serve(rsort, torch, np, keygen, args):
+    """Served sorting: a Poisson stream of requests at a fixed rate, sizes
+    log-uniform in [2^10, 2^26] keys, key type 50% uint32 / 50% uint64 (uniform
+    full range), admitted under a 64 GB HBM cap onto 4 streams and batched on
+    arrival.  Latency = submit to completion seen by the server."""
+    num, rate = args.serve_requests, args.serve_rate
+    sizes = keygen.log_uniform_sizes(num, keygen.SEED_SERVE)
+    kinds = keygen.unit_doubles(keygen.SEED_SERVE + 1, num) < 0.5     # True: uint32
+    arrivals = keygen.poisson_arrivals(num, rate, keygen.SEED_SERVE + 2)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(keygen.SEED_SERVE + 3)
+    ins, outs = [], []
+    for n, u32 in zip(sizes, kinds):
+        if u32:
+            k = torch.randint(-2 ** 31, 2 ** 31, (int(n),), dtype=torch.int32, device="cuda",
+                              generator=g).view(torch.uint32)
+        else:
+            k = torch.randint(-2 ** 63, 2 ** 63 - 1, (int(n),), dtype=torch.int64, device="cuda",
+                              generator=g).view(torch.uint64)
+        ins.append(k)
+        outs.append(torch.empty_like(k))
+    torch.cuda.synchronize()
+    total = int(sizes.sum())
+    log("serve: %d requests, %d keys, %.0f req/s" % (num, total, rate))
+    srv = rsort.Server(64 * 10 ** 9, num_streams=4)
+    # warm-up: one request of each kind and path
+    for i in (int(np.argmin(sizes)), int(np.argmax(sizes))):
+        srv.wait(srv.submit(ins[i], outs[i]))
+    srv.reset_stats()
+    tickets = []
+    t0 = time.perf_counter()
+    for i in range(num):
+        while time.perf_counter() - t0 < arrivals[i]:
+            pass
+        tickets.append(srv.submit(ins[i], outs[i]))
+    for t in tickets:
+        srv.wait(t)
+    wall = time.perf_counter() - t0
+    p50, p99, kps, done = srv.latency()
+    srv.destroy()
+    # each result equals the same request sorted alone
+    pick = sorted(set([int(np.argmin(sizes)), int(np.argmax(sizes))] +
+                      list(np.random.default_rng(1).choice(num, 14, replace=False))))
+    same = True
+    for i in pick:
+        o = torch.empty_like(ins[i])
+        rsort.rsort_sort(ins[i], o)
+        torch.cuda.synchronize()
+        same = same and bool(torch.equal(o.view(torch.uint8), outs[i].view(torch.uint8)))
+    small = int((sizes <= 8192).sum())
+    return {"workload": "%d requests, Poisson %.0f req/s, sizes log-uniform [2^10, 2^26], "
+                        "50%% uint32 / 50%% uint64, cap 64 GB, 4 streams" % (num, rate),
+            "keys": total, "completed": int(done), "small_requests": small,
+            "latency_us_p50": round(p50, 1), "latency_us_p99": round(p99, 1),
+            "gkeys_per_s": round(kps / 1e9, 3), "wall_s": round(wall, 4),
+            "offered_gkeys_per_s": round(total / arrivals[-1] / 1e9, 3),
+            "alone_equals_mix": "%d sampled requests %s" % (len(pick), "identical" if same
+                                                             else "DIFFER")}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -186,6 +248,8 @@ def main():
                     help="minimum CPU time spent timing the oracle (0 disables)")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--kv-log2n", type=int, default=28)
+    ap.add_argument("--serve-requests", type=int, default=300)
+    ap.add_argument("--serve-rate", type=float, default=1000.0, help="arrivals per second")
     ap.add_argument("--kv-dists", default="uniform,zipf,equal",
                     help="comma list of key distributions for the key-value leg "
                          "(uniform, low16, zipf, equal, presorted, reverse)")
@@ -287,21 +351,34 @@ def main():
     }
 
     if not args.no_variants:
-        variants = {}
-        for algo in ("lsd16",):
-            try:
-                rsort.rsort_sort(dk, out, algo=algo)
-            except rsort.RsortError as e:
-                variants[algo] = "unavailable: %s" % e.status
-                continue
-            s = time_steps(lambda: rsort.rsort_sort(dk, out, algo=algo), max(3, args.steps // 4), 1, torch)
-            variants[algo] = {"gkeys_per_s": round(n / s / 1e9, 3), "ms": round(s * 1e3, 3)}
-        result["variants"] = variants
+        # PR2 (radix 2^16, two rounds) on the same keys, with per-pass timings
+        reps = max(3, args.steps // 4)
+        s16 = time_steps(lambda: rsort.rsort_sort(dk, out, algo="lsd16"), reps, 1, torch)
+        rsort.rsort_profile_enable(True)
+        for _ in range(reps):
+            rsort.rsort_sort(dk, out, algo="lsd16")
+        parts = {}
+        for name, kind in (("count_rows", rsort.RSORT_KERNEL_COUNT),
+                           ("column_scan", rsort.RSORT_KERNEL_TILESCAN),
+                           ("place", rsort.RSORT_KERNEL_ROUND)):
+            cnt_l, ms = rsort.rsort_profile_read(kind)
+            parts[name] = round(ms / max(cnt_l, 1), 5)
+        rsort.rsort_profile_enable(False)
+        got16 = out.cpu().numpy()
+        pass_ms = sum(parts.values())
+        result["variants"] = {"lsd16": {
+            "algo": "PR2, radix 2^16, 2 rounds", "ms": round(s16 * 1e3, 3),
+            "gkeys_per_s": round(n / s16 / 1e9, 3),
+            "per_pass_ms": parts,
+            "per_pass_gbps": round(2 * n * 4 / (pass_ms * 1e-3) / 1e9, 1),
+            "place_kernel_gbps": round(2 * n * 4 / (parts["place"] * 1e-3) / 1e9, 1),
+            "same_as_pr4": bool(np.array_equal(got16, got))}}
 
     if not args.no_variants:
         result["batched"] = bench_batched(rsort, torch, np, keygen, args)
         del dk, out
         result["kv"] = bench_kv(rsort, torch, np, keygen, args)
+        result["serve"] = bench_serve(rsort, torch, np, keygen, args)
 
     if args.cpu_seconds > 0:
         import oracle

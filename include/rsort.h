@@ -205,6 +205,54 @@ int rsort_sample_sort_workspace_bytes(rsort_ctx* ctx, int key_type, int has_vals
 int rsort_sample_sort_stats(rsort_ctx* ctx, int p_cap, int* p_used, uint32_t* cnt,
                             uint32_t* bucket, uint32_t* split_key, uint32_t* split_index);
 
+/*
+ * Sort server: a request loop with continuous batching over the sorts above.
+ * Requests are device-resident key arrays (keys only, uint32 or uint64, whole
+ * keys); each is sorted stably from keys_in into keys_out (equal pointers sort
+ * in place).  A scheduling thread owned by the server admits requests in
+ * arrival order onto num_streams streams while the summed HBM footprint of
+ * the requests in flight (their key buffers plus workspace) stays within
+ * hbm_cap_bytes; requests arriving while others run are admitted as streams
+ * and memory free up, so they overlap on the device.  Small requests (at most
+ * 8192 keys) of one key type that are waiting together are sorted by one
+ * launch, one workgroup each, whole in LDS; larger ones run alone through the
+ * radix-2^8 sort.  Each result equals the stable sort of that request's keys
+ * regardless of what else is in flight.  The caller keeps the buffers alive
+ * and untouched until the request completes.
+ */
+typedef struct rsort_server rsort_server;
+
+/* Create a server on HIP device hip_device with 1..64 streams.  Starts its
+ * scheduling thread. */
+int rsort_server_create(int hip_device, size_t hbm_cap_bytes, int num_streams,
+                        rsort_server** out);
+
+/* Queue one sort (thread-safe).  *ticket identifies it.  RSORT_ENOMEM if the
+ * request's footprint alone exceeds the cap; RSORT_EINVAL for host pointers or
+ * partially overlapping buffers; RSORT_EBUSY once destruction has begun. */
+int rsort_server_submit(rsort_server* sv, int key_type, const void* keys_in, void* keys_out,
+                        size_t n, uint64_t* ticket);
+
+/* *done = 1 once the result is in keys_out (then returns the request's
+ * status), else 0 and RSORT_OK.  Thread-safe. */
+int rsort_server_poll(rsort_server* sv, uint64_t ticket, int* done);
+
+/* Block until the request completes; returns its status.  Thread-safe. */
+int rsort_server_wait(rsort_server* sv, uint64_t ticket);
+
+/* Submit-to-completion latency percentiles (nearest rank, microseconds) over
+ * the requests completed since creation or the last reset, the number of
+ * such requests, and their keys per second of wall time from the first
+ * submission to the last completion.  Any output pointer may be NULL. */
+int rsort_server_latency(rsort_server* sv, double* p50_us, double* p99_us, double* keys_per_s,
+                         uint64_t* completed);
+
+/* Forget the latency statistics and the tickets of completed requests. */
+int rsort_server_reset_stats(rsort_server* sv);
+
+/* Finish every queued and running request, stop the thread, free the server. */
+int rsort_server_destroy(rsort_server* sv);
+
 /* Wait for `stream`, then report any device-side failure recorded by this
  * context's kernels since the last call (RSORT_EDEVICE) and clear it. */
 int rsort_synchronize(rsort_ctx* ctx, void* stream);

@@ -135,6 +135,18 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t ntiles)
     return (b & 7) * (ntiles >> 3) + (b >> 3);
 }
 
+// The value held by the lowest active lane of the wave.
+__device__ __forceinline__ uint32_t first_lane_value(uint32_t x)
+{
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
+}
+__device__ __forceinline__ uint64_t first_lane_value(uint64_t x)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // Zero the global histogram copies, the block tickets and the tile-scan words.
 __global__ void k_init(uint32_t* hist, uint32_t hist_words, uint32_t* tickets,
                        uint32_t nrounds, uint32_t* blk_state, size_t state_words)
@@ -167,6 +179,26 @@ __global__ __launch_bounds__(kHistWG) void k_hist(const K* __restrict__ keys, ui
         mask[d] = (1u << w) - 1u;
     }
 
+    // One key per active lane.  When every active lane of the wave holds the
+    // same key (long runs of equal keys), one lane adds the lane count: the
+    // same-address LDS atomics of the other lanes would serialise.
+    auto count_key = [&](K key) {
+        const uint64_t active = __ballot(1);
+        const int leader = __ffsll((unsigned long long)active) - 1;
+        const K first = first_lane_value(key);
+        if (__all(key == first)) {
+            if ((int)(threadIdx.x & 63) == leader) {
+                const uint32_t c = (uint32_t)__popcll(active);
+#pragma unroll
+                for (int d = 0; d < kMaxRounds; ++d)
+                    if ((uint32_t)d < nrounds) atomicAdd(&h[d * R + digit_of(key, shift[d], mask[d])], c);
+            }
+        } else {
+#pragma unroll
+            for (int d = 0; d < kMaxRounds; ++d)
+                if ((uint32_t)d < nrounds) atomicAdd(&h[d * R + digit_of(key, shift[d], mask[d])], 1u);
+        }
+    };
     const uint32_t stride = gridDim.x * kHistWG;
     uint32_t i = blockIdx.x * kHistWG + threadIdx.x;
     for (; i + (kHistUnroll - 1) * stride < n; i += kHistUnroll * stride) {
@@ -174,20 +206,9 @@ __global__ __launch_bounds__(kHistWG) void k_hist(const K* __restrict__ keys, ui
 #pragma unroll
         for (int u = 0; u < kHistUnroll; ++u) k[u] = keys[i + u * stride];
 #pragma unroll
-        for (int u = 0; u < kHistUnroll; ++u) {
-#pragma unroll
-            for (int d = 0; d < kMaxRounds; ++d) {
-                if ((uint32_t)d < nrounds)
-                    atomicAdd(&h[d * R + digit_of(k[u], shift[d], mask[d])], 1u);
-            }
-        }
+        for (int u = 0; u < kHistUnroll; ++u) count_key(k[u]);
     }
-    for (; i < n; i += stride) {
-        K key = keys[i];
-#pragma unroll
-        for (int d = 0; d < kMaxRounds; ++d)
-            if ((uint32_t)d < nrounds) atomicAdd(&h[d * R + digit_of(key, shift[d], mask[d])], 1u);
-    }
+    for (; i < n; i += stride) count_key(keys[i]);
     __syncthreads();
     uint32_t* dst = hist + (blockIdx.x % kHistReplicas) * nrounds * R;
     for (uint32_t b = threadIdx.x; b < nrounds * R; b += kHistWG) {
@@ -241,7 +262,7 @@ __global__ __launch_bounds__(R) void k_plan(const uint32_t* hist, uint32_t nroun
         // identity round, or copy the input to the temporary first).
         int precopy = 0;
         if (!in_place && m == 0) {
-            exec[nrounds - 1] = 1;
+            exec[nrounds - 1] = 2;   // every round is the identity: a plain copy
             m = 1;
         } else if (in_place && (m & 1)) {
             int added = 0;
@@ -297,7 +318,7 @@ __global__ __launch_bounds__(WG) void k_count(RoundArgs a)
     constexpr uint32_t TILE = (uint32_t)WG * ITEMS;
     __shared__ uint32_t h[R * 32];
     const RoundPlan pl = a.plan[a.round];
-    if (!pl.exec) return;
+    if (pl.exec != 1) return;
     const uint32_t tid = threadIdx.x;
     for (uint32_t i = tid; i < R * 32 / 4; i += WG) ((uint4*)h)[i] = make_uint4(0, 0, 0, 0);
     __syncthreads();
@@ -345,7 +366,7 @@ __global__ __launch_bounds__(R) void k_tilescan(RoundArgs a)
 {
     __shared__ uint32_t blk_s;
     const RoundPlan pl = a.plan[a.round];
-    if (!pl.exec) return;
+    if (pl.exec != 1) return;
     const uint32_t v = threadIdx.x;
     if (v == 0) blk_s = atomicAdd(&a.tickets[a.round], 1u);
     __syncthreads();
@@ -461,6 +482,13 @@ __global__ __launch_bounds__(WG, KV ? RSORT_R8_WAVES_PER_EU_KV : RSORT_R8_WAVES_
     const uint32_t* vsrc = KV ? pick<uint32_t>(pl.src, a.vals_in, a.vals_out, a.vals_tmp) : nullptr;
     K* dst = pick<K>(pl.dst, (const K*)a.keys_in, (K*)a.keys_out, (K*)a.keys_tmp);
     uint32_t* vdst = KV ? pick<uint32_t>(pl.dst, a.vals_in, a.vals_out, a.vals_tmp) : nullptr;
+    if (pl.exec == 2) {   // identity round standing for a copy
+        for (uint32_t i = blockIdx.x * WG + tid; i < a.n; i += gridDim.x * WG) {
+            dst[i] = src[i];
+            if (KV) vdst[i] = vsrc[i];
+        }
+        return;
+    }
 
     auto load = [&](uint32_t t, K (&kk)[ITEMS], uint32_t (&vv)[ITEMS]) {
         const uint2 tr = tile_range(a, t, TILE);

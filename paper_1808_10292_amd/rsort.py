@@ -45,7 +45,9 @@ EXPORTED = ("rsort_create", "rsort_destroy", "rsort_status_string", "rsort_last_
             "rsort_profile_enable", "rsort_profile_read", "rsort_segmented_sort",
             "rsort_segmented_workspace_bytes", "rsort_segmented_set_split",
             "rsort_segmented_tune", "rsort_sample_sort", "rsort_sample_sort_workspace_bytes",
-            "rsort_sample_sort_stats")
+            "rsort_sample_sort_stats", "rsort_server_create", "rsort_server_submit",
+            "rsort_server_poll", "rsort_server_wait", "rsort_server_latency",
+            "rsort_server_reset_stats", "rsort_server_destroy")
 
 RSORT_KERNEL_ROUND = 0
 RSORT_KERNEL_HIST = 1
@@ -100,6 +102,16 @@ def load_library():
         lib.rsort_sample_sort.argtypes = [vp, i, vp, vp, u32p, u32p, sz, i, i, vp, sz, vp]
         lib.rsort_sample_sort_workspace_bytes.argtypes = [vp, i, i, sz, i, i, ctypes.POINTER(sz)]
         lib.rsort_sample_sort_stats.argtypes = [vp, i, ctypes.POINTER(i), vp, vp, vp, vp]
+        lib.rsort_server_create.argtypes = [i, sz, i, ctypes.POINTER(vp)]
+        lib.rsort_server_submit.argtypes = [vp, i, vp, vp, sz, ctypes.POINTER(ctypes.c_uint64)]
+        lib.rsort_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(i)]
+        lib.rsort_server_wait.argtypes = [vp, ctypes.c_uint64]
+        lib.rsort_server_latency.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                             ctypes.POINTER(ctypes.c_double),
+                                             ctypes.POINTER(ctypes.c_double),
+                                             ctypes.POINTER(ctypes.c_uint64)]
+        lib.rsort_server_reset_stats.argtypes = [vp]
+        lib.rsort_server_destroy.argtypes = [vp]
         lib.rsort_profile_read.argtypes = [vp, i, ctypes.POINTER(ctypes.c_uint64),
                                            ctypes.POINTER(ctypes.c_double)]
         for name in EXPORTED:
@@ -402,6 +414,86 @@ def rsort_sample_sort_stats(p_cap=1024, device=None):
     p = used.value
     return {"p": p, "cnt": cnt[:p * p].reshape(p, p), "bucket": bucket[:p],
             "split_key": sk[:max(p - 1, 0)], "split_index": si[:max(p - 1, 0)]}
+
+
+class Server:
+    """rsort_server: continuous-batching sort server on one device.  Methods
+    carry the C names without the prefix; submit takes torch tensors and keeps
+    references to them until the request is waited on."""
+
+    def __init__(self, hbm_cap_bytes, num_streams=4, device=None):
+        lib = load_library()
+        if device is None:
+            device = torch.cuda.current_device()
+        h = ctypes.c_void_p()
+        rc = lib.rsort_server_create(int(device), int(hbm_cap_bytes), int(num_streams),
+                                     ctypes.byref(h))
+        if rc != RSORT_OK:
+            raise RsortError(rc, "rsort_server_create")
+        self.handle = h
+        self._lib = lib
+        self._held = {}
+        self._lock = threading.Lock()
+
+    def submit(self, keys_in, keys_out):
+        kt = _key_type(keys_in)
+        n = keys_in.numel()
+        if keys_out.dtype != keys_in.dtype:
+            raise TypeError("keys_out must have the dtype of keys_in")
+        _check_tensor(keys_in, n, "keys_in")
+        _check_tensor(keys_out, n, "keys_out")
+        t = ctypes.c_uint64()
+        rc = self._lib.rsort_server_submit(self.handle, kt, _ptr(keys_in), _ptr(keys_out), n,
+                                           ctypes.byref(t))
+        if rc != RSORT_OK:
+            raise RsortError(rc, "rsort_server_submit")
+        with self._lock:
+            self._held[t.value] = (keys_in, keys_out)
+        return t.value
+
+    def poll(self, ticket):
+        done = ctypes.c_int()
+        rc = self._lib.rsort_server_poll(self.handle, int(ticket), ctypes.byref(done))
+        if rc != RSORT_OK:
+            raise RsortError(rc, "rsort_server_poll")
+        if done.value:
+            with self._lock:
+                self._held.pop(int(ticket), None)
+        return bool(done.value)
+
+    def wait(self, ticket):
+        rc = self._lib.rsort_server_wait(self.handle, int(ticket))
+        with self._lock:
+            self._held.pop(int(ticket), None)
+        if rc != RSORT_OK:
+            raise RsortError(rc, "rsort_server_wait")
+
+    def latency(self):
+        """(p50 us, p99 us, keys/s, completed requests)"""
+        p50, p99, kps = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        done = ctypes.c_uint64()
+        rc = self._lib.rsort_server_latency(self.handle, ctypes.byref(p50), ctypes.byref(p99),
+                                            ctypes.byref(kps), ctypes.byref(done))
+        if rc != RSORT_OK:
+            raise RsortError(rc, "rsort_server_latency")
+        return p50.value, p99.value, kps.value, done.value
+
+    def reset_stats(self):
+        rc = self._lib.rsort_server_reset_stats(self.handle)
+        if rc != RSORT_OK:
+            raise RsortError(rc, "rsort_server_reset_stats")
+
+    def destroy(self):
+        if self.handle:
+            self._lib.rsort_server_destroy(self.handle)
+            self.handle = None
+            self._held.clear()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
 
 
 # ---------------------------------------------------------------------------
