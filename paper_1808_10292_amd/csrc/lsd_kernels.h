@@ -84,7 +84,7 @@ struct RoundArgs {
     uint32_t mask;
     uint32_t round;
     uint32_t ntiles;
-    const uint32_t* bases;   // [round][256] start of each digit's bucket
+    uint32_t* bases;         // [round][256] start of each digit's bucket (written by the tile scan)
     const RoundPlan* plan;
     uint32_t* counts;        // [ntiles][256] tile counts, then tile output starts
     uint32_t* blk_state;     // [round][nblocks][256] look-back words of k_tilescan
@@ -158,9 +158,62 @@ __global__ void k_init(uint32_t* hist, uint32_t hist_words, uint32_t* tickets,
     for (size_t i = g; i < state_words; i += stride) blk_state[i] = 0;
 }
 
+// The 8-bit digits of [begin_bit, end_bit), least significant first (the
+// last one narrower when the range is not a multiple of 8).
+struct DigitSet {
+    uint32_t shift[kMaxRounds];
+    uint32_t mask[kMaxRounds];
+};
+__device__ __forceinline__ DigitSet digit_set(uint32_t begin_bit, uint32_t end_bit)
+{
+    DigitSet ds;
+#pragma unroll
+    for (int d = 0; d < kMaxRounds; ++d) {
+        const uint32_t lo = begin_bit + 8u * d;
+        const uint32_t w = lo < end_bit ? min(8u, end_bit - lo) : 0u;
+        ds.shift[d] = lo < end_bit ? lo : 0u;
+        ds.mask[d] = (1u << w) - 1u;
+    }
+    return ds;
+}
+
+// Adds one key per active lane to the LDS histograms h[d * 256 + v] of every
+// digit d < nrounds.  When every active lane of the wave holds the same key
+// (long runs of equal keys) one lane adds the lane count: the same-address
+// LDS atomics of the other lanes would serialise.
+template <typename K>
+__device__ __forceinline__ void hist_add(uint32_t* h, const DigitSet& ds, uint32_t nrounds, K key)
+{
+    const uint64_t active = __ballot(1);
+    const int leader = __ffsll((unsigned long long)active) - 1;
+    const K first = first_lane_value(key);
+    if (__all(key == first)) {
+        if ((int)(threadIdx.x & 63) == leader) {
+            const uint32_t c = (uint32_t)__popcll(active);
+#pragma unroll
+            for (int d = 0; d < kMaxRounds; ++d)
+                if ((uint32_t)d < nrounds) atomicAdd(&h[d * R + digit_of(key, ds.shift[d], ds.mask[d])], c);
+        }
+    } else {
+#pragma unroll
+        for (int d = 0; d < kMaxRounds; ++d)
+            if ((uint32_t)d < nrounds) atomicAdd(&h[d * R + digit_of(key, ds.shift[d], ds.mask[d])], 1u);
+    }
+}
+
+// Adds a workgroup's LDS histograms to global copy (block index mod 8), one
+// atomic per nonzero bin; the copies spread contention across the XCDs.
+__device__ __forceinline__ void hist_flush(const uint32_t* h, uint32_t nrounds, uint32_t* hist)
+{
+    uint32_t* dst = hist + (blockIdx.x % kHistReplicas) * nrounds * R;
+    for (uint32_t b = threadIdx.x; b < nrounds * R; b += blockDim.x) {
+        const uint32_t c = h[b];
+        if (c) atomicAdd(&dst[b], c);
+    }
+}
+
 // Counts of every 8-bit digit of [begin_bit, end_bit) in one pass over the
-// keys: LDS histograms per workgroup, then one global atomic per nonzero bin
-// into copy (block index mod 8), which spreads contention across the XCDs.
+// keys (the histogram entry point; the sort takes them in its first count).
 template <typename K>
 __global__ __launch_bounds__(kHistWG) void k_hist(const K* __restrict__ keys, uint32_t n,
                                                   uint32_t begin_bit, uint32_t end_bit,
@@ -169,36 +222,7 @@ __global__ __launch_bounds__(kHistWG) void k_hist(const K* __restrict__ keys, ui
     __shared__ uint32_t h[kMaxRounds * R];
     for (uint32_t i = threadIdx.x; i < nrounds * R; i += kHistWG) h[i] = 0;
     __syncthreads();
-
-    uint32_t shift[kMaxRounds], mask[kMaxRounds];
-#pragma unroll
-    for (int d = 0; d < kMaxRounds; ++d) {
-        uint32_t lo = begin_bit + 8u * d;
-        uint32_t w = lo < end_bit ? min(8u, end_bit - lo) : 0u;
-        shift[d] = lo < end_bit ? lo : 0u;
-        mask[d] = (1u << w) - 1u;
-    }
-
-    // One key per active lane.  When every active lane of the wave holds the
-    // same key (long runs of equal keys), one lane adds the lane count: the
-    // same-address LDS atomics of the other lanes would serialise.
-    auto count_key = [&](K key) {
-        const uint64_t active = __ballot(1);
-        const int leader = __ffsll((unsigned long long)active) - 1;
-        const K first = first_lane_value(key);
-        if (__all(key == first)) {
-            if ((int)(threadIdx.x & 63) == leader) {
-                const uint32_t c = (uint32_t)__popcll(active);
-#pragma unroll
-                for (int d = 0; d < kMaxRounds; ++d)
-                    if ((uint32_t)d < nrounds) atomicAdd(&h[d * R + digit_of(key, shift[d], mask[d])], c);
-            }
-        } else {
-#pragma unroll
-            for (int d = 0; d < kMaxRounds; ++d)
-                if ((uint32_t)d < nrounds) atomicAdd(&h[d * R + digit_of(key, shift[d], mask[d])], 1u);
-        }
-    };
+    const DigitSet ds = digit_set(begin_bit, end_bit);
     const uint32_t stride = gridDim.x * kHistWG;
     uint32_t i = blockIdx.x * kHistWG + threadIdx.x;
     for (; i + (kHistUnroll - 1) * stride < n; i += kHistUnroll * stride) {
@@ -206,15 +230,11 @@ __global__ __launch_bounds__(kHistWG) void k_hist(const K* __restrict__ keys, ui
 #pragma unroll
         for (int u = 0; u < kHistUnroll; ++u) k[u] = keys[i + u * stride];
 #pragma unroll
-        for (int u = 0; u < kHistUnroll; ++u) count_key(k[u]);
+        for (int u = 0; u < kHistUnroll; ++u) hist_add(h, ds, nrounds, k[u]);
     }
-    for (; i < n; i += stride) count_key(keys[i]);
+    for (; i < n; i += stride) hist_add(h, ds, nrounds, keys[i]);
     __syncthreads();
-    uint32_t* dst = hist + (blockIdx.x % kHistReplicas) * nrounds * R;
-    for (uint32_t b = threadIdx.x; b < nrounds * R; b += kHistWG) {
-        uint32_t c = h[b];
-        if (c) atomicAdd(&dst[b], c);
-    }
+    hist_flush(h, nrounds, hist);
 }
 
 // Block-wide (256 threads) inclusive sum; wsum is 4 words of LDS.
@@ -230,24 +250,20 @@ __device__ __forceinline__ uint32_t block256_inclusive_sum(uint32_t x, uint32_t*
     return pre + incl;
 }
 
-// Round bases (exclusive prefix of each round's counts) and the round plan.
-// One workgroup of 256 threads, thread t owns digit value t.
-__global__ __launch_bounds__(R) void k_plan(const uint32_t* hist, uint32_t nrounds, uint32_t n,
-                                            int in_place, uint32_t* bases, RoundPlan* plan)
+// The round plan.  mixed[0..1] = OR over all keys of (key XOR first key) (low
+// and high 32 bits): a round is the identity -- one digit value holds every
+// key -- exactly when its digit's bits are zero there.
+__global__ void k_plan(const uint32_t* mixed, uint32_t nrounds, uint32_t begin_bit,
+                       uint32_t end_bit, int in_place, RoundPlan* plan)
 {
-    __shared__ uint32_t wsum[4];
-    __shared__ int identity[kMaxRounds];
     const uint32_t t = threadIdx.x;
-    if (t < kMaxRounds) identity[t] = 0;
-    __syncthreads();
+    const uint64_t mx = (uint64_t)mixed[0] | ((uint64_t)mixed[1] << 32);
+    int identity[kMaxRounds];
     for (uint32_t d = 0; d < nrounds; ++d) {
-        uint32_t c = 0;
-        for (int rep = 0; rep < kHistReplicas; ++rep) c += hist[(rep * nrounds + d) * R + t];
-        uint32_t incl = block256_inclusive_sum(c, wsum);
-        bases[d * R + t] = incl - c;
-        if (c == n) identity[d] = 1;
+        const uint32_t lo = begin_bit + 8u * d;
+        const uint32_t w = min(8u, end_bit - lo);
+        identity[d] = ((mx >> lo) & ((1ull << w) - 1ull)) == 0;
     }
-    __syncthreads();
     if (t == 0) {
         int exec[kMaxRounds];
         int m = 0;
@@ -311,16 +327,32 @@ __global__ void k_precopy(const RoundPlan* plan, const K* keys, K* keys_tmp,
 //
 // Every lane counts into its own column of a [256][32] table (lane l of every
 // wave uses column l mod 32), so the 32 lanes of a half-wave always hit 32
-// different LDS banks; the columns are summed at the end.
-template <typename K, int WG, int ITEMS>
-__global__ __launch_bounds__(WG) void k_count(RoundArgs a)
+// different LDS banks; the columns are summed at the end.  Full tiles of the
+// plain sort are read with 16-byte loads.
+//
+// FIRST (first round of the plain sort only): the same read also ORs every
+// key's difference from the first key into mixed[0..1], from which the
+// planning kernel finds the identity rounds; this kernel then runs before the
+// plan exists.
+template <typename K, int WG, int ITEMS, bool FIRST>
+__global__ __launch_bounds__(WG) void k_count(RoundArgs a, uint32_t* mixed)
 {
+    constexpr bool ALL = FIRST;
     constexpr uint32_t TILE = (uint32_t)WG * ITEMS;
+    constexpr int VEC = 16 / sizeof(K);   // keys per 16-byte load
+    static_assert(ITEMS % VEC == 0, "whole vectors per thread");
     __shared__ uint32_t h[R * 32];
-    const RoundPlan pl = a.plan[a.round];
-    if (pl.exec != 1) return;
+    __shared__ uint32_t mix_s[2];
+    RoundPlan pl;
+    if (ALL) {
+        pl = RoundPlan{1, 0, 0, 0};
+    } else {
+        pl = a.plan[a.round];
+        if (pl.exec != 1) return;
+    }
     const uint32_t tid = threadIdx.x;
     for (uint32_t i = tid; i < R * 32 / 4; i += WG) ((uint4*)h)[i] = make_uint4(0, 0, 0, 0);
+    if (ALL && tid < 2) mix_s[tid] = 0;
     __syncthreads();
     uint32_t tile;
     if (a.ntiles_dev) {
@@ -333,17 +365,57 @@ __global__ __launch_bounds__(WG) void k_count(RoundArgs a)
     const uint32_t base = tr.x;
     const uint32_t lim = tr.y;
     const K* src = pick<K>(pl.src, (const K*)a.keys_in, (K*)a.keys_out, (K*)a.keys_tmp) + base;
-    K k[ITEMS];
-#pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        const uint32_t o = i * WG + tid;
-        k[i] = o < lim ? src[o] : K(0);
-    }
     const uint32_t col = tid & 31;
+    const K ref = ALL ? ((const K*)a.keys_in)[0] : K(0);
+    K acc = 0;
+    K k[ITEMS];
+    const bool vec = !a.tiles && lim == TILE && ((uintptr_t)src & 15) == 0;
+    if (vec) {
 #pragma unroll
-    for (int i = 0; i < ITEMS; ++i)
-        if (i * WG + tid < lim) atomicAdd(&h[digit_of(k[i], a.shift, a.mask) * 32 + col], 1u);
+        for (int q = 0; q < ITEMS / VEC; ++q) {
+            const uint4 x = ((const uint4*)src)[q * WG + tid];
+            const K* kx = (const K*)&x;
+#pragma unroll
+            for (int c = 0; c < VEC; ++c) k[q * VEC + c] = kx[c];
+        }
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            atomicAdd(&h[digit_of(k[i], a.shift, a.mask) * 32 + col], 1u);
+            if (ALL) acc |= k[i] ^ ref;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t o = i * WG + tid;
+            k[i] = o < lim ? src[o] : K(0);
+        }
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            if (i * WG + tid < lim) {
+                atomicAdd(&h[digit_of(k[i], a.shift, a.mask) * 32 + col], 1u);
+                if (ALL) acc |= k[i] ^ ref;
+            }
+        }
+    }
+    if (ALL) {
+        const uint64_t a64 = (uint64_t)acc;
+        uint32_t lo = (uint32_t)a64, hi = (uint32_t)(a64 >> 32);
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            lo |= __shfl_xor(lo, o, 64);
+            hi |= __shfl_xor(hi, o, 64);
+        }
+        if ((tid & 63) == 0) {
+            if (lo) atomicOr(&mix_s[0], lo);
+            if (hi) atomicOr(&mix_s[1], hi);
+        }
+    }
     __syncthreads();
+    if (ALL && tid < 2) {
+        // only bits the global word lacks cost an atomic
+        const uint32_t mine = mix_s[tid];
+        if (mine & ~ld_agent(&mixed[tid])) atomicOr(&mixed[tid], mine);
+    }
     for (uint32_t v = tid; v < R; v += WG) {
         const uint4* r4 = (const uint4*)&h[v * 32];
         uint32_t s = 0;
@@ -357,8 +429,8 @@ __global__ __launch_bounds__(WG) void k_count(RoundArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// k_tilescan: replaces counts[t][v] by bases[v] + sum of counts[t'][v] over
-// t' < t.  Workgroup = block of kScanBlock tiles taken in ticket order; thread
+// k_tilescan: replaces counts[t][v] by the sum of counts[t'][v] over t' < t,
+// and (last block) writes the round's digit starts bases[v].  Workgroup = block of kScanBlock tiles taken in ticket order; thread
 // v sums its digit over the block, publishes the block total, folds the totals
 // of earlier blocks by decoupled look-back (a packed flag+count word per block
 // and digit), publishes the inclusive prefix and rewrites its column.
@@ -423,7 +495,14 @@ __global__ __launch_bounds__(R) void k_tilescan(RoundArgs a)
         }
         st_agent(&state[(size_t)blk * R + v], kFlagPrefix | ((excl + total) & kCountMask));
     }
-    uint32_t run = a.bases[a.round * R + v] + excl;
+    if (blk == nblocks - 1) {
+        // excl + total is digit v's total over all tiles: the last block turns
+        // the totals into the round's digit starts
+        __shared__ uint32_t wsum[4];
+        const uint32_t all = excl + total;
+        a.bases[a.round * R + v] = block256_inclusive_sum(all, wsum) - all;
+    }
+    uint32_t run = excl;
 #pragma unroll
     for (uint32_t i = 0; i < kScanBlock; ++i) {
         if (t0 + i < t1) col[(size_t)(t0 + i) * R] = run;
@@ -511,7 +590,10 @@ __global__ __launch_bounds__(WG, KV ? RSORT_R8_WAVES_PER_EU_KV : RSORT_R8_WAVES_
         for (uint32_t i = tid; i < HW * R / 2; i += WG)
             ((uint4*)&sm.u.slot[0][0])[i] = make_uint4(0, 0, 0, 0);
         uint32_t toff = 0;
-        if (tid < R) toff = a.counts[(size_t)tile * R + tid];
+        if (tid < R) {
+            toff = a.counts[(size_t)tile * R + tid];
+            if (a.bases) toff += a.bases[a.round * R + tid];
+        }
         __syncthreads();
 
         // Rank row by row; the high word of a slot is advanced by the lanes of

@@ -18,10 +18,10 @@
 //              write consecutive slots of each digit's run -- with the payload
 //              moved alongside.
 //
-// Before the first round, k_hist counts every digit of every round in a single
-// read of the keys and k_plan turns those counts into the digit starts of
-// each round and the round plan: a round whose digit is the same for all n
-// keys is the identity and is skipped.
+// The first round's k_count also ORs together every key's difference from the
+// first key in the same read, and k_plan derives the round plan from it: a
+// round whose digit is the same for all n keys is the identity and is
+// skipped.  Each round's digit starts come out of its own tile scan.
 //
 // No tile of a round waits for another tile: the dependencies are kernel
 // boundaries, except the chain of tile blocks inside k_tilescan.
@@ -85,6 +85,34 @@ uint32_t persistent_blocks(const void* kernel, int wg)
     return v;
 }
 
+RoundArgs round_args(const void* keys_in, void* keys_out, void* keys_tmp, const uint32_t* vals_in,
+                     uint32_t* vals_out, uint32_t* vals_tmp, size_t n, int begin_bit, int end_bit,
+                     uint32_t d, const LsdR8Layout& L, uint32_t* bases, RoundPlan* plan,
+                     uint32_t* counts, uint32_t* blk_state, uint32_t* tickets, uint32_t* dev_err)
+{
+    RoundArgs a;
+    a.keys_in = keys_in;
+    a.keys_out = keys_out;
+    a.keys_tmp = keys_tmp;
+    a.vals_in = vals_in;
+    a.vals_out = vals_out;
+    a.vals_tmp = vals_tmp;
+    a.n = (uint32_t)n;
+    a.shift = (uint32_t)begin_bit + 8u * d;
+    a.mask = (1u << std::min(8u, (uint32_t)end_bit - a.shift)) - 1u;
+    a.round = d;
+    a.ntiles = L.ntiles;
+    a.bases = bases;
+    a.plan = plan;
+    a.counts = counts;
+    a.blk_state = blk_state;
+    a.tickets = tickets;
+    a.err = dev_err;
+    a.tiles = nullptr;
+    a.ntiles_dev = nullptr;
+    return a;
+}
+
 template <typename K, bool KV>
 hipError_t run(const void* keys_in, void* keys_out, const uint32_t* vals_in, uint32_t* vals_out,
                size_t n, int begin_bit, int end_bit, void* ws, const LsdR8Layout& L,
@@ -105,15 +133,21 @@ hipError_t run(const void* keys_in, void* keys_out, const uint32_t* vals_in, uin
     const bool in_place = keys_in == keys_out || (KV && vals_in == vals_out);
     const uint32_t nblk = nblocks_of(L.ntiles);
 
-    hipLaunchKernelGGL(k_init, dim3(256), dim3(256), 0, stream, hist,
-                       (uint32_t)(kHistReplicas * nr * R), tickets, nr, blk_state,
+    uint32_t* mixed = hist;   // 2 words
+    hipLaunchKernelGGL(k_init, dim3(256), dim3(256), 0, stream, mixed, 2u, tickets, nr, blk_state,
                        (size_t)nr * nblk * R);
-    if (prof) profiler_mark(prof, stream, kKindHist, true);
-    hipLaunchKernelGGL(k_hist<K>, dim3(hist_grid(n)), dim3(kHistWG), 0, stream,
-                       (const K*)keys_in, (uint32_t)n, (uint32_t)begin_bit, (uint32_t)end_bit, nr, hist);
-    if (prof) profiler_mark(prof, stream, kKindHist, false);
-    hipLaunchKernelGGL(k_plan, dim3(1), dim3(R), 0, stream, (const uint32_t*)hist, nr,
-                       (uint32_t)n, (int)in_place, bases, plan);
+    // Round 0's tile counts and the identity test of every round in one read.
+    {
+        RoundArgs a0 = round_args(keys_in, keys_out, keys_tmp, vals_in, vals_out, vals_tmp, n,
+                                  begin_bit, end_bit, 0, L, bases, plan, counts, blk_state,
+                                  tickets, dev_err);
+        if (prof) profiler_mark(prof, stream, kKindHist, true);
+        hipLaunchKernelGGL((k_count<K, WG, ITEMS, true>), dim3(L.ntiles), dim3(WG), 0, stream, a0,
+                           mixed);
+        if (prof) profiler_mark(prof, stream, kKindHist, false);
+    }
+    hipLaunchKernelGGL(k_plan, dim3(1), dim3(64), 0, stream, (const uint32_t*)mixed, nr,
+                       (uint32_t)begin_bit, (uint32_t)end_bit, (int)in_place, plan);
     if (in_place && (nr & 1)) {
         uint32_t g = (uint32_t)std::min<size_t>((n + 255) / 256, 2048);
         hipLaunchKernelGGL(k_precopy<K>, dim3(g), dim3(256), 0, stream, (const RoundPlan*)plan,
@@ -127,29 +161,15 @@ hipError_t run(const void* keys_in, void* keys_out, const uint32_t* vals_in, uin
         sgrid = std::min<uint32_t>(L.ntiles, resident & ~7u ? resident & ~7u : resident);
     }
     for (uint32_t d = 0; d < nr; ++d) {
-        RoundArgs a;
-        a.keys_in = keys_in;
-        a.keys_out = keys_out;
-        a.keys_tmp = keys_tmp;
-        a.vals_in = vals_in;
-        a.vals_out = vals_out;
-        a.vals_tmp = vals_tmp;
-        a.n = (uint32_t)n;
-        a.shift = (uint32_t)begin_bit + 8u * d;
-        a.mask = (1u << std::min(8u, (uint32_t)end_bit - a.shift)) - 1u;
-        a.round = d;
-        a.ntiles = L.ntiles;
-        a.bases = bases;
-        a.plan = plan;
-        a.counts = counts;
-        a.blk_state = blk_state;
-        a.tickets = tickets;
-        a.err = dev_err;
-        a.tiles = nullptr;
-        a.ntiles_dev = nullptr;
-        if (prof) profiler_mark(prof, stream, kKindCount, true);
-        hipLaunchKernelGGL((k_count<K, WG, ITEMS>), dim3(L.ntiles), dim3(WG), 0, stream, a);
-        if (prof) profiler_mark(prof, stream, kKindCount, false);
+        const RoundArgs a = round_args(keys_in, keys_out, keys_tmp, vals_in, vals_out, vals_tmp, n,
+                                       begin_bit, end_bit, d, L, bases, plan, counts, blk_state,
+                                       tickets, dev_err);
+        if (d > 0) {   // round 0 was counted with the histograms
+            if (prof) profiler_mark(prof, stream, kKindCount, true);
+            hipLaunchKernelGGL((k_count<K, WG, ITEMS, false>), dim3(L.ntiles), dim3(WG), 0, stream,
+                               a, nullptr);
+            if (prof) profiler_mark(prof, stream, kKindCount, false);
+        }
         if (prof) profiler_mark(prof, stream, kKindTileScan, true);
         hipLaunchKernelGGL(k_tilescan, dim3(nblk), dim3(R), 0, stream, a);
         if (prof) profiler_mark(prof, stream, kKindTileScan, false);
