@@ -38,6 +38,11 @@ constexpr uint32_t kNoTile = 0xFFFFFFFFu;
 #ifndef RSORT_SCATTER_PERSIST
 #define RSORT_SCATTER_PERSIST 0
 #endif
+// Lanes per ranking group of the scatter: 32 (64-bit slots {lane set, count})
+// or 16 (32-bit slots count << 16 | lane set).
+#ifndef RSORT_RANK_GROUP
+#define RSORT_RANK_GROUP 32
+#endif
 // Scatter ranking order: 1 = rank, then bases; 0 = count, bases, then rank;
 // -1 = rank first with payloads, count first without (the faster of each).
 #ifndef RSORT_RANK_FIRST
@@ -52,20 +57,32 @@ constexpr uint32_t kNoTile = 0xFFFFFFFFu;
 #endif
 // Tiles per block of the tile scan, and predecessor blocks read per look-back step.
 #ifndef RSORT_SCAN_BLOCK
-#define RSORT_SCAN_BLOCK 32
+#define RSORT_SCAN_BLOCK 64
 #endif
 #ifndef LB_WINDOW
 #define LB_WINDOW 4
 #endif
 
+// Count kernel workgroup size (same tile, ITEMS = tile / CWG) and whether full
+// tiles are read with 16-byte loads.
+#ifndef RSORT_COUNT_WG
+#define RSORT_COUNT_WG 512
+#endif
+#ifndef RSORT_COUNT_VEC
+#define RSORT_COUNT_VEC 1
+#endif
 template <typename K> struct R8Config;
 template <> struct R8Config<uint32_t> {
     static constexpr int WG = RSORT_R8_WG32;
     static constexpr int ITEMS = RSORT_R8_ITEMS32;
+    static constexpr int CWG = RSORT_COUNT_WG;
+    static constexpr int CITEMS = WG * ITEMS / CWG;
 };
 template <> struct R8Config<uint64_t> {
     static constexpr int WG = RSORT_R8_WG64;
     static constexpr int ITEMS = RSORT_R8_ITEMS64;
+    static constexpr int CWG = RSORT_COUNT_WG;
+    static constexpr int CITEMS = WG * ITEMS / CWG;
 };
 
 constexpr int kHistWG = 256;
@@ -369,7 +386,7 @@ __global__ __launch_bounds__(WG) void k_count(RoundArgs a, uint32_t* mixed)
     const K ref = ALL ? ((const K*)a.keys_in)[0] : K(0);
     K acc = 0;
     K k[ITEMS];
-    const bool vec = !a.tiles && lim == TILE && ((uintptr_t)src & 15) == 0;
+    const bool vec = RSORT_COUNT_VEC && !a.tiles && lim == TILE && ((uintptr_t)src & 15) == 0;
     if (vec) {
 #pragma unroll
         for (int q = 0; q < ITEMS / VEC; ++q) {
@@ -533,13 +550,17 @@ __global__ __launch_bounds__(R) void k_tilescan(RoundArgs a)
 template <typename K, bool KV, int WG, int ITEMS>
 __global__ __launch_bounds__(WG, KV ? RSORT_R8_WAVES_PER_EU_KV : RSORT_R8_WAVES_PER_EU) void k_scatter(RoundArgs a)
 {
-    constexpr int HW = WG / 32;                 // half-waves
+    constexpr int G = RSORT_RANK_GROUP;         // lanes per ranking group
+    constexpr int NG = WG / G;                  // ranking groups
     constexpr uint32_t TILE = (uint32_t)WG * ITEMS;
     constexpr bool rank_first = RSORT_RANK_FIRST < 0 ? KV : RSORT_RANK_FIRST != 0;
-    static_assert(TILE * sizeof(K) >= HW * R * sizeof(uint2), "staging must cover the slots");
+    static_assert(G == 16 || G == 32, "ranking groups of 16 or 32 lanes");
+    static_assert(G == 32 || (uint64_t)TILE < 65536, "16-bit slot counts");
+    static_assert(TILE * sizeof(K) >= NG * R * (G == 32 ? 8 : 4), "staging must cover the slots");
     struct Smem {
         union {
-            uint2 slot[HW][R];           // {lane set, count}, then {-, slot base}
+            uint2 slot[NG][R];           // 32-lane groups: {lane set, count}, then {-, slot base}
+            uint32_t slot16[NG][R];      // 16-lane groups: count << 16 | lane set
             K keys[TILE];                // staging: the tile in digit order
             uint32_t vals[TILE];         // staging of the payloads (second pass)
         } u;
@@ -554,9 +575,9 @@ __global__ __launch_bounds__(WG, KV ? RSORT_R8_WAVES_PER_EU_KV : RSORT_R8_WAVES_
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63;
     const uint32_t wave = tid >> 6;
-    const uint32_t hw = tid >> 5;
-    const uint32_t hl = tid & 31;
-    const uint32_t hofs = hw * ITEMS * 32 + hl;
+    const uint32_t grp = tid / G;
+    const uint32_t gl = tid % G;
+    const uint32_t hofs = grp * ITEMS * G + gl;   // position of row 0 of this lane
     const K* src = pick<K>(pl.src, (const K*)a.keys_in, (K*)a.keys_out, (K*)a.keys_tmp);
     const uint32_t* vsrc = KV ? pick<uint32_t>(pl.src, a.vals_in, a.vals_out, a.vals_tmp) : nullptr;
     K* dst = pick<K>(pl.dst, (const K*)a.keys_in, (K*)a.keys_out, (K*)a.keys_tmp);
@@ -575,7 +596,7 @@ __global__ __launch_bounds__(WG, KV ? RSORT_R8_WAVES_PER_EU_KV : RSORT_R8_WAVES_
         const uint32_t lim = tr.y;
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
-            const uint32_t o = hofs + i * 32;
+            const uint32_t o = hofs + i * G;
             kk[i] = o < lim ? src[base + o] : K(0);
             if (KV) vv[i] = o < lim ? vsrc[base + o] : 0u;
         }
@@ -587,8 +608,9 @@ __global__ __launch_bounds__(WG, KV ? RSORT_R8_WAVES_PER_EU_KV : RSORT_R8_WAVES_
     auto process = [&](uint32_t tile, K (&k)[ITEMS], uint32_t (&v)[ITEMS], uint32_t tn,
                        K (&kn)[ITEMS], uint32_t (&vn)[ITEMS]) {
         const uint32_t lim = tile_range(a, tile, TILE).y;   // keys in this tile
-        for (uint32_t i = tid; i < HW * R / 2; i += WG)
-            ((uint4*)&sm.u.slot[0][0])[i] = make_uint4(0, 0, 0, 0);
+        constexpr uint32_t slot_u4 = NG * R * (G == 32 ? 8 : 4) / 16;
+        for (uint32_t i = tid; i < slot_u4; i += WG)
+            ((uint4*)&sm.u)[i] = make_uint4(0, 0, 0, 0);
         uint32_t toff = 0;
         if (tid < R) {
             toff = a.counts[(size_t)tile * R + tid];
@@ -596,40 +618,72 @@ __global__ __launch_bounds__(WG, KV ? RSORT_R8_WAVES_PER_EU_KV : RSORT_R8_WAVES_
         }
         __syncthreads();
 
-        // Rank row by row; the high word of a slot is advanced by the lanes of
-        // the row that hold its digit.  Gives each key's rank plus the word's
-        // value before the key's row.
+        // Rank row by row; a slot's count is advanced by the lanes of the row
+        // that hold its digit.  Gives each key's rank plus the count before
+        // the key's row.
         uint32_t pos[ITEMS];
         auto rank = [&]() {
-            uint2* sl = sm.u.slot[hw];
-            const uint32_t bit = 1u << hl;
-            const uint32_t lowsel = lane < 32 ? ~0u : 0u;
+            const uint32_t bit = 1u << gl;
+            if constexpr (G == 32) {
+                uint2* sl = sm.u.slot[grp];
+                const uint32_t lowsel = lane < 32 ? ~0u : 0u;
 #pragma unroll
-            for (int i = 0; i < ITEMS; ++i) {
-                const bool ok = hofs + i * 32 < lim;
-                const uint32_t d = digit_of(k[i], a.shift, a.mask);
-                if (ok) __hip_atomic_fetch_or(&sl[d].x, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                wave_lds_order();
-                const uint64_t s = ok ? __hip_atomic_load((uint64_t*)&sl[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : 0ull;
-                const uint32_t m = (uint32_t)s, c = (uint32_t)(s >> 32);
-                pos[i] = __builtin_amdgcn_mbcnt_hi(m, __builtin_amdgcn_mbcnt_lo(m & lowsel, c));
-                wave_lds_order();
-                if (ok)
-                    __hip_atomic_store((uint64_t*)&sl[d], (uint64_t)(c + __builtin_popcount(m)) << 32,
-                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                wave_lds_order();
+                for (int i = 0; i < ITEMS; ++i) {
+                    const bool ok = hofs + i * G < lim;
+                    const uint32_t d = digit_of(k[i], a.shift, a.mask);
+                    if (ok) __hip_atomic_fetch_or(&sl[d].x, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    wave_lds_order();
+                    const uint64_t s = ok ? __hip_atomic_load((uint64_t*)&sl[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : 0ull;
+                    const uint32_t m = (uint32_t)s, c = (uint32_t)(s >> 32);
+                    pos[i] = __builtin_amdgcn_mbcnt_hi(m, __builtin_amdgcn_mbcnt_lo(m & lowsel, c));
+                    wave_lds_order();
+                    if (ok)
+                        __hip_atomic_store((uint64_t*)&sl[d], (uint64_t)(c + __builtin_popcount(m)) << 32,
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    wave_lds_order();
+                }
+            } else {
+                uint32_t* sl = sm.u.slot16[grp];
+                const uint32_t below = bit - 1u;
+#pragma unroll
+                for (int i = 0; i < ITEMS; ++i) {
+                    const bool ok = hofs + i * G < lim;
+                    const uint32_t d = digit_of(k[i], a.shift, a.mask);
+                    if (ok) __hip_atomic_fetch_or(&sl[d], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    wave_lds_order();
+                    const uint32_t s = ok ? __hip_atomic_load(&sl[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : 0u;
+                    const uint32_t c = s >> 16;
+                    pos[i] = c + __builtin_popcount(s & below);
+                    wave_lds_order();
+                    if (ok)
+                        __hip_atomic_store(&sl[d], (c + __builtin_popcount(s & 0xFFFFu)) << 16,
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    wave_lds_order();
+                }
             }
+        };
+        auto slot_count = [&](int g, uint32_t v) -> uint32_t {
+            if constexpr (G == 32) return sm.u.slot[g][v].y;
+            else return sm.u.slot16[g][v] >> 16;
+        };
+        auto set_slot_count = [&](int g, uint32_t v, uint32_t c) {
+            if constexpr (G == 32) sm.u.slot[g][v].y = c;
+            else sm.u.slot16[g][v] = c << 16;
         };
 
         if (rank_first) {
             // rank with counts starting at zero; the counts end up in the slots
             rank();
         } else {
-            // count first: the slots' high words get the per-half-wave counts
-            uint2* sl = sm.u.slot[hw];
+            // count first: the slots' counts get the per-group digit counts
 #pragma unroll
-            for (int i = 0; i < ITEMS; ++i)
-                if (hofs + i * 32 < lim) atomicAdd(&sl[digit_of(k[i], a.shift, a.mask)].y, 1u);
+            for (int i = 0; i < ITEMS; ++i) {
+                if (hofs + i * G < lim) {
+                    const uint32_t d = digit_of(k[i], a.shift, a.mask);
+                    if constexpr (G == 32) atomicAdd(&sm.u.slot[grp][d].y, 1u);
+                    else atomicAdd(&sm.u.slot16[grp][d], 1u << 16);
+                }
+            }
         }
         if (RSORT_SCATTER_PERSIST && tn != kNoTile) load(tn, kn, vn);
         __syncthreads();
@@ -639,7 +693,7 @@ __global__ __launch_bounds__(WG, KV ? RSORT_R8_WAVES_PER_EU_KV : RSORT_R8_WAVES_
         if (tid < R) {
             uint32_t total = 0;
 #pragma unroll
-            for (int h = 0; h < HW; ++h) total += sm.u.slot[h][tid].y;
+            for (int g = 0; g < NG; ++g) total += slot_count(g, tid);
             const uint32_t incl = wave_inclusive_sum(total);
             if (lane == 63) sm.wsum[wave] = incl;
             run = incl - total;
@@ -649,9 +703,9 @@ __global__ __launch_bounds__(WG, KV ? RSORT_R8_WAVES_PER_EU_KV : RSORT_R8_WAVES_
             for (uint32_t w = 0; w < wave; ++w) run += sm.wsum[w];
             sm.goff[tid] = toff - run;
 #pragma unroll
-            for (int h = 0; h < HW; ++h) {
-                const uint32_t c = sm.u.slot[h][tid].y;
-                sm.u.slot[h][tid].y = run;
+            for (int g = 0; g < NG; ++g) {
+                const uint32_t c = slot_count(g, tid);
+                set_slot_count(g, tid, run);
                 run += c;
             }
         }
@@ -662,17 +716,17 @@ __global__ __launch_bounds__(WG, KV ? RSORT_R8_WAVES_PER_EU_KV : RSORT_R8_WAVES_
                 // Recompute the digit here rather than keep 16 slot addresses
                 // alive across the bases phase (registers limit occupancy).
                 __asm__ volatile("" : "+v"(k[i]));
-                pos[i] += sm.u.slot[hw][digit_of(k[i], a.shift, a.mask)].y;
+                pos[i] += slot_count(grp, digit_of(k[i], a.shift, a.mask));
             }
         } else {
-            rank();   // the high words now start at the slot bases
+            rank();   // the counts now start at the slot bases
         }
         __syncthreads();
 
         // scatter
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i)
-            if (hofs + i * 32 < lim) sm.u.keys[pos[i]] = k[i];
+            if (hofs + i * G < lim) sm.u.keys[pos[i]] = k[i];
         __syncthreads();
         uint32_t outi[KV ? ITEMS : 1];
 #pragma unroll
@@ -690,7 +744,7 @@ __global__ __launch_bounds__(WG, KV ? RSORT_R8_WAVES_PER_EU_KV : RSORT_R8_WAVES_
             __syncthreads();
 #pragma unroll
             for (int i = 0; i < ITEMS; ++i)
-                if (hofs + i * 32 < lim) sm.u.vals[pos[i]] = v[i];
+                if (hofs + i * G < lim) sm.u.vals[pos[i]] = v[i];
             __syncthreads();
 #pragma unroll
             for (int i = 0; i < ITEMS; ++i) {
@@ -705,17 +759,17 @@ __global__ __launch_bounds__(WG, KV ? RSORT_R8_WAVES_PER_EU_KV : RSORT_R8_WAVES_
     // each workgroup loops.  When both counts are multiples of 8 every XCD owns
     // a contiguous eighth of the tiles (blocks are dealt to XCDs in turn), so
     // neighbouring tiles write their shared cache lines through the same L2.
-    const uint32_t b = blockIdx.x, G = gridDim.x;
+    const uint32_t b = blockIdx.x, nb = gridDim.x;
     const uint32_t ntiles = a.ntiles_dev ? *a.ntiles_dev : a.ntiles;
-    const bool xcd = !a.ntiles_dev && (a.ntiles & 7) == 0 && (G & 7) == 0;
-    const uint32_t per = a.ntiles >> 3, g8 = G >> 3, x = b & 7;
+    const bool xcd = !a.ntiles_dev && (a.ntiles & 7) == 0 && (nb & 7) == 0;
+    const uint32_t per = a.ntiles >> 3, g8 = nb >> 3, x = b & 7;
     uint32_t tile = xcd ? x * per + (b >> 3) : b;
     auto next_of = [&](uint32_t t) -> uint32_t {
         if (xcd) {
             const uint32_t l = t - x * per + g8;
             return l < per ? x * per + l : kNoTile;
         }
-        return t + G < ntiles ? t + G : kNoTile;
+        return t + nb < ntiles ? t + nb : kNoTile;
     };
     if (tile >= ntiles) return;
 

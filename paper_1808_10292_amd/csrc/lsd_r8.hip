@@ -142,7 +142,7 @@ hipError_t run(const void* keys_in, void* keys_out, const uint32_t* vals_in, uin
                                   begin_bit, end_bit, 0, L, bases, plan, counts, blk_state,
                                   tickets, dev_err);
         if (prof) profiler_mark(prof, stream, kKindHist, true);
-        hipLaunchKernelGGL((k_count<K, WG, ITEMS, true>), dim3(L.ntiles), dim3(WG), 0, stream, a0,
+        hipLaunchKernelGGL((k_count<K, R8Config<K>::CWG, R8Config<K>::CITEMS, true>), dim3(L.ntiles), dim3(R8Config<K>::CWG), 0, stream, a0,
                            mixed);
         if (prof) profiler_mark(prof, stream, kKindHist, false);
     }
@@ -166,7 +166,7 @@ hipError_t run(const void* keys_in, void* keys_out, const uint32_t* vals_in, uin
                                        tickets, dev_err);
         if (d > 0) {   // round 0 was counted with the histograms
             if (prof) profiler_mark(prof, stream, kKindCount, true);
-            hipLaunchKernelGGL((k_count<K, WG, ITEMS, false>), dim3(L.ntiles), dim3(WG), 0, stream,
+            hipLaunchKernelGGL((k_count<K, R8Config<K>::CWG, R8Config<K>::CITEMS, false>), dim3(L.ntiles), dim3(R8Config<K>::CWG), 0, stream,
                                a, nullptr);
             if (prof) profiler_mark(prof, stream, kKindCount, false);
         }

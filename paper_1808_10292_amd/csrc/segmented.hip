@@ -270,7 +270,7 @@ hipError_t run_segmented(const void* keys_in, void* keys_out, const uint32_t* va
         a.tiles = tiles;
         a.ntiles_dev = nullptr;
         if (prof) profiler_mark(prof, stream, kKindCount, true);
-        hipLaunchKernelGGL((k_count<K, WG, ITEMS, false>), dim3(nt), dim3(WG), 0, stream, a, nullptr);
+        hipLaunchKernelGGL((k_count<K, R8Config<K>::CWG, R8Config<K>::CITEMS, false>), dim3(nt), dim3(R8Config<K>::CWG), 0, stream, a, nullptr);
         if (prof) profiler_mark(prof, stream, kKindCount, false);
         if (prof) profiler_mark(prof, stream, kKindTileScan, true);
         hipLaunchKernelGGL(k_segscan, dim3((uint32_t)P.lsegs.size()), dim3(R), 0, stream, a, lsegs);
@@ -425,7 +425,7 @@ hipError_t run_devseg(const void* keys_in, void* keys_out, const uint32_t* vals_
         a.tiles = tiles;
         a.ntiles_dev = ntiles;
         if (prof) profiler_mark(prof, stream, kKindCount, true);
-        hipLaunchKernelGGL((k_count<K, WG, ITEMS, false>), dim3(L.max_tiles), dim3(WG), 0, stream, a, nullptr);
+        hipLaunchKernelGGL((k_count<K, R8Config<K>::CWG, R8Config<K>::CITEMS, false>), dim3(L.max_tiles), dim3(R8Config<K>::CWG), 0, stream, a, nullptr);
         if (prof) profiler_mark(prof, stream, kKindCount, false);
         if (prof) profiler_mark(prof, stream, kKindTileScan, true);
         hipLaunchKernelGGL(k_segscan, dim3(nseg), dim3(R), 0, stream, a, (const uint4*)lsegs);
