@@ -371,13 +371,9 @@ __global__ __launch_bounds__(WG) void k_count(RoundArgs a, uint32_t* mixed)
     for (uint32_t i = tid; i < R * 32 / 4; i += WG) ((uint4*)h)[i] = make_uint4(0, 0, 0, 0);
     if (ALL && tid < 2) mix_s[tid] = 0;
     __syncthreads();
-    uint32_t tile;
-    if (a.ntiles_dev) {
-        tile = blockIdx.x;
-        if (tile >= *a.ntiles_dev) return;
-    } else {
-        tile = xcd_tile(a.ntiles);
-    }
+    // with a device-side tile count the grid (a.ntiles) is an upper bound
+    const uint32_t tile = xcd_tile(a.ntiles);
+    if (a.ntiles_dev && tile >= *a.ntiles_dev) return;
     const uint2 tr = tile_range(a, tile, TILE);
     const uint32_t base = tr.x;
     const uint32_t lim = tr.y;
@@ -761,7 +757,7 @@ __global__ __launch_bounds__(WG, KV ? RSORT_R8_WAVES_PER_EU_KV : RSORT_R8_WAVES_
     // neighbouring tiles write their shared cache lines through the same L2.
     const uint32_t b = blockIdx.x, nb = gridDim.x;
     const uint32_t ntiles = a.ntiles_dev ? *a.ntiles_dev : a.ntiles;
-    const bool xcd = !a.ntiles_dev && (a.ntiles & 7) == 0 && (nb & 7) == 0;
+    const bool xcd = (a.ntiles & 7) == 0 && (nb & 7) == 0;
     const uint32_t per = a.ntiles >> 3, g8 = nb >> 3, x = b & 7;
     uint32_t tile = xcd ? x * per + (b >> 3) : b;
     auto next_of = [&](uint32_t t) -> uint32_t {

@@ -9,8 +9,8 @@
 //            count one half of the digit range (32768 LDS counters, 128 KiB);
 //   prefix   rows[w][v] becomes the output index of chunk w's first key of
 //            digit v: sum over all digits u < v of their totals plus the
-//            counts of v in chunks before w (column sums, a scan of the 65536
-//            totals, column prefixes);
+//            counts of v in chunks before w (column sums scanned in blocks of
+//            256 digits, a scan of the block totals, column prefixes);
 //   place    k_scatter16: workgroup w walks its chunk in order, tile by tile.
 //            Each tile is stable-sorted by the 16-bit digit in LDS (two 8-bit
 //            counting sub-rounds), every key goes to rows[w][v] + its rank in
@@ -83,51 +83,56 @@ __global__ __launch_bounds__(kRowsWG) void k_rows16(const K* __restrict__ keys, 
     for (uint32_t b = tid; b < hb; b += kRowsWG) row[b] = cnt[b];
 }
 
-// tot[v] = sum over the chunks of rows[w][v].
+// Column sums and their exclusive scan, in two levels: workgroup b sums the
+// columns v in [256 b, 256 b + 256) over the chunks, scans them inside the
+// block (excl[v]) and writes the block total; k_blockscan16 scans the block
+// totals; k_colprefix16 adds them up.
 __global__ __launch_bounds__(256) void k_colsum16(const uint32_t* rows, uint32_t nchunks,
-                                                  uint32_t nbins, uint32_t* tot)
+                                                  uint32_t nbins, uint32_t* excl,
+                                                  uint32_t* block_total)
 {
+    __shared__ uint32_t wsum[4];
     const uint32_t v = blockIdx.x * 256 + threadIdx.x;
-    if (v >= nbins) return;
-    uint32_t s = 0, w = 0;
-    for (; w + 4 <= nchunks; w += 4)
-        s += rows[(size_t)w * kR16 + v] + rows[(size_t)(w + 1) * kR16 + v] +
-             rows[(size_t)(w + 2) * kR16 + v] + rows[(size_t)(w + 3) * kR16 + v];
-    for (; w < nchunks; ++w) s += rows[(size_t)w * kR16 + v];
-    tot[v] = s;
-}
-
-// In-place exclusive scan of tot[0..nbins) (nbins <= 65536) by one workgroup:
-// thread t owns 64 consecutive digits.
-__global__ __launch_bounds__(1024) void k_totscan16(uint32_t* tot, uint32_t nbins)
-{
-    __shared__ uint32_t wsum[16];
-    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint32_t v0 = tid * 64;
     uint32_t s = 0;
-    for (uint32_t j = 0; j < 64; ++j)
-        if (v0 + j < nbins) s += tot[v0 + j];
+    if (v < nbins) {
+        uint32_t w = 0;
+        for (; w + 4 <= nchunks; w += 4)
+            s += rows[(size_t)w * kR16 + v] + rows[(size_t)(w + 1) * kR16 + v] +
+                 rows[(size_t)(w + 2) * kR16 + v] + rows[(size_t)(w + 3) * kR16 + v];
+        for (; w < nchunks; ++w) s += rows[(size_t)w * kR16 + v];
+    }
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t incl = wave_inclusive_sum(s);
     if (lane == 63) wsum[wave] = incl;
     __syncthreads();
-    uint32_t run = incl - s;
-    for (uint32_t w = 0; w < wave; ++w) run += wsum[w];
-    for (uint32_t j = 0; j < 64; ++j) {
-        if (v0 + j < nbins) {
-            const uint32_t c = tot[v0 + j];
-            tot[v0 + j] = run;
-            run += c;
-        }
-    }
+    uint32_t before = 0;
+    for (uint32_t q = 0; q < wave; ++q) before += wsum[q];
+    if (v < nbins) excl[v] = before + incl - s;
+    if (threadIdx.x == 255) block_total[blockIdx.x] = before + incl;
 }
 
-// rows[w][v] = tot[v] (the digit's start) + sum over chunks w' < w of rows[w'][v].
+// Exclusive scan of the (at most 256) block totals, in place.
+__global__ __launch_bounds__(256) void k_blockscan16(uint32_t* block_total, uint32_t nblocks)
+{
+    __shared__ uint32_t wsum[4];
+    const uint32_t t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const uint32_t x = t < nblocks ? block_total[t] : 0u;
+    const uint32_t incl = wave_inclusive_sum(x);
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0;
+    for (uint32_t q = 0; q < wave; ++q) before += wsum[q];
+    if (t < nblocks) block_total[t] = before + incl - x;
+}
+
+// rows[w][v] = (digit v's start) + sum over chunks w' < w of rows[w'][v].
 __global__ __launch_bounds__(256) void k_colprefix16(uint32_t* rows, uint32_t nchunks,
-                                                     uint32_t nbins, const uint32_t* start)
+                                                     uint32_t nbins, const uint32_t* excl,
+                                                     const uint32_t* block_pre)
 {
     const uint32_t v = blockIdx.x * 256 + threadIdx.x;
     if (v >= nbins) return;
-    uint32_t run = start[v];
+    uint32_t run = block_pre[blockIdx.x] + excl[v];
     for (uint32_t w = 0; w < nchunks; ++w) {
         uint32_t* p = rows + (size_t)w * kR16 + v;
         const uint32_t c = *p;
@@ -228,7 +233,7 @@ __global__ __launch_bounds__(R16Config<K>::WG) void k_scatter16(
             const uint32_t pd = i == 0 ? dprev : dg[i - 1];
             if (o < len && (o == 0 || pd != dg[i])) cur = o;
             rank[i] = o - cur;
-            base[i] = o < len ? ld_agent(&row[dg[i]]) : 0u;
+            base[i] = o < len ? __hip_atomic_load(&row[dg[i]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : 0u;
         }
         __syncthreads();   // every read of the row precedes its updates
 #pragma unroll
@@ -241,11 +246,11 @@ __global__ __launch_bounds__(R16Config<K>::WG) void k_scatter16(
                     if (KV) vals_out[d] = vv[i];
                 }
                 const uint32_t nd = i + 1 < ITEMS ? dg[i + 1] : dnext;
-                if (o + 1 == len || nd != dg[i]) st_agent(&row[dg[i]], d + 1);
+                if (o + 1 == len || nd != dg[i])
+                    __hip_atomic_store(&row[dg[i]], d + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             }
         }
-        __threadfence();
-        __syncthreads();
+        __syncthreads();   // the row is this workgroup's alone: workgroup scope suffices
     }
 }
 
@@ -292,10 +297,13 @@ hipError_t run16(const void* keys_in, void* keys_out, const uint32_t* vals_in, u
                            src, (uint32_t)n, L.chunk, shift, mask, rows);
         if (prof) profiler_mark(prof, stream, kKindCount, false);
         if (prof) profiler_mark(prof, stream, kKindTileScan, true);
-        const dim3 cg((nbins + 255) / 256);
-        hipLaunchKernelGGL(k_colsum16, cg, dim3(256), 0, stream, (const uint32_t*)rows, L.nchunks, nbins, tot);
-        hipLaunchKernelGGL(k_totscan16, dim3(1), dim3(1024), 0, stream, tot, nbins);
-        hipLaunchKernelGGL(k_colprefix16, cg, dim3(256), 0, stream, rows, L.nchunks, nbins, (const uint32_t*)tot);
+        const uint32_t nb = (nbins + 255) / 256;
+        uint32_t* btot = tot + kR16;
+        hipLaunchKernelGGL(k_colsum16, dim3(nb), dim3(256), 0, stream, (const uint32_t*)rows, L.nchunks,
+                           nbins, tot, btot);
+        hipLaunchKernelGGL(k_blockscan16, dim3(1), dim3(256), 0, stream, btot, nb);
+        hipLaunchKernelGGL(k_colprefix16, dim3(nb), dim3(256), 0, stream, rows, L.nchunks, nbins,
+                           (const uint32_t*)tot, (const uint32_t*)btot);
         if (prof) profiler_mark(prof, stream, kKindTileScan, false);
         if (prof) profiler_mark(prof, stream, kKindRound, true);
         hipLaunchKernelGGL((k_scatter16<K, KV>), dim3(L.nchunks), dim3(R16Config<K>::WG), 0, stream,
@@ -322,7 +330,7 @@ LsdR16Layout lsd_r16_layout(int key_bytes, bool has_vals, size_t n, int begin_bi
     L.off_tmp_keys = o;  o = align_up(o + n * key_bytes);
     L.off_tmp_vals = o;  o = align_up(o + (has_vals ? n * 4 : 0));
     L.off_rows = o;      o = align_up(o + (size_t)L.nchunks * kR16 * 4);
-    L.off_tot = o;       o = align_up(o + (size_t)kR16 * 4);
+    L.off_tot = o;       o = align_up(o + (size_t)(kR16 + 256) * 4);
     L.bytes = o;
     return L;
 }

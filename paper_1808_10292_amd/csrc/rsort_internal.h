@@ -98,7 +98,7 @@ hipError_t segmented_sort(int key_bytes, const void* keys_in, void* keys_out,
 // Device-planned segmented sort: offsets (nseg + 1 u32, nondecreasing) live in
 // device memory.  ws must hold devseg_layout(...).bytes bytes.
 struct DevSegLayout {
-    uint32_t max_tiles;   // upper bound of the tile count: ceil(n / tile) + nseg
+    uint32_t max_tiles;   // upper bound of the tile count: ceil(n / tile) + nseg, rounded up to 8
     size_t off_tmp_keys, off_tmp_vals, off_counts, off_plan, off_small, off_tiles, off_lsegs,
         off_ntiles;
     size_t bytes;

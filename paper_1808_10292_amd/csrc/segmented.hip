@@ -443,7 +443,7 @@ DevSegLayout devseg_layout(int key_bytes, bool has_vals, size_t n, uint32_t nseg
 {
     DevSegLayout L;
     const uint32_t tile = large_tile(key_bytes);
-    L.max_tiles = (uint32_t)((n + tile - 1) / tile) + nseg;
+    L.max_tiles = ((uint32_t)((n + tile - 1) / tile) + nseg + 7) & ~7u;   // multiple of 8: XCD slices
     size_t o = 0;
     L.off_tmp_keys = o;  o = align_up(o + n * key_bytes);
     L.off_tmp_vals = o;  o = align_up(o + (has_vals ? n * 4 : 0));
