@@ -23,8 +23,10 @@ Printed as one JSON line:
                sort per array, latency p50/p99, graph replay
   kv           2^28 key-value pairs per key distribution: PR4 vs the
                regular-oversampling sample sort (GSD, p = 256, r = 32)
-  serve        Poisson stream of mixed-size uint32/uint64 requests through
-               the continuous-batching server: p50/p99 latency, keys/s
+  small        2^20 keys uniform in [0, 2^31): per-call latency p50/p99
+  serve        Poisson streams (rho = 0.5, 0.8 of the plain-launch capacity) of
+               mixed-size uint32/uint64 requests through the continuous-
+               batching server: p50/p99 latency, keys/s, alone == in the mix
 """
 import argparse
 import hashlib
@@ -140,13 +142,22 @@ def bench_batched(rsort, torch, np, keygen, args):
             "check": "segments sorted (sampled)" if ok else "FAILED"}
 
 
+def identity_rounds(np, keys, digit_bits=8):
+    """Rounds whose digit is the same for every key (skipped by the sort)."""
+    diff = np.bitwise_or.reduce(keys ^ keys[0]) if keys.size else 0
+    width = keys.dtype.itemsize * 8
+    return [d for d in range(width // digit_bits)
+            if (int(diff) >> (digit_bits * d)) & ((1 << digit_bits) - 1) == 0]
+
+
 def bench_kv(rsort, torch, np, keygen, args):
     """Key-value sort, radix (PR4) against the regular-oversampling sample sort
     (GSD, p = 256 buckets, oversampling factor r = 32): 2^28 pairs by default
     (uint32 key, uint32 payload = input index) per key distribution."""
     n = 1 << args.kv_log2n
     res = {"workload": "2^%d (uint32 key, uint32 payload = input index) pairs; PR4 vs GSD "
-                       "p=256 r=32" % args.kv_log2n, "n": n}
+                       "p=256 r=32" % args.kv_log2n, "n": n,
+           "algorithmic_bytes_per_pass": 2 * n * 8}
     dv = torch.arange(n, dtype=torch.int32, device="cuda")
     ko = torch.empty(n, dtype=torch.uint32, device="cuda")
     vo = torch.empty_like(dv)
@@ -155,6 +166,7 @@ def bench_kv(rsort, torch, np, keygen, args):
         log("kv %s: generating %d keys" % (dist, n))
         keys = keygen.kv_keys(dist, n)
         dk = torch.from_numpy(keys).cuda()
+        skipped = identity_rounds(np, keys)
         row = {}
         for algo in ("lsd8", "sample"):
             fn = (lambda: rsort.rsort_sort(dk, ko, dv, vo, algo="lsd8")) if algo == "lsd8" else \
@@ -170,6 +182,11 @@ def bench_kv(rsort, torch, np, keygen, args):
             ok = ok and bool(np.all(head[1:] >= head[:-1]))
             row[algo] = {"ms": round(sec * 1e3, 3), "gkeys_per_s": round(n / sec / 1e9, 3),
                          "check": "sampled ok" if ok else "FAILED"}
+        executed = 4 - len(skipped)
+        row["lsd8"]["rounds_executed"] = executed
+        if executed:
+            row["lsd8"]["gbps_per_executed_pass"] = round(
+                2 * n * 8 * executed / (row["lsd8"]["ms"] * 1e-3) / 1e9, 1)
         st = rsort.rsort_sample_sort_stats()
         row["sample"]["max_bucket"] = int(st["bucket"].max())
         row["sample"]["lemma1_bound"] = round((1 + 1 / 32) * n / 256 + 32 * 256, 1)
@@ -178,64 +195,184 @@ def bench_kv(rsort, torch, np, keygen, args):
     return res
 
 
+def bench_small(rsort, torch, np, keygen, args):
+    """The small single-array sort: 2^20 keys uniform in [0, 2^31), keys only,
+    PR4; per-call latency (launch to completion, one call at a time)."""
+    n = 1 << 20
+    keys = keygen.uniform_u31(n, keygen.SEED_SMALL)
+    dk = torch.from_numpy(keys).cuda()
+    out = torch.empty_like(dk)
+    for _ in range(5):
+        rsort.rsort_sort(dk, out)
+    torch.cuda.synchronize()
+    lat = []
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    for _ in range(max(50, args.steps)):
+        ev[0].record()
+        rsort.rsort_sort(dk, out)
+        ev[1].record()
+        ev[1].synchronize()
+        lat.append(ev[0].elapsed_time(ev[1]) * 1e3)
+    lat = np.array(lat)
+    ok = bool(np.all(np.diff(out.cpu().numpy().astype(np.int64)) >= 0))
+    # the same sort captured once in a HIP graph and replayed (no per-kernel host launches)
+    need = rsort.rsort_workspace_bytes(torch.uint32, False, n)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    rsort.rsort_sort(dk, out, workspace=ws)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        rsort.rsort_sort(dk, out, workspace=ws)
+    glat = []
+    for _ in range(max(50, args.steps)):
+        ev[0].record()
+        g.replay()
+        ev[1].record()
+        ev[1].synchronize()
+        glat.append(ev[0].elapsed_time(ev[1]) * 1e3)
+    glat = np.array(glat)
+    ok = ok and bool(np.all(np.diff(out.cpu().numpy().astype(np.int64)) >= 0))
+    res = {"workload": "2^20 keys uniform in [0, 2^31), keys only, PR4", "runs": int(lat.size),
+           "us_p50": round(float(np.percentile(lat, 50)), 1),
+           "us_p99": round(float(np.percentile(lat, 99)), 1),
+           "gkeys_per_s_p50": round(n / (np.percentile(lat, 50) * 1e-6) / 1e9, 3),
+           "graph_us_p50": round(float(np.percentile(glat, 50)), 1),
+           "graph_us_p99": round(float(np.percentile(glat, 99)), 1),
+           "check": "sorted" if ok else "FAILED"}
+    if args.cpu_seconds > 0:
+        import oracle
+        t0 = time.perf_counter()
+        oracle.sr4(keys)
+        res["oracle_ms"] = round((time.perf_counter() - t0) * 1e3, 2)
+    return res
+
+
 def bench_serve(rsort, torch, np, keygen, args):
-    """Served sorting: a Poisson stream of requests at a fixed rate, sizes
-    log-uniform in [2^10, 2^26] keys, key type 50% uint32 / 50% uint64 (uniform
-    full range), admitted under a 64 GB HBM cap onto 4 streams and batched on
-    arrival.  Latency = submit to completion seen by the server."""
-    num, rate = args.serve_requests, args.serve_rate
-    sizes = keygen.log_uniform_sizes(num, keygen.SEED_SERVE)
-    kinds = keygen.unit_doubles(keygen.SEED_SERVE + 1, num) < 0.5     # True: uint32
-    arrivals = keygen.poisson_arrivals(num, rate, keygen.SEED_SERVE + 2)
+    """Served sorting: Poisson streams of requests, sizes log-uniform in
+    [2^10, 2^26] keys, key type 50% uint32 / 50% uint64 (uniform full range),
+    admitted under a 64 GB HBM cap onto 4 streams and batched on arrival.  The
+    rate is set to rho times what one plain launch per request sustains on the
+    same mix.  Latency = submit to completion seen by the server."""
+    num, warm = args.serve_requests, args.serve_warmup
+    total_req = num + warm
+    sizes = keygen.log_uniform_sizes(total_req, keygen.SEED_SERVE)
+    u32 = keygen.unit_doubles(keygen.SEED_SERVE + 1, total_req) < 0.5
+    # input arena of random 64-bit words; every request reads a window of it
     g = torch.Generator(device="cuda")
     g.manual_seed(keygen.SEED_SERVE + 3)
-    ins, outs = [], []
-    for n, u32 in zip(sizes, kinds):
-        if u32:
-            k = torch.randint(-2 ** 31, 2 ** 31, (int(n),), dtype=torch.int32, device="cuda",
-                              generator=g).view(torch.uint32)
-        else:
-            k = torch.randint(-2 ** 63, 2 ** 63 - 1, (int(n),), dtype=torch.int64, device="cuda",
-                              generator=g).view(torch.uint64)
-        ins.append(k)
-        outs.append(torch.empty_like(k))
+    arena = torch.randint(-2 ** 63, 2 ** 63 - 1, (1 << 27,), dtype=torch.int64, device="cuda",
+                          generator=g)
+    a64, a32 = arena.view(torch.uint64), arena.view(torch.uint32)
+    offs = keygen.unit_doubles(keygen.SEED_SERVE + 4, total_req)
+
+    def request_input(i):
+        n = int(sizes[i])
+        src = a32 if u32[i] else a64
+        start = int(offs[i] * (src.numel() - n))
+        return src[start:start + n]
+
+    # output ring: a request's output region is reused only after its last user completed
+    ring = torch.empty(8 << 30, dtype=torch.uint8, device="cuda")
+    ring_users = []   # (start, end, ticket)
+    ring_at = [0]
+
+    def request_output(i, srv):
+        nbytes = int(sizes[i]) * (4 if u32[i] else 8)
+        start = (ring_at[0] + 255) // 256 * 256
+        if start + nbytes > ring.numel():
+            start = 0
+        end = start + nbytes
+        for (a, b, t) in list(ring_users):
+            if a < end and start < b:
+                srv.wait(t)
+                ring_users.remove((a, b, t))
+        ring_at[0] = end
+        view = ring[start:end].view(torch.uint32 if u32[i] else torch.uint64)
+        return view, (start, end)
+
+    # capacity: one plain launch per request, back to back on one stream
+    outs_plain = torch.empty(1 << 27, dtype=torch.int64, device="cuda")
     torch.cuda.synchronize()
-    total = int(sizes.sum())
-    log("serve: %d requests, %d keys, %.0f req/s" % (num, total, rate))
-    srv = rsort.Server(64 * 10 ** 9, num_streams=4)
-    # warm-up: one request of each kind and path
-    for i in (int(np.argmin(sizes)), int(np.argmax(sizes))):
-        srv.wait(srv.submit(ins[i], outs[i]))
-    srv.reset_stats()
-    tickets = []
     t0 = time.perf_counter()
-    for i in range(num):
-        while time.perf_counter() - t0 < arrivals[i]:
-            pass
-        tickets.append(srv.submit(ins[i], outs[i]))
-    for t in tickets:
-        srv.wait(t)
-    wall = time.perf_counter() - t0
-    p50, p99, kps, done = srv.latency()
-    srv.destroy()
-    # each result equals the same request sorted alone
-    pick = sorted(set([int(np.argmin(sizes)), int(np.argmax(sizes))] +
-                      list(np.random.default_rng(1).choice(num, 14, replace=False))))
-    same = True
-    for i in pick:
-        o = torch.empty_like(ins[i])
-        rsort.rsort_sort(ins[i], o)
-        torch.cuda.synchronize()
-        same = same and bool(torch.equal(o.view(torch.uint8), outs[i].view(torch.uint8)))
-    small = int((sizes <= 8192).sum())
-    return {"workload": "%d requests, Poisson %.0f req/s, sizes log-uniform [2^10, 2^26], "
-                        "50%% uint32 / 50%% uint64, cap 64 GB, 4 streams" % (num, rate),
-            "keys": total, "completed": int(done), "small_requests": small,
+    for i in range(warm, total_req):
+        x = request_input(i)
+        o = outs_plain[:x.numel()].view(torch.uint64) if not u32[i] else \
+            outs_plain.view(torch.uint32)[:x.numel()]
+        rsort.rsort_sort(x, o)
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t0
+    keys_meas = int(sizes[warm:].sum())
+    cap_kps = keys_meas / plain_s
+    mean_n = float(sizes[warm:].mean())
+    res = {"workload": "Poisson stream, sizes log-uniform [2^10, 2^26], 50%% uint32 / 50%% "
+                       "uint64, cap 64 GB, 4 streams; %d requests after %d warm-up" % (num, warm),
+           "plain_launch_gkeys_per_s": round(cap_kps / 1e9, 3)}
+    for rho in (0.5, 0.8):
+        rate = rho * cap_kps / mean_n
+        arrivals = keygen.poisson_arrivals(total_req, rate, keygen.SEED_SERVE + 2)
+        srv = rsort.Server(64 * 10 ** 9, num_streams=4)
+        ring_users.clear()
+        ring_at[0] = 0
+        pick = set(int(j) for j in np.random.default_rng(1).choice(np.arange(warm, total_req), 16,
+                                                                    replace=False))
+        pick |= {warm + int(np.argmin(sizes[warm:])), warm + int(np.argmax(sizes[warm:]))}
+        kept = {}
+        t0 = time.perf_counter()
+        tickets = []
+        for i in range(total_req):
+            if i == warm:
+                for t in tickets:
+                    srv.wait(t)
+                ring_users.clear()   # all complete; their tickets are forgotten below
+                srv.reset_stats()
+                tickets = []
+                t0 = time.perf_counter() - arrivals[warm]
+            while time.perf_counter() - t0 < arrivals[i]:
+                pass
+            x = request_input(i)
+            if i in pick:
+                o = torch.empty_like(x)
+                kept[i] = o
+                tickets.append(srv.submit(x, o))
+            else:
+                o, (a, b) = request_output(i, srv)
+                t = srv.submit(x, o)
+                ring_users.append((a, b, t))
+                tickets.append(t)
+        for t in tickets:
+            srv.wait(t)
+        p50, p99, kps, done = srv.latency()
+        srv.destroy()
+        same = True
+        for i, o in kept.items():
+            x = request_input(i)
+            ref = torch.empty_like(x)
+            rsort.rsort_sort(x, ref)
+            torch.cuda.synchronize()
+            same = same and bool(torch.equal(ref.view(torch.uint8), o.view(torch.uint8)))
+        res["rho_%.1f" % rho] = {
+            "rate_req_per_s": round(rate, 1), "completed": int(done),
             "latency_us_p50": round(p50, 1), "latency_us_p99": round(p99, 1),
-            "gkeys_per_s": round(kps / 1e9, 3), "wall_s": round(wall, 4),
-            "offered_gkeys_per_s": round(total / arrivals[-1] / 1e9, 3),
-            "alone_equals_mix": "%d sampled requests %s" % (len(pick), "identical" if same
+            "gkeys_per_s": round(kps / 1e9, 3),
+            "offered_gkeys_per_s": round(keys_meas / (arrivals[-1] - arrivals[warm]) / 1e9, 3),
+            "alone_equals_mix": "%d sampled requests %s" % (len(kept), "identical" if same
                                                              else "DIFFER")}
+        log("serve rho %.1f: p50 %.0f us p99 %.0f us" % (rho, p50, p99))
+    res["small_requests_frac"] = round(float((sizes <= 8192).mean()), 3)
+    del ring, arena, outs_plain
+    return res
+
+
+def host_info():
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cpu": model, "nproc": os.cpu_count()}
 
 
 def main():
@@ -248,9 +385,9 @@ def main():
                     help="minimum CPU time spent timing the oracle (0 disables)")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--kv-log2n", type=int, default=28)
-    ap.add_argument("--serve-requests", type=int, default=300)
-    ap.add_argument("--serve-rate", type=float, default=1000.0, help="arrivals per second")
-    ap.add_argument("--kv-dists", default="uniform,zipf,equal",
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-warmup", type=int, default=200)
+    ap.add_argument("--kv-dists", default="uniform,low16,zipf,equal,presorted,reverse",
                     help="comma list of key distributions for the key-value leg "
                          "(uniform, low16, zipf, equal, presorted, reverse)")
     ap.add_argument("--mode", choices=("sort", "copy"), default="sort",
@@ -314,6 +451,12 @@ def main():
     if not ok:
         log("OUTPUT CHECK FAILED")
 
+    # the library's plain copy of the same bytes: the achievable streaming rate
+    copy_s = time_steps(lambda: rsort.rsort_sort(dk, out, begin_bit=0, end_bit=0), 10, 2, torch)
+    copy_gbps = 2 * n * 4 / copy_s / 1e9
+    rsort.rsort_sort(dk, out, algo="lsd8")
+    torch.cuda.synchronize()
+
     round_avg_ms = round_ms / max(launches, 1)
     bytes_per_round = 2 * n * 4
     achieved = bytes_per_round / (round_avg_ms * 1e-3) / 1e9
@@ -340,7 +483,9 @@ def main():
                      "traffic": traffic,
                      "kernel": "k_scatter<uint32, keys-only> (rank and route of one count-sort round)",
                      "algorithmic_bytes_per_launch": bytes_per_round,
-                     "avg_launch_ms": round(round_avg_ms, 5), "timed_launches": launches},
+                     "avg_launch_ms": round(round_avg_ms, 5), "timed_launches": launches,
+                     "copy_gbps": round(copy_gbps, 1),
+                     "frac_of_copy": round(achieved / copy_gbps, 4)},
         "per_round_ms": {"count": round(count_ms / max(cl, 1), 5),
                          "tilescan": round(scan_ms / max(sl, 1), 5),
                          "scatter": round(round_avg_ms, 5)},
@@ -375,6 +520,7 @@ def main():
             "same_as_pr4": bool(np.array_equal(got16, got))}}
 
     if not args.no_variants:
+        result["small"] = bench_small(rsort, torch, np, keygen, args)
         result["batched"] = bench_batched(rsort, torch, np, keygen, args)
         del dk, out
         result["kv"] = bench_kv(rsort, torch, np, keygen, args)
@@ -390,7 +536,7 @@ def main():
             t += time.perf_counter() - t0
             runs += 1
         result["cpu_baseline"] = {"value": round(n * runs / t / 1e9, 4), "unit": "Gkeys/s",
-                                  "cores": 1, "kind": "oracle",
+                                  "cores": 1, "kind": "oracle", "host": host_info(),
                                   "sample": "%d full runs of serial SR4 (C, one thread) on the "
                                             "same 2^%d keys, %.1f s" % (runs, args.log2n, t)}
     print(json.dumps(result), flush=True)

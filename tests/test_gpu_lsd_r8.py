@@ -190,3 +190,37 @@ def test_full_size_2p27_keys_only(rs):
     want, _ = oracle.sr4(keys)
     assert np.array_equal(got, want)
     rs.rsort_synchronize()
+
+
+def test_graph_capture_replays(rs):
+    """The plain sort enqueues kernels only: captured once into a HIP graph,
+    every replay (with eager work between) equals the eager result and follows
+    new input data."""
+    import torch
+    n = (1 << 20) + 77
+    announce("graph", n)
+    keys = keygen.zipf_keys(n, 19)
+    vals = np.arange(n, dtype=np.uint32)
+    dk, dv = dev(keys), dev(vals)
+    ko, vo = torch.empty_like(dk), torch.empty_like(dv)
+    need = rs.rsort_workspace_bytes(torch.uint32, True, n)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    rs.rsort_sort(dk, ko, dv, vo, workspace=ws)
+    torch.cuda.synchronize()
+    wk, wv = oracle.sr4(keys, vals)
+    assert np.array_equal(host(ko), wk) and np.array_equal(host(vo), wv)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        rs.rsort_sort(dk, ko, dv, vo, workspace=ws)
+    for rep in range(3):
+        ko.view(torch.int32).fill_(rep)
+        vo.view(torch.int32).fill_(rep)
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(ko), wk), rep
+        assert np.array_equal(host(vo), wv), rep
+    keys2 = keygen.uniform_u32(n, 20)
+    dk.copy_(dev(keys2))
+    g.replay()
+    torch.cuda.synchronize()
+    assert np.array_equal(host(ko), oracle.sr4(keys2)[0])
