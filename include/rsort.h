@@ -148,6 +148,26 @@ int rsort_segmented_sort(rsort_ctx* ctx, int key_type, const void* keys_in, void
 int rsort_segmented_workspace_bytes(rsort_ctx* ctx, int key_type, int has_vals,
                                     const uint64_t* seg_offsets, size_t num_segs, size_t* bytes);
 
+/*
+ * The batched segmented sort with the segment offsets in DEVICE memory
+ * (num_segs + 1 nondecreasing uint32_t, offsets[num_segs] <= total_n; the key
+ * and payload arrays hold total_n elements).  Nothing is read back to the host:
+ * one planning kernel classifies the segments on the device, so the call can
+ * be captured in a HIP graph without a preceding eager call (with a
+ * caller-owned workspace of rsort_segmented_device_workspace_bytes()).  Offsets
+ * that decrease or end beyond total_n leave the arrays untouched and make the
+ * next rsort_synchronize on ctx return RSORT_EDEVICE.  Other arguments as in
+ * rsort_segmented_sort.
+ */
+int rsort_segmented_sort_device(rsort_ctx* ctx, int key_type, const void* keys_in, void* keys_out,
+                                const uint32_t* vals_in, uint32_t* vals_out,
+                                const uint32_t* seg_offsets, size_t num_segs, size_t total_n,
+                                void* workspace, size_t ws_bytes, void* stream);
+
+/* Workspace rsort_segmented_sort_device needs (depends on the counts only). */
+int rsort_segmented_device_workspace_bytes(rsort_ctx* ctx, int key_type, int has_vals,
+                                           size_t num_segs, size_t total_n, size_t* bytes);
+
 /* Largest segment sorted whole in LDS (<= 8192; 0 sends every segment through
  * the tiled path).  Chosen by the tuner; applies to later calls on ctx. */
 int rsort_segmented_set_split(rsort_ctx* ctx, uint32_t small_max);

@@ -564,6 +564,57 @@ int rsort_segmented_workspace_bytes(rsort_ctx* ctx, int key_type, int has_vals,
     return RSORT_OK;
 }
 
+int rsort_segmented_device_workspace_bytes(rsort_ctx* ctx, int key_type, int has_vals,
+                                           size_t num_segs, size_t total_n, size_t* bytes)
+{
+    if (!ctx || !bytes) return RSORT_EINVAL;
+    const int kb = key_bytes_of(key_type);
+    if (!kb) return fail(ctx, RSORT_EINVAL, "unknown key type %d", key_type);
+    if (total_n >= kMaxN || num_segs >= kMaxN)
+        return fail(ctx, RSORT_EUNSUPPORTED, "total_n or num_segs >= 2^30");
+    *bytes = rsort::devseg_layout(kb, has_vals != 0, total_n, (uint32_t)num_segs).bytes;
+    return RSORT_OK;
+}
+
+int rsort_segmented_sort_device(rsort_ctx* ctx, int key_type, const void* keys_in, void* keys_out,
+                                const uint32_t* vals_in, uint32_t* vals_out,
+                                const uint32_t* seg_offsets, size_t num_segs, size_t total_n,
+                                void* workspace, size_t ws_bytes, void* stream)
+{
+    if (!ctx) return RSORT_EINVAL;
+    ctx->last_error.clear();
+    const int kb = key_bytes_of(key_type);
+    if (!kb) return fail(ctx, RSORT_EINVAL, "unknown key type %d", key_type);
+    if ((vals_in == nullptr) != (vals_out == nullptr))
+        return fail(ctx, RSORT_EINVAL, "vals_in and vals_out must both be NULL or both be set");
+    if ((workspace == nullptr) != (ws_bytes == 0))
+        return fail(ctx, RSORT_EINVAL, "workspace and ws_bytes must both be 0 or both be set");
+    if (total_n >= kMaxN || num_segs >= kMaxN)
+        return fail(ctx, RSORT_EUNSUPPORTED, "total_n or num_segs >= 2^30");
+    if (num_segs == 0 || total_n == 0) return RSORT_OK;
+    if (!keys_in || !keys_out || !seg_offsets) return fail(ctx, RSORT_EINVAL, "NULL pointer");
+    DeviceGuard g(ctx->device);
+    int rc = check_arrays(ctx, kb, keys_in, keys_out, vals_in, vals_out, total_n);
+    if (rc) return rc;
+    if (!is_device_pointer(seg_offsets, ctx->device))
+        return fail(ctx, RSORT_EINVAL, "seg_offsets must be device memory of device %d", ctx->device);
+    const rsort::DevSegLayout L = rsort::devseg_layout(kb, vals_in != nullptr, total_n, (uint32_t)num_segs);
+    void* ws = workspace;
+    if (ws) {
+        if (ws_bytes < L.bytes)
+            return fail(ctx, RSORT_EINVAL, "workspace of %zu bytes < %zu needed", ws_bytes, L.bytes);
+        if (!is_device_pointer(ws, ctx->device))
+            return fail(ctx, RSORT_EINVAL, "workspace must be device memory");
+    } else {
+        rc = ensure_workspace(ctx, L.bytes, &ws);
+        if (rc) return rc;
+    }
+    hipError_t e = rsort::devseg_sort(kb, keys_in, keys_out, vals_in, vals_out, total_n, seg_offsets,
+                                      (uint32_t)num_segs, ctx->small_max, ws, L, ctx->dev_err,
+                                      (hipStream_t)stream, ctx->prof);
+    return e == hipSuccess ? RSORT_OK : hip_fail(ctx, e, "kernel launch");
+}
+
 int rsort_segmented_set_split(rsort_ctx* ctx, uint32_t small_max)
 {
     if (!ctx) return RSORT_EINVAL;
@@ -723,8 +774,9 @@ int rsort_synchronize(rsort_ctx* ctx, void* stream)
     if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpy(error word)");
     if (err) {
         (void)hipMemset(ctx->dev_err, 0, 4);
-        return fail(ctx, RSORT_EDEVICE, "device-side failure bits 0x%x%s", err,
-                    (err & 1u) ? " (look-back wait timed out)" : "");
+        return fail(ctx, RSORT_EDEVICE, "device-side failure bits 0x%x%s%s", err,
+                    (err & 1u) ? " (look-back wait timed out)" : "",
+                    (err & 2u) ? " (invalid device segment offsets: nothing sorted)" : "");
     }
     return RSORT_OK;
 }

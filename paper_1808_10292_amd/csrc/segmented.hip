@@ -329,13 +329,32 @@ __device__ uint32_t plan_exclusive_sum(uint32_t x, uint32_t* wsum, uint32_t* tot
 }
 
 __global__ __launch_bounds__(kPlanWG) void k_devseg_plan(const uint32_t* off, uint32_t nseg,
-                                                         uint32_t small_max, uint32_t tile,
-                                                         uint32_t rounds, RoundPlan* plan,
-                                                         uint2* small, uint2* tiles, uint4* lsegs,
-                                                         uint32_t* ntiles)
+                                                         uint32_t n, uint32_t small_max,
+                                                         uint32_t tile, uint32_t rounds,
+                                                         RoundPlan* plan, uint2* small,
+                                                         uint2* tiles, uint4* lsegs,
+                                                         uint32_t* ntiles, uint32_t* err)
 {
     __shared__ uint32_t wsum[kPlanWG / 64];
     const uint32_t tid = threadIdx.x;
+    // Offsets must be nondecreasing and end within the arrays; otherwise
+    // nothing is sorted (every round disabled, no segment) and the error word
+    // records a bad plan.
+    bool bad = false;
+    for (uint32_t j = tid; j < nseg; j += kPlanWG) bad |= off[j + 1] < off[j];
+    if (tid == 0) bad |= off[nseg] > n;
+    if (__syncthreads_or(bad)) {
+        if (tid <= (uint32_t)kMaxRounds) plan[tid] = RoundPlan{0, -1, 0, -1};
+        for (uint32_t j = tid; j < nseg; j += kPlanWG) {
+            for (uint32_t k = 0; k < 3; ++k) small[(size_t)k * nseg + j] = make_uint2(0, 0);
+            lsegs[j] = make_uint4(0, 0, 0, 0);
+        }
+        if (tid == 0) {
+            *ntiles = 0;
+            atomicOr(err, (uint32_t)kErrBadPlan);
+        }
+        return;
+    }
     if (tid <= (uint32_t)kMaxRounds) {
         RoundPlan r{0, -1, 0, -1};
         if (tid < rounds) {
@@ -394,8 +413,9 @@ hipError_t run_devseg(const void* keys_in, void* keys_out, const uint32_t* vals_
     uint4* lsegs = (uint4*)(w + L.off_lsegs);
     uint32_t* ntiles = (uint32_t*)(w + L.off_ntiles);
     const uint32_t rounds = sizeof(K);
-    hipLaunchKernelGGL(k_devseg_plan, dim3(1), dim3(kPlanWG), 0, stream, off, nseg, small_max,
-                       large_tile(sizeof(K)), rounds, plan, small, tiles, lsegs, ntiles);
+    hipLaunchKernelGGL(k_devseg_plan, dim3(1), dim3(kPlanWG), 0, stream, off, nseg, (uint32_t)n,
+                       small_max, large_tile(sizeof(K)), rounds, plan, small, tiles, lsegs, ntiles,
+                       dev_err);
     if (prof) profiler_mark(prof, stream, kKindSmall, true);
     for (int c = 0; c < 3; ++c)
         launch_small<K, KV>(c, keys_in, keys_out, KV ? vals_in : nullptr, KV ? vals_out : nullptr,

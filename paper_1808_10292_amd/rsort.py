@@ -45,7 +45,8 @@ EXPORTED = ("rsort_create", "rsort_destroy", "rsort_status_string", "rsort_last_
             "rsort_profile_enable", "rsort_profile_read", "rsort_segmented_sort",
             "rsort_segmented_workspace_bytes", "rsort_segmented_set_split",
             "rsort_segmented_tune", "rsort_sample_sort", "rsort_sample_sort_workspace_bytes",
-            "rsort_sample_sort_stats", "rsort_server_create", "rsort_server_submit",
+            "rsort_sample_sort_stats", "rsort_segmented_sort_device",
+            "rsort_segmented_device_workspace_bytes", "rsort_server_create", "rsort_server_submit",
             "rsort_server_poll", "rsort_server_wait", "rsort_server_latency",
             "rsort_server_reset_stats", "rsort_server_destroy")
 
@@ -102,6 +103,9 @@ def load_library():
         lib.rsort_sample_sort.argtypes = [vp, i, vp, vp, u32p, u32p, sz, i, i, vp, sz, vp]
         lib.rsort_sample_sort_workspace_bytes.argtypes = [vp, i, i, sz, i, i, ctypes.POINTER(sz)]
         lib.rsort_sample_sort_stats.argtypes = [vp, i, ctypes.POINTER(i), vp, vp, vp, vp]
+        lib.rsort_segmented_sort_device.argtypes = [vp, i, vp, vp, u32p, u32p, vp, sz, sz, vp, sz,
+                                                    vp]
+        lib.rsort_segmented_device_workspace_bytes.argtypes = [vp, i, i, sz, sz, ctypes.POINTER(sz)]
         lib.rsort_server_create.argtypes = [i, sz, i, ctypes.POINTER(vp)]
         lib.rsort_server_submit.argtypes = [vp, i, vp, vp, sz, ctypes.POINTER(ctypes.c_uint64)]
         lib.rsort_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(i)]
@@ -326,6 +330,38 @@ def rsort_segmented_workspace_bytes(key_dtype, has_vals, seg_offsets, device=Non
                                                        ctypes.c_void_p(off.ctypes.data),
                                                        off.size - 1, ctypes.byref(out)),
               "rsort_segmented_workspace_bytes")
+    return out.value
+
+
+def rsort_segmented_sort_device(keys_in, keys_out, seg_offsets, vals_in=None, vals_out=None,
+                                workspace=None, stream=None):
+    """Segmented sort with the offsets in a device tensor (int32/uint32,
+    num_segs + 1 entries)."""
+    kt = _key_type(keys_in)
+    n = _check_kv(keys_in, keys_out, vals_in, vals_out)
+    if not seg_offsets.is_cuda or seg_offsets.dtype not in (torch.int32, torch.uint32) or \
+            not seg_offsets.is_contiguous() or seg_offsets.dim() != 1 or seg_offsets.numel() < 1:
+        raise ValueError("seg_offsets must be a contiguous 1-D 32-bit device tensor")
+    ctx = context(keys_in.device)
+    ws_ptr, ws_bytes = None, 0
+    if workspace is not None:
+        ws_ptr, ws_bytes = _ptr(workspace), workspace.numel() * workspace.element_size()
+    rc = ctx._lib.rsort_segmented_sort_device(ctx.handle, kt, _ptr(keys_in), _ptr(keys_out),
+                                              _ptr(vals_in), _ptr(vals_out), _ptr(seg_offsets),
+                                              seg_offsets.numel() - 1, n, ws_ptr, ws_bytes,
+                                              _stream_handle(stream))
+    ctx.check(rc, "rsort_segmented_sort_device")
+    return keys_out, vals_out
+
+
+def rsort_segmented_device_workspace_bytes(key_dtype, has_vals, num_segs, total_n, device=None):
+    ctx = context(device)
+    kt = _key_type(torch.empty(0, dtype=key_dtype))
+    out = ctypes.c_size_t()
+    ctx.check(ctx._lib.rsort_segmented_device_workspace_bytes(ctx.handle, kt, int(bool(has_vals)),
+                                                              int(num_segs), int(total_n),
+                                                              ctypes.byref(out)),
+              "rsort_segmented_device_workspace_bytes")
     return out.value
 
 

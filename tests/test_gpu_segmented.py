@@ -178,3 +178,76 @@ def test_graph_capture_replays(rs):
     with pytest.raises(rs.RsortError):
         with torch.cuda.graph(g2):
             rs.rsort_segmented_sort(dk, ko, off2, dv, vo, workspace=ws)
+
+
+def test_device_offsets_match_and_capture(rs):
+    """Offsets in device memory: same result as the host-offset call and the
+    oracle; capturable with no preceding eager call; replays follow new data."""
+    import torch
+    sizes = keygen.lognormal_sizes(700, seed=15)
+    sizes[::50] = 0
+    off = keygen.offsets_from_sizes(sizes)
+    n = int(off[-1]) + 33   # a tail outside every segment stays untouched
+    announce("seg device offsets", n)
+    keys = keygen.uniform_u32(n, 16)
+    vals = np.arange(n, dtype=np.uint32)
+    end = int(off[-1])
+
+    def expect(k, v):
+        wk, wv = oracle.segmented(k, v, off)
+        wk[end:] = k[end:]            # the oracle leaves elements outside segments unset
+        if v is not None:
+            wv[end:] = v[end:]
+        return wk, wv
+
+    wk, wv = expect(keys, vals)
+    doff = torch.from_numpy(off.astype(np.int64)).to(torch.int32).cuda()
+    dk, dv = dev(keys), dev(vals)
+    ko, vo = dev(keys.copy()), dev(vals.copy())
+    rs.rsort_segmented_sort_device(dk, ko, doff, dv, vo)
+    rs.rsort_synchronize()
+    assert np.array_equal(host(ko), wk) and np.array_equal(host(vo), wv)
+    need = rs.rsort_segmented_device_workspace_bytes(torch.uint32, True, off.size - 1, n)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        rs.rsort_segmented_sort_device(dk, ko, doff, dv, vo, workspace=ws)
+    for rep in range(3):
+        ko.copy_(dk)
+        vo.copy_(dv)
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(ko), wk), rep
+        assert np.array_equal(host(vo), wv), rep
+    keys2 = keygen.zipf_keys(n, 17)
+    dk.copy_(dev(keys2))
+    ko.copy_(dk)
+    g.replay()
+    torch.cuda.synchronize()
+    assert np.array_equal(host(ko), expect(keys2, vals)[0])
+    # u64 keys, keys only
+    k64 = keygen.uniform_u64(n, 18)
+    d64 = dev(k64)
+    o64 = dev(k64.copy())
+    rs.rsort_segmented_sort_device(d64, o64, doff)
+    rs.rsort_synchronize()
+    assert np.array_equal(host(o64), expect(k64, None)[0])
+
+
+def test_device_offsets_invalid_are_reported(rs):
+    """Decreasing offsets, or offsets past the arrays: nothing is written and
+    the next synchronize reports a device error."""
+    import torch
+    n = 5000
+    keys = keygen.uniform_u32(n, 21)
+    dk = dev(keys)
+    for bad in ([0, 3000, 2000, 5000], [0, 1000, 6000]):
+        announce("seg device offsets invalid", bad)
+        ko = dev(keys.copy())
+        doff = torch.tensor(bad, dtype=torch.int32, device="cuda")
+        rs.rsort_segmented_sort_device(dk, ko, doff)
+        with pytest.raises(rs.RsortError) as e:
+            rs.rsort_synchronize()
+        assert e.value.status == rs.RSORT_EDEVICE
+        assert np.array_equal(host(ko), keys)
+    rs.rsort_synchronize()   # the error word was cleared
