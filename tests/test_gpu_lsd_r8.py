@@ -14,7 +14,9 @@ from tests.gpu_util import announce, check_kv_invariants, dev, host
 
 pytestmark = pytest.mark.gpu
 
-SIZES = [1, 2, 63, 64, 65, 1000, 8191, 8192, 8193, 3 * 8192 + 17, 100003, 1 << 20]
+# One to a few hundred 8192-key tiles, ragged tails, powers of two.
+SIZES = [1, 2, 63, 64, 65, 1000, 2047, 2048, 2049, 8191, 8192, 8193, 3 * 8192 + 17, 100003,
+         1 << 20, 1 << 21, (1 << 21) + 1, 3 * (1 << 20) + 4097]
 
 
 @pytest.fixture(scope="module")
@@ -61,9 +63,9 @@ def test_keys_only_sizes(rs, n):
     assert np.array_equal(host(ko), want)
 
 
+@pytest.mark.parametrize("n", [200003, 2500009])
 @pytest.mark.parametrize("dist", keygen.KV_DISTRIBUTIONS)
-def test_kv_distributions(rs, dist):
-    n = 200003
+def test_kv_distributions(rs, dist, n):
     announce("kv u32", dist, n)
     keys = keygen.kv_keys(dist, n)
     vals = np.arange(n, dtype=np.uint32)
