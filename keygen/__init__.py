@@ -192,3 +192,11 @@ def offsets_from_sizes(sizes: np.ndarray) -> np.ndarray:
     off = np.zeros(len(sizes) + 1, dtype=np.uint64)
     off[1:] = np.cumsum(np.asarray(sizes, dtype=np.uint64))
     return off
+
+
+def sample_positions(seed: int, count: int, n: int) -> np.ndarray:
+    """Uniform draws with replacement from [0, n): position i is
+    ((splitmix64 value i) >> 32) * n >> 32 (the high 32 bits scaled to n)."""
+    hi = splitmix64(seed, count) >> np.uint64(32)
+    with np.errstate(over="ignore"):
+        return ((hi * np.uint64(n)) >> np.uint64(32)).astype(np.uint32)

@@ -57,6 +57,9 @@ def _configure(lib):
     lib.gsd_u32.argtypes = [vp, vp, sz, i, i, vp, vp, vp, vp, vp,
                             ctypes.POINTER(ctypes.c_int)]
     lib.gsd_u32.restype = i
+    lib.ger_u32.argtypes = [vp, vp, sz, i, i, vp, sz, vp, vp, vp, vp, vp,
+                            ctypes.POINTER(ctypes.c_int)]
+    lib.ger_u32.restype = i
     return lib
 
 
@@ -153,6 +156,34 @@ def gsd(keys, vals, p: int, r: int):
                          _ptr(sk), _ptr(sg), ctypes.byref(used))
     if rc:
         raise ValueError("oracle gsd failed (%d)" % rc)
+    pu = used.value
+    cnt = cnt.reshape(pu, pu)
+    return {"keys": ko, "vals": vo, "p": pu, "cnt": cnt,
+            "split_key": sk[:pu - 1], "split_g": sg[:pu - 1],
+            "bucket": cnt.sum(axis=0)}
+
+
+def ger(keys, vals, p: int, s: int, positions):
+    """GER (Algorithm 2) on uint32 keys with the random draws given:
+    ``positions`` (uint32, at least s*min(p, n) - 1 of them, each < n) are the
+    sample positions into the locally sorted blocks.  Returns the same dict as
+    ``gsd``."""
+    keys = np.ascontiguousarray(keys, dtype=np.uint32)
+    n = keys.size
+    if vals is not None:
+        vals = np.ascontiguousarray(vals, dtype=np.uint32)
+    pos = np.ascontiguousarray(positions, dtype=np.uint32)
+    pmax = max(1, min(p, n))
+    ko = np.empty_like(keys)
+    vo = None if vals is None else np.empty_like(vals)
+    cnt = np.zeros(pmax * pmax, dtype=np.uint64)
+    sk = np.zeros(max(pmax - 1, 1), dtype=np.uint32)
+    sg = np.zeros(max(pmax - 1, 1), dtype=np.uint64)
+    used = ctypes.c_int(0)
+    rc = _load().ger_u32(_ptr(keys), _ptr(vals), n, p, s, _ptr(pos), pos.size, _ptr(ko),
+                         _ptr(vo), _ptr(cnt), _ptr(sk), _ptr(sg), ctypes.byref(used))
+    if rc:
+        raise ValueError("oracle ger failed (%d)" % rc)
     pu = used.value
     cnt = cnt.reshape(pu, pu)
     return {"keys": ko, "vals": vo, "p": pu, "cnt": cnt,

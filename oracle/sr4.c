@@ -260,56 +260,36 @@ static void heap_sift_down(head* h, size_t m, size_t i)
     }
 }
 
-int gsd_u32(const uint32_t* keys_in, const uint32_t* vals_in, size_t n,
-            int p_req, int r,
-            uint32_t* keys_out, uint32_t* vals_out,
-            uint64_t* cnt /* p*p */, uint32_t* split_key /* p-1 */,
-            uint64_t* split_g /* p-1 */, int* p_used)
+/* Step 1 of GSD and GER: X = the p near-equal blocks of the input, each sorted
+ * by SR4 (payloads alongside); lo[k] = first index of block k, lo[p] = n. */
+static int local_sort(const uint32_t* keys_in, const uint32_t* vals_in, size_t n, size_t p,
+                      uint32_t* X, uint32_t* XV, uint64_t* lo)
 {
-    if (p_req < 1 || r < 1 || n == 0 || n >= ((uint64_t)1 << 32) ||
-        !keys_in || !keys_out || (vals_in && !vals_out))
-        return -1;
-    size_t p = (size_t)p_req < n ? (size_t)p_req : n;
-    *p_used = (int)p;
-    const size_t s = (size_t)r * p;
+    for (size_t k = 0; k <= p; ++k) lo[k] = (uint64_t)((k * (unsigned __int128)n) / p);
+    for (size_t k = 0; k < p; ++k) {
+        int rc = lsd_u32(keys_in + lo[k], vals_in ? vals_in + lo[k] : NULL, lo[k + 1] - lo[k],
+                         8, 0, 32, X + lo[k], vals_in ? XV + lo[k] : NULL);
+        if (rc) return rc;
+    }
+    return 0;
+}
 
-    /* step 1: local sorting of p near-equal blocks */
-    uint32_t* X = (uint32_t*)malloc(n * sizeof(uint32_t));
-    uint32_t* XV = vals_in ? (uint32_t*)malloc(n * sizeof(uint32_t)) : NULL;
-    uint64_t* lo = (uint64_t*)malloc((p + 1) * sizeof(uint64_t));
-    uint32_t* Tk = (uint32_t*)malloc(p * s * sizeof(uint32_t));
-    uint32_t* Tg = (uint32_t*)malloc(p * s * sizeof(uint32_t));
-    uint32_t* Sk = (uint32_t*)malloc(p * s * sizeof(uint32_t));
-    uint32_t* Sg = (uint32_t*)malloc(p * s * sizeof(uint32_t));
+/* Steps 3-5 of GSD and GER, given the sample sorted by composite (Sk, Sg):
+ * splitters, split by binary search, p-way merge into keys_out/vals_out. */
+static int split_and_merge(const uint32_t* X, const uint32_t* XV, const uint64_t* lo, size_t n,
+                           size_t p, size_t s, const uint32_t* Sk, const uint32_t* Sg,
+                           uint32_t* keys_out, uint32_t* vals_out, uint64_t* cnt,
+                           uint32_t* split_key, uint64_t* split_g)
+{
     uint64_t* b = (uint64_t*)malloc(p * (p + 1) * sizeof(uint64_t));
     head* heap = (head*)malloc(p * sizeof(head));
     uint64_t* cur = (uint64_t*)malloc(p * sizeof(uint64_t));
     int rc = 0;
-    if (!X || (vals_in && !XV) || !lo || !Tk || !Tg || !Sk || !Sg || !b || !heap || !cur) {
+    const int has_vals = XV != NULL;
+    if (!b || !heap || !cur) {
         rc = -2;
         goto done;
     }
-    for (size_t k = 0; k <= p; ++k) lo[k] = (uint64_t)((k * (unsigned __int128)n) / p);
-    for (size_t k = 0; k < p; ++k) {
-        rc = lsd_u32(keys_in + lo[k], vals_in ? vals_in + lo[k] : NULL, lo[k + 1] - lo[k],
-                     8, 0, 32, X + lo[k], vals_in ? XV + lo[k] : NULL);
-        if (rc) goto done;
-    }
-
-    /* step 2: regular sample of s keys per block, the last one the block maximum */
-    for (size_t k = 0; k < p; ++k) {
-        uint64_t Nk = lo[k + 1] - lo[k];
-        for (size_t j = 1; j <= s; ++j) {
-            uint64_t q = (j * Nk + s - 1) / s - 1;          /* ceil(j Nk / s) - 1 */
-            Tk[k * s + j - 1] = X[lo[k] + q];
-            Tg[k * s + j - 1] = (uint32_t)(lo[k] + q);
-        }
-    }
-    /* sort the sample by (key, g): T is laid out in block order, so g already
-       increases along equal keys and a stable sort by key suffices */
-    rc = lsd_u32(Tk, Tg, p * s, 8, 0, 32, Sk, Sg);
-    if (rc) goto done;
-
     /* step 3: splitters = the (i s)-th smallest sample composites */
     for (size_t i = 1; i < p; ++i) {
         split_key[i - 1] = Sk[i * s - 1];
@@ -354,7 +334,7 @@ int gsd_u32(const uint32_t* keys_in, const uint32_t* vals_in, size_t n,
             uint32_t k = heap[0].run;
             if (o >= n) { rc = -3; goto done; }          /* runs overlap: split is broken */
             keys_out[o] = X[lo[k] + cur[k]];
-            if (vals_in) vals_out[o] = XV[lo[k] + cur[k]];
+            if (has_vals) vals_out[o] = XV[lo[k] + cur[k]];
             ++o;
             ++cur[k];
             if (cur[k] < b[(size_t)k * (p + 1) + j + 1]) {
@@ -368,7 +348,118 @@ int gsd_u32(const uint32_t* keys_in, const uint32_t* vals_in, size_t n,
     if (o != n) rc = -3;
 
 done:
-    free(X); free(XV); free(lo); free(Tk); free(Tg); free(Sk); free(Sg);
     free(b); free(heap); free(cur);
+    return rc;
+}
+
+int gsd_u32(const uint32_t* keys_in, const uint32_t* vals_in, size_t n,
+            int p_req, int r,
+            uint32_t* keys_out, uint32_t* vals_out,
+            uint64_t* cnt /* p*p */, uint32_t* split_key /* p-1 */,
+            uint64_t* split_g /* p-1 */, int* p_used)
+{
+    if (p_req < 1 || r < 1 || n == 0 || n >= ((uint64_t)1 << 32) ||
+        !keys_in || !keys_out || (vals_in && !vals_out))
+        return -1;
+    size_t p = (size_t)p_req < n ? (size_t)p_req : n;
+    *p_used = (int)p;
+    const size_t s = (size_t)r * p;
+
+    uint32_t* X = (uint32_t*)malloc(n * sizeof(uint32_t));
+    uint32_t* XV = vals_in ? (uint32_t*)malloc(n * sizeof(uint32_t)) : NULL;
+    uint64_t* lo = (uint64_t*)malloc((p + 1) * sizeof(uint64_t));
+    uint32_t* Tk = (uint32_t*)malloc(p * s * sizeof(uint32_t));
+    uint32_t* Tg = (uint32_t*)malloc(p * s * sizeof(uint32_t));
+    uint32_t* Sk = (uint32_t*)malloc(p * s * sizeof(uint32_t));
+    uint32_t* Sg = (uint32_t*)malloc(p * s * sizeof(uint32_t));
+    int rc = 0;
+    if (!X || (vals_in && !XV) || !lo || !Tk || !Tg || !Sk || !Sg) {
+        rc = -2;
+        goto done;
+    }
+    /* step 1: local sorting of p near-equal blocks */
+    rc = local_sort(keys_in, vals_in, n, p, X, XV, lo);
+    if (rc) goto done;
+
+    /* step 2: regular sample of s keys per block, the last one the block maximum */
+    for (size_t k = 0; k < p; ++k) {
+        uint64_t Nk = lo[k + 1] - lo[k];
+        for (size_t j = 1; j <= s; ++j) {
+            uint64_t q = (j * Nk + s - 1) / s - 1;          /* ceil(j Nk / s) - 1 */
+            Tk[k * s + j - 1] = X[lo[k] + q];
+            Tg[k * s + j - 1] = (uint32_t)(lo[k] + q);
+        }
+    }
+    /* sort the sample by (key, g): T is laid out in block order, so g already
+       increases along equal keys and a stable sort by key suffices */
+    rc = lsd_u32(Tk, Tg, p * s, 8, 0, 32, Sk, Sg);
+    if (rc) goto done;
+
+    /* steps 3-5 */
+    rc = split_and_merge(X, XV, lo, n, p, s, Sk, Sg, keys_out, vals_out, cnt, split_key, split_g);
+
+done:
+    free(X); free(XV); free(lo); free(Tk); free(Tg); free(Sk); free(Sg);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* GER, Algorithm 2 (Section 3.3): the GSD skeleton with a random sample.
+ *
+ * Readings where the paper is silent:
+ *  - Steps 1 and 3-5 as in GSD above (same blocks, composites, split and
+ *    stable merge).
+ *  - Step 2 draws s p - 1 keys "uniformly at random from the keys of all X_k"
+ *    with replacement: the draws are the caller's positions pos[0 .. s p - 1)
+ *    into X, each in [0, n), so that a test and the GPU use the same draws.
+ *    Sample element i is the composite (X[pos[i]], pos[i]).
+ *  - The sample is sorted by composite (SR4 by position, then SR4 by key,
+ *    both stable) instead of BTN; splitter i is the (i s)-th smallest.
+ */
+int ger_u32(const uint32_t* keys_in, const uint32_t* vals_in, size_t n, int p_req, int s_req,
+            const uint32_t* pos, size_t npos, uint32_t* keys_out, uint32_t* vals_out,
+            uint64_t* cnt /* p*p */, uint32_t* split_key /* p-1 */,
+            uint64_t* split_g /* p-1 */, int* p_used)
+{
+    if (p_req < 1 || s_req < 1 || n == 0 || n >= ((uint64_t)1 << 32) ||
+        !keys_in || !keys_out || (vals_in && !vals_out))
+        return -1;
+    size_t p = (size_t)p_req < n ? (size_t)p_req : n;
+    *p_used = (int)p;
+    const size_t s = (size_t)s_req;
+    const size_t m = s * p - 1;            /* sample size */
+    if (npos < m || (m && !pos)) return -1;
+    for (size_t i = 0; i < m; ++i)
+        if (pos[i] >= n) return -1;
+
+    uint32_t* X = (uint32_t*)malloc(n * sizeof(uint32_t));
+    uint32_t* XV = vals_in ? (uint32_t*)malloc(n * sizeof(uint32_t)) : NULL;
+    uint64_t* lo = (uint64_t*)malloc((p + 1) * sizeof(uint64_t));
+    uint32_t* Tk = (uint32_t*)malloc((m ? m : 1) * sizeof(uint32_t));
+    uint32_t* Tg = (uint32_t*)malloc((m ? m : 1) * sizeof(uint32_t));
+    uint32_t* Uk = (uint32_t*)malloc((m ? m : 1) * sizeof(uint32_t));
+    uint32_t* Ug = (uint32_t*)malloc((m ? m : 1) * sizeof(uint32_t));
+    int rc = 0;
+    if (!X || (vals_in && !XV) || !lo || !Tk || !Tg || !Uk || !Ug) {
+        rc = -2;
+        goto done;
+    }
+    /* step 1 */
+    rc = local_sort(keys_in, vals_in, n, p, X, XV, lo);
+    if (rc) goto done;
+    /* step 2: the random sample, sorted by (key, position) */
+    for (size_t i = 0; i < m; ++i) {
+        Tg[i] = pos[i];
+        Tk[i] = X[pos[i]];
+    }
+    rc = lsd_u32(Tg, Tk, m, 8, 0, 32, Ug, Uk);        /* by position */
+    if (rc) goto done;
+    rc = lsd_u32(Uk, Ug, m, 8, 0, 32, Tk, Tg);        /* then by key, stably */
+    if (rc) goto done;
+    /* steps 3-5 */
+    rc = split_and_merge(X, XV, lo, n, p, s, Tk, Tg, keys_out, vals_out, cnt, split_key, split_g);
+
+done:
+    free(X); free(XV); free(lo); free(Tk); free(Tg); free(Uk); free(Ug);
     return rc;
 }

@@ -321,3 +321,73 @@ def test_gsd_splitters_brute_force():
         want = [sample[i * s - 1] for i in range(1, p)]
         got = list(zip(res["split_key"].tolist(), res["split_g"].tolist()))
         assert got == want
+
+
+# ---------------------------------------------------------------------------
+# GER (Algorithm 2): the GSD skeleton with a random sample whose draws (positions
+# into the locally sorted blocks) are an input.
+
+def _local_blocks(keys, p):
+    """X and its composites by brute force: block k stable-sorted by Python."""
+    n = keys.size
+    X = []
+    for k in range(p):
+        a, b = (k * n) // p, ((k + 1) * n) // p
+        X.extend(sorted(int(x) for x in keys[a:b]))   # equal keys: any order, same values
+    return X
+
+
+@pytest.mark.parametrize("dist", ["uniform", "zipf", "equal", "low16"])
+def test_ger_output_split_and_splitters(dist):
+    """Sorted output = the stable sort; splitters = the (i s)-th smallest
+    (key, position) sample composites; cnt = the composite split of each block;
+    all recomputed by brute force from the definition of Algorithm 2."""
+    n, p, s = 20011, 12, 9
+    keys = keygen.kv_keys(dist, n)
+    idx = np.arange(n, dtype=np.uint32)
+    pos = keygen.sample_positions(1234 + len(dist), s * p - 1, n)
+    res = oracle.ger(keys, idx, p, s, pos)
+    assert np.array_equal(res["vals"], np.argsort(keys, kind="stable").astype(np.uint32))
+    X = _local_blocks(keys, p)
+    sample = sorted((X[q], int(q)) for q in pos)
+    want = [sample[i * s - 1] for i in range(1, p)]
+    got = list(zip(res["split_key"].tolist(), res["split_g"].tolist()))
+    assert got == want
+    bounds = [(k * n) // p for k in range(p + 1)]
+    comp = [(X[q], q) for q in range(n)]
+    for k in range(p):
+        for j in range(p):
+            lo_s = want[j - 1] if j > 0 else None
+            hi_s = want[j] if j < p - 1 else None
+            c = sum(1 for q in range(bounds[k], bounds[k + 1])
+                    if (lo_s is None or comp[q] > lo_s) and (hi_s is None or comp[q] <= hi_s))
+            assert res["cnt"][k, j] == c, (k, j)
+    assert int(res["cnt"].sum()) == n
+
+
+def test_ger_small_and_degenerate():
+    """p = 1 (no splitters), p clamped to n, s = 1, and repeated draws."""
+    rng = np.random.default_rng(4)
+    for n, p, s in [(1, 4, 3), (7, 16, 2), (1000, 1, 5), (999, 9, 1), (4096, 8, 40)]:
+        keys = rng.integers(0, 30, size=n, dtype=np.uint64).astype(np.uint32)
+        idx = np.arange(n, dtype=np.uint32)
+        pu = min(p, n)
+        pos = keygen.sample_positions(77 + n, max(s * pu - 1, 0), n)
+        res = oracle.ger(keys, idx, p, s, pos)
+        assert res["p"] == pu
+        assert np.array_equal(res["vals"], np.argsort(keys, kind="stable").astype(np.uint32))
+        assert int(res["cnt"].sum()) == n
+        gsd_composite_check(keys, res)
+    with pytest.raises(ValueError):
+        oracle.ger(np.arange(10, dtype=np.uint32), None, 2, 3, np.array([0, 1], dtype=np.uint32))
+    with pytest.raises(ValueError):
+        oracle.ger(np.arange(10, dtype=np.uint32), None, 2, 1, np.array([10], dtype=np.uint32))
+
+
+def test_sample_positions_closed_form():
+    """Position i is floor((splitmix64 value i >> 32) * n / 2^32)."""
+    z = keygen.splitmix64(5, 8)
+    got = keygen.sample_positions(5, 8, 1000)
+    want = [((int(v) >> 32) * 1000) >> 32 for v in z]
+    assert got.tolist() == want
+    assert keygen.sample_positions(5, 100000, 7).max() == 6

@@ -41,6 +41,9 @@ MUTANTS = {
     "merge_ties_reversed": (
         "return a.key < b.key || (a.key == b.key && a.run < b.run);",
         "return a.key < b.key || (a.key == b.key && a.run > b.run);"),
+    "ger_sample_not_ordered_by_position": (
+        "rc = lsd_u32(Tg, Tk, m, 8, 0, 32, Ug, Uk);        /* by position */",
+        "memcpy(Ug, Tg, m * 4); memcpy(Uk, Tk, m * 4);"),
     "split_strict_instead_of_nonstrict": (
         "if (!comp_less(split_key[i - 1], split_g[i - 1], X[lo[k] + mid], lo[k] + mid))",
         "if (comp_less(X[lo[k] + mid], lo[k] + mid, split_key[i - 1], split_g[i - 1]))"),
@@ -56,6 +59,8 @@ PINS = [
     pins.test_gsd_ragged_and_small,
     pins.test_gsd_closed_form_identity_input,
     pins.test_gsd_splitters_brute_force,
+    lambda: pins.test_ger_output_split_and_splitters("zipf"),
+    lambda: pins.test_ger_output_split_and_splitters("equal"),
 ]
 
 
