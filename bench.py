@@ -156,7 +156,7 @@ def bench_kv(rsort, torch, np, keygen, args):
     (uint32 key, uint32 payload = input index) per key distribution."""
     n = 1 << args.kv_log2n
     res = {"workload": "2^%d (uint32 key, uint32 payload = input index) pairs; PR4 vs GSD "
-                       "p=256 r=32" % args.kv_log2n, "n": n,
+                       "p=256 r=32 vs GER p=256 s=2w^2 lg n" % args.kv_log2n, "n": n,
            "algorithmic_bytes_per_pass": 2 * n * 8}
     dv = torch.arange(n, dtype=torch.int32, device="cuda")
     ko = torch.empty(n, dtype=torch.uint32, device="cuda")
@@ -168,9 +168,12 @@ def bench_kv(rsort, torch, np, keygen, args):
         dk = torch.from_numpy(keys).cuda()
         skipped = identity_rounds(np, keys)
         row = {}
-        for algo in ("lsd8", "sample"):
-            fn = (lambda: rsort.rsort_sort(dk, ko, dv, vo, algo="lsd8")) if algo == "lsd8" else \
-                (lambda: rsort.rsort_sample_sort(dk, ko, dv, vo, p=256, r=32))
+        fns = {"lsd8": lambda: rsort.rsort_sort(dk, ko, dv, vo, algo="lsd8"),
+               "sample": lambda: rsort.rsort_sample_sort(dk, ko, dv, vo, p=256, r=32),
+               "sample_random": lambda: rsort.rsort_sample_sort_random(dk, ko, dv, vo, p=256,
+                                                                       s=0, seed=11)}
+        buckets = {}
+        for algo, fn in fns.items():
             sec = time_steps(fn, steps, 1, torch)
             # spot check: sorted keys and payloads that point at their keys
             idx = np.random.default_rng(5).integers(0, n, 4096)
@@ -182,14 +185,16 @@ def bench_kv(rsort, torch, np, keygen, args):
             ok = ok and bool(np.all(head[1:] >= head[:-1]))
             row[algo] = {"ms": round(sec * 1e3, 3), "gkeys_per_s": round(n / sec / 1e9, 3),
                          "check": "sampled ok" if ok else "FAILED"}
+            if algo != "lsd8":
+                buckets[algo] = int(rsort.rsort_sample_sort_stats()["bucket"].max())
         executed = 4 - len(skipped)
         row["lsd8"]["rounds_executed"] = executed
         if executed:
             row["lsd8"]["gbps_per_executed_pass"] = round(
                 2 * n * 8 * executed / (row["lsd8"]["ms"] * 1e-3) / 1e9, 1)
-        st = rsort.rsort_sample_sort_stats()
-        row["sample"]["max_bucket"] = int(st["bucket"].max())
+        row["sample"]["max_bucket"] = buckets["sample"]
         row["sample"]["lemma1_bound"] = round((1 + 1 / 32) * n / 256 + 32 * 256, 1)
+        row["sample_random"]["max_bucket"] = buckets["sample_random"]
         res[dist] = row
         del dk
     return res

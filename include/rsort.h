@@ -213,6 +213,28 @@ int rsort_sample_sort_workspace_bytes(rsort_ctx* ctx, int key_type, int has_vals
                                       int p, int r, size_t* bytes);
 
 /*
+ * Random-oversampling sample sort, GER (Section 3.3, Algorithm 2): the GSD
+ * skeleton above with a different step 2.  The sample is s p - 1 keys drawn
+ * uniformly at random, with replacement, from the locally sorted blocks: draw i
+ * is position ((SplitMix64 value i of stream `seed`) >> 32) * n >> 32 of the
+ * concatenated blocks, SplitMix64 being the counter-based generator of Steele,
+ * Lea and Flood (value i = mix(seed + (i + 1) * 0x9E3779B97F4A7C15)).  The
+ * sample is ordered by (key, position) and splitter i is its (i s)-th smallest
+ * element; split, route and the stable finish are as in GSD, so the result is
+ * again the stable sort.  s = 0 selects s = 2 w^2 lg n with w = ceil(lg lg n)
+ * (the paper's s = 2 w_n^2 lg n); s p <= 2^26.  Bucket sizes are bounded with
+ * high probability (Lemma 2), not deterministically.  The statistics call
+ * reports the split of the last sample sort of either kind.
+ */
+int rsort_sample_sort_random(rsort_ctx* ctx, int key_type, const void* keys_in, void* keys_out,
+                             const uint32_t* vals_in, uint32_t* vals_out, size_t n, int p, int s,
+                             uint64_t seed, void* workspace, size_t ws_bytes, void* stream);
+
+/* Workspace rsort_sample_sort_random needs for (n, p, s, payload). */
+int rsort_sample_sort_random_workspace_bytes(rsort_ctx* ctx, int key_type, int has_vals, size_t n,
+                                             int p, int s, size_t* bytes);
+
+/*
  * Split statistics of the last sample sort on ctx (waits for the device).
  * *p_used receives the number of buckets; each non-NULL HOST array must hold
  * p_cap >= *p_used (or p_cap^2 for cnt) entries:

@@ -228,15 +228,18 @@ int check_arrays(rsort_ctx* ctx, int kb, const void* keys_in, const void* keys_o
     return RSORT_OK;
 }
 
-int check_gsd_params(rsort_ctx* ctx, int key_type, int p, int r)
+// p and the oversampling parameter q: r for GSD (sample r p^2), s for GER
+// (sample s p - 1).
+int check_gsd_params(rsort_ctx* ctx, int key_type, int p, int q, bool random = false)
 {
     if (key_type != RSORT_U32)
         return fail(ctx, RSORT_EUNSUPPORTED, "the sample sort takes uint32 keys only");
     if (p < 1 || p > kMaxP) return fail(ctx, RSORT_EINVAL, "p = %d outside [1, %d]", p, kMaxP);
-    if (r < 1) return fail(ctx, RSORT_EINVAL, "r = %d < 1", r);
-    if ((uint64_t)r * p * p > kMaxSample)
-        return fail(ctx, RSORT_EUNSUPPORTED, "sample r p^2 = %llu above 2^26",
-                    (unsigned long long)r * p * p);
+    if (q < 1) return fail(ctx, RSORT_EINVAL, "oversampling %d < 1", q);
+    const uint64_t sample = random ? (uint64_t)q * p : (uint64_t)q * p * p;
+    if (sample > kMaxSample)
+        return fail(ctx, RSORT_EUNSUPPORTED, "sample of %llu keys above 2^26",
+                    (unsigned long long)sample);
     return RSORT_OK;
 }
 
@@ -324,13 +327,17 @@ int rsort_sample_sort_workspace_bytes(rsort_ctx* ctx, int key_type, int has_vals
     return RSORT_OK;
 }
 
-int rsort_sample_sort(rsort_ctx* ctx, int key_type, const void* keys_in, void* keys_out,
-                      const uint32_t* vals_in, uint32_t* vals_out, size_t n, int p, int r,
-                      void* workspace, size_t ws_bytes, void* stream)
+}  // extern "C"
+
+namespace {
+
+// Shared part of the two sample sorts once the layout is known.
+int run_skeleton(rsort_ctx* ctx, int key_type, const void* keys_in, void* keys_out,
+                 const uint32_t* vals_in, uint32_t* vals_out, size_t n, bool random, int p, int s,
+                 uint64_t seed, void* workspace, size_t ws_bytes, void* stream)
 {
-    if (!ctx) return RSORT_EINVAL;
     ctx->last_error.clear();
-    int rc = check_gsd_params(ctx, key_type, p, r);
+    int rc = check_gsd_params(ctx, key_type, p, s, random);
     if (rc) return rc;
     if ((vals_in == nullptr) != (vals_out == nullptr))
         return fail(ctx, RSORT_EINVAL, "vals_in and vals_out must both be NULL or both be set");
@@ -342,11 +349,13 @@ int rsort_sample_sort(rsort_ctx* ctx, int key_type, const void* keys_in, void* k
     DeviceGuard g(ctx->device);
     rc = check_arrays(ctx, 4, keys_in, keys_out, vals_in, vals_out, n);
     if (rc) return rc;
-    const rsort::GsdLayout L = rsort::gsd_layout(vals_in != nullptr, n, (uint32_t)p, (uint32_t)r);
-    hipStream_t s = (hipStream_t)stream;
+    const rsort::GsdLayout L =
+        random ? rsort::ger_layout(vals_in != nullptr, n, (uint32_t)p, (uint32_t)s)
+               : rsort::gsd_layout(vals_in != nullptr, n, (uint32_t)p, (uint32_t)s);
+    hipStream_t st = (hipStream_t)stream;
     if (!ctx->gsd_stats) {
         hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-        if (hipStreamIsCapturing(s, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone)
+        if (hipStreamIsCapturing(st, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone)
             return fail(ctx, RSORT_EINVAL,
                         "first sample sort on a context cannot be captured (it allocates)");
         hipError_t e = hipMalloc(&ctx->gsd_stats, rsort::gsd_stats_words(kMaxP) * 4);
@@ -366,9 +375,56 @@ int rsort_sample_sort(rsort_ctx* ctx, int key_type, const void* keys_in, void* k
         if (rc) return rc;
     }
     hipError_t e = rsort::gsd_sort((const uint32_t*)keys_in, (uint32_t*)keys_out, vals_in, vals_out,
-                                   n, L, ws, ctx->gsd_stats, ctx->dev_err, s, ctx->prof);
+                                   n, L, seed, ws, ctx->gsd_stats, ctx->dev_err, st, ctx->prof);
     if (e != hipSuccess) return hip_fail(ctx, e, "kernel launch");
     ctx->gsd_p = L.p;
+    return RSORT_OK;
+}
+
+// Default GER oversampling s = 2 w^2 lg n with w = ceil(lg lg n) (at least 1).
+int ger_default_s(size_t n)
+{
+    int lg = 0;
+    while (((size_t)1 << lg) < n) ++lg;
+    int w = 0;
+    while ((1 << w) < lg) ++w;
+    if (w < 1) w = 1;
+    if (lg < 1) lg = 1;
+    return 2 * w * w * lg;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rsort_sample_sort(rsort_ctx* ctx, int key_type, const void* keys_in, void* keys_out,
+                      const uint32_t* vals_in, uint32_t* vals_out, size_t n, int p, int r,
+                      void* workspace, size_t ws_bytes, void* stream)
+{
+    if (!ctx) return RSORT_EINVAL;
+    return run_skeleton(ctx, key_type, keys_in, keys_out, vals_in, vals_out, n, false, p, r, 0,
+                        workspace, ws_bytes, stream);
+}
+
+int rsort_sample_sort_random(rsort_ctx* ctx, int key_type, const void* keys_in, void* keys_out,
+                             const uint32_t* vals_in, uint32_t* vals_out, size_t n, int p, int s,
+                             uint64_t seed, void* workspace, size_t ws_bytes, void* stream)
+{
+    if (!ctx) return RSORT_EINVAL;
+    if (s == 0) s = ger_default_s(n);
+    return run_skeleton(ctx, key_type, keys_in, keys_out, vals_in, vals_out, n, true, p, s, seed,
+                        workspace, ws_bytes, stream);
+}
+
+int rsort_sample_sort_random_workspace_bytes(rsort_ctx* ctx, int key_type, int has_vals, size_t n,
+                                             int p, int s, size_t* bytes)
+{
+    if (!ctx || !bytes) return RSORT_EINVAL;
+    if (s == 0) s = ger_default_s(n);
+    int rc = check_gsd_params(ctx, key_type, p, s, true);
+    if (rc) return rc;
+    if (n >= kMaxN) return fail(ctx, RSORT_EUNSUPPORTED, "n = %zu >= 2^30", n);
+    *bytes = n ? rsort::ger_layout(has_vals != 0, n, (uint32_t)p, (uint32_t)s).bytes : 0;
     return RSORT_OK;
 }
 

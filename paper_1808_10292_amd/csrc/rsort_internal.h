@@ -115,20 +115,23 @@ struct GsdLayout {
     uint32_t p;                 // blocks = buckets (the request clamped to n)
     uint32_t s;                 // samples per block, r p
     uint32_t tiles_per_block;   // route workgroups per block
-    size_t nT;                  // sample size p s
-    LsdR8Layout LT;             // the sample's sort
+    size_t nT;                  // sample size: p s (GSD), s p - 1 (GER)
+    bool random;                // GER: random sample
+    LsdR8Layout LT;             // the sample's sort by key (with positions)
+    LsdR8Layout LTk;            // GER: the sort of the drawn positions
     DevSegLayout LS;            // local sort and bucket finish
     size_t off_lo, off_boff, off_bsize, off_coloff, off_Tk, off_Tg, off_Sk, off_Sg, off_lsd,
         off_Y, off_YV, off_seg;
     size_t bytes;
 };
 GsdLayout gsd_layout(bool has_vals, size_t n, uint32_t p, uint32_t r);
+GsdLayout ger_layout(bool has_vals, size_t n, uint32_t p, uint32_t s);
 // Statistics area (device, u32): split bounds p x (p+1), splitter keys (p),
 // splitter indexes (p).
 size_t gsd_stats_words(uint32_t p);
 hipError_t gsd_sort(const uint32_t* keys_in, uint32_t* keys_out, const uint32_t* vals_in,
-                    uint32_t* vals_out, size_t n, const GsdLayout& L, void* ws, uint32_t* stats,
-                    uint32_t* dev_err, hipStream_t stream, Profiler* prof);
+                    uint32_t* vals_out, size_t n, const GsdLayout& L, uint64_t seed, void* ws,
+                    uint32_t* stats, uint32_t* dev_err, hipStream_t stream, Profiler* prof);
 
 // Plain device copy used when a sort moves nothing (empty bit range).
 hipError_t copy_bytes(void* dst, const void* src, size_t bytes, hipStream_t stream);

@@ -1,5 +1,8 @@
 // Deterministic regular-oversampling sample sort (GSD, arXiv 1808.10292
-// Section 3.3, Algorithm 1) for 32-bit keys with an optional 32-bit payload.
+// Section 3.3, Algorithm 1) for 32-bit keys with an optional 32-bit payload,
+// and its random-oversampling sibling GER (Algorithm 2), which differs only in
+// step 2: s p - 1 sample keys drawn uniformly at random (with replacement)
+// from the locally sorted blocks, sorted by (key, position).
 //
 //   1. local sort     the n keys are cut into p near-equal blocks
 //                     (block k = [floor(kn/p), floor((k+1)n/p))) and every block
@@ -57,6 +60,36 @@ __global__ void k_gsd_sample(const uint32_t* __restrict__ X, const uint32_t* lo,
     const uint32_t q = (uint32_t)((j * nk + s - 1) / s - 1);
     Tk[t] = X[b + q];
     Tg[t] = b + q;
+}
+
+// GER (Algorithm 2) step 2: draw i of the random sample is the position
+// ((SplitMix64 value i of stream seed) >> 32) * n >> 32, uniform in [0, n)
+// with replacement.  SplitMix64 (Steele, Lea, Flood 2014) used counter-based:
+// value i = mix(seed + (i + 1) * golden gamma).
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t i)
+{
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ void k_ger_draw(uint64_t seed, uint32_t n, size_t m, uint32_t* pos)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    pos[i] = (uint32_t)(((splitmix64_at(seed, i) >> 32) * (uint64_t)n) >> 32);
+}
+
+// Sample composites (key, position) in position order.
+__global__ void k_ger_gather(const uint32_t* __restrict__ X, const uint32_t* pos_sorted, size_t m,
+                             uint32_t* Tk, uint32_t* Tg)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const uint32_t q = pos_sorted[i];
+    Tk[i] = X[q];
+    Tg[i] = q;
 }
 
 // Composite order (key, index).
@@ -221,15 +254,18 @@ __global__ __launch_bounds__(kRouteWG) void k_gsd_route(const uint32_t* __restri
 
 }  // namespace
 
-GsdLayout gsd_layout(bool has_vals, size_t n, uint32_t p_req, uint32_t r)
+namespace {
+
+GsdLayout skeleton_layout(bool has_vals, size_t n, uint32_t p, uint32_t s, size_t nT, bool random)
 {
     GsdLayout L{};
-    const uint32_t p = (uint32_t)std::min<size_t>(p_req, n ? n : 1);
     L.p = p;
-    L.s = r * p;
-    L.nT = (size_t)p * L.s;
+    L.s = s;
+    L.nT = nT;
+    L.random = random;
     L.tiles_per_block = (uint32_t)((n / p + 1 + kRouteTile - 1) / kRouteTile);
     L.LT = lsd_r8_layout(4, true, L.nT, 0, 32);
+    L.LTk = lsd_r8_layout(4, false, L.nT, 0, 32);
     L.LS = devseg_layout(4, has_vals, n, p);
     size_t o = 0;
     L.off_lo = o;    o = align_up(o + (size_t)(p + 1) * 4);
@@ -240,7 +276,7 @@ GsdLayout gsd_layout(bool has_vals, size_t n, uint32_t p_req, uint32_t r)
     L.off_Tg = o;    o = align_up(o + L.nT * 4);
     L.off_Sk = o;    o = align_up(o + L.nT * 4);
     L.off_Sg = o;    o = align_up(o + L.nT * 4);
-    L.off_lsd = o;   o = align_up(o + L.LT.bytes);
+    L.off_lsd = o;   o = align_up(o + std::max(L.LT.bytes, L.LTk.bytes));
     L.off_Y = o;     o = align_up(o + n * 4);
     L.off_YV = o;    o = align_up(o + (has_vals ? n * 4 : 0));
     L.off_seg = o;   o = align_up(o + L.LS.bytes);
@@ -248,11 +284,25 @@ GsdLayout gsd_layout(bool has_vals, size_t n, uint32_t p_req, uint32_t r)
     return L;
 }
 
+}  // namespace
+
+GsdLayout gsd_layout(bool has_vals, size_t n, uint32_t p_req, uint32_t r)
+{
+    const uint32_t p = (uint32_t)std::min<size_t>(p_req, n ? n : 1);
+    return skeleton_layout(has_vals, n, p, r * p, (size_t)p * r * p, false);
+}
+
+GsdLayout ger_layout(bool has_vals, size_t n, uint32_t p_req, uint32_t s)
+{
+    const uint32_t p = (uint32_t)std::min<size_t>(p_req, n ? n : 1);
+    return skeleton_layout(has_vals, n, p, s, (size_t)s * p - 1, true);
+}
+
 size_t gsd_stats_words(uint32_t p) { return (size_t)p * (p + 1) + 2 * (size_t)p; }
 
 hipError_t gsd_sort(const uint32_t* keys_in, uint32_t* keys_out, const uint32_t* vals_in,
-                    uint32_t* vals_out, size_t n, const GsdLayout& L, void* ws, uint32_t* stats,
-                    uint32_t* dev_err, hipStream_t stream, Profiler* prof)
+                    uint32_t* vals_out, size_t n, const GsdLayout& L, uint64_t seed, void* ws,
+                    uint32_t* stats, uint32_t* dev_err, hipStream_t stream, Profiler* prof)
 {
     if (!n) return hipSuccess;
     const uint32_t p = L.p, s = L.s;
@@ -278,11 +328,24 @@ hipError_t gsd_sort(const uint32_t* keys_in, uint32_t* keys_out, const uint32_t*
     hipError_t e = devseg_sort(4, keys_in, keys_out, vals_in, vals_out, n, lo, p, small_max,
                                seg_ws, L.LS, dev_err, stream, prof);
     if (e != hipSuccess) return e;
-    // 2-3. regular sample, sorted by composite
-    hipLaunchKernelGGL(k_gsd_sample, dim3((uint32_t)((L.nT + 255) / 256)), dim3(256), 0, stream,
-                       keys_out, lo, p, s, Tk, Tg);
-    e = lsd_r8_sort(4, Tk, Sk, Tg, Sg, L.nT, 0, 32, w + L.off_lsd, L.LT, dev_err, stream, nullptr);
-    if (e != hipSuccess) return e;
+    // 2-3. the sample, sorted by composite (key, position)
+    const dim3 sg((uint32_t)((L.nT + 255) / 256));
+    if (!L.random) {
+        // GSD: regular sample, built in position order
+        hipLaunchKernelGGL(k_gsd_sample, sg, dim3(256), 0, stream, keys_out, lo, p, s, Tk, Tg);
+    } else if (L.nT) {
+        // GER: random positions, put in position order, then their keys
+        hipLaunchKernelGGL(k_ger_draw, sg, dim3(256), 0, stream, seed, (uint32_t)n, L.nT, Tg);
+        e = lsd_r8_sort(4, Tg, Sg, nullptr, nullptr, L.nT, 0, 32, w + L.off_lsd, L.LTk, dev_err,
+                        stream, nullptr);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_ger_gather, sg, dim3(256), 0, stream, keys_out, Sg, L.nT, Tk, Tg);
+    }
+    if (L.nT) {   // stable by key: ties stay in position order
+        e = lsd_r8_sort(4, Tk, Sk, Tg, Sg, L.nT, 0, 32, w + L.off_lsd, L.LT, dev_err, stream,
+                        nullptr);
+        if (e != hipSuccess) return e;
+    }
     // 4-5. splitters and split
     const uint32_t nb = p * (p + 1);
     hipLaunchKernelGGL(k_gsd_split, dim3((nb + 255) / 256), dim3(256), 0, stream, keys_out, lo, p,

@@ -45,7 +45,8 @@ EXPORTED = ("rsort_create", "rsort_destroy", "rsort_status_string", "rsort_last_
             "rsort_profile_enable", "rsort_profile_read", "rsort_segmented_sort",
             "rsort_segmented_workspace_bytes", "rsort_segmented_set_split",
             "rsort_segmented_tune", "rsort_sample_sort", "rsort_sample_sort_workspace_bytes",
-            "rsort_sample_sort_stats", "rsort_segmented_sort_device",
+            "rsort_sample_sort_stats", "rsort_sample_sort_random",
+            "rsort_sample_sort_random_workspace_bytes", "rsort_segmented_sort_device",
             "rsort_segmented_device_workspace_bytes", "rsort_server_create", "rsort_server_submit",
             "rsort_server_poll", "rsort_server_wait", "rsort_server_latency",
             "rsort_server_reset_stats", "rsort_server_destroy")
@@ -103,6 +104,10 @@ def load_library():
         lib.rsort_sample_sort.argtypes = [vp, i, vp, vp, u32p, u32p, sz, i, i, vp, sz, vp]
         lib.rsort_sample_sort_workspace_bytes.argtypes = [vp, i, i, sz, i, i, ctypes.POINTER(sz)]
         lib.rsort_sample_sort_stats.argtypes = [vp, i, ctypes.POINTER(i), vp, vp, vp, vp]
+        lib.rsort_sample_sort_random.argtypes = [vp, i, vp, vp, u32p, u32p, sz, i, i,
+                                                 ctypes.c_uint64, vp, sz, vp]
+        lib.rsort_sample_sort_random_workspace_bytes.argtypes = [vp, i, i, sz, i, i,
+                                                                 ctypes.POINTER(sz)]
         lib.rsort_segmented_sort_device.argtypes = [vp, i, vp, vp, u32p, u32p, vp, sz, sz, vp, sz,
                                                     vp]
         lib.rsort_segmented_device_workspace_bytes.argtypes = [vp, i, i, sz, sz, ctypes.POINTER(sz)]
@@ -428,6 +433,33 @@ def rsort_sample_sort_workspace_bytes(key_dtype, has_vals, n, p=256, r=32, devic
                                                          int(n), int(p), int(r),
                                                          ctypes.byref(out)),
               "rsort_sample_sort_workspace_bytes")
+    return out.value
+
+
+def rsort_sample_sort_random(keys_in, keys_out, vals_in=None, vals_out=None, p=256, s=0,
+                             seed=0x18081029, workspace=None, stream=None):
+    """GER sample sort (p buckets, s p - 1 random sample keys, s = 0: default)."""
+    kt = _key_type(keys_in)
+    n = _check_kv(keys_in, keys_out, vals_in, vals_out)
+    ctx = context(keys_in.device)
+    ws_ptr, ws_bytes = None, 0
+    if workspace is not None:
+        ws_ptr, ws_bytes = _ptr(workspace), workspace.numel() * workspace.element_size()
+    rc = ctx._lib.rsort_sample_sort_random(ctx.handle, kt, _ptr(keys_in), _ptr(keys_out),
+                                           _ptr(vals_in), _ptr(vals_out), n, int(p), int(s),
+                                           int(seed) & 0xFFFFFFFFFFFFFFFF, ws_ptr, ws_bytes,
+                                           _stream_handle(stream))
+    ctx.check(rc, "rsort_sample_sort_random")
+    return keys_out, vals_out
+
+
+def rsort_sample_sort_random_workspace_bytes(key_dtype, has_vals, n, p=256, s=0, device=None):
+    ctx = context(device)
+    kt = _key_type(torch.empty(0, dtype=key_dtype))
+    out = ctypes.c_size_t()
+    ctx.check(ctx._lib.rsort_sample_sort_random_workspace_bytes(
+        ctx.handle, kt, int(bool(has_vals)), int(n), int(p), int(s), ctypes.byref(out)),
+        "rsort_sample_sort_random_workspace_bytes")
     return out.value
 
 

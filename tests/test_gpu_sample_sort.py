@@ -1,5 +1,6 @@
 """GPU parity of the regular-oversampling sample sort (GSD, Algorithm 1)
-against the oracle's GSD.
+against the oracle's GSD, and of the random-oversampling variant (GER,
+Algorithm 2) against the oracle's GER fed the same random draws.
 
 Compared bit-exactly: the sorted keys and payloads, the p x p split matrix
 cnt[k][j] = |X_{k,j}|, the bucket sizes and the p - 1 splitter composites
@@ -162,6 +163,88 @@ def test_graph_capture_replays(rs):
     g.replay()
     torch.cuda.synchronize()
     assert np.array_equal(host(ko), oracle.gsd(keys2, vals, 256, 32)["keys"])
+
+
+# ---------------------------------------------------------------------------
+# GER (Algorithm 2): the random sample is drawn on the GPU from SplitMix64
+# stream `seed`; the oracle gets the same draws from the input generator.
+
+def run_ger(rs, keys, p, s, seed, with_vals=True):
+    import torch
+    n = keys.size
+    pu = min(p, n)
+    vals = np.arange(n, dtype=np.uint32)
+    pos = keygen.sample_positions(seed, s * pu - 1, n)
+    want = oracle.ger(keys, vals if with_vals else None, p, s, pos)
+    dk = dev(keys)
+    dv = dev(vals) if with_vals else None
+    ko = torch.empty_like(dk)
+    vo = torch.empty_like(dv) if with_vals else None
+    rs.rsort_sample_sort_random(dk, ko, dv, vo, p=p, s=s, seed=seed)
+    rs.rsort_synchronize()
+    assert np.array_equal(host(ko), want["keys"])
+    if with_vals:
+        assert np.array_equal(host(vo), want["vals"])
+    st = rs.rsort_sample_sort_stats()
+    assert st["p"] == want["p"]
+    assert np.array_equal(st["cnt"].astype(np.uint64), want["cnt"])
+    assert np.array_equal(st["split_key"], want["split_key"])
+    assert np.array_equal(st["split_index"].astype(np.uint64), want["split_g"])
+    return st
+
+
+@pytest.mark.parametrize("dist", keygen.KV_DISTRIBUTIONS)
+def test_ger_distributions(rs, dist):
+    n = 1000003
+    announce("ger", dist, n)
+    run_ger(rs, keygen.kv_keys(dist, n), 256, 40, 0x5EED + len(dist))
+
+
+@pytest.mark.parametrize("n,p,s", [(1, 256, 3), (2, 4, 1), (999, 9, 1), (1000, 1, 5),
+                                   (50000, 7, 300), (65536, 1024, 4), (300007, 256, 140)])
+def test_ger_shapes(rs, n, p, s):
+    announce("ger shape", n, p, s)
+    run_ger(rs, keygen.zipf_keys(n, 60 + p), p, s, 1000 + n)
+
+
+def test_ger_default_oversampling_and_keys_only(rs):
+    """s = 0 takes s = 2 w^2 lg n, w = ceil(lg lg n): 2 * 25 * 22 = 1100 at n = 2^22."""
+    import torch
+    n = 1 << 22
+    announce("ger default", n)
+    keys = keygen.uniform_u32(n, 61)
+    run_ger(rs, keys, 256, 1100, 7, with_vals=False)
+    ko = torch.empty_like(dev(keys))
+    rs.rsort_sample_sort_random(dev(keys), ko, p=256, s=0, seed=7)
+    rs.rsort_synchronize()
+    assert np.array_equal(host(ko), oracle.sr4(keys)[0])
+    need0 = rs.rsort_sample_sort_random_workspace_bytes(torch.uint32, False, n, 256, 0)
+    need1 = rs.rsort_sample_sort_random_workspace_bytes(torch.uint32, False, n, 256, 1100)
+    assert need0 == need1
+    with pytest.raises(rs.RsortError) as e:
+        rs.rsort_sample_sort_random(dev(keys), ko, p=1024, s=1 << 17)
+    assert e.value.status == rs.RSORT_EUNSUPPORTED
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("dist", ["uniform", "zipf", "equal"])
+def test_ger_full_size_kv(rs, dist):
+    """2^28 pairs, p = 256, default s: the stable sort (four invariants) and
+    buckets near n/p (Lemma 2 bounds them with high probability)."""
+    import torch
+    n = 1 << 28
+    announce("ger full", dist, n)
+    keys = keygen.kv_keys(dist, n)
+    dk = dev(keys)
+    dv = torch.arange(n, dtype=torch.int32, device="cuda")
+    ko, vo = torch.empty_like(dk), torch.empty_like(dv)
+    rs.rsort_sample_sort_random(dk, ko, dv, vo, p=256, s=0, seed=11)
+    rs.rsort_synchronize()
+    del dk
+    st = rs.rsort_sample_sort_stats()
+    assert int(st["bucket"].astype(np.uint64).sum()) == n
+    assert int(st["bucket"].max()) <= 1.25 * n / 256
+    check_kv_invariants(keys, host(ko), host(vo).view(np.uint32))
 
 
 @pytest.mark.slow
