@@ -12,6 +12,8 @@ The arithmetic lives in ``sr4.c`` (plain serial C, built with gcc into
 * ``digit_counts``  -- the counting loop of one count-sort round.
 * ``gsd``           -- Section 3.3 Algorithm 1 (GSD) steps 1-5, returning the
                        intermediate split counts and splitters as well.
+* ``ger``, ``gvr``   -- Section 3.3 Algorithms 2 and 3 with their random draws
+                       passed in as positions.
 * ``segmented``     -- SR4 on every CSR segment.
 """
 from __future__ import annotations
@@ -60,6 +62,9 @@ def _configure(lib):
     lib.ger_u32.argtypes = [vp, vp, sz, i, i, vp, sz, vp, vp, vp, vp, vp,
                             ctypes.POINTER(ctypes.c_int)]
     lib.ger_u32.restype = i
+    lib.gvr_u32.argtypes = [vp, vp, sz, i, i, vp, sz, vp, vp, vp, vp, vp,
+                            ctypes.POINTER(ctypes.c_int)]
+    lib.gvr_u32.restype = i
     return lib
 
 
@@ -163,11 +168,22 @@ def gsd(keys, vals, p: int, r: int):
             "bucket": cnt.sum(axis=0)}
 
 
+def gvr(keys, vals, p: int, s: int, positions):
+    """GVR (Algorithm 3) on uint32 keys with the random draws given:
+    ``positions`` (at least s*min(p, n) - 1, each < n) index the INPUT.
+    cnt[k, j] = elements of input block k in bucket j.  Same dict as ``gsd``."""
+    return _skeleton_random("gvr_u32", keys, vals, p, s, positions)
+
+
 def ger(keys, vals, p: int, s: int, positions):
     """GER (Algorithm 2) on uint32 keys with the random draws given:
     ``positions`` (uint32, at least s*min(p, n) - 1 of them, each < n) are the
     sample positions into the locally sorted blocks.  Returns the same dict as
     ``gsd``."""
+    return _skeleton_random("ger_u32", keys, vals, p, s, positions)
+
+
+def _skeleton_random(fn, keys, vals, p: int, s: int, positions):
     keys = np.ascontiguousarray(keys, dtype=np.uint32)
     n = keys.size
     if vals is not None:
@@ -180,10 +196,10 @@ def ger(keys, vals, p: int, s: int, positions):
     sk = np.zeros(max(pmax - 1, 1), dtype=np.uint32)
     sg = np.zeros(max(pmax - 1, 1), dtype=np.uint64)
     used = ctypes.c_int(0)
-    rc = _load().ger_u32(_ptr(keys), _ptr(vals), n, p, s, _ptr(pos), pos.size, _ptr(ko),
-                         _ptr(vo), _ptr(cnt), _ptr(sk), _ptr(sg), ctypes.byref(used))
+    rc = getattr(_load(), fn)(_ptr(keys), _ptr(vals), n, p, s, _ptr(pos), pos.size, _ptr(ko),
+                              _ptr(vo), _ptr(cnt), _ptr(sk), _ptr(sg), ctypes.byref(used))
     if rc:
-        raise ValueError("oracle ger failed (%d)" % rc)
+        raise ValueError("oracle %s failed (%d)" % (fn, rc))
     pu = used.value
     cnt = cnt.reshape(pu, pu)
     return {"keys": ko, "vals": vo, "p": pu, "cnt": cnt,

@@ -23,6 +23,12 @@
  *   digit_counts_*     the counting loop of one round on its own.
  *   gsd_u32            Section 3.3, Algorithm 1 (GSD), steps 1-5, with the
  *                      readings listed at the function.
+ *   ger_u32            Section 3.3, Algorithm 2 (GER): GSD's skeleton with a
+ *                      random sample of the locally sorted blocks.
+ *   gvr_u32            Section 3.3, Algorithm 3 (GVR): a random sample of the
+ *                      input, splitting of the unsorted blocks by binary search
+ *                      and a count sort on the bucket index, then SR4 per
+ *                      bucket.  The random draws of both are caller inputs.
  *   segmented_u32/u64  SR4 applied independently to each segment of a CSR
  *                      segment list (the batched workload).
  *
@@ -461,5 +467,105 @@ int ger_u32(const uint32_t* keys_in, const uint32_t* vals_in, size_t n, int p_re
 
 done:
     free(X); free(XV); free(lo); free(Tk); free(Tg); free(Uk); free(Ug);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* GVR, Algorithm 3 (Section 3.3): sample first, split the unsorted blocks,
+ * sort each bucket.
+ *
+ * Readings where the paper is silent:
+ *  - Blocks X_k = [floor(k n / p), floor((k+1) n / p)) of the input, p clamped
+ *    to n.
+ *  - Step 1 draws s p - 1 keys uniformly at random, with replacement, from the
+ *    input: the draws are the caller's input positions pos[0 .. s p - 1).
+ *    Sample element i is the composite (x[pos[i]], pos[i]); the sample is
+ *    sorted by composite (SR4 by position, then SR4 by key) instead of BTN.
+ *  - Step 2: splitter i is the (i s)-th smallest sample composite.
+ *  - Step 3: an element e = (x_q, q) of block k belongs to X_{k,j} with
+ *    j = #{i : S_i < e} (binary search over the splitters); X_{k,j} keeps input
+ *    order (a stable count sort by j).
+ *  - Step 4: Y_j = X_{0,j} ... X_{p-1,j} is sorted by SR4 (stable), so equal
+ *    keys stay in input order and the result is the stable sort.
+ */
+int gvr_u32(const uint32_t* keys_in, const uint32_t* vals_in, size_t n, int p_req, int s_req,
+            const uint32_t* pos, size_t npos, uint32_t* keys_out, uint32_t* vals_out,
+            uint64_t* cnt /* p*p */, uint32_t* split_key /* p-1 */,
+            uint64_t* split_g /* p-1 */, int* p_used)
+{
+    if (p_req < 1 || s_req < 1 || n == 0 || n >= ((uint64_t)1 << 32) ||
+        !keys_in || !keys_out || (vals_in && !vals_out))
+        return -1;
+    size_t p = (size_t)p_req < n ? (size_t)p_req : n;
+    *p_used = (int)p;
+    const size_t s = (size_t)s_req;
+    const size_t m = s * p - 1;
+    if (npos < m || (m && !pos)) return -1;
+    for (size_t i = 0; i < m; ++i)
+        if (pos[i] >= n) return -1;
+
+    uint32_t* Tk = (uint32_t*)malloc((m ? m : 1) * sizeof(uint32_t));
+    uint32_t* Tg = (uint32_t*)malloc((m ? m : 1) * sizeof(uint32_t));
+    uint32_t* Uk = (uint32_t*)malloc((m ? m : 1) * sizeof(uint32_t));
+    uint32_t* Ug = (uint32_t*)malloc((m ? m : 1) * sizeof(uint32_t));
+    uint32_t* bucket = (uint32_t*)malloc(n * sizeof(uint32_t));
+    uint64_t* start = (uint64_t*)malloc((p + 1) * sizeof(uint64_t));
+    uint32_t* Y = (uint32_t*)malloc(n * sizeof(uint32_t));
+    uint32_t* YV = vals_in ? (uint32_t*)malloc(n * sizeof(uint32_t)) : NULL;
+    int rc = 0;
+    if (!Tk || !Tg || !Uk || !Ug || !bucket || !start || !Y || (vals_in && !YV)) {
+        rc = -2;
+        goto done;
+    }
+    /* step 1: the random sample, sorted by (key, position) */
+    for (size_t i = 0; i < m; ++i) {
+        Tg[i] = pos[i];
+        Tk[i] = keys_in[pos[i]];
+    }
+    rc = lsd_u32(Tg, Tk, m, 8, 0, 32, Ug, Uk);        /* by input position */
+    if (rc) goto done;
+    rc = lsd_u32(Uk, Ug, m, 8, 0, 32, Tk, Tg);        /* then by key, stably */
+    if (rc) goto done;
+    /* step 2: splitters */
+    for (size_t i = 1; i < p; ++i) {
+        split_key[i - 1] = Tk[i * s - 1];
+        split_g[i - 1] = Tg[i * s - 1];
+    }
+    /* step 3: bucket of every element = number of splitters below it */
+    memset(cnt, 0, p * p * sizeof(uint64_t));
+    for (size_t q = 0; q < n; ++q) {
+        size_t a = 0, e = p - 1;                      /* first splitter not below x_q */
+        while (a < e) {
+            size_t mid = a + (e - a) / 2;
+            if (comp_less(split_key[mid], split_g[mid], keys_in[q], q))
+                a = mid + 1;
+            else
+                e = mid;
+        }
+        bucket[q] = (uint32_t)a;
+        size_t k = (size_t)(((unsigned __int128)q * p + p - 1) / n);   /* q's block */
+        while (k > 0 && (uint64_t)((k * (unsigned __int128)n) / p) > q) --k;
+        while ((uint64_t)(((k + 1) * (unsigned __int128)n) / p) <= q) ++k;
+        cnt[k * p + a] += 1;
+    }
+    /* route: Y_j = the elements of bucket j in input order (stable count sort) */
+    memset(start, 0, (p + 1) * sizeof(uint64_t));
+    for (size_t q = 0; q < n; ++q) start[bucket[q] + 1] += 1;
+    for (size_t j = 0; j < p; ++j) start[j + 1] += start[j];
+    for (size_t q = 0; q < n; ++q) {
+        uint64_t o = start[bucket[q]]++;
+        Y[o] = keys_in[q];
+        if (vals_in) YV[o] = vals_in[q];
+    }
+    /* step 4: every bucket sorted by SR4; start[j] is now the end of bucket j */
+    for (size_t j = 0; j < p; ++j) {
+        uint64_t lo = j ? start[j - 1] : 0, hi = start[j];
+        rc = lsd_u32(Y + lo, vals_in ? YV + lo : NULL, hi - lo, 8, 0, 32, keys_out + lo,
+                     vals_in ? vals_out + lo : NULL);
+        if (rc) goto done;
+    }
+
+done:
+    free(Tk); free(Tg); free(Uk); free(Ug); free(bucket); free(start); free(Y); free(YV);
     return rc;
 }

@@ -384,6 +384,69 @@ def test_ger_small_and_degenerate():
         oracle.ger(np.arange(10, dtype=np.uint32), None, 2, 1, np.array([10], dtype=np.uint32))
 
 
+# ---------------------------------------------------------------------------
+# GVR (Algorithm 3): random sample of the INPUT (draws = input positions), the
+# unsorted blocks split by binary search + a count sort on the bucket index,
+# then SR4 on every bucket.
+
+@pytest.mark.parametrize("dist", ["uniform", "zipf", "equal", "low16"])
+def test_gvr_output_split_and_splitters(dist):
+    """Sorted output = the stable sort; splitters = the (i s)-th smallest
+    (key, input position) sample composites; cnt[k, j] = elements of input
+    block k whose composite lies in (S_{j-1}, S_j]; all by brute force from
+    the definition of Algorithm 3."""
+    n, p, s = 20011, 12, 9
+    keys = keygen.kv_keys(dist, n)
+    idx = np.arange(n, dtype=np.uint32)
+    pos = keygen.sample_positions(4321 + len(dist), s * p - 1, n)
+    res = oracle.gvr(keys, idx, p, s, pos)
+    assert np.array_equal(res["vals"], np.argsort(keys, kind="stable").astype(np.uint32))
+    assert np.array_equal(res["keys"], np.sort(keys, kind="stable"))
+    sample = sorted((int(keys[q]), int(q)) for q in pos)
+    want = [sample[i * s - 1] for i in range(1, p)]
+    got = list(zip(res["split_key"].tolist(), res["split_g"].tolist()))
+    assert got == want
+    bounds = [(k * n) // p for k in range(p + 1)]
+    for k in range(p):
+        for j in range(p):
+            lo_s = want[j - 1] if j > 0 else None
+            hi_s = want[j] if j < p - 1 else None
+            c = sum(1 for q in range(bounds[k], bounds[k + 1])
+                    if (lo_s is None or (int(keys[q]), q) > lo_s) and
+                    (hi_s is None or (int(keys[q]), q) <= hi_s))
+            assert res["cnt"][k, j] == c, (k, j)
+    assert int(res["cnt"].sum()) == n
+
+
+def test_gvr_small_and_degenerate():
+    """p = 1 (no splitters), p clamped to n, s = 1, repeated draws, and a
+    sample drawn from one position only (every splitter equal)."""
+    rng = np.random.default_rng(5)
+    for n, p, s in [(1, 4, 3), (7, 16, 2), (1000, 1, 5), (999, 9, 1), (4096, 8, 40)]:
+        keys = rng.integers(0, 30, size=n, dtype=np.uint64).astype(np.uint32)
+        idx = np.arange(n, dtype=np.uint32)
+        pu = min(p, n)
+        pos = keygen.sample_positions(91 + n, max(s * pu - 1, 0), n)
+        res = oracle.gvr(keys, idx, p, s, pos)
+        assert res["p"] == pu
+        assert np.array_equal(res["vals"], np.argsort(keys, kind="stable").astype(np.uint32))
+        assert int(res["cnt"].sum()) == n
+        bounds = [(k * n) // pu for k in range(pu + 1)]
+        assert np.array_equal(res["cnt"].sum(axis=1), np.diff(bounds).astype(np.uint64))
+    # one repeated draw: all splitters are (x_q, q); everything at or below goes
+    # to bucket 0, the rest to bucket p - 1
+    n, p, s, q = 500, 5, 3, 123
+    keys = rng.integers(0, 10, size=n, dtype=np.uint64).astype(np.uint32)
+    res = oracle.gvr(keys, None, p, s, np.full(s * p - 1, q, dtype=np.uint32))
+    below = sum(1 for i in range(n) if (int(keys[i]), i) <= (int(keys[q]), q))
+    assert res["bucket"].tolist() == [below, 0, 0, 0, n - below]
+    assert np.array_equal(res["keys"], np.sort(keys))
+    with pytest.raises(ValueError):
+        oracle.gvr(np.arange(10, dtype=np.uint32), None, 2, 3, np.array([0, 1], dtype=np.uint32))
+    with pytest.raises(ValueError):
+        oracle.gvr(np.arange(10, dtype=np.uint32), None, 2, 1, np.array([10], dtype=np.uint32))
+
+
 def test_sample_positions_closed_form():
     """Position i is floor((splitmix64 value i >> 32) * n / 2^32)."""
     z = keygen.splitmix64(5, 8)

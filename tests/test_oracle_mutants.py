@@ -1,8 +1,9 @@
 """Plausible mistakes planted in a copy of the oracle must fail its pins.
 
 Each mutant is the oracle source with one textual change (a dropped round, an
-unstable output loop, an off-by-one sample or splitter index, a reversed
-tie-break, a strict/non-strict comparison swapped).  The copy is compiled into
+unstable output or routing loop, an off-by-one sample or splitter index, a
+reversed tie-break, a strict/non-strict comparison swapped, a sample left
+unordered by position).  The copy is compiled into
 a temporary library and the pins of ``test_oracle.py`` are run against it in a
 child process: at least one must fail (a crash of the child counts as caught).
 """
@@ -44,6 +45,15 @@ MUTANTS = {
     "ger_sample_not_ordered_by_position": (
         "rc = lsd_u32(Tg, Tk, m, 8, 0, 32, Ug, Uk);        /* by position */",
         "memcpy(Ug, Tg, m * 4); memcpy(Uk, Tk, m * 4);"),
+    "gvr_sample_not_ordered_by_position": (
+        "rc = lsd_u32(Tg, Tk, m, 8, 0, 32, Ug, Uk);        /* by input position */",
+        "memcpy(Ug, Tg, m * 4); memcpy(Uk, Tk, m * 4);"),
+    "gvr_bucket_search_nonstrict": (
+        "if (comp_less(split_key[mid], split_g[mid], keys_in[q], q))",
+        "if (!comp_less(keys_in[q], q, split_key[mid], split_g[mid]))"),
+    "gvr_route_backward": (
+        "    for (size_t q = 0; q < n; ++q) {\n        uint64_t o = start[bucket[q]]++;",
+        "    for (size_t q = n; q-- > 0;) {\n        uint64_t o = start[bucket[q]]++;"),
     "split_strict_instead_of_nonstrict": (
         "if (!comp_less(split_key[i - 1], split_g[i - 1], X[lo[k] + mid], lo[k] + mid))",
         "if (comp_less(X[lo[k] + mid], lo[k] + mid, split_key[i - 1], split_g[i - 1]))"),
@@ -61,6 +71,9 @@ PINS = [
     pins.test_gsd_splitters_brute_force,
     lambda: pins.test_ger_output_split_and_splitters("zipf"),
     lambda: pins.test_ger_output_split_and_splitters("equal"),
+    lambda: pins.test_gvr_output_split_and_splitters("zipf"),
+    lambda: pins.test_gvr_output_split_and_splitters("equal"),
+    pins.test_gvr_small_and_degenerate,
 ]
 
 
