@@ -151,12 +151,13 @@ def identity_rounds(np, keys, digit_bits=8):
 
 
 def bench_kv(rsort, torch, np, keygen, args):
-    """Key-value sort, radix (PR4) against the regular-oversampling sample sort
-    (GSD, p = 256 buckets, oversampling factor r = 32): 2^28 pairs by default
-    (uint32 key, uint32 payload = input index) per key distribution."""
+    """Key-value sort, radix (PR4) against the sample sorts: regular
+    oversampling (GSD, p = 256 buckets, oversampling factor r = 32) and the two
+    random-oversampling ones (GER, GVR; p = 256, s = 2 w^2 lg n): 2^28 pairs by
+    default (uint32 key, uint32 payload = input index) per key distribution."""
     n = 1 << args.kv_log2n
     res = {"workload": "2^%d (uint32 key, uint32 payload = input index) pairs; PR4 vs GSD "
-                       "p=256 r=32 vs GER p=256 s=2w^2 lg n" % args.kv_log2n, "n": n,
+                       "p=256 r=32 vs GER and GVR p=256 s=2w^2 lg n" % args.kv_log2n, "n": n,
            "algorithmic_bytes_per_pass": 2 * n * 8}
     dv = torch.arange(n, dtype=torch.int32, device="cuda")
     ko = torch.empty(n, dtype=torch.uint32, device="cuda")
@@ -171,7 +172,9 @@ def bench_kv(rsort, torch, np, keygen, args):
         fns = {"lsd8": lambda: rsort.rsort_sort(dk, ko, dv, vo, algo="lsd8"),
                "sample": lambda: rsort.rsort_sample_sort(dk, ko, dv, vo, p=256, r=32),
                "sample_random": lambda: rsort.rsort_sample_sort_random(dk, ko, dv, vo, p=256,
-                                                                       s=0, seed=11)}
+                                                                       s=0, seed=11),
+               "sample_gvr": lambda: rsort.rsort_sample_sort_gvr(dk, ko, dv, vo, p=256, s=0,
+                                                                 seed=12)}
         buckets = {}
         for algo, fn in fns.items():
             sec = time_steps(fn, steps, 1, torch)
@@ -195,6 +198,7 @@ def bench_kv(rsort, torch, np, keygen, args):
         row["sample"]["max_bucket"] = buckets["sample"]
         row["sample"]["lemma1_bound"] = round((1 + 1 / 32) * n / 256 + 32 * 256, 1)
         row["sample_random"]["max_bucket"] = buckets["sample_random"]
+        row["sample_gvr"]["max_bucket"] = buckets["sample_gvr"]
         res[dist] = row
         del dk
     return res

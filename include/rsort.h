@@ -224,7 +224,7 @@ int rsort_sample_sort_workspace_bytes(rsort_ctx* ctx, int key_type, int has_vals
  * again the stable sort.  s = 0 selects s = 2 w^2 lg n with w = ceil(lg lg n)
  * (the paper's s = 2 w_n^2 lg n); s p <= 2^26.  Bucket sizes are bounded with
  * high probability (Lemma 2), not deterministically.  The statistics call
- * reports the split of the last sample sort of either kind.
+ * reports the split of the last sample sort of any kind.
  */
 int rsort_sample_sort_random(rsort_ctx* ctx, int key_type, const void* keys_in, void* keys_out,
                              const uint32_t* vals_in, uint32_t* vals_out, size_t n, int p, int s,
@@ -233,6 +233,29 @@ int rsort_sample_sort_random(rsort_ctx* ctx, int key_type, const void* keys_in, 
 /* Workspace rsort_sample_sort_random needs for (n, p, s, payload). */
 int rsort_sample_sort_random_workspace_bytes(rsort_ctx* ctx, int key_type, int has_vals, size_t n,
                                              int p, int s, size_t* bytes);
+
+/*
+ * Random-oversampling sample sort that samples before sorting, GVR (Section
+ * 3.3, Algorithm 3).  The input is cut into p blocks as in GSD but not sorted
+ * first.  s p - 1 positions of the INPUT are drawn exactly as in GER (same
+ * generator, same seed semantics, here indexing the input), the keys there are
+ * ordered by (key, input index) and splitter i is the (i s)-th smallest of
+ * them.  Every element goes to the bucket counted by the splitters below its
+ * (key, input index) -- a binary search over the splitters -- and is moved
+ * there by a stable count sort on the bucket index, so bucket j is X_{0,j}
+ * ... X_{p-1,j} with each X_{k,j} in input order; then every bucket is
+ * stable-sorted.  The result is the stable sort.  s = 0 selects s = 2 w^2 lg n
+ * as for GER; 1 <= p <= 256 (one 8-bit routing digit), s p <= 2^26.  The
+ * statistics call reports cnt[k][j] for the input blocks k.  Same pointer,
+ * overlap, workspace, stream and error rules as rsort_sort.
+ */
+int rsort_sample_sort_gvr(rsort_ctx* ctx, int key_type, const void* keys_in, void* keys_out,
+                          const uint32_t* vals_in, uint32_t* vals_out, size_t n, int p, int s,
+                          uint64_t seed, void* workspace, size_t ws_bytes, void* stream);
+
+/* Workspace rsort_sample_sort_gvr needs for (n, p, s, payload). */
+int rsort_sample_sort_gvr_workspace_bytes(rsort_ctx* ctx, int key_type, int has_vals, size_t n,
+                                          int p, int s, size_t* bytes);
 
 /*
  * Split statistics of the last sample sort on ctx (waits for the device).

@@ -228,15 +228,16 @@ int check_arrays(rsort_ctx* ctx, int kb, const void* keys_in, const void* keys_o
     return RSORT_OK;
 }
 
-// p and the oversampling parameter q: r for GSD (sample r p^2), s for GER
-// (sample s p - 1).
-int check_gsd_params(rsort_ctx* ctx, int key_type, int p, int q, bool random = false)
+// p and the oversampling parameter q: r for GSD (sample r p^2), s for GER and
+// GVR (sample s p - 1).
+int check_gsd_params(rsort_ctx* ctx, int key_type, int p, int q, int kind = rsort::kGSD)
 {
     if (key_type != RSORT_U32)
         return fail(ctx, RSORT_EUNSUPPORTED, "the sample sort takes uint32 keys only");
-    if (p < 1 || p > kMaxP) return fail(ctx, RSORT_EINVAL, "p = %d outside [1, %d]", p, kMaxP);
+    const int pmax = kind == rsort::kGVR ? (int)rsort::kGvrMaxP : kMaxP;
+    if (p < 1 || p > pmax) return fail(ctx, RSORT_EINVAL, "p = %d outside [1, %d]", p, pmax);
     if (q < 1) return fail(ctx, RSORT_EINVAL, "oversampling %d < 1", q);
-    const uint64_t sample = random ? (uint64_t)q * p : (uint64_t)q * p * p;
+    const uint64_t sample = kind != rsort::kGSD ? (uint64_t)q * p : (uint64_t)q * p * p;
     if (sample > kMaxSample)
         return fail(ctx, RSORT_EUNSUPPORTED, "sample of %llu keys above 2^26",
                     (unsigned long long)sample);
@@ -331,13 +332,20 @@ int rsort_sample_sort_workspace_bytes(rsort_ctx* ctx, int key_type, int has_vals
 
 namespace {
 
-// Shared part of the two sample sorts once the layout is known.
+rsort::GsdLayout skeleton_layout(int kind, bool has_vals, size_t n, int p, int q)
+{
+    if (kind == rsort::kGER) return rsort::ger_layout(has_vals, n, (uint32_t)p, (uint32_t)q);
+    if (kind == rsort::kGVR) return rsort::gvr_layout(has_vals, n, (uint32_t)p, (uint32_t)q);
+    return rsort::gsd_layout(has_vals, n, (uint32_t)p, (uint32_t)q);
+}
+
+// Shared part of the sample sorts once the layout is known.
 int run_skeleton(rsort_ctx* ctx, int key_type, const void* keys_in, void* keys_out,
-                 const uint32_t* vals_in, uint32_t* vals_out, size_t n, bool random, int p, int s,
+                 const uint32_t* vals_in, uint32_t* vals_out, size_t n, int kind, int p, int s,
                  uint64_t seed, void* workspace, size_t ws_bytes, void* stream)
 {
     ctx->last_error.clear();
-    int rc = check_gsd_params(ctx, key_type, p, s, random);
+    int rc = check_gsd_params(ctx, key_type, p, s, kind);
     if (rc) return rc;
     if ((vals_in == nullptr) != (vals_out == nullptr))
         return fail(ctx, RSORT_EINVAL, "vals_in and vals_out must both be NULL or both be set");
@@ -349,9 +357,7 @@ int run_skeleton(rsort_ctx* ctx, int key_type, const void* keys_in, void* keys_o
     DeviceGuard g(ctx->device);
     rc = check_arrays(ctx, 4, keys_in, keys_out, vals_in, vals_out, n);
     if (rc) return rc;
-    const rsort::GsdLayout L =
-        random ? rsort::ger_layout(vals_in != nullptr, n, (uint32_t)p, (uint32_t)s)
-               : rsort::gsd_layout(vals_in != nullptr, n, (uint32_t)p, (uint32_t)s);
+    const rsort::GsdLayout L = skeleton_layout(kind, vals_in != nullptr, n, p, s);
     hipStream_t st = (hipStream_t)stream;
     if (!ctx->gsd_stats) {
         hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
@@ -402,7 +408,7 @@ int rsort_sample_sort(rsort_ctx* ctx, int key_type, const void* keys_in, void* k
                       void* workspace, size_t ws_bytes, void* stream)
 {
     if (!ctx) return RSORT_EINVAL;
-    return run_skeleton(ctx, key_type, keys_in, keys_out, vals_in, vals_out, n, false, p, r, 0,
+    return run_skeleton(ctx, key_type, keys_in, keys_out, vals_in, vals_out, n, rsort::kGSD, p, r, 0,
                         workspace, ws_bytes, stream);
 }
 
@@ -412,8 +418,8 @@ int rsort_sample_sort_random(rsort_ctx* ctx, int key_type, const void* keys_in, 
 {
     if (!ctx) return RSORT_EINVAL;
     if (s == 0) s = ger_default_s(n);
-    return run_skeleton(ctx, key_type, keys_in, keys_out, vals_in, vals_out, n, true, p, s, seed,
-                        workspace, ws_bytes, stream);
+    return run_skeleton(ctx, key_type, keys_in, keys_out, vals_in, vals_out, n, rsort::kGER, p, s,
+                        seed, workspace, ws_bytes, stream);
 }
 
 int rsort_sample_sort_random_workspace_bytes(rsort_ctx* ctx, int key_type, int has_vals, size_t n,
@@ -421,10 +427,32 @@ int rsort_sample_sort_random_workspace_bytes(rsort_ctx* ctx, int key_type, int h
 {
     if (!ctx || !bytes) return RSORT_EINVAL;
     if (s == 0) s = ger_default_s(n);
-    int rc = check_gsd_params(ctx, key_type, p, s, true);
+    int rc = check_gsd_params(ctx, key_type, p, s, rsort::kGER);
     if (rc) return rc;
     if (n >= kMaxN) return fail(ctx, RSORT_EUNSUPPORTED, "n = %zu >= 2^30", n);
     *bytes = n ? rsort::ger_layout(has_vals != 0, n, (uint32_t)p, (uint32_t)s).bytes : 0;
+    return RSORT_OK;
+}
+
+int rsort_sample_sort_gvr(rsort_ctx* ctx, int key_type, const void* keys_in, void* keys_out,
+                          const uint32_t* vals_in, uint32_t* vals_out, size_t n, int p, int s,
+                          uint64_t seed, void* workspace, size_t ws_bytes, void* stream)
+{
+    if (!ctx) return RSORT_EINVAL;
+    if (s == 0) s = ger_default_s(n);
+    return run_skeleton(ctx, key_type, keys_in, keys_out, vals_in, vals_out, n, rsort::kGVR, p, s,
+                        seed, workspace, ws_bytes, stream);
+}
+
+int rsort_sample_sort_gvr_workspace_bytes(rsort_ctx* ctx, int key_type, int has_vals, size_t n,
+                                          int p, int s, size_t* bytes)
+{
+    if (!ctx || !bytes) return RSORT_EINVAL;
+    if (s == 0) s = ger_default_s(n);
+    int rc = check_gsd_params(ctx, key_type, p, s, rsort::kGVR);
+    if (rc) return rc;
+    if (n >= kMaxN) return fail(ctx, RSORT_EUNSUPPORTED, "n = %zu >= 2^30", n);
+    *bytes = n ? rsort::gvr_layout(has_vals != 0, n, (uint32_t)p, (uint32_t)s).bytes : 0;
     return RSORT_OK;
 }
 

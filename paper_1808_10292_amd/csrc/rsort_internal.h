@@ -110,22 +110,32 @@ hipError_t devseg_sort(int key_bytes, const void* keys_in, void* keys_out, const
                        hipStream_t stream, Profiler* prof);
 
 // ---------------------------------------------------------------------------
-// Regular-oversampling sample sort, GSD (sample_sort.hip), 32-bit keys.
+// Oversampling sample sorts (sample_sort.hip), 32-bit keys: GSD (regular
+// sample of the sorted blocks), GER (random sample of the sorted blocks) and
+// GVR (random sample of the input, no local sort, the input split around the
+// splitters by a count sort on the bucket index).
+enum SampleKind { kGSD = 0, kGER = 1, kGVR = 2 };
+constexpr uint32_t kGvrMaxP = 256;   // GVR buckets: one 8-bit routing digit
 struct GsdLayout {
     uint32_t p;                 // blocks = buckets (the request clamped to n)
-    uint32_t s;                 // samples per block, r p
+    uint32_t s;                 // samples per block (r p for GSD)
     uint32_t tiles_per_block;   // route workgroups per block
-    size_t nT;                  // sample size: p s (GSD), s p - 1 (GER)
-    bool random;                // GER: random sample
+    size_t nT;                  // sample size: p s (GSD), s p - 1 (GER, GVR)
+    int kind;                   // SampleKind
     LsdR8Layout LT;             // the sample's sort by key (with positions)
-    LsdR8Layout LTk;            // GER: the sort of the drawn positions
+    LsdR8Layout LTk;            // GER, GVR: the sort of the drawn positions
     DevSegLayout LS;            // local sort and bucket finish
     size_t off_lo, off_boff, off_bsize, off_coloff, off_Tk, off_Tg, off_Sk, off_Sg, off_lsd,
         off_Y, off_YV, off_seg;
+    // GVR route: tile counts, tile-scan state, round plan + ticket, bucket
+    // starts, and one bucket byte per key
+    uint32_t route_tpb, route_ntiles;
+    size_t off_rcounts, off_rstate, off_rplan, off_rbases, off_bkt;
     size_t bytes;
 };
 GsdLayout gsd_layout(bool has_vals, size_t n, uint32_t p, uint32_t r);
 GsdLayout ger_layout(bool has_vals, size_t n, uint32_t p, uint32_t s);
+GsdLayout gvr_layout(bool has_vals, size_t n, uint32_t p, uint32_t s);
 // Statistics area (device, u32): split bounds p x (p+1), splitter keys (p),
 // splitter indexes (p).
 size_t gsd_stats_words(uint32_t p);

@@ -27,6 +27,15 @@
 // Duplicate keys: comparing composites (key, index) instead of keys keeps the
 // bucket bound of Lemma 1 for any key distribution, and the split of equal
 // keys by index keeps the result stable.
+//
+// GVR (Algorithm 3) samples before any sorting: s p - 1 input positions drawn
+// as in GER, the keys there ordered by (key, input index), splitters picked
+// the same way.  Each input element then finds its bucket (the number of
+// splitters below its composite) by binary search, and one stable count-sort
+// round on the bucket index -- per-tile bucket counts, the device-wide tile
+// scan of the radix rounds, a rank-and-scatter -- moves the unsorted input
+// into bucket order (X_{k,j} for k = 0..p-1 concatenated is bucket j).  The
+// finish sorts every bucket as above.  p <= 256: one 8-bit routing digit.
 #include <algorithm>
 
 #include "lsd_kernels.h"
@@ -252,17 +261,278 @@ __global__ __launch_bounds__(kRouteWG) void k_gsd_route(const uint32_t* __restri
     }
 }
 
+// ---------------------------------------------------------------------------
+// GVR route.  Route tile t covers keys [t' T, min(N_k, (t'+1) T)) of input
+// block k = t / tpb (t' = t mod tpb); tiles past a block's end are empty.
+constexpr uint32_t kGvrWG = 512;
+constexpr uint32_t kGvrItems = 16;
+constexpr uint32_t kGvrTile = kGvrWG * kGvrItems;
+constexpr uint32_t kGvrGroups = kGvrWG / 32;   // ranking groups of 32 lanes
+
+__device__ __forceinline__ uint2 gvr_tile(const uint32_t* lo, uint32_t tpb, uint32_t t)
+{
+    const uint32_t k = t / tpb, u0 = (t - k * tpb) * kGvrTile;
+    const uint32_t b = lo[k], nk = lo[k + 1] - b;
+    return make_uint2(b + u0, u0 < nk ? min(kGvrTile, nk - u0) : 0u);
+}
+
+// Round plan {exec = 1}, ticket and look-back words of the route's tile scan.
+__global__ void k_gvr_init(RoundPlan* plan, uint32_t* ticket, uint32_t* state, size_t words)
+{
+    const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g == 0) {
+        *plan = RoundPlan{1, 0, 1, 1};
+        *ticket = 0;
+    }
+    for (size_t i = g; i < words; i += (size_t)gridDim.x * blockDim.x) state[i] = 0;
+}
+
+// Bucket of every key of the tile: the number of splitters S_i below its
+// composite (key, input index), by binary search over the splitters in LDS;
+// written as one byte per key, and counted per tile (counts[t][v], v < 256).
+__global__ __launch_bounds__(kGvrWG) void k_gvr_count(const uint32_t* __restrict__ X,
+                                                      const uint32_t* lo, uint32_t p, uint32_t s,
+                                                      uint32_t tpb, const uint32_t* Sk,
+                                                      const uint32_t* Sg, uint8_t* bkt,
+                                                      uint32_t* counts)
+{
+    __shared__ uint2 spl[kGvrMaxP];
+    __shared__ uint32_t h[R * 32];
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t i = tid; i < R * 32 / 4; i += kGvrWG) ((uint4*)h)[i] = make_uint4(0, 0, 0, 0);
+    if (tid + 1 < p) spl[tid] = make_uint2(Sk[(size_t)(tid + 1) * s - 1], Sg[(size_t)(tid + 1) * s - 1]);
+    __syncthreads();
+    const uint32_t t = blockIdx.x;
+    const uint2 tr = gvr_tile(lo, tpb, t);
+    const uint32_t base = tr.x, len = tr.y;
+    uint32_t top = 1;   // smallest power of two >= p
+    while (top < p) top <<= 1;
+    const uint32_t col = tid & 31;
+    // element (q WG + tid) 4 + c: each 4-key group is one 16-byte load (when
+    // the tile start is aligned) and one 4-byte store of bucket bytes
+    const bool vec = len == kGvrTile && (base & 3) == 0 && ((uintptr_t)(X + base) & 15) == 0;
+#pragma unroll 2
+    for (uint32_t q = 0; q < kGvrItems / 4; ++q) {
+        const uint32_t u = (q * kGvrWG + tid) * 4;
+        uint32_t key[4];
+        if (vec) {
+            typedef uint32_t v4 __attribute__((ext_vector_type(4)));
+            const v4 x = __builtin_nontemporal_load((const v4*)(X + base + u));
+            key[0] = x.x; key[1] = x.y; key[2] = x.z; key[3] = x.w;
+        } else {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) key[c] = u + c < len ? X[base + u + c] : 0u;
+        }
+        uint32_t packed = 0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const uint32_t g = base + u + c;
+            uint32_t b = 0;   // largest b with S_b below (key, g) (S_1..S_b all below)
+            for (uint32_t step = top >> 1; step; step >>= 1) {
+                const uint32_t cand = b + step;
+                if (cand < p) {
+                    const uint2 sp = spl[cand - 1];
+                    if (comp_less(sp.x, sp.y, key[c], g)) b = cand;
+                }
+            }
+            packed |= b << (8 * c);
+            if (u + c < len) atomicAdd(&h[b * 32 + col], 1u);
+        }
+        if (vec) {
+            *(uint32_t*)(bkt + base + u) = packed;
+        } else {
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                if (u + c < len) bkt[base + u + c] = (uint8_t)(packed >> (8 * c));
+        }
+    }
+    __syncthreads();
+    for (uint32_t v = tid; v < R; v += kGvrWG) {
+        const uint4* r4 = (const uint4*)&h[v * 32];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const uint4 x = r4[(q + v) & 7];
+            sum += x.x + x.y + x.z + x.w;
+        }
+        counts[(size_t)t * R + v] = sum;
+    }
+}
+
+// Stable scatter of one route tile by bucket: counts[t][v] now holds the keys
+// of bucket v in earlier tiles and bases[v] the start of bucket v, so the key
+// of bucket v with tile rank q lands at bases[v] + counts[t][v] + q.  The rank
+// among the tile's keys of one bucket, in input order, comes from 64-bit slots
+// {lanes of the current row, keys of earlier rows} per 32-lane group (rows in
+// order); the tile is staged in LDS in bucket order with its bucket bytes and
+// written run by run, the payloads in a second staging pass.
+template <bool KV>
+__global__ __launch_bounds__(kGvrWG) void k_gvr_scatter(const uint32_t* __restrict__ X,
+                                                        const uint32_t* __restrict__ XV,
+                                                        const uint32_t* lo, uint32_t tpb,
+                                                        const uint8_t* __restrict__ bkt,
+                                                        const uint32_t* counts,
+                                                        const uint32_t* bases, uint32_t n,
+                                                        uint32_t* Y, uint32_t* YV)
+{
+    constexpr int ITEMS = kGvrItems;
+    constexpr uint32_t TILE = kGvrTile;
+    struct Smem {
+        union {
+            uint2 slot[kGvrGroups][R];
+            uint32_t keys[TILE];
+            uint32_t vals[TILE];
+        } u;
+        uint8_t dig[TILE];
+        uint32_t goff[R];
+        uint32_t wsum[kGvrWG / 64];
+    };
+    __shared__ Smem sm;
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t grp = tid >> 5, gl = tid & 31;
+    const uint32_t hofs = grp * ITEMS * 32 + gl;   // row 0 position of this lane
+    const uint32_t t = blockIdx.x;
+    const uint2 tr = gvr_tile(lo, tpb, t);
+    const uint32_t base = tr.x, len = tr.y;
+    if (len == 0) return;
+
+    uint32_t k[ITEMS], v[ITEMS], d[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t o = hofs + i * 32;
+        const bool ok = o < len;
+        k[i] = ok ? X[base + o] : 0u;
+        d[i] = ok ? bkt[base + o] : 0u;
+        if (KV) v[i] = ok ? XV[base + o] : 0u;
+    }
+    for (uint32_t i = tid; i < kGvrGroups * R / 2; i += kGvrWG)
+        ((uint4*)&sm.u.slot[0][0])[i] = make_uint4(0, 0, 0, 0);
+    const uint32_t toff = tid < R ? counts[(size_t)t * R + tid] + bases[tid] : 0u;
+    __syncthreads();
+
+    // rank within the group, rows in order
+    uint32_t pos[ITEMS];
+    {
+        uint2* sl = sm.u.slot[grp];
+        const uint32_t bit = 1u << gl;
+        const uint32_t lowsel = lane < 32 ? ~0u : 0u;
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const bool ok = hofs + i * 32 < len;
+            if (ok) __hip_atomic_fetch_or(&sl[d[i]].x, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            wave_lds_order();
+            const uint64_t w = ok ? __hip_atomic_load((uint64_t*)&sl[d[i]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : 0ull;
+            const uint32_t m = (uint32_t)w, c = (uint32_t)(w >> 32);
+            pos[i] = __builtin_amdgcn_mbcnt_hi(m, __builtin_amdgcn_mbcnt_lo(m & lowsel, c));
+            wave_lds_order();
+            if (ok)
+                __hip_atomic_store((uint64_t*)&sl[d[i]], (uint64_t)(c + __builtin_popcount(m)) << 32,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            wave_lds_order();
+        }
+    }
+    __syncthreads();
+    // slot bases: bucket-major, groups in order within a bucket
+    uint32_t run = 0;
+    if (tid < R) {
+        uint32_t total = 0;
+#pragma unroll
+        for (uint32_t g = 0; g < kGvrGroups; ++g) total += sm.u.slot[g][tid].y;
+        const uint32_t incl = wave_inclusive_sum(total);
+        if (lane == 63) sm.wsum[wave] = incl;
+        run = incl - total;
+    }
+    __syncthreads();
+    if (tid < R) {
+        for (uint32_t w = 0; w < wave; ++w) run += sm.wsum[w];
+        sm.goff[tid] = toff - run;
+#pragma unroll
+        for (uint32_t g = 0; g < kGvrGroups; ++g) {
+            const uint32_t c = sm.u.slot[g][tid].y;
+            sm.u.slot[g][tid].y = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) pos[i] += sm.u.slot[grp][d[i]].y;
+    __syncthreads();
+    // stage in bucket order, then write each bucket's run
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i)
+        if (hofs + i * 32 < len) {
+            sm.u.keys[pos[i]] = k[i];
+            sm.dig[pos[i]] = (uint8_t)d[i];
+        }
+    __syncthreads();
+    uint32_t outi[KV ? ITEMS : 1];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t q = i * kGvrWG + tid;
+        uint32_t o = n;
+        if (q < len) {
+            o = sm.goff[sm.dig[q]] + q;
+            if (o < n) Y[o] = sm.u.keys[q];   // always true unless a tile-scan wait was abandoned
+        }
+        if (KV) outi[i] = o;
+    }
+    if (KV) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i)
+            if (hofs + i * 32 < len) sm.u.vals[pos[i]] = v[i];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t q = i * kGvrWG + tid;
+            if (q < len && outi[i] < n) YV[outi[i]] = sm.u.vals[q];
+        }
+    }
+}
+
+// After the route: bucket starts boff[j] (boff[p] = n), and the statistics --
+// bnd[k][j] = keys of input block k in buckets below j (from the scanned tile
+// counts: the keys of bucket j in block k are the difference of the exclusive
+// tile prefixes at the first tiles of blocks k + 1 and k) and the splitters.
+__global__ __launch_bounds__(R) void k_gvr_stats(const uint32_t* counts, const uint32_t* bases,
+                                                 uint32_t n, uint32_t p, uint32_t s,
+                                                 uint32_t tpb, const uint32_t* Sk,
+                                                 const uint32_t* Sg, uint32_t* boff,
+                                                 uint32_t* bnd, uint32_t* split_key,
+                                                 uint32_t* split_g)
+{
+    __shared__ uint32_t wsum[4];
+    const uint32_t k = blockIdx.x, j = threadIdx.x;
+    const uint32_t start_j = bases[j];
+    const uint32_t total_j = (j + 1 < R ? bases[j + 1] : n) - start_j;
+    const uint32_t a = counts[(size_t)k * tpb * R + j];
+    const uint32_t b = k + 1 < p ? counts[(size_t)(k + 1) * tpb * R + j] : total_j;
+    const uint32_t c = j < p ? b - a : 0u;
+    const uint32_t incl = block256_inclusive_sum(c, wsum);
+    uint32_t* row = bnd + (size_t)k * (p + 1);
+    if (j < p) row[j] = incl - c;
+    if (j == p - 1) row[p] = incl;
+    if (k == 0) {
+        if (j < p) boff[j] = start_j;
+        if (j == 0) boff[p] = n;
+        if (j + 1 < p) {
+            split_key[j] = Sk[(size_t)(j + 1) * s - 1];
+            split_g[j] = Sg[(size_t)(j + 1) * s - 1];
+        }
+    }
+}
+
 }  // namespace
 
 namespace {
 
-GsdLayout skeleton_layout(bool has_vals, size_t n, uint32_t p, uint32_t s, size_t nT, bool random)
+GsdLayout skeleton_layout(bool has_vals, size_t n, uint32_t p, uint32_t s, size_t nT, int kind)
 {
     GsdLayout L{};
     L.p = p;
     L.s = s;
     L.nT = nT;
-    L.random = random;
+    L.kind = kind;
     L.tiles_per_block = (uint32_t)((n / p + 1 + kRouteTile - 1) / kRouteTile);
     L.LT = lsd_r8_layout(4, true, L.nT, 0, 32);
     L.LTk = lsd_r8_layout(4, false, L.nT, 0, 32);
@@ -280,6 +550,16 @@ GsdLayout skeleton_layout(bool has_vals, size_t n, uint32_t p, uint32_t s, size_
     L.off_Y = o;     o = align_up(o + n * 4);
     L.off_YV = o;    o = align_up(o + (has_vals ? n * 4 : 0));
     L.off_seg = o;   o = align_up(o + L.LS.bytes);
+    if (kind == kGVR) {
+        L.route_tpb = (uint32_t)(((n + p - 1) / p + kGvrTile - 1) / kGvrTile);
+        L.route_ntiles = p * L.route_tpb;
+        const size_t nblocks = (L.route_ntiles + kScanBlock - 1) / kScanBlock;
+        L.off_rcounts = o; o = align_up(o + (size_t)L.route_ntiles * R * 4);
+        L.off_rstate = o;  o = align_up(o + nblocks * R * 4);
+        L.off_rplan = o;   o = align_up(o + sizeof(RoundPlan) + 4);
+        L.off_rbases = o;  o = align_up(o + R * 4);
+        L.off_bkt = o;     o = align_up(o + n);
+    }
     L.bytes = o;
     return L;
 }
@@ -289,16 +569,93 @@ GsdLayout skeleton_layout(bool has_vals, size_t n, uint32_t p, uint32_t s, size_
 GsdLayout gsd_layout(bool has_vals, size_t n, uint32_t p_req, uint32_t r)
 {
     const uint32_t p = (uint32_t)std::min<size_t>(p_req, n ? n : 1);
-    return skeleton_layout(has_vals, n, p, r * p, (size_t)p * r * p, false);
+    return skeleton_layout(has_vals, n, p, r * p, (size_t)p * r * p, kGSD);
 }
 
 GsdLayout ger_layout(bool has_vals, size_t n, uint32_t p_req, uint32_t s)
 {
     const uint32_t p = (uint32_t)std::min<size_t>(p_req, n ? n : 1);
-    return skeleton_layout(has_vals, n, p, s, (size_t)s * p - 1, true);
+    return skeleton_layout(has_vals, n, p, s, (size_t)s * p - 1, kGER);
+}
+
+GsdLayout gvr_layout(bool has_vals, size_t n, uint32_t p_req, uint32_t s)
+{
+    const uint32_t p = (uint32_t)std::min<size_t>(p_req, n ? n : 1);
+    return skeleton_layout(has_vals, n, p, s, (size_t)s * p - 1, kGVR);
 }
 
 size_t gsd_stats_words(uint32_t p) { return (size_t)p * (p + 1) + 2 * (size_t)p; }
+
+namespace {
+
+// The sample of GER and GVR: s p - 1 drawn positions, put in position order,
+// their keys gathered from src, then ordered by key (ties stay in position
+// order) into Sk / Sg.
+hipError_t random_sample(const uint32_t* src, size_t n, const GsdLayout& L, uint64_t seed,
+                         uint8_t* w, uint32_t* Tk, uint32_t* Tg, uint32_t* Sk, uint32_t* Sg,
+                         uint32_t* dev_err, hipStream_t stream)
+{
+    if (!L.nT) return hipSuccess;
+    const dim3 sg((uint32_t)((L.nT + 255) / 256));
+    hipLaunchKernelGGL(k_ger_draw, sg, dim3(256), 0, stream, seed, (uint32_t)n, L.nT, Tg);
+    hipError_t e = lsd_r8_sort(4, Tg, Sg, nullptr, nullptr, L.nT, 0, 32, w + L.off_lsd, L.LTk,
+                               dev_err, stream, nullptr);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ger_gather, sg, dim3(256), 0, stream, src, Sg, L.nT, Tk, Tg);
+    return lsd_r8_sort(4, Tk, Sk, Tg, Sg, L.nT, 0, 32, w + L.off_lsd, L.LT, dev_err, stream,
+                       nullptr);
+}
+
+// GVR (Algorithm 3): sample the input, route it by bucket, sort the buckets.
+hipError_t gvr_sort(const uint32_t* keys_in, uint32_t* keys_out, const uint32_t* vals_in,
+                    uint32_t* vals_out, size_t n, const GsdLayout& L, uint64_t seed, uint8_t* w,
+                    const uint32_t* lo, uint32_t* Tk, uint32_t* Tg, uint32_t* Sk, uint32_t* Sg,
+                    uint32_t* Y, uint32_t* YV, uint32_t* bnd, uint32_t* split_key,
+                    uint32_t* split_g, uint32_t* boff, uint32_t* dev_err, hipStream_t stream,
+                    Profiler* prof)
+{
+    const uint32_t p = L.p, s = L.s, tpb = L.route_tpb, nt = L.route_ntiles;
+    uint32_t* counts = (uint32_t*)(w + L.off_rcounts);
+    uint32_t* state = (uint32_t*)(w + L.off_rstate);
+    RoundPlan* plan = (RoundPlan*)(w + L.off_rplan);
+    uint32_t* ticket = (uint32_t*)(w + L.off_rplan + sizeof(RoundPlan));
+    uint32_t* bases = (uint32_t*)(w + L.off_rbases);
+    uint8_t* bkt = w + L.off_bkt;
+    const size_t nblocks = (nt + kScanBlock - 1) / kScanBlock;
+    // 1-2. sample of the input and splitters
+    hipError_t e = random_sample(keys_in, n, L, seed, w, Tk, Tg, Sk, Sg, dev_err, stream);
+    if (e != hipSuccess) return e;
+    // 3. bucket of every key, the tile counts, their scan, the stable route
+    hipLaunchKernelGGL(k_gvr_init, dim3((uint32_t)std::min<size_t>(1024, (nblocks * R + 255) / 256)),
+                       dim3(256), 0, stream, plan, ticket, state, nblocks * R);
+    hipLaunchKernelGGL(k_gvr_count, dim3(nt), dim3(kGvrWG), 0, stream, keys_in, lo, p, s, tpb, Sk,
+                       Sg, bkt, counts);
+    RoundArgs a{};
+    a.n = (uint32_t)n;
+    a.ntiles = nt;
+    a.bases = bases;
+    a.plan = plan;
+    a.counts = counts;
+    a.blk_state = state;
+    a.tickets = ticket;
+    a.err = dev_err;
+    hipLaunchKernelGGL(k_tilescan, dim3((uint32_t)nblocks), dim3(R), 0, stream, a);
+    if (vals_in)
+        hipLaunchKernelGGL(k_gvr_scatter<true>, dim3(nt), dim3(kGvrWG), 0, stream, keys_in,
+                           vals_in, lo, tpb, bkt, counts, bases, (uint32_t)n, Y, YV);
+    else
+        hipLaunchKernelGGL(k_gvr_scatter<false>, dim3(nt), dim3(kGvrWG), 0, stream, keys_in,
+                           nullptr, lo, tpb, bkt, counts, bases, (uint32_t)n, Y, nullptr);
+    hipLaunchKernelGGL(k_gvr_stats, dim3(p), dim3(R), 0, stream, counts, bases, (uint32_t)n, p, s,
+                       tpb, Sk, Sg, boff, bnd, split_key, split_g);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // 4. every bucket stable-sorted into the output
+    return devseg_sort(4, Y, keys_out, YV, vals_out, n, boff, p, kSmallMaxDefault, w + L.off_seg,
+                       L.LS, dev_err, stream, prof);
+}
+
+}  // namespace
 
 hipError_t gsd_sort(const uint32_t* keys_in, uint32_t* keys_out, const uint32_t* vals_in,
                     uint32_t* vals_out, size_t n, const GsdLayout& L, uint64_t seed, void* ws,
@@ -324,28 +681,26 @@ hipError_t gsd_sort(const uint32_t* keys_in, uint32_t* keys_out, const uint32_t*
     const uint32_t small_max = kSmallMaxDefault;
 
     hipLaunchKernelGGL(k_gsd_blocks, dim3((p + 256) / 256), dim3(256), 0, stream, lo, (uint32_t)n, p);
+    if (L.kind == kGVR)
+        return gvr_sort(keys_in, keys_out, vals_in, vals_out, n, L, seed, w, lo, Tk, Tg, Sk, Sg, Y,
+                        YV, bnd, split_key, split_g, boff, dev_err, stream, prof);
     // 1. local sort of the blocks into the output arrays
     hipError_t e = devseg_sort(4, keys_in, keys_out, vals_in, vals_out, n, lo, p, small_max,
                                seg_ws, L.LS, dev_err, stream, prof);
     if (e != hipSuccess) return e;
     // 2-3. the sample, sorted by composite (key, position)
-    const dim3 sg((uint32_t)((L.nT + 255) / 256));
-    if (!L.random) {
-        // GSD: regular sample, built in position order
+    if (L.kind == kGSD) {
+        // GSD: regular sample, built in position order; stable by key, so
+        // ties stay in position order
+        const dim3 sg((uint32_t)((L.nT + 255) / 256));
         hipLaunchKernelGGL(k_gsd_sample, sg, dim3(256), 0, stream, keys_out, lo, p, s, Tk, Tg);
-    } else if (L.nT) {
-        // GER: random positions, put in position order, then their keys
-        hipLaunchKernelGGL(k_ger_draw, sg, dim3(256), 0, stream, seed, (uint32_t)n, L.nT, Tg);
-        e = lsd_r8_sort(4, Tg, Sg, nullptr, nullptr, L.nT, 0, 32, w + L.off_lsd, L.LTk, dev_err,
-                        stream, nullptr);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_ger_gather, sg, dim3(256), 0, stream, keys_out, Sg, L.nT, Tk, Tg);
-    }
-    if (L.nT) {   // stable by key: ties stay in position order
         e = lsd_r8_sort(4, Tk, Sk, Tg, Sg, L.nT, 0, 32, w + L.off_lsd, L.LT, dev_err, stream,
                         nullptr);
-        if (e != hipSuccess) return e;
+    } else {
+        // GER: random positions into the sorted blocks
+        e = random_sample(keys_out, n, L, seed, w, Tk, Tg, Sk, Sg, dev_err, stream);
     }
+    if (e != hipSuccess) return e;
     // 4-5. splitters and split
     const uint32_t nb = p * (p + 1);
     hipLaunchKernelGGL(k_gsd_split, dim3((nb + 255) / 256), dim3(256), 0, stream, keys_out, lo, p,

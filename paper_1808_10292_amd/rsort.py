@@ -46,7 +46,8 @@ EXPORTED = ("rsort_create", "rsort_destroy", "rsort_status_string", "rsort_last_
             "rsort_segmented_workspace_bytes", "rsort_segmented_set_split",
             "rsort_segmented_tune", "rsort_sample_sort", "rsort_sample_sort_workspace_bytes",
             "rsort_sample_sort_stats", "rsort_sample_sort_random",
-            "rsort_sample_sort_random_workspace_bytes", "rsort_segmented_sort_device",
+            "rsort_sample_sort_random_workspace_bytes", "rsort_sample_sort_gvr",
+            "rsort_sample_sort_gvr_workspace_bytes", "rsort_segmented_sort_device",
             "rsort_segmented_device_workspace_bytes", "rsort_server_create", "rsort_server_submit",
             "rsort_server_poll", "rsort_server_wait", "rsort_server_latency",
             "rsort_server_reset_stats", "rsort_server_destroy")
@@ -108,6 +109,9 @@ def load_library():
                                                  ctypes.c_uint64, vp, sz, vp]
         lib.rsort_sample_sort_random_workspace_bytes.argtypes = [vp, i, i, sz, i, i,
                                                                  ctypes.POINTER(sz)]
+        lib.rsort_sample_sort_gvr.argtypes = lib.rsort_sample_sort_random.argtypes
+        lib.rsort_sample_sort_gvr_workspace_bytes.argtypes = \
+            lib.rsort_sample_sort_random_workspace_bytes.argtypes
         lib.rsort_segmented_sort_device.argtypes = [vp, i, vp, vp, u32p, u32p, vp, sz, sz, vp, sz,
                                                     vp]
         lib.rsort_segmented_device_workspace_bytes.argtypes = [vp, i, i, sz, sz, ctypes.POINTER(sz)]
@@ -436,31 +440,54 @@ def rsort_sample_sort_workspace_bytes(key_dtype, has_vals, n, p=256, r=32, devic
     return out.value
 
 
-def rsort_sample_sort_random(keys_in, keys_out, vals_in=None, vals_out=None, p=256, s=0,
-                             seed=0x18081029, workspace=None, stream=None):
-    """GER sample sort (p buckets, s p - 1 random sample keys, s = 0: default)."""
+def _random_sample_sort(name, keys_in, keys_out, vals_in, vals_out, p, s, seed, workspace,
+                        stream):
     kt = _key_type(keys_in)
     n = _check_kv(keys_in, keys_out, vals_in, vals_out)
     ctx = context(keys_in.device)
     ws_ptr, ws_bytes = None, 0
     if workspace is not None:
         ws_ptr, ws_bytes = _ptr(workspace), workspace.numel() * workspace.element_size()
-    rc = ctx._lib.rsort_sample_sort_random(ctx.handle, kt, _ptr(keys_in), _ptr(keys_out),
-                                           _ptr(vals_in), _ptr(vals_out), n, int(p), int(s),
-                                           int(seed) & 0xFFFFFFFFFFFFFFFF, ws_ptr, ws_bytes,
-                                           _stream_handle(stream))
-    ctx.check(rc, "rsort_sample_sort_random")
+    rc = getattr(ctx._lib, name)(ctx.handle, kt, _ptr(keys_in), _ptr(keys_out), _ptr(vals_in),
+                                 _ptr(vals_out), n, int(p), int(s),
+                                 int(seed) & 0xFFFFFFFFFFFFFFFF, ws_ptr, ws_bytes,
+                                 _stream_handle(stream))
+    ctx.check(rc, name)
     return keys_out, vals_out
 
 
-def rsort_sample_sort_random_workspace_bytes(key_dtype, has_vals, n, p=256, s=0, device=None):
+def _random_sample_ws(name, key_dtype, has_vals, n, p, s, device):
     ctx = context(device)
     kt = _key_type(torch.empty(0, dtype=key_dtype))
     out = ctypes.c_size_t()
-    ctx.check(ctx._lib.rsort_sample_sort_random_workspace_bytes(
-        ctx.handle, kt, int(bool(has_vals)), int(n), int(p), int(s), ctypes.byref(out)),
-        "rsort_sample_sort_random_workspace_bytes")
+    ctx.check(getattr(ctx._lib, name)(ctx.handle, kt, int(bool(has_vals)), int(n), int(p),
+                                      int(s), ctypes.byref(out)), name)
     return out.value
+
+
+def rsort_sample_sort_random(keys_in, keys_out, vals_in=None, vals_out=None, p=256, s=0,
+                             seed=0x18081029, workspace=None, stream=None):
+    """GER sample sort (p buckets, s p - 1 random sample keys, s = 0: default)."""
+    return _random_sample_sort("rsort_sample_sort_random", keys_in, keys_out, vals_in, vals_out,
+                               p, s, seed, workspace, stream)
+
+
+def rsort_sample_sort_random_workspace_bytes(key_dtype, has_vals, n, p=256, s=0, device=None):
+    return _random_sample_ws("rsort_sample_sort_random_workspace_bytes", key_dtype, has_vals, n,
+                             p, s, device)
+
+
+def rsort_sample_sort_gvr(keys_in, keys_out, vals_in=None, vals_out=None, p=256, s=0,
+                          seed=0x18081029, workspace=None, stream=None):
+    """GVR sample sort (p <= 256 buckets, s p - 1 random input positions,
+    s = 0: default)."""
+    return _random_sample_sort("rsort_sample_sort_gvr", keys_in, keys_out, vals_in, vals_out, p,
+                               s, seed, workspace, stream)
+
+
+def rsort_sample_sort_gvr_workspace_bytes(key_dtype, has_vals, n, p=256, s=0, device=None):
+    return _random_sample_ws("rsort_sample_sort_gvr_workspace_bytes", key_dtype, has_vals, n, p,
+                             s, device)
 
 
 def rsort_sample_sort_stats(p_cap=1024, device=None):

@@ -1,6 +1,7 @@
 """GPU parity of the regular-oversampling sample sort (GSD, Algorithm 1)
-against the oracle's GSD, and of the random-oversampling variant (GER,
-Algorithm 2) against the oracle's GER fed the same random draws.
+against the oracle's GSD, and of the random-oversampling variants (GER,
+Algorithm 2; GVR, Algorithm 3) against the oracle's GER and GVR fed the same
+random draws.
 
 Compared bit-exactly: the sorted keys and payloads, the p x p split matrix
 cnt[k][j] = |X_{k,j}|, the bucket sizes and the p - 1 splitter composites
@@ -243,6 +244,112 @@ def test_ger_full_size_kv(rs, dist):
     del dk
     st = rs.rsort_sample_sort_stats()
     assert int(st["bucket"].astype(np.uint64).sum()) == n
+    assert int(st["bucket"].max()) <= 1.25 * n / 256
+    check_kv_invariants(keys, host(ko), host(vo).view(np.uint32))
+
+
+# ---------------------------------------------------------------------------
+# GVR (Algorithm 3): the sample is drawn from the input with the same
+# generator; no local sort; the input is routed by bucket, then each bucket is
+# sorted.  cnt[k][j] counts input block k's keys in bucket j.
+
+def run_gvr(rs, keys, p, s, seed, with_vals=True, in_place=False, offset=0):
+    """offset > 0 sorts a view starting `offset` elements into a larger device
+    array (an input pointer not 16-byte aligned)."""
+    import torch
+    n = keys.size
+    pu = min(p, n)
+    vals = np.arange(n, dtype=np.uint32)
+    pos = keygen.sample_positions(seed, s * pu - 1, n)
+    want = oracle.gvr(keys, vals if with_vals else None, p, s, pos)
+    big = dev(np.concatenate([np.zeros(offset, np.uint32), keys]))
+    dk = big[offset:]
+    dv = dev(vals) if with_vals else None
+    if in_place:
+        ko, vo = dk, dv
+    else:
+        ko = torch.empty_like(dk)
+        vo = torch.empty_like(dv) if with_vals else None
+    rs.rsort_sample_sort_gvr(dk, ko, dv, vo, p=p, s=s, seed=seed)
+    rs.rsort_synchronize()
+    assert np.array_equal(host(ko), want["keys"])
+    if with_vals:
+        assert np.array_equal(host(vo), want["vals"])
+    st = rs.rsort_sample_sort_stats()
+    assert st["p"] == want["p"]
+    assert np.array_equal(st["cnt"].astype(np.uint64), want["cnt"])
+    assert np.array_equal(st["bucket"].astype(np.uint64), want["bucket"])
+    assert np.array_equal(st["split_key"], want["split_key"])
+    assert np.array_equal(st["split_index"].astype(np.uint64), want["split_g"])
+    return st
+
+
+@pytest.mark.parametrize("dist", keygen.KV_DISTRIBUTIONS)
+def test_gvr_distributions(rs, dist):
+    """p = 64 blocks of about 47 K keys: several route tiles per block, the
+    last one ragged."""
+    n = 3000017
+    announce("gvr", dist, n)
+    run_gvr(rs, keygen.kv_keys(dist, n), 64, 60, 0x6E5 + len(dist))
+
+
+@pytest.mark.parametrize("n,p,s", [(1, 256, 3), (2, 4, 1), (999, 9, 1), (1000, 1, 5),
+                                   (50000, 7, 300), (65536, 256, 4), (300007, 256, 140),
+                                   (8192 * 16, 16, 50), ((1 << 21) + 77, 16, 50)])
+def test_gvr_shapes(rs, n, p, s):
+    announce("gvr shape", n, p, s)
+    run_gvr(rs, keygen.zipf_keys(n, 70 + p), p, s, 2000 + n)
+
+
+def test_gvr_in_place_unaligned_and_keys_only(rs):
+    n = 1000003
+    announce("gvr in place / unaligned / keys only", n)
+    keys = keygen.uniform_u32(n, 63)
+    run_gvr(rs, keys, 256, 40, 9, in_place=True)
+    run_gvr(rs, keys, 256, 40, 10, offset=1)
+    run_gvr(rs, keys, 128, 40, 11, with_vals=False, offset=3)
+
+
+def test_gvr_default_oversampling_and_errors(rs):
+    """s = 0 takes s = 2 w^2 lg n as for GER; p above 256 is refused."""
+    import torch
+    n = 1 << 22
+    announce("gvr default", n)
+    keys = keygen.uniform_u32(n, 64)
+    run_gvr(rs, keys, 256, 1100, 8, with_vals=False)
+    ko = torch.empty_like(dev(keys))
+    rs.rsort_sample_sort_gvr(dev(keys), ko, p=256, s=0, seed=8)
+    rs.rsort_synchronize()
+    assert np.array_equal(host(ko), oracle.sr4(keys)[0])
+    need0 = rs.rsort_sample_sort_gvr_workspace_bytes(torch.uint32, False, n, 256, 0)
+    need1 = rs.rsort_sample_sort_gvr_workspace_bytes(torch.uint32, False, n, 256, 1100)
+    assert need0 == need1
+    with pytest.raises(rs.RsortError) as e:
+        rs.rsort_sample_sort_gvr(dev(keys), ko, p=257, s=4)
+    assert e.value.status == rs.RSORT_EINVAL
+    with pytest.raises(rs.RsortError) as e:
+        rs.rsort_sample_sort_gvr(dev(keys), ko, p=256, s=(1 << 18) + 1)
+    assert e.value.status == rs.RSORT_EUNSUPPORTED
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("dist", ["uniform", "zipf", "equal"])
+def test_gvr_full_size_kv(rs, dist):
+    """2^28 pairs, p = 256, default s: the stable sort (four invariants), the
+    bucket sizes summing to n, and the column sums of cnt equal to them."""
+    import torch
+    n = 1 << 28
+    announce("gvr full", dist, n)
+    keys = keygen.kv_keys(dist, n)
+    dk = dev(keys)
+    dv = torch.arange(n, dtype=torch.int32, device="cuda")
+    ko, vo = torch.empty_like(dk), torch.empty_like(dv)
+    rs.rsort_sample_sort_gvr(dk, ko, dv, vo, p=256, s=0, seed=12)
+    rs.rsort_synchronize()
+    del dk
+    st = rs.rsort_sample_sort_stats()
+    assert int(st["bucket"].astype(np.uint64).sum()) == n
+    assert np.array_equal(st["cnt"].astype(np.uint64).sum(axis=0), st["bucket"].astype(np.uint64))
     assert int(st["bucket"].max()) <= 1.25 * n / 256
     check_kv_invariants(keys, host(ko), host(vo).view(np.uint32))
 
