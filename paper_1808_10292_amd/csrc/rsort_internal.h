@@ -130,7 +130,7 @@ struct GsdLayout {
     // GVR route: tile counts, tile-scan state, round plan + ticket, bucket
     // starts, and one bucket byte per key
     uint32_t route_tpb, route_ntiles;
-    size_t off_rcounts, off_rstate, off_rplan, off_rbases, off_bkt;
+    size_t off_rcounts, off_rstate, off_rplan, off_rbases, off_bkt, off_rtab;
     size_t bytes;
 };
 GsdLayout gsd_layout(bool has_vals, size_t n, uint32_t p, uint32_t r);

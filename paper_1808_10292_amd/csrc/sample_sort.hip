@@ -268,6 +268,8 @@ constexpr uint32_t kGvrWG = 512;
 constexpr uint32_t kGvrItems = 16;
 constexpr uint32_t kGvrTile = kGvrWG * kGvrItems;
 constexpr uint32_t kGvrGroups = kGvrWG / 32;   // ranking groups of 32 lanes
+constexpr uint32_t kGvrTabBits = 12;            // bucket-search table over the top key bits
+constexpr uint32_t kGvrTab = 1u << kGvrTabBits;
 
 __device__ __forceinline__ uint2 gvr_tile(const uint32_t* lo, uint32_t tpb, uint32_t t)
 {
@@ -287,64 +289,121 @@ __global__ void k_gvr_init(RoundPlan* plan, uint32_t* ticket, uint32_t* state, s
     for (size_t i = g; i < words; i += (size_t)gridDim.x * blockDim.x) state[i] = 0;
 }
 
+// Search table: tab[c] = number of splitters whose key's top 12 bits are
+// below c, c = 0..4096.  A key with top bits c has exactly tab[c] splitters
+// with smaller keys and at least the splitters from tab[c + 1] on above it, so
+// only splitters tab[c] .. tab[c+1]-1 need comparing (none, mostly, for
+// spread-out keys).  One workgroup: a histogram of the splitters' top bits
+// and its exclusive scan (values <= 255: p <= 256).
+__global__ __launch_bounds__(1024) void k_gvr_table(const uint32_t* Sk, uint32_t p, uint32_t s,
+                                                    uint8_t* tab)
+{
+    __shared__ uint32_t hc[kGvrTab];
+    __shared__ uint32_t wsum[16];
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (uint32_t c = tid; c < kGvrTab; c += 1024) hc[c] = 0;
+    __syncthreads();
+    if (tid + 1 < p) atomicAdd(&hc[Sk[(size_t)(tid + 1) * s - 1] >> (32 - kGvrTabBits)], 1u);
+    __syncthreads();
+    // thread tid owns entries 4 tid .. 4 tid + 3
+    uint32_t c4[4], sum = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        c4[q] = hc[4 * tid + q];
+        sum += c4[q];
+    }
+    const uint32_t incl = wave_inclusive_sum(sum);
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    uint32_t run = incl - sum;
+    for (uint32_t w = 0; w < wave; ++w) run += wsum[w];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        tab[4 * tid + q] = (uint8_t)run;
+        run += c4[q];
+    }
+    if (tid == 1023) tab[kGvrTab] = (uint8_t)run;
+}
+
 // Bucket of every key of the tile: the number of splitters S_i below its
 // composite (key, input index), by binary search over the splitters in LDS;
 // written as one byte per key, and counted per tile (counts[t][v], v < 256).
+// Thread layout: key (q WG + tid) 4 + c, c < 4, so each group of 4 is one
+// 16-byte load (aligned full tiles) and one 4-byte store of bucket bytes; the
+// 16 searches of a thread advance together, one LDS probe each per step.
 __global__ __launch_bounds__(kGvrWG) void k_gvr_count(const uint32_t* __restrict__ X,
                                                       const uint32_t* lo, uint32_t p, uint32_t s,
                                                       uint32_t tpb, const uint32_t* Sk,
-                                                      const uint32_t* Sg, uint8_t* bkt,
-                                                      uint32_t* counts)
+                                                      const uint32_t* Sg, const uint8_t* gtab,
+                                                      uint8_t* bkt, uint32_t* counts)
 {
+    constexpr int ITEMS = kGvrItems;
     __shared__ uint2 spl[kGvrMaxP];
     __shared__ uint32_t h[R * 32];
+    __shared__ uint8_t tab[kGvrTab + 4];
     const uint32_t tid = threadIdx.x;
     for (uint32_t i = tid; i < R * 32 / 4; i += kGvrWG) ((uint4*)h)[i] = make_uint4(0, 0, 0, 0);
     if (tid + 1 < p) spl[tid] = make_uint2(Sk[(size_t)(tid + 1) * s - 1], Sg[(size_t)(tid + 1) * s - 1]);
-    __syncthreads();
-    const uint32_t t = blockIdx.x;
+    for (uint32_t c = tid; c <= kGvrTab; c += kGvrWG) tab[c] = gtab[c];
+    const uint32_t t = xcd_tile(gridDim.x);
     const uint2 tr = gvr_tile(lo, tpb, t);
     const uint32_t base = tr.x, len = tr.y;
-    uint32_t top = 1;   // smallest power of two >= p
-    while (top < p) top <<= 1;
-    const uint32_t col = tid & 31;
-    // element (q WG + tid) 4 + c: each 4-key group is one 16-byte load (when
-    // the tile start is aligned) and one 4-byte store of bucket bytes
     const bool vec = len == kGvrTile && (base & 3) == 0 && ((uintptr_t)(X + base) & 15) == 0;
-#pragma unroll 2
-    for (uint32_t q = 0; q < kGvrItems / 4; ++q) {
-        const uint32_t u = (q * kGvrWG + tid) * 4;
-        uint32_t key[4];
-        if (vec) {
-            typedef uint32_t v4 __attribute__((ext_vector_type(4)));
-            const v4 x = __builtin_nontemporal_load((const v4*)(X + base + u));
-            key[0] = x.x; key[1] = x.y; key[2] = x.z; key[3] = x.w;
-        } else {
+    uint32_t key[ITEMS];
+    if (vec) {
+        typedef uint32_t v4 __attribute__((ext_vector_type(4)));
 #pragma unroll
-            for (int c = 0; c < 4; ++c) key[c] = u + c < len ? X[base + u + c] : 0u;
+        for (int q = 0; q < ITEMS / 4; ++q) {
+            const v4 x = __builtin_nontemporal_load((const v4*)(X + base) + q * kGvrWG + tid);
+            key[4 * q] = x.x; key[4 * q + 1] = x.y; key[4 * q + 2] = x.z; key[4 * q + 3] = x.w;
         }
-        uint32_t packed = 0;
+    } else {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const uint32_t g = base + u + c;
-            uint32_t b = 0;   // largest b with S_b below (key, g) (S_1..S_b all below)
-            for (uint32_t step = top >> 1; step; step >>= 1) {
-                const uint32_t cand = b + step;
-                if (cand < p) {
-                    const uint2 sp = spl[cand - 1];
-                    if (comp_less(sp.x, sp.y, key[c], g)) b = cand;
-                }
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t u = ((i >> 2) * kGvrWG + tid) * 4 + (i & 3);
+            key[i] = u < len ? X[base + u] : 0u;
+        }
+    }
+    __syncthreads();
+    // b[i] = number of splitters below key i: binary search of the splitters
+    // the table leaves open, [b, e); every open range shrinks each step, and
+    // ranges hold at most 255 splitters, so 8 steps close all of them
+    uint32_t b[ITEMS], e[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t c = key[i] >> (32 - kGvrTabBits);
+        b[i] = tab[c];
+        e[i] = tab[c + 1];
+    }
+    for (int step = 0; step < 8; ++step) {
+        bool open = false;
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            if (b[i] < e[i]) {
+                const uint32_t g = base + ((i >> 2) * kGvrWG + tid) * 4 + (i & 3);
+                const uint32_t mid = (b[i] + e[i]) >> 1;
+                const uint2 sp = spl[mid];
+                if (comp_less(sp.x, sp.y, key[i], g)) b[i] = mid + 1; else e[i] = mid;
+                open |= b[i] < e[i];
             }
-            packed |= b << (8 * c);
-            if (u + c < len) atomicAdd(&h[b * 32 + col], 1u);
         }
+        if (!__builtin_amdgcn_ballot_w64(open)) break;
+    }
+    const uint32_t col = tid & 31;
+#pragma unroll
+    for (int q = 0; q < ITEMS / 4; ++q) {
+        const uint32_t u = (q * kGvrWG + tid) * 4;
+        const uint32_t packed = b[4 * q] | (b[4 * q + 1] << 8) | (b[4 * q + 2] << 16) | (b[4 * q + 3] << 24);
         if (vec) {
             *(uint32_t*)(bkt + base + u) = packed;
         } else {
 #pragma unroll
             for (int c = 0; c < 4; ++c)
-                if (u + c < len) bkt[base + u + c] = (uint8_t)(packed >> (8 * c));
+                if (u + c < len) bkt[base + u + c] = (uint8_t)b[4 * q + c];
         }
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            if (u + c < len) atomicAdd(&h[b[4 * q + c] * 32 + col], 1u);
     }
     __syncthreads();
     for (uint32_t v = tid; v < R; v += kGvrWG) {
@@ -379,11 +438,12 @@ __global__ __launch_bounds__(kGvrWG) void k_gvr_scatter(const uint32_t* __restri
     constexpr uint32_t TILE = kGvrTile;
     struct Smem {
         union {
-            uint2 slot[kGvrGroups][R];
-            uint32_t keys[TILE];
-            uint32_t vals[TILE];
+            uint2 slot[kGvrGroups][R];   // ranking
+            struct {
+                uint32_t keys[TILE];     // staging in bucket order (payloads second)
+                uint8_t dig[TILE];       // bucket of each staged key
+            } st;
         } u;
-        uint8_t dig[TILE];
         uint32_t goff[R];
         uint32_t wsum[kGvrWG / 64];
     };
@@ -391,7 +451,9 @@ __global__ __launch_bounds__(kGvrWG) void k_gvr_scatter(const uint32_t* __restri
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t grp = tid >> 5, gl = tid & 31;
     const uint32_t hofs = grp * ITEMS * 32 + gl;   // row 0 position of this lane
-    const uint32_t t = blockIdx.x;
+    // every XCD takes a contiguous range of tiles (grid = tile count): tiles
+    // whose bucket runs meet in one cache line write it through one L2
+    const uint32_t t = xcd_tile(gridDim.x);
     const uint2 tr = gvr_tile(lo, tpb, t);
     const uint32_t base = tr.x, len = tr.y;
     if (len == 0) return;
@@ -461,8 +523,8 @@ __global__ __launch_bounds__(kGvrWG) void k_gvr_scatter(const uint32_t* __restri
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i)
         if (hofs + i * 32 < len) {
-            sm.u.keys[pos[i]] = k[i];
-            sm.dig[pos[i]] = (uint8_t)d[i];
+            sm.u.st.keys[pos[i]] = k[i];
+            sm.u.st.dig[pos[i]] = (uint8_t)d[i];
         }
     __syncthreads();
     uint32_t outi[KV ? ITEMS : 1];
@@ -471,8 +533,8 @@ __global__ __launch_bounds__(kGvrWG) void k_gvr_scatter(const uint32_t* __restri
         const uint32_t q = i * kGvrWG + tid;
         uint32_t o = n;
         if (q < len) {
-            o = sm.goff[sm.dig[q]] + q;
-            if (o < n) Y[o] = sm.u.keys[q];   // always true unless a tile-scan wait was abandoned
+            o = sm.goff[sm.u.st.dig[q]] + q;
+            if (o < n) Y[o] = sm.u.st.keys[q];   // always true unless a tile-scan wait was abandoned
         }
         if (KV) outi[i] = o;
     }
@@ -480,12 +542,12 @@ __global__ __launch_bounds__(kGvrWG) void k_gvr_scatter(const uint32_t* __restri
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i)
-            if (hofs + i * 32 < len) sm.u.vals[pos[i]] = v[i];
+            if (hofs + i * 32 < len) sm.u.st.keys[pos[i]] = v[i];
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
             const uint32_t q = i * kGvrWG + tid;
-            if (q < len && outi[i] < n) YV[outi[i]] = sm.u.vals[q];
+            if (q < len && outi[i] < n) YV[outi[i]] = sm.u.st.keys[q];
         }
     }
 }
@@ -559,6 +621,7 @@ GsdLayout skeleton_layout(bool has_vals, size_t n, uint32_t p, uint32_t s, size_
         L.off_rplan = o;   o = align_up(o + sizeof(RoundPlan) + 4);
         L.off_rbases = o;  o = align_up(o + R * 4);
         L.off_bkt = o;     o = align_up(o + n);
+        L.off_rtab = o;    o = align_up(o + kGvrTab + 4);
     }
     L.bytes = o;
     return L;
@@ -628,8 +691,10 @@ hipError_t gvr_sort(const uint32_t* keys_in, uint32_t* keys_out, const uint32_t*
     // 3. bucket of every key, the tile counts, their scan, the stable route
     hipLaunchKernelGGL(k_gvr_init, dim3((uint32_t)std::min<size_t>(1024, (nblocks * R + 255) / 256)),
                        dim3(256), 0, stream, plan, ticket, state, nblocks * R);
+    uint8_t* tab = w + L.off_rtab;
+    hipLaunchKernelGGL(k_gvr_table, dim3(1), dim3(1024), 0, stream, Sk, p, s, tab);
     hipLaunchKernelGGL(k_gvr_count, dim3(nt), dim3(kGvrWG), 0, stream, keys_in, lo, p, s, tpb, Sk,
-                       Sg, bkt, counts);
+                       Sg, tab, bkt, counts);
     RoundArgs a{};
     a.n = (uint32_t)n;
     a.ntiles = nt;
