@@ -127,6 +127,11 @@ struct GsdLayout {
     DevSegLayout LS;            // local sort and bucket finish
     size_t off_lo, off_boff, off_bsize, off_coloff, off_Tk, off_Tg, off_Sk, off_Sg, off_lsd,
         off_Y, off_YV, off_seg;
+    // GSD step 5 as a merge (p <= 256): pieces cut at every g-th sorted
+    // sample element, M boundaries, F = (M + 2) x p run bounds
+    bool merge;
+    uint32_t g, M;
+    size_t off_F, off_BK;
     // GVR route: tile counts, tile-scan state, round plan + ticket, bucket
     // starts, and one bucket byte per key
     uint32_t route_tpb, route_ntiles;

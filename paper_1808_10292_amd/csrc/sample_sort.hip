@@ -24,6 +24,10 @@
 //                     S_{j+1} as composites, so the concatenation is the stable
 //                     sort of the input; the paper merges the p sorted runs of
 //                     a bucket, which gives the same array.
+// With p <= 256, GSD replaces steps 5-7 by the merge of step 5 itself: the
+// buckets are cut further at every g-th sorted sample element into pieces of
+// about 2048 keys, and one workgroup merges the p sorted sub-runs of a piece
+// straight from the sorted blocks into the output (see k_gsd_merge).
 // Duplicate keys: comparing composites (key, index) instead of keys keeps the
 // bucket bound of Lemma 1 for any key distribution, and the split of equal
 // keys by index keeps the result stable.
@@ -39,6 +43,7 @@
 #include <algorithm>
 
 #include "lsd_kernels.h"
+#include "tile_sort.h"
 
 namespace rsort {
 namespace {
@@ -584,6 +589,335 @@ __global__ __launch_bounds__(R) void k_gvr_stats(const uint32_t* counts, const u
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// GSD step 5 as a merge of the p sorted runs of every bucket.  The sorted
+// regular sample gives finer boundaries B_m = T[m g - 1], m = 1..M (M = p s /
+// g; g divides s, so the splitters S_i = B_{i s / g} are among them).  Piece m
+// (m = 0..M) holds the elements whose composite lies in (B_m, B_{m+1}]
+// (B_0 = -inf, B_{M+1} = +inf): from every sorted block k the positions
+// [F[k][m], F[k][m+1]), F[k][m] = #{q in block k : (X_q, index) <= B_m}.  The
+// pieces cover the output in order, piece m from sum_k F[k][m] on, and a
+// piece is the merge of its p sorted sub-runs.  By Lemma 1's argument a piece
+// holds at most (g + p - 1) x keys (x = block keys per sample); g is chosen so
+// that the average is about 2048.
+constexpr uint32_t kMergeWG = 256;
+constexpr int kMergeItems = 16;
+constexpr uint32_t kMergeCap = kMergeWG * kMergeItems;   // piece merged whole in LDS
+constexpr uint32_t kMergeMaxP = 256;                     // one run per thread
+constexpr uint32_t kMarkLen = kMergeCap + kMergeCap / 8; // padded run map (u16 entries)
+
+// F[k][m] for m = 0..M+1, block-major (M + 2 per block).  Workgroup (c, k) takes
+// chunk c (8192 keys) of sorted block k into LDS and handles the boundaries
+// whose rank in the block falls in the chunk: B_m with X[c0 - 1] <= B_m <
+// X[c1 - 1] (first chunk: no lower condition; last: no upper one), found by
+// two binary searches over the boundaries; each is then ranked inside the
+// chunk by binary search in LDS.  Every block key is read once.
+constexpr uint32_t kFineChunk = 8192;
+constexpr uint32_t kCoarse = 256;   // boundaries per entry of the coarse index
+
+// BK[m - 1] = B_m as one 64-bit composite (key << 32 | index), m = 1..M.
+__global__ void k_gsd_bounds(const uint32_t* Sk, const uint32_t* Sg, uint32_t g, uint32_t M,
+                             uint64_t* BK)
+{
+    const uint32_t m = blockIdx.x * blockDim.x + threadIdx.x + 1;
+    if (m <= M) BK[m - 1] = ((uint64_t)Sk[(size_t)m * g - 1] << 32) | Sg[(size_t)m * g - 1];
+}
+
+__global__ __launch_bounds__(256) void k_gsd_fine_split(const uint32_t* __restrict__ X,
+                                                        const uint32_t* lo, uint32_t p, uint32_t M,
+                                                        const uint64_t* __restrict__ BK,
+                                                        uint32_t* F)
+{
+    __shared__ uint32_t xs[kFineChunk];
+    __shared__ uint64_t ci[1024];   // BK[i kCoarse], i < ceil(M / kCoarse) (<= 1024 used)
+    __shared__ uint32_t range[2];
+    const uint32_t k = blockIdx.y, tid = threadIdx.x;
+    const uint32_t b = lo[k], nk = lo[k + 1] - b;
+    const uint32_t c0 = blockIdx.x * kFineChunk;
+    if (blockIdx.x == 0) {   // rows 0 and M + 1
+        if (tid == 0) F[(size_t)k * (M + 2)] = 0;
+        if (tid == 1) F[(size_t)k * (M + 2) + M + 1] = nk;
+    }
+    if (c0 >= nk && c0 != 0) return;
+    const uint32_t c1 = min(nk, c0 + kFineChunk);
+    const bool last = c1 == nk;
+    const uint32_t nci = min(1024u, (M + kCoarse - 1) / kCoarse);
+    for (uint32_t i = tid; i < c1 - c0; i += 256) xs[i] = X[b + c0 + i];
+    for (uint32_t i = tid; i < nci; i += 256) ci[i] = BK[(size_t)i * kCoarse];
+    __syncthreads();
+    // index of the first boundary >= x (composite), in [0, M]
+    auto first_not_below = [&](uint64_t x) -> uint32_t {
+        uint32_t a = 0, e = nci;   // coarse: first i with ci[i] >= x
+        while (a < e) {
+            const uint32_t mid = (a + e) >> 1;
+            if (ci[mid] < x) a = mid + 1; else e = mid;
+        }
+        // the answer lies in ((a - 1) kCoarse, a kCoarse]
+        uint32_t lo_i = a == 0 ? 0u : (a - 1) * kCoarse + 1, hi_i = min(M, a * kCoarse);
+        if (nci == 1024 && a == nci) hi_i = M;   // beyond the indexed part
+        while (lo_i < hi_i) {
+            const uint32_t mid = (lo_i + hi_i) >> 1;
+            if (BK[mid] < x) lo_i = mid + 1; else hi_i = mid;
+        }
+        return lo_i;
+    };
+    if (tid == 0)   // the key before the chunk, (X_{c0-1}, index)
+        range[0] = c0 == 0 ? 0u : first_not_below((uint64_t)X[b + c0 - 1] << 32 | (b + c0 - 1));
+    if (tid == 64)
+        range[1] = last ? M : first_not_below((uint64_t)xs[c1 - c0 - 1] << 32 | (b + c1 - 1));
+    __syncthreads();
+    // boundaries with index i in [range[0], range[1]) are B_{i+1}
+    for (uint32_t i = range[0] + tid; i < range[1]; i += 256) {
+        const uint64_t bnd = BK[i];
+        uint32_t a = 0, e = c1 - c0;   // first q in the chunk with B < (X_q, index)
+        while (a < e) {
+            const uint32_t mid = (a + e) >> 1;
+            if (bnd < ((uint64_t)xs[mid] << 32 | (b + c0 + mid))) e = mid; else a = mid + 1;
+        }
+        F[(size_t)k * (M + 2) + i + 1] = c0 + a;
+    }
+}
+
+// Split bounds of the p buckets (bnd[k][i] = F[k][i s / g]) and the splitters,
+// for the statistics.
+__global__ void k_gsd_fine_bnd(const uint32_t* F, uint32_t p, uint32_t s, uint32_t g, uint32_t M,
+                               const uint32_t* Sk, const uint32_t* Sg, uint32_t* bnd,
+                               uint32_t* split_key, uint32_t* split_g)
+{
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= p * (p + 1)) return;
+    const uint32_t k = t / (p + 1), i = t - k * (p + 1);
+    const uint32_t row = i == p ? M + 1 : i * (s / g);
+    bnd[t] = F[(size_t)k * (M + 2) + row];
+    if (k == 0 && i > 0 && i < p) {
+        split_key[i - 1] = Sk[(size_t)i * s - 1];
+        split_g[i - 1] = Sg[(size_t)i * s - 1];
+    }
+}
+
+__device__ __forceinline__ uint32_t wave_inclusive_max(uint32_t x)
+{
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= (uint32_t)o) x = max(x, y);
+    }
+    return x;
+}
+
+// Run map index of piece position u: blocks of 16 u16 entries padded by one
+// dword, so thread t's block (entries 16 t .. 16 t + 15) starts at dword 9 t
+// and the 64 lanes of a wave hit 64 different banks.
+__device__ __forceinline__ uint32_t mark_idx(uint32_t u) { return u + 2 * (u >> 4); }
+
+// One workgroup per piece: the p sub-runs are read in run order (block order,
+// which is input order on equal keys), combined by a stable sort in LDS --
+// one tile_round per byte, rounds whose byte is the same for the whole piece
+// skipped -- which is their merge, and written once at the piece's start.  A
+// piece larger than the LDS tile is gathered into a temporary and sorted in
+// chunks, round by round, between the temporary and its own output range.
+template <bool KV>
+__global__ __launch_bounds__(kMergeWG) void k_gsd_merge(const uint32_t* __restrict__ X,
+                                                        const uint32_t* __restrict__ XV,
+                                                        const uint32_t* lo, uint32_t p,
+                                                        uint32_t M, uint32_t g,
+                                                        const uint32_t* Sk, const uint32_t* F,
+                                                        uint32_t* out, uint32_t* vout,
+                                                        uint32_t* tmp, uint32_t* vtmp)
+{
+    constexpr int ITEMS = kMergeItems;
+    constexpr uint32_t C = kMergeCap;
+    static_assert(kMarkLen * 2 <= sizeof(uint2) * (kMergeWG / 32) * kTileRadix,
+                  "the run map lives in the ranking slots");
+    __shared__ TileSmem<uint32_t, KV, kMergeWG, ITEMS> sm;
+    __shared__ union {
+        struct {
+            uint32_t src[kMergeMaxP];        // first element of run k in X
+            uint32_t off[kMergeMaxP + 1];    // start of run k in the piece
+        } r;
+        struct {
+            uint32_t st[R];                  // next output index of each digit
+            uint32_t cs[R];                  // digit starts inside the chunk
+            uint32_t cc[R];                  // digit counts of the chunk
+        } d;
+    } aux;
+    __shared__ uint32_t wsc[4];
+    __shared__ uint32_t tot[2];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t hofs = (tid >> 5) * ITEMS * 32 + (tid & 31);
+    // Piece of this workgroup.  The grid (a multiple of 8) is dealt to the 8
+    // XCDs in turn; XCD x takes the x-th eighth of the pieces, so neighbouring
+    // pieces, whose runs and outputs share cache lines, meet in one L2.  The
+    // last eighth runs backwards: the two edge pieces (keys below the first and
+    // above the last boundary of every block, the largest) start first.
+    const uint32_t per = gridDim.x >> 3, x = blockIdx.x & 7, j = blockIdx.x >> 3;
+    const uint32_t m = x * per + (x == 7 ? per - 1 - j : j);
+    if (m > M) return;
+    // keys of the piece lie between the keys of its bounding boundaries: the
+    // bytes above their highest differing bit are the same for all of them
+    const uint32_t klo = m == 0 ? 0u : Sk[(size_t)m * g - 1];
+    const uint32_t khi = m == M ? 0xFFFFFFFFu : Sk[(size_t)(m + 1) * g - 1];
+    const uint32_t varying = klo ^ khi;
+    uint32_t len = 0, before = 0;
+    if (tid < p) {
+        const uint32_t* f = F + (size_t)tid * (M + 2) + m;
+        before = f[0];
+        len = f[1] - before;
+    }
+    const uint32_t incl = block256_inclusive_sum(len, wsc);
+    const uint32_t start = block256_inclusive_sum(before, wsc);
+    if (tid < p) {
+        aux.r.src[tid] = lo[tid] + before;
+        aux.r.off[tid] = incl - len;
+    }
+    if (tid == kMergeWG - 1) {
+        tot[0] = incl;    // keys in the piece
+        tot[1] = start;   // keys before it: its output start
+        aux.r.off[p] = incl;
+    }
+    __syncthreads();
+    const uint32_t L = tot[0], base = tot[1];
+    if (L == 0) return;
+
+    uint16_t* mark = (uint16_t*)&sm.slot[0][0];
+    uint32_t k[ITEMS], v[ITEMS];
+    // Registers <- piece positions [c0, c0 + nc) in the ranking layout
+    // (position c0 + hofs + 32 i in register i).  The run of every position is
+    // found through a map: run k + 1 is marked at its first position in the
+    // chunk, and a running maximum fills the positions after it.
+    auto gather = [&](uint32_t c0, uint32_t nc) {
+        for (uint32_t j = tid; j < kMarkLen / 2; j += kMergeWG) ((uint32_t*)mark)[j] = 0;
+        __syncthreads();
+        if (tid < p) {
+            const uint32_t a = aux.r.off[tid], e = aux.r.off[tid + 1];
+            const uint32_t s0 = max(a, c0), e0 = min(e, c0 + nc);
+            if (s0 < e0) mark[mark_idx(s0 - c0)] = (uint16_t)(tid + 1);
+        }
+        __syncthreads();
+        uint32_t run = 0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) run = max(run, (uint32_t)mark[mark_idx(16 * tid + j)]);
+        const uint32_t wmax = wave_inclusive_max(run);
+        if ((tid & 63) == 63) wsc[tid >> 6] = wmax;
+        __syncthreads();
+        uint32_t cur = __shfl_up(wmax, 1, 64);
+        if ((tid & 63) == 0) cur = 0;
+        for (uint32_t w = 0; w < (tid >> 6); ++w) cur = max(cur, wsc[w]);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            cur = max(cur, (uint32_t)mark[mark_idx(16 * tid + j)]);
+            mark[mark_idx(16 * tid + j)] = (uint16_t)cur;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t u = hofs + i * 32;
+            k[i] = 0;
+            v[i] = 0;
+            if (u < nc) {
+                const uint32_t r = mark[mark_idx(u)] - 1u;
+                const uint32_t q = aux.r.src[r] + (c0 + u - aux.r.off[r]);
+                k[i] = X[q];
+                if (KV) v[i] = XV[q];
+            }
+        }
+        __syncthreads();   // the map area is the ranking slots again
+    };
+
+    if (L <= C) {
+        gather(0, L);
+#pragma unroll 1
+        for (uint32_t d = 0; d < 4 && (varying >> (8 * d)); ++d)
+            tile_round<uint32_t, KV, kMergeWG, ITEMS>(sm, k, v, L, 8u * d, 0xFFu);
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t u = hofs + i * 32;
+            if (u < L) {
+                out[base + u] = k[i];
+                if (KV) vout[base + u] = v[i];
+            }
+        }
+        return;
+    }
+
+    // Large piece: gather into tmp[base, base + L), then per byte a stable
+    // count sort of the whole piece, chunk by chunk, between tmp and
+    // out[base, base + L) (both owned by this piece alone).
+    for (uint32_t c0 = 0; c0 < L; c0 += C) {
+        const uint32_t nc = min(C, L - c0);
+        gather(c0, nc);
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t u = hofs + i * 32;
+            if (u < nc) {
+                tmp[base + c0 + u] = k[i];
+                if (KV) vtmp[base + c0 + u] = v[i];
+            }
+        }
+    }
+    __syncthreads();
+    uint32_t* ck = tmp + base;      // current keys
+    uint32_t* cv = KV ? vtmp + base : nullptr;
+    uint32_t* ok = out + base;      // the other buffer
+    uint32_t* ov = KV ? vout + base : nullptr;
+#pragma unroll 1
+    for (uint32_t d = 0; d < 4 && (varying >> (8 * d)); ++d) {
+        const uint32_t shift = 8u * d;
+        aux.d.st[tid] = 0;
+        __syncthreads();
+        for (uint32_t j = tid; j < L; j += kMergeWG) atomicAdd(&aux.d.st[digit_of(ck[j], shift, 0xFFu)], 1u);
+        __syncthreads();
+        const uint32_t cnt = aux.d.st[tid];
+        if (__syncthreads_or(cnt == L)) continue;   // one byte value everywhere: nothing moves
+        const uint32_t ex = block256_inclusive_sum(cnt, wsc) - cnt;
+        aux.d.st[tid] = ex;
+        __syncthreads();
+#pragma unroll 1
+        for (uint32_t c0 = 0; c0 < L; c0 += C) {
+            const uint32_t nc = min(C, L - c0);
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                const uint32_t u = hofs + i * 32;
+                k[i] = u < nc ? ck[c0 + u] : 0u;
+                v[i] = KV && u < nc ? cv[c0 + u] : 0u;
+            }
+            aux.d.cc[tid] = 0;
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i)
+                if (hofs + i * 32 < nc) atomicAdd(&aux.d.cc[digit_of(k[i], shift, 0xFFu)], 1u);
+            __syncthreads();
+            const uint32_t c = aux.d.cc[tid];
+            aux.d.cs[tid] = block256_inclusive_sum(c, wsc) - c;
+            __syncthreads();
+            tile_round<uint32_t, KV, kMergeWG, ITEMS>(sm, k, v, nc, shift, 0xFFu);
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                const uint32_t u = hofs + i * 32;
+                if (u < nc) {
+                    const uint32_t dv = digit_of(k[i], shift, 0xFFu);
+                    const uint32_t o = aux.d.st[dv] + u - aux.d.cs[dv];
+                    ok[o] = k[i];
+                    if (KV) ov[o] = v[i];
+                }
+            }
+            __syncthreads();
+            aux.d.st[tid] += c;
+            __syncthreads();
+        }
+        uint32_t* t = ck; ck = ok; ok = t;
+        if (KV) { t = cv; cv = ov; ov = t; }
+    }
+    if (ck != out + base) {
+        for (uint32_t j = tid; j < L; j += kMergeWG) {
+            out[base + j] = ck[j];
+            if (KV) vout[base + j] = cv[j];
+        }
+    }
+}
+
 }  // namespace
 
 namespace {
@@ -612,6 +946,18 @@ GsdLayout skeleton_layout(bool has_vals, size_t n, uint32_t p, uint32_t s, size_
     L.off_Y = o;     o = align_up(o + n * 4);
     L.off_YV = o;    o = align_up(o + (has_vals ? n * 4 : 0));
     L.off_seg = o;   o = align_up(o + L.LS.bytes);
+    if (kind == kGSD && p <= kMergeMaxP && n <= L.nT * 4096) {
+        // the merge finish: g = the largest divisor of s with average piece
+        // g n / nT at most 2048 (at least 1)
+        L.merge = true;
+        const uint64_t want = std::max<uint64_t>(1, (uint64_t)2048 * L.nT / n);
+        uint32_t g = (uint32_t)std::min<uint64_t>(want, s);
+        while (s % g) --g;
+        L.g = g;
+        L.M = (uint32_t)(L.nT / g);
+        L.off_F = o;       o = align_up(o + ((size_t)L.M + 2) * p * 4);
+        L.off_BK = o;      o = align_up(o + (size_t)L.M * 8);
+    }
     if (kind == kGVR) {
         L.route_tpb = (uint32_t)(((n + p - 1) / p + kGvrTile - 1) / kGvrTile);
         L.route_ntiles = p * L.route_tpb;
@@ -720,6 +1066,48 @@ hipError_t gvr_sort(const uint32_t* keys_in, uint32_t* keys_out, const uint32_t*
                        L.LS, dev_err, stream, prof);
 }
 
+// GSD with the merge finish: local sort into Y, regular sample, splitters,
+// fine split, and the piece merge from Y into the output.
+hipError_t gsd_merge_sort(const uint32_t* keys_in, uint32_t* keys_out, const uint32_t* vals_in,
+                          uint32_t* vals_out, size_t n, const GsdLayout& L, uint8_t* w,
+                          const uint32_t* lo, uint32_t* Tk, uint32_t* Tg, uint32_t* Sk,
+                          uint32_t* Sg, uint32_t* Y, uint32_t* YV, uint32_t* bnd,
+                          uint32_t* split_key, uint32_t* split_g, uint32_t* dev_err,
+                          hipStream_t stream, Profiler* prof)
+{
+    const uint32_t p = L.p, s = L.s, g = L.g, M = L.M;
+    uint32_t* F = (uint32_t*)(w + L.off_F);
+    uint8_t* seg_ws = w + L.off_seg;
+    uint32_t* tmp = (uint32_t*)(seg_ws + L.LS.off_tmp_keys);
+    uint32_t* vtmp = vals_in ? (uint32_t*)(seg_ws + L.LS.off_tmp_vals) : nullptr;
+    // 1. local sort of the blocks into Y
+    hipError_t e = devseg_sort(4, keys_in, Y, vals_in, YV, n, lo, p, kSmallMaxDefault, seg_ws,
+                               L.LS, dev_err, stream, prof);
+    if (e != hipSuccess) return e;
+    // 2-3. regular sample of the sorted blocks, sorted by composite
+    hipLaunchKernelGGL(k_gsd_sample, dim3((uint32_t)((L.nT + 255) / 256)), dim3(256), 0, stream, Y,
+                       lo, p, s, Tk, Tg);
+    e = lsd_r8_sort(4, Tk, Sk, Tg, Sg, L.nT, 0, 32, w + L.off_lsd, L.LT, dev_err, stream, nullptr);
+    if (e != hipSuccess) return e;
+    // 4. splitters, the fine split, the buckets' split bounds
+    uint64_t* BK = (uint64_t*)(w + L.off_BK);
+    hipLaunchKernelGGL(k_gsd_bounds, dim3((M + 255) / 256), dim3(256), 0, stream, Sk, Sg, g, M, BK);
+    const uint32_t chunks = (uint32_t)std::max<size_t>(1, ((n + p - 1) / p + kFineChunk - 1) / kFineChunk);
+    hipLaunchKernelGGL(k_gsd_fine_split, dim3(chunks, p), dim3(256), 0, stream, Y, lo, p, M, BK, F);
+    const uint32_t nb = p * (p + 1);
+    hipLaunchKernelGGL(k_gsd_fine_bnd, dim3((nb + 255) / 256), dim3(256), 0, stream, F, p, s, g, M,
+                       Sk, Sg, bnd, split_key, split_g);
+    // 5. merge every piece into the output
+    const dim3 mg((M + 1 + 7) & ~7u);
+    if (vals_in)
+        hipLaunchKernelGGL(k_gsd_merge<true>, mg, dim3(kMergeWG), 0, stream, Y, YV, lo, p, M, g, Sk,
+                           F, keys_out, vals_out, tmp, vtmp);
+    else
+        hipLaunchKernelGGL(k_gsd_merge<false>, mg, dim3(kMergeWG), 0, stream, Y, nullptr, lo, p, M,
+                           g, Sk, F, keys_out, nullptr, tmp, nullptr);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t gsd_sort(const uint32_t* keys_in, uint32_t* keys_out, const uint32_t* vals_in,
@@ -749,6 +1137,9 @@ hipError_t gsd_sort(const uint32_t* keys_in, uint32_t* keys_out, const uint32_t*
     if (L.kind == kGVR)
         return gvr_sort(keys_in, keys_out, vals_in, vals_out, n, L, seed, w, lo, Tk, Tg, Sk, Sg, Y,
                         YV, bnd, split_key, split_g, boff, dev_err, stream, prof);
+    if (L.merge) return gsd_merge_sort(keys_in, keys_out, vals_in, vals_out, n, L, w, lo, Tk, Tg,
+                                       Sk, Sg, Y, YV, bnd, split_key, split_g, dev_err, stream,
+                                       prof);
     // 1. local sort of the blocks into the output arrays
     hipError_t e = devseg_sort(4, keys_in, keys_out, vals_in, vals_out, n, lo, p, small_max,
                                seg_ws, L.LS, dev_err, stream, prof);

@@ -87,6 +87,16 @@ def test_shapes(rs, n, p, r):
     run_case(rs, keys, p, r)
 
 
+@pytest.mark.parametrize("dist", ["uniform", "zipf", "equal", "presorted"])
+@pytest.mark.parametrize("n,p,r", [((1 << 22) + 5, 64, 4), (1 << 21, 16, 2)])
+def test_merge_pieces_beyond_lds(rs, dist, n, p, r):
+    """Shapes whose merge pieces often exceed one LDS tile (4096 keys): the
+    edge pieces at n = 2^22 + 5, p = 64 (about 8 K keys each), and pieces of
+    about 4096 keys on average at n = 2^21, p = 16, r = 2."""
+    announce("gsd merge large pieces", dist, n, p, r)
+    run_case(rs, keygen.kv_keys(dist, n), p, r)
+
+
 def test_keys_only_and_in_place(rs):
     n = 1000003
     announce("gsd keys only / in place", n)
