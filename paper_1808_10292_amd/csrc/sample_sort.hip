@@ -946,12 +946,12 @@ GsdLayout skeleton_layout(bool has_vals, size_t n, uint32_t p, uint32_t s, size_
     L.off_Y = o;     o = align_up(o + n * 4);
     L.off_YV = o;    o = align_up(o + (has_vals ? n * 4 : 0));
     L.off_seg = o;   o = align_up(o + L.LS.bytes);
-    if (kind == kGSD && p <= kMergeMaxP && n <= L.nT * 4096) {
+    if ((kind == kGSD || kind == kGER) && p <= kMergeMaxP && L.nT && n <= L.nT * 4096) {
         // the merge finish: g = the largest divisor of s with average piece
-        // g n / nT at most 2048 (at least 1)
+        // g n / nT at most 2048 (at least 1) and at least one boundary (g <= nT)
         L.merge = true;
         const uint64_t want = std::max<uint64_t>(1, (uint64_t)2048 * L.nT / n);
-        uint32_t g = (uint32_t)std::min<uint64_t>(want, s);
+        uint32_t g = (uint32_t)std::min<uint64_t>(std::min<uint64_t>(want, s), L.nT);
         while (s % g) --g;
         L.g = g;
         L.M = (uint32_t)(L.nT / g);
@@ -1066,10 +1066,11 @@ hipError_t gvr_sort(const uint32_t* keys_in, uint32_t* keys_out, const uint32_t*
                        L.LS, dev_err, stream, prof);
 }
 
-// GSD with the merge finish: local sort into Y, regular sample, splitters,
-// fine split, and the piece merge from Y into the output.
+// GSD / GER with the merge finish: local sort into Y, the sample (regular or
+// random) and splitters, fine split, and the piece merge from Y into the output.
 hipError_t gsd_merge_sort(const uint32_t* keys_in, uint32_t* keys_out, const uint32_t* vals_in,
-                          uint32_t* vals_out, size_t n, const GsdLayout& L, uint8_t* w,
+                          uint32_t* vals_out, size_t n, const GsdLayout& L, uint64_t seed,
+                          uint8_t* w,
                           const uint32_t* lo, uint32_t* Tk, uint32_t* Tg, uint32_t* Sk,
                           uint32_t* Sg, uint32_t* Y, uint32_t* YV, uint32_t* bnd,
                           uint32_t* split_key, uint32_t* split_g, uint32_t* dev_err,
@@ -1084,10 +1085,15 @@ hipError_t gsd_merge_sort(const uint32_t* keys_in, uint32_t* keys_out, const uin
     hipError_t e = devseg_sort(4, keys_in, Y, vals_in, YV, n, lo, p, kSmallMaxDefault, seg_ws,
                                L.LS, dev_err, stream, prof);
     if (e != hipSuccess) return e;
-    // 2-3. regular sample of the sorted blocks, sorted by composite
-    hipLaunchKernelGGL(k_gsd_sample, dim3((uint32_t)((L.nT + 255) / 256)), dim3(256), 0, stream, Y,
-                       lo, p, s, Tk, Tg);
-    e = lsd_r8_sort(4, Tk, Sk, Tg, Sg, L.nT, 0, 32, w + L.off_lsd, L.LT, dev_err, stream, nullptr);
+    // 2-3. the sample of the sorted blocks, sorted by composite
+    if (L.kind == kGSD) {
+        hipLaunchKernelGGL(k_gsd_sample, dim3((uint32_t)((L.nT + 255) / 256)), dim3(256), 0, stream,
+                           Y, lo, p, s, Tk, Tg);
+        e = lsd_r8_sort(4, Tk, Sk, Tg, Sg, L.nT, 0, 32, w + L.off_lsd, L.LT, dev_err, stream,
+                        nullptr);
+    } else {
+        e = random_sample(Y, n, L, seed, w, Tk, Tg, Sk, Sg, dev_err, stream);
+    }
     if (e != hipSuccess) return e;
     // 4. splitters, the fine split, the buckets' split bounds
     uint64_t* BK = (uint64_t*)(w + L.off_BK);
@@ -1137,8 +1143,8 @@ hipError_t gsd_sort(const uint32_t* keys_in, uint32_t* keys_out, const uint32_t*
     if (L.kind == kGVR)
         return gvr_sort(keys_in, keys_out, vals_in, vals_out, n, L, seed, w, lo, Tk, Tg, Sk, Sg, Y,
                         YV, bnd, split_key, split_g, boff, dev_err, stream, prof);
-    if (L.merge) return gsd_merge_sort(keys_in, keys_out, vals_in, vals_out, n, L, w, lo, Tk, Tg,
-                                       Sk, Sg, Y, YV, bnd, split_key, split_g, dev_err, stream,
+    if (L.merge) return gsd_merge_sort(keys_in, keys_out, vals_in, vals_out, n, L, seed, w, lo, Tk,
+                                       Tg, Sk, Sg, Y, YV, bnd, split_key, split_g, dev_err, stream,
                                        prof);
     // 1. local sort of the blocks into the output arrays
     hipError_t e = devseg_sort(4, keys_in, keys_out, vals_in, vals_out, n, lo, p, small_max,
