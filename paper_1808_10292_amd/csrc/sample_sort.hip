@@ -662,13 +662,25 @@ __global__ __launch_bounds__(256) void k_gsd_fine_split(const uint32_t* __restri
         }
         return lo_i;
     };
+    // Boundaries with index i in [range[0], range[1]) (B_{i+1}) rank in this
+    // chunk; of those, the ones below the block's first key rank 0 and the
+    // ones at or above its last key rank N_k (first / last chunk only), which
+    // needs no search: with presorted input most boundaries are of this kind
+    // and fall to the two end chunks of every block.
+    __shared__ uint32_t inner[2];
     if (tid == 0)   // the key before the chunk, (X_{c0-1}, index)
         range[0] = c0 == 0 ? 0u : first_not_below((uint64_t)X[b + c0 - 1] << 32 | (b + c0 - 1));
     if (tid == 64)
         range[1] = last ? M : first_not_below((uint64_t)xs[c1 - c0 - 1] << 32 | (b + c1 - 1));
+    if (tid == 128)   // first boundary not below the block's first key
+        inner[0] = c0 == 0 && c1 > c0 ? first_not_below((uint64_t)xs[0] << 32 | b) : 0u;
+    if (tid == 192)   // first boundary not below the block's last key
+        inner[1] = last && c1 > c0 ? first_not_below((uint64_t)xs[c1 - c0 - 1] << 32 | (b + c1 - 1)) : M;
     __syncthreads();
-    // boundaries with index i in [range[0], range[1]) are B_{i+1}
-    for (uint32_t i = range[0] + tid; i < range[1]; i += 256) {
+    const uint32_t i0 = max(range[0], inner[0]), i1 = max(i0, min(range[1], inner[1]));
+    for (uint32_t i = range[0] + tid; i < i0; i += 256) F[(size_t)k * (M + 2) + i + 1] = 0;
+    for (uint32_t i = i1 + tid; i < range[1]; i += 256) F[(size_t)k * (M + 2) + i + 1] = nk;
+    for (uint32_t i = i0 + tid; i < i1; i += 256) {
         const uint64_t bnd = BK[i];
         uint32_t a = 0, e = c1 - c0;   // first q in the chunk with B < (X_q, index)
         while (a < e) {
