@@ -67,6 +67,14 @@ __device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t x)
     return x;
 }
 
+// True (for the whole wave) when every lane of the wave is valid and holds
+// the same digit d: then the lanes of a 32-lane group rank in lane order.
+__device__ __forceinline__ bool wave_one_digit(bool valid, uint32_t d)
+{
+    const uint32_t d0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)d);
+    return __builtin_amdgcn_ballot_w64(valid && d == d0) == ~0ull;
+}
+
 template <typename K>
 __device__ __forceinline__ uint32_t digit_of(K key, uint32_t shift, uint32_t mask)
 {

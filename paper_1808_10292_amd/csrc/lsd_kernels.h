@@ -53,7 +53,17 @@ constexpr uint32_t kNoTile = 0xFFFFFFFFu;
 #define RSORT_R8_WAVES_PER_EU 8
 #endif
 #ifndef RSORT_R8_WAVES_PER_EU_KV
-#define RSORT_R8_WAVES_PER_EU_KV 5
+#define RSORT_R8_WAVES_PER_EU_KV 4
+#endif
+#ifndef RSORT_R8_WAVES_PER_EU_KV64
+#define RSORT_R8_WAVES_PER_EU_KV64 5
+#endif
+// LDS the scatter of 32-bit keys with payloads reserves beyond its needs (u32
+// words), so that at most two of its 512-thread workgroups (4 waves per SIMD)
+// share a CU.  Measured with 2^28 key-value pairs: 4.54 ms per sort at two
+// workgroups per CU, 5.57 ms at three (uniform keys).
+#ifndef RSORT_SCATTER_KV_LDS_RESERVE
+#define RSORT_SCATTER_KV_LDS_RESERVE 6144
 #endif
 // Tiles per block of the tile scan, and predecessor blocks read per look-back step.
 #ifndef RSORT_SCAN_BLOCK
@@ -562,7 +572,7 @@ __global__ __launch_bounds__(R) void k_tilescan(RoundArgs a)
 //   scatter consecutive threads write consecutive slots of a digit's run; the
 //          payloads follow in a second staging pass through the same LDS.
 template <typename K, bool KV, int WG, int ITEMS>
-__global__ __launch_bounds__(WG, KV ? RSORT_R8_WAVES_PER_EU_KV : RSORT_R8_WAVES_PER_EU) void k_scatter(RoundArgs a)
+__global__ __launch_bounds__(WG, !KV ? RSORT_R8_WAVES_PER_EU : sizeof(K) == 4 ? RSORT_R8_WAVES_PER_EU_KV : RSORT_R8_WAVES_PER_EU_KV64) void k_scatter(RoundArgs a)
 {
     constexpr int G = RSORT_RANK_GROUP;         // lanes per ranking group
     constexpr int NG = WG / G;                  // ranking groups
@@ -580,6 +590,7 @@ __global__ __launch_bounds__(WG, KV ? RSORT_R8_WAVES_PER_EU_KV : RSORT_R8_WAVES_
         } u;
         uint32_t goff[R];                // output index of tile slot 0 of each digit
         uint32_t wsum[4];
+        uint32_t reserve[KV && sizeof(K) == 4 ? RSORT_SCATTER_KV_LDS_RESERVE : 1];   // occupancy cap, unused
     };
     __shared__ Smem sm;
 
@@ -646,6 +657,18 @@ __global__ __launch_bounds__(WG, KV ? RSORT_R8_WAVES_PER_EU_KV : RSORT_R8_WAVES_
                 for (int i = 0; i < ITEMS; ++i) {
                     const bool ok = hofs + i * G < lim;
                     const uint32_t d = digit_of(k[i], a.shift, a.mask);
+                    if (wave_one_digit(ok, d)) {
+                        // every lane of the wave holds this digit: no lane
+                        // set to build, one lane per group moves the count
+                        const uint32_t c = (uint32_t)(__hip_atomic_load((uint64_t*)&sl[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >> 32);
+                        pos[i] = c + gl;
+                        wave_lds_order();
+                        if (gl == 0)
+                            __hip_atomic_store((uint64_t*)&sl[d], (uint64_t)(c + 32) << 32,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        wave_lds_order();
+                        continue;
+                    }
                     if (ok) __hip_atomic_fetch_or(&sl[d].x, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                     wave_lds_order();
                     const uint64_t s = ok ? __hip_atomic_load((uint64_t*)&sl[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : 0ull;
@@ -693,8 +716,13 @@ __global__ __launch_bounds__(WG, KV ? RSORT_R8_WAVES_PER_EU_KV : RSORT_R8_WAVES_
             // count first: the slots' counts get the per-group digit counts
 #pragma unroll
             for (int i = 0; i < ITEMS; ++i) {
-                if (hofs + i * G < lim) {
-                    const uint32_t d = digit_of(k[i], a.shift, a.mask);
+                const bool ok = hofs + i * G < lim;
+                const uint32_t d = digit_of(k[i], a.shift, a.mask);
+                if (G == 32 && wave_one_digit(ok, d)) {   // one add per group
+                    if (gl == 0) atomicAdd(&sm.u.slot[grp][d].y, 32u);
+                    continue;
+                }
+                if (ok) {
                     if constexpr (G == 32) atomicAdd(&sm.u.slot[grp][d].y, 1u);
                     else atomicAdd(&sm.u.slot16[grp][d], 1u << 16);
                 }

@@ -55,8 +55,15 @@ __device__ bool tile_round(TileSmem<K, KV, WG, ITEMS>& sm, K (&k)[ITEMS], uint32
     // count
     uint2* sl = sm.slot[hw];
 #pragma unroll
-    for (int i = 0; i < ITEMS; ++i)
-        if (hofs + i * 32 < len) atomicAdd(&sl[digit_of(k[i], shift, mask)].y, 1u);
+    for (int i = 0; i < ITEMS; ++i) {
+        const bool ok = hofs + i * 32 < len;
+        const uint32_t d = digit_of(k[i], shift, mask);
+        if (wave_one_digit(ok, d)) {   // whole wave one digit: one add per half-wave
+            if (hl == 0) atomicAdd(&sl[d].y, 32u);
+            continue;
+        }
+        if (ok) atomicAdd(&sl[d].y, 1u);
+    }
     __syncthreads();
     // bases
     uint32_t run = 0, total = 0;
@@ -88,6 +95,16 @@ __device__ bool tile_round(TileSmem<K, KV, WG, ITEMS>& sm, K (&k)[ITEMS], uint32
         for (int i = 0; i < ITEMS; ++i) {
             const bool ok = hofs + i * 32 < len;
             const uint32_t d = digit_of(k[i], shift, mask);
+            if (wave_one_digit(ok, d)) {   // whole wave one digit: ranks in lane order
+                const uint32_t c = (uint32_t)(__hip_atomic_load((uint64_t*)&sl[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >> 32);
+                pos[i] = c + hl;
+                wave_lds_order();
+                if (hl == 0)
+                    __hip_atomic_store((uint64_t*)&sl[d], (uint64_t)(c + 32) << 32, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                wave_lds_order();
+                continue;
+            }
             if (ok) __hip_atomic_fetch_or(&sl[d].x, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             wave_lds_order();
             const uint64_t s = ok ? __hip_atomic_load((uint64_t*)&sl[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : 0ull;
