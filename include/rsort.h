@@ -324,7 +324,10 @@ int rsort_synchronize(rsort_ctx* ctx, void* stream);
 
 /* Kernel timing for measurement.  While enabled, every sort on ctx records a
  * HIP event on its stream immediately before and after each kernel of the
- * kinds below; enabling (or disabling) resets the totals. */
+ * timed kinds below; enabling (or disabling) resets the totals.  enable: 0
+ * disables, otherwise a bit mask of the kinds to time (bit 1 << kind; -1 times
+ * every kind).  Each event pair delays the stream by a few microseconds, so
+ * time only the kinds you read. */
 enum rsort_kernel_kind {
     RSORT_KERNEL_ROUND = 0,     /* rank-and-scatter kernel of a count-sort round  */
     RSORT_KERNEL_HIST = 1,      /* all-rounds digit counting before the rounds    */

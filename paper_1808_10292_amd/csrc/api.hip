@@ -23,6 +23,7 @@ struct Profiler {
     };
     std::vector<hipEvent_t> pool;
     std::vector<Pair> pending;
+    uint32_t kinds = ~0u;   // bit k: kernels of kind k are timed
     hipEvent_t open_start[kNumKinds] = {};
     uint64_t launches[kNumKinds] = {};
     double total_ms[kNumKinds] = {};
@@ -61,6 +62,7 @@ struct Profiler {
 
 void profiler_mark(Profiler* p, hipStream_t s, int kind, bool begin)
 {
+    if (!(p->kinds & (1u << kind))) return;
     hipEvent_t e = p->get();
     if (!e) return;
     (void)hipEventRecord(e, s);
@@ -598,6 +600,7 @@ int rsort_profile_enable(rsort_ctx* ctx, int enable)
     if (enable) {
         ctx->prof = new (std::nothrow) rsort::Profiler;
         if (!ctx->prof) return fail(ctx, RSORT_ENOMEM, "profiler");
+        ctx->prof->kinds = (uint32_t)enable;
     }
     return RSORT_OK;
 }

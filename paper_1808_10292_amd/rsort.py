@@ -278,10 +278,14 @@ def rsort_synchronize(stream=None, device=None):
               "rsort_synchronize")
 
 
-def rsort_profile_enable(enable=True, device=None):
+def rsort_profile_enable(enable=True, kinds=None, device=None):
+    """Start (or stop, enable=False) kernel timing; kinds: iterable of
+    RSORT_KERNEL_* values to time (default: every kind)."""
     ctx = context(device)
-    ctx.check(ctx._lib.rsort_profile_enable(ctx.handle, int(bool(enable))),
-              "rsort_profile_enable")
+    mask = 0
+    if enable:
+        mask = -1 if kinds is None else sum(1 << int(k) for k in set(kinds))
+    ctx.check(ctx._lib.rsort_profile_enable(ctx.handle, int(mask)), "rsort_profile_enable")
 
 
 def rsort_profile_read(kind=RSORT_KERNEL_ROUND, device=None):
