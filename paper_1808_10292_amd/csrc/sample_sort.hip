@@ -41,6 +41,7 @@
 // into bucket order (X_{k,j} for k = 0..p-1 concatenated is bucket j).  The
 // finish sorts every bucket as above.  p <= 256: one 8-bit routing digit.
 #include <algorithm>
+#include <type_traits>
 
 #include "lsd_kernels.h"
 #include "tile_sort.h"
@@ -53,6 +54,12 @@ constexpr uint32_t kRouteItems = 16;
 constexpr uint32_t kRouteTile = kRouteWG * kRouteItems;   // keys per route workgroup
 constexpr uint32_t kScanCols = 64;                        // bucket columns per scan workgroup
 constexpr uint32_t kScanGroups = 16;                      // block groups per column
+
+// dst[0 .. count) = value.
+__global__ void k_fill_u32(uint32_t* dst, uint32_t count, uint32_t value)
+{
+    for (uint32_t i = threadIdx.x; i < count; i += blockDim.x) dst[i] = value;
+}
 
 // lo[k] = floor(k n / p), k = 0..p.
 __global__ void k_gsd_blocks(uint32_t* lo, uint32_t n, uint32_t p)
@@ -724,54 +731,79 @@ __device__ __forceinline__ uint32_t wave_inclusive_max(uint32_t x)
 // and the 64 lanes of a wave hit 64 different banks.
 __device__ __forceinline__ uint32_t mark_idx(uint32_t u) { return u + 2 * (u >> 4); }
 
-// One workgroup per piece: the p sub-runs are read in run order (block order,
-// which is input order on equal keys), combined by a stable sort in LDS --
-// one tile_round per byte, rounds whose byte is the same for the whole piece
-// skipped -- which is their merge, and written once at the piece's start.  A
-// piece larger than the LDS tile is gathered into a temporary and sorted in
-// chunks, round by round, between the temporary and its own output range.
+// LDS of the piece merge outside the ranking tile.
+struct MergeRuns {
+    uint32_t src[kMergeMaxP];        // first element of run k in X
+    uint32_t off[kMergeMaxP + 1];    // start of run k in the piece
+};
+struct MergeDigits {
+    uint32_t st[R];                  // next output index of each digit
+    uint32_t cs[R];                  // digit starts inside the chunk
+    uint32_t cc[R];                  // digit counts of the chunk
+};
+union MergeAux {
+    MergeRuns r;
+    MergeDigits d;
+};
+
+// Registers <- piece positions [c0, c0 + nc) in the ranking layout (position
+// c0 + hofs + 32 i in register i).  The run of every position is found
+// through a map: run k + 1 is marked at its first position in the chunk, and
+// a running maximum fills the positions after it.
 template <bool KV>
-__global__ __launch_bounds__(kMergeWG) void k_gsd_merge(const uint32_t* __restrict__ X,
-                                                        const uint32_t* __restrict__ XV,
-                                                        const uint32_t* lo, uint32_t p,
-                                                        uint32_t M, uint32_t g,
-                                                        const uint32_t* Sk, const uint32_t* F,
-                                                        uint32_t* out, uint32_t* vout,
-                                                        uint32_t* tmp, uint32_t* vtmp)
+__device__ __forceinline__ void merge_gather(const uint32_t* __restrict__ X,
+                                             const uint32_t* __restrict__ XV, uint32_t p,
+                                             const MergeRuns& runs, uint16_t* mark, uint32_t* wsc,
+                                             uint32_t c0, uint32_t nc,
+                                             uint32_t (&k)[kMergeItems], uint32_t (&v)[kMergeItems])
 {
-    constexpr int ITEMS = kMergeItems;
-    constexpr uint32_t C = kMergeCap;
-    static_assert(kMarkLen * 2 <= sizeof(uint2) * (kMergeWG / 32) * kTileRadix,
-                  "the run map lives in the ranking slots");
-    __shared__ TileSmem<uint32_t, KV, kMergeWG, ITEMS> sm;
-    __shared__ union {
-        struct {
-            uint32_t src[kMergeMaxP];        // first element of run k in X
-            uint32_t off[kMergeMaxP + 1];    // start of run k in the piece
-        } r;
-        struct {
-            uint32_t st[R];                  // next output index of each digit
-            uint32_t cs[R];                  // digit starts inside the chunk
-            uint32_t cc[R];                  // digit counts of the chunk
-        } d;
-    } aux;
-    __shared__ uint32_t wsc[4];
-    __shared__ uint32_t tot[2];
     const uint32_t tid = threadIdx.x;
-    const uint32_t hofs = (tid >> 5) * ITEMS * 32 + (tid & 31);
-    // Piece of this workgroup.  The grid (a multiple of 8) is dealt to the 8
-    // XCDs in turn; XCD x takes the x-th eighth of the pieces, so neighbouring
-    // pieces, whose runs and outputs share cache lines, meet in one L2.  The
-    // last eighth runs backwards: the two edge pieces (keys below the first and
-    // above the last boundary of every block, the largest) start first.
-    const uint32_t per = gridDim.x >> 3, x = blockIdx.x & 7, j = blockIdx.x >> 3;
-    const uint32_t m = x * per + (x == 7 ? per - 1 - j : j);
-    if (m > M) return;
-    // keys of the piece lie between the keys of its bounding boundaries: the
-    // bytes above their highest differing bit are the same for all of them
-    const uint32_t klo = m == 0 ? 0u : Sk[(size_t)m * g - 1];
-    const uint32_t khi = m == M ? 0xFFFFFFFFu : Sk[(size_t)(m + 1) * g - 1];
-    const uint32_t varying = klo ^ khi;
+    const uint32_t hofs = (tid >> 5) * kMergeItems * 32 + (tid & 31);
+    for (uint32_t j = tid; j < kMarkLen / 2; j += kMergeWG) ((uint32_t*)mark)[j] = 0;
+    __syncthreads();
+    if (tid < p) {
+        const uint32_t a = runs.off[tid], e = runs.off[tid + 1];
+        const uint32_t s0 = max(a, c0), e0 = min(e, c0 + nc);
+        if (s0 < e0) mark[mark_idx(s0 - c0)] = (uint16_t)(tid + 1);
+    }
+    __syncthreads();
+    uint32_t run = 0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) run = max(run, (uint32_t)mark[mark_idx(16 * tid + j)]);
+    const uint32_t wmax = wave_inclusive_max(run);
+    if ((tid & 63) == 63) wsc[tid >> 6] = wmax;
+    __syncthreads();
+    uint32_t cur = __shfl_up(wmax, 1, 64);
+    if ((tid & 63) == 0) cur = 0;
+    for (uint32_t w = 0; w < (tid >> 6); ++w) cur = max(cur, wsc[w]);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        cur = max(cur, (uint32_t)mark[mark_idx(16 * tid + j)]);
+        mark[mark_idx(16 * tid + j)] = (uint16_t)cur;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kMergeItems; ++i) {
+        const uint32_t u = hofs + i * 32;
+        k[i] = 0;
+        v[i] = 0;
+        if (u < nc) {
+            const uint32_t r = mark[mark_idx(u)] - 1u;
+            const uint32_t q = runs.src[r] + (c0 + u - runs.off[r]);
+            k[i] = X[q];
+            if (KV) v[i] = XV[q];
+        }
+    }
+    __syncthreads();   // the map area is free again
+}
+
+// Piece m's runs: aux.r.src / aux.r.off from the bounds F (p <= 256, one run
+// per thread); returns {keys in the piece, its output start}.
+__device__ __forceinline__ uint2 merge_setup(const uint32_t* lo, uint32_t p, uint32_t M,
+                                             const uint32_t* F, uint32_t m, MergeRuns& runs,
+                                             uint32_t* wsc, uint32_t* tot)
+{
+    const uint32_t tid = threadIdx.x;
     uint32_t len = 0, before = 0;
     if (tid < p) {
         const uint32_t* f = F + (size_t)tid * (M + 2) + m;
@@ -781,85 +813,138 @@ __global__ __launch_bounds__(kMergeWG) void k_gsd_merge(const uint32_t* __restri
     const uint32_t incl = block256_inclusive_sum(len, wsc);
     const uint32_t start = block256_inclusive_sum(before, wsc);
     if (tid < p) {
-        aux.r.src[tid] = lo[tid] + before;
-        aux.r.off[tid] = incl - len;
+        runs.src[tid] = lo[tid] + before;
+        runs.off[tid] = incl - len;
     }
     if (tid == kMergeWG - 1) {
         tot[0] = incl;    // keys in the piece
         tot[1] = start;   // keys before it: its output start
-        aux.r.off[p] = incl;
+        runs.off[p] = incl;
     }
     __syncthreads();
-    const uint32_t L = tot[0], base = tot[1];
-    if (L == 0) return;
+    return make_uint2(tot[0], tot[1]);
+}
 
-    uint16_t* mark = (uint16_t*)&sm.slot[0][0];
-    uint32_t k[ITEMS], v[ITEMS];
-    // Registers <- piece positions [c0, c0 + nc) in the ranking layout
-    // (position c0 + hofs + 32 i in register i).  The run of every position is
-    // found through a map: run k + 1 is marked at its first position in the
-    // chunk, and a running maximum fills the positions after it.
-    auto gather = [&](uint32_t c0, uint32_t nc) {
-        for (uint32_t j = tid; j < kMarkLen / 2; j += kMergeWG) ((uint32_t*)mark)[j] = 0;
-        __syncthreads();
-        if (tid < p) {
-            const uint32_t a = aux.r.off[tid], e = aux.r.off[tid + 1];
-            const uint32_t s0 = max(a, c0), e0 = min(e, c0 + nc);
-            if (s0 < e0) mark[mark_idx(s0 - c0)] = (uint16_t)(tid + 1);
-        }
-        __syncthreads();
-        uint32_t run = 0;
-#pragma unroll
-        for (int j = 0; j < 16; ++j) run = max(run, (uint32_t)mark[mark_idx(16 * tid + j)]);
-        const uint32_t wmax = wave_inclusive_max(run);
-        if ((tid & 63) == 63) wsc[tid >> 6] = wmax;
-        __syncthreads();
-        uint32_t cur = __shfl_up(wmax, 1, 64);
-        if ((tid & 63) == 0) cur = 0;
-        for (uint32_t w = 0; w < (tid >> 6); ++w) cur = max(cur, wsc[w]);
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            cur = max(cur, (uint32_t)mark[mark_idx(16 * tid + j)]);
-            mark[mark_idx(16 * tid + j)] = (uint16_t)cur;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i) {
-            const uint32_t u = hofs + i * 32;
-            k[i] = 0;
-            v[i] = 0;
-            if (u < nc) {
-                const uint32_t r = mark[mark_idx(u)] - 1u;
-                const uint32_t q = aux.r.src[r] + (c0 + u - aux.r.off[r]);
-                k[i] = X[q];
-                if (KV) v[i] = XV[q];
-            }
-        }
-        __syncthreads();   // the map area is the ranking slots again
+// Key bounds of piece m: its keys lie between the keys of its two boundaries.
+__device__ __forceinline__ uint2 merge_key_bounds(const uint32_t* Sk, uint32_t g, uint32_t M,
+                                                  uint32_t m)
+{
+    return make_uint2(m == 0 ? 0u : Sk[(size_t)m * g - 1],
+                      m == M ? 0xFFFFFFFFu : Sk[(size_t)(m + 1) * g - 1]);
+}
+
+// One workgroup per piece: the p sub-runs are read in run order (block order,
+// which is input order on equal keys), combined by a stable sort in LDS --
+// one tile_round per byte, rounds whose byte is the same for the whole piece
+// skipped -- which is their merge, and written once at the piece's start.
+// The piece is sorted as words key - lower bound (with payloads (key - lower
+// bound) << 12 | position, the payloads following by position; that needs
+// keys within 2^20 of the lower bound), keys only, on the bits the piece's
+// key range spans.  Pieces beyond one LDS tile, and with
+// payloads pieces of a wider key range, are only listed here (large[0] =
+// count, large[1..] = pieces) for k_gsd_merge_large.
+// 3 waves per SIMD: three 4-wave workgroups per CU fit its LDS.
+template <bool KV>
+__global__ __launch_bounds__(kMergeWG, 3) void k_gsd_merge(const uint32_t* __restrict__ X,
+                                                           const uint32_t* __restrict__ XV,
+                                                           const uint32_t* lo, uint32_t p,
+                                                           uint32_t M, uint32_t g,
+                                                           const uint32_t* Sk, const uint32_t* F,
+                                                           uint32_t* out, uint32_t* vout,
+                                                           uint32_t* large)
+{
+    constexpr int ITEMS = kMergeItems;
+    constexpr uint32_t C = kMergeCap;
+    static_assert(kMarkLen * 2 <= sizeof(uint2) * (kMergeWG / 32) * kTileRadix,
+                  "the run map lives in the ranking slots");
+    // LDS: the keys-only ranking tile, with payloads followed by the payloads
+    // staged by piece position
+    using SmK = TileSmem<uint32_t, false, kMergeWG, ITEMS>;
+    struct Packed {
+        SmK t;
+        uint32_t vst[KV ? C : 1];
     };
-
-    if (L <= C) {
-        gather(0, L);
-#pragma unroll 1
-        for (uint32_t d = 0; d < 4 && (varying >> (8 * d)); ++d)
-            tile_round<uint32_t, KV, kMergeWG, ITEMS>(sm, k, v, L, 8u * d, 0xFFu);
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i) {
-            const uint32_t u = hofs + i * 32;
-            if (u < L) {
-                out[base + u] = k[i];
-                if (KV) vout[base + u] = v[i];
-            }
-        }
+    __shared__ Packed smu;
+    __shared__ MergeRuns runs;
+    __shared__ uint32_t wsc[4];
+    __shared__ uint32_t tot[2];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t hofs = (tid >> 5) * ITEMS * 32 + (tid & 31);
+    // Piece of this workgroup.  The grid (a multiple of 8) is dealt to the 8
+    // XCDs in turn; XCD x takes the x-th eighth of the pieces, so neighbouring
+    // pieces, whose runs and outputs share cache lines, meet in one L2.
+    const uint32_t per = gridDim.x >> 3, x = blockIdx.x & 7, j = blockIdx.x >> 3;
+    const uint32_t m = x * per + j;
+    if (m > M) return;
+    const uint2 kb = merge_key_bounds(Sk, g, M, m);
+    const uint32_t klo = kb.x, khi = kb.y;
+    const uint2 lb = merge_setup(lo, p, M, F, m, runs, wsc, tot);
+    const uint32_t L = lb.x, base = lb.y;
+    if (L == 0) return;
+    if (L > C || (KV && khi - klo >= (1u << 20))) {
+        if (tid == 0) large[1 + atomicAdd(&large[0], 1u)] = m;
         return;
     }
+    uint16_t* mark = (uint16_t*)&smu.t.slot[0][0];   // run map in the ranking slots
+    uint32_t k[ITEMS], v[ITEMS];
+    merge_gather<KV>(X, XV, p, runs, mark, wsc, 0, L, k, v);
+    // word = (key - klo) << 12 | position with payloads (range < 2^20), or
+    // key - klo without; a keys-only stable sort on the range bits
+    constexpr uint32_t low = KV ? 12u : 0u;
+    const uint32_t range = khi - klo;
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t u = hofs + i * 32;
+        if (KV && u < L) smu.vst[u] = v[i];
+        k[i] = ((k[i] - klo) << low) | (KV ? u : 0u);
+    }
+    const uint32_t nb = range ? 32u - __builtin_clz(range) : 0u;
+#pragma unroll 1
+    for (uint32_t sh = 0; sh < nb; sh += 8) {
+        const uint32_t w = min(8u, nb - sh);
+        tile_round<uint32_t, false, kMergeWG, ITEMS>(smu.t, k, v, L, low + sh, (1u << w) - 1u);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t u = hofs + i * 32;
+        if (u < L) {
+            out[base + u] = klo + (k[i] >> low);
+            if (KV) vout[base + u] = smu.vst[k[i] & 0xFFFu];
+        }
+    }
+}
 
-    // Large piece: gather into tmp[base, base + L), then per byte a stable
-    // count sort of the whole piece, chunk by chunk, between tmp and
-    // out[base, base + L) (both owned by this piece alone).
+// The pieces k_gsd_merge listed (beyond one LDS tile, or with payloads a
+// key range of 2^20 or more: mostly the two edge pieces), one workgroup each;
+// the grid is an upper bound (every piece) and surplus workgroups exit.  The piece is gathered
+// into tmp[base, base + L), then per byte stably count-sorted, chunk by
+// chunk, between tmp and out[base, base + L) (both owned by this piece).
+template <bool KV>
+__global__ __launch_bounds__(kMergeWG) void k_gsd_merge_large(
+    const uint32_t* __restrict__ X, const uint32_t* __restrict__ XV, const uint32_t* lo,
+    uint32_t p, uint32_t M, uint32_t g, const uint32_t* Sk, const uint32_t* F, uint32_t* out,
+    uint32_t* vout, uint32_t* tmp, uint32_t* vtmp, const uint32_t* large)
+{
+    constexpr int ITEMS = kMergeItems;
+    constexpr uint32_t C = kMergeCap;
+    __shared__ TileSmem<uint32_t, KV, kMergeWG, ITEMS> sm;
+    __shared__ MergeAux aux;
+    __shared__ uint32_t wsc[4];
+    __shared__ uint32_t tot[2];
+    if (blockIdx.x >= large[0]) return;
+    const uint32_t m = large[1 + blockIdx.x];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t hofs = (tid >> 5) * ITEMS * 32 + (tid & 31);
+    const uint2 kb = merge_key_bounds(Sk, g, M, m);
+    const uint32_t varying = kb.x ^ kb.y;
+    const uint2 lb = merge_setup(lo, p, M, F, m, aux.r, wsc, tot);
+    const uint32_t L = lb.x, base = lb.y;
+    uint16_t* mark = (uint16_t*)&sm.slot[0][0];
+    uint32_t k[ITEMS], v[ITEMS];
     for (uint32_t c0 = 0; c0 < L; c0 += C) {
         const uint32_t nc = min(C, L - c0);
-        gather(c0, nc);
+        merge_gather<KV>(X, XV, p, aux.r, mark, wsc, c0, nc, k, v);
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
             const uint32_t u = hofs + i * 32;
@@ -874,17 +959,18 @@ __global__ __launch_bounds__(kMergeWG) void k_gsd_merge(const uint32_t* __restri
     uint32_t* cv = KV ? vtmp + base : nullptr;
     uint32_t* ok = out + base;      // the other buffer
     uint32_t* ov = KV ? vout + base : nullptr;
+    MergeDigits& dg = aux.d;
 #pragma unroll 1
     for (uint32_t d = 0; d < 4 && (varying >> (8 * d)); ++d) {
         const uint32_t shift = 8u * d;
-        aux.d.st[tid] = 0;
+        dg.st[tid] = 0;
         __syncthreads();
-        for (uint32_t j = tid; j < L; j += kMergeWG) atomicAdd(&aux.d.st[digit_of(ck[j], shift, 0xFFu)], 1u);
+        for (uint32_t j = tid; j < L; j += kMergeWG) atomicAdd(&dg.st[digit_of(ck[j], shift, 0xFFu)], 1u);
         __syncthreads();
-        const uint32_t cnt = aux.d.st[tid];
+        const uint32_t cnt = dg.st[tid];
         if (__syncthreads_or(cnt == L)) continue;   // one byte value everywhere: nothing moves
         const uint32_t ex = block256_inclusive_sum(cnt, wsc) - cnt;
-        aux.d.st[tid] = ex;
+        dg.st[tid] = ex;
         __syncthreads();
 #pragma unroll 1
         for (uint32_t c0 = 0; c0 < L; c0 += C) {
@@ -895,14 +981,14 @@ __global__ __launch_bounds__(kMergeWG) void k_gsd_merge(const uint32_t* __restri
                 k[i] = u < nc ? ck[c0 + u] : 0u;
                 v[i] = KV && u < nc ? cv[c0 + u] : 0u;
             }
-            aux.d.cc[tid] = 0;
+            dg.cc[tid] = 0;
             __syncthreads();
 #pragma unroll
             for (int i = 0; i < ITEMS; ++i)
-                if (hofs + i * 32 < nc) atomicAdd(&aux.d.cc[digit_of(k[i], shift, 0xFFu)], 1u);
+                if (hofs + i * 32 < nc) atomicAdd(&dg.cc[digit_of(k[i], shift, 0xFFu)], 1u);
             __syncthreads();
-            const uint32_t c = aux.d.cc[tid];
-            aux.d.cs[tid] = block256_inclusive_sum(c, wsc) - c;
+            const uint32_t c = dg.cc[tid];
+            dg.cs[tid] = block256_inclusive_sum(c, wsc) - c;
             __syncthreads();
             tile_round<uint32_t, KV, kMergeWG, ITEMS>(sm, k, v, nc, shift, 0xFFu);
 #pragma unroll
@@ -910,13 +996,13 @@ __global__ __launch_bounds__(kMergeWG) void k_gsd_merge(const uint32_t* __restri
                 const uint32_t u = hofs + i * 32;
                 if (u < nc) {
                     const uint32_t dv = digit_of(k[i], shift, 0xFFu);
-                    const uint32_t o = aux.d.st[dv] + u - aux.d.cs[dv];
+                    const uint32_t o = dg.st[dv] + u - dg.cs[dv];
                     ok[o] = k[i];
                     if (KV) ov[o] = v[i];
                 }
             }
             __syncthreads();
-            aux.d.st[tid] += c;
+            dg.st[tid] += c;
             __syncthreads();
         }
         uint32_t* t = ck; ck = ok; ok = t;
@@ -969,6 +1055,7 @@ GsdLayout skeleton_layout(bool has_vals, size_t n, uint32_t p, uint32_t s, size_
         L.M = (uint32_t)(L.nT / g);
         L.off_F = o;       o = align_up(o + ((size_t)L.M + 2) * p * 4);
         L.off_BK = o;      o = align_up(o + (size_t)L.M * 8);
+        L.off_large = o;   o = align_up(o + ((size_t)L.M + 2) * 4);
     }
     if (kind == kGVR) {
         L.route_tpb = (uint32_t)(((n + p - 1) / p + kGvrTile - 1) / kGvrTile);
@@ -1116,13 +1203,21 @@ hipError_t gsd_merge_sort(const uint32_t* keys_in, uint32_t* keys_out, const uin
     hipLaunchKernelGGL(k_gsd_fine_bnd, dim3((nb + 255) / 256), dim3(256), 0, stream, F, p, s, g, M,
                        Sk, Sg, bnd, split_key, split_g);
     // 5. merge every piece into the output
+    uint32_t* large = (uint32_t*)(w + L.off_large);
+    const uint32_t max_large = M + 1;
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, stream, large, 1u, 0u);
     const dim3 mg((M + 1 + 7) & ~7u);
-    if (vals_in)
+    if (vals_in) {
         hipLaunchKernelGGL(k_gsd_merge<true>, mg, dim3(kMergeWG), 0, stream, Y, YV, lo, p, M, g, Sk,
-                           F, keys_out, vals_out, tmp, vtmp);
-    else
+                           F, keys_out, vals_out, large);
+        hipLaunchKernelGGL(k_gsd_merge_large<true>, dim3(max_large), dim3(kMergeWG), 0, stream, Y,
+                           YV, lo, p, M, g, Sk, F, keys_out, vals_out, tmp, vtmp, large);
+    } else {
         hipLaunchKernelGGL(k_gsd_merge<false>, mg, dim3(kMergeWG), 0, stream, Y, nullptr, lo, p, M,
-                           g, Sk, F, keys_out, nullptr, tmp, nullptr);
+                           g, Sk, F, keys_out, nullptr, large);
+        hipLaunchKernelGGL(k_gsd_merge_large<false>, dim3(max_large), dim3(kMergeWG), 0, stream, Y,
+                           nullptr, lo, p, M, g, Sk, F, keys_out, nullptr, tmp, nullptr, large);
+    }
     return hipGetLastError();
 }
 

@@ -37,7 +37,7 @@ struct TileSmem {
 // untouched); true if k / v now hold the new order and LDS keys[] / vals[]
 // hold the tile in that order.  Every thread of the workgroup must call it.
 template <typename K, bool KV, int WG, int ITEMS>
-__device__ bool tile_round(TileSmem<K, KV, WG, ITEMS>& sm, K (&k)[ITEMS], uint32_t (&v)[ITEMS],
+__device__ __forceinline__ bool tile_round(TileSmem<K, KV, WG, ITEMS>& sm, K (&k)[ITEMS], uint32_t (&v)[ITEMS],
                            uint32_t len, uint32_t shift, uint32_t mask)
 {
     constexpr int HW = WG / 32;
