@@ -131,7 +131,7 @@ struct GsdLayout {
     // sample element, M boundaries, F = (M + 2) x p run bounds
     bool merge;
     uint32_t g, M;
-    size_t off_F, off_BK, off_large;
+    size_t off_F, off_BK, off_large, off_R;
     // GVR route: tile counts, tile-scan state, round plan + ticket, bucket
     // starts, and one bucket byte per key
     uint32_t route_tpb, route_ntiles;

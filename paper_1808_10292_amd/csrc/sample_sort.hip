@@ -614,14 +614,11 @@ constexpr uint32_t kMergeCap = kMergeWG * kMergeItems;   // piece merged whole i
 constexpr uint32_t kMergeMaxP = 256;                     // one run per thread
 constexpr uint32_t kMarkLen = kMergeCap + kMergeCap / 8; // padded run map (u16 entries)
 
-// F[k][m] for m = 0..M+1, block-major (M + 2 per block).  Workgroup (c, k) takes
-// chunk c (8192 keys) of sorted block k into LDS and handles the boundaries
-// whose rank in the block falls in the chunk: B_m with X[c0 - 1] <= B_m <
-// X[c1 - 1] (first chunk: no lower condition; last: no upper one), found by
-// two binary searches over the boundaries; each is then ranked inside the
-// chunk by binary search in LDS.  Every block key is read once.
+// F[k][m] for m = 0..M+1, block-major (M + 2 per block).  Chunk c (8192 keys)
+// of sorted block k handles the boundaries whose rank in the block falls in
+// it: B_m with X[c0 - 1] <= B_m < X[c1 - 1] (first chunk: no lower
+// condition; last: no upper one); every block key is read once.
 constexpr uint32_t kFineChunk = 8192;
-constexpr uint32_t kCoarse = 256;   // boundaries per entry of the coarse index
 
 // BK[m - 1] = B_m as one 64-bit composite (key << 32 | index), m = 1..M.
 __global__ void k_gsd_bounds(const uint32_t* Sk, const uint32_t* Sg, uint32_t g, uint32_t M,
@@ -631,14 +628,59 @@ __global__ void k_gsd_bounds(const uint32_t* Sk, const uint32_t* Sg, uint32_t g,
     if (m <= M) BK[m - 1] = ((uint64_t)Sk[(size_t)m * g - 1] << 32) | Sg[(size_t)m * g - 1];
 }
 
+// Index (0..M) of the first boundary not below composite x: BK[i] >= x.
+__device__ __forceinline__ uint32_t first_boundary_not_below(const uint64_t* __restrict__ BK,
+                                                             uint32_t M, uint64_t x)
+{
+    uint32_t a = 0, e = M;
+    while (a < e) {
+        const uint32_t mid = (a + e) >> 1;
+        if (BK[mid] < x) a = mid + 1; else e = mid;
+    }
+    return a;
+}
+
+// Boundary ranges of the fine split's chunks, all searched at once: for block
+// k, R[k][c] (c = 1 .. nch - 1) = first boundary not below the key before
+// chunk c; R[k][nch] / R[k][nch + 1] = first boundary not below the block's
+// first / last key (0 and M for an empty block).
+__global__ void k_gsd_chunk_ranges(const uint32_t* __restrict__ X, const uint32_t* lo, uint32_t p,
+                                   uint32_t M, uint32_t nch, const uint64_t* __restrict__ BK,
+                                   uint32_t* R)
+{
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t w = nch + 2;
+    if (t >= p * w) return;
+    const uint32_t k = t / w, c = t - k * w;
+    const uint32_t b = lo[k], nk = lo[k + 1] - b;
+    uint32_t q;   // block position of the key compared, or none
+    uint32_t res;
+    if (c == 0) {
+        res = 0;
+    } else if (c < nch) {
+        q = c * kFineChunk - 1;
+        res = q < nk ? first_boundary_not_below(BK, M, (uint64_t)X[b + q] << 32 | (b + q)) : M;
+    } else if (nk == 0) {
+        res = c == nch ? 0u : M;
+    } else {
+        q = c == nch ? 0u : nk - 1;
+        res = first_boundary_not_below(BK, M, (uint64_t)X[b + q] << 32 | (b + q));
+    }
+    R[t] = res;
+}
+
+// Workgroup (c, k): chunk c of sorted block k in LDS; the boundaries whose
+// rank in the block falls in the chunk, [R[k][c], R[k][c+1]) (last chunk: up
+// to M), are ranked there by binary search in LDS.  Of those, the ones below
+// the block's first key rank 0 and the ones at or above its last key rank N_k
+// with no search: with presorted input most boundaries are of this kind and
+// fall to the two end chunks of every block.
 __global__ __launch_bounds__(256) void k_gsd_fine_split(const uint32_t* __restrict__ X,
                                                         const uint32_t* lo, uint32_t p, uint32_t M,
-                                                        const uint64_t* __restrict__ BK,
-                                                        uint32_t* F)
+                                                        uint32_t nch, const uint64_t* __restrict__ BK,
+                                                        const uint32_t* R, uint32_t* F)
 {
     __shared__ uint32_t xs[kFineChunk];
-    __shared__ uint64_t ci[1024];   // BK[i kCoarse], i < ceil(M / kCoarse) (<= 1024 used)
-    __shared__ uint32_t range[2];
     const uint32_t k = blockIdx.y, tid = threadIdx.x;
     const uint32_t b = lo[k], nk = lo[k + 1] - b;
     const uint32_t c0 = blockIdx.x * kFineChunk;
@@ -649,44 +691,14 @@ __global__ __launch_bounds__(256) void k_gsd_fine_split(const uint32_t* __restri
     if (c0 >= nk && c0 != 0) return;
     const uint32_t c1 = min(nk, c0 + kFineChunk);
     const bool last = c1 == nk;
-    const uint32_t nci = min(1024u, (M + kCoarse - 1) / kCoarse);
+    const uint32_t* r = R + (size_t)k * (nch + 2);
+    const uint32_t r0 = r[blockIdx.x], r1 = last ? M : r[blockIdx.x + 1];
+    const uint32_t in0 = blockIdx.x == 0 ? r[nch] : 0u, in1 = last ? r[nch + 1] : M;
     for (uint32_t i = tid; i < c1 - c0; i += 256) xs[i] = X[b + c0 + i];
-    for (uint32_t i = tid; i < nci; i += 256) ci[i] = BK[(size_t)i * kCoarse];
     __syncthreads();
-    // index of the first boundary >= x (composite), in [0, M]
-    auto first_not_below = [&](uint64_t x) -> uint32_t {
-        uint32_t a = 0, e = nci;   // coarse: first i with ci[i] >= x
-        while (a < e) {
-            const uint32_t mid = (a + e) >> 1;
-            if (ci[mid] < x) a = mid + 1; else e = mid;
-        }
-        // the answer lies in ((a - 1) kCoarse, a kCoarse]
-        uint32_t lo_i = a == 0 ? 0u : (a - 1) * kCoarse + 1, hi_i = min(M, a * kCoarse);
-        if (nci == 1024 && a == nci) hi_i = M;   // beyond the indexed part
-        while (lo_i < hi_i) {
-            const uint32_t mid = (lo_i + hi_i) >> 1;
-            if (BK[mid] < x) lo_i = mid + 1; else hi_i = mid;
-        }
-        return lo_i;
-    };
-    // Boundaries with index i in [range[0], range[1]) (B_{i+1}) rank in this
-    // chunk; of those, the ones below the block's first key rank 0 and the
-    // ones at or above its last key rank N_k (first / last chunk only), which
-    // needs no search: with presorted input most boundaries are of this kind
-    // and fall to the two end chunks of every block.
-    __shared__ uint32_t inner[2];
-    if (tid == 0)   // the key before the chunk, (X_{c0-1}, index)
-        range[0] = c0 == 0 ? 0u : first_not_below((uint64_t)X[b + c0 - 1] << 32 | (b + c0 - 1));
-    if (tid == 64)
-        range[1] = last ? M : first_not_below((uint64_t)xs[c1 - c0 - 1] << 32 | (b + c1 - 1));
-    if (tid == 128)   // first boundary not below the block's first key
-        inner[0] = c0 == 0 && c1 > c0 ? first_not_below((uint64_t)xs[0] << 32 | b) : 0u;
-    if (tid == 192)   // first boundary not below the block's last key
-        inner[1] = last && c1 > c0 ? first_not_below((uint64_t)xs[c1 - c0 - 1] << 32 | (b + c1 - 1)) : M;
-    __syncthreads();
-    const uint32_t i0 = max(range[0], inner[0]), i1 = max(i0, min(range[1], inner[1]));
-    for (uint32_t i = range[0] + tid; i < i0; i += 256) F[(size_t)k * (M + 2) + i + 1] = 0;
-    for (uint32_t i = i1 + tid; i < range[1]; i += 256) F[(size_t)k * (M + 2) + i + 1] = nk;
+    const uint32_t i0 = max(r0, in0), i1 = max(i0, min(r1, in1));
+    for (uint32_t i = r0 + tid; i < i0; i += 256) F[(size_t)k * (M + 2) + i + 1] = 0;
+    for (uint32_t i = i1 + tid; i < r1; i += 256) F[(size_t)k * (M + 2) + i + 1] = nk;
     for (uint32_t i = i0 + tid; i < i1; i += 256) {
         const uint64_t bnd = BK[i];
         uint32_t a = 0, e = c1 - c0;   // first q in the chunk with B < (X_q, index)
@@ -1056,6 +1068,8 @@ GsdLayout skeleton_layout(bool has_vals, size_t n, uint32_t p, uint32_t s, size_
         L.off_F = o;       o = align_up(o + ((size_t)L.M + 2) * p * 4);
         L.off_BK = o;      o = align_up(o + (size_t)L.M * 8);
         L.off_large = o;   o = align_up(o + ((size_t)L.M + 2) * 4);
+        const size_t nch = std::max<size_t>(1, ((n + p - 1) / p + kFineChunk - 1) / kFineChunk);
+        L.off_R = o;       o = align_up(o + (size_t)p * (nch + 2) * 4);
     }
     if (kind == kGVR) {
         L.route_tpb = (uint32_t)(((n + p - 1) / p + kGvrTile - 1) / kGvrTile);
@@ -1198,7 +1212,12 @@ hipError_t gsd_merge_sort(const uint32_t* keys_in, uint32_t* keys_out, const uin
     uint64_t* BK = (uint64_t*)(w + L.off_BK);
     hipLaunchKernelGGL(k_gsd_bounds, dim3((M + 255) / 256), dim3(256), 0, stream, Sk, Sg, g, M, BK);
     const uint32_t chunks = (uint32_t)std::max<size_t>(1, ((n + p - 1) / p + kFineChunk - 1) / kFineChunk);
-    hipLaunchKernelGGL(k_gsd_fine_split, dim3(chunks, p), dim3(256), 0, stream, Y, lo, p, M, BK, F);
+    uint32_t* R = (uint32_t*)(w + L.off_R);
+    const uint32_t nr = p * (chunks + 2);
+    hipLaunchKernelGGL(k_gsd_chunk_ranges, dim3((nr + 255) / 256), dim3(256), 0, stream, Y, lo, p, M,
+                       chunks, BK, R);
+    hipLaunchKernelGGL(k_gsd_fine_split, dim3(chunks, p), dim3(256), 0, stream, Y, lo, p, M, chunks,
+                       BK, R, F);
     const uint32_t nb = p * (p + 1);
     hipLaunchKernelGGL(k_gsd_fine_bnd, dim3((nb + 255) / 256), dim3(256), 0, stream, F, p, s, g, M,
                        Sk, Sg, bnd, split_key, split_g);
