@@ -97,8 +97,16 @@ def bench_batched(rsort, torch, np, keygen, args):
     keys = keygen.uniform_u32(total, keygen.SEED_SEGMENTS)
     dk = torch.from_numpy(keys).cuda()
     out = torch.empty_like(dk)
-    split, tune_ms = rsort.rsort_segmented_tune(dk, out, off, reps=3)
     reps = max(5, args.steps // 2)
+    # the small-segment sorters (radix rounds, BTN, OET) at the 4096-key split
+    rsort.rsort_segmented_set_split(4096)
+    sorter_ms = {}
+    for name in ("radix", "btn", "oet"):
+        rsort.rsort_segmented_set_small_sort(name)
+        sorter_ms[name] = round(time_steps(lambda: rsort.rsort_segmented_sort(dk, out, off),
+                                           reps, 1, torch) * 1e3, 3)
+    split, tune_ms = rsort.rsort_segmented_tune(dk, out, off, reps=3)
+    sorter = {v: k for k, v in rsort.SMALL_SORTS.items()}[rsort.rsort_segmented_get_small_sort()]
     # per-call latency: submit -> completion, one call at a time
     lat = []
     for _ in range(reps):
@@ -130,7 +138,8 @@ def bench_batched(rsort, torch, np, keygen, args):
     lat_us = np.array(lat) * 1e6
     return {"workload": "4096 arrays, lognormal sizes (median 4096, sigma 1.5, clip [16, 2^20]), "
                         "uniform u32 keys, keys only",
-            "keys": total, "split_small_max": split,
+            "keys": total, "split_small_max": split, "small_sorter": sorter,
+            "small_sorter_ms_at_split_4096": sorter_ms,
             "batched_ms": round(batched * 1e3, 3), "batched_gkeys_per_s": round(total / batched / 1e9, 3),
             "graph_replay_ms": round(graph * 1e3, 3),
             "graph_gkeys_per_s": round(total / graph / 1e9, 3),

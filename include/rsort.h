@@ -172,10 +172,30 @@ int rsort_segmented_device_workspace_bytes(rsort_ctx* ctx, int key_type, int has
  * the tiled path).  Chosen by the tuner; applies to later calls on ctx. */
 int rsort_segmented_set_split(rsort_ctx* ctx, uint32_t small_max);
 
-/* Tuner for the small/large split: sorts the given batch (into keys_out /
- * vals_out) reps times with each candidate split (0, 1024, 4096, 8192 keys),
- * keeps the fastest on ctx and returns it, with its time per sort in ms.
- * Synchronises the stream. */
+/*
+ * Sorter of the segments sorted whole in LDS by the segmented sorts on ctx
+ * (both entry points):
+ *   RSORT_SMALL_RADIX  one stable count-sort round per byte in LDS (default);
+ *   RSORT_SMALL_BTN    the paper's BTN (Section 2): each of P threads sorts a
+ *                      run of R (key, position) composites, then the runs are
+ *                      ordered by the lg P (lg P + 1) / 2 stages of a bitonic
+ *                      sorter whose comparisons merge two runs and split them
+ *                      into the lower and upper half;
+ *   RSORT_SMALL_OET    the paper's OET: the same runs ordered by P rounds of
+ *                      odd-even transposition with the same merge-split.
+ * All three give the stable sort.  BTN and OET apply to 32-bit keys in
+ * segments of up to 4096 keys (P x R = 256 x 4 or 512 x 8); other small
+ * segments use the radix rounds.  RSORT_EINVAL for another value.
+ */
+enum rsort_small_sort { RSORT_SMALL_RADIX = 0, RSORT_SMALL_BTN = 1, RSORT_SMALL_OET = 2 };
+int rsort_segmented_set_small_sort(rsort_ctx* ctx, int small_sort);
+int rsort_segmented_get_small_sort(rsort_ctx* ctx, int* small_sort);
+
+/* Tuner for the segmented sort: sorts the given batch (into keys_out /
+ * vals_out) reps times with each candidate split (0, 1024, 4096, 8192 keys)
+ * and each small-segment sorter, keeps the fastest pair on ctx and returns its
+ * split (the sorter: rsort_segmented_get_small_sort), with its time per sort
+ * in ms.  Synchronises the stream. */
 int rsort_segmented_tune(rsort_ctx* ctx, int key_type, const void* keys_in, void* keys_out,
                          const uint32_t* vals_in, uint32_t* vals_out,
                          const uint64_t* seg_offsets, size_t num_segs, int reps, void* stream,

@@ -90,6 +90,7 @@ struct rsort_ctx {
     hipEvent_t meta_done = nullptr;
     bool meta_pending = false;
     uint32_t small_max = rsort::kSmallMaxDefault;
+    int small_sort = RSORT_SMALL_RADIX;   // sorter of the small segments
     rsort::SegPlan plan;
     uint64_t upload_sig = 0;         // plan last uploaded into upload_ws
     void* upload_ws = nullptr;
@@ -698,8 +699,25 @@ int rsort_segmented_sort_device(rsort_ctx* ctx, int key_type, const void* keys_i
     }
     hipError_t e = rsort::devseg_sort(kb, keys_in, keys_out, vals_in, vals_out, total_n, seg_offsets,
                                       (uint32_t)num_segs, ctx->small_max, ws, L, ctx->dev_err,
-                                      (hipStream_t)stream, ctx->prof);
+                                      (hipStream_t)stream, ctx->prof, ctx->small_sort);
     return e == hipSuccess ? RSORT_OK : hip_fail(ctx, e, "kernel launch");
+}
+
+int rsort_segmented_set_small_sort(rsort_ctx* ctx, int small_sort)
+{
+    if (!ctx) return RSORT_EINVAL;
+    if (small_sort != RSORT_SMALL_RADIX && small_sort != RSORT_SMALL_BTN &&
+        small_sort != RSORT_SMALL_OET)
+        return fail(ctx, RSORT_EINVAL, "unknown small-segment sorter %d", small_sort);
+    ctx->small_sort = small_sort;
+    return RSORT_OK;
+}
+
+int rsort_segmented_get_small_sort(rsort_ctx* ctx, int* small_sort)
+{
+    if (!ctx || !small_sort) return RSORT_EINVAL;
+    *small_sort = ctx->small_sort;
+    return RSORT_OK;
 }
 
 int rsort_segmented_set_split(rsort_ctx* ctx, uint32_t small_max)
@@ -771,7 +789,7 @@ int rsort_segmented_sort(rsort_ctx* ctx, int key_type, const void* keys_in, void
             return fail(ctx, RSORT_EINVAL, "capturing a segmented sort needs one identical call "
                                            "with the same workspace outside the capture first");
         hipError_t e = rsort::segmented_sort(kb, keys_in, keys_out, vals_in, vals_out, total, P,
-                                             nullptr, ws, ctx->dev_err, s, nullptr);
+                                             nullptr, ws, ctx->dev_err, s, nullptr, ctx->small_sort);
         return e == hipSuccess ? RSORT_OK : hip_fail(ctx, e, "segmented sort capture");
     }
     // pinned staging of the plan: wait until its previous upload has completed
@@ -793,7 +811,8 @@ int rsort_segmented_sort(rsort_ctx* ctx, int key_type, const void* keys_in, void
         return fail(ctx, RSORT_EDEVICE, "hipEventCreate");
     rsort::segmented_pack(P, kb, ctx->meta_host);
     hipError_t e = rsort::segmented_sort(kb, keys_in, keys_out, vals_in, vals_out, total, P,
-                                         ctx->meta_host, ws, ctx->dev_err, s, ctx->prof);
+                                         ctx->meta_host, ws, ctx->dev_err, s, ctx->prof,
+                                         ctx->small_sort);
     if (e != hipSuccess) return hip_fail(ctx, e, "segmented sort launch");
     if (hipEventRecord(ctx->meta_done, s) == hipSuccess) ctx->meta_pending = true;
     ctx->upload_sig = sig;
@@ -808,6 +827,7 @@ int rsort_segmented_tune(rsort_ctx* ctx, int key_type, const void* keys_in, void
 {
     if (!ctx || !best_split) return RSORT_EINVAL;
     static const uint32_t cands[] = {0, 1024, 4096, 8192};
+    static const int sorters[] = {RSORT_SMALL_RADIX, RSORT_SMALL_BTN, RSORT_SMALL_OET};
     if (reps < 1) reps = 3;
     hipStream_t s = (hipStream_t)stream;
     DeviceGuard g(ctx->device);
@@ -817,11 +837,16 @@ int rsort_segmented_tune(rsort_ctx* ctx, int key_type, const void* keys_in, void
         return fail(ctx, RSORT_EDEVICE, "hipEventCreate");
     }
     const uint32_t saved = ctx->small_max;
+    const int saved_sort = ctx->small_sort;
     double best = 1e30;
     uint32_t pick = saved;
+    int pick_sort = saved_sort;
     int rc = RSORT_OK;
-    for (uint32_t c : cands) {
+    for (uint32_t c : cands)
+    for (int srt : sorters) {
+        if (c == 0 && srt != RSORT_SMALL_RADIX) continue;   // no small segments
         ctx->small_max = c;
+        ctx->small_sort = srt;
         rc = rsort_segmented_sort(ctx, key_type, keys_in, keys_out, vals_in, vals_out, seg_offsets,
                                   num_segs, nullptr, 0, stream);   // warm-up, sizes the workspace
         if (rc) break;
@@ -839,11 +864,13 @@ int rsort_segmented_tune(rsort_ctx* ctx, int key_type, const void* keys_in, void
         if (ms / reps < best) {
             best = ms / reps;
             pick = c;
+            pick_sort = srt;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     ctx->small_max = rc ? saved : pick;
+    ctx->small_sort = rc ? saved_sort : pick_sort;
     if (rc) return rc;
     *best_split = pick;
     if (best_ms) *best_ms = best;

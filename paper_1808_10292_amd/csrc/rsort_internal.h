@@ -90,10 +90,11 @@ void segmented_plan(const uint64_t* offsets, size_t num_segs, uint32_t small_max
 size_t segmented_meta_bytes(const SegPlan& P);
 size_t segmented_ws_bytes(int key_bytes, bool has_vals, size_t total, const SegPlan& P);
 void segmented_pack(const SegPlan& P, int key_bytes, void* host);
+// small_sort: the sorter of the small segments (0 radix rounds, 1 BTN, 2 OET).
 hipError_t segmented_sort(int key_bytes, const void* keys_in, void* keys_out,
                           const uint32_t* vals_in, uint32_t* vals_out, size_t total,
                           const SegPlan& P, const void* host_meta, void* ws, uint32_t* dev_err,
-                          hipStream_t stream, Profiler* prof);
+                          hipStream_t stream, Profiler* prof, int small_sort = 0);
 
 // Device-planned segmented sort: offsets (nseg + 1 u32, nondecreasing) live in
 // device memory.  ws must hold devseg_layout(...).bytes bytes.
@@ -107,7 +108,7 @@ DevSegLayout devseg_layout(int key_bytes, bool has_vals, size_t n, uint32_t nseg
 hipError_t devseg_sort(int key_bytes, const void* keys_in, void* keys_out, const uint32_t* vals_in,
                        uint32_t* vals_out, size_t n, const uint32_t* off, uint32_t nseg,
                        uint32_t small_max, void* ws, const DevSegLayout& L, uint32_t* dev_err,
-                       hipStream_t stream, Profiler* prof);
+                       hipStream_t stream, Profiler* prof, int small_sort = 0);
 
 // ---------------------------------------------------------------------------
 // Oversampling sample sorts (sample_sort.hip), 32-bit keys: GSD (regular

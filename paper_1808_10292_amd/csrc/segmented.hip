@@ -104,11 +104,163 @@ uint32_t large_tile(int key_bytes)
                           : R8Config<uint32_t>::WG * R8Config<uint32_t>::ITEMS;
 }
 
+
+// ---------------------------------------------------------------------------
+// BTN and OET (Section 2) as whole-segment sorts inside one workgroup, the
+// alternatives to the in-LDS radix rounds for small segments (32-bit keys,
+// up to 4096 keys).  The P threads are the paper's processors: thread t holds
+// the run of segment positions [t R, t R + R) as (key, position) composites,
+// sorts it (a register sorting network; the paper sorts the runs by SR4),
+// then the runs are ordered as P 'keys':
+//   BTN  lg P (lg P + 1) / 2 stages of Batcher's bitonic sorter;
+//   OET  P rounds of odd-even transposition;
+// where comparing two runs means merging them and giving the lower R
+// composites to the lower-indexed thread of the pair (the upper to the
+// other).  Composites are unique, so the result is the stable sort; payloads
+// are staged in LDS by position and gathered at the end (in place is safe).
+
+__device__ __forceinline__ bool comp_lt(uint32_t a, uint32_t ai, uint32_t b, uint32_t bi)
+{
+    return a < b || (a == b && ai < bi);
+}
+
+// (k[a], x[a]) <= (k[b], x[b]) afterwards.
+template <int R>
+__device__ __forceinline__ void comp_order(uint32_t (&k)[R], uint32_t (&x)[R], int a, int b)
+{
+    const bool sw = comp_lt(k[b], x[b], k[a], x[a]);
+    const uint32_t ka = k[a], kb = k[b], xa = x[a], xb = x[b];
+    k[a] = sw ? kb : ka;
+    k[b] = sw ? ka : kb;
+    x[a] = sw ? xb : xa;
+    x[b] = sw ? xa : xb;
+}
+
+// Bitonic sorting network on R registers, ascending.
+template <int R>
+__device__ __forceinline__ void reg_sort(uint32_t (&k)[R], uint32_t (&x)[R])
+{
+#pragma unroll
+    for (int size = 2; size <= R; size <<= 1)
+#pragma unroll
+        for (int stride = size >> 1; stride > 0; stride >>= 1)
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                const int j = i ^ stride;
+                if (j > i) {
+                    if ((i & size) == 0) comp_order<R>(k, x, i, j);
+                    else comp_order<R>(k, x, j, i);
+                }
+            }
+}
+
+// A bitonic sequence of R registers sorted ascending (half-cleaners).
+template <int R>
+__device__ __forceinline__ void reg_bitonic_merge(uint32_t (&k)[R], uint32_t (&x)[R])
+{
+#pragma unroll
+    for (int stride = R >> 1; stride > 0; stride >>= 1)
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int j = i ^ stride;
+            if (j > i) comp_order<R>(k, x, i, j);
+        }
+}
+
+template <bool KV, int P, int R, bool OET>
+__global__ __launch_bounds__(P) void k_seg_network(const uint32_t* __restrict__ keys_in,
+                                                   uint32_t* keys_out,
+                                                   const uint32_t* __restrict__ vals_in,
+                                                   uint32_t* vals_out, const uint2* segs)
+{
+    __shared__ uint32_t xk[R][P];   // run exchange, register i of thread t at [i][t]
+    __shared__ uint32_t xi[R][P];
+    __shared__ uint32_t vst[KV ? P * R : 1];
+    const uint2 seg = segs[blockIdx.x];
+    const uint32_t base = seg.x, len = seg.y - seg.x;
+    if (len == 0) return;
+    const uint32_t t = threadIdx.x;
+    uint32_t k[R], x[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const uint32_t u = t * R + i;
+        k[i] = u < len ? keys_in[base + u] : 0xFFFFFFFFu;   // padding sorts last: position >= len
+        x[i] = u;
+    }
+    if (KV)
+        for (uint32_t u = t; u < len; u += P) vst[u] = vals_in[base + u];
+    reg_sort<R>(k, x);
+    // run t against run `partner`: keep the lower (or upper) R of the two
+    auto merge_split = [&](bool active, uint32_t partner, bool lower) {
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            xk[i][t] = k[i];
+            xi[i][t] = x[i];
+        }
+        __syncthreads();
+        if (active) {
+            uint32_t bk[R], bx[R];
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                bk[i] = xk[R - 1 - i][partner];
+                bx[i] = xi[R - 1 - i][partner];
+            }
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                const bool mine = comp_lt(k[i], x[i], bk[i], bx[i]) == lower;
+                k[i] = mine ? k[i] : bk[i];
+                x[i] = mine ? x[i] : bx[i];
+            }
+            reg_bitonic_merge<R>(k, x);
+        }
+        __syncthreads();
+    };
+    if (!OET) {
+        for (uint32_t size = 2; size <= P; size <<= 1)
+            for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+                const uint32_t partner = t ^ stride;
+                const bool asc = (t & size) == 0;
+                merge_split(true, partner, (t < partner) == asc);
+            }
+    } else {
+        for (uint32_t r = 0; r < P; ++r) {
+            const bool left = (t & 1) == (r & 1);   // pairs (t, t + 1) with t of this round's parity
+            const uint32_t partner = left ? t + 1 : t - 1;
+            merge_split(left ? t + 1 < P : t > 0, partner, left);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const uint32_t u = t * R + i;
+        if (u < len) {
+            keys_out[base + u] = k[i];
+            if (KV) vals_out[base + u] = vst[x[i]];
+        }
+    }
+}
+
+// Small-segment class cls (capacities 1024, 4096, 8192).  small_sort picks
+// the in-LDS radix rounds (0), BTN (1) or OET (2); the two networks take
+// 32-bit keys in the first two classes, other segments take the radix rounds.
 template <typename K, bool KV>
 void launch_small(int cls, const void* ki, void* ko, const uint32_t* vi, uint32_t* vo,
-                  const uint2* segs, uint32_t nsegs, uint32_t nrounds, hipStream_t s)
+                  const uint2* segs, uint32_t nsegs, uint32_t nrounds, hipStream_t s,
+                  int small_sort = 0)
 {
     if (!nsegs) return;
+    if (small_sort != 0 && sizeof(K) == 4 && cls < 2) {
+        const uint32_t* k32 = (const uint32_t*)ki;
+        uint32_t* o32 = (uint32_t*)ko;
+        const bool oet = small_sort == 2;
+        if (cls == 0) {
+            if (oet) hipLaunchKernelGGL((k_seg_network<KV, 256, 4, true>), dim3(nsegs), dim3(256), 0, s, k32, o32, vi, vo, segs);
+            else hipLaunchKernelGGL((k_seg_network<KV, 256, 4, false>), dim3(nsegs), dim3(256), 0, s, k32, o32, vi, vo, segs);
+        } else {
+            if (oet) hipLaunchKernelGGL((k_seg_network<KV, 512, 8, true>), dim3(nsegs), dim3(512), 0, s, k32, o32, vi, vo, segs);
+            else hipLaunchKernelGGL((k_seg_network<KV, 512, 8, false>), dim3(nsegs), dim3(512), 0, s, k32, o32, vi, vo, segs);
+        }
+        return;
+    }
     switch (cls) {
     case 0:
         hipLaunchKernelGGL((k_seg_small<K, KV, 256, 4>), dim3(nsegs), dim3(256), 0, s,
@@ -210,7 +362,8 @@ namespace {
 template <typename K, bool KV>
 hipError_t run_segmented(const void* keys_in, void* keys_out, const uint32_t* vals_in,
                          uint32_t* vals_out, size_t total, const SegPlan& P, const void* host_meta,
-                         void* ws, uint32_t* dev_err, hipStream_t stream, Profiler* prof)
+                         void* ws, uint32_t* dev_err, hipStream_t stream, Profiler* prof,
+                         int small_sort)
 {
     const uint32_t nrounds = sizeof(K);   // 8-bit digits over the whole key
     const size_t nt = P.tiles.size();
@@ -240,7 +393,7 @@ hipError_t run_segmented(const void* keys_in, void* keys_out, const uint32_t* va
     if (prof) profiler_mark(prof, stream, kKindSmall, true);
     for (int c = 0; c < 3; ++c)
         launch_small<K, KV>(c, keys_in, keys_out, KV ? vals_in : nullptr, KV ? vals_out : nullptr,
-                            small[c], (uint32_t)P.small[c].size(), nrounds, stream);
+                            small[c], (uint32_t)P.small[c].size(), nrounds, stream, small_sort);
     if (prof) profiler_mark(prof, stream, kKindSmall, false);
     if (!nt) return hipGetLastError();
 
@@ -287,14 +440,14 @@ hipError_t run_segmented(const void* keys_in, void* keys_out, const uint32_t* va
 hipError_t segmented_sort(int key_bytes, const void* keys_in, void* keys_out,
                           const uint32_t* vals_in, uint32_t* vals_out, size_t total,
                           const SegPlan& P, const void* host_meta, void* ws, uint32_t* dev_err,
-                          hipStream_t stream, Profiler* prof)
+                          hipStream_t stream, Profiler* prof, int small_sort)
 {
     const bool kv = vals_in != nullptr;
     if (key_bytes == 4)
-        return kv ? run_segmented<uint32_t, true>(keys_in, keys_out, vals_in, vals_out, total, P, host_meta, ws, dev_err, stream, prof)
-                  : run_segmented<uint32_t, false>(keys_in, keys_out, vals_in, vals_out, total, P, host_meta, ws, dev_err, stream, prof);
-    return kv ? run_segmented<uint64_t, true>(keys_in, keys_out, vals_in, vals_out, total, P, host_meta, ws, dev_err, stream, prof)
-              : run_segmented<uint64_t, false>(keys_in, keys_out, vals_in, vals_out, total, P, host_meta, ws, dev_err, stream, prof);
+        return kv ? run_segmented<uint32_t, true>(keys_in, keys_out, vals_in, vals_out, total, P, host_meta, ws, dev_err, stream, prof, small_sort)
+                  : run_segmented<uint32_t, false>(keys_in, keys_out, vals_in, vals_out, total, P, host_meta, ws, dev_err, stream, prof, small_sort);
+    return kv ? run_segmented<uint64_t, true>(keys_in, keys_out, vals_in, vals_out, total, P, host_meta, ws, dev_err, stream, prof, small_sort)
+              : run_segmented<uint64_t, false>(keys_in, keys_out, vals_in, vals_out, total, P, host_meta, ws, dev_err, stream, prof, small_sort);
 }
 
 
@@ -401,7 +554,7 @@ template <typename K, bool KV>
 hipError_t run_devseg(const void* keys_in, void* keys_out, const uint32_t* vals_in,
                       uint32_t* vals_out, size_t n, const uint32_t* off, uint32_t nseg,
                       uint32_t small_max, void* ws, const DevSegLayout& L, uint32_t* dev_err,
-                      hipStream_t stream, Profiler* prof)
+                      hipStream_t stream, Profiler* prof, int small_sort)
 {
     uint8_t* w = (uint8_t*)ws;
     K* keys_tmp = (K*)(w + L.off_tmp_keys);
@@ -419,7 +572,7 @@ hipError_t run_devseg(const void* keys_in, void* keys_out, const uint32_t* vals_
     if (prof) profiler_mark(prof, stream, kKindSmall, true);
     for (int c = 0; c < 3; ++c)
         launch_small<K, KV>(c, keys_in, keys_out, KV ? vals_in : nullptr, KV ? vals_out : nullptr,
-                            small + (size_t)c * nseg, nseg, rounds, stream);
+                            small + (size_t)c * nseg, nseg, rounds, stream, small_sort);
     if (prof) profiler_mark(prof, stream, kKindSmall, false);
     constexpr int WG = R8Config<K>::WG;
     constexpr int ITEMS = R8Config<K>::ITEMS;
@@ -480,15 +633,15 @@ DevSegLayout devseg_layout(int key_bytes, bool has_vals, size_t n, uint32_t nseg
 hipError_t devseg_sort(int key_bytes, const void* keys_in, void* keys_out, const uint32_t* vals_in,
                        uint32_t* vals_out, size_t n, const uint32_t* off, uint32_t nseg,
                        uint32_t small_max, void* ws, const DevSegLayout& L, uint32_t* dev_err,
-                       hipStream_t stream, Profiler* prof)
+                       hipStream_t stream, Profiler* prof, int small_sort)
 {
     if (!nseg || !n) return hipSuccess;
     const bool kv = vals_in != nullptr;
     if (key_bytes == 4)
-        return kv ? run_devseg<uint32_t, true>(keys_in, keys_out, vals_in, vals_out, n, off, nseg, small_max, ws, L, dev_err, stream, prof)
-                  : run_devseg<uint32_t, false>(keys_in, keys_out, vals_in, vals_out, n, off, nseg, small_max, ws, L, dev_err, stream, prof);
-    return kv ? run_devseg<uint64_t, true>(keys_in, keys_out, vals_in, vals_out, n, off, nseg, small_max, ws, L, dev_err, stream, prof)
-              : run_devseg<uint64_t, false>(keys_in, keys_out, vals_in, vals_out, n, off, nseg, small_max, ws, L, dev_err, stream, prof);
+        return kv ? run_devseg<uint32_t, true>(keys_in, keys_out, vals_in, vals_out, n, off, nseg, small_max, ws, L, dev_err, stream, prof, small_sort)
+                  : run_devseg<uint32_t, false>(keys_in, keys_out, vals_in, vals_out, n, off, nseg, small_max, ws, L, dev_err, stream, prof, small_sort);
+    return kv ? run_devseg<uint64_t, true>(keys_in, keys_out, vals_in, vals_out, n, off, nseg, small_max, ws, L, dev_err, stream, prof, small_sort)
+              : run_devseg<uint64_t, false>(keys_in, keys_out, vals_in, vals_out, n, off, nseg, small_max, ws, L, dev_err, stream, prof, small_sort);
 }
 
 }  // namespace rsort

@@ -44,13 +44,19 @@ EXPORTED = ("rsort_create", "rsort_destroy", "rsort_status_string", "rsort_last_
             "rsort_workspace_bytes", "rsort_sort", "rsort_histogram", "rsort_synchronize",
             "rsort_profile_enable", "rsort_profile_read", "rsort_segmented_sort",
             "rsort_segmented_workspace_bytes", "rsort_segmented_set_split",
-            "rsort_segmented_tune", "rsort_sample_sort", "rsort_sample_sort_workspace_bytes",
+            "rsort_segmented_tune", "rsort_segmented_set_small_sort",
+            "rsort_segmented_get_small_sort", "rsort_sample_sort", "rsort_sample_sort_workspace_bytes",
             "rsort_sample_sort_stats", "rsort_sample_sort_random",
             "rsort_sample_sort_random_workspace_bytes", "rsort_sample_sort_gvr",
             "rsort_sample_sort_gvr_workspace_bytes", "rsort_segmented_sort_device",
             "rsort_segmented_device_workspace_bytes", "rsort_server_create", "rsort_server_submit",
             "rsort_server_poll", "rsort_server_wait", "rsort_server_latency",
             "rsort_server_reset_stats", "rsort_server_destroy")
+
+RSORT_SMALL_RADIX = 0
+RSORT_SMALL_BTN = 1
+RSORT_SMALL_OET = 2
+SMALL_SORTS = {"radix": RSORT_SMALL_RADIX, "btn": RSORT_SMALL_BTN, "oet": RSORT_SMALL_OET}
 
 RSORT_KERNEL_ROUND = 0
 RSORT_KERNEL_HIST = 1
@@ -99,6 +105,8 @@ def load_library():
         lib.rsort_segmented_sort.argtypes = [vp, i, vp, vp, u32p, u32p, vp, sz, vp, sz, vp]
         lib.rsort_segmented_workspace_bytes.argtypes = [vp, i, i, vp, sz, ctypes.POINTER(sz)]
         lib.rsort_segmented_set_split.argtypes = [vp, ctypes.c_uint32]
+        lib.rsort_segmented_set_small_sort.argtypes = [vp, i]
+        lib.rsort_segmented_get_small_sort.argtypes = [vp, ctypes.POINTER(i)]
         lib.rsort_segmented_tune.argtypes = [vp, i, vp, vp, u32p, u32p, vp, sz, i, vp,
                                              ctypes.POINTER(ctypes.c_uint32),
                                              ctypes.POINTER(ctypes.c_double)]
@@ -384,9 +392,27 @@ def rsort_segmented_set_split(small_max, device=None):
               "rsort_segmented_set_split")
 
 
+def rsort_segmented_set_small_sort(small_sort, device=None):
+    """Sorter of the small segments: "radix", "btn", "oet" (or RSORT_SMALL_*)."""
+    ctx = context(device)
+    v = SMALL_SORTS[small_sort] if isinstance(small_sort, str) else int(small_sort)
+    ctx.check(ctx._lib.rsort_segmented_set_small_sort(ctx.handle, v),
+              "rsort_segmented_set_small_sort")
+
+
+def rsort_segmented_get_small_sort(device=None):
+    ctx = context(device)
+    out = ctypes.c_int()
+    ctx.check(ctx._lib.rsort_segmented_get_small_sort(ctx.handle, ctypes.byref(out)),
+              "rsort_segmented_get_small_sort")
+    return out.value
+
+
 def rsort_segmented_tune(keys_in, keys_out, seg_offsets, vals_in=None, vals_out=None, reps=3,
                          stream=None):
-    """Pick the fastest small/large split for this batch; returns (split, ms)."""
+    """Pick the fastest small/large split and small-segment sorter for this
+    batch (both left set); returns (split, ms) -- the sorter through
+    rsort_segmented_get_small_sort()."""
     kt = _key_type(keys_in)
     off = _host_offsets(seg_offsets)
     ctx = context(keys_in.device)

@@ -3,8 +3,8 @@
 Segments cover every size class boundary of the in-LDS path (1024 / 4096 /
 8192 keys), the tiled path (longer segments, ragged last tiles), empty and
 one-key segments, constant segments (identity rounds), u64 keys, payloads,
-in-place sorting, the all-tiled split, and the lognormal 4096-segment batch.
-Every comparison is bit-exact.
+in-place sorting, the all-tiled split, the lognormal 4096-segment batch, and
+the BTN / OET small-segment sorters.  Every comparison is bit-exact.
 """
 import numpy as np
 import pytest
@@ -122,6 +122,56 @@ def test_offsets_not_starting_at_zero_and_errors(rs):
     rs.rsort_segmented_sort(e, e, np.array([0], dtype=np.uint64))
 
 
+# ---------------------------------------------------------------------------
+# BTN and OET as the sorters of the small segments (32-bit keys, <= 4096 keys;
+# other small segments keep the radix rounds): same bit-exact result.
+
+NETWORK_SIZES = [1, 2, 3, 4, 5, 31, 255, 256, 257, 1000, 1023, 1024, 1025, 2048, 3001, 4095,
+                 4096, 4097, 8192, 20000, 0, 9]
+
+
+@pytest.mark.parametrize("sorter", ["btn", "oet"])
+@pytest.mark.parametrize("with_vals,in_place", [(True, False), (False, False), (True, True)])
+def test_network_small_sorters_u32(rs, sorter, with_vals, in_place):
+    n = int(sum(NETWORK_SIZES))
+    announce("seg network", sorter, with_vals, in_place)
+    keys = keygen.uniform_u32(n, 41)
+    keys[::3] = keys[1::3][: keys[::3].size]        # duplicates: ties resolved by position
+    rs.rsort_segmented_set_small_sort(sorter)
+    try:
+        assert rs.rsort_segmented_get_small_sort() == rs.SMALL_SORTS[sorter]
+        run_case(rs, keys, NETWORK_SIZES, with_vals, in_place)
+        run_case(rs, keygen.zipf_keys(n, 42), NETWORK_SIZES, with_vals, in_place)
+    finally:
+        rs.rsort_segmented_set_small_sort("radix")
+
+
+@pytest.mark.parametrize("sorter", ["btn", "oet"])
+def test_network_small_sorters_u64_and_device_offsets(rs, sorter):
+    """64-bit keys take the radix rounds whatever the setting; the
+    device-offset entry point uses the setting too."""
+    import torch
+    n = int(sum(NETWORK_SIZES))
+    announce("seg network u64 / device", sorter)
+    rs.rsort_segmented_set_small_sort(sorter)
+    try:
+        run_case(rs, keygen.uniform_u64(n, 43), NETWORK_SIZES, True)
+        keys = keygen.uniform_u32(n, 44)
+        vals = np.arange(n, dtype=np.uint32)
+        off = keygen.offsets_from_sizes(np.asarray(NETWORK_SIZES))
+        doff = torch.from_numpy(off.astype(np.uint32).view(np.int32)).cuda()
+        dk, dv = dev(keys), dev(vals)
+        ko, vo = torch.empty_like(dk), torch.empty_like(dv)
+        rs.rsort_segmented_sort_device(dk, ko, doff, dv, vo)
+        rs.rsort_synchronize()
+        wk, wv = oracle.segmented(keys, vals, off)
+        assert np.array_equal(host(ko), wk) and np.array_equal(host(vo), wv)
+    finally:
+        rs.rsort_segmented_set_small_sort("radix")
+    with pytest.raises(rs.RsortError):
+        rs.rsort_segmented_set_small_sort(3)
+
+
 def test_tuner_picks_a_split_and_stays_exact(rs):
     import torch
     sizes = keygen.lognormal_sizes(512, seed=77)
@@ -133,10 +183,12 @@ def test_tuner_picks_a_split_and_stays_exact(rs):
     ko = torch.empty_like(dk)
     split, ms = rs.rsort_segmented_tune(dk, ko, off, reps=2)
     assert split in (0, 1024, 4096, 8192) and ms > 0
+    assert rs.rsort_segmented_get_small_sort() in (0, 1, 2)
     rs.rsort_segmented_sort(dk, ko, off)
     want, _ = oracle.segmented(keys, None, off)
     assert np.array_equal(host(ko), want)
     rs.rsort_segmented_set_split(8192)
+    rs.rsort_segmented_set_small_sort("radix")
 
 
 def test_graph_capture_replays(rs):
