@@ -51,7 +51,13 @@ enum rsort_status {
     RSORT_EUNSUPPORTED = -5   /* valid request outside this build's limits         */
 };
 
-enum rsort_key_type { RSORT_U32 = 0, RSORT_U64 = 1 };
+enum rsort_key_type {
+    RSORT_U32 = 0, RSORT_U64 = 1,   /* unsigned integers: every entry point */
+    /* rsort_sort and rsort_workspace_bytes only (whole keys, radix sorts):
+     * two's complement integers, and IEEE 754 binary32 / binary64 ordered by
+     * totalOrder (-NaN < -inf < ... < -0 < +0 < ... < +inf < +NaN) */
+    RSORT_I32 = 2, RSORT_F32 = 3, RSORT_I64 = 4, RSORT_F64 = 5
+};
 
 enum rsort_algo {
     RSORT_AUTO = 0,            /* currently RSORT_LSD_R8                           */
@@ -83,7 +89,11 @@ int rsort_workspace_bytes(rsort_ctx* ctx, int key_type, int has_vals, size_t n,
 /*
  * Stable sort of n keys on the key bits [begin_bit, end_bit).
  *
- *   key_type   RSORT_U32 (keys are uint32_t) or RSORT_U64 (uint64_t).
+ *   key_type   RSORT_U32 (keys are uint32_t) or RSORT_U64 (uint64_t); also
+ *              RSORT_I32 / RSORT_I64 (signed) and RSORT_F32 / RSORT_F64 (IEEE
+ *              totalOrder), whole keys with RSORT_AUTO / _LSD_R8 / _LSD_R16:
+ *              mapped by an order-preserving bijection into a workspace copy,
+ *              sorted as unsigned keys and mapped back (two extra passes).
  *   keys_in    device array of n keys; read only unless it equals keys_out.
  *   keys_out   device array of n keys receiving the sorted keys.  keys_in ==
  *              keys_out sorts in place; any other overlap is RSORT_EINVAL.

@@ -15,6 +15,8 @@ The arithmetic lives in ``sr4.c`` (plain serial C, built with gcc into
 * ``ger``, ``gvr``   -- Section 3.3 Algorithms 2 and 3 with their random draws
                        passed in as positions.
 * ``segmented``     -- SR4 on every CSR segment.
+* ``sort_signed_or_float`` -- stable comparison sort of signed integer or IEEE
+                       float keys (totalOrder); not in the paper.
 """
 from __future__ import annotations
 
@@ -62,6 +64,8 @@ def _configure(lib):
     lib.ger_u32.argtypes = [vp, vp, sz, i, i, vp, sz, vp, vp, vp, vp, vp,
                             ctypes.POINTER(ctypes.c_int)]
     lib.ger_u32.restype = i
+    lib.sort_kind.argtypes = [vp, vp, sz, i, i]
+    lib.sort_kind.restype = i
     lib.gvr_u32.argtypes = [vp, vp, sz, i, i, vp, sz, vp, vp, vp, vp, vp,
                             ctypes.POINTER(ctypes.c_int)]
     lib.gvr_u32.restype = i
@@ -205,3 +209,17 @@ def _skeleton_random(fn, keys, vals, p: int, s: int, positions):
     return {"keys": ko, "vals": vo, "p": pu, "cnt": cnt,
             "split_key": sk[:pu - 1], "split_g": sg[:pu - 1],
             "bucket": cnt.sum(axis=0)}
+
+
+def sort_signed_or_float(keys, vals=None, kind="signed"):
+    """Stable sort of int32/int64 (kind "signed") or float32/float64 (kind
+    "float", IEEE totalOrder) keys by comparison; returns (keys, vals)."""
+    keys = np.ascontiguousarray(keys)
+    bits = keys.dtype.itemsize * 8
+    k = keys.view(np.uint32 if bits == 32 else np.uint64).astype(np.uint64)
+    v = None if vals is None else np.ascontiguousarray(vals, dtype=np.uint32).copy()
+    rc = _load().sort_kind(_ptr(k), _ptr(v), k.size, bits, 1 if kind == "signed" else 2)
+    if rc:
+        raise ValueError("oracle sort_kind failed (%d)" % rc)
+    out = k.astype(np.uint32 if bits == 32 else np.uint64).view(keys.dtype)
+    return out, v

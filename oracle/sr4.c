@@ -29,6 +29,8 @@
  *                      input, splitting of the unsorted blocks by binary search
  *                      and a count sort on the bucket index, then SR4 per
  *                      bucket.  The random draws of both are caller inputs.
+ *   sort_kind          signed and IEEE float keys (not in the paper): a stable
+ *                      merge sort by comparison (totalOrder for floats).
  *   segmented_u32/u64  SR4 applied independently to each segment of a CSR
  *                      segment list (the batched workload).
  *
@@ -567,5 +569,65 @@ int gvr_u32(const uint32_t* keys_in, const uint32_t* vals_in, size_t n, int p_re
 
 done:
     free(Tk); free(Tg); free(Uk); free(Ug); free(bucket); free(start); free(Y); free(YV);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Signed and floating-point keys (not in the paper, which sorts unsigned
+ * integers): a stable merge sort by comparison.
+ *   kind 1  two's complement integers, ordered as signed numbers;
+ *   kind 2  IEEE 754 bit patterns ordered by totalOrder: every key with the
+ *           sign bit set precedes every key without it; among keys without
+ *           it a larger bit pattern is larger, among keys with it a larger
+ *           bit pattern is smaller (-NaN < -inf < ... < -0 < +0 < ... < +inf
+ *           < +NaN).
+ * Ties keep input order, so with payloads the result is the stable sort.   */
+static int cmp_kind(uint64_t a, uint64_t b, int bits, int kind)
+{
+    const uint64_t sign = (uint64_t)1 << (bits - 1);
+    const int sa = (a & sign) != 0, sb = (b & sign) != 0;
+    if (sa != sb) return sa ? -1 : 1;                 /* negative first */
+    if (a == b) return 0;
+    if (kind == 1) return a < b ? -1 : 1;             /* same sign: bits order as numbers */
+    if (!sa) return a < b ? -1 : 1;                   /* float, both positive */
+    return a < b ? 1 : -1;                            /* float, both negative: reversed */
+}
+
+static int merge_sort_kind(uint64_t* k, uint32_t* v, size_t n, int bits, int kind)
+{
+    uint64_t* tk = (uint64_t*)malloc((n ? n : 1) * sizeof(uint64_t));
+    uint32_t* tv = (uint32_t*)malloc((n ? n : 1) * sizeof(uint32_t));
+    if (!tk || !tv) {
+        free(tk); free(tv);
+        return -2;
+    }
+    for (size_t width = 1; width < n; width *= 2) {
+        for (size_t lo = 0; lo < n; lo += 2 * width) {
+            size_t mid = lo + width < n ? lo + width : n;
+            size_t hi = lo + 2 * width < n ? lo + 2 * width : n;
+            size_t i = lo, j = mid, o = lo;
+            while (i < mid && j < hi) {                   /* left first on ties: stable */
+                if (cmp_kind(k[j], k[i], bits, kind) < 0) { tk[o] = k[j]; tv[o++] = v[j++]; }
+                else { tk[o] = k[i]; tv[o++] = v[i++]; }
+            }
+            while (i < mid) { tk[o] = k[i]; tv[o++] = v[i++]; }
+            while (j < hi) { tk[o] = k[j]; tv[o++] = v[j++]; }
+        }
+        memcpy(k, tk, n * sizeof(uint64_t));
+        memcpy(v, tv, n * sizeof(uint32_t));
+    }
+    free(tk);
+    free(tv);
+    return 0;
+}
+
+/* keys: n keys of `bits` (32 or 64) bits in 64-bit slots; vals may be NULL. */
+int sort_kind(uint64_t* keys, uint32_t* vals, size_t n, int bits, int kind)
+{
+    if ((bits != 32 && bits != 64) || (kind != 1 && kind != 2) || (n && !keys)) return -1;
+    uint32_t* v = vals ? vals : (uint32_t*)calloc(n ? n : 1, sizeof(uint32_t));
+    if (!v) return -2;
+    int rc = merge_sort_kind(keys, v, n, bits, kind);
+    if (!vals) free(v);
     return rc;
 }

@@ -190,6 +190,19 @@ int key_bytes_of(int key_type)
     return key_type == RSORT_U32 ? 4 : (key_type == RSORT_U64 ? 8 : 0);
 }
 
+// Signed and floating-point key types: the unsigned type of the same width
+// and the order-preserving map between them.  False for the unsigned types.
+bool mapped_key(int key_type, int* ukey, int* kind)
+{
+    switch (key_type) {
+    case RSORT_I32: *ukey = RSORT_U32; *kind = rsort::kKeySigned; return true;
+    case RSORT_F32: *ukey = RSORT_U32; *kind = rsort::kKeyFloat; return true;
+    case RSORT_I64: *ukey = RSORT_U64; *kind = rsort::kKeySigned; return true;
+    case RSORT_F64: *ukey = RSORT_U64; *kind = rsort::kKeyFloat; return true;
+    default: return false;
+    }
+}
+
 int validate_bits(rsort_ctx* ctx, int key_type, int begin_bit, int end_bit)
 {
     const int width = key_bytes_of(key_type) * 8;
@@ -311,6 +324,17 @@ int rsort_workspace_bytes(rsort_ctx* ctx, int key_type, int has_vals, size_t n, 
                           size_t* bytes)
 {
     if (!ctx || !bytes) return RSORT_EINVAL;
+    int ukey = 0, kind = 0;
+    if (mapped_key(key_type, &ukey, &kind)) {
+        // the unsigned sort's workspace, then the mapped keys
+        if (algo == RSORT_SAMPLE_REGULAR)
+            return fail(ctx, RSORT_EUNSUPPORTED, "the sample sort takes uint32 keys only");
+        size_t inner = 0;
+        const int rc = rsort_workspace_bytes(ctx, ukey, has_vals, n, algo, &inner);
+        if (rc) return rc;
+        *bytes = rsort::align_up(inner) + n * key_bytes_of(ukey);
+        return RSORT_OK;
+    }
     if (!key_bytes_of(key_type)) return fail(ctx, RSORT_EINVAL, "unknown key type %d", key_type);
     if (n >= kMaxN) return fail(ctx, RSORT_EUNSUPPORTED, "n = %zu >= 2^30", n);
     if (algo == RSORT_SAMPLE_REGULAR)
@@ -340,6 +364,51 @@ rsort::GsdLayout skeleton_layout(int kind, bool has_vals, size_t n, int p, int q
     if (kind == rsort::kGER) return rsort::ger_layout(has_vals, n, (uint32_t)p, (uint32_t)q);
     if (kind == rsort::kGVR) return rsort::gvr_layout(has_vals, n, (uint32_t)p, (uint32_t)q);
     return rsort::gsd_layout(has_vals, n, (uint32_t)p, (uint32_t)q);
+}
+
+// Signed / floating-point keys: map into a workspace temporary, sort that as
+// unsigned keys into keys_out (never in place, whatever the caller's
+// pointers), map keys_out back.
+int sort_mapped(rsort_ctx* ctx, int ukey, int kind, const void* keys_in, void* keys_out,
+                const uint32_t* vals_in, uint32_t* vals_out, size_t n, int begin_bit, int end_bit,
+                int algo, void* workspace, size_t ws_bytes, void* stream)
+{
+    const int kb = key_bytes_of(ukey);
+    if (begin_bit != 0 || end_bit != kb * 8)
+        return fail(ctx, RSORT_EUNSUPPORTED, "signed and floating-point keys are sorted whole");
+    if (algo != RSORT_AUTO && algo != RSORT_LSD_R8 && algo != RSORT_LSD_R16)
+        return fail(ctx, RSORT_EUNSUPPORTED, "signed and floating-point keys take the radix sorts");
+    if ((vals_in == nullptr) != (vals_out == nullptr))
+        return fail(ctx, RSORT_EINVAL, "vals_in and vals_out must both be NULL or both be set");
+    if ((workspace == nullptr) != (ws_bytes == 0))
+        return fail(ctx, RSORT_EINVAL, "workspace and ws_bytes must both be 0 or both be set");
+    if (n == 0) return RSORT_OK;
+    if (n >= kMaxN) return fail(ctx, RSORT_EUNSUPPORTED, "n = %zu >= 2^30", n);
+    if (!keys_in || !keys_out) return fail(ctx, RSORT_EINVAL, "NULL key pointer with n > 0");
+    DeviceGuard g(ctx->device);
+    int rc = check_arrays(ctx, kb, keys_in, keys_out, vals_in, vals_out, n);
+    if (rc) return rc;
+    const size_t inner = rsort::align_up(sort_ws_bytes(ukey, vals_in != nullptr, n, algo, 0, kb * 8));
+    const size_t need = inner + n * kb;
+    void* ws = workspace;
+    if (ws) {
+        if (ws_bytes < need)
+            return fail(ctx, RSORT_EINVAL, "workspace of %zu bytes < %zu needed", ws_bytes, need);
+        if (!is_device_pointer(ws, ctx->device))
+            return fail(ctx, RSORT_EINVAL, "workspace must be device memory");
+    } else {
+        rc = ensure_workspace(ctx, need, &ws);
+        if (rc) return rc;
+    }
+    void* mapped = (uint8_t*)ws + inner;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = rsort::map_keys(kb, kind, false, keys_in, mapped, n, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "kernel launch");
+    rc = rsort_sort(ctx, ukey, mapped, keys_out, vals_in, vals_out, n, 0, kb * 8, algo, ws, inner,
+                    stream);
+    if (rc) return rc;
+    e = rsort::map_keys(kb, kind, true, keys_out, keys_out, n, s);
+    return e == hipSuccess ? RSORT_OK : hip_fail(ctx, e, "kernel launch");
 }
 
 // Shared part of the sample sorts once the layout is known.
@@ -496,6 +565,10 @@ int rsort_sort(rsort_ctx* ctx, int key_type, const void* keys_in, void* keys_out
 {
     if (!ctx) return RSORT_EINVAL;
     ctx->last_error.clear();
+    int ukey = 0, kind = 0;
+    if (mapped_key(key_type, &ukey, &kind))
+        return sort_mapped(ctx, ukey, kind, keys_in, keys_out, vals_in, vals_out, n, begin_bit,
+                           end_bit, algo, workspace, ws_bytes, stream);
     const int kb = key_bytes_of(key_type);
     if (!kb) return fail(ctx, RSORT_EINVAL, "unknown key type %d", key_type);
     if (algo != RSORT_AUTO && algo != RSORT_LSD_R8 && algo != RSORT_LSD_R16 &&

@@ -1,0 +1,67 @@
+// Signed and IEEE-754 floating-point keys sorted by the unsigned radix rounds:
+// an order-preserving bijection maps each key to an unsigned integer of the
+// same width, the unsigned sort runs, and the inverse restores the keys.
+//   signed   flip the sign bit (two's complement order = offset order);
+//   float    negative (sign bit set): complement every bit; otherwise flip the
+//            sign bit.  The result orders keys by IEEE 754 totalOrder:
+//            -NaN < -inf < ... < -0 < +0 < ... < +inf < +NaN.
+#include <algorithm>
+
+#include "device_common.h"
+#include "rsort_internal.h"
+
+namespace rsort {
+namespace {
+
+template <typename U>
+__device__ __forceinline__ U to_ordered(U x, int kind)
+{
+    constexpr U sign = U(1) << (sizeof(U) * 8 - 1);
+    if (kind == kKeySigned) return x ^ sign;
+    return (x & sign) ? U(~x) : U(x ^ sign);
+}
+
+template <typename U>
+__device__ __forceinline__ U from_ordered(U y, int kind)
+{
+    constexpr U sign = U(1) << (sizeof(U) * 8 - 1);
+    if (kind == kKeySigned) return y ^ sign;
+    return (y & sign) ? U(y ^ sign) : U(~y);
+}
+
+template <typename U, bool INVERSE>
+__global__ void k_map_keys(const U* __restrict__ in, U* out, size_t n, int kind)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const U x = in[i];
+        out[i] = INVERSE ? from_ordered<U>(x, kind) : to_ordered<U>(x, kind);
+    }
+}
+
+}  // namespace
+
+hipError_t map_keys(int key_bytes, int kind, bool inverse, const void* in, void* out, size_t n,
+                    hipStream_t stream)
+{
+    if (!n) return hipSuccess;
+    const dim3 grid((uint32_t)std::min<size_t>(16384, (n + 255) / 256)), block(256);
+    if (key_bytes == 4) {
+        if (inverse)
+            hipLaunchKernelGGL((k_map_keys<uint32_t, true>), grid, block, 0, stream,
+                               (const uint32_t*)in, (uint32_t*)out, n, kind);
+        else
+            hipLaunchKernelGGL((k_map_keys<uint32_t, false>), grid, block, 0, stream,
+                               (const uint32_t*)in, (uint32_t*)out, n, kind);
+    } else {
+        if (inverse)
+            hipLaunchKernelGGL((k_map_keys<uint64_t, true>), grid, block, 0, stream,
+                               (const uint64_t*)in, (uint64_t*)out, n, kind);
+        else
+            hipLaunchKernelGGL((k_map_keys<uint64_t, false>), grid, block, 0, stream,
+                               (const uint64_t*)in, (uint64_t*)out, n, kind);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace rsort

@@ -149,6 +149,12 @@ hipError_t gsd_sort(const uint32_t* keys_in, uint32_t* keys_out, const uint32_t*
                     uint32_t* vals_out, size_t n, const GsdLayout& L, uint64_t seed, void* ws,
                     uint32_t* stats, uint32_t* dev_err, hipStream_t stream, Profiler* prof);
 
+// Order-preserving maps of signed / IEEE float keys onto unsigned ones
+// (key_order.hip); inverse = true restores the keys.  in == out is allowed.
+enum KeyKind { kKeyUnsigned = 0, kKeySigned = 1, kKeyFloat = 2 };
+hipError_t map_keys(int key_bytes, int kind, bool inverse, const void* in, void* out, size_t n,
+                    hipStream_t stream);
+
 // Plain device copy used when a sort moves nothing (empty bit range).
 hipError_t copy_bytes(void* dst, const void* src, size_t bytes, hipStream_t stream);
 

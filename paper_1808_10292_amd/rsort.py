@@ -29,6 +29,12 @@ RSORT_EUNSUPPORTED = -5
 
 RSORT_U32 = 0
 RSORT_U64 = 1
+RSORT_I32 = 2
+RSORT_F32 = 3
+RSORT_I64 = 4
+RSORT_F64 = 5
+KEY_TYPES = {"u32": RSORT_U32, "u64": RSORT_U64, "i32": RSORT_I32, "f32": RSORT_F32,
+             "i64": RSORT_I64, "f64": RSORT_F64}
 
 RSORT_AUTO = 0
 RSORT_LSD_R8 = 1
@@ -196,13 +202,25 @@ def context(device=None) -> Context:
     return ctx
 
 
-def _key_type(t: torch.Tensor) -> int:
+def _key_type(t: torch.Tensor, key_type=None) -> int:
+    """Integer tensors sort their bit patterns as unsigned unless key_type
+    ("i32", "i64", ...) says otherwise; float32 / float64 sort by IEEE
+    totalOrder."""
+    if key_type is not None:
+        kt = KEY_TYPES[key_type] if isinstance(key_type, str) else int(key_type)
+        width = 4 if kt in (RSORT_U32, RSORT_I32, RSORT_F32) else 8
+        if t.element_size() != width:
+            raise TypeError("key_type %s needs %d-byte elements, got %s" % (key_type, width, t.dtype))
+        return kt
     if t.dtype in (torch.int32, torch.uint32):
         return RSORT_U32
     if t.dtype in (torch.int64, torch.uint64):
         return RSORT_U64
-    raise TypeError("keys must be a 32- or 64-bit integer tensor (bit pattern sorted as "
-                    "unsigned), got %s" % t.dtype)
+    if t.dtype == torch.float32:
+        return RSORT_F32
+    if t.dtype == torch.float64:
+        return RSORT_F64
+    raise TypeError("keys must be a 32- or 64-bit integer or float tensor, got %s" % t.dtype)
 
 
 def _ptr(t):
@@ -225,9 +243,10 @@ def _check_tensor(t, n, name):
 # ---------------------------------------------------------------------------
 # Entry points under their C names.
 
-def rsort_workspace_bytes(key_dtype, has_vals: bool, n: int, algo="auto", device=None) -> int:
+def rsort_workspace_bytes(key_dtype, has_vals: bool, n: int, algo="auto", device=None,
+                          key_type=None) -> int:
     ctx = context(device)
-    kt = _key_type(torch.empty(0, dtype=key_dtype))
+    kt = _key_type(torch.empty(0, dtype=key_dtype), key_type)
     out = ctypes.c_size_t()
     ctx.check(ctx._lib.rsort_workspace_bytes(ctx.handle, kt, int(bool(has_vals)), int(n),
                                              ALGOS[algo] if isinstance(algo, str) else int(algo),
@@ -236,9 +255,11 @@ def rsort_workspace_bytes(key_dtype, has_vals: bool, n: int, algo="auto", device
 
 
 def rsort_sort(keys_in, keys_out, vals_in=None, vals_out=None, begin_bit=0, end_bit=None,
-               algo="auto", workspace=None, stream=None):
-    """Stable sort of keys_in into keys_out (may be the same tensor)."""
-    kt = _key_type(keys_in)
+               algo="auto", workspace=None, stream=None, key_type=None):
+    """Stable sort of keys_in into keys_out (may be the same tensor).
+    key_type: "u32" / "u64" (default for integer tensors), "i32" / "i64"
+    (signed), "f32" / "f64" (default for float tensors)."""
+    kt = _key_type(keys_in, key_type)
     n = keys_in.numel()
     if keys_out.dtype != keys_in.dtype:
         raise TypeError("keys_out must have the dtype of keys_in")
@@ -252,7 +273,7 @@ def rsort_sort(keys_in, keys_out, vals_in=None, vals_out=None, begin_bit=0, end_
                 raise TypeError("%s must be a 32-bit integer tensor" % name)
             _check_tensor(t, n, name)
     if end_bit is None:
-        end_bit = 32 if kt == RSORT_U32 else 64
+        end_bit = 8 * keys_in.element_size()
     ctx = context(keys_in.device)
     ws_ptr, ws_bytes = None, 0
     if workspace is not None:
@@ -624,9 +645,9 @@ class Server:
 # ---------------------------------------------------------------------------
 # Convenience wrapper.
 
-def sort(keys, values=None, algo="auto", begin_bit=0, end_bit=None, stream=None):
+def sort(keys, values=None, algo="auto", begin_bit=0, end_bit=None, stream=None, key_type=None):
     """Return (sorted_keys, moved_values or None) as new tensors."""
     ko = torch.empty_like(keys)
     vo = None if values is None else torch.empty_like(values)
-    rsort_sort(keys, ko, values, vo, begin_bit, end_bit, algo, stream=stream)
+    rsort_sort(keys, ko, values, vo, begin_bit, end_bit, algo, stream=stream, key_type=key_type)
     return ko, vo

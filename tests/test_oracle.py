@@ -454,3 +454,43 @@ def test_sample_positions_closed_form():
     want = [((int(v) >> 32) * 1000) >> 32 for v in z]
     assert got.tolist() == want
     assert keygen.sample_positions(5, 100000, 7).max() == 6
+
+
+# ---------------------------------------------------------------------------
+# Signed and floating-point keys (an extension: the paper sorts unsigned
+# integers): pinned to numpy's stable argsort and to totalOrder's special
+# values written out.
+
+@pytest.mark.parametrize("dtype", [np.int32, np.int64])
+def test_signed_vs_numpy(dtype):
+    rng = np.random.default_rng(11)
+    info = np.iinfo(dtype)
+    k = rng.integers(info.min, info.max, 20000, dtype=dtype, endpoint=True)
+    k[:4] = [info.min, info.max, 0, -1]
+    k[100:2000] = k[2000:3900]                      # duplicates
+    ko, vo = oracle.sort_signed_or_float(k, np.arange(k.size, dtype=np.uint32), "signed")
+    ref = np.argsort(k, kind="stable")
+    assert np.array_equal(vo, ref.astype(np.uint32))
+    assert np.array_equal(ko, k[ref])
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_float_vs_numpy(dtype):
+    """Without NaNs and negative zeros numpy's order is totalOrder."""
+    rng = np.random.default_rng(12)
+    k = (rng.standard_normal(20000) * 1e3).astype(dtype)
+    k[::5] = np.round(k[::5])                        # duplicates
+    k[:6] = [np.inf, -np.inf, 0.0, np.finfo(dtype).tiny, -np.finfo(dtype).max, 1e-45]
+    k[k == 0] = 0.0                                  # rounding made -0.0s: numpy ties them with +0.0
+    ko, vo = oracle.sort_signed_or_float(k, np.arange(k.size, dtype=np.uint32), "float")
+    ref = np.argsort(k, kind="stable")
+    assert np.array_equal(vo, ref.astype(np.uint32))
+
+
+def test_float_total_order_special_values():
+    """-NaN < -inf < -1 < -0 < +0 < 1 < +inf < +NaN, ties in input order."""
+    for dtype in (np.float32, np.float64):
+        k = np.array([0.0, -0.0, np.inf, -np.inf, 1.0, -1.0, np.nan, -np.nan, -0.0, 0.0],
+                     dtype=dtype)
+        ko, vo = oracle.sort_signed_or_float(k, np.arange(k.size, dtype=np.uint32), "float")
+        assert vo.tolist() == [7, 3, 5, 1, 8, 0, 9, 4, 2, 6]

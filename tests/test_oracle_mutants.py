@@ -12,6 +12,7 @@ import os
 import subprocess
 import sys
 
+import numpy as np
 import pytest
 
 import oracle
@@ -54,6 +55,12 @@ MUTANTS = {
     "gvr_route_backward": (
         "    for (size_t q = 0; q < n; ++q) {\n        uint64_t o = start[bucket[q]]++;",
         "    for (size_t q = n; q-- > 0;) {\n        uint64_t o = start[bucket[q]]++;"),
+    "float_negatives_not_reversed": (
+        "    return a < b ? 1 : -1;                            /* float, both negative: reversed */",
+        "    return a < b ? -1 : 1;                            /* float, both negative: reversed */"),
+    "merge_ties_take_right": (
+        "if (cmp_kind(k[j], k[i], bits, kind) < 0) { tk[o] = k[j]; tv[o++] = v[j++]; }",
+        "if (cmp_kind(k[j], k[i], bits, kind) <= 0) { tk[o] = k[j]; tv[o++] = v[j++]; }"),
     "split_strict_instead_of_nonstrict": (
         "if (!comp_less(split_key[i - 1], split_g[i - 1], X[lo[k] + mid], lo[k] + mid))",
         "if (comp_less(X[lo[k] + mid], lo[k] + mid, split_key[i - 1], split_g[i - 1]))"),
@@ -74,6 +81,9 @@ PINS = [
     lambda: pins.test_gvr_output_split_and_splitters("zipf"),
     lambda: pins.test_gvr_output_split_and_splitters("equal"),
     pins.test_gvr_small_and_degenerate,
+    lambda: pins.test_signed_vs_numpy(np.int32),
+    lambda: pins.test_float_vs_numpy(np.float32),
+    pins.test_float_total_order_special_values,
 ]
 
 
