@@ -108,7 +108,8 @@ DevSegLayout devseg_layout(int key_bytes, bool has_vals, size_t n, uint32_t nseg
 hipError_t devseg_sort(int key_bytes, const void* keys_in, void* keys_out, const uint32_t* vals_in,
                        uint32_t* vals_out, size_t n, const uint32_t* off, uint32_t nseg,
                        uint32_t small_max, void* ws, const DevSegLayout& L, uint32_t* dev_err,
-                       hipStream_t stream, Profiler* prof, int small_sort = 0);
+                       hipStream_t stream, Profiler* prof, int small_sort = 0,
+                       const uint32_t* dev_rounds = nullptr);
 
 // ---------------------------------------------------------------------------
 // Oversampling sample sorts (sample_sort.hip), 32-bit keys: GSD (regular
@@ -134,9 +135,11 @@ struct GsdLayout {
     uint32_t g, M;
     size_t off_F, off_BK, off_large, off_R;
     // GVR route: tile counts, tile-scan state, round plan + ticket, bucket
-    // starts, and one bucket byte per key
+    // starts, one bucket byte per key, the bucket-search table, and the
+    // bucket key offsets (+ the round count), the tiles' key minima / maxima
     uint32_t route_tpb, route_ntiles;
-    size_t off_rcounts, off_rstate, off_rplan, off_rbases, off_bkt, off_rtab;
+    size_t off_rcounts, off_rstate, off_rplan, off_rbases, off_bkt, off_rtab, off_rshift,
+        off_rmm;
     size_t bytes;
 };
 GsdLayout gsd_layout(bool has_vals, size_t n, uint32_t p, uint32_t r);

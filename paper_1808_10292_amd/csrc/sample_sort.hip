@@ -343,14 +343,18 @@ __global__ __launch_bounds__(1024) void k_gvr_table(const uint32_t* Sk, uint32_t
 // Thread layout: key (q WG + tid) 4 + c, c < 4, so each group of 4 is one
 // 16-byte load (aligned full tiles) and one 4-byte store of bucket bytes; the
 // 16 searches of a thread advance together, one LDS probe each per step.
+// The tile's key minimum and maximum go to tmm[t] and tmm[ntiles + t] (an
+// empty tile writes 2^32 - 1 and 0).
 __global__ __launch_bounds__(kGvrWG) void k_gvr_count(const uint32_t* __restrict__ X,
                                                       const uint32_t* lo, uint32_t p, uint32_t s,
                                                       uint32_t tpb, const uint32_t* Sk,
                                                       const uint32_t* Sg, const uint8_t* gtab,
-                                                      uint8_t* bkt, uint32_t* counts)
+                                                      uint8_t* bkt, uint32_t* counts,
+                                                      uint32_t* tmm)
 {
     constexpr int ITEMS = kGvrItems;
     __shared__ uint2 spl[kGvrMaxP];
+    __shared__ uint2 wmm[kGvrWG / 64];
     __shared__ uint32_t h[R * 32];
     __shared__ uint8_t tab[kGvrTab + 4];
     const uint32_t tid = threadIdx.x;
@@ -375,6 +379,23 @@ __global__ __launch_bounds__(kGvrWG) void k_gvr_count(const uint32_t* __restrict
             const uint32_t u = ((i >> 2) * kGvrWG + tid) * 4 + (i & 3);
             key[i] = u < len ? X[base + u] : 0u;
         }
+    }
+    {
+        uint32_t kmin = ~0u, kmax = 0u;
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t u = ((i >> 2) * kGvrWG + tid) * 4 + (i & 3);
+            if (u < len) {
+                kmin = min(kmin, key[i]);
+                kmax = max(kmax, key[i]);
+            }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, o, 64));
+            kmax = max(kmax, (uint32_t)__shfl_xor((int)kmax, o, 64));
+        }
+        if ((tid & 63) == 0) wmm[tid >> 6] = make_uint2(kmin, kmax);
     }
     __syncthreads();
     // b[i] = number of splitters below key i: binary search of the splitters
@@ -418,6 +439,16 @@ __global__ __launch_bounds__(kGvrWG) void k_gvr_count(const uint32_t* __restrict
             if (u + c < len) atomicAdd(&h[b[4 * q + c] * 32 + col], 1u);
     }
     __syncthreads();
+    if (tid == 0) {
+        uint2 m = wmm[0];
+#pragma unroll
+        for (uint32_t w = 1; w < kGvrWG / 64; ++w) {
+            m.x = min(m.x, wmm[w].x);
+            m.y = max(m.y, wmm[w].y);
+        }
+        tmm[t] = m.x;
+        tmm[gridDim.x + t] = m.y;
+    }
     for (uint32_t v = tid; v < R; v += kGvrWG) {
         const uint4* r4 = (const uint4*)&h[v * 32];
         uint32_t sum = 0;
@@ -430,20 +461,86 @@ __global__ __launch_bounds__(kGvrWG) void k_gvr_count(const uint32_t* __restrict
     }
 }
 
+// Key offsets of the buckets: bucket j holds keys from lo_j (the key of
+// splitter S_j; the smallest key for j = 0) to hi_j (the key of S_{j+1}; the
+// largest key for j = p - 1), since its composites lie in (S_j, S_{j+1}].  The
+// route stores key - lo_j, so the bucket sort only needs the low digits that
+// cover the widest span hi_j - lo_j: rounds = ceil(bits / 8) of the largest
+// span (0 when every bucket holds one key value).  When that still takes all
+// four rounds the offsets are set to 0 (the route stores the keys as they are
+// and nothing is added back).  The smallest and largest keys come from the
+// route tiles' minima and maxima tmm.  One workgroup.
+constexpr uint32_t kRangeWG = 1024;
+__global__ __launch_bounds__(kRangeWG) void k_gvr_range(const uint32_t* Sk, uint32_t p,
+                                                        uint32_t s, const uint32_t* tmm,
+                                                        uint32_t ntiles, uint32_t* shift,
+                                                        uint32_t* rounds)
+{
+    __shared__ uint2 wred[kRangeWG / 64];
+    __shared__ uint32_t red[3];
+    const uint32_t tid = threadIdx.x;
+    uint32_t a = ~0u, b = 0u;
+    for (uint32_t i = tid; i < ntiles; i += 8 * kRangeWG) {
+        uint32_t x[8], y[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint32_t j = i + u * kRangeWG;
+            x[u] = j < ntiles ? tmm[j] : ~0u;
+            y[u] = j < ntiles ? tmm[ntiles + j] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            a = min(a, x[u]);
+            b = max(b, y[u]);
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        a = min(a, (uint32_t)__shfl_xor((int)a, o, 64));
+        b = max(b, (uint32_t)__shfl_xor((int)b, o, 64));
+    }
+    if ((tid & 63) == 0) wred[tid >> 6] = make_uint2(a, b);
+    __syncthreads();
+    if (tid == 0) {
+        for (uint32_t w = 1; w < kRangeWG / 64; ++w) {
+            a = min(a, wred[w].x);
+            b = max(b, wred[w].y);
+        }
+        red[0] = a;
+        red[1] = b;
+        red[2] = 0;
+    }
+    __syncthreads();
+    uint32_t bits = 0, lo = 0;
+    if (tid < p) {
+        lo = tid ? Sk[(size_t)tid * s - 1] : red[0];
+        const uint32_t hi = tid + 1 < p ? Sk[(size_t)(tid + 1) * s - 1] : red[1];
+        const uint32_t span = hi - lo;
+        bits = span ? 32u - (uint32_t)__clz(span) : 0u;
+    }
+    atomicMax(&red[2], bits);
+    __syncthreads();
+    const uint32_t nr = (red[2] + 7) / 8;
+    if (tid < kGvrMaxP) shift[tid] = nr < 4 ? lo : 0u;
+    if (tid == 0) *rounds = nr;
+}
+
 // Stable scatter of one route tile by bucket: counts[t][v] now holds the keys
 // of bucket v in earlier tiles and bases[v] the start of bucket v, so the key
 // of bucket v with tile rank q lands at bases[v] + counts[t][v] + q.  The rank
 // among the tile's keys of one bucket, in input order, comes from 64-bit slots
 // {lanes of the current row, keys of earlier rows} per 32-lane group (rows in
 // order); the tile is staged in LDS in bucket order with its bucket bytes and
-// written run by run, the payloads in a second staging pass.
+// written run by run, the payloads in a second staging pass.  A key of bucket
+// v is stored as key - shift[v].
 template <bool KV>
 __global__ __launch_bounds__(kGvrWG) void k_gvr_scatter(const uint32_t* __restrict__ X,
                                                         const uint32_t* __restrict__ XV,
                                                         const uint32_t* lo, uint32_t tpb,
                                                         const uint8_t* __restrict__ bkt,
                                                         const uint32_t* counts,
-                                                        const uint32_t* bases, uint32_t n,
+                                                        const uint32_t* bases,
+                                                        const uint32_t* shift, uint32_t n,
                                                         uint32_t* Y, uint32_t* YV)
 {
     constexpr int ITEMS = kGvrItems;
@@ -457,6 +554,7 @@ __global__ __launch_bounds__(kGvrWG) void k_gvr_scatter(const uint32_t* __restri
             } st;
         } u;
         uint32_t goff[R];
+        uint32_t sub[R];
         uint32_t wsum[kGvrWG / 64];
     };
     __shared__ Smem sm;
@@ -482,6 +580,7 @@ __global__ __launch_bounds__(kGvrWG) void k_gvr_scatter(const uint32_t* __restri
     for (uint32_t i = tid; i < kGvrGroups * R / 2; i += kGvrWG)
         ((uint4*)&sm.u.slot[0][0])[i] = make_uint4(0, 0, 0, 0);
     const uint32_t toff = tid < R ? counts[(size_t)t * R + tid] + bases[tid] : 0u;
+    if (tid < R) sm.sub[tid] = shift[tid];
     __syncthreads();
 
     // rank within the group, rows in order
@@ -535,7 +634,7 @@ __global__ __launch_bounds__(kGvrWG) void k_gvr_scatter(const uint32_t* __restri
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i)
         if (hofs + i * 32 < len) {
-            sm.u.st.keys[pos[i]] = k[i];
+            sm.u.st.keys[pos[i]] = k[i] - sm.sub[d[i]];
             sm.u.st.dig[pos[i]] = (uint8_t)d[i];
         }
     __syncthreads();
@@ -592,6 +691,71 @@ __global__ __launch_bounds__(R) void k_gvr_stats(const uint32_t* counts, const u
         if (j + 1 < p) {
             split_key[j] = Sk[(size_t)(j + 1) * s - 1];
             split_g[j] = Sg[(size_t)(j + 1) * s - 1];
+        }
+    }
+}
+
+// The bucket sort leaves key - shift[j] at the positions [boff[j], boff[j+1])
+// of bucket j; this adds shift[j] back (nothing to do after all four rounds:
+// the offsets were 0).  When it ran no round, the routed keys Y (and
+// payloads YV) are already in order and are copied.  Thread
+// groups of 4 consecutive keys (one 16-byte access where aligned), 4 groups
+// per thread strided by the workgroup; the bucket of a thread's first key is
+// found by binary search over the bucket starts, later keys walk forward.
+constexpr uint32_t kUnshiftWG = 256;
+constexpr uint32_t kUnshiftTile = kUnshiftWG * 16;
+template <bool KV>
+__global__ __launch_bounds__(kUnshiftWG) void k_gvr_unshift(uint32_t* keys_out, uint32_t* vals_out,
+                                                            const uint32_t* Y, const uint32_t* YV,
+                                                            const uint32_t* boff,
+                                                            const uint32_t* shift,
+                                                            const uint32_t* rounds, uint32_t p,
+                                                            uint32_t n)
+{
+    __shared__ uint32_t sb[kGvrMaxP + 1];
+    __shared__ uint32_t sh[kGvrMaxP];
+    const uint32_t nr = *rounds;
+    if (nr >= 4) return;
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t j = tid; j <= p; j += kUnshiftWG) sb[j] = boff[j];
+    if (tid < p) sh[tid] = shift[tid];
+    const bool copy = nr == 0;
+    const uint32_t* src = copy ? Y : keys_out;
+    __syncthreads();
+    const uint32_t base = blockIdx.x * kUnshiftTile;
+    const uint32_t i0 = base + tid * 4;
+    if (i0 >= n) return;
+    uint32_t a = 0, b = p - 1;   // largest j < p with sb[j] <= i0 (sb[0] = 0)
+    while (a < b) {
+        const uint32_t mid = (a + b + 1) >> 1;
+        if (sb[mid] <= i0) a = mid; else b = mid - 1;
+    }
+    uint32_t j = a;
+    const bool vec = ((uintptr_t)keys_out & 15) == 0 && ((uintptr_t)src & 15) == 0 &&
+                     (!KV || !copy || (((uintptr_t)vals_out & 15) == 0 && ((uintptr_t)YV & 15) == 0));
+    typedef uint32_t v4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t i = base + (q * kUnshiftWG + tid) * 4;
+        if (i >= n) break;
+        uint32_t add[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            while (sb[j + 1] <= i + c && j + 1 < p) ++j;
+            add[c] = sh[j];
+        }
+        if (vec && i + 4 <= n) {
+            v4 x = *(const v4*)(src + i);
+            x.x += add[0]; x.y += add[1]; x.z += add[2]; x.w += add[3];
+            *(v4*)(keys_out + i) = x;
+            if (KV && copy) *(v4*)(vals_out + i) = *(const v4*)(YV + i);
+        } else {
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                if (i + c < n) {
+                    keys_out[i + c] = src[i + c] + add[c];
+                    if (KV && copy) vals_out[i + c] = YV[i + c];
+                }
         }
     }
 }
@@ -1081,6 +1245,8 @@ GsdLayout skeleton_layout(bool has_vals, size_t n, uint32_t p, uint32_t s, size_
         L.off_rbases = o;  o = align_up(o + R * 4);
         L.off_bkt = o;     o = align_up(o + n);
         L.off_rtab = o;    o = align_up(o + kGvrTab + 4);
+        L.off_rshift = o;  o = align_up(o + (kGvrMaxP + 1) * 4);
+        L.off_rmm = o;     o = align_up(o + (size_t)L.route_ntiles * 8);
     }
     L.bytes = o;
     return L;
@@ -1143,6 +1309,9 @@ hipError_t gvr_sort(const uint32_t* keys_in, uint32_t* keys_out, const uint32_t*
     uint32_t* ticket = (uint32_t*)(w + L.off_rplan + sizeof(RoundPlan));
     uint32_t* bases = (uint32_t*)(w + L.off_rbases);
     uint8_t* bkt = w + L.off_bkt;
+    uint32_t* shift = (uint32_t*)(w + L.off_rshift);
+    uint32_t* rounds = shift + kGvrMaxP;
+    uint32_t* tmm = (uint32_t*)(w + L.off_rmm);
     const size_t nblocks = (nt + kScanBlock - 1) / kScanBlock;
     // 1-2. sample of the input and splitters
     hipError_t e = random_sample(keys_in, n, L, seed, w, Tk, Tg, Sk, Sg, dev_err, stream);
@@ -1153,7 +1322,9 @@ hipError_t gvr_sort(const uint32_t* keys_in, uint32_t* keys_out, const uint32_t*
     uint8_t* tab = w + L.off_rtab;
     hipLaunchKernelGGL(k_gvr_table, dim3(1), dim3(1024), 0, stream, Sk, p, s, tab);
     hipLaunchKernelGGL(k_gvr_count, dim3(nt), dim3(kGvrWG), 0, stream, keys_in, lo, p, s, tpb, Sk,
-                       Sg, tab, bkt, counts);
+                       Sg, tab, bkt, counts, tmm);
+    hipLaunchKernelGGL(k_gvr_range, dim3(1), dim3(kRangeWG), 0, stream, Sk, p, s, tmm, nt, shift,
+                       rounds);
     RoundArgs a{};
     a.n = (uint32_t)n;
     a.ntiles = nt;
@@ -1166,17 +1337,27 @@ hipError_t gvr_sort(const uint32_t* keys_in, uint32_t* keys_out, const uint32_t*
     hipLaunchKernelGGL(k_tilescan, dim3((uint32_t)nblocks), dim3(R), 0, stream, a);
     if (vals_in)
         hipLaunchKernelGGL(k_gvr_scatter<true>, dim3(nt), dim3(kGvrWG), 0, stream, keys_in,
-                           vals_in, lo, tpb, bkt, counts, bases, (uint32_t)n, Y, YV);
+                           vals_in, lo, tpb, bkt, counts, bases, shift, (uint32_t)n, Y, YV);
     else
         hipLaunchKernelGGL(k_gvr_scatter<false>, dim3(nt), dim3(kGvrWG), 0, stream, keys_in,
-                           nullptr, lo, tpb, bkt, counts, bases, (uint32_t)n, Y, nullptr);
+                           nullptr, lo, tpb, bkt, counts, bases, shift, (uint32_t)n, Y, nullptr);
     hipLaunchKernelGGL(k_gvr_stats, dim3(p), dim3(R), 0, stream, counts, bases, (uint32_t)n, p, s,
                        tpb, Sk, Sg, boff, bnd, split_key, split_g);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // 4. every bucket stable-sorted into the output
-    return devseg_sort(4, Y, keys_out, YV, vals_out, n, boff, p, kSmallMaxDefault, w + L.off_seg,
-                       L.LS, dev_err, stream, prof);
+    // 4. every bucket stable-sorted into the output by the digits its keys
+    // span, then the bucket offsets added back
+    e = devseg_sort(4, Y, keys_out, YV, vals_out, n, boff, p, kSmallMaxDefault, w + L.off_seg,
+                    L.LS, dev_err, stream, prof, 0, rounds);
+    if (e != hipSuccess) return e;
+    const dim3 ug((uint32_t)((n + kUnshiftTile - 1) / kUnshiftTile));
+    if (vals_in)
+        hipLaunchKernelGGL(k_gvr_unshift<true>, ug, dim3(kUnshiftWG), 0, stream, keys_out,
+                           vals_out, Y, YV, boff, shift, rounds, p, (uint32_t)n);
+    else
+        hipLaunchKernelGGL(k_gvr_unshift<false>, ug, dim3(kUnshiftWG), 0, stream, keys_out,
+                           nullptr, Y, nullptr, boff, shift, rounds, p, (uint32_t)n);
+    return hipGetLastError();
 }
 
 // GSD / GER with the merge finish: local sort into Y, the sample (regular or

@@ -483,7 +483,8 @@ __device__ uint32_t plan_exclusive_sum(uint32_t x, uint32_t* wsum, uint32_t* tot
 
 __global__ __launch_bounds__(kPlanWG) void k_devseg_plan(const uint32_t* off, uint32_t nseg,
                                                          uint32_t n, uint32_t small_max,
-                                                         uint32_t tile, uint32_t rounds,
+                                                         uint32_t tile, uint32_t key_rounds,
+                                                         const uint32_t* dev_rounds,
                                                          RoundPlan* plan, uint2* small,
                                                          uint2* tiles, uint4* lsegs,
                                                          uint32_t* ntiles, uint32_t* err)
@@ -508,6 +509,9 @@ __global__ __launch_bounds__(kPlanWG) void k_devseg_plan(const uint32_t* off, ui
         }
         return;
     }
+    // the large segments' rounds: the low digits the keys can differ in
+    // (dev_rounds, when given), so the last one still writes the output
+    const uint32_t rounds = dev_rounds ? min(key_rounds, *dev_rounds) : key_rounds;
     if (tid <= (uint32_t)kMaxRounds) {
         RoundPlan r{0, -1, 0, -1};
         if (tid < rounds) {
@@ -554,7 +558,8 @@ template <typename K, bool KV>
 hipError_t run_devseg(const void* keys_in, void* keys_out, const uint32_t* vals_in,
                       uint32_t* vals_out, size_t n, const uint32_t* off, uint32_t nseg,
                       uint32_t small_max, void* ws, const DevSegLayout& L, uint32_t* dev_err,
-                      hipStream_t stream, Profiler* prof, int small_sort)
+                      hipStream_t stream, Profiler* prof, int small_sort,
+                      const uint32_t* dev_rounds)
 {
     uint8_t* w = (uint8_t*)ws;
     K* keys_tmp = (K*)(w + L.off_tmp_keys);
@@ -567,8 +572,8 @@ hipError_t run_devseg(const void* keys_in, void* keys_out, const uint32_t* vals_
     uint32_t* ntiles = (uint32_t*)(w + L.off_ntiles);
     const uint32_t rounds = sizeof(K);
     hipLaunchKernelGGL(k_devseg_plan, dim3(1), dim3(kPlanWG), 0, stream, off, nseg, (uint32_t)n,
-                       small_max, large_tile(sizeof(K)), rounds, plan, small, tiles, lsegs, ntiles,
-                       dev_err);
+                       small_max, large_tile(sizeof(K)), rounds, dev_rounds, plan, small, tiles,
+                       lsegs, ntiles, dev_err);
     if (prof) profiler_mark(prof, stream, kKindSmall, true);
     for (int c = 0; c < 3; ++c)
         launch_small<K, KV>(c, keys_in, keys_out, KV ? vals_in : nullptr, KV ? vals_out : nullptr,
@@ -633,15 +638,16 @@ DevSegLayout devseg_layout(int key_bytes, bool has_vals, size_t n, uint32_t nseg
 hipError_t devseg_sort(int key_bytes, const void* keys_in, void* keys_out, const uint32_t* vals_in,
                        uint32_t* vals_out, size_t n, const uint32_t* off, uint32_t nseg,
                        uint32_t small_max, void* ws, const DevSegLayout& L, uint32_t* dev_err,
-                       hipStream_t stream, Profiler* prof, int small_sort)
+                       hipStream_t stream, Profiler* prof, int small_sort,
+                       const uint32_t* dev_rounds)
 {
     if (!nseg || !n) return hipSuccess;
     const bool kv = vals_in != nullptr;
     if (key_bytes == 4)
-        return kv ? run_devseg<uint32_t, true>(keys_in, keys_out, vals_in, vals_out, n, off, nseg, small_max, ws, L, dev_err, stream, prof, small_sort)
-                  : run_devseg<uint32_t, false>(keys_in, keys_out, vals_in, vals_out, n, off, nseg, small_max, ws, L, dev_err, stream, prof, small_sort);
-    return kv ? run_devseg<uint64_t, true>(keys_in, keys_out, vals_in, vals_out, n, off, nseg, small_max, ws, L, dev_err, stream, prof, small_sort)
-              : run_devseg<uint64_t, false>(keys_in, keys_out, vals_in, vals_out, n, off, nseg, small_max, ws, L, dev_err, stream, prof, small_sort);
+        return kv ? run_devseg<uint32_t, true>(keys_in, keys_out, vals_in, vals_out, n, off, nseg, small_max, ws, L, dev_err, stream, prof, small_sort, dev_rounds)
+                  : run_devseg<uint32_t, false>(keys_in, keys_out, vals_in, vals_out, n, off, nseg, small_max, ws, L, dev_err, stream, prof, small_sort, dev_rounds);
+    return kv ? run_devseg<uint64_t, true>(keys_in, keys_out, vals_in, vals_out, n, off, nseg, small_max, ws, L, dev_err, stream, prof, small_sort, dev_rounds)
+              : run_devseg<uint64_t, false>(keys_in, keys_out, vals_in, vals_out, n, off, nseg, small_max, ws, L, dev_err, stream, prof, small_sort, dev_rounds);
 }
 
 }  // namespace rsort

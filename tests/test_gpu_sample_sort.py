@@ -320,6 +320,53 @@ def test_gvr_in_place_unaligned_and_keys_only(rs):
     run_gvr(rs, keys, 128, 40, 11, with_vals=False, offset=3)
 
 
+def _span_keys(case, n, seed):
+    rng = np.random.default_rng(seed)
+    if case == "one_value":
+        return np.full(n, 0x9E3779B9, np.uint32)
+    if case == "one_value_max":
+        return np.full(n, 0xFFFFFFFF, np.uint32)
+    if case == "top_byte_span":      # keys in [2^32 - 256, 2^32): spans below 2^8
+        return (0xFFFFFF00 + rng.integers(0, 256, n)).astype(np.uint32)
+    if case == "low16":
+        return rng.integers(0, 1 << 16, n, dtype=np.uint32)
+    if case == "low24":
+        return rng.integers(0, 1 << 24, n, dtype=np.uint32)
+    if case == "two_values":
+        return np.where(rng.random(n) < 0.5, 5, 0xFFFFFFF0).astype(np.uint32)
+    k = rng.integers(0, 1 << 32, n, dtype=np.uint32)   # "uniform_extremes"
+    k[0], k[-1] = 0xFFFFFFFF, 0
+    return k
+
+
+@pytest.mark.parametrize("case,p,with_vals,in_place,offset", [
+    ("one_value", 16, True, False, 0),
+    ("one_value", 16, False, True, 0),
+    ("one_value_max", 7, True, False, 1),
+    ("top_byte_span", 4, True, False, 0),
+    ("top_byte_span", 1, False, False, 3),
+    ("low16", 1, True, False, 0),
+    ("low16", 64, True, True, 0),
+    ("low24", 4, True, False, 0),
+    ("low24", 4, False, False, 2),
+    ("two_values", 2, True, False, 0),
+    ("uniform_extremes", 64, True, False, 0),
+    ("uniform_extremes", 1, True, False, 1),
+    ("uniform_extremes", 2, False, False, 0),
+])
+def test_gvr_bucket_spans(rs, case, p, with_vals, in_place, offset):
+    """The route stores key - lo_j and the bucket sort runs only the digits of
+    the widest bucket span: no round (one key value: the routed keys are
+    copied), one, two, three (keys below 2^24 in 4 buckets) or four (spread
+    keys: the keys are routed unchanged), including the extreme keys 0 and 2^32 - 1, unaligned
+    outputs (scalar path) and a ragged tail; buckets above the small-segment
+    limit take the tiled rounds."""
+    n = (1 << 20) + 3
+    announce("gvr spans", case, p, with_vals, in_place, offset)
+    run_gvr(rs, _span_keys(case, n, 31 + p), p, 20, 77 + p, with_vals=with_vals,
+            in_place=in_place, offset=offset)
+
+
 def test_gvr_default_oversampling_and_errors(rs):
     """s = 0 takes s = 2 w^2 lg n as for GER; p above 256 is refused."""
     import torch
