@@ -40,6 +40,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBPS = 8000.0
 METRIC = "Gkeys/s + % HBM roofline, 2^27 uint32; batched vs plain; p50/p99 latency"
+ROUND_SAMPLE_PERIOD = 5   # time launches 0, 5, 10, ... of the scatter in the timed region
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_scatter_u32_keys_2p27_counters.md")
 ROUND_SOURCE = os.path.join(ROOT, "paper_1808_10292_amd", "csrc", "lsd_r8.hip")
 
@@ -75,10 +76,18 @@ def committed_traffic():
         return None
 
 
+WARM_MS = 40.0   # the GPU's clocks take about 30 ms of work to recover from an idle gap
+
+
 def time_steps(fn, steps, warmup, torch):
-    for _ in range(warmup):
+    """Seconds per call of fn over `steps` calls, after at least `warmup`
+    calls and at least WARM_MS of device work."""
+    t0 = time.perf_counter()
+    done = 0
+    while done < warmup or (time.perf_counter() - t0) * 1e3 < WARM_MS:
         fn()
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        done += 1
     t0 = time.perf_counter()
     for _ in range(steps):
         fn()
@@ -397,7 +406,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    # the GPU lowers its clocks whenever it idles; about 20 sorts of 2^27
+    # keys (30 ms) pass before they are back at their steady rate
+    ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--log2n", type=int, default=27)
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="minimum CPU time spent timing the oracle (0 disables)")
@@ -448,8 +459,10 @@ def main():
         step()
     torch.cuda.synchronize()
     # timed region: HIP events on the launch stream around the dominant kernel
-    # only (every event pair delays the stream a little)
+    # only, and around every fifth launch of it (every event pair delays the
+    # stream; 5 against 4 rounds per sort samples each round equally often)
     rsort.rsort_profile_enable(True, kinds=[rsort.RSORT_KERNEL_ROUND])
+    rsort.rsort_profile_set_period(ROUND_SAMPLE_PERIOD)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -510,6 +523,7 @@ def main():
                      "kernel": "k_scatter<uint32, keys-only> (rank and route of one count-sort round)",
                      "algorithmic_bytes_per_launch": bytes_per_round,
                      "avg_launch_ms": round(round_avg_ms, 5), "timed_launches": launches,
+                     "launches_in_timed_region": 4 * args.steps,
                      "copy_gbps": round(copy_gbps, 1),
                      "frac_of_copy": round(achieved / copy_gbps, 4)},
         "per_round_ms": {"count": round(count_ms / max(cl, 1), 5),

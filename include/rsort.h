@@ -372,6 +372,15 @@ int rsort_profile_enable(rsort_ctx* ctx, int enable);
  * durations in milliseconds. */
 int rsort_profile_read(rsort_ctx* ctx, int kind, uint64_t* launches, double* total_ms);
 
+/* Time only every `period`-th launch of each timed kind: launches 0, period,
+ * 2 period, ... of that kind since profiling was enabled (period 1, the
+ * default, times them all).  Fewer event pairs delay the stream less; a period
+ * coprime with a sort's launches of the kind (5 against the 4 count-sort
+ * rounds of 32-bit keys) still samples every round equally often.  Returns
+ * RSORT_EINVAL when profiling is not enabled or period is 0; enabling again
+ * resets the period to 1. */
+int rsort_profile_set_period(rsort_ctx* ctx, uint32_t period);
+
 #ifdef __cplusplus
 }
 #endif

@@ -24,6 +24,9 @@ struct Profiler {
     std::vector<hipEvent_t> pool;
     std::vector<Pair> pending;
     uint32_t kinds = ~0u;   // bit k: kernels of kind k are timed
+    uint32_t period = 1;    // time launches 0, period, 2 period, ... of each kind
+    uint64_t seen[kNumKinds] = {};
+    bool skipping[kNumKinds] = {};
     hipEvent_t open_start[kNumKinds] = {};
     uint64_t launches[kNumKinds] = {};
     double total_ms[kNumKinds] = {};
@@ -63,6 +66,12 @@ struct Profiler {
 void profiler_mark(Profiler* p, hipStream_t s, int kind, bool begin)
 {
     if (!(p->kinds & (1u << kind))) return;
+    if (begin) {
+        p->skipping[kind] = p->seen[kind]++ % p->period != 0;
+        if (p->skipping[kind]) return;
+    } else if (p->skipping[kind]) {
+        return;
+    }
     hipEvent_t e = p->get();
     if (!e) return;
     (void)hipEventRecord(e, s);
@@ -676,6 +685,15 @@ int rsort_profile_enable(rsort_ctx* ctx, int enable)
         if (!ctx->prof) return fail(ctx, RSORT_ENOMEM, "profiler");
         ctx->prof->kinds = (uint32_t)enable;
     }
+    return RSORT_OK;
+}
+
+int rsort_profile_set_period(rsort_ctx* ctx, uint32_t period)
+{
+    if (!ctx) return RSORT_EINVAL;
+    if (!ctx->prof) return fail(ctx, RSORT_EINVAL, "profiling is not enabled");
+    if (!period) return fail(ctx, RSORT_EINVAL, "period must be at least 1");
+    ctx->prof->period = period;
     return RSORT_OK;
 }
 

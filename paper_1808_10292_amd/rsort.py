@@ -48,7 +48,8 @@ ALGOS = {"auto": RSORT_AUTO, "lsd8": RSORT_LSD_R8, "pr4": RSORT_LSD_R8,
 # Every symbol include/rsort.h declares; the loader checks they all exist.
 EXPORTED = ("rsort_create", "rsort_destroy", "rsort_status_string", "rsort_last_error",
             "rsort_workspace_bytes", "rsort_sort", "rsort_histogram", "rsort_synchronize",
-            "rsort_profile_enable", "rsort_profile_read", "rsort_segmented_sort",
+            "rsort_profile_enable", "rsort_profile_read", "rsort_profile_set_period",
+            "rsort_segmented_sort",
             "rsort_segmented_workspace_bytes", "rsort_segmented_set_split",
             "rsort_segmented_tune", "rsort_segmented_set_small_sort",
             "rsort_segmented_get_small_sort", "rsort_sample_sort", "rsort_sample_sort_workspace_bytes",
@@ -108,6 +109,7 @@ def load_library():
         lib.rsort_histogram.argtypes = [vp, i, vp, sz, i, i, i, u32p, vp]
         lib.rsort_synchronize.argtypes = [vp, vp]
         lib.rsort_profile_enable.argtypes = [vp, i]
+        lib.rsort_profile_set_period.argtypes = [vp, ctypes.c_uint32]
         lib.rsort_segmented_sort.argtypes = [vp, i, vp, vp, u32p, u32p, vp, sz, vp, sz, vp]
         lib.rsort_segmented_workspace_bytes.argtypes = [vp, i, i, vp, sz, ctypes.POINTER(sz)]
         lib.rsort_segmented_set_split.argtypes = [vp, ctypes.c_uint32]
@@ -315,6 +317,13 @@ def rsort_profile_enable(enable=True, kinds=None, device=None):
     if enable:
         mask = -1 if kinds is None else sum(1 << int(k) for k in set(kinds))
     ctx.check(ctx._lib.rsort_profile_enable(ctx.handle, int(mask)), "rsort_profile_enable")
+
+
+def rsort_profile_set_period(period, device=None):
+    """Time only launches 0, period, 2 period, ... of each timed kind."""
+    ctx = context(device)
+    ctx.check(ctx._lib.rsort_profile_set_period(ctx.handle, int(period)),
+              "rsort_profile_set_period")
 
 
 def rsort_profile_read(kind=RSORT_KERNEL_ROUND, device=None):

@@ -181,6 +181,36 @@ def test_argument_errors(rs):
     rs.rsort_synchronize()
 
 
+def test_profile_counts_and_period(rs):
+    """Kernel timing: every round launch of a 4-round sort is timed; with a
+    period of 5 only launches 0, 5, 10, ... of the kind are; period 0 and a
+    disabled profiler are errors."""
+    import torch
+    announce("profiler")
+    keys = keygen.uniform_u32(1 << 20, 41)
+    dk = dev(keys)
+    out = torch.empty_like(dk)
+    rs.rsort_profile_enable(True, kinds=[rs.RSORT_KERNEL_ROUND])
+    for _ in range(3):
+        rs.rsort_sort(dk, out, algo="lsd8")
+    launches, ms = rs.rsort_profile_read(rs.RSORT_KERNEL_ROUND)
+    assert launches == 12 and ms > 0
+    assert rs.rsort_profile_read(rs.RSORT_KERNEL_COUNT) == (0, 0.0)   # kind not timed
+    rs.rsort_profile_enable(True, kinds=[rs.RSORT_KERNEL_ROUND])
+    rs.rsort_profile_set_period(5)
+    for _ in range(6):
+        rs.rsort_sort(dk, out, algo="lsd8")
+    launches, ms = rs.rsort_profile_read(rs.RSORT_KERNEL_ROUND)
+    assert launches == 5 and ms > 0                                   # 0, 5, 10, 15, 20 of 24
+    with pytest.raises(rs.RsortError):
+        rs.rsort_profile_set_period(0)
+    rs.rsort_profile_enable(False)
+    with pytest.raises(rs.RsortError):
+        rs.rsort_profile_set_period(2)
+    rs.rsort_synchronize()
+    assert np.array_equal(host(out), np.sort(keys))
+
+
 @pytest.mark.slow
 def test_full_size_2p27_keys_only(rs):
     """The benchmark workload itself: 2^27 uniform 32-bit keys, bit-exact."""
