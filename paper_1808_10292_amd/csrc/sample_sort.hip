@@ -1019,9 +1019,10 @@ __device__ __forceinline__ uint2 merge_key_bounds(const uint32_t* Sk, uint32_t g
 // key range spans.  Pieces beyond one LDS tile, and with
 // payloads pieces of a wider key range, are only listed here (large[0] =
 // count, large[1..] = pieces) for k_gsd_merge_large.
-// 3 waves per SIMD: three 4-wave workgroups per CU fit its LDS.
+// The ranking slots share LDS with the key staging: with payloads about
+// 35 KiB per workgroup, four 4-wave workgroups per CU.
 template <bool KV>
-__global__ __launch_bounds__(kMergeWG, 3) void k_gsd_merge(const uint32_t* __restrict__ X,
+__global__ __launch_bounds__(kMergeWG, 4) void k_gsd_merge(const uint32_t* __restrict__ X,
                                                            const uint32_t* __restrict__ XV,
                                                            const uint32_t* lo, uint32_t p,
                                                            uint32_t M, uint32_t g,
@@ -1035,7 +1036,7 @@ __global__ __launch_bounds__(kMergeWG, 3) void k_gsd_merge(const uint32_t* __res
                   "the run map lives in the ranking slots");
     // LDS: the keys-only ranking tile, with payloads followed by the payloads
     // staged by piece position
-    using SmK = TileSmem<uint32_t, false, kMergeWG, ITEMS>;
+    using SmK = TileSmem<uint32_t, false, kMergeWG, ITEMS, true>;
     struct Packed {
         SmK t;
         uint32_t vst[KV ? C : 1];

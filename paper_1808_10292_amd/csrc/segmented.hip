@@ -31,7 +31,7 @@ __global__ __launch_bounds__(WG) void k_seg_small(const K* __restrict__ keys_in,
                                                   uint32_t* vals_out, const uint2* segs,
                                                   uint32_t nrounds)
 {
-    __shared__ TileSmem<K, KV, WG, ITEMS> sm;
+    __shared__ TileSmem<K, KV, WG, ITEMS, true> sm;
     const uint32_t tid = threadIdx.x;
     const uint32_t hofs = (tid >> 5) * ITEMS * 32 + (tid & 31);
     const uint2 seg = segs[blockIdx.x];

@@ -57,7 +57,7 @@ int serve_class(uint64_t n)
 template <typename K, int WG, int ITEMS>
 __global__ __launch_bounds__(WG) void k_serve_small(const ServeDesc* descs)
 {
-    __shared__ TileSmem<K, false, WG, ITEMS> sm;
+    __shared__ TileSmem<K, false, WG, ITEMS, true> sm;
     const ServeDesc d = descs[blockIdx.x];
     const K* in = (const K*)d.in;
     K* out = (K*)d.out;

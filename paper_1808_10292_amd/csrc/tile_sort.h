@@ -23,7 +23,11 @@ namespace {
 
 constexpr uint32_t kTileRadix = 256;
 
-template <typename K, bool KV, int WG, int ITEMS>
+// SHARED: the slots and the key staging share their LDS (they are never live
+// together; one more barrier separates the ranking from the restaging), so
+// more workgroups fit a CU.  The keys of an identity round then do not stay
+// in LDS.
+template <typename K, bool KV, int WG, int ITEMS, bool SHARED = false>
 struct TileSmem {
     static constexpr uint32_t TILE = (uint32_t)WG * ITEMS;
     static constexpr int HW = WG / 32;
@@ -32,12 +36,23 @@ struct TileSmem {
     uint2 slot[HW][kTileRadix];
     uint32_t wsum[4];
 };
+template <typename K, bool KV, int WG, int ITEMS>
+struct TileSmem<K, KV, WG, ITEMS, true> {
+    static constexpr uint32_t TILE = (uint32_t)WG * ITEMS;
+    static constexpr int HW = WG / 32;
+    union {
+        K keys[TILE];
+        uint2 slot[HW][kTileRadix];
+    };
+    uint32_t vals[KV ? TILE : 1];
+    uint32_t wsum[4];
+};
 
 // Returns false if the round was the identity (nothing moved, LDS keys[]
 // untouched); true if k / v now hold the new order and LDS keys[] / vals[]
 // hold the tile in that order.  Every thread of the workgroup must call it.
-template <typename K, bool KV, int WG, int ITEMS>
-__device__ __forceinline__ bool tile_round(TileSmem<K, KV, WG, ITEMS>& sm, K (&k)[ITEMS], uint32_t (&v)[ITEMS],
+template <typename K, bool KV, int WG, int ITEMS, bool SHARED>
+__device__ __forceinline__ bool tile_round(TileSmem<K, KV, WG, ITEMS, SHARED>& sm, K (&k)[ITEMS], uint32_t (&v)[ITEMS],
                            uint32_t len, uint32_t shift, uint32_t mask)
 {
     constexpr int HW = WG / 32;
@@ -118,6 +133,7 @@ __device__ __forceinline__ bool tile_round(TileSmem<K, KV, WG, ITEMS>& sm, K (&k
         }
     }
     // restage in the new order and reload in the ranking layout
+    if constexpr (SHARED) __syncthreads();   // every slot read before keys overwrite them
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         if (hofs + i * 32 < len) {
