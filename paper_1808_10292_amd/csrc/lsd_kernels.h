@@ -8,6 +8,7 @@
 #pragma once
 
 #include <algorithm>
+#include <type_traits>
 
 #include "device_common.h"
 #include "rsort_internal.h"
@@ -615,10 +616,12 @@ __global__ __launch_bounds__(WG, !KV ? RSORT_R8_WAVES_PER_EU : sizeof(K) == 4 ? 
         return;
     }
 
-    auto load = [&](uint32_t t, K (&kk)[ITEMS], uint32_t (&vv)[ITEMS]) {
+    // full: std::true_type when the tile holds TILE keys (every tile but a
+    // last or segment-end one), so that the bounds tests fold away
+    auto load = [&](auto full, uint32_t t, K (&kk)[ITEMS], uint32_t (&vv)[ITEMS]) {
         const uint2 tr = tile_range(a, t, TILE);
         const uint32_t base = tr.x;
-        const uint32_t lim = tr.y;
+        const uint32_t lim = decltype(full)::value ? TILE : tr.y;
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
             const uint32_t o = hofs + i * G;
@@ -630,9 +633,10 @@ __global__ __launch_bounds__(WG, !KV ? RSORT_R8_WAVES_PER_EU : sizeof(K) == 4 ? 
     // One tile whose keys are in k/v; the keys of tile tn (if any) are loaded
     // into kn/vn once k has been counted, so that those loads are in flight
     // while this tile is ranked, staged and written.
-    auto process = [&](uint32_t tile, K (&k)[ITEMS], uint32_t (&v)[ITEMS], uint32_t tn,
+    auto process = [&](auto full, uint32_t tile, K (&k)[ITEMS], uint32_t (&v)[ITEMS], uint32_t tn,
                        K (&kn)[ITEMS], uint32_t (&vn)[ITEMS]) {
-        const uint32_t lim = tile_range(a, tile, TILE).y;   // keys in this tile
+        // keys in this tile
+        const uint32_t lim = decltype(full)::value ? TILE : tile_range(a, tile, TILE).y;
         constexpr uint32_t slot_u4 = NG * R * (G == 32 ? 8 : 4) / 16;
         for (uint32_t i = tid; i < slot_u4; i += WG)
             ((uint4*)&sm.u)[i] = make_uint4(0, 0, 0, 0);
@@ -728,7 +732,7 @@ __global__ __launch_bounds__(WG, !KV ? RSORT_R8_WAVES_PER_EU : sizeof(K) == 4 ? 
                 }
             }
         }
-        if (RSORT_SCATTER_PERSIST && tn != kNoTile) load(tn, kn, vn);
+        if (RSORT_SCATTER_PERSIST && tn != kNoTile) load(std::false_type{}, tn, kn, vn);
         __syncthreads();
 
         // bases
@@ -818,20 +822,26 @@ __global__ __launch_bounds__(WG, !KV ? RSORT_R8_WAVES_PER_EU : sizeof(K) == 4 ? 
 
     K ka[ITEMS];
     uint32_t va[ITEMS];
-    load(tile, ka, va);
     if constexpr (!RSORT_SCATTER_PERSIST) {
-        process(tile, ka, va, kNoTile, ka, va);
+        if (tile_range(a, tile, TILE).y == TILE) {
+            load(std::true_type{}, tile, ka, va);
+            process(std::true_type{}, tile, ka, va, kNoTile, ka, va);
+        } else {
+            load(std::false_type{}, tile, ka, va);
+            process(std::false_type{}, tile, ka, va, kNoTile, ka, va);
+        }
         return;
     }
+    load(std::false_type{}, tile, ka, va);
     K kb[ITEMS];
     uint32_t vb[ITEMS];
     for (;;) {
         uint32_t tn = next_of(tile);
-        process(tile, ka, va, tn, kb, vb);
+        process(std::false_type{}, tile, ka, va, tn, kb, vb);
         tile = tn;
         if (tile == kNoTile) break;
         tn = next_of(tile);
-        process(tile, kb, vb, tn, ka, va);
+        process(std::false_type{}, tile, kb, vb, tn, ka, va);
         tile = tn;
         if (tile == kNoTile) break;
     }
