@@ -355,15 +355,30 @@ __global__ void k_plan(const uint32_t* mixed, uint32_t nrounds, uint32_t begin_b
 }
 
 // In-place sorts with an odd number of running rounds: copy input -> temporary.
+constexpr int kPrecopyItems = 8;
+
 template <typename K>
 __global__ void k_precopy(const RoundPlan* plan, const K* keys, K* keys_tmp,
                           const uint32_t* vals, uint32_t* vals_tmp, uint32_t n)
 {
     if (!plan[kMaxRounds].exec) return;
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        keys_tmp[i] = keys[i];
-        if (vals) vals_tmp[i] = vals[i];
+    // kPrecopyItems elements per thread, all loaded before the first store
+    const size_t base = (size_t)blockIdx.x * blockDim.x * kPrecopyItems + threadIdx.x;
+    K kk[kPrecopyItems];
+    uint32_t vv[kPrecopyItems];
+#pragma unroll
+    for (int j = 0; j < kPrecopyItems; ++j) {
+        const size_t i = base + (size_t)j * blockDim.x;
+        kk[j] = i < n ? keys[i] : K(0);
+        vv[j] = vals && i < n ? vals[i] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < kPrecopyItems; ++j) {
+        const size_t i = base + (size_t)j * blockDim.x;
+        if (i < n) {
+            keys_tmp[i] = kk[j];
+            if (vals) vals_tmp[i] = vv[j];
+        }
     }
 }
 
@@ -608,10 +623,24 @@ __global__ __launch_bounds__(WG, !KV ? RSORT_R8_WAVES_PER_EU : sizeof(K) == 4 ? 
     const uint32_t* vsrc = KV ? pick<uint32_t>(pl.src, a.vals_in, a.vals_out, a.vals_tmp) : nullptr;
     K* dst = pick<K>(pl.dst, (const K*)a.keys_in, (K*)a.keys_out, (K*)a.keys_tmp);
     uint32_t* vdst = KV ? pick<uint32_t>(pl.dst, a.vals_in, a.vals_out, a.vals_tmp) : nullptr;
-    if (pl.exec == 2) {   // identity round standing for a copy
-        for (uint32_t i = blockIdx.x * WG + tid; i < a.n; i += gridDim.x * WG) {
-            dst[i] = src[i];
-            if (KV) vdst[i] = vsrc[i];
+    if (pl.exec == 2) {   // identity round standing for a copy: tile by tile, loads first
+        for (uint32_t t = blockIdx.x; (size_t)t * TILE < a.n; t += gridDim.x) {
+            K kk[ITEMS];
+            uint32_t vv[ITEMS];
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) {
+                const size_t i = (size_t)t * TILE + j * WG + tid;
+                kk[j] = i < a.n ? src[i] : K(0);
+                if (KV) vv[j] = i < a.n ? vsrc[i] : 0u;
+            }
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) {
+                const size_t i = (size_t)t * TILE + j * WG + tid;
+                if (i < a.n) {
+                    dst[i] = kk[j];
+                    if (KV) vdst[i] = vv[j];
+                }
+            }
         }
         return;
     }

@@ -176,7 +176,7 @@ hipError_t run(const void* keys_in, void* keys_out, const uint32_t* vals_in, uin
     hipLaunchKernelGGL(k_plan, dim3(1), dim3(64), 0, stream, (const uint32_t*)mixed, nr,
                        (uint32_t)begin_bit, (uint32_t)end_bit, (int)in_place, plan);
     if (in_place && (nr & 1)) {
-        uint32_t g = (uint32_t)std::min<size_t>((n + 255) / 256, 2048);
+        const uint32_t g = (uint32_t)((n + 256 * kPrecopyItems - 1) / (256 * kPrecopyItems));
         hipLaunchKernelGGL(k_precopy<K>, dim3(g), dim3(256), 0, stream, (const RoundPlan*)plan,
                            (const K*)keys_in, keys_tmp, KV ? vals_in : nullptr, vals_tmp, (uint32_t)n);
     }

@@ -356,11 +356,22 @@ __global__ __launch_bounds__(kGvrWG) void k_gvr_count(const uint32_t* __restrict
     __shared__ uint2 spl[kGvrMaxP];
     __shared__ uint2 wmm[kGvrWG / 64];
     __shared__ uint32_t h[R * 32];
-    __shared__ uint8_t tab[kGvrTab + 4];
+    __shared__ uint32_t tabw[(kGvrTab + 4) / 4];
+    uint8_t* tab = (uint8_t*)tabw;
     const uint32_t tid = threadIdx.x;
     for (uint32_t i = tid; i < R * 32 / 4; i += kGvrWG) ((uint4*)h)[i] = make_uint4(0, 0, 0, 0);
     if (tid + 1 < p) spl[tid] = make_uint2(Sk[(size_t)(tid + 1) * s - 1], Sg[(size_t)(tid + 1) * s - 1]);
-    for (uint32_t c = tid; c <= kGvrTab; c += kGvrWG) tab[c] = gtab[c];
+    {
+        // the table (4097 bytes, 4100 allocated) as words, all loads first
+        constexpr uint32_t W = (kGvrTab + 4) / 4, PER = (W + kGvrWG - 1) / kGvrWG;
+        const uint32_t* g4 = (const uint32_t*)gtab;
+        uint32_t t4[PER];
+#pragma unroll
+        for (uint32_t j = 0; j < PER; ++j) t4[j] = j * kGvrWG + tid < W ? g4[j * kGvrWG + tid] : 0u;
+#pragma unroll
+        for (uint32_t j = 0; j < PER; ++j)
+            if (j * kGvrWG + tid < W) tabw[j * kGvrWG + tid] = t4[j];
+    }
     const uint32_t t = xcd_tile(gridDim.x);
     const uint2 tr = gvr_tile(lo, tpb, t);
     const uint32_t base = tr.x, len = tr.y;
@@ -858,13 +869,32 @@ __global__ __launch_bounds__(256) void k_gsd_fine_split(const uint32_t* __restri
     const uint32_t* r = R + (size_t)k * (nch + 2);
     const uint32_t r0 = r[blockIdx.x], r1 = last ? M : r[blockIdx.x + 1];
     const uint32_t in0 = blockIdx.x == 0 ? r[nch] : 0u, in1 = last ? r[nch + 1] : M;
-    for (uint32_t i = tid; i < c1 - c0; i += 256) xs[i] = X[b + c0 + i];
+    // the chunk into LDS: all of a thread's loads issued before the first
+    // store (a loop of load -> store would wait out every load in turn)
+    {
+        constexpr int PER = kFineChunk / 256;
+        const uint32_t len = c1 - c0;
+        uint32_t v[PER];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const uint32_t i = j * 256 + tid;
+            v[j] = i < len ? X[b + c0 + i] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const uint32_t i = j * 256 + tid;
+            if (i < len) xs[i] = v[j];
+        }
+    }
     __syncthreads();
     const uint32_t i0 = max(r0, in0), i1 = max(i0, min(r1, in1));
     for (uint32_t i = r0 + tid; i < i0; i += 256) F[(size_t)k * (M + 2) + i + 1] = 0;
     for (uint32_t i = i1 + tid; i < r1; i += 256) F[(size_t)k * (M + 2) + i + 1] = nk;
+    // the next boundary is loaded while this one is searched
+    uint64_t next = i0 + tid < i1 ? BK[i0 + tid] : 0ull;
     for (uint32_t i = i0 + tid; i < i1; i += 256) {
-        const uint64_t bnd = BK[i];
+        const uint64_t bnd = next;
+        if (i + 256 < i1) next = BK[i + 256];
         uint32_t a = 0, e = c1 - c0;   // first q in the chunk with B < (X_q, index)
         while (a < e) {
             const uint32_t mid = (a + e) >> 1;
@@ -1142,7 +1172,17 @@ __global__ __launch_bounds__(kMergeWG) void k_gsd_merge_large(
         const uint32_t shift = 8u * d;
         dg.st[tid] = 0;
         __syncthreads();
-        for (uint32_t j = tid; j < L; j += kMergeWG) atomicAdd(&dg.st[digit_of(ck[j], shift, 0xFFu)], 1u);
+        for (uint32_t j0 = 0; j0 < L; j0 += kMergeWG * 16) {   // 16 loads in flight per thread
+            uint32_t x[16];
+#pragma unroll
+            for (uint32_t q = 0; q < 16; ++q) {
+                const uint32_t j = j0 + q * kMergeWG + tid;
+                x[q] = j < L ? ck[j] : 0u;
+            }
+#pragma unroll
+            for (uint32_t q = 0; q < 16; ++q)
+                if (j0 + q * kMergeWG + tid < L) atomicAdd(&dg.st[digit_of(x[q], shift, 0xFFu)], 1u);
+        }
         __syncthreads();
         const uint32_t cnt = dg.st[tid];
         if (__syncthreads_or(cnt == L)) continue;   // one byte value everywhere: nothing moves
@@ -1186,9 +1226,22 @@ __global__ __launch_bounds__(kMergeWG) void k_gsd_merge_large(
         if (KV) { t = cv; cv = ov; ov = t; }
     }
     if (ck != out + base) {
-        for (uint32_t j = tid; j < L; j += kMergeWG) {
-            out[base + j] = ck[j];
-            if (KV) vout[base + j] = cv[j];
+        for (uint32_t j0 = 0; j0 < L; j0 += kMergeWG * 8) {
+            uint32_t x[8], y[8];
+#pragma unroll
+            for (uint32_t q = 0; q < 8; ++q) {
+                const uint32_t j = j0 + q * kMergeWG + tid;
+                x[q] = j < L ? ck[j] : 0u;
+                y[q] = KV && j < L ? cv[j] : 0u;
+            }
+#pragma unroll
+            for (uint32_t q = 0; q < 8; ++q) {
+                const uint32_t j = j0 + q * kMergeWG + tid;
+                if (j < L) {
+                    out[base + j] = x[q];
+                    if (KV) vout[base + j] = y[q];
+                }
+            }
         }
     }
 }

@@ -71,24 +71,32 @@ __global__ __launch_bounds__(R) void k_segscan(RoundArgs a, const uint4* lsegs)
     const uint4 sg = lsegs[blockIdx.x];
     const uint32_t v = threadIdx.x;
     uint32_t* col = a.counts + v;
+    // the column in batches of B tiles, each batch's loads issued together
+    constexpr uint32_t B = 16;
     uint32_t total = 0;
-    uint32_t t = sg.x;
-    for (; t + 4 <= sg.y; t += 4) {
-        const uint32_t c0 = col[(size_t)t * R], c1 = col[(size_t)(t + 1) * R];
-        const uint32_t c2 = col[(size_t)(t + 2) * R], c3 = col[(size_t)(t + 3) * R];
-        total += c0 + c1 + c2 + c3;
+    for (uint32_t t = sg.x; t < sg.y; t += B) {
+        uint32_t c[B];
+#pragma unroll
+        for (uint32_t j = 0; j < B; ++j) c[j] = t + j < sg.y ? col[(size_t)(t + j) * R] : 0u;
+#pragma unroll
+        for (uint32_t j = 0; j < B; ++j) total += c[j];
     }
-    for (; t < sg.y; ++t) total += col[(size_t)t * R];
     const uint32_t lane = v & 63, wave = v >> 6;
     const uint32_t incl = wave_inclusive_sum(total);
     if (lane == 63) wsum[wave] = incl;
     __syncthreads();
     uint32_t run = sg.z + incl - total;
     for (uint32_t w = 0; w < wave; ++w) run += wsum[w];
-    for (t = sg.x; t < sg.y; ++t) {
-        const uint32_t c = col[(size_t)t * R];
-        col[(size_t)t * R] = run;
-        run += c;
+    for (uint32_t t = sg.x; t < sg.y; t += B) {
+        uint32_t c[B];
+#pragma unroll
+        for (uint32_t j = 0; j < B; ++j) c[j] = t + j < sg.y ? col[(size_t)(t + j) * R] : 0u;
+#pragma unroll
+        for (uint32_t j = 0; j < B; ++j)
+            if (t + j < sg.y) {
+                col[(size_t)(t + j) * R] = run;
+                run += c[j];
+            }
     }
 }
 
