@@ -29,13 +29,23 @@ __device__ __forceinline__ U from_ordered(U y, int kind)
     return (y & sign) ? U(y ^ sign) : U(~y);
 }
 
+constexpr int kMapItems = 8;
+
 template <typename U, bool INVERSE>
 __global__ void k_map_keys(const U* __restrict__ in, U* out, size_t n, int kind)
 {
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const U x = in[i];
-        out[i] = INVERSE ? from_ordered<U>(x, kind) : to_ordered<U>(x, kind);
+    // kMapItems keys per thread, all loaded before the first store
+    const size_t base = (size_t)blockIdx.x * blockDim.x * kMapItems + threadIdx.x;
+    U x[kMapItems];
+#pragma unroll
+    for (int j = 0; j < kMapItems; ++j) {
+        const size_t i = base + (size_t)j * blockDim.x;
+        x[j] = i < n ? in[i] : U(0);
+    }
+#pragma unroll
+    for (int j = 0; j < kMapItems; ++j) {
+        const size_t i = base + (size_t)j * blockDim.x;
+        if (i < n) out[i] = INVERSE ? from_ordered<U>(x[j], kind) : to_ordered<U>(x[j], kind);
     }
 }
 
@@ -45,7 +55,7 @@ hipError_t map_keys(int key_bytes, int kind, bool inverse, const void* in, void*
                     hipStream_t stream)
 {
     if (!n) return hipSuccess;
-    const dim3 grid((uint32_t)std::min<size_t>(16384, (n + 255) / 256)), block(256);
+    const dim3 grid((uint32_t)((n + 256 * kMapItems - 1) / (256 * kMapItems))), block(256);
     if (key_bytes == 4) {
         if (inverse)
             hipLaunchKernelGGL((k_map_keys<uint32_t, true>), grid, block, 0, stream,
