@@ -256,7 +256,15 @@ __global__ __launch_bounds__(kRouteWG) void k_gsd_route(const uint32_t* __restri
         sd[j - j0] = boff[j] + off[(size_t)k * p + j] - row[j];
     __syncthreads();
     const uint32_t nr = j1 - j0 + 1;
-#pragma unroll 4
+    // the tile's keys (and payloads) loaded together, then each routed
+    uint32_t kx[kRouteItems], vx[KV ? kRouteItems : 1];
+#pragma unroll
+    for (uint32_t i = 0; i < kRouteItems; ++i) {
+        const uint32_t u = u0 + i * kRouteWG + threadIdx.x;
+        kx[i] = u < u1 ? X[b + u] : 0u;
+        if (KV) vx[i] = u < u1 ? XV[b + u] : 0u;
+    }
+#pragma unroll
     for (uint32_t i = 0; i < kRouteItems; ++i) {
         const uint32_t u = u0 + i * kRouteWG + threadIdx.x;
         if (u >= u1) break;
@@ -267,8 +275,8 @@ __global__ __launch_bounds__(kRouteWG) void k_gsd_route(const uint32_t* __restri
         }
         const uint32_t d = sd[a] + u;
         if (d < n) {   // always true when the split is consistent
-            Y[d] = X[b + u];
-            if (KV) YV[d] = XV[b + u];
+            Y[d] = kx[i];
+            if (KV) YV[d] = vx[i];
         }
     }
 }

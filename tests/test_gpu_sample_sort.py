@@ -87,6 +87,16 @@ def test_shapes(rs, n, p, r):
     run_case(rs, keys, p, r)
 
 
+@pytest.mark.parametrize("dist", ["uniform", "zipf", "equal"])
+def test_route_path_p512(rs, dist):
+    """p = 512 > 256 takes the route + bucket re-sort finish instead of the
+    merge: blocks of ~8192 keys, two route tiles each (the last ragged)."""
+    n = (1 << 22) + 5
+    announce("gsd route p512", dist, n)
+    run_case(rs, keygen.kv_keys(dist, n), 512, 8)
+    run_case(rs, keygen.kv_keys(dist, n), 512, 8, with_vals=False)
+
+
 @pytest.mark.parametrize("dist", ["uniform", "zipf", "equal", "presorted"])
 @pytest.mark.parametrize("n,p,r", [((1 << 22) + 5, 64, 4), (1 << 21, 16, 2)])
 def test_merge_pieces_beyond_lds(rs, dist, n, p, r):
