@@ -1269,28 +1269,41 @@ GsdLayout skeleton_layout(bool has_vals, size_t n, uint32_t p, uint32_t s, size_
     L.LT = lsd_r8_layout(4, true, L.nT, 0, 32);
     L.LTk = lsd_r8_layout(4, false, L.nT, 0, 32);
     L.LS = devseg_layout(4, has_vals, n, p);
+    // the merge finish (GSD, GER with p <= 256) cuts its pieces at a sorted
+    // regular sample of the sorted blocks: GSD's own, or for GER a second one
+    // of about one element per 128 block keys (its random sample gives
+    // unevenly sized pieces; the splitters and statistics stay GER's)
+    L.s2 = s;
+    L.nT2 = L.nT;
+    if (kind == kGER && n) {
+        L.s2 = (uint32_t)std::min<size_t>(8192, std::max<size_t>(1, (n / p + 127) / 128));
+        L.nT2 = (size_t)p * L.s2;
+    }
+    L.LT2 = lsd_r8_layout(4, true, L.nT2, 0, 32);
+    const size_t nTmax = std::max(L.nT, L.nT2);
     size_t o = 0;
     L.off_lo = o;    o = align_up(o + (size_t)(p + 1) * 4);
     L.off_boff = o;  o = align_up(o + (size_t)(p + 1) * 4);
     L.off_bsize = o; o = align_up(o + (size_t)p * 4);
     L.off_coloff = o; o = align_up(o + (size_t)p * p * 4);
-    L.off_Tk = o;    o = align_up(o + L.nT * 4);
-    L.off_Tg = o;    o = align_up(o + L.nT * 4);
-    L.off_Sk = o;    o = align_up(o + L.nT * 4);
-    L.off_Sg = o;    o = align_up(o + L.nT * 4);
-    L.off_lsd = o;   o = align_up(o + std::max(L.LT.bytes, L.LTk.bytes));
+    L.off_Tk = o;    o = align_up(o + nTmax * 4);
+    L.off_Tg = o;    o = align_up(o + nTmax * 4);
+    L.off_Sk = o;    o = align_up(o + nTmax * 4);
+    L.off_Sg = o;    o = align_up(o + nTmax * 4);
+    L.off_lsd = o;   o = align_up(o + std::max(std::max(L.LT.bytes, L.LTk.bytes), L.LT2.bytes));
     L.off_Y = o;     o = align_up(o + n * 4);
     L.off_YV = o;    o = align_up(o + (has_vals ? n * 4 : 0));
     L.off_seg = o;   o = align_up(o + L.LS.bytes);
-    if ((kind == kGSD || kind == kGER) && p <= kMergeMaxP && L.nT && n <= L.nT * 4096) {
-        // the merge finish: g = the largest divisor of s with average piece
-        // g n / nT at most 2048 (at least 1) and at least one boundary (g <= nT)
+    if ((kind == kGSD || kind == kGER) && p <= kMergeMaxP && L.nT2 && n <= L.nT2 * 4096) {
+        // the merge finish: g = the largest divisor of s2 with average piece
+        // g n / nT2 at most 2048 (at least 1) and at least one boundary (g <= nT2)
         L.merge = true;
-        const uint64_t want = std::max<uint64_t>(1, (uint64_t)2048 * L.nT / n);
-        uint32_t g = (uint32_t)std::min<uint64_t>(std::min<uint64_t>(want, s), L.nT);
-        while (s % g) --g;
+        const uint32_t s2 = L.s2;
+        const uint64_t want = std::max<uint64_t>(1, (uint64_t)2048 * L.nT2 / n);
+        uint32_t g = (uint32_t)std::min<uint64_t>(std::min<uint64_t>(want, s2), L.nT2);
+        while (s2 % g) --g;
         L.g = g;
-        L.M = (uint32_t)(L.nT / g);
+        L.M = (uint32_t)(L.nT2 / g);
         L.off_F = o;       o = align_up(o + ((size_t)L.M + 2) * p * 4);
         L.off_BK = o;      o = align_up(o + (size_t)L.M * 8);
         L.off_large = o;   o = align_up(o + ((size_t)L.M + 2) * 4);
@@ -1442,14 +1455,20 @@ hipError_t gsd_merge_sort(const uint32_t* keys_in, uint32_t* keys_out, const uin
                                L.LS, dev_err, stream, prof);
     if (e != hipSuccess) return e;
     // 2-3. the sample of the sorted blocks, sorted by composite
-    if (L.kind == kGSD) {
-        hipLaunchKernelGGL(k_gsd_sample, dim3((uint32_t)((L.nT + 255) / 256)), dim3(256), 0, stream,
-                           Y, lo, p, s, Tk, Tg);
-        e = lsd_r8_sort(4, Tk, Sk, Tg, Sg, L.nT, 0, 32, w + L.off_lsd, L.LT, dev_err, stream,
-                        nullptr);
-    } else {
+    if (L.kind == kGER) {
+        // GER: the random sample gives the splitters, and the split bounds of
+        // the statistics come from them by binary search in the sorted
+        // blocks; the merge's boundaries come from a regular sample (below)
         e = random_sample(Y, n, L, seed, w, Tk, Tg, Sk, Sg, dev_err, stream);
+        if (e != hipSuccess) return e;
+        const uint32_t nb = p * (p + 1);
+        hipLaunchKernelGGL(k_gsd_split, dim3((nb + 255) / 256), dim3(256), 0, stream, Y, lo, p, s,
+                           Sk, Sg, bnd, split_key, split_g);
     }
+    hipLaunchKernelGGL(k_gsd_sample, dim3((uint32_t)((L.nT2 + 255) / 256)), dim3(256), 0, stream,
+                       Y, lo, p, L.s2, Tk, Tg);
+    e = lsd_r8_sort(4, Tk, Sk, Tg, Sg, L.nT2, 0, 32, w + L.off_lsd, L.LT2, dev_err, stream,
+                    nullptr);
     if (e != hipSuccess) return e;
     // 4. splitters, the fine split, the buckets' split bounds
     uint64_t* BK = (uint64_t*)(w + L.off_BK);
@@ -1461,9 +1480,11 @@ hipError_t gsd_merge_sort(const uint32_t* keys_in, uint32_t* keys_out, const uin
                        chunks, BK, R);
     hipLaunchKernelGGL(k_gsd_fine_split, dim3(chunks, p), dim3(256), 0, stream, Y, lo, p, M, chunks,
                        BK, R, F);
-    const uint32_t nb = p * (p + 1);
-    hipLaunchKernelGGL(k_gsd_fine_bnd, dim3((nb + 255) / 256), dim3(256), 0, stream, F, p, s, g, M,
-                       Sk, Sg, bnd, split_key, split_g);
+    if (L.kind == kGSD) {   // the splitters are boundaries B_{i s / g}
+        const uint32_t nb = p * (p + 1);
+        hipLaunchKernelGGL(k_gsd_fine_bnd, dim3((nb + 255) / 256), dim3(256), 0, stream, F, p, s, g,
+                           M, Sk, Sg, bnd, split_key, split_g);
+    }
     // 5. merge every piece into the output
     uint32_t* large = (uint32_t*)(w + L.off_large);
     const uint32_t max_large = M + 1;
