@@ -69,6 +69,28 @@ __global__ void k_gsd_blocks(uint32_t* lo, uint32_t n, uint32_t p)
 }
 
 // Regular sample of the sorted blocks: element t = k s + j - 1.
+// The merge's boundary sample: s per block as well, but block k's j-th
+// element at position floor((j p - k - 1) N_k / (s p)), j = 1..s, i.e. the
+// regular positions shifted back by (k + 1) / p of a sample interval.  With
+// unshifted positions the j-th elements of all blocks sit at the same rank in
+// their blocks and, for blocks of similar keys, cluster in value near both
+// ends of the key range, leaving pieces of many block keys between clusters;
+// shifted, they spread over the interval.  Written in block order, positions
+// increasing, so a stable sort by key orders the composites.
+__global__ void k_merge_sample(const uint32_t* __restrict__ X, const uint32_t* lo, uint32_t p,
+                               uint32_t s, uint32_t* Tk, uint32_t* Tg)
+{
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (size_t)p * s) return;
+    const uint32_t k = (uint32_t)(t / s);
+    const uint64_t j = t - (size_t)k * s + 1;
+    const uint32_t b = lo[k];
+    const uint64_t nk = lo[k + 1] - b;
+    const uint32_t q = (uint32_t)(((j * p - k - 1) * nk) / ((uint64_t)s * p));
+    Tk[t] = X[b + q];
+    Tg[t] = b + q;
+}
+
 __global__ void k_gsd_sample(const uint32_t* __restrict__ X, const uint32_t* lo, uint32_t p,
                              uint32_t s, uint32_t* Tk, uint32_t* Tg)
 {
@@ -781,16 +803,20 @@ __global__ __launch_bounds__(kUnshiftWG) void k_gvr_unshift(uint32_t* keys_out, 
 
 
 // ---------------------------------------------------------------------------
-// GSD step 5 as a merge of the p sorted runs of every bucket.  The sorted
-// regular sample gives finer boundaries B_m = T[m g - 1], m = 1..M (M = p s /
-// g; g divides s, so the splitters S_i = B_{i s / g} are among them).  Piece m
-// (m = 0..M) holds the elements whose composite lies in (B_m, B_{m+1}]
-// (B_0 = -inf, B_{M+1} = +inf): from every sorted block k the positions
-// [F[k][m], F[k][m+1]), F[k][m] = #{q in block k : (X_q, index) <= B_m}.  The
-// pieces cover the output in order, piece m from sum_k F[k][m] on, and a
-// piece is the merge of its p sorted sub-runs.  By Lemma 1's argument a piece
-// holds at most (g + p - 1) x keys (x = block keys per sample); g is chosen so
-// that the average is about 2048.
+// GSD step 5 as a merge of the p sorted runs of every bucket (also GER's).
+// A sorted sample T of the sorted blocks gives boundaries B_m = T[m g - 1],
+// m = 1..M (M = |T| / g): GSD's own regular sample, with g dividing s so that
+// its splitters S_i = B_{i s / g} are among them; for GER the boundary sample
+// of k_merge_sample (its own random sample gives unevenly sized pieces).
+// Piece m (m = 0..M)
+// holds the elements whose composite lies in (B_m, B_{m+1}] (B_0 = -inf,
+// B_{M+1} = +inf): from every sorted block k the positions [F[k][m],
+// F[k][m+1]), F[k][m] = #{q in block k : (X_q, index) <= B_m}.  The pieces
+// cover the output in order, piece m from sum_k F[k][m] on, and a piece is the
+// merge of its p sorted sub-runs; the buckets are unions of consecutive
+// pieces' sub-runs, so merging piece by piece merges every bucket.  By Lemma
+// 1's argument a piece holds at most (g + p - 1) x keys (x = block keys per
+// sample); g is chosen so that the average is about 2048.
 constexpr uint32_t kMergeWG = 256;
 constexpr int kMergeItems = 16;
 constexpr uint32_t kMergeCap = kMergeWG * kMergeItems;   // piece merged whole in LDS
@@ -912,8 +938,8 @@ __global__ __launch_bounds__(256) void k_gsd_fine_split(const uint32_t* __restri
     }
 }
 
-// Split bounds of the p buckets (bnd[k][i] = F[k][i s / g]) and the splitters,
-// for the statistics.
+// GSD: split bounds of the p buckets (bnd[k][i] = F[k][i s / g]: the
+// splitters are boundaries) and the splitters, for the statistics.
 __global__ void k_gsd_fine_bnd(const uint32_t* F, uint32_t p, uint32_t s, uint32_t g, uint32_t M,
                                const uint32_t* Sk, const uint32_t* Sg, uint32_t* bnd,
                                uint32_t* split_key, uint32_t* split_g)
@@ -1270,9 +1296,9 @@ GsdLayout skeleton_layout(bool has_vals, size_t n, uint32_t p, uint32_t s, size_
     L.LTk = lsd_r8_layout(4, false, L.nT, 0, 32);
     L.LS = devseg_layout(4, has_vals, n, p);
     // the merge finish (GSD, GER with p <= 256) cuts its pieces at a sorted
-    // regular sample of the sorted blocks: GSD's own, or for GER a second one
-    // of about one element per 128 block keys (its random sample gives
-    // unevenly sized pieces; the splitters and statistics stay GER's)
+    // sample of the sorted blocks: GSD's own; for GER a boundary sample
+    // (k_merge_sample) of about one element per 128 block keys, its
+    // splitters and statistics staying those of its random sample
     L.s2 = s;
     L.nT2 = L.nT;
     if (kind == kGER && n) {
@@ -1295,13 +1321,16 @@ GsdLayout skeleton_layout(bool has_vals, size_t n, uint32_t p, uint32_t s, size_
     L.off_YV = o;    o = align_up(o + (has_vals ? n * 4 : 0));
     L.off_seg = o;   o = align_up(o + L.LS.bytes);
     if ((kind == kGSD || kind == kGER) && p <= kMergeMaxP && L.nT2 && n <= L.nT2 * 4096) {
-        // the merge finish: g = the largest divisor of s2 with average piece
-        // g n / nT2 at most 2048 (at least 1) and at least one boundary (g <= nT2)
+        // the merge finish: every g-th sample element, g n / nT2 at most about
+        // 2048 keys per piece (g >= 1), at least one boundary (g <= nT2), and
+        // for GSD g dividing s
         L.merge = true;
-        const uint32_t s2 = L.s2;
         const uint64_t want = std::max<uint64_t>(1, (uint64_t)2048 * L.nT2 / n);
-        uint32_t g = (uint32_t)std::min<uint64_t>(std::min<uint64_t>(want, s2), L.nT2);
-        while (s2 % g) --g;
+        uint32_t g = (uint32_t)std::min<uint64_t>(want, L.nT2);
+        if (kind == kGSD) {
+            g = std::min(g, s);
+            while (s % g) --g;
+        }
         L.g = g;
         L.M = (uint32_t)(L.nT2 / g);
         L.off_F = o;       o = align_up(o + ((size_t)L.M + 2) * p * 4);
@@ -1455,20 +1484,25 @@ hipError_t gsd_merge_sort(const uint32_t* keys_in, uint32_t* keys_out, const uin
                                L.LS, dev_err, stream, prof);
     if (e != hipSuccess) return e;
     // 2-3. the sample of the sorted blocks, sorted by composite
-    if (L.kind == kGER) {
-        // GER: the random sample gives the splitters, and the split bounds of
-        // the statistics come from them by binary search in the sorted
-        // blocks; the merge's boundaries come from a regular sample (below)
+    const uint32_t nb = p * (p + 1);
+    if (L.kind == kGSD) {
+        hipLaunchKernelGGL(k_gsd_sample, dim3((uint32_t)((L.nT + 255) / 256)), dim3(256), 0, stream,
+                           Y, lo, p, s, Tk, Tg);
+        e = lsd_r8_sort(4, Tk, Sk, Tg, Sg, L.nT, 0, 32, w + L.off_lsd, L.LT, dev_err, stream,
+                        nullptr);
+    } else {
+        // GER: the random sample's splitters and the split bounds of the
+        // statistics (binary search of each splitter in each sorted block),
+        // then the boundary sample for the merge in the same buffers
         e = random_sample(Y, n, L, seed, w, Tk, Tg, Sk, Sg, dev_err, stream);
         if (e != hipSuccess) return e;
-        const uint32_t nb = p * (p + 1);
         hipLaunchKernelGGL(k_gsd_split, dim3((nb + 255) / 256), dim3(256), 0, stream, Y, lo, p, s,
                            Sk, Sg, bnd, split_key, split_g);
+        hipLaunchKernelGGL(k_merge_sample, dim3((uint32_t)((L.nT2 + 255) / 256)), dim3(256), 0,
+                           stream, Y, lo, p, L.s2, Tk, Tg);
+        e = lsd_r8_sort(4, Tk, Sk, Tg, Sg, L.nT2, 0, 32, w + L.off_lsd, L.LT2, dev_err, stream,
+                        nullptr);
     }
-    hipLaunchKernelGGL(k_gsd_sample, dim3((uint32_t)((L.nT2 + 255) / 256)), dim3(256), 0, stream,
-                       Y, lo, p, L.s2, Tk, Tg);
-    e = lsd_r8_sort(4, Tk, Sk, Tg, Sg, L.nT2, 0, 32, w + L.off_lsd, L.LT2, dev_err, stream,
-                    nullptr);
     if (e != hipSuccess) return e;
     // 4. splitters, the fine split, the buckets' split bounds
     uint64_t* BK = (uint64_t*)(w + L.off_BK);
@@ -1480,11 +1514,9 @@ hipError_t gsd_merge_sort(const uint32_t* keys_in, uint32_t* keys_out, const uin
                        chunks, BK, R);
     hipLaunchKernelGGL(k_gsd_fine_split, dim3(chunks, p), dim3(256), 0, stream, Y, lo, p, M, chunks,
                        BK, R, F);
-    if (L.kind == kGSD) {   // the splitters are boundaries B_{i s / g}
-        const uint32_t nb = p * (p + 1);
+    if (L.kind == kGSD)
         hipLaunchKernelGGL(k_gsd_fine_bnd, dim3((nb + 255) / 256), dim3(256), 0, stream, F, p, s, g,
                            M, Sk, Sg, bnd, split_key, split_g);
-    }
     // 5. merge every piece into the output
     uint32_t* large = (uint32_t*)(w + L.off_large);
     const uint32_t max_large = M + 1;
