@@ -583,7 +583,9 @@ __global__ __launch_bounds__(R) void k_tilescan(RoundArgs a)
 //          write the slot back as {no lanes, count + lanes in the set};
 //   bases  digit thread v turns the counts of all half-waves into slot bases
 //          inside the tile (prefix over half-waves plus the tile's prefix over
-//          digits), written over the counts;
+//          digits), written over the counts (keys only: the counts are first
+//          added up in a separate array of 4-byte words, which spreads those
+//          additions over all 64 LDS banks);
 //   stage  each key goes to LDS at base + rank, the tile now in digit order;
 //   scatter consecutive threads write consecutive slots of a digit's run; the
 //          payloads follow in a second staging pass through the same LDS.
@@ -594,12 +596,20 @@ __global__ __launch_bounds__(WG, !KV ? RSORT_R8_WAVES_PER_EU : sizeof(K) == 4 ? 
     constexpr int NG = WG / G;                  // ranking groups
     constexpr uint32_t TILE = (uint32_t)WG * ITEMS;
     constexpr bool rank_first = RSORT_RANK_FIRST < 0 ? KV : RSORT_RANK_FIRST != 0;
+    // LDS banks: a slot {lane set, count} is 8 bytes, so one word kind of all
+    // slots sits in half of the 64 banks.  Counting first adds into a separate
+    // array of 4-byte counts instead (all banks); ranking first (with
+    // payloads), odd groups keep {count, lane set}, so the two groups of a
+    // wave OR their lane bits into different banks.
+    constexpr bool split_counts = G == 32 && !rank_first;
+    constexpr bool swap_words = G == 32 && rank_first;
     static_assert(G == 16 || G == 32, "ranking groups of 16 or 32 lanes");
     static_assert(G == 32 || (uint64_t)TILE < 65536, "16-bit slot counts");
     static_assert(TILE * sizeof(K) >= NG * R * (G == 32 ? 8 : 4), "staging must cover the slots");
     struct Smem {
         union {
             uint2 slot[NG][R];           // 32-lane groups: {lane set, count}, then {-, slot base}
+            uint32_t words[2 * NG * R];  // count first: counts at words[NG R + g R + d]
             uint32_t slot16[NG][R];      // 16-lane groups: count << 16 | lane set
             K keys[TILE];                // staging: the tile in digit order
             uint32_t vals[TILE];         // staging of the payloads (second pass)
@@ -686,6 +696,7 @@ __global__ __launch_bounds__(WG, !KV ? RSORT_R8_WAVES_PER_EU : sizeof(K) == 4 ? 
             if constexpr (G == 32) {
                 uint2* sl = sm.u.slot[grp];
                 const uint32_t lowsel = lane < 32 ? ~0u : 0u;
+                const uint32_t cs = swap_words && (grp & 1) ? 0u : 32u;   // bit offset of the count
 #pragma unroll
                 for (int i = 0; i < ITEMS; ++i) {
                     const bool ok = hofs + i * G < lim;
@@ -693,23 +704,23 @@ __global__ __launch_bounds__(WG, !KV ? RSORT_R8_WAVES_PER_EU : sizeof(K) == 4 ? 
                     if (wave_one_digit(ok, d)) {
                         // every lane of the wave holds this digit: no lane
                         // set to build, one lane per group moves the count
-                        const uint32_t c = (uint32_t)(__hip_atomic_load((uint64_t*)&sl[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >> 32);
+                        const uint32_t c = (uint32_t)(__hip_atomic_load((uint64_t*)&sl[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >> cs);
                         pos[i] = c + gl;
                         wave_lds_order();
                         if (gl == 0)
-                            __hip_atomic_store((uint64_t*)&sl[d], (uint64_t)(c + 32) << 32,
+                            __hip_atomic_store((uint64_t*)&sl[d], (uint64_t)(c + 32) << cs,
                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                         wave_lds_order();
                         continue;
                     }
-                    if (ok) __hip_atomic_fetch_or(&sl[d].x, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    if (ok) __hip_atomic_fetch_or(cs ? &sl[d].x : &sl[d].y, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                     wave_lds_order();
                     const uint64_t s = ok ? __hip_atomic_load((uint64_t*)&sl[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : 0ull;
-                    const uint32_t m = (uint32_t)s, c = (uint32_t)(s >> 32);
+                    const uint32_t m = (uint32_t)(s >> (32u - cs)), c = (uint32_t)(s >> cs);
                     pos[i] = __builtin_amdgcn_mbcnt_hi(m, __builtin_amdgcn_mbcnt_lo(m & lowsel, c));
                     wave_lds_order();
                     if (ok)
-                        __hip_atomic_store((uint64_t*)&sl[d], (uint64_t)(c + __builtin_popcount(m)) << 32,
+                        __hip_atomic_store((uint64_t*)&sl[d], (uint64_t)(c + __builtin_popcount(m)) << cs,
                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                     wave_lds_order();
                 }
@@ -734,11 +745,14 @@ __global__ __launch_bounds__(WG, !KV ? RSORT_R8_WAVES_PER_EU : sizeof(K) == 4 ? 
             }
         };
         auto slot_count = [&](int g, uint32_t v) -> uint32_t {
-            if constexpr (G == 32) return sm.u.slot[g][v].y;
+            if constexpr (G == 32) return swap_words && (g & 1) ? sm.u.slot[g][v].x : sm.u.slot[g][v].y;
             else return sm.u.slot16[g][v] >> 16;
         };
         auto set_slot_count = [&](int g, uint32_t v, uint32_t c) {
-            if constexpr (G == 32) sm.u.slot[g][v].y = c;
+            if constexpr (G == 32) {
+                if (swap_words && (g & 1)) sm.u.slot[g][v].x = c;
+                else sm.u.slot[g][v].y = c;
+            }
             else sm.u.slot16[g][v] = c << 16;
         };
 
@@ -752,11 +766,11 @@ __global__ __launch_bounds__(WG, !KV ? RSORT_R8_WAVES_PER_EU : sizeof(K) == 4 ? 
                 const bool ok = hofs + i * G < lim;
                 const uint32_t d = digit_of(k[i], a.shift, a.mask);
                 if (G == 32 && wave_one_digit(ok, d)) {   // one add per group
-                    if (gl == 0) atomicAdd(&sm.u.slot[grp][d].y, 32u);
+                    if (gl == 0) atomicAdd(&sm.u.words[NG * R + grp * R + d], 32u);
                     continue;
                 }
                 if (ok) {
-                    if constexpr (G == 32) atomicAdd(&sm.u.slot[grp][d].y, 1u);
+                    if constexpr (G == 32) atomicAdd(&sm.u.words[NG * R + grp * R + d], 1u);
                     else atomicAdd(&sm.u.slot16[grp][d], 1u << 16);
                 }
             }
@@ -765,17 +779,45 @@ __global__ __launch_bounds__(WG, !KV ? RSORT_R8_WAVES_PER_EU : sizeof(K) == 4 ? 
         __syncthreads();
 
         // bases
+        auto count_of = [&](int g, uint32_t v) -> uint32_t {
+            if constexpr (split_counts) return sm.u.words[NG * R + g * R + v];
+            else return slot_count(g, v);
+        };
         uint32_t run = 0;
         if (tid < R) {
             uint32_t total = 0;
 #pragma unroll
-            for (int g = 0; g < NG; ++g) total += slot_count(g, tid);
+            for (int g = 0; g < NG; ++g) total += count_of(g, tid);
             const uint32_t incl = wave_inclusive_sum(total);
             if (lane == 63) sm.wsum[wave] = incl;
             run = incl - total;
         }
         __syncthreads();
-        if (tid < R) {
+        if constexpr (split_counts) {
+            // slots of groups < NG/2 lie below the counts; the others overlap
+            // them, so their counts are read before any of them is written
+            uint32_t hi[NG / 2];
+            if (tid < R) {
+                for (uint32_t w = 0; w < wave; ++w) run += sm.wsum[w];
+                sm.goff[tid] = toff - run;
+#pragma unroll
+                for (int g = 0; g < NG / 2; ++g) {
+                    const uint32_t c = count_of(g, tid);
+                    sm.u.slot[g][tid] = make_uint2(0u, run);
+                    run += c;
+                }
+#pragma unroll
+                for (int g = NG / 2; g < NG; ++g) hi[g - NG / 2] = count_of(g, tid);
+            }
+            __syncthreads();
+            if (tid < R) {
+#pragma unroll
+                for (int g = NG / 2; g < NG; ++g) {
+                    sm.u.slot[g][tid] = make_uint2(0u, run);
+                    run += hi[g - NG / 2];
+                }
+            }
+        } else if (tid < R) {
             for (uint32_t w = 0; w < wave; ++w) run += sm.wsum[w];
             sm.goff[tid] = toff - run;
 #pragma unroll
