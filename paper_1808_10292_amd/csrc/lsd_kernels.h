@@ -575,8 +575,9 @@ __global__ __launch_bounds__(R) void k_tilescan(RoundArgs a)
 // h*ITEMS*32 + i*32 + (l & 31), so "earlier in the input" is lexicographic
 // (h, i, l) -- the order the ranking preserves.
 // Each half-wave has one 64-bit slot per digit value: the set of its lanes
-// holding that digit in the current row (low word) and the number of its keys
-// of that digit in earlier rows (high word).
+// holding that digit in the current row and the number of its keys of that
+// digit in earlier rows (low and high word below digit 128, swapped above, so
+// that each word kind spreads over all LDS banks).
 //   rank   row by row, lanes OR their bit into the slot of their digit, read
 //          the slot back -- the lanes below with the same digit plus the count
 //          give the key's rank among the half-wave's keys of that digit -- and
@@ -596,19 +597,19 @@ __global__ __launch_bounds__(WG, !KV ? RSORT_R8_WAVES_PER_EU : sizeof(K) == 4 ? 
     constexpr int NG = WG / G;                  // ranking groups
     constexpr uint32_t TILE = (uint32_t)WG * ITEMS;
     constexpr bool rank_first = RSORT_RANK_FIRST < 0 ? KV : RSORT_RANK_FIRST != 0;
-    // LDS banks: a slot {lane set, count} is 8 bytes, so one word kind of all
-    // slots sits in half of the 64 banks.  Counting first adds into a separate
-    // array of 4-byte counts instead (all banks); ranking first (with
-    // payloads), odd groups keep {count, lane set}, so the two groups of a
-    // wave OR their lane bits into different banks.
+    // LDS banks: a slot is 8 bytes, so one word of every slot would sit in
+    // half of the 64 banks.  Slots of digits below 128 hold {lane set,
+    // count}, those of digits from 128 on {count, lane set}, so the lane-set
+    // ORs of a half-wave spread over all banks; counting first adds into a
+    // separate array of 4-byte counts (all banks as well).
     constexpr bool split_counts = G == 32 && !rank_first;
-    constexpr bool swap_words = G == 32 && rank_first;
     static_assert(G == 16 || G == 32, "ranking groups of 16 or 32 lanes");
     static_assert(G == 32 || (uint64_t)TILE < 65536, "16-bit slot counts");
     static_assert(TILE * sizeof(K) >= NG * R * (G == 32 ? 8 : 4), "staging must cover the slots");
     struct Smem {
         union {
             uint2 slot[NG][R];           // 32-lane groups: {lane set, count}, then {-, slot base}
+                                         // (the two words swapped for digits >= 128)
             uint32_t words[2 * NG * R];  // count first: counts at words[NG R + g R + d]
             uint32_t slot16[NG][R];      // 16-lane groups: count << 16 | lane set
             K keys[TILE];                // staging: the tile in digit order
@@ -696,11 +697,11 @@ __global__ __launch_bounds__(WG, !KV ? RSORT_R8_WAVES_PER_EU : sizeof(K) == 4 ? 
             if constexpr (G == 32) {
                 uint2* sl = sm.u.slot[grp];
                 const uint32_t lowsel = lane < 32 ? ~0u : 0u;
-                const uint32_t cs = swap_words && (grp & 1) ? 0u : 32u;   // bit offset of the count
 #pragma unroll
                 for (int i = 0; i < ITEMS; ++i) {
                     const bool ok = hofs + i * G < lim;
                     const uint32_t d = digit_of(k[i], a.shift, a.mask);
+                    const uint32_t cs = (d & 128u) ? 0u : 32u;   // bit offset of the count
                     if (wave_one_digit(ok, d)) {
                         // every lane of the wave holds this digit: no lane
                         // set to build, one lane per group moves the count
@@ -745,12 +746,12 @@ __global__ __launch_bounds__(WG, !KV ? RSORT_R8_WAVES_PER_EU : sizeof(K) == 4 ? 
             }
         };
         auto slot_count = [&](int g, uint32_t v) -> uint32_t {
-            if constexpr (G == 32) return swap_words && (g & 1) ? sm.u.slot[g][v].x : sm.u.slot[g][v].y;
+            if constexpr (G == 32) return (v & 128u) ? sm.u.slot[g][v].x : sm.u.slot[g][v].y;
             else return sm.u.slot16[g][v] >> 16;
         };
         auto set_slot_count = [&](int g, uint32_t v, uint32_t c) {
             if constexpr (G == 32) {
-                if (swap_words && (g & 1)) sm.u.slot[g][v].x = c;
+                if (v & 128u) sm.u.slot[g][v].x = c;
                 else sm.u.slot[g][v].y = c;
             }
             else sm.u.slot16[g][v] = c << 16;
@@ -803,7 +804,7 @@ __global__ __launch_bounds__(WG, !KV ? RSORT_R8_WAVES_PER_EU : sizeof(K) == 4 ? 
 #pragma unroll
                 for (int g = 0; g < NG / 2; ++g) {
                     const uint32_t c = count_of(g, tid);
-                    sm.u.slot[g][tid] = make_uint2(0u, run);
+                    sm.u.slot[g][tid] = (tid & 128u) ? make_uint2(run, 0u) : make_uint2(0u, run);
                     run += c;
                 }
 #pragma unroll
@@ -813,7 +814,7 @@ __global__ __launch_bounds__(WG, !KV ? RSORT_R8_WAVES_PER_EU : sizeof(K) == 4 ? 
             if (tid < R) {
 #pragma unroll
                 for (int g = NG / 2; g < NG; ++g) {
-                    sm.u.slot[g][tid] = make_uint2(0u, run);
+                    sm.u.slot[g][tid] = (tid & 128u) ? make_uint2(run, 0u) : make_uint2(0u, run);
                     run += hi[g - NG / 2];
                 }
             }
