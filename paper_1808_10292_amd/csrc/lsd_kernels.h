@@ -295,14 +295,28 @@ __device__ __forceinline__ uint32_t block256_inclusive_sum(uint32_t x, uint32_t*
     return pre + incl;
 }
 
-// The round plan.  mixed[0..1] = OR over all keys of (key XOR first key) (low
-// and high 32 bits): a round is the identity -- one digit value holds every
+// Round 0's count ORs every key's difference from the first key into one of
+// kMixSlots pairs of words (low and high 32 bits), each pair in a cache line
+// of its own, picked by workgroup index, so that the atomics of the first
+// workgroups to finish do not all queue on one line.
+constexpr uint32_t kMixSlots = 64;
+constexpr uint32_t kMixStride = 32;   // words between pairs (128 bytes)
+constexpr uint32_t kMixWords = kMixSlots * kMixStride;
+
+// The round plan.  The OR of the kMixSlots pairs is the OR over all keys of
+// (key XOR first key): a round is the identity -- one digit value holds every
 // key -- exactly when its digit's bits are zero there.
 __global__ void k_plan(const uint32_t* mixed, uint32_t nrounds, uint32_t begin_bit,
                        uint32_t end_bit, int in_place, RoundPlan* plan)
 {
-    const uint32_t t = threadIdx.x;
-    const uint64_t mx = (uint64_t)mixed[0] | ((uint64_t)mixed[1] << 32);
+    const uint32_t t = threadIdx.x;   // 64 threads, one per pair
+    uint32_t mlo = mixed[t * kMixStride], mhi = mixed[t * kMixStride + 1];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        mlo |= __shfl_xor(mlo, o, 64);
+        mhi |= __shfl_xor(mhi, o, 64);
+    }
+    const uint64_t mx = (uint64_t)mlo | ((uint64_t)mhi << 32);
     int identity[kMaxRounds];
     for (uint32_t d = 0; d < nrounds; ++d) {
         const uint32_t lo = begin_bit + 8u * d;
@@ -391,7 +405,7 @@ __global__ void k_precopy(const RoundPlan* plan, const K* keys, K* keys_tmp,
 // plain sort are read with 16-byte loads.
 //
 // FIRST (first round of the plain sort only): the same read also ORs every
-// key's difference from the first key into mixed[0..1], from which the
+// key's difference from the first key into its pair of mixed words, from which the
 // planning kernel finds the identity rounds; this kernel then runs before the
 // plan exists.
 template <typename K, int WG, int ITEMS, bool FIRST>
@@ -469,9 +483,10 @@ __global__ __launch_bounds__(WG) void k_count(RoundArgs a, uint32_t* mixed)
     }
     __syncthreads();
     if (ALL && tid < 2) {
-        // only bits the global word lacks cost an atomic
+        // only bits the workgroup's pair lacks cost an atomic
+        uint32_t* mw = &mixed[(blockIdx.x % kMixSlots) * kMixStride + tid];
         const uint32_t mine = mix_s[tid];
-        if (mine & ~ld_agent(&mixed[tid])) atomicOr(&mixed[tid], mine);
+        if (mine & ~ld_agent(mw)) atomicOr(mw, mine);
     }
     for (uint32_t v = tid; v < R; v += WG) {
         const uint4* r4 = (const uint4*)&h[v * 32];

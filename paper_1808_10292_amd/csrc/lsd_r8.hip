@@ -160,8 +160,9 @@ hipError_t run(const void* keys_in, void* keys_out, const uint32_t* vals_in, uin
     const bool in_place = keys_in == keys_out || (KV && vals_in == vals_out);
     const uint32_t nblk = nblocks_of(L.ntiles);
 
-    uint32_t* mixed = hist;   // 2 words
-    hipLaunchKernelGGL(k_init, dim3(256), dim3(256), 0, stream, mixed, 2u, tickets, nr, blk_state,
+    uint32_t* mixed = hist;   // kMixWords words
+    static_assert(kMixWords <= (size_t)kHistReplicas * kMaxRounds * R, "identity words fit");
+    hipLaunchKernelGGL(k_init, dim3(256), dim3(256), 0, stream, mixed, kMixWords, tickets, nr, blk_state,
                        (size_t)nr * nblk * R);
     // Round 0's tile counts and the identity test of every round in one read.
     {
