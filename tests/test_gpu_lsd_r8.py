@@ -133,6 +133,29 @@ def test_in_place_with_identity_rounds(rs, dist):
     assert np.array_equal(host(k), wk)
 
 
+@pytest.mark.parametrize("dtype", [np.uint32, np.uint64])
+@pytest.mark.parametrize("tile", [0, 1, 63, 64, 100, 129])
+def test_one_key_differs(rs, dtype, tile):
+    """All keys equal but one, in the given tile: only that tile's workgroup
+    sees a difference, so the round plan must take it from wherever round 0's
+    count recorded it; every other round is the identity."""
+    tile_keys = 8192 if dtype == np.uint32 else 4096
+    n = 129 * tile_keys + 5              # the last tile holds 5 keys
+    announce("one-differs", np.dtype(dtype).name, tile)
+    same = dtype(0x5A5A5A5A) if dtype == np.uint32 else dtype(0x5A5A5A5A5A5A5A5A)
+    keys = np.full(n, same, dtype=dtype)
+    pos = min(tile * tile_keys + 3, n - 1)
+    keys[pos] = same - dtype(0x00010000)     # differs in the third digit, sorts first
+    vals = np.arange(n, dtype=np.uint32)
+    wk, wv = oracle.sr4(keys, vals)
+    assert wk[0] == keys[pos] and wv[0] == pos
+    ko, vo = rs.sort(dev(keys), dev(vals))
+    assert np.array_equal(host(ko), wk) and np.array_equal(host(vo), wv)
+    k = dev(keys)
+    rs.rsort_sort(k, k)
+    assert np.array_equal(host(k), wk)
+
+
 def test_repeatable(rs):
     n = (1 << 20) + 3
     keys = keygen.zipf_keys(n, 77)
