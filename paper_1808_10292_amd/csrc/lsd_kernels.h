@@ -303,11 +303,69 @@ constexpr uint32_t kMixSlots = 64;
 constexpr uint32_t kMixStride = 32;   // words between pairs (128 bytes)
 constexpr uint32_t kMixWords = kMixSlots * kMixStride;
 
-// The round plan.  The OR of the kMixSlots pairs is the OR over all keys of
-// (key XOR first key): a round is the identity -- one digit value holds every
-// key -- exactly when its digit's bits are zero there.
+// alias: bit 0 set when keys or payloads are sorted in place (keys_in ==
+// keys_out or vals_in == vals_out), bit 1 set when every output array is its
+// input (nothing to write when every round is the identity).
+constexpr int kAliasAny = 1;
+constexpr int kAliasAll = 2;
+
+// The round plan from the identity rounds (identity[d] != 0: one digit value
+// holds every key, so the stable count sort of round d is the identity).
+__device__ void plan_rounds(const int* identity, uint32_t nrounds, int alias, RoundPlan* plan)
+{
+    const bool in_place = (alias & kAliasAny) != 0;
+    int exec[kMaxRounds];
+    int m = 0;
+    for (uint32_t d = 0; d < nrounds; ++d) {
+        exec[d] = !identity[d];
+        m += exec[d];
+    }
+    // The last round must land in the caller's output and no round may read
+    // and write the same buffer.  Rounds alternate between output and
+    // temporary backwards from the last one, so: when every round is the
+    // identity, a copy writes each output that is not its own input (the copy
+    // moves every element to its own index, so an aliased array only rewrites
+    // itself); otherwise, in place, an even number of rounds must run
+    // (re-enable an identity round, or copy the input to the temporary first).
+    int precopy = 0;
+    if (m == 0) {
+        if (!(alias & kAliasAll)) {
+            exec[nrounds - 1] = 2;   // a plain copy input -> output
+            m = 1;
+        }
+    } else if (in_place && (m & 1)) {
+        int added = 0;
+        for (int d = (int)nrounds - 1; d >= 0 && !added; --d)
+            if (!exec[d]) { exec[d] = 1; added = 1; }
+        if (added) ++m; else precopy = 1;
+    }
+    int ord = 0;
+    int src = precopy ? 2 : 0;
+    for (uint32_t d = 0; d < nrounds; ++d) {
+        RoundPlan p;
+        p.exec = exec[d];
+        p.ord = exec[d] ? ord : -1;
+        p.src = src;
+        p.dst = exec[d] ? (((m - 1 - ord) & 1) ? 2 : 1) : -1;
+        if (exec[d]) {
+            src = p.dst;
+            ++ord;
+        }
+        plan[d] = p;
+    }
+    RoundPlan pc;
+    pc.exec = precopy;
+    pc.ord = m;
+    pc.src = 0;
+    pc.dst = 2;
+    plan[kMaxRounds] = pc;
+}
+
+// The round plan of the count-first path.  The OR of the kMixSlots pairs is
+// the OR over all keys of (key XOR first key): a round is the identity
+// exactly when its digit's bits are zero there.
 __global__ void k_plan(const uint32_t* mixed, uint32_t nrounds, uint32_t begin_bit,
-                       uint32_t end_bit, int in_place, RoundPlan* plan)
+                       uint32_t end_bit, int alias, RoundPlan* plan)
 {
     const uint32_t t = threadIdx.x;   // 64 threads, one per pair
     uint32_t mlo = mixed[t * kMixStride], mhi = mixed[t * kMixStride + 1];
@@ -317,54 +375,14 @@ __global__ void k_plan(const uint32_t* mixed, uint32_t nrounds, uint32_t begin_b
         mhi |= __shfl_xor(mhi, o, 64);
     }
     const uint64_t mx = (uint64_t)mlo | ((uint64_t)mhi << 32);
-    int identity[kMaxRounds];
-    for (uint32_t d = 0; d < nrounds; ++d) {
-        const uint32_t lo = begin_bit + 8u * d;
-        const uint32_t w = min(8u, end_bit - lo);
-        identity[d] = ((mx >> lo) & ((1ull << w) - 1ull)) == 0;
-    }
     if (t == 0) {
-        int exec[kMaxRounds];
-        int m = 0;
+        int identity[kMaxRounds];
         for (uint32_t d = 0; d < nrounds; ++d) {
-            exec[d] = !identity[d];
-            m += exec[d];
+            const uint32_t lo = begin_bit + 8u * d;
+            const uint32_t w = min(8u, end_bit - lo);
+            identity[d] = ((mx >> lo) & ((1ull << w) - 1ull)) == 0;
         }
-        // The last round must land in the caller's output and no round may
-        // read and write the same buffer.  Rounds alternate between output and
-        // temporary backwards from the last one, so: without aliasing at least
-        // one round must run; in place, an even number must (re-enable an
-        // identity round, or copy the input to the temporary first).
-        int precopy = 0;
-        if (!in_place && m == 0) {
-            exec[nrounds - 1] = 2;   // every round is the identity: a plain copy
-            m = 1;
-        } else if (in_place && (m & 1)) {
-            int added = 0;
-            for (int d = (int)nrounds - 1; d >= 0 && !added; --d)
-                if (!exec[d]) { exec[d] = 1; added = 1; }
-            if (added) ++m; else precopy = 1;
-        }
-        int ord = 0;
-        int src = precopy ? 2 : 0;
-        for (uint32_t d = 0; d < nrounds; ++d) {
-            RoundPlan p;
-            p.exec = exec[d];
-            p.ord = exec[d] ? ord : -1;
-            p.src = src;
-            p.dst = exec[d] ? (((m - 1 - ord) & 1) ? 2 : 1) : -1;
-            if (exec[d]) {
-                src = p.dst;
-                ++ord;
-            }
-            plan[d] = p;
-        }
-        RoundPlan pc;
-        pc.exec = precopy;
-        pc.ord = m;
-        pc.src = 0;
-        pc.dst = 2;
-        plan[kMaxRounds] = pc;
+        plan_rounds(identity, nrounds, alias, plan);
     }
 }
 

@@ -275,8 +275,9 @@ hipError_t run16(const void* keys_in, void* keys_out, const uint32_t* vals_in, u
     const K* src = (const K*)keys_in;
     const uint32_t* vsrc = vals_in;
     hipError_t e;
-    if ((rounds & 1) && keys_in == keys_out) {
-        // an odd round count ends in the output: start from a copy
+    if ((rounds & 1) && (keys_in == keys_out || (KV && vals_in == vals_out))) {
+        // an odd round count ends in the output, so round 0 would read and
+        // write the aliased array: start from a copy
         e = copy_bytes(tmp, keys_in, n * sizeof(K), stream);
         if (e == hipSuccess && KV) e = copy_bytes(vtmp, vals_in, n * 4, stream);
         if (e != hipSuccess) return e;

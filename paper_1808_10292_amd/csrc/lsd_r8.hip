@@ -157,7 +157,9 @@ hipError_t run(const void* keys_in, void* keys_out, const uint32_t* vals_in, uin
     K* keys_tmp = (K*)(w + L.off_tmp_keys);
     uint32_t* vals_tmp = KV ? (uint32_t*)(w + L.off_tmp_vals) : nullptr;
     const uint32_t nr = L.rounds;
-    const bool in_place = keys_in == keys_out || (KV && vals_in == vals_out);
+    const bool keys_alias = keys_in == keys_out, vals_alias = KV && vals_in == vals_out;
+    const bool in_place = keys_alias || vals_alias;
+    const int alias = (in_place ? kAliasAny : 0) | (keys_alias && (!KV || vals_alias) ? kAliasAll : 0);
     const uint32_t nblk = nblocks_of(L.ntiles);
 
     uint32_t* mixed = hist;   // kMixWords words
@@ -175,7 +177,7 @@ hipError_t run(const void* keys_in, void* keys_out, const uint32_t* vals_in, uin
         if (prof) profiler_mark(prof, stream, kKindHist, false);
     }
     hipLaunchKernelGGL(k_plan, dim3(1), dim3(64), 0, stream, (const uint32_t*)mixed, nr,
-                       (uint32_t)begin_bit, (uint32_t)end_bit, (int)in_place, plan);
+                       (uint32_t)begin_bit, (uint32_t)end_bit, alias, plan);
     if (in_place && (nr & 1)) {
         const uint32_t g = (uint32_t)((n + 256 * kPrecopyItems - 1) / (256 * kPrecopyItems));
         hipLaunchKernelGGL(k_precopy<K>, dim3(g), dim3(256), 0, stream, (const RoundPlan*)plan,

@@ -91,6 +91,26 @@ def test_in_place_and_keys_only(rs, dtype):
     assert np.array_equal(host(ko).view(np.uint8), wk.view(np.uint8))
 
 
+
+@pytest.mark.parametrize("algo", ["lsd8", "lsd16"])
+@pytest.mark.parametrize("dtype", [np.int32, np.float32, np.int64, np.float64])
+def test_all_equal_payloads_in_place(rs, dtype, algo):
+    """Equal keys (every round the identity) with the payloads sorted in
+    place and the keys not: the mapped keys must still reach keys_out before
+    the inverse map."""
+    import torch
+    n = 40009
+    announce("key types equal, payloads in place", dtype.__name__, algo)
+    k = np.full(n, -3, dtype=dtype)
+    vals = np.arange(n, dtype=np.uint32)
+    wk, wv = oracle.sort_signed_or_float(k, vals, kind_of(dtype))
+    dk, dv = as_tensor(k), dev(vals)
+    ko = torch.empty_like(dk)
+    rs.rsort_sort(dk, ko, dv, dv, algo=algo, key_type=key_type_of(dtype))
+    rs.rsort_synchronize()
+    assert np.array_equal(host(ko).view(np.uint8), wk.view(np.uint8))
+    assert np.array_equal(host(dv).view(np.uint32), wv)
+
 def test_float_tensors_default_to_total_order(rs):
     import torch
     k = np.array([0.0, -0.0, np.inf, -np.inf, 1.0, -1.0, np.nan, -np.nan, -0.0, 0.0],

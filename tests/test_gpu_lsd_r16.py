@@ -94,6 +94,30 @@ def test_bit_ranges_in_and_out_of_place(rs, lo, hi):
     assert np.array_equal(host(k), wk) and np.array_equal(host(v), wv)
 
 
+
+@pytest.mark.parametrize("lo,hi", [(0, 16), (8, 24), (0, 48)])
+@pytest.mark.parametrize("alias", ["vals", "keys"])
+def test_one_array_in_place_odd_rounds(rs, lo, hi, alias):
+    """An odd number of 16-bit rounds with only the payloads (or only the
+    keys) sorted in place: round 0 must not read and write the same array."""
+    import torch
+    n = 70001
+    announce("pr2 one array in place", lo, hi, alias)
+    keys = keygen.zipf_keys(n, 8) if hi <= 32 else keygen.uniform_u64(n, 8)
+    vals = np.arange(n, dtype=np.uint32)
+    wk, wv = oracle.lsd_sort(keys, vals, 16, lo, hi)
+    k, v = dev(keys), dev(vals)
+    if alias == "vals":
+        ko = torch.empty_like(k)
+        rs.rsort_sort(k, ko, v, v, lo, hi, algo="lsd16")
+        vo = v
+    else:
+        vo = torch.empty_like(v)
+        rs.rsort_sort(k, k, v, vo, lo, hi, algo="lsd16")
+        ko = k
+    rs.rsort_synchronize()
+    assert np.array_equal(host(ko), wk) and np.array_equal(host(vo), wv)
+
 def test_caller_workspace_and_repeat(rs):
     import torch
     n = 523459

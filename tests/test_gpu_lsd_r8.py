@@ -279,3 +279,37 @@ def test_graph_capture_replays(rs):
     g.replay()
     torch.cuda.synchronize()
     assert np.array_equal(host(ko), oracle.sr4(keys2)[0])
+
+
+@pytest.mark.parametrize("dtype", [np.uint32, np.uint64])
+@pytest.mark.parametrize("case", ["equal", "range_agrees", "one_round"])
+@pytest.mark.parametrize("alias", ["vals", "keys"])
+def test_one_array_in_place(rs, dtype, case, alias):
+    """Only one of keys / payloads sorted in place (keys_in != keys_out but
+    vals_in == vals_out, or the reverse), also when every round is the
+    identity: the array that is not its own input must still be written."""
+    import torch
+    n = 3 * 8192 + 11
+    announce("one array in place", np.dtype(dtype).name, case, alias)
+    keys = keygen.uniform_u32(n, 91).astype(dtype)
+    lo, hi = 0, 8 * keys.itemsize
+    if case == "equal":
+        keys[:] = keys[0]
+    elif case == "range_agrees":
+        keys = (keys & dtype(0xFF)) | dtype(0xA500)     # bits [8, 24) agree
+        lo, hi = 8, 24
+    else:
+        keys = keys & dtype(0xFF)                        # one running round
+    vals = np.arange(n, dtype=np.uint32)
+    wk, wv = oracle.lsd_sort(keys, vals, 8, lo, hi)
+    k, v = dev(keys), dev(vals)
+    if alias == "vals":
+        ko = torch.empty_like(k)
+        rs.rsort_sort(k, ko, v, v, lo, hi)
+        vo = v
+    else:
+        vo = torch.empty_like(v)
+        rs.rsort_sort(k, k, v, vo, lo, hi)
+        ko = k
+    rs.rsort_synchronize()
+    assert np.array_equal(host(ko), wk) and np.array_equal(host(vo), wv)
