@@ -121,6 +121,32 @@ int rsort_sort(rsort_ctx* ctx, int key_type,
                void* workspace, size_t ws_bytes, void* stream);
 
 /*
+ * How RSORT_LSD_R8 (and RSORT_AUTO) carries out each count-sort round of
+ * Section 3.2 (count the digits of each block, exchange the p x r counts so
+ * that every block knows where its keys of each digit go, route the keys):
+ *
+ *   RSORT_PR4_COUNTED      (default) per round three kernels: per-tile digit
+ *                          counts (one read of the keys), a scan of the counts
+ *                          over tiles, and the routing kernel (a second read
+ *                          and one write).
+ *   RSORT_PR4_SINGLE_READ  32-bit keys, at most four rounds: one counting pass
+ *                          before the first round (per-chunk digit counts and
+ *                          the joint counts of each digit with the top bits of
+ *                          the digit below it), then per round one kernel that
+ *                          counts a tile, learns the keys of each digit in the
+ *                          earlier tiles of its chain by a look-back over
+ *                          counts the other tiles publish, and routes (one read
+ *                          and one write per round).  Other requests fall back
+ *                          to the counted rounds.
+ *
+ * Both give the same, stable result.  The choice applies to later calls on
+ * ctx (it changes rsort_workspace_bytes).  Returns RSORT_EINVAL for another
+ * value.
+ */
+enum rsort_pr4_rounds { RSORT_PR4_COUNTED = 0, RSORT_PR4_SINGLE_READ = 1 };
+int rsort_set_pr4_rounds(rsort_ctx* ctx, int kind);
+
+/*
  * The counting step of every count-sort round, for all rounds at once
  * (Section 3.2: each round first counts digit occurrences): one read of the
  * keys produces, for every digit d of the key bits [begin_bit, end_bit) taken

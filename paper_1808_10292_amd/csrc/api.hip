@@ -100,6 +100,7 @@ struct rsort_ctx {
     bool meta_pending = false;
     uint32_t small_max = rsort::kSmallMaxDefault;
     int small_sort = RSORT_SMALL_RADIX;   // sorter of the small segments
+    int pr4_rounds = RSORT_PR4_COUNTED;  // round kind of RSORT_LSD_R8
     rsort::SegPlan plan;
     uint64_t upload_sig = 0;         // plan last uploaded into upload_ws
     void* upload_ws = nullptr;
@@ -220,13 +221,15 @@ int validate_bits(rsort_ctx* ctx, int key_type, int begin_bit, int end_bit)
     return RSORT_OK;
 }
 
-size_t sort_ws_bytes(int key_type, bool has_vals, size_t n, int algo, int begin_bit, int end_bit)
+size_t sort_ws_bytes(int key_type, bool has_vals, size_t n, int algo, int begin_bit, int end_bit,
+                     int pr4_rounds)
 {
     if (algo == RSORT_SAMPLE_REGULAR)
         return rsort::gsd_layout(has_vals, n, kDefaultP, kDefaultR).bytes;
     if (algo == RSORT_LSD_R16)
         return rsort::lsd_r16_layout(key_bytes_of(key_type), has_vals, n, begin_bit, end_bit).bytes;
-    return rsort::lsd_r8_layout(key_bytes_of(key_type), has_vals, n, begin_bit, end_bit).bytes;
+    return rsort::lsd_r8_layout(key_bytes_of(key_type), has_vals, n, begin_bit, end_bit,
+                                pr4_rounds == RSORT_PR4_SINGLE_READ).bytes;
 }
 
 // Device residency and aliasing of the key / payload arrays of a sort of n
@@ -349,7 +352,8 @@ int rsort_workspace_bytes(rsort_ctx* ctx, int key_type, int has_vals, size_t n, 
     if (algo == RSORT_SAMPLE_REGULAR)
         return rsort_sample_sort_workspace_bytes(ctx, key_type, has_vals, n, kDefaultP, kDefaultR,
                                                  bytes);
-    *bytes = sort_ws_bytes(key_type, has_vals != 0, n, algo, 0, key_bytes_of(key_type) * 8);
+    *bytes = sort_ws_bytes(key_type, has_vals != 0, n, algo, 0, key_bytes_of(key_type) * 8,
+                           ctx->pr4_rounds);
     return RSORT_OK;
 }
 
@@ -397,7 +401,8 @@ int sort_mapped(rsort_ctx* ctx, int ukey, int kind, const void* keys_in, void* k
     DeviceGuard g(ctx->device);
     int rc = check_arrays(ctx, kb, keys_in, keys_out, vals_in, vals_out, n);
     if (rc) return rc;
-    const size_t inner = rsort::align_up(sort_ws_bytes(ukey, vals_in != nullptr, n, algo, 0, kb * 8));
+    const size_t inner =
+        rsort::align_up(sort_ws_bytes(ukey, vals_in != nullptr, n, algo, 0, kb * 8, ctx->pr4_rounds));
     const size_t need = inner + n * kb;
     void* ws = workspace;
     if (ws) {
@@ -628,7 +633,8 @@ int rsort_sort(rsort_ctx* ctx, int key_type, const void* keys_in, void* keys_out
                                            end_bit, ws, L16, s, ctx->prof);
         return e == hipSuccess ? RSORT_OK : hip_fail(ctx, e, "kernel launch");
     }
-    const rsort::LsdR8Layout L = rsort::lsd_r8_layout(kb, vals_in != nullptr, n, begin_bit, end_bit);
+    const rsort::LsdR8Layout L = rsort::lsd_r8_layout(kb, vals_in != nullptr, n, begin_bit, end_bit,
+                                                      ctx->pr4_rounds == RSORT_PR4_SINGLE_READ);
     void* ws = workspace;
     if (ws) {
         if (ws_bytes < L.bytes)
@@ -808,6 +814,15 @@ int rsort_segmented_get_small_sort(rsort_ctx* ctx, int* small_sort)
 {
     if (!ctx || !small_sort) return RSORT_EINVAL;
     *small_sort = ctx->small_sort;
+    return RSORT_OK;
+}
+
+int rsort_set_pr4_rounds(rsort_ctx* ctx, int kind)
+{
+    if (!ctx) return RSORT_EINVAL;
+    if (kind != RSORT_PR4_COUNTED && kind != RSORT_PR4_SINGLE_READ)
+        return fail(ctx, RSORT_EINVAL, "unknown PR4 round kind %d", kind);
+    ctx->pr4_rounds = kind;
     return RSORT_OK;
 }
 

@@ -26,6 +26,7 @@
 // No tile of a round waits for another tile: the dependencies are kernel
 // boundaries, except the chain of tile blocks inside k_tilescan.
 #include "lsd_kernels.h"
+#include "onesweep_kernels.h"
 
 namespace rsort {
 namespace {
@@ -210,9 +211,99 @@ hipError_t run(const void* keys_in, void* keys_out, const uint32_t* vals_in, uin
     return hipGetLastError();
 }
 
+// Single-read rounds of 32-bit keys (onesweep_kernels.h).
+template <bool KV>
+hipError_t run_os(const void* keys_in, void* keys_out, const uint32_t* vals_in, uint32_t* vals_out,
+                  size_t n, int begin_bit, int end_bit, void* ws, const LsdR8Layout& L,
+                  uint32_t* dev_err, hipStream_t stream, Profiler* prof)
+{
+    typedef uint32_t K;
+    constexpr int WG = R8Config<K>::WG;
+    constexpr int ITEMS = R8Config<K>::ITEMS;
+    uint8_t* w = (uint8_t*)ws;
+    uint32_t* mixed = (uint32_t*)(w + L.off_hist);
+    uint32_t* bases = (uint32_t*)(w + L.off_bases);
+    RoundPlan* plan = (RoundPlan*)(w + L.off_plan);
+    uint32_t* rows = (uint32_t*)(w + L.off_os_rows);
+    uint32_t* cbx = (uint32_t*)(w + L.off_os_cbx);
+    uint32_t* tot = (uint32_t*)(w + L.off_os_tot);
+    uint32_t* J = (uint32_t*)(w + L.off_os_J);
+    uint32_t* jx = (uint32_t*)(w + L.off_os_jx);
+    OsRound* rinfo = (OsRound*)(w + L.off_os_rinfo);
+    uint4* tt = (uint4*)(w + L.off_os_tt);
+    uint32_t* chains = (uint32_t*)(w + L.off_os_chains);
+    uint32_t* state = (uint32_t*)(w + L.off_os_state);
+    uint32_t* tick = (uint32_t*)(w + L.off_os_tick);
+    K* keys_tmp = (K*)(w + L.off_tmp_keys);
+    uint32_t* vals_tmp = KV ? (uint32_t*)(w + L.off_tmp_vals) : nullptr;
+    const uint32_t nr = L.rounds;
+    const bool keys_alias = keys_in == keys_out, vals_alias = KV && vals_in == vals_out;
+    const bool in_place = keys_alias || vals_alias;
+    const int alias = (in_place ? kAliasAny : 0) | (keys_alias && (!KV || vals_alias) ? kAliasAll : 0);
+    OsShape sh;
+    sh.nchunks = L.os_nchunks;
+    sh.chunk_keys = L.os_chunk_keys;
+    sh.roww = L.os_roww;
+    sh.maxrows = L.os_maxrows;
+    sh.cmax = L.os_cmax;
+    const uint32_t state_words = sh.maxrows * R;
+
+    hipLaunchKernelGGL(k_os_init, dim3(16), dim3(256), 0, stream, mixed, kMixWords, tick,
+                       nr * kQueues * kQueueStride);
+    if (prof) profiler_mark(prof, stream, kKindHist, true);
+    hipLaunchKernelGGL(k_os_count<K>, dim3(sh.nchunks), dim3(kOsCountWG), 0, stream, (const K*)keys_in,
+                       (uint32_t)n, sh.chunk_keys, (uint32_t)begin_bit, (uint32_t)end_bit, nr, rows,
+                       sh.roww, mixed, state, state_words);
+    if (prof) profiler_mark(prof, stream, kKindHist, false);
+    if (prof) profiler_mark(prof, stream, kKindTileScan, true);
+    hipLaunchKernelGGL(k_os_reduce, dim3((sh.roww + 63) / 64), dim3(kOsReduceWG), 0, stream,
+                       (const uint32_t*)rows, sh.nchunks, sh.roww, nr, cbx, tot, J);
+    hipLaunchKernelGGL(k_os_plan, dim3(1), dim3(kOsPlanWG), 0, stream, (const uint32_t*)mixed, nr,
+                       (uint32_t)begin_bit, (uint32_t)end_bit, alias, (uint32_t)n, L.tile, sh, plan,
+                       (const uint32_t*)tot, (const uint32_t*)J, bases, jx, rinfo, chains);
+    hipLaunchKernelGGL(k_os_tickets, dim3((sh.maxrows + kOsTicketWG - 1) / kOsTicketWG, nr),
+                       dim3(kOsTicketWG), 0, stream, (const RoundPlan*)plan, (const OsRound*)rinfo,
+                       (const uint32_t*)chains, sh.cmax, sh.maxrows, (uint32_t)n, L.tile, tt);
+    if (prof) profiler_mark(prof, stream, kKindTileScan, false);
+    if (in_place && (nr & 1)) {
+        const uint32_t g = (uint32_t)((n + 256 * kPrecopyItems - 1) / (256 * kPrecopyItems));
+        hipLaunchKernelGGL(k_precopy<K>, dim3(g), dim3(256), 0, stream, (const RoundPlan*)plan,
+                           (const K*)keys_in, keys_tmp, KV ? vals_in : nullptr, vals_tmp, (uint32_t)n);
+    }
+    for (uint32_t d = 0; d < nr; ++d) {
+        OsArgs a;
+        a.keys_in = keys_in;
+        a.keys_out = keys_out;
+        a.keys_tmp = keys_tmp;
+        a.vals_in = vals_in;
+        a.vals_out = vals_out;
+        a.vals_tmp = vals_tmp;
+        a.n = (uint32_t)n;
+        a.shift = (uint32_t)begin_bit + 8u * d;
+        a.mask = (1u << std::min(8u, (uint32_t)end_bit - a.shift)) - 1u;
+        a.round = d;
+        a.plan = plan;
+        a.rinfo = rinfo;
+        a.tt = tt + (size_t)d * sh.maxrows;
+        a.row0 = chains + (size_t)(3 * d + 2) * sh.cmax;
+        a.cb_chunk = cbx + (size_t)d * sh.nchunks * R;
+        a.cb_joint = jx + (size_t)d * kJointChains * R;
+        a.bases = bases;
+        a.state = state;
+        a.maxrows = sh.maxrows;
+        a.tick = tick + (size_t)d * kQueues * kQueueStride;
+        a.err = dev_err;
+        if (prof) profiler_mark(prof, stream, kKindRound, true);
+        hipLaunchKernelGGL((k_onesweep<K, KV, WG, ITEMS>), dim3(sh.maxrows), dim3(WG), 0, stream, a);
+        if (prof) profiler_mark(prof, stream, kKindRound, false);
+    }
+    return hipGetLastError();
+}
+
 }  // namespace
 
-LsdR8Layout lsd_r8_layout(int key_bytes, bool has_vals, size_t n, int begin_bit, int end_bit)
+LsdR8Layout lsd_r8_layout(int key_bytes, bool has_vals, size_t n, int begin_bit, int end_bit,
+                          bool single_read)
 {
     LsdR8Layout L{};
     L.rounds = rounds_of(begin_bit, end_bit, 8);
@@ -229,6 +320,26 @@ LsdR8Layout lsd_r8_layout(int key_bytes, bool has_vals, size_t n, int begin_bit,
     L.off_bases = o;     o = align_up(o + (size_t)kMaxRounds * R * 4);
     L.off_plan = o;      o = align_up(o + (kMaxRounds + 1) * sizeof(RoundPlan));
     L.off_tickets = o;   o = align_up(o + kMaxRounds * 4);
+    L.onesweep = single_read && key_bytes == 4 && L.rounds > 0 && L.rounds <= 4;
+    if (L.onesweep) {
+        const uint32_t cpt = std::max<uint32_t>(kOsMinChunkTiles, (L.ntiles + kOsMaxChunks - 1) / kOsMaxChunks);
+        L.os_nchunks = std::max<uint32_t>(1, (L.ntiles + cpt - 1) / cpt);
+        L.os_chunk_keys = cpt * L.tile;
+        L.os_roww = L.rounds * R + (L.rounds - 1) * kJointBins;
+        L.os_maxrows = (L.ntiles + kJointChains + 7) & ~7u;
+        L.os_cmax = std::max<uint32_t>(L.os_nchunks, kJointChains);
+        const size_t nr = L.rounds;
+        L.off_os_rows = o;   o = align_up(o + (size_t)L.os_nchunks * L.os_roww * 4);
+        L.off_os_cbx = o;    o = align_up(o + nr * L.os_nchunks * R * 4);
+        L.off_os_tot = o;    o = align_up(o + nr * R * 4);
+        L.off_os_J = o;      o = align_up(o + nr * kJointBins * 4);
+        L.off_os_jx = o;     o = align_up(o + nr * kJointChains * R * 4);
+        L.off_os_rinfo = o;  o = align_up(o + nr * sizeof(OsRound));
+        L.off_os_tt = o;     o = align_up(o + nr * L.os_maxrows * sizeof(uint4));
+        L.off_os_chains = o; o = align_up(o + 3 * nr * L.os_cmax * 4);
+        L.off_os_state = o;  o = align_up(o + 2 * (size_t)L.os_maxrows * R * 4);
+        L.off_os_tick = o;   o = align_up(o + nr * kQueues * kQueueStride * 4);
+    }
     L.bytes = o;
     return L;
 }
@@ -239,6 +350,9 @@ hipError_t lsd_r8_sort(int key_bytes, const void* keys_in, void* keys_out,
                        uint32_t* dev_err, hipStream_t stream, Profiler* prof)
 {
     const bool kv = vals_in != nullptr;
+    if (L.onesweep)
+        return kv ? run_os<true>(keys_in, keys_out, vals_in, vals_out, n, begin_bit, end_bit, ws, L, dev_err, stream, prof)
+                  : run_os<false>(keys_in, keys_out, vals_in, vals_out, n, begin_bit, end_bit, ws, L, dev_err, stream, prof);
     if (key_bytes == 4)
         return kv ? run<uint32_t, true>(keys_in, keys_out, vals_in, vals_out, n, begin_bit, end_bit, ws, L, dev_err, stream, prof)
                   : run<uint32_t, false>(keys_in, keys_out, vals_in, vals_out, n, begin_bit, end_bit, ws, L, dev_err, stream, prof);

@@ -35,17 +35,28 @@ struct Profiler;
 void profiler_mark(Profiler* p, hipStream_t s, int kind, bool begin);
 
 // ---------------------------------------------------------------------------
-// Radix 2^8 LSD (PR4) with one-sweep rounds.
+// Radix 2^8 LSD (PR4).  Counted rounds (per-tile counts, a scan over tiles,
+// then the routing kernel) for every key type; 32-bit keys can instead run
+// single-read rounds (onesweep_kernels.h: one counting pass, then per round
+// one kernel that counts, looks back inside its chain of tiles and routes).
 struct LsdR8Layout {
     uint32_t rounds;     // number of 8-bit (or narrower, last) digits
     uint32_t tile;       // keys per tile in a round
     uint32_t ntiles;
     size_t off_tmp_keys, off_tmp_vals, off_counts, off_blk_state;
     size_t off_hist, off_bases, off_plan, off_tickets;
+    // single-read rounds (onesweep == true)
+    bool onesweep;
+    uint32_t os_nchunks, os_chunk_keys, os_roww, os_maxrows, os_cmax;
+    size_t off_os_rows, off_os_cbx, off_os_tot, off_os_J, off_os_jx, off_os_rinfo, off_os_tt,
+        off_os_chains, off_os_state, off_os_tick;
     size_t bytes;
 };
 
-LsdR8Layout lsd_r8_layout(int key_bytes, bool has_vals, size_t n, int begin_bit, int end_bit);
+// single_read: 32-bit keys with at most four rounds use the single-read
+// rounds (other requests keep the counted rounds).
+LsdR8Layout lsd_r8_layout(int key_bytes, bool has_vals, size_t n, int begin_bit, int end_bit,
+                          bool single_read = false);
 
 // Enqueue the whole sort on `stream`.  ws must hold layout.bytes bytes.
 hipError_t lsd_r8_sort(int key_bytes, const void* keys_in, void* keys_out,

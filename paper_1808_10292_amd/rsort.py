@@ -47,7 +47,8 @@ ALGOS = {"auto": RSORT_AUTO, "lsd8": RSORT_LSD_R8, "pr4": RSORT_LSD_R8,
 
 # Every symbol include/rsort.h declares; the loader checks they all exist.
 EXPORTED = ("rsort_create", "rsort_destroy", "rsort_status_string", "rsort_last_error",
-            "rsort_workspace_bytes", "rsort_sort", "rsort_histogram", "rsort_synchronize",
+            "rsort_workspace_bytes", "rsort_sort", "rsort_set_pr4_rounds", "rsort_histogram",
+            "rsort_synchronize",
             "rsort_profile_enable", "rsort_profile_read", "rsort_profile_set_period",
             "rsort_segmented_sort",
             "rsort_segmented_workspace_bytes", "rsort_segmented_set_split",
@@ -59,6 +60,10 @@ EXPORTED = ("rsort_create", "rsort_destroy", "rsort_status_string", "rsort_last_
             "rsort_segmented_device_workspace_bytes", "rsort_server_create", "rsort_server_submit",
             "rsort_server_poll", "rsort_server_wait", "rsort_server_latency",
             "rsort_server_reset_stats", "rsort_server_destroy")
+
+RSORT_PR4_COUNTED = 0
+RSORT_PR4_SINGLE_READ = 1
+PR4_ROUNDS = {"counted": RSORT_PR4_COUNTED, "single_read": RSORT_PR4_SINGLE_READ}
 
 RSORT_SMALL_RADIX = 0
 RSORT_SMALL_BTN = 1
@@ -107,6 +112,7 @@ def load_library():
         lib.rsort_workspace_bytes.argtypes = [vp, i, i, sz, i, ctypes.POINTER(sz)]
         lib.rsort_sort.argtypes = [vp, i, vp, vp, u32p, u32p, sz, i, i, i, vp, sz, vp]
         lib.rsort_histogram.argtypes = [vp, i, vp, sz, i, i, i, u32p, vp]
+        lib.rsort_set_pr4_rounds.argtypes = [vp, i]
         lib.rsort_synchronize.argtypes = [vp, vp]
         lib.rsort_profile_enable.argtypes = [vp, i]
         lib.rsort_profile_set_period.argtypes = [vp, ctypes.c_uint32]
@@ -286,6 +292,13 @@ def rsort_sort(keys_in, keys_out, vals_in=None, vals_out=None, begin_bit=0, end_
                              ws_ptr, ws_bytes, _stream_handle(stream))
     ctx.check(rc, "rsort_sort")
     return keys_out, vals_out
+
+
+def rsort_set_pr4_rounds(kind, device=None):
+    """Round kind of RSORT_LSD_R8: "counted" (default) or "single_read"."""
+    ctx = context(device)
+    ctx.check(ctx._lib.rsort_set_pr4_rounds(ctx.handle, PR4_ROUNDS[kind] if isinstance(kind, str)
+                                            else int(kind)), "rsort_set_pr4_rounds")
 
 
 def rsort_histogram(keys, digit_bits=8, begin_bit=0, end_bit=None, out=None, stream=None):
