@@ -121,6 +121,28 @@ int rsort_sort(rsort_ctx* ctx, int key_type,
                void* workspace, size_t ws_bytes, void* stream);
 
 /*
+ * rsort_sort with RSORT_LSD_R8 for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the call allocates nothing (no hipMalloc, hipFree or allocating
+ * library routine) and uses as its workspace a scratch array of 64 MiB that
+ * the library's code object holds on each GPU from its load until the process
+ * ends.  Arguments, result and errors as in rsort_sort (algo RSORT_LSD_R8, no
+ * workspace argument).  Requests whose workspace (rsort_workspace_bytes with
+ * RSORT_LSD_R8) exceeds 64 MiB return RSORT_EUNSUPPORTED without enqueuing
+ * anything: about 15 million uint32 keys, or 7.8 million uint32 key-value
+ * pairs or uint64 keys, fit.  Every call on a GPU shares that GPU's scratch
+ * array (each call initialises what it needs; nothing carries over), so calls
+ * whose execution overlaps on one GPU -- other streams, other threads, other
+ * contexts of the same device -- race and give wrong results: order them on
+ * one stream or synchronise between them.  Kernel timing (rsort_profile_*) is
+ * not recorded for this call.
+ */
+int rsort_sort_noalloc(rsort_ctx* ctx, int key_type,
+                       const void* keys_in, void* keys_out,
+                       const uint32_t* vals_in, uint32_t* vals_out,
+                       size_t n, int begin_bit, int end_bit, void* stream);
+
+/*
  * How RSORT_LSD_R8 (and RSORT_AUTO) carries out each count-sort round of
  * Section 3.2 (count the digits of each block, exchange the p x r counts so
  * that every block knows where its keys of each digit go, route the keys):

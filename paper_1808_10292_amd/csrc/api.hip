@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -86,8 +87,39 @@ void profiler_mark(Profiler* p, hipStream_t s, int kind, bool begin)
 
 }  // namespace rsort
 
+namespace {
+
+// Workspace of rsort_sort_noalloc: a file-scope device array, so every GPU the
+// library runs on holds its own copy (allocated when the code object is loaded
+// there, kept until the process ends).  Host code never uses the array's name
+// as an address: the address on each device comes from hipGetSymbolAddress,
+// taken once per device when a context is created on it.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+
+// Device address of `scratch` on `device` (the caller has made it current), or
+// nullptr if the runtime cannot resolve it.
+void* scratch_address(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) == hipSuccess) g_scratch_ptr[device] = ptr;
+        else (void)hipGetLastError();
+    }
+    return g_scratch_ptr[device];
+}
+
+}  // namespace
+
 struct rsort_ctx {
     int device = 0;
+    void* scratch = nullptr;     // this device's address of `scratch` (rsort_sort_noalloc)
     void* ws = nullptr;          // cached workspace (grown on demand)
     size_t ws_bytes = 0;
     uint32_t* dev_err = nullptr; // device-side failure bits (DeviceError)
@@ -109,6 +141,7 @@ struct rsort_ctx {
     uint32_t gsd_p = 0;
     std::string last_error;
 };
+
 
 namespace {
 
@@ -146,6 +179,14 @@ bool is_device_pointer(const void* p, int device)
         return false;
     }
     return attr.type == hipMemoryTypeDevice && attr.device == device;
+}
+
+// A caller's workspace must be device memory of the context's device; the
+// scratch of rsort_sort_noalloc is (it is not a hipMalloc allocation, so the
+// pointer query is not asked about it).
+bool workspace_ok(const rsort_ctx* ctx, const void* ws)
+{
+    return (ctx->scratch && ws == ctx->scratch) || is_device_pointer(ws, ctx->device);
 }
 
 bool overlap_partial(const void* a, size_t abytes, const void* b, size_t bbytes)
@@ -293,6 +334,7 @@ int rsort_create(int hip_device, rsort_ctx** out)
         delete ctx;
         return RSORT_ENOMEM;
     }
+    ctx->scratch = scratch_address(hip_device);
     *out = ctx;
     return RSORT_OK;
 }
@@ -408,7 +450,7 @@ int sort_mapped(rsort_ctx* ctx, int ukey, int kind, const void* keys_in, void* k
     if (ws) {
         if (ws_bytes < need)
             return fail(ctx, RSORT_EINVAL, "workspace of %zu bytes < %zu needed", ws_bytes, need);
-        if (!is_device_pointer(ws, ctx->device))
+        if (!workspace_ok(ctx, ws))
             return fail(ctx, RSORT_EINVAL, "workspace must be device memory");
     } else {
         rc = ensure_workspace(ctx, need, &ws);
@@ -460,7 +502,7 @@ int run_skeleton(rsort_ctx* ctx, int key_type, const void* keys_in, void* keys_o
     if (ws) {
         if (ws_bytes < L.bytes)
             return fail(ctx, RSORT_EINVAL, "workspace of %zu bytes < %zu needed", ws_bytes, L.bytes);
-        if (!is_device_pointer(ws, ctx->device))
+        if (!workspace_ok(ctx, ws))
             return fail(ctx, RSORT_EINVAL, "workspace must be device memory");
     } else {
         rc = ensure_workspace(ctx, L.bytes, &ws);
@@ -623,7 +665,7 @@ int rsort_sort(rsort_ctx* ctx, int key_type, const void* keys_in, void* keys_out
         if (ws) {
             if (ws_bytes < L16.bytes)
                 return fail(ctx, RSORT_EINVAL, "workspace of %zu bytes < %zu needed", ws_bytes, L16.bytes);
-            if (!is_device_pointer(ws, ctx->device))
+            if (!workspace_ok(ctx, ws))
                 return fail(ctx, RSORT_EINVAL, "workspace must be device memory");
         } else {
             rc = ensure_workspace(ctx, L16.bytes, &ws);
@@ -649,6 +691,30 @@ int rsort_sort(rsort_ctx* ctx, int key_type, const void* keys_in, void* keys_out
                                       end_bit, ws, L, ctx->dev_err, s, ctx->prof);
     if (e != hipSuccess) return hip_fail(ctx, e, "kernel launch");
     return RSORT_OK;
+}
+
+int rsort_sort_noalloc(rsort_ctx* ctx, int key_type, const void* keys_in, void* keys_out,
+                       const uint32_t* vals_in, uint32_t* vals_out, size_t n, int begin_bit,
+                       int end_bit, void* stream)
+{
+    if (!ctx) return RSORT_EINVAL;
+    ctx->last_error.clear();
+    if (!ctx->scratch)
+        return fail(ctx, RSORT_EDEVICE, "no address of the scratch array on device %d", ctx->device);
+    size_t need = 0;
+    int rc = rsort_workspace_bytes(ctx, key_type, vals_in != nullptr, n, RSORT_LSD_R8, &need);
+    if (rc) return rc;
+    if (need > kScratchBytes)
+        return fail(ctx, RSORT_EUNSUPPORTED,
+                    "n = %zu needs %zu bytes of workspace, above the %zu-byte scratch of "
+                    "rsort_sort_noalloc", n, need, kScratchBytes);
+    // no event is created or recorded: the profiler stays off for this call
+    rsort::Profiler* prof = ctx->prof;
+    ctx->prof = nullptr;
+    rc = rsort_sort(ctx, key_type, keys_in, keys_out, vals_in, vals_out, n, begin_bit, end_bit,
+                    RSORT_LSD_R8, ctx->scratch, kScratchBytes, stream);
+    ctx->prof = prof;
+    return rc;
 }
 
 int rsort_histogram(rsort_ctx* ctx, int key_type, const void* keys, size_t n, int digit_bits,

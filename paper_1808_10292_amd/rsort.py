@@ -47,7 +47,8 @@ ALGOS = {"auto": RSORT_AUTO, "lsd8": RSORT_LSD_R8, "pr4": RSORT_LSD_R8,
 
 # Every symbol include/rsort.h declares; the loader checks they all exist.
 EXPORTED = ("rsort_create", "rsort_destroy", "rsort_status_string", "rsort_last_error",
-            "rsort_workspace_bytes", "rsort_sort", "rsort_set_pr4_rounds", "rsort_histogram",
+            "rsort_workspace_bytes", "rsort_sort", "rsort_sort_noalloc", "rsort_set_pr4_rounds",
+            "rsort_histogram",
             "rsort_synchronize",
             "rsort_profile_enable", "rsort_profile_read", "rsort_profile_set_period",
             "rsort_segmented_sort",
@@ -113,6 +114,7 @@ def load_library():
         lib.rsort_sort.argtypes = [vp, i, vp, vp, u32p, u32p, sz, i, i, i, vp, sz, vp]
         lib.rsort_histogram.argtypes = [vp, i, vp, sz, i, i, i, u32p, vp]
         lib.rsort_set_pr4_rounds.argtypes = [vp, i]
+        lib.rsort_sort_noalloc.argtypes = [vp, i, vp, vp, u32p, u32p, sz, i, i, vp]
         lib.rsort_synchronize.argtypes = [vp, vp]
         lib.rsort_profile_enable.argtypes = [vp, i]
         lib.rsort_profile_set_period.argtypes = [vp, ctypes.c_uint32]
@@ -291,6 +293,33 @@ def rsort_sort(keys_in, keys_out, vals_in=None, vals_out=None, begin_bit=0, end_
                              ALGOS[algo] if isinstance(algo, str) else int(algo),
                              ws_ptr, ws_bytes, _stream_handle(stream))
     ctx.check(rc, "rsort_sort")
+    return keys_out, vals_out
+
+
+def rsort_sort_noalloc(keys_in, keys_out, vals_in=None, vals_out=None, begin_bit=0, end_bit=None,
+                       stream=None, key_type=None):
+    """rsort_sort (radix 2^8) with the library's own scratch array as workspace:
+    the call allocates nothing.  Arguments as in rsort_sort."""
+    kt = _key_type(keys_in, key_type)
+    n = keys_in.numel()
+    if keys_out.dtype != keys_in.dtype:
+        raise TypeError("keys_out must have the dtype of keys_in")
+    _check_tensor(keys_in, n, "keys_in")
+    _check_tensor(keys_out, n, "keys_out")
+    if (vals_in is None) != (vals_out is None):
+        raise ValueError("vals_in and vals_out must both be given or both be None")
+    if vals_in is not None:
+        for t, name in ((vals_in, "vals_in"), (vals_out, "vals_out")):
+            if t.dtype not in (torch.int32, torch.uint32):
+                raise TypeError("%s must be a 32-bit integer tensor" % name)
+            _check_tensor(t, n, name)
+    if end_bit is None:
+        end_bit = 8 * keys_in.element_size()
+    ctx = context(keys_in.device)
+    rc = ctx._lib.rsort_sort_noalloc(ctx.handle, kt, _ptr(keys_in), _ptr(keys_out), _ptr(vals_in),
+                                     _ptr(vals_out), n, int(begin_bit), int(end_bit),
+                                     _stream_handle(stream))
+    ctx.check(rc, "rsort_sort_noalloc")
     return keys_out, vals_out
 
 
