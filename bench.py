@@ -24,9 +24,11 @@ Printed as one JSON line:
   kv           2^28 key-value pairs per key distribution: PR4 vs the
                regular-oversampling sample sort (GSD, p = 256, r = 32)
   small        2^20 keys uniform in [0, 2^31): per-call latency p50/p99
-  serve        Poisson streams (rho = 0.5, 0.8 of the plain-launch capacity) of
-               mixed-size uint32/uint64 requests through the continuous-
-               batching server: p50/p99 latency, keys/s, alone == in the mix
+  serve        Poisson streams (rho = 0.5, 0.8 of the plain-launch capacity) and
+               a saturated stream (every request at once) of mixed-size
+               uint32/uint64 requests through the continuous-batching server:
+               p50/p99 latency, keys/s against one plain launch per request,
+               peak HBM in flight, alone == in the mix
 """
 import argparse
 import hashlib
@@ -334,10 +336,16 @@ def bench_serve(rsort, torch, np, keygen, args):
     res = {"workload": "Poisson stream, sizes log-uniform [2^10, 2^26], 50%% uint32 / 50%% "
                        "uint64, cap 64 GB, 4 streams; %d requests after %d warm-up" % (num, warm),
            "plain_launch_gkeys_per_s": round(cap_kps / 1e9, 3)}
-    for rho in (0.5, 0.8):
-        rate = rho * cap_kps / mean_n
-        arrivals = keygen.poisson_arrivals(total_req, rate, keygen.SEED_SERVE + 2)
+    for rho in (0.5, 0.8, None):
+        # rho None: every request submitted at once (closed loop, the server saturated)
+        if rho is None:
+            rate = float("inf")
+            arrivals = np.zeros(total_req)
+        else:
+            rate = rho * cap_kps / mean_n
+            arrivals = keygen.poisson_arrivals(total_req, rate, keygen.SEED_SERVE + 2)
         srv = rsort.Server(64 * 10 ** 9, num_streams=4)
+        srv.reserve("u64", int(sizes.max()))   # slot workspaces allocated before traffic
         ring_users.clear()
         ring_at[0] = 0
         pick = set(int(j) for j in np.random.default_rng(1).choice(np.arange(warm, total_req), 16,
@@ -369,6 +377,7 @@ def bench_serve(rsort, torch, np, keygen, args):
         for t in tickets:
             srv.wait(t)
         p50, p99, kps, done = srv.latency()
+        _, max_in_flight, held = srv.memory()
         srv.destroy()
         same = True
         for i, o in kept.items():
@@ -377,14 +386,22 @@ def bench_serve(rsort, torch, np, keygen, args):
             rsort.rsort_sort(x, ref)
             torch.cuda.synchronize()
             same = same and bool(torch.equal(ref.view(torch.uint8), o.view(torch.uint8)))
-        res["rho_%.1f" % rho] = {
-            "rate_req_per_s": round(rate, 1), "completed": int(done),
-            "latency_us_p50": round(p50, 1), "latency_us_p99": round(p99, 1),
-            "gkeys_per_s": round(kps / 1e9, 3),
-            "offered_gkeys_per_s": round(keys_meas / (arrivals[-1] - arrivals[warm]) / 1e9, 3),
-            "alone_equals_mix": "%d sampled requests %s" % (len(kept), "identical" if same
-                                                             else "DIFFER")}
-        log("serve rho %.1f: p50 %.0f us p99 %.0f us" % (rho, p50, p99))
+        leg = {"rate_req_per_s": round(rate, 1) if rho is not None else "all at once",
+               "completed": int(done),
+               "latency_us_p50": round(p50, 1), "latency_us_p99": round(p99, 1),
+               "gkeys_per_s": round(kps / 1e9, 3),
+               "max_in_flight_gb": round(max_in_flight / 1e9, 3),
+               "server_held_gb": round(held / 1e9, 3),
+               "alone_equals_mix": "%d sampled requests %s" % (len(kept), "identical" if same
+                                                                else "DIFFER")}
+        if rho is not None:
+            leg["offered_gkeys_per_s"] = round(keys_meas / (arrivals[-1] - arrivals[warm]) / 1e9, 3)
+        else:
+            res["served_gkeys_per_s"] = leg["gkeys_per_s"]
+            res["served_vs_plain"] = round(kps / cap_kps, 3)
+        res["saturated" if rho is None else "rho_%.1f" % rho] = leg
+        log("serve %s: p50 %.0f us p99 %.0f us, %.2f Gkeys/s" %
+            ("saturated" if rho is None else "rho %.1f" % rho, p50, p99, kps / 1e9))
     res["small_requests_frac"] = round(float((sizes <= 8192).mean()), 3)
     del ring, arena, outs_plain
     return res
@@ -499,6 +516,9 @@ def main():
     round_avg_ms = round_ms / max(launches, 1)
     bytes_per_round = 2 * n * 4
     achieved = bytes_per_round / (round_avg_ms * 1e-3) / 1e9
+    # a whole count-sort round: tile counts + scan of the counts + rank and scatter
+    pass_ms = count_ms / max(cl, 1) + scan_ms / max(sl, 1) + round_avg_ms
+    pass_gbps = bytes_per_round / (pass_ms * 1e-3) / 1e9
     gkeys = n / sec / 1e9
     traffic = committed_traffic()
     result = {
@@ -519,6 +539,7 @@ def main():
                    "algo": "lsd_r8", "rounds": 4},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBPS, 4),
+                     "pass_frac": round(pass_gbps / PEAK_HBM_GBPS, 4),
                      "traffic": traffic,
                      "kernel": "k_scatter<uint32, keys-only> (rank and route of one count-sort round)",
                      "algorithmic_bytes_per_launch": bytes_per_round,
@@ -528,7 +549,9 @@ def main():
                      "frac_of_copy": round(achieved / copy_gbps, 4)},
         "per_round_ms": {"count": round(count_ms / max(cl, 1), 5),
                          "tilescan": round(scan_ms / max(sl, 1), 5),
-                         "scatter": round(round_avg_ms, 5)},
+                         "scatter": round(round_avg_ms, 5),
+                         "pass": round(pass_ms, 5), "pass_gbps": round(pass_gbps, 1),
+                         "pass_frac": round(pass_gbps / PEAK_HBM_GBPS, 4)},
         "whole_sort": {"algorithmic_bytes": n * 4 + 4 * bytes_per_round,
                        "gbps": round((n * 4 + 4 * bytes_per_round) / sec / 1e9, 1),
                        "hist_kernel_ms": round(hist_ms / max(hl, 1), 5)},
@@ -558,6 +581,28 @@ def main():
             "per_pass_gbps": round(2 * n * 4 / (pass_ms * 1e-3) / 1e9, 1),
             "place_kernel_gbps": round(2 * n * 4 / (parts["place"] * 1e-3) / 1e9, 1),
             "same_as_pr4": bool(np.array_equal(got16, got))}}
+        # PR4 with single-read rounds (one counting pass, then one kernel per
+        # round that counts, looks back inside its chain of tiles and routes)
+        rsort.rsort_set_pr4_rounds("single_read")
+        s1 = time_steps(step, reps, 30, torch)
+        rsort.rsort_profile_enable(True)
+        for _ in range(reps):
+            step()
+        parts1 = {}
+        for name, kind in (("counting_pass", rsort.RSORT_KERNEL_HIST),
+                           ("chain_plan", rsort.RSORT_KERNEL_TILESCAN),
+                           ("round", rsort.RSORT_KERNEL_ROUND)):
+            cnt_l, ms = rsort.rsort_profile_read(kind)
+            parts1[name] = round(ms / max(cnt_l, 1), 5)
+        rsort.rsort_profile_enable(False)
+        got1 = out.cpu().numpy()
+        rsort.rsort_set_pr4_rounds("counted")
+        result["variants"]["lsd8_single_read"] = {
+            "algo": "PR4, single-read rounds (look-back inside chains of tiles)",
+            "ms": round(s1 * 1e3, 3), "gkeys_per_s": round(n / s1 / 1e9, 3),
+            "per_sort_or_round_ms": parts1,
+            "round_gbps": round(2 * n * 4 / (parts1["round"] * 1e-3) / 1e9, 1),
+            "same_as_pr4": bool(np.array_equal(got1, got))}
 
     if not args.no_variants:
         result["small"] = bench_small(rsort, torch, np, keygen, args)

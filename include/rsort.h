@@ -360,8 +360,9 @@ int rsort_sample_sort_stats(rsort_ctx* ctx, int p_cap, int* p_used, uint32_t* cn
  * 8192 keys) of one key type that are waiting together are sorted by one
  * launch, one workgroup each, whole in LDS; larger ones run alone through the
  * radix-2^8 sort.  Each result equals the stable sort of that request's keys
- * regardless of what else is in flight.  The caller keeps the buffers alive
- * and untouched until the request completes.
+ * regardless of what else is in flight; a request whose sort hits a device-side
+ * failure completes with RSORT_EDEVICE.  The caller keeps the buffers alive and
+ * untouched until the request completes.
  */
 typedef struct rsort_server rsort_server;
 
@@ -370,11 +371,41 @@ typedef struct rsort_server rsort_server;
 int rsort_server_create(int hip_device, size_t hbm_cap_bytes, int num_streams,
                         rsort_server** out);
 
-/* Queue one sort (thread-safe).  *ticket identifies it.  RSORT_ENOMEM if the
- * request's footprint alone exceeds the cap; RSORT_EINVAL for host pointers or
- * partially overlapping buffers; RSORT_EBUSY once destruction has begun. */
+/* Queue one sort (thread-safe).  *ticket identifies it.  The sort starts only
+ * after all work enqueued on `stream` (a hipStream_t of the server's device,
+ * NULL = the null stream) before this call: the writes of keys_in and any
+ * earlier use of keys_out may still be in flight there.  Work enqueued on
+ * `stream` later is not ordered with the sort: wait for the ticket before
+ * reading keys_out.  RSORT_ENOMEM if the request's footprint alone exceeds the
+ * cap; RSORT_EINVAL for host pointers or partially overlapping buffers;
+ * RSORT_EBUSY once destruction has begun; RSORT_EDEVICE if the stream point
+ * cannot be recorded. */
+int rsort_server_submit_async(rsort_server* sv, int key_type, const void* keys_in,
+                              void* keys_out, size_t n, void* stream, uint64_t* ticket);
+
+/* rsort_server_submit_async on the null stream. */
 int rsort_server_submit(rsort_server* sv, int key_type, const void* keys_in, void* keys_out,
                         size_t n, uint64_t* ticket);
+
+/* Allocate now, on the calling thread, the workspace that requests of up to
+ * max_n keys of key_type need on every stream slot, so that the scheduling
+ * thread allocates nothing for them (larger requests still grow a slot's
+ * workspace when they start).  Call while no request is queued or running
+ * (RSORT_EBUSY otherwise); RSORT_ENOMEM if the device memory is not there. */
+int rsort_server_reserve(rsort_server* sv, int key_type, size_t max_n);
+
+/* Test hook for the failure path: the next request that runs through the
+ * radix path (more than 8192 keys) has its slot's device error word set after
+ * its sort, exactly as a look-back wait that gave up would set it, so that it
+ * completes with RSORT_EDEVICE (poll / wait return it).  No kernel faults. */
+int rsort_server_fail_next(rsort_server* sv);
+
+/* HBM accounting: the summed footprint of the requests in flight now, its
+ * maximum since creation or the last rsort_server_reset_stats, and the device
+ * memory the server itself holds (slot workspaces, descriptors).  Any output
+ * pointer may be NULL. */
+int rsort_server_memory(rsort_server* sv, size_t* in_flight, size_t* max_in_flight,
+                        size_t* reserved);
 
 /* *done = 1 once the result is in keys_out (then returns the request's
  * status), else 0 and RSORT_OK.  Thread-safe. */

@@ -46,14 +46,13 @@ constexpr uint32_t kJointBins = kJointChains * R;     // 4096 per round
 constexpr uint32_t kQueues = 8;                       // ticket queues (XCDs)
 constexpr uint32_t kQueueStride = 32;                 // words between ticket counters
 // Chunk chains dealt together in one queue (0: all of the queue's chains).
+// More chains in flight shorten the look-back walks but space out the tiles
+// of a chain, whose output runs share cache lines, beyond what the L2 merges:
+// measured at 2^27 keys (first round, chunk chains) 233 us per round without
+// look-back at 4 or 8 chains, 244 at 16; with look-back 300 us at 8, 324 at
+// 16, 377 at 32, 385 with all 64.
 #ifndef RSORT_OS_CHUNK_GROUP
-#define RSORT_OS_CHUNK_GROUP 0
-#endif
-// 1: the look-back words are read after the ranking and folded after the
-// staging (predecessors get more time to publish); 0: read right after the
-// tile's own counts are published, folded after the ranking.
-#ifndef RSORT_OS_LATE
-#define RSORT_OS_LATE 1
+#define RSORT_OS_CHUNK_GROUP 8
 #endif
 constexpr int kOsCountWG = 512;
 constexpr int kOsReduceWG = 1024;
@@ -512,14 +511,16 @@ __global__ __launch_bounds__(kOsTicketWG) void k_os_tickets(const RoundPlan* pla
 //   load     the tile's keys (and payloads)
 //   count    per-group digit counts in LDS
 //   publish  digit thread v publishes the tile's count of v (its inclusive
-//            count at once when it is the chain's first tile) and issues the
-//            look-back loads of the 8 nearest predecessors (two halves of 4,
-//            threads v and v + 256), then the slot bases are laid out
-//   rank     stable rank in the tile (overlaps the look-back loads)
+//            count at once when it is the chain's first tile), then the slot
+//            bases are laid out
+//   rank     stable rank in the tile
+//   stage    digit thread v reads its nearest predecessor's word; the tile is
+//            staged in digit order in LDS while that read is in flight
 //   resolve  fold the predecessors' words nearest first (counts added, the
 //            first inclusive count ends the walk, a word not yet published is
-//            polled again), publish the inclusive count, output offsets
-//   write    stage in digit order, consecutive threads write consecutive keys
+//            polled again, further words 4 at a time), publish the inclusive
+//            count, output offsets
+//   write    consecutive threads write consecutive keys
 #ifndef RSORT_OS_WAVES_PER_EU
 #define RSORT_OS_WAVES_PER_EU 8
 #endif
@@ -529,7 +530,7 @@ __global__ __launch_bounds__(kOsTicketWG) void k_os_tickets(const RoundPlan* pla
 #ifndef RSORT_OS_KV_LDS_RESERVE
 #define RSORT_OS_KV_LDS_RESERVE 6144
 #endif
-constexpr int kOsHalf = 4;   // predecessor words per thread per look-back step
+constexpr int kOsWindow = 4;   // predecessor words per look-back step after the first
 
 template <typename K, bool KV, int WG, int ITEMS>
 __global__ __launch_bounds__(WG, KV ? RSORT_OS_WAVES_PER_EU_KV : RSORT_OS_WAVES_PER_EU) void k_onesweep(OsArgs a)
@@ -548,8 +549,6 @@ __global__ __launch_bounds__(WG, KV ? RSORT_OS_WAVES_PER_EU_KV : RSORT_OS_WAVES_
         } u;
         uint32_t goff[R];
         uint32_t wsum[4];
-        uint32_t lb_sum[R];              // second look-back half: sum of its words
-        uint32_t lb_state[R];            // 0 gap at lb_state >> 2, 1 all counts, 2 inclusive found
         uint4 e;
         uint32_t reserve[KV ? RSORT_OS_KV_LDS_RESERVE : 1];
     };
@@ -655,9 +654,6 @@ __global__ __launch_bounds__(WG, KV ? RSORT_OS_WAVES_PER_EU_KV : RSORT_OS_WAVES_
 
     // publish, look-back loads, slot bases
     uint32_t total = 0, run = 0;
-    const uint32_t dv = tid & (R - 1);
-    const uint32_t half = tid / R;
-    uint32_t lb[kOsHalf];
     if (tid < R) {
 #pragma unroll
         for (int g = 0; g < NG; ++g) total += sm.u.words[NG * R + g * R + tid];
@@ -666,14 +662,6 @@ __global__ __launch_bounds__(WG, KV ? RSORT_OS_WAVES_PER_EU_KV : RSORT_OS_WAVES_
         if (lane == 63) sm.wsum[wave] = incl;
         run = incl - total;
     }
-    auto lookback_loads = [&]() {
-#pragma unroll
-        for (int i = 0; i < kOsHalf; ++i) {
-            const uint32_t q = half * kOsHalf + i;
-            lb[i] = q < jpre ? ld_agent(&st[(size_t)(row - 1 - q) * R + dv]) : 0u;
-        }
-    };
-    if (!RSORT_OS_LATE) lookback_loads();
     __syncthreads();
     uint32_t hi[NG / 2];
     uint32_t tstart = 0;   // tile-local start of digit tid
@@ -733,62 +721,42 @@ __global__ __launch_bounds__(WG, KV ? RSORT_OS_WAVES_PER_EU_KV : RSORT_OS_WAVES_
         }
     }
 
-    if (RSORT_OS_LATE) {
-        lookback_loads();
-        __syncthreads();
-        // stage in digit order while the look-back words are in flight
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i)
-            if (hofs + i * G < lim) sm.u.keys[pos[i]] = k[i];
-    }
-
-    // resolve the look-back: fold words nearest first
-    //   state 0: a word not yet published at index `at`; 1: only counts
-    //   (continue past the window); 2: an inclusive count ended the walk
-    uint32_t fsum = 0, fstate = 1, fat = 0;
-#pragma unroll
-    for (int i = 0; i < kOsHalf; ++i) {
-        const uint32_t q = half * kOsHalf + i;
-        if (fstate == 1 && q < jpre) {
-            const uint32_t f = lb[i] >> kFlagShift;
-            if (f == 0) {
-                fstate = 0;
-                fat = q;
-            } else {
-                fsum += lb[i] & kCountMask;
-                if (f == (kFlagPrefix >> kFlagShift)) fstate = 2;
-            }
-        }
-    }
-    if (half == 1 && jpre > (uint32_t)kOsHalf) {
-        sm.lb_sum[dv] = fsum;
-        sm.lb_state[dv] = fstate | (fat << 2);
-    }
+    // the nearest predecessor's word, read after the ranking (predecessors get
+    // that long to publish) and folded after the staging
+    uint32_t w0 = 0;
+    if (tid < R && jpre > 0) w0 = ld_agent(&st[(size_t)(row - 1) * R + tid]);
     __syncthreads();
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i)
+        if (hofs + i * G < lim) sm.u.keys[pos[i]] = k[i];
+
+    // resolve the look-back: fold predecessor words nearest first -- counts
+    // are added and passed over, the first inclusive count ends the walk, a
+    // word not yet published is polled again
     if (tid < R) {
         uint32_t excl = 0;
         if (jpre > 0) {
-            excl = fsum;
-            uint32_t q;   // next predecessor to read, or done
-            bool done = fstate == 2;
-            q = fstate == 0 ? fat : (uint32_t)kOsHalf;
-            if (fstate == 1 && jpre > (uint32_t)kOsHalf) {
-                const uint32_t s2 = sm.lb_state[tid];
-                excl += sm.lb_sum[tid];
-                done = (s2 & 3u) == 2;
-                q = (s2 & 3u) == 0 ? (s2 >> 2) : 2u * kOsHalf;
+            uint32_t q = 0;   // next predecessor to fold
+            bool done = false;
+            {
+                const uint32_t f = w0 >> kFlagShift;
+                if (f != 0) {
+                    excl = w0 & kCountMask;
+                    q = 1;
+                    done = f == (kFlagPrefix >> kFlagShift);
+                }
             }
             uint32_t spins = 0;
             while (!done) {
                 // q < jpre here: the chain's first tile publishes an inclusive count
-                uint32_t w4[kOsHalf];
+                uint32_t w4[kOsWindow];
 #pragma unroll
-                for (int i = 0; i < kOsHalf; ++i)
+                for (int i = 0; i < kOsWindow; ++i)
                     w4[i] = q + i < jpre ? ld_agent(&st[(size_t)(row - 1 - q - i) * R + tid]) : 0u;
                 uint32_t used = 0;
                 bool gap = false;
 #pragma unroll
-                for (int i = 0; i < kOsHalf; ++i) {
+                for (int i = 0; i < kOsWindow; ++i) {
                     if (!done && !gap && q + i < jpre) {
                         const uint32_t f = w4[i] >> kFlagShift;
                         if (f == 0) {
@@ -818,13 +786,7 @@ __global__ __launch_bounds__(WG, KV ? RSORT_OS_WAVES_PER_EU_KV : RSORT_OS_WAVES_
     }
     __syncthreads();
 
-    // write: stage in digit order, consecutive threads store consecutive keys
-    if (!RSORT_OS_LATE) {
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i)
-            if (hofs + i * G < lim) sm.u.keys[pos[i]] = k[i];
-        __syncthreads();
-    }
+    // write: consecutive threads store consecutive keys of the staged tile
     uint32_t outi[KV ? ITEMS : 1];
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {

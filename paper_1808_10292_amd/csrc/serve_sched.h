@@ -31,6 +31,7 @@ struct ServeRequest {
     double t_submit = 0.0;   // seconds, host clock
     const void* keys_in = nullptr;
     void* keys_out = nullptr;
+    void* ready = nullptr;   // event the request's sort waits for (opaque here)
 };
 
 struct ServeBatch {
@@ -80,6 +81,7 @@ public:
                 }
             }
             used_ += b.footprint;
+            if (used_ > max_used_) max_used_ = used_;
             slot_busy_[slot] = true;
             slot_fp_[slot] = b.footprint;
             out.push_back(std::move(b));
@@ -98,6 +100,8 @@ public:
 
     size_t queued() const { return queue_.size(); }
     uint64_t used() const { return used_; }
+    uint64_t max_used() const { return max_used_; }
+    void reset_max_used() { max_used_ = used_; }
     uint64_t cap() const { return cap_; }
     size_t busy_slots() const
     {
@@ -119,6 +123,7 @@ private:
     uint64_t small_max_;
     size_t max_batch_;
     uint64_t used_ = 0;
+    uint64_t max_used_ = 0;
     std::vector<bool> slot_busy_;
     std::vector<uint64_t> slot_fp_;
     std::deque<ServeRequest> queue_;

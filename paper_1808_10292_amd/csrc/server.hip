@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <iterator>
@@ -90,6 +91,19 @@ void launch_serve_small(int cls, const ServeDesc* d, uint32_t count, hipStream_t
     }
 }
 
+// Clears a slot's error word in stream order (a kernel, not a memset, so the
+// sequence can sit in a captured graph).
+__global__ void k_serve_clear(uint32_t* w)
+{
+    w[threadIdx.x] = 0;
+}
+
+// Sets a failure bit in a slot's error word (rsort_server_fail_next).
+__global__ void k_serve_flag(uint32_t* w, uint32_t bits)
+{
+    w[0] |= bits;
+}
+
 double now_s()
 {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -100,6 +114,8 @@ struct Slot {
     hipEvent_t done = nullptr;
     void* ws = nullptr;
     size_t ws_bytes = 0;
+    uint32_t* err_dev = nullptr;    // device error word of this slot's sorts
+    uint32_t* err_host = nullptr;   // pinned copy, written before `done` completes
     ServeDesc* desc_host = nullptr;   // pinned
     ServeDesc* desc_dev = nullptr;
     size_t desc_cap = 0;
@@ -120,7 +136,6 @@ struct rsort_server {
     int device = 0;
     rsort::ServeScheduler sched;
     std::vector<rsort::Slot> slots;
-    uint32_t* dev_err = nullptr;
     std::mutex mu;
     std::condition_variable cv_work;   // submissions, stop
     std::condition_variable cv_done;   // completions
@@ -128,6 +143,8 @@ struct rsort_server {
     bool stop = false;
     uint64_t next_ticket = 1;
     std::unordered_map<uint64_t, rsort::TicketState> tickets;
+    std::vector<hipEvent_t> free_events;   // input-ready events of finished requests
+    std::atomic<int> fail_next{0};         // rsort_server_fail_next
     std::vector<double> latency_s;
     uint64_t keys_done = 0;
     double t_first = 0.0, t_last = 0.0;
@@ -166,6 +183,11 @@ int launch_batch(rsort_server* sv, Slot& sl)
     const ServeBatch& b = sl.batch;
     const int kb = b.key_type == RSORT_U64 ? 8 : 4;
     hipError_t e = hipSuccess;
+    // nothing of the batch starts before its inputs are written
+    for (const ServeRequest& r : b.reqs)
+        if (r.ready && hipStreamWaitEvent(sl.stream, (hipEvent_t)r.ready, 0) != hipSuccess)
+            return RSORT_EDEVICE;
+    *sl.err_host = 0;
     if (b.small) {
         const size_t cnt = b.reqs.size();
         if (cnt > sl.desc_cap) {
@@ -206,10 +228,17 @@ int launch_batch(rsort_server* sv, Slot& sl)
     } else {
         const ServeRequest& r = b.reqs[0];
         const LsdR8Layout L = lsd_r8_layout(kb, false, (size_t)r.n, 0, 8 * kb);
-        e = grow(&sl.ws, &sl.ws_bytes, L.bytes);
+        e = grow(&sl.ws, &sl.ws_bytes, L.bytes);   // no-op for requests within the reservation
         if (e != hipSuccess) return RSORT_ENOMEM;
+        hipLaunchKernelGGL(k_serve_clear, dim3(1), dim3(64), 0, sl.stream, sl.err_dev);
         e = lsd_r8_sort(kb, r.keys_in, r.keys_out, nullptr, nullptr, (size_t)r.n, 0, 8 * kb, sl.ws, L,
-                        sv->dev_err, sl.stream, nullptr);
+                        sl.err_dev, sl.stream, nullptr);
+        if (e == hipSuccess && sv->fail_next.exchange(0))
+            hipLaunchKernelGGL(k_serve_flag, dim3(1), dim3(1), 0, sl.stream, sl.err_dev,
+                               (uint32_t)kErrLookbackTimeout);
+        // the slot's error word comes back with the batch (read once `done` completes)
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(sl.err_host, sl.err_dev, sizeof(uint32_t), hipMemcpyDeviceToHost, sl.stream);
     }
     if (e != hipSuccess) return RSORT_EDEVICE;
     e = hipEventRecord(sl.done, sl.stream);
@@ -243,6 +272,8 @@ void worker_main(rsort_server* sv)
             }
             const hipError_t q = hipEventQuery(sl.done);
             if (q == hipSuccess) {
+                // a look-back wait of the sort gave up: its output is not the stable sort
+                if (*sl.err_host) sl.status = RSORT_EDEVICE;
                 finished.push_back((int)i);
             } else if (q == hipErrorNotReady) {
                 running = true;
@@ -256,6 +287,7 @@ void worker_main(rsort_server* sv)
         for (int i : finished) {
             Slot& sl = sv->slots[(size_t)i];
             for (const ServeRequest& r : sl.batch.reqs) {
+                if (r.ready) sv->free_events.push_back((hipEvent_t)r.ready);
                 TicketState& ts = sv->tickets[r.ticket];
                 ts.done = true;
                 ts.status = sl.status;
@@ -272,10 +304,15 @@ void worker_main(rsort_server* sv)
         if (!finished.empty()) sv->cv_done.notify_all();
         if (sv->stop && !running && sv->sched.queued() == 0 && sv->sched.busy_slots() == 0) break;
         if (!finished.empty() || !admitted.empty()) continue;
-        if (running)
-            sv->cv_work.wait_for(lk, std::chrono::microseconds(20));
-        else
+        if (running) {
+            // poll the running batches' events without a timed sleep (a timed
+            // wait oversleeps by tens of microseconds on a loaded host)
+            lk.unlock();
+            std::this_thread::yield();
+            lk.lock();
+        } else {
             sv->cv_work.wait_for(lk, std::chrono::milliseconds(5));
+        }
     }
 }
 
@@ -310,13 +347,25 @@ int rsort_server_create(int hip_device, size_t hbm_cap_bytes, int num_streams, r
     if (!sv) {
         rc = RSORT_ENOMEM;
     } else {
-        if (hipMalloc(&sv->dev_err, 256) != hipSuccess || hipMemset(sv->dev_err, 0, 256) != hipSuccess)
-            rc = RSORT_ENOMEM;
         for (rsort::Slot& sl : sv->slots) {
             if (rc) break;
             if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
-                hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess)
+                hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) {
                 rc = RSORT_EDEVICE;
+                break;
+            }
+            // error word and the descriptors of the largest small-request batch,
+            // so that the scheduling thread never allocates for them
+            const size_t dbytes = rsort::kServeMaxBatch * sizeof(rsort::ServeDesc);
+            if (hipMalloc((void**)&sl.err_dev, 256) != hipSuccess ||
+                hipHostMalloc((void**)&sl.err_host, 256, hipHostMallocDefault) != hipSuccess ||
+                hipHostMalloc((void**)&sl.desc_host, dbytes, hipHostMallocDefault) != hipSuccess ||
+                hipMalloc((void**)&sl.desc_dev, dbytes) != hipSuccess) {
+                rc = RSORT_ENOMEM;
+                break;
+            }
+            *sl.err_host = 0;
+            sl.desc_cap = rsort::kServeMaxBatch;
         }
         if (!rc) {
             try {
@@ -329,8 +378,11 @@ int rsort_server_create(int hip_device, size_t hbm_cap_bytes, int num_streams, r
             for (rsort::Slot& sl : sv->slots) {
                 if (sl.stream) (void)hipStreamDestroy(sl.stream);
                 if (sl.done) (void)hipEventDestroy(sl.done);
+                if (sl.err_dev) (void)hipFree(sl.err_dev);
+                if (sl.err_host) (void)hipHostFree(sl.err_host);
+                if (sl.desc_host) (void)hipHostFree(sl.desc_host);
+                if (sl.desc_dev) (void)hipFree(sl.desc_dev);
             }
-            if (sv->dev_err) (void)hipFree(sv->dev_err);
             delete sv;
             sv = nullptr;
         }
@@ -340,8 +392,8 @@ int rsort_server_create(int hip_device, size_t hbm_cap_bytes, int num_streams, r
     return rc;
 }
 
-int rsort_server_submit(rsort_server* sv, int key_type, const void* keys_in, void* keys_out,
-                        size_t n, uint64_t* ticket)
+int rsort_server_submit_async(rsort_server* sv, int key_type, const void* keys_in, void* keys_out,
+                              size_t n, void* stream, uint64_t* ticket)
 {
     if (!sv || !ticket) return RSORT_EINVAL;
     if (key_type != RSORT_U32 && key_type != RSORT_U64) return RSORT_EINVAL;
@@ -362,8 +414,37 @@ int rsort_server_submit(rsort_server* sv, int key_type, const void* keys_in, voi
     r.keys_out = keys_out;
     r.footprint = rsort::request_footprint(kb, n, keys_in == keys_out);
     if (!sv->sched.admissible(r.footprint)) return RSORT_ENOMEM;
+    if (n) {
+        // mark the point of `stream` the sort must wait for: everything enqueued
+        // there so far (the writes of keys_in, earlier uses of keys_out)
+        hipEvent_t ev = nullptr;
+        {
+            std::lock_guard<std::mutex> g(sv->mu);
+            if (!sv->free_events.empty()) {
+                ev = sv->free_events.back();
+                sv->free_events.pop_back();
+            }
+        }
+        int prev = 0;
+        (void)hipGetDevice(&prev);
+        if (prev != sv->device) (void)hipSetDevice(sv->device);
+        hipError_t e = ev ? hipSuccess : hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(ev, (hipStream_t)stream);
+        if (prev != sv->device) (void)hipSetDevice(prev);
+        if (e != hipSuccess) {
+            if (ev) {
+                std::lock_guard<std::mutex> g(sv->mu);
+                sv->free_events.push_back(ev);
+            }
+            return RSORT_EDEVICE;
+        }
+        r.ready = ev;
+    }
     std::lock_guard<std::mutex> g(sv->mu);
-    if (sv->stop) return RSORT_EBUSY;
+    if (sv->stop) {
+        if (r.ready) sv->free_events.push_back((hipEvent_t)r.ready);
+        return RSORT_EBUSY;
+    }
     r.ticket = sv->next_ticket++;
     r.t_submit = rsort::now_s();
     if (sv->t_first == 0.0) sv->t_first = r.t_submit;
@@ -376,6 +457,58 @@ int rsort_server_submit(rsort_server* sv, int key_type, const void* keys_in, voi
     sv->tickets[r.ticket] = rsort::TicketState{};
     sv->sched.push(r);
     sv->cv_work.notify_one();
+    return RSORT_OK;
+}
+
+int rsort_server_submit(rsort_server* sv, int key_type, const void* keys_in, void* keys_out,
+                        size_t n, uint64_t* ticket)
+{
+    return rsort_server_submit_async(sv, key_type, keys_in, keys_out, n, nullptr, ticket);
+}
+
+int rsort_server_reserve(rsort_server* sv, int key_type, size_t max_n)
+{
+    if (!sv) return RSORT_EINVAL;
+    if (key_type != RSORT_U32 && key_type != RSORT_U64) return RSORT_EINVAL;
+    if (max_n >= ((size_t)1 << 30)) return RSORT_EUNSUPPORTED;
+    const int kb = key_type == RSORT_U64 ? 8 : 4;
+    std::lock_guard<std::mutex> g(sv->mu);
+    if (sv->sched.queued() || sv->sched.busy_slots()) return RSORT_EBUSY;
+    if (max_n <= rsort::kServeSmallMax) return RSORT_OK;
+    const size_t need = rsort::lsd_r8_layout(kb, false, max_n, 0, 8 * kb).bytes;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    if (prev != sv->device) (void)hipSetDevice(sv->device);
+    int rc = RSORT_OK;
+    for (rsort::Slot& sl : sv->slots)
+        if (rsort::grow(&sl.ws, &sl.ws_bytes, need) != hipSuccess) {
+            rc = RSORT_ENOMEM;
+            break;
+        }
+    if (prev != sv->device) (void)hipSetDevice(prev);
+    return rc;
+}
+
+int rsort_server_fail_next(rsort_server* sv)
+{
+    if (!sv) return RSORT_EINVAL;
+    sv->fail_next.store(1);
+    return RSORT_OK;
+}
+
+int rsort_server_memory(rsort_server* sv, size_t* in_flight, size_t* max_in_flight,
+                        size_t* reserved)
+{
+    if (!sv) return RSORT_EINVAL;
+    std::lock_guard<std::mutex> g(sv->mu);
+    if (in_flight) *in_flight = (size_t)sv->sched.used();
+    if (max_in_flight) *max_in_flight = (size_t)sv->sched.max_used();
+    if (reserved) {
+        size_t r = 0;
+        for (const rsort::Slot& sl : sv->slots)
+            r += sl.ws_bytes + 2 * sl.desc_cap * sizeof(rsort::ServeDesc) + 2 * 256;
+        *reserved = r;
+    }
     return RSORT_OK;
 }
 
@@ -437,6 +570,7 @@ int rsort_server_reset_stats(rsort_server* sv)
     if (!sv) return RSORT_EINVAL;
     std::lock_guard<std::mutex> g(sv->mu);
     sv->latency_s.clear();
+    sv->sched.reset_max_used();
     sv->keys_done = 0;
     sv->t_first = sv->t_last = 0.0;
     for (auto it = sv->tickets.begin(); it != sv->tickets.end();)
@@ -465,8 +599,10 @@ int rsort_server_destroy(rsort_server* sv)
         if (sl.ws) (void)hipFree(sl.ws);
         if (sl.desc_host) (void)hipHostFree(sl.desc_host);
         if (sl.desc_dev) (void)hipFree(sl.desc_dev);
+        if (sl.err_dev) (void)hipFree(sl.err_dev);
+        if (sl.err_host) (void)hipHostFree(sl.err_host);
     }
-    if (sv->dev_err) (void)hipFree(sv->dev_err);
+    for (hipEvent_t ev : sv->free_events) (void)hipEventDestroy(ev);
     (void)hipSetDevice(prev);
     delete sv;
     return RSORT_OK;

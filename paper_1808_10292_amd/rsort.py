@@ -59,6 +59,8 @@ EXPORTED = ("rsort_create", "rsort_destroy", "rsort_status_string", "rsort_last_
             "rsort_sample_sort_random_workspace_bytes", "rsort_sample_sort_gvr",
             "rsort_sample_sort_gvr_workspace_bytes", "rsort_segmented_sort_device",
             "rsort_segmented_device_workspace_bytes", "rsort_server_create", "rsort_server_submit",
+            "rsort_server_submit_async", "rsort_server_reserve", "rsort_server_memory",
+            "rsort_server_fail_next",
             "rsort_server_poll", "rsort_server_wait", "rsort_server_latency",
             "rsort_server_reset_stats", "rsort_server_destroy")
 
@@ -141,6 +143,10 @@ def load_library():
         lib.rsort_segmented_device_workspace_bytes.argtypes = [vp, i, i, sz, sz, ctypes.POINTER(sz)]
         lib.rsort_server_create.argtypes = [i, sz, i, ctypes.POINTER(vp)]
         lib.rsort_server_submit.argtypes = [vp, i, vp, vp, sz, ctypes.POINTER(ctypes.c_uint64)]
+        lib.rsort_server_submit_async.argtypes = [vp, i, vp, vp, sz, vp, ctypes.POINTER(ctypes.c_uint64)]
+        lib.rsort_server_reserve.argtypes = [vp, i, sz]
+        lib.rsort_server_fail_next.argtypes = [vp]
+        lib.rsort_server_memory.argtypes = [vp, ctypes.POINTER(sz), ctypes.POINTER(sz), ctypes.POINTER(sz)]
         lib.rsort_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(i)]
         lib.rsort_server_wait.argtypes = [vp, ctypes.c_uint64]
         lib.rsort_server_latency.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
@@ -632,7 +638,9 @@ class Server:
         self._held = {}
         self._lock = threading.Lock()
 
-    def submit(self, keys_in, keys_out):
+    def submit(self, keys_in, keys_out, stream=None):
+        """Queue a sort that starts after the work already enqueued on `stream`
+        (default: torch's current stream), e.g. the kernel that wrote keys_in."""
         kt = _key_type(keys_in)
         n = keys_in.numel()
         if keys_out.dtype != keys_in.dtype:
@@ -640,10 +648,10 @@ class Server:
         _check_tensor(keys_in, n, "keys_in")
         _check_tensor(keys_out, n, "keys_out")
         t = ctypes.c_uint64()
-        rc = self._lib.rsort_server_submit(self.handle, kt, _ptr(keys_in), _ptr(keys_out), n,
-                                           ctypes.byref(t))
+        rc = self._lib.rsort_server_submit_async(self.handle, kt, _ptr(keys_in), _ptr(keys_out), n,
+                                                 _stream_handle(stream), ctypes.byref(t))
         if rc != RSORT_OK:
-            raise RsortError(rc, "rsort_server_submit")
+            raise RsortError(rc, "rsort_server_submit_async")
         with self._lock:
             self._held[t.value] = (keys_in, keys_out)
         return t.value
@@ -674,6 +682,27 @@ class Server:
         if rc != RSORT_OK:
             raise RsortError(rc, "rsort_server_latency")
         return p50.value, p99.value, kps.value, done.value
+
+    def reserve(self, key_type, max_n):
+        """Allocate every slot's workspace for requests of up to max_n keys now."""
+        rc = self._lib.rsort_server_reserve(self.handle, KEY_TYPES[key_type], int(max_n))
+        if rc != RSORT_OK:
+            raise RsortError(rc, "rsort_server_reserve")
+
+    def fail_next(self):
+        """Test hook: the next radix-path request completes with RSORT_EDEVICE."""
+        rc = self._lib.rsort_server_fail_next(self.handle)
+        if rc != RSORT_OK:
+            raise RsortError(rc, "rsort_server_fail_next")
+
+    def memory(self):
+        """(bytes in flight, max bytes in flight, bytes the server holds)"""
+        a, b, c = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+        rc = self._lib.rsort_server_memory(self.handle, ctypes.byref(a), ctypes.byref(b),
+                                           ctypes.byref(c))
+        if rc != RSORT_OK:
+            raise RsortError(rc, "rsort_server_memory")
+        return a.value, b.value, c.value
 
     def reset_stats(self):
         rc = self._lib.rsort_server_reset_stats(self.handle)

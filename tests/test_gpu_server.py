@@ -140,3 +140,75 @@ def test_destroy_drains_queued_requests(rs):
     torch.cuda.synchronize()
     for k, o in zip(reqs, outs):
         assert np.array_equal(host(o), oracle.sr4(k)[0])
+
+
+def test_device_failure_completes_with_edevice(rs):
+    """A sort whose slot error word is set (as a look-back that gave up would
+    set it) completes with RSORT_EDEVICE; the next request is unaffected."""
+    import torch
+    announce("server failure path")
+    srv = rs.Server(1 << 30, num_streams=2)
+    keys = keygen.uniform_u32(100000, 31)
+    d = dev(keys)
+    o = torch.empty_like(d)
+    srv.fail_next()
+    t = srv.submit(d, o)
+    with pytest.raises(rs.RsortError) as e:
+        srv.wait(t)
+    assert e.value.status == rs.RSORT_EDEVICE
+    o2 = torch.empty_like(d)
+    srv.wait(srv.submit(d, o2))
+    assert np.array_equal(host(o2), oracle.sr4(keys)[0])
+    srv.destroy()
+
+
+def test_submit_waits_for_the_producing_stream(rs):
+    """keys_in is written on a side stream behind slow work; the request is
+    submitted at once, without a host synchronisation, and must see the keys."""
+    import torch
+    announce("server stream order")
+    srv = rs.Server(1 << 30, num_streams=2)
+    n = 1 << 20
+    keys = keygen.uniform_u32(n, 32)
+    src = dev(keys)
+    side = torch.cuda.Stream()
+    junk = torch.ones(1 << 26, dtype=torch.float32, device="cuda")
+    results = []
+    for rep in range(3):
+        kin = torch.zeros(n, dtype=torch.uint32, device="cuda")
+        out = torch.empty_like(kin)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(side):
+            for _ in range(20):        # about a millisecond of work ahead of the copy
+                junk.mul_(1.0000001)
+            kin.copy_(src)
+            t = srv.submit(kin, out)  # ordered after the copy on `side`
+        srv.wait(t)
+        results.append(host(out))
+    want = oracle.sr4(keys)[0]
+    for got in results:
+        assert np.array_equal(got, want)
+    srv.destroy()
+
+
+def test_reserve_and_memory_accounting(rs):
+    import torch
+    announce("server reserve")
+    srv = rs.Server(1 << 32, num_streams=3)
+    srv.reserve("u64", 1 << 20)
+    inflight, peak, held = srv.memory()
+    assert inflight == 0 and peak == 0
+    assert held >= 3 * 8 * (1 << 20)   # each slot: at least the temporary keys of 2^20 u64
+    reqs = make_requests(12, [1 << 20, 300001, 5000, 1 << 19])
+    ins = [dev(k) for k in reqs]
+    outs = [torch.empty_like(d) for d in ins]
+    ts = [srv.submit(a, b) for a, b in zip(ins, outs)]
+    for t in ts:
+        srv.wait(t)
+    for k, o in zip(reqs, outs):
+        assert np.array_equal(host(o), oracle.sr4(k)[0])
+    inflight, peak, held2 = srv.memory()
+    assert inflight == 0 and peak > 0 and held2 == held   # nothing grew past the reservation
+    srv.reset_stats()
+    assert srv.memory()[1] == 0
+    srv.destroy()
