@@ -313,3 +313,37 @@ def test_one_array_in_place(rs, dtype, case, alias):
         ko = k
     rs.rsort_synchronize()
     assert np.array_equal(host(ko), wk) and np.array_equal(host(vo), wv)
+
+
+@pytest.mark.parametrize("dist", ["uniform", "zipf", "presorted"])
+def test_kv_2p21_pairs_xcd_sliced_tiles(rs, dist):
+    """2^21 pairs = 256 tiles, a multiple of 8: the scatter deals the tiles to
+    the XCDs in contiguous slices, which the other key-value sizes here do not
+    reach; bit-exact against the oracle."""
+    n = 1 << 21
+    announce("kv 2^21", dist)
+    keys = keygen.kv_keys(dist, n, 77)
+    vals = np.arange(n, dtype=np.uint32)
+    ko, vo = rs.sort(dev(keys), dev(vals))
+    wk, wv = oracle.sr4(keys, vals)
+    assert np.array_equal(host(ko), wk) and np.array_equal(host(vo), wv)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("dist", keygen.KV_DISTRIBUTIONS)
+def test_full_size_kv_pr4(rs, dist):
+    """The key-value workload at full size through PR4: 2^28 (key, input index)
+    pairs per distribution.  The four invariants of check_kv_invariants
+    determine the stable sort uniquely, so they stand in for the oracle at this
+    size."""
+    import torch
+    n = 1 << 28
+    announce("pr4 kv full", dist, n)
+    keys = keygen.kv_keys(dist, n)
+    dk = dev(keys)
+    dv = torch.arange(n, dtype=torch.int32, device="cuda")
+    ko, vo = torch.empty_like(dk), torch.empty_like(dv)
+    rs.rsort_sort(dk, ko, dv, vo, algo="lsd8")
+    rs.rsort_synchronize()
+    del dk, dv
+    check_kv_invariants(keys, host(ko), host(vo).view(np.uint32))

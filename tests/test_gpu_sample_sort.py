@@ -15,6 +15,7 @@ import pytest
 
 import keygen
 import oracle
+from tests.lemma2 import default_omega_and_s, gvr_n_max, lemma2_bucket_bound
 from tests.gpu_util import announce, check_kv_invariants, dev, host
 
 pytestmark = pytest.mark.gpu
@@ -250,8 +251,9 @@ def test_ger_default_oversampling_and_keys_only(rs):
 @pytest.mark.slow
 @pytest.mark.parametrize("dist", ["uniform", "zipf", "equal"])
 def test_ger_full_size_kv(rs, dist):
-    """2^28 pairs, p = 256, default s: the stable sort (four invariants) and
-    buckets near n/p (Lemma 2 bounds them with high probability)."""
+    """2^28 pairs, p = 256, default s = 1400: the stable sort (four invariants)
+    and every bucket within the sampling lemma's ceil((1 + eps)(n - p + 1)/p)
+    for rho = 1 (eps about 0.24; exceeded with probability at most 2^-28)."""
     import torch
     n = 1 << 28
     announce("ger full", dist, n)
@@ -264,7 +266,8 @@ def test_ger_full_size_kv(rs, dist):
     del dk
     st = rs.rsort_sample_sort_stats()
     assert int(st["bucket"].astype(np.uint64).sum()) == n
-    assert int(st["bucket"].max()) <= 1.25 * n / 256
+    _, s = default_omega_and_s(n)
+    assert int(st["bucket"].max()) <= lemma2_bucket_bound(n, 256, s)
     check_kv_invariants(keys, host(ko), host(vo).view(np.uint32))
 
 
@@ -403,7 +406,9 @@ def test_gvr_default_oversampling_and_errors(rs):
 @pytest.mark.parametrize("dist", ["uniform", "zipf", "equal"])
 def test_gvr_full_size_kv(rs, dist):
     """2^28 pairs, p = 256, default s: the stable sort (four invariants), the
-    bucket sizes summing to n, and the column sums of cnt equal to them."""
+    bucket sizes summing to n, the column sums of cnt equal to them, and every
+    bucket within GVR's n_max = (1 + 1/omega)(n/p) = 1.2 n/p and within the
+    sampling lemma's bound for rho = 1."""
     import torch
     n = 1 << 28
     announce("gvr full", dist, n)
@@ -417,7 +422,9 @@ def test_gvr_full_size_kv(rs, dist):
     st = rs.rsort_sample_sort_stats()
     assert int(st["bucket"].astype(np.uint64).sum()) == n
     assert np.array_equal(st["cnt"].astype(np.uint64).sum(axis=0), st["bucket"].astype(np.uint64))
-    assert int(st["bucket"].max()) <= 1.25 * n / 256
+    w, s = default_omega_and_s(n)
+    assert int(st["bucket"].max()) <= gvr_n_max(n, 256, w)
+    assert int(st["bucket"].max()) <= lemma2_bucket_bound(n, 256, s)
     check_kv_invariants(keys, host(ko), host(vo).view(np.uint32))
 
 
