@@ -121,7 +121,25 @@ struct RoundArgs {
     const uint2* tiles;      // tile list {first key, end} (segmented), or null
     const uint32_t* ntiles_dev;  // tile count known only on the device (grid is an
                                  // upper bound; surplus workgroups exit), or null
+    // Segmented sorts: per-segment round plans (a round whose digit is the same
+    // for every key of a segment is skipped for that segment).  tile_seg[t] is
+    // the large segment of tile t, seg_plan[s * (kMaxRounds + 1) + d] segment
+    // s's plan of round d; seg_or (two words per segment) collects, in round
+    // 0's count, the OR of every key's difference from its segment's first key
+    // (lsegs[s].z); all null for the plain sort.
+    const uint32_t* tile_seg = nullptr;
+    const RoundPlan* seg_plan = nullptr;
+    uint32_t* seg_or = nullptr;
+    const uint4* lsegs = nullptr;
 };
+
+// The plan of round a.round for tile t: the segment's plan in a segmented
+// sort, the sort's plan otherwise.
+__device__ __forceinline__ RoundPlan round_plan_of(const RoundArgs& a, uint32_t t)
+{
+    if (a.seg_plan) return a.seg_plan[(size_t)a.tile_seg[t] * (kMaxRounds + 1) + a.round];
+    return a.plan[a.round];
+}
 
 // First key and key count of tile t (at most TILE keys).
 __device__ __forceinline__ uint2 tile_range(const RoundArgs& a, uint32_t t, uint32_t tile_keys)
@@ -435,26 +453,29 @@ __global__ __launch_bounds__(WG) void k_count(RoundArgs a, uint32_t* mixed)
     static_assert(ITEMS % VEC == 0, "whole vectors per thread");
     __shared__ uint32_t h[R * 32];
     __shared__ uint32_t mix_s[2];
+    // with a device-side tile count the grid (a.ntiles) is an upper bound
+    const uint32_t tile = xcd_tile(a.ntiles);
+    if (a.ntiles_dev && tile >= *a.ntiles_dev) return;
     RoundPlan pl;
     if (ALL) {
         pl = RoundPlan{1, 0, 0, 0};
     } else {
-        pl = a.plan[a.round];
+        pl = round_plan_of(a, tile);
         if (pl.exec != 1) return;
     }
     const uint32_t tid = threadIdx.x;
     for (uint32_t i = tid; i < R * 32 / 4; i += WG) ((uint4*)h)[i] = make_uint4(0, 0, 0, 0);
     if (ALL && tid < 2) mix_s[tid] = 0;
     __syncthreads();
-    // with a device-side tile count the grid (a.ntiles) is an upper bound
-    const uint32_t tile = xcd_tile(a.ntiles);
-    if (a.ntiles_dev && tile >= *a.ntiles_dev) return;
     const uint2 tr = tile_range(a, tile, TILE);
     const uint32_t base = tr.x;
     const uint32_t lim = tr.y;
     const K* src = pick<K>(pl.src, (const K*)a.keys_in, (K*)a.keys_out, (K*)a.keys_tmp) + base;
     const uint32_t col = tid & 31;
-    const K ref = ALL ? ((const K*)a.keys_in)[0] : K(0);
+    // identity test: differences from the first key of the array, or of the
+    // tile's segment
+    const K ref = !ALL ? K(0) : a.seg_or ? ((const K*)a.keys_in)[a.lsegs[a.tile_seg[tile]].z]
+                                         : ((const K*)a.keys_in)[0];
     K acc = 0;
     K k[ITEMS];
     const bool vec = RSORT_COUNT_VEC && !a.tiles && lim == TILE && ((uintptr_t)src & 15) == 0;
@@ -502,7 +523,8 @@ __global__ __launch_bounds__(WG) void k_count(RoundArgs a, uint32_t* mixed)
     __syncthreads();
     if (ALL && tid < 2) {
         // only bits the workgroup's pair lacks cost an atomic
-        uint32_t* mw = &mixed[(blockIdx.x % kMixSlots) * kMixStride + tid];
+        uint32_t* mw = a.seg_or ? &a.seg_or[2 * a.tile_seg[tile] + tid]
+                                : &mixed[(blockIdx.x % kMixSlots) * kMixStride + tid];
         const uint32_t mine = mix_s[tid];
         if (mine & ~ld_agent(mw)) atomicOr(mw, mine);
     }
@@ -654,7 +676,19 @@ __global__ __launch_bounds__(WG, !KV ? RSORT_R8_WAVES_PER_EU : sizeof(K) == 4 ? 
     };
     __shared__ Smem sm;
 
-    const RoundPlan pl = a.plan[a.round];
+    // Tile sequence of this workgroup: with a grid smaller than the tile count
+    // each workgroup loops.  When both counts are multiples of 8 every XCD owns
+    // a contiguous eighth of the tiles (blocks are dealt to XCDs in turn), so
+    // neighbouring tiles write their shared cache lines through the same L2.
+    const uint32_t b = blockIdx.x, nb = gridDim.x;
+    const uint32_t ntiles = a.ntiles_dev ? *a.ntiles_dev : a.ntiles;
+    const bool xcd = (a.ntiles & 7) == 0 && (nb & 7) == 0;
+    const uint32_t per = a.ntiles >> 3, g8 = nb >> 3, x = b & 7;
+    uint32_t tile = xcd ? x * per + (b >> 3) : b;
+    // a per-segment plan needs the tile; the plain sort's plan is read even by
+    // surplus workgroups (its copy round covers the whole array)
+    if (a.seg_plan && tile >= ntiles) return;
+    const RoundPlan pl = a.seg_plan ? round_plan_of(a, tile) : a.plan[a.round];
     if (!pl.exec) return;
 
     const uint32_t tid = threadIdx.x;
@@ -667,6 +701,26 @@ __global__ __launch_bounds__(WG, !KV ? RSORT_R8_WAVES_PER_EU : sizeof(K) == 4 ? 
     const uint32_t* vsrc = KV ? pick<uint32_t>(pl.src, a.vals_in, a.vals_out, a.vals_tmp) : nullptr;
     K* dst = pick<K>(pl.dst, (const K*)a.keys_in, (K*)a.keys_out, (K*)a.keys_tmp);
     uint32_t* vdst = KV ? pick<uint32_t>(pl.dst, a.vals_in, a.vals_out, a.vals_tmp) : nullptr;
+    if (pl.exec == 2 && a.tiles) {   // a segment's rounds are all identities: copy the tile
+        const uint2 tr = tile_range(a, tile, TILE);
+        K kk[ITEMS];
+        uint32_t vv[ITEMS];
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const uint32_t i = j * WG + tid;
+            kk[j] = i < tr.y ? src[tr.x + i] : K(0);
+            if (KV) vv[j] = i < tr.y ? vsrc[tr.x + i] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const uint32_t i = j * WG + tid;
+            if (i < tr.y) {
+                dst[tr.x + i] = kk[j];
+                if (KV) vdst[tr.x + i] = vv[j];
+            }
+        }
+        return;
+    }
     if (pl.exec == 2) {   // identity round standing for a copy: tile by tile, loads first
         for (uint32_t t = blockIdx.x; (size_t)t * TILE < a.n; t += gridDim.x) {
             K kk[ITEMS];
@@ -907,15 +961,6 @@ __global__ __launch_bounds__(WG, !KV ? RSORT_R8_WAVES_PER_EU : sizeof(K) == 4 ? 
         __syncthreads();   // staging and goff are free for the next tile
     };
 
-    // Tile sequence of this workgroup: with a grid smaller than the tile count
-    // each workgroup loops.  When both counts are multiples of 8 every XCD owns
-    // a contiguous eighth of the tiles (blocks are dealt to XCDs in turn), so
-    // neighbouring tiles write their shared cache lines through the same L2.
-    const uint32_t b = blockIdx.x, nb = gridDim.x;
-    const uint32_t ntiles = a.ntiles_dev ? *a.ntiles_dev : a.ntiles;
-    const bool xcd = (a.ntiles & 7) == 0 && (nb & 7) == 0;
-    const uint32_t per = a.ntiles >> 3, g8 = nb >> 3, x = b & 7;
-    uint32_t tile = xcd ? x * per + (b >> 3) : b;
     auto next_of = [&](uint32_t t) -> uint32_t {
         if (xcd) {
             const uint32_t l = t - x * per + g8;

@@ -94,6 +94,7 @@ struct SegPlan {
     std::vector<uint2> small[3];   // {first key, end} per small segment, by class
     std::vector<uint2> tiles;      // {first key, end} per tile of the large segments
     std::vector<uint4> lsegs;      // {first tile, end tile, first key, 0} per large segment
+    std::vector<uint32_t> tile_seg;   // large segment (index into lsegs) of every tile
 };
 constexpr uint32_t kSmallMaxDefault = 8192;
 void segmented_plan(const uint64_t* offsets, size_t num_segs, uint32_t small_max, int key_bytes,
@@ -112,7 +113,7 @@ hipError_t segmented_sort(int key_bytes, const void* keys_in, void* keys_out,
 struct DevSegLayout {
     uint32_t max_tiles;   // upper bound of the tile count: ceil(n / tile) + nseg, rounded up to 8
     size_t off_tmp_keys, off_tmp_vals, off_counts, off_plan, off_small, off_tiles, off_lsegs,
-        off_ntiles;
+        off_ntiles, off_tile_seg, off_seg_or, off_seg_plan;
     size_t bytes;
 };
 DevSegLayout devseg_layout(int key_bytes, bool has_vals, size_t n, uint32_t nseg);

@@ -66,8 +66,9 @@ __global__ __launch_bounds__(WG) void k_seg_small(const K* __restrict__ keys_in,
 __global__ __launch_bounds__(R) void k_segscan(RoundArgs a, const uint4* lsegs)
 {
     __shared__ uint32_t wsum[4];
-    const RoundPlan pl = a.plan[a.round];
-    if (!pl.exec) return;
+    const RoundPlan pl = a.seg_plan ? a.seg_plan[(size_t)blockIdx.x * (kMaxRounds + 1) + a.round]
+                                    : a.plan[a.round];
+    if (pl.exec != 1) return;
     const uint4 sg = lsegs[blockIdx.x];
     const uint32_t v = threadIdx.x;
     uint32_t* col = a.counts + v;
@@ -98,6 +99,29 @@ __global__ __launch_bounds__(R) void k_segscan(RoundArgs a, const uint4* lsegs)
                 run += c[j];
             }
     }
+}
+
+// Zero `words` words (the segments' identity words before round 0's count).
+__global__ void k_zero_words(uint32_t* words, uint32_t count)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
+        words[i] = 0;
+}
+
+// k_seg_plans: thread s turns segment s's identity words (the OR of every key's
+// difference from the segment's first key, from round 0's count) into its
+// round plan: a round whose digit bits are zero there is the identity for the
+// segment and is skipped, with the rounds that run alternating between the
+// temporary and the output so that the last one writes the output.
+__global__ void k_seg_plans(const uint32_t* seg_or, uint32_t nseg, uint32_t nrounds, int alias,
+                            RoundPlan* seg_plan)
+{
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nseg) return;
+    const uint64_t mx = (uint64_t)seg_or[2 * s] | ((uint64_t)seg_or[2 * s + 1] << 32);
+    int identity[kMaxRounds];
+    for (uint32_t d = 0; d < nrounds; ++d) identity[d] = ((mx >> (8u * d)) & 0xFFull) == 0;
+    plan_rounds(identity, nrounds, alias, seg_plan + (size_t)s * (kMaxRounds + 1));
 }
 
 // Small-segment kernel classes: capacity = WG * ITEMS keys.
@@ -297,6 +321,7 @@ void segmented_plan(const uint64_t* off, size_t nsegs, uint32_t small_max, int k
     P.small[2].clear();
     P.tiles.clear();
     P.lsegs.clear();
+    P.tile_seg.clear();
     const uint32_t tile = large_tile(key_bytes);
     for (size_t s = 0; s < nsegs; ++s) {
         const uint32_t lo = (uint32_t)off[s], hi = (uint32_t)off[s + 1];
@@ -309,7 +334,10 @@ void segmented_plan(const uint64_t* off, size_t nsegs, uint32_t small_max, int k
             P.small[cls].push_back(make_uint2(lo, hi));
         } else {
             const uint32_t t0 = (uint32_t)P.tiles.size();
-            for (uint32_t b = lo; b < hi; b += tile) P.tiles.push_back(make_uint2(b, std::min(hi, b + tile)));
+            for (uint32_t b = lo; b < hi; b += tile) {
+                P.tiles.push_back(make_uint2(b, std::min(hi, b + tile)));
+                P.tile_seg.push_back((uint32_t)P.lsegs.size());
+            }
             P.lsegs.push_back(make_uint4(t0, (uint32_t)P.tiles.size(), lo, 0));
         }
     }
@@ -322,6 +350,8 @@ size_t segmented_ws_bytes(int key_bytes, bool has_vals, size_t total, const SegP
     o = align_up(o + (P.tiles.empty() ? 0 : total * key_bytes));          // tmp keys
     o = align_up(o + (P.tiles.empty() || !has_vals ? 0 : total * 4));      // tmp vals
     o = align_up(o + nt * R * 4);                                          // tile counts
+    o = align_up(o + P.lsegs.size() * 2 * 4);                              // segment identity words
+    o = align_up(o + P.lsegs.size() * (kMaxRounds + 1) * sizeof(RoundPlan)); // segment plans
     o = align_up(o + segmented_meta_bytes(P));                             // plan + lists
     return o;
 }
@@ -330,13 +360,14 @@ size_t segmented_meta_bytes(const SegPlan& P)
 {
     return align_up((kMaxRounds + 1) * sizeof(RoundPlan), 16) +
            (P.small[0].size() + P.small[1].size() + P.small[2].size() + P.tiles.size()) * sizeof(uint2) +
-           P.lsegs.size() * sizeof(uint4);
+           P.lsegs.size() * sizeof(uint4) + P.tile_seg.size() * sizeof(uint32_t);
 }
 
 // Pack the round plan and the lists into `host` (pinned): plan, small[0..2],
-// tiles, lsegs.  Large segments run every round (no identity skipping), so the
-// plan is static; the key width gives an even number of rounds, which ends in
-// the output whether or not the sort is in place.
+// tiles, lsegs, tile_seg.  The large segments' rounds follow per-segment plans
+// made on the device after round 0's count (k_seg_plans); the static plan here
+// (every round runs; an even number of rounds ends in the output) is the
+// reference layout of the lists only.
 void segmented_pack(const SegPlan& P, int key_bytes, void* host)
 {
     uint8_t* h = (uint8_t*)host;
@@ -363,6 +394,8 @@ void segmented_pack(const SegPlan& P, int key_bytes, void* host)
     memcpy(h, P.tiles.data(), P.tiles.size() * sizeof(uint2));
     h += P.tiles.size() * sizeof(uint2);
     memcpy(h, P.lsegs.data(), P.lsegs.size() * sizeof(uint4));
+    h += P.lsegs.size() * sizeof(uint4);
+    memcpy(h, P.tile_seg.data(), P.tile_seg.size() * sizeof(uint32_t));
 }
 
 namespace {
@@ -380,6 +413,9 @@ hipError_t run_segmented(const void* keys_in, void* keys_out, const uint32_t* va
     K* keys_tmp = (K*)(w + o);          o = align_up(o + (nt ? total * sizeof(K) : 0));
     uint32_t* vals_tmp = (uint32_t*)(w + o); o = align_up(o + (nt && KV ? total * 4 : 0));
     uint32_t* counts = (uint32_t*)(w + o);   o = align_up(o + nt * R * 4);
+    const uint32_t nls = (uint32_t)P.lsegs.size();
+    uint32_t* seg_or = (uint32_t*)(w + o);   o = align_up(o + nls * 2 * 4);
+    RoundPlan* seg_plan = (RoundPlan*)(w + o); o = align_up(o + nls * (kMaxRounds + 1) * sizeof(RoundPlan));
     uint8_t* meta = w + o;
     const size_t meta_bytes = segmented_meta_bytes(P);
     hipError_t e = hipSuccess;
@@ -397,6 +433,8 @@ hipError_t run_segmented(const void* keys_in, void* keys_out, const uint32_t* va
     const uint2* tiles = (const uint2*)m;
     m += nt * sizeof(uint2);
     const uint4* lsegs = (const uint4*)m;
+    m += nls * sizeof(uint4);
+    const uint32_t* tile_seg = (const uint32_t*)m;
 
     if (prof) profiler_mark(prof, stream, kKindSmall, true);
     for (int c = 0; c < 3; ++c)
@@ -405,10 +443,15 @@ hipError_t run_segmented(const void* keys_in, void* keys_out, const uint32_t* va
     if (prof) profiler_mark(prof, stream, kKindSmall, false);
     if (!nt) return hipGetLastError();
 
-    // Large segments: every round runs; the plan arrived with the lists.
+    // Large segments: round 0's count also takes every segment's identity
+    // words, from which k_seg_plans makes the per-segment round plans.
     constexpr int WG = R8Config<K>::WG;
     constexpr int ITEMS = R8Config<K>::ITEMS;
     const int rounds = (int)nrounds;
+    const bool keys_alias = keys_in == keys_out, vals_alias = KV && vals_in == vals_out;
+    const int alias = (keys_alias || vals_alias ? kAliasAny : 0) |
+                      (keys_alias && (!KV || vals_alias) ? kAliasAll : 0);
+    hipLaunchKernelGGL(k_zero_words, dim3((2 * nls + 255) / 256), dim3(256), 0, stream, seg_or, 2 * nls);
     for (int d = 0; d < rounds; ++d) {
         RoundArgs a;
         a.keys_in = keys_in;
@@ -430,8 +473,19 @@ hipError_t run_segmented(const void* keys_in, void* keys_out, const uint32_t* va
         a.err = dev_err;
         a.tiles = tiles;
         a.ntiles_dev = nullptr;
+        a.tile_seg = tile_seg;
+        a.seg_plan = seg_plan;
+        a.lsegs = lsegs;
         if (prof) profiler_mark(prof, stream, kKindCount, true);
-        hipLaunchKernelGGL((k_count<K, R8Config<K>::CWG, R8Config<K>::CITEMS, false>), dim3(nt), dim3(R8Config<K>::CWG), 0, stream, a, nullptr);
+        if (d == 0) {
+            a.seg_or = seg_or;
+            hipLaunchKernelGGL((k_count<K, R8Config<K>::CWG, R8Config<K>::CITEMS, true>), dim3(nt), dim3(R8Config<K>::CWG), 0, stream, a, nullptr);
+            a.seg_or = nullptr;
+            hipLaunchKernelGGL(k_seg_plans, dim3((nls + 255) / 256), dim3(256), 0, stream, (const uint32_t*)seg_or,
+                               nls, nrounds, alias, seg_plan);
+        } else {
+            hipLaunchKernelGGL((k_count<K, R8Config<K>::CWG, R8Config<K>::CITEMS, false>), dim3(nt), dim3(R8Config<K>::CWG), 0, stream, a, nullptr);
+        }
         if (prof) profiler_mark(prof, stream, kKindCount, false);
         if (prof) profiler_mark(prof, stream, kKindTileScan, true);
         hipLaunchKernelGGL(k_segscan, dim3((uint32_t)P.lsegs.size()), dim3(R), 0, stream, a, lsegs);
@@ -495,6 +549,7 @@ __global__ __launch_bounds__(kPlanWG) void k_devseg_plan(const uint32_t* off, ui
                                                          const uint32_t* dev_rounds,
                                                          RoundPlan* plan, uint2* small,
                                                          uint2* tiles, uint4* lsegs,
+                                                         uint32_t* tile_seg,
                                                          uint32_t* ntiles, uint32_t* err)
 {
     __shared__ uint32_t wsum[kPlanWG / 64];
@@ -555,6 +610,7 @@ __global__ __launch_bounds__(kPlanWG) void k_devseg_plan(const uint32_t* off, ui
             for (uint32_t b = 0; b < nt; ++b) {
                 const uint32_t first = lo + b * tile;
                 tiles[t0 + b] = make_uint2(first, min(hi, first + tile));
+                tile_seg[t0 + b] = j;
             }
         }
         base += total;
@@ -578,10 +634,14 @@ hipError_t run_devseg(const void* keys_in, void* keys_out, const uint32_t* vals_
     uint2* tiles = (uint2*)(w + L.off_tiles);
     uint4* lsegs = (uint4*)(w + L.off_lsegs);
     uint32_t* ntiles = (uint32_t*)(w + L.off_ntiles);
+    uint32_t* tile_seg = (uint32_t*)(w + L.off_tile_seg);
+    uint32_t* seg_or = (uint32_t*)(w + L.off_seg_or);
+    RoundPlan* seg_plan = (RoundPlan*)(w + L.off_seg_plan);
     const uint32_t rounds = sizeof(K);
     hipLaunchKernelGGL(k_devseg_plan, dim3(1), dim3(kPlanWG), 0, stream, off, nseg, (uint32_t)n,
                        small_max, large_tile(sizeof(K)), rounds, dev_rounds, plan, small, tiles,
-                       lsegs, ntiles, dev_err);
+                       lsegs, tile_seg, ntiles, dev_err);
+    hipLaunchKernelGGL(k_zero_words, dim3((2 * nseg + 255) / 256), dim3(256), 0, stream, seg_or, 2 * nseg);
     if (prof) profiler_mark(prof, stream, kKindSmall, true);
     for (int c = 0; c < 3; ++c)
         launch_small<K, KV>(c, keys_in, keys_out, KV ? vals_in : nullptr, KV ? vals_out : nullptr,
@@ -589,6 +649,9 @@ hipError_t run_devseg(const void* keys_in, void* keys_out, const uint32_t* vals_
     if (prof) profiler_mark(prof, stream, kKindSmall, false);
     constexpr int WG = R8Config<K>::WG;
     constexpr int ITEMS = R8Config<K>::ITEMS;
+    const bool keys_alias = keys_in == keys_out, vals_alias = KV && vals_in == vals_out;
+    const int alias = (keys_alias || vals_alias ? kAliasAny : 0) |
+                      (keys_alias && (!KV || vals_alias) ? kAliasAll : 0);
     for (uint32_t d = 0; d < rounds; ++d) {
         RoundArgs a;
         a.keys_in = keys_in;
@@ -610,8 +673,21 @@ hipError_t run_devseg(const void* keys_in, void* keys_out, const uint32_t* vals_
         a.err = dev_err;
         a.tiles = tiles;
         a.ntiles_dev = ntiles;
+        a.tile_seg = tile_seg;
+        a.seg_plan = seg_plan;
+        a.lsegs = lsegs;
         if (prof) profiler_mark(prof, stream, kKindCount, true);
-        hipLaunchKernelGGL((k_count<K, R8Config<K>::CWG, R8Config<K>::CITEMS, false>), dim3(L.max_tiles), dim3(R8Config<K>::CWG), 0, stream, a, nullptr);
+        if (d == 0) {
+            // round 0's count also takes the segments' identity words, from
+            // which every large segment gets its own round plan
+            a.seg_or = seg_or;
+            hipLaunchKernelGGL((k_count<K, R8Config<K>::CWG, R8Config<K>::CITEMS, true>), dim3(L.max_tiles), dim3(R8Config<K>::CWG), 0, stream, a, nullptr);
+            a.seg_or = nullptr;
+            hipLaunchKernelGGL(k_seg_plans, dim3((nseg + 255) / 256), dim3(256), 0, stream,
+                               (const uint32_t*)seg_or, nseg, rounds, alias, seg_plan);
+        } else {
+            hipLaunchKernelGGL((k_count<K, R8Config<K>::CWG, R8Config<K>::CITEMS, false>), dim3(L.max_tiles), dim3(R8Config<K>::CWG), 0, stream, a, nullptr);
+        }
         if (prof) profiler_mark(prof, stream, kKindCount, false);
         if (prof) profiler_mark(prof, stream, kKindTileScan, true);
         hipLaunchKernelGGL(k_segscan, dim3(nseg), dim3(R), 0, stream, a, (const uint4*)lsegs);
@@ -639,6 +715,9 @@ DevSegLayout devseg_layout(int key_bytes, bool has_vals, size_t n, uint32_t nseg
     L.off_tiles = o;     o = align_up(o + (size_t)L.max_tiles * sizeof(uint2));
     L.off_lsegs = o;     o = align_up(o + (size_t)nseg * sizeof(uint4));
     L.off_ntiles = o;    o = align_up(o + 4);
+    L.off_tile_seg = o;  o = align_up(o + (size_t)L.max_tiles * 4);
+    L.off_seg_or = o;    o = align_up(o + (size_t)nseg * 2 * 4);
+    L.off_seg_plan = o;  o = align_up(o + (size_t)nseg * (kMaxRounds + 1) * sizeof(RoundPlan));
     L.bytes = o;
     return L;
 }

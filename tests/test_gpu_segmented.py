@@ -303,3 +303,68 @@ def test_device_offsets_invalid_are_reported(rs):
         assert e.value.status == rs.RSORT_EDEVICE
         assert np.array_equal(host(ko), keys)
     rs.rsort_synchronize()   # the error word was cleared
+
+
+def shaped_segments(kind, sizes, seed, dtype=np.uint32):
+    """Keys whose digits are constant inside a segment in different ways, so
+    that segments skip different rounds: a per-segment high half, a constant
+    low byte, a constant interior byte, all-equal segments, and uniform ones."""
+    parts = []
+    for i, s in enumerate(sizes):
+        if dtype == np.uint32:
+            u = keygen.uniform_u32(int(s), seed + i)
+        else:
+            u = keygen.uniform_u64(int(s), seed + i)
+        k = (i + kind) % 5
+        if k == 0:      # only the low 16 bits vary; the rest is the segment's own
+            base = dtype(((i * 0x9E3779B1) & 0xFFFF) << 16)
+            u = (u & dtype(0xFFFF)) | base
+        elif k == 1:    # low byte constant
+            u = (u & ~dtype(0xFF)) | dtype(0x5A)
+        elif k == 2:    # an interior byte constant
+            u = (u & ~dtype(0xFF00)) | dtype(0x3C00)
+        elif k == 3:    # all equal
+            u = np.full(int(s), u[0] if s else 0, dtype=dtype)
+        parts.append(u.astype(dtype))
+    return np.concatenate(parts) if parts else np.zeros(0, dtype=dtype)
+
+
+@pytest.mark.parametrize("dtype", [np.uint32, np.uint64])
+@pytest.mark.parametrize("with_vals", [False, True])
+@pytest.mark.parametrize("in_place", [False, True])
+def test_per_segment_identity_rounds(rs, dtype, with_vals, in_place):
+    """Large segments skip the rounds whose digit is constant inside them (each
+    segment its own plan, ending in the output); bit-exact against the
+    oracle, tiled path only (split 0) and mixed with in-LDS segments."""
+    sizes = [20000, 8193, 70001, 16384, 30000, 9000, 100003, 5000, 8192, 65536, 12345, 0, 40000]
+    for kind in range(5):
+        keys = shaped_segments(kind, sizes, 90 + kind, dtype)
+        for split in (0, 8192):
+            announce("seg identity", dtype.__name__, with_vals, in_place, kind, split)
+            rs.rsort_segmented_set_split(split)
+            run_case(rs, keys, sizes, with_vals, in_place)
+    rs.rsort_segmented_set_split(8192)
+
+
+@pytest.mark.parametrize("with_vals", [False, True])
+def test_per_segment_identity_rounds_device_offsets(rs, with_vals):
+    """The same through the device-planned path (offsets in device memory)."""
+    import torch
+    sizes = [20000, 8193, 70001, 16384, 30000, 9000, 100003, 5000, 8192, 65536, 12345, 0, 40000]
+    for kind in range(5):
+        keys = shaped_segments(kind, sizes, 120 + kind)
+        off = keygen.offsets_from_sizes(np.asarray(sizes))
+        n = keys.size
+        vals = np.arange(n, dtype=np.uint32)
+        announce("seg identity device", with_vals, kind)
+        wk, wv = oracle.segmented(keys, vals if with_vals else None, off)
+        dk = dev(keys)
+        dv = dev(vals) if with_vals else None
+        ko = torch.empty_like(dk)
+        vo = torch.empty_like(dv) if with_vals else None
+        doff = dev(off.astype(np.uint32))
+        rs.rsort_segmented_sort_device(dk, ko, doff, dv, vo)
+        rs.rsort_synchronize()
+        assert np.array_equal(host(ko), wk)
+        if with_vals:
+            assert np.array_equal(host(vo), wv)
