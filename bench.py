@@ -118,6 +118,7 @@ def bench_batched(rsort, torch, np, keygen, args):
                                            reps, 1, torch) * 1e3, 3)
     split, tune_ms = rsort.rsort_segmented_tune(dk, out, off, reps=3)
     sorter = {v: k for k, v in rsort.SMALL_SORTS.items()}[rsort.rsort_segmented_get_small_sort()]
+    tuned = rsort.rsort_segmented_get_config()
     # per-call latency: submit -> completion, one call at a time
     lat = []
     for _ in range(reps):
@@ -150,6 +151,9 @@ def bench_batched(rsort, torch, np, keygen, args):
     return {"workload": "4096 arrays, lognormal sizes (median 4096, sigma 1.5, clip [16, 2^20]), "
                         "uniform u32 keys, keys only",
             "keys": total, "split_small_max": split, "small_sorter": sorter,
+            "tuned": {"split": tuned["split"], "small_sorter": sorter,
+                      "tile_threads": tuned["tile_threads"], "radix_bits": tuned["radix_bits"],
+                      "tune_ms": round(tune_ms, 3)},
             "small_sorter_ms_at_split_4096": sorter_ms,
             "batched_ms": round(batched * 1e3, 3), "batched_gkeys_per_s": round(total / batched / 1e9, 3),
             "graph_replay_ms": round(graph * 1e3, 3),

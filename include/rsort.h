@@ -226,6 +226,21 @@ int rsort_segmented_sort_device(rsort_ctx* ctx, int key_type, const void* keys_i
 int rsort_segmented_device_workspace_bytes(rsort_ctx* ctx, int key_type, int has_vals,
                                            size_t num_segs, size_t total_n, size_t* bytes);
 
+/* Tile of the large segments' tiled rounds: the workgroup size of the count
+ * and scatter kernels, 256, 512 or 1024 threads (16 keys per thread for
+ * 32-bit keys, 8 for 64-bit ones: tiles of 4096 / 8192 / 16384 or 2048 /
+ * 4096 / 8192 keys); 0 restores the default, 512.  Chosen by the tuner;
+ * applies to later calls on ctx.  RSORT_EINVAL for other values. */
+int rsort_segmented_set_tile(rsort_ctx* ctx, int tile_threads);
+
+/* The segmented sort's current configuration on ctx: the small/large split,
+ * the small-segment sorter, the tile workgroup size of the large path and
+ * the radix width in bits of every count-sort round (8: the rounds of the
+ * segmented sort are the paper's radix-2^8 rounds; a wider radix has no tile
+ * that fits LDS with per-group ranking slots).  Any output may be NULL. */
+int rsort_segmented_get_config(rsort_ctx* ctx, uint32_t* small_max, int* small_sort,
+                               int* tile_threads, int* radix_bits);
+
 /* Largest segment sorted whole in LDS (<= 8192; 0 sends every segment through
  * the tiled path).  Chosen by the tuner; applies to later calls on ctx. */
 int rsort_segmented_set_split(rsort_ctx* ctx, uint32_t small_max);
@@ -250,10 +265,11 @@ int rsort_segmented_set_small_sort(rsort_ctx* ctx, int small_sort);
 int rsort_segmented_get_small_sort(rsort_ctx* ctx, int* small_sort);
 
 /* Tuner for the segmented sort: sorts the given batch (into keys_out /
- * vals_out) reps times with each candidate split (0, 1024, 4096, 8192 keys)
- * and each small-segment sorter, keeps the fastest pair on ctx and returns its
- * split (the sorter: rsort_segmented_get_small_sort), with its time per sort
- * in ms.  Synchronises the stream. */
+ * vals_out) reps times with each candidate split (0, 1024, 4096, 8192 keys),
+ * each small-segment sorter and each tile workgroup of the large path (256,
+ * 512, 1024 threads), keeps the fastest combination on ctx and returns its
+ * split (the rest: rsort_segmented_get_config), with its time per sort in ms.
+ * Synchronises the stream. */
 int rsort_segmented_tune(rsort_ctx* ctx, int key_type, const void* keys_in, void* keys_out,
                          const uint32_t* vals_in, uint32_t* vals_out,
                          const uint64_t* seg_offsets, size_t num_segs, int reps, void* stream,

@@ -132,6 +132,7 @@ struct rsort_ctx {
     bool meta_pending = false;
     uint32_t small_max = rsort::kSmallMaxDefault;
     int small_sort = RSORT_SMALL_RADIX;   // sorter of the small segments
+    int seg_tile_shape = rsort::kSegTileShapeDefault;   // tiles of the large segments
     int pr4_rounds = RSORT_PR4_COUNTED;  // round kind of RSORT_LSD_R8
     rsort::SegPlan plan;
     uint64_t upload_sig = 0;         // plan last uploaded into upload_ws
@@ -810,7 +811,7 @@ int rsort_segmented_workspace_bytes(rsort_ctx* ctx, int key_type, int has_vals,
     int rc = check_offsets(ctx, seg_offsets, num_segs, &total);
     if (rc) return rc;
     rsort::SegPlan P;
-    rsort::segmented_plan(seg_offsets, num_segs, ctx->small_max, kb, P);
+    rsort::segmented_plan(seg_offsets, num_segs, ctx->small_max, kb, P, ctx->seg_tile_shape);
     *bytes = rsort::segmented_ws_bytes(kb, has_vals != 0, total, P);
     return RSORT_OK;
 }
@@ -892,6 +893,31 @@ int rsort_set_pr4_rounds(rsort_ctx* ctx, int kind)
     return RSORT_OK;
 }
 
+int rsort_segmented_set_tile(rsort_ctx* ctx, int tile_threads)
+{
+    if (!ctx) return RSORT_EINVAL;
+    int shape = -1;
+    if (tile_threads == 0) shape = rsort::kSegTileShapeDefault;
+    else if (tile_threads == 256) shape = 0;
+    else if (tile_threads == 512) shape = 1;
+    else if (tile_threads == 1024) shape = 2;
+    if (shape < 0) return fail(ctx, RSORT_EINVAL, "tile workgroup of %d threads (256, 512, 1024)", tile_threads);
+    ctx->seg_tile_shape = shape;
+    return RSORT_OK;
+}
+
+int rsort_segmented_get_config(rsort_ctx* ctx, uint32_t* small_max, int* small_sort,
+                               int* tile_threads, int* radix_bits)
+{
+    if (!ctx) return RSORT_EINVAL;
+    static const int threads[rsort::kSegTileShapes] = {256, 512, 1024};
+    if (small_max) *small_max = ctx->small_max;
+    if (small_sort) *small_sort = ctx->small_sort;
+    if (tile_threads) *tile_threads = threads[ctx->seg_tile_shape];
+    if (radix_bits) *radix_bits = 8;
+    return RSORT_OK;
+}
+
 int rsort_segmented_set_split(rsort_ctx* ctx, uint32_t small_max)
 {
     if (!ctx) return RSORT_EINVAL;
@@ -932,7 +958,7 @@ int rsort_segmented_sort(rsort_ctx* ctx, int key_type, const void* keys_in, void
         return fail(ctx, RSORT_EINVAL, "vals_in and vals_out overlap without being equal");
 
     rsort::SegPlan& P = ctx->plan;
-    rsort::segmented_plan(seg_offsets, num_segs, ctx->small_max, kb, P);
+    rsort::segmented_plan(seg_offsets, num_segs, ctx->small_max, kb, P, ctx->seg_tile_shape);
     const size_t need = rsort::segmented_ws_bytes(kb, vals_in != nullptr, total, P);
     void* ws = workspace;
     if (ws) {
@@ -952,6 +978,7 @@ int rsort_segmented_sort(rsort_ctx* ctx, int key_type, const void* keys_in, void
     mix((uint64_t)kb);
     mix(vals_in != nullptr);
     mix(ctx->small_max);
+    mix((uint64_t)ctx->seg_tile_shape);
     mix(num_segs);
     for (size_t i = 0; i <= num_segs; ++i) mix(seg_offsets[i]);
     if (cap == hipStreamCaptureStatusActive) {
@@ -1010,15 +1037,19 @@ int rsort_segmented_tune(rsort_ctx* ctx, int key_type, const void* keys_in, void
     }
     const uint32_t saved = ctx->small_max;
     const int saved_sort = ctx->small_sort;
+    const int saved_shape = ctx->seg_tile_shape;
     double best = 1e30;
     uint32_t pick = saved;
     int pick_sort = saved_sort;
+    int pick_shape = saved_shape;
     int rc = RSORT_OK;
     for (uint32_t c : cands)
-    for (int srt : sorters) {
+    for (int srt : sorters)
+    for (int shape = 0; shape < rsort::kSegTileShapes && !rc; ++shape) {
         if (c == 0 && srt != RSORT_SMALL_RADIX) continue;   // no small segments
         ctx->small_max = c;
         ctx->small_sort = srt;
+        ctx->seg_tile_shape = shape;
         rc = rsort_segmented_sort(ctx, key_type, keys_in, keys_out, vals_in, vals_out, seg_offsets,
                                   num_segs, nullptr, 0, stream);   // warm-up, sizes the workspace
         if (rc) break;
@@ -1037,12 +1068,14 @@ int rsort_segmented_tune(rsort_ctx* ctx, int key_type, const void* keys_in, void
             best = ms / reps;
             pick = c;
             pick_sort = srt;
+            pick_shape = shape;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     ctx->small_max = rc ? saved : pick;
     ctx->small_sort = rc ? saved_sort : pick_sort;
+    ctx->seg_tile_shape = rc ? saved_shape : pick_shape;
     if (rc) return rc;
     *best_split = pick;
     if (best_ms) *best_ms = best;

@@ -672,7 +672,7 @@ __global__ __launch_bounds__(WG, !KV ? RSORT_R8_WAVES_PER_EU : sizeof(K) == 4 ? 
         } u;
         uint32_t goff[R];                // output index of tile slot 0 of each digit
         uint32_t wsum[4];
-        uint32_t reserve[KV && sizeof(K) == 4 ? RSORT_SCATTER_KV_LDS_RESERVE : 1];   // occupancy cap, unused
+        uint32_t reserve[KV && sizeof(K) == 4 && WG == 512 ? RSORT_SCATTER_KV_LDS_RESERVE : 1];   // occupancy cap, unused
     };
     __shared__ Smem sm;
 

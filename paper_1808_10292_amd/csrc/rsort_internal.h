@@ -90,15 +90,21 @@ hipError_t histogram(int key_bytes, const void* keys, size_t n, int digit_bits,
 // Batched segmented sort (segmented.hip).  Segments of at most small_max keys
 // are sorted whole in LDS by one workgroup (three capacity classes); larger
 // ones are cut into tiles for the round kernels.
+// Tile shapes of the large-segment path (workgroup size; keys per thread are
+// 16 for 32-bit and 8 for 64-bit keys): 256, 512 (default) or 1024 threads.
+constexpr int kSegTileShapes = 3;
+constexpr int kSegTileShapeDefault = 1;
+uint32_t seg_tile_keys(int key_bytes, int shape);
 struct SegPlan {
     std::vector<uint2> small[3];   // {first key, end} per small segment, by class
     std::vector<uint2> tiles;      // {first key, end} per tile of the large segments
     std::vector<uint4> lsegs;      // {first tile, end tile, first key, 0} per large segment
     std::vector<uint32_t> tile_seg;   // large segment (index into lsegs) of every tile
+    int tile_shape = kSegTileShapeDefault;   // of the large path's tiles
 };
 constexpr uint32_t kSmallMaxDefault = 8192;
 void segmented_plan(const uint64_t* offsets, size_t num_segs, uint32_t small_max, int key_bytes,
-                    SegPlan& P);
+                    SegPlan& P, int tile_shape = kSegTileShapeDefault);
 size_t segmented_meta_bytes(const SegPlan& P);
 size_t segmented_ws_bytes(int key_bytes, bool has_vals, size_t total, const SegPlan& P);
 void segmented_pack(const SegPlan& P, int key_bytes, void* host);

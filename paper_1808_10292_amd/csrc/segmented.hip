@@ -313,16 +313,24 @@ void launch_small(int cls, const void* ki, void* ko, const uint32_t* vi, uint32_
 
 // Host-side plan: which segments go to which small class, the large tiles and
 // the large segments.  Built from host CSR offsets.
-void segmented_plan(const uint64_t* off, size_t nsegs, uint32_t small_max, int key_bytes,
-                    SegPlan& P)
+uint32_t seg_tile_keys(int key_bytes, int shape)
 {
+    static const uint32_t wg[kSegTileShapes] = {256, 512, 1024};
+    const int s = shape >= 0 && shape < kSegTileShapes ? shape : kSegTileShapeDefault;
+    return wg[s] * (key_bytes == 8 ? 8u : 16u);
+}
+
+void segmented_plan(const uint64_t* off, size_t nsegs, uint32_t small_max, int key_bytes,
+                    SegPlan& P, int tile_shape)
+{
+    P.tile_shape = tile_shape >= 0 && tile_shape < kSegTileShapes ? tile_shape : kSegTileShapeDefault;
     P.small[0].clear();
     P.small[1].clear();
     P.small[2].clear();
     P.tiles.clear();
     P.lsegs.clear();
     P.tile_seg.clear();
-    const uint32_t tile = large_tile(key_bytes);
+    const uint32_t tile = seg_tile_keys(key_bytes, P.tile_shape);
     for (size_t s = 0; s < nsegs; ++s) {
         const uint32_t lo = (uint32_t)off[s], hi = (uint32_t)off[s + 1];
         const uint32_t len = hi - lo;
@@ -400,6 +408,82 @@ void segmented_pack(const SegPlan& P, int key_bytes, void* host)
 
 namespace {
 
+// The large segments' rounds with tiles of WG * ITEMS keys: round 0's count
+// also takes every segment's identity words, from which k_seg_plans makes the
+// per-segment round plans; then per round the tile counts, the per-segment
+// scan and the scatter, each reading its tile's segment plan.
+struct LargeArgs {
+    const void* keys_in;
+    void* keys_out;
+    void* keys_tmp;
+    const uint32_t* vals_in;
+    uint32_t* vals_out;
+    uint32_t* vals_tmp;
+    size_t total;
+    size_t nt;
+    uint32_t nls;
+    const RoundPlan* plan;
+    uint32_t* counts;
+    uint32_t* seg_or;
+    RoundPlan* seg_plan;
+    const uint2* tiles;
+    const uint4* lsegs;
+    const uint32_t* tile_seg;
+    int alias;
+    uint32_t* dev_err;
+    hipStream_t stream;
+    Profiler* prof;
+};
+
+template <typename K, bool KV, int WG, int ITEMS>
+void run_large(const LargeArgs& L)
+{
+    const int rounds = (int)sizeof(K);   // 8-bit digits over the whole key
+    const uint32_t nrounds = sizeof(K);
+    for (int d = 0; d < rounds; ++d) {
+        RoundArgs a;
+        a.keys_in = L.keys_in;
+        a.keys_out = L.keys_out;
+        a.keys_tmp = L.keys_tmp;
+        a.vals_in = L.vals_in;
+        a.vals_out = L.vals_out;
+        a.vals_tmp = L.vals_tmp;
+        a.n = (uint32_t)L.total;
+        a.shift = 8u * d;
+        a.mask = 0xFFu;
+        a.round = d;
+        a.ntiles = (uint32_t)L.nt;
+        a.bases = nullptr;
+        a.plan = L.plan;
+        a.counts = L.counts;
+        a.blk_state = nullptr;
+        a.tickets = nullptr;
+        a.err = L.dev_err;
+        a.tiles = L.tiles;
+        a.ntiles_dev = nullptr;
+        a.tile_seg = L.tile_seg;
+        a.seg_plan = L.seg_plan;
+        a.lsegs = L.lsegs;
+        if (L.prof) profiler_mark(L.prof, L.stream, kKindCount, true);
+        if (d == 0) {
+            a.seg_or = L.seg_or;
+            hipLaunchKernelGGL((k_count<K, WG, ITEMS, true>), dim3(L.nt), dim3(WG), 0, L.stream, a, nullptr);
+            a.seg_or = nullptr;
+            hipLaunchKernelGGL(k_seg_plans, dim3((L.nls + 255) / 256), dim3(256), 0, L.stream,
+                               (const uint32_t*)L.seg_or, L.nls, nrounds, L.alias, L.seg_plan);
+        } else {
+            hipLaunchKernelGGL((k_count<K, WG, ITEMS, false>), dim3(L.nt), dim3(WG), 0, L.stream, a, nullptr);
+        }
+        if (L.prof) profiler_mark(L.prof, L.stream, kKindCount, false);
+        if (L.prof) profiler_mark(L.prof, L.stream, kKindTileScan, true);
+        hipLaunchKernelGGL(k_segscan, dim3(L.nls), dim3(R), 0, L.stream, a, L.lsegs);
+        if (L.prof) profiler_mark(L.prof, L.stream, kKindTileScan, false);
+        if (L.prof) profiler_mark(L.prof, L.stream, kKindRound, true);
+        hipLaunchKernelGGL((k_scatter<K, KV, WG, ITEMS>), dim3(L.nt), dim3(WG), 0, L.stream, a);
+        if (L.prof) profiler_mark(L.prof, L.stream, kKindRound, false);
+    }
+}
+
 template <typename K, bool KV>
 hipError_t run_segmented(const void* keys_in, void* keys_out, const uint32_t* vals_in,
                          uint32_t* vals_out, size_t total, const SegPlan& P, const void* host_meta,
@@ -443,56 +527,17 @@ hipError_t run_segmented(const void* keys_in, void* keys_out, const uint32_t* va
     if (prof) profiler_mark(prof, stream, kKindSmall, false);
     if (!nt) return hipGetLastError();
 
-    // Large segments: round 0's count also takes every segment's identity
-    // words, from which k_seg_plans makes the per-segment round plans.
-    constexpr int WG = R8Config<K>::WG;
-    constexpr int ITEMS = R8Config<K>::ITEMS;
-    const int rounds = (int)nrounds;
     const bool keys_alias = keys_in == keys_out, vals_alias = KV && vals_in == vals_out;
     const int alias = (keys_alias || vals_alias ? kAliasAny : 0) |
                       (keys_alias && (!KV || vals_alias) ? kAliasAll : 0);
     hipLaunchKernelGGL(k_zero_words, dim3((2 * nls + 255) / 256), dim3(256), 0, stream, seg_or, 2 * nls);
-    for (int d = 0; d < rounds; ++d) {
-        RoundArgs a;
-        a.keys_in = keys_in;
-        a.keys_out = keys_out;
-        a.keys_tmp = keys_tmp;
-        a.vals_in = vals_in;
-        a.vals_out = vals_out;
-        a.vals_tmp = vals_tmp;
-        a.n = (uint32_t)total;
-        a.shift = 8u * d;
-        a.mask = 0xFFu;
-        a.round = d;
-        a.ntiles = (uint32_t)nt;
-        a.bases = nullptr;
-        a.plan = plan;
-        a.counts = counts;
-        a.blk_state = nullptr;
-        a.tickets = nullptr;
-        a.err = dev_err;
-        a.tiles = tiles;
-        a.ntiles_dev = nullptr;
-        a.tile_seg = tile_seg;
-        a.seg_plan = seg_plan;
-        a.lsegs = lsegs;
-        if (prof) profiler_mark(prof, stream, kKindCount, true);
-        if (d == 0) {
-            a.seg_or = seg_or;
-            hipLaunchKernelGGL((k_count<K, R8Config<K>::CWG, R8Config<K>::CITEMS, true>), dim3(nt), dim3(R8Config<K>::CWG), 0, stream, a, nullptr);
-            a.seg_or = nullptr;
-            hipLaunchKernelGGL(k_seg_plans, dim3((nls + 255) / 256), dim3(256), 0, stream, (const uint32_t*)seg_or,
-                               nls, nrounds, alias, seg_plan);
-        } else {
-            hipLaunchKernelGGL((k_count<K, R8Config<K>::CWG, R8Config<K>::CITEMS, false>), dim3(nt), dim3(R8Config<K>::CWG), 0, stream, a, nullptr);
-        }
-        if (prof) profiler_mark(prof, stream, kKindCount, false);
-        if (prof) profiler_mark(prof, stream, kKindTileScan, true);
-        hipLaunchKernelGGL(k_segscan, dim3((uint32_t)P.lsegs.size()), dim3(R), 0, stream, a, lsegs);
-        if (prof) profiler_mark(prof, stream, kKindTileScan, false);
-        if (prof) profiler_mark(prof, stream, kKindRound, true);
-        hipLaunchKernelGGL((k_scatter<K, KV, WG, ITEMS>), dim3(nt), dim3(WG), 0, stream, a);
-        if (prof) profiler_mark(prof, stream, kKindRound, false);
+    LargeArgs la{keys_in, keys_out, keys_tmp, vals_in, vals_out, vals_tmp, total, nt, nls, plan,
+                 counts, seg_or, seg_plan, tiles, lsegs, tile_seg, alias, dev_err, stream, prof};
+    constexpr int IT = sizeof(K) == 8 ? 8 : 16;
+    switch (P.tile_shape) {
+    case 0: run_large<K, KV, 256, IT>(la); break;
+    case 2: run_large<K, KV, 1024, IT>(la); break;
+    default: run_large<K, KV, 512, IT>(la); break;
     }
     return hipGetLastError();
 }

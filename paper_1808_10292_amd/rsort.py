@@ -54,7 +54,8 @@ EXPORTED = ("rsort_create", "rsort_destroy", "rsort_status_string", "rsort_last_
             "rsort_segmented_sort",
             "rsort_segmented_workspace_bytes", "rsort_segmented_set_split",
             "rsort_segmented_tune", "rsort_segmented_set_small_sort",
-            "rsort_segmented_get_small_sort", "rsort_sample_sort", "rsort_sample_sort_workspace_bytes",
+            "rsort_segmented_get_small_sort", "rsort_segmented_set_tile",
+            "rsort_segmented_get_config", "rsort_sample_sort", "rsort_sample_sort_workspace_bytes",
             "rsort_sample_sort_stats", "rsort_sample_sort_random",
             "rsort_sample_sort_random_workspace_bytes", "rsort_sample_sort_gvr",
             "rsort_sample_sort_gvr_workspace_bytes", "rsort_segmented_sort_device",
@@ -125,6 +126,10 @@ def load_library():
         lib.rsort_segmented_set_split.argtypes = [vp, ctypes.c_uint32]
         lib.rsort_segmented_set_small_sort.argtypes = [vp, i]
         lib.rsort_segmented_get_small_sort.argtypes = [vp, ctypes.POINTER(i)]
+        lib.rsort_segmented_set_tile.argtypes = [vp, i]
+        lib.rsort_segmented_get_config.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32),
+                                                   ctypes.POINTER(i), ctypes.POINTER(i),
+                                                   ctypes.POINTER(i)]
         lib.rsort_segmented_tune.argtypes = [vp, i, vp, vp, u32p, u32p, vp, sz, i, vp,
                                              ctypes.POINTER(ctypes.c_uint32),
                                              ctypes.POINTER(ctypes.c_double)]
@@ -486,11 +491,31 @@ def rsort_segmented_get_small_sort(device=None):
     return out.value
 
 
+def rsort_segmented_set_tile(tile_threads, device=None):
+    """Tile workgroup of the large segments' rounds: 256, 512 or 1024 threads
+    (0 = default)."""
+    ctx = context(device)
+    ctx.check(ctx._lib.rsort_segmented_set_tile(ctx.handle, int(tile_threads)),
+              "rsort_segmented_set_tile")
+
+
+def rsort_segmented_get_config(device=None):
+    """dict(split, small_sort, tile_threads, radix_bits) of the segmented sort."""
+    ctx = context(device)
+    sm, ss, tt, rb = ctypes.c_uint32(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    ctx.check(ctx._lib.rsort_segmented_get_config(ctx.handle, ctypes.byref(sm), ctypes.byref(ss),
+                                                  ctypes.byref(tt), ctypes.byref(rb)),
+              "rsort_segmented_get_config")
+    names = {v: k for k, v in SMALL_SORTS.items()}
+    return {"split": sm.value, "small_sort": names.get(ss.value, ss.value),
+            "tile_threads": tt.value, "radix_bits": rb.value}
+
+
 def rsort_segmented_tune(keys_in, keys_out, seg_offsets, vals_in=None, vals_out=None, reps=3,
                          stream=None):
-    """Pick the fastest small/large split and small-segment sorter for this
-    batch (both left set); returns (split, ms) -- the sorter through
-    rsort_segmented_get_small_sort()."""
+    """Pick the fastest small/large split, small-segment sorter and tile
+    workgroup of the large path for this batch (all left set); returns
+    (split, ms) -- the rest through rsort_segmented_get_config()."""
     kt = _key_type(keys_in)
     off = _host_offsets(seg_offsets)
     ctx = context(keys_in.device)

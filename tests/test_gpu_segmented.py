@@ -27,6 +27,7 @@ def rs():
     rsort.load_library()
     yield rsort
     rsort.rsort_segmented_set_split(8192)
+    rsort.rsort_segmented_set_tile(0)
 
 
 def run_case(rs, keys, sizes, with_vals, in_place=False):
@@ -184,11 +185,40 @@ def test_tuner_picks_a_split_and_stays_exact(rs):
     split, ms = rs.rsort_segmented_tune(dk, ko, off, reps=2)
     assert split in (0, 1024, 4096, 8192) and ms > 0
     assert rs.rsort_segmented_get_small_sort() in (0, 1, 2)
+    cfg = rs.rsort_segmented_get_config()
+    assert cfg["split"] == split and cfg["tile_threads"] in (256, 512, 1024)
+    assert cfg["radix_bits"] == 8
     rs.rsort_segmented_sort(dk, ko, off)
     want, _ = oracle.segmented(keys, None, off)
     assert np.array_equal(host(ko), want)
     rs.rsort_segmented_set_split(8192)
     rs.rsort_segmented_set_small_sort("radix")
+    rs.rsort_segmented_set_tile(0)
+
+
+@pytest.mark.parametrize("tile_threads", [256, 512, 1024])
+@pytest.mark.parametrize("dtype", [np.uint32, np.uint64])
+def test_tile_shapes_exact(rs, tile_threads, dtype):
+    """Every tile shape the tuner searches (tiles of 256 / 512 / 1024 threads x
+    16 or 8 keys), through the tiled path alone (split 0) and mixed with the
+    in-LDS path, with payloads and in place, with per-segment identity
+    rounds: bit-exact against the oracle."""
+    sizes = [1, 100, 5000, 8192, 8193, 16384, 16385, 30000, 70001, 0, 100003, 4097]
+    rs.rsort_segmented_set_tile(tile_threads)
+    try:
+        assert rs.rsort_segmented_get_config()["tile_threads"] == tile_threads
+        for kind in (4, 0, 3):   # uniform, segment-constant high half, all equal
+            keys = shaped_segments(kind, sizes, 200 + kind, dtype)
+            for split in (0, 8192):
+                announce("seg tile", tile_threads, dtype.__name__, kind, split)
+                rs.rsort_segmented_set_split(split)
+                run_case(rs, keys, sizes, True)
+                run_case(rs, keys, sizes, False, in_place=True)
+    finally:
+        rs.rsort_segmented_set_split(8192)
+        rs.rsort_segmented_set_tile(0)
+    with pytest.raises(rs.RsortError):
+        rs.rsort_segmented_set_tile(384)
 
 
 def test_graph_capture_replays(rs):
