@@ -440,9 +440,10 @@ def main():
     ap.add_argument("--kv-dists", default="uniform,low16,zipf,equal,presorted,reverse",
                     help="comma list of key distributions for the key-value leg "
                          "(uniform, low16, zipf, equal, presorted, reverse)")
-    ap.add_argument("--mode", choices=("sort", "copy"), default="sort",
+    ap.add_argument("--mode", choices=("sort", "copy", "pr2"), default="sort",
                     help="copy: time the library's plain device copy of the same bytes "
-                         "(calibrates rocprofv3 byte counters against a known transfer)")
+                         "(calibrates rocprofv3 byte counters against a known transfer); "
+                         "pr2: time only the radix-65536 sort of the same keys (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -470,6 +471,15 @@ def main():
                          args.steps, args.warmup, torch)
         print(json.dumps({"mode": "copy", "bytes_moved": 2 * n * 4, "ms": round(sec * 1e3, 4),
                           "gbps": round(2 * n * 4 / sec / 1e9, 1)}), flush=True)
+        return
+
+    if args.mode == "pr2":
+        sec = time_steps(lambda: rsort.rsort_sort(dk, out, algo="lsd16"), args.steps, args.warmup,
+                         torch)
+        got = out.cpu().numpy()
+        print(json.dumps({"mode": "pr2", "keys": n, "ms": round(sec * 1e3, 4),
+                          "gkeys_per_s": round(n / sec / 1e9, 3),
+                          "sorted": bool(np.all(got[1:] >= got[:-1]))}), flush=True)
         return
 
     def step():
@@ -570,7 +580,8 @@ def main():
         for _ in range(reps):
             rsort.rsort_sort(dk, out, algo="lsd16")
         parts = {}
-        for name, kind in (("count_rows", rsort.RSORT_KERNEL_COUNT),
+        for name, kind in (("group_high_byte", rsort.RSORT_KERNEL_GROUP),
+                           ("count_rows", rsort.RSORT_KERNEL_COUNT),
                            ("column_scan", rsort.RSORT_KERNEL_TILESCAN),
                            ("place", rsort.RSORT_KERNEL_ROUND)):
             cnt_l, ms = rsort.rsort_profile_read(kind)

@@ -458,7 +458,8 @@ enum rsort_kernel_kind {
     RSORT_KERNEL_HIST = 1,      /* all-rounds digit counting before the rounds    */
     RSORT_KERNEL_COUNT = 2,     /* per-tile digit counts of a round               */
     RSORT_KERNEL_TILESCAN = 3,  /* exclusive scan of the tile counts of a round   */
-    RSORT_KERNEL_SMALL = 4      /* whole-segment in-LDS sorts (segmented sort)    */
+    RSORT_KERNEL_SMALL = 4,     /* whole-segment in-LDS sorts (segmented sort)    */
+    RSORT_KERNEL_GROUP = 5      /* high-byte grouping pass of a radix-2^16 round  */
 };
 int rsort_profile_enable(rsort_ctx* ctx, int enable);
 

@@ -673,7 +673,7 @@ int rsort_sort(rsort_ctx* ctx, int key_type, const void* keys_in, void* keys_out
             if (rc) return rc;
         }
         hipError_t e = rsort::lsd_r16_sort(kb, keys_in, keys_out, vals_in, vals_out, n, begin_bit,
-                                           end_bit, ws, L16, s, ctx->prof);
+                                           end_bit, ws, L16, ctx->dev_err, s, ctx->prof);
         return e == hipSuccess ? RSORT_OK : hip_fail(ctx, e, "kernel launch");
     }
     const rsort::LsdR8Layout L = rsort::lsd_r8_layout(kb, vals_in != nullptr, n, begin_bit, end_bit,

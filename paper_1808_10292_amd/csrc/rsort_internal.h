@@ -30,7 +30,8 @@ constexpr int kHistReplicas = 8;   // global histogram copies, picked by block i
 
 // Optional kernel timing: HIP events recorded on the launch stream around the
 // kernels of one kind (implemented in api.hip).  nullptr disables it.
-enum KernelKind { kKindRound = 0, kKindHist = 1, kKindCount = 2, kKindTileScan = 3, kKindSmall = 4, kNumKinds = 5 };
+enum KernelKind { kKindRound = 0, kKindHist = 1, kKindCount = 2, kKindTileScan = 3, kKindSmall = 4,
+                  kKindGroup = 5, kNumKinds = 6 };
 struct Profiler;
 void profiler_mark(Profiler* p, hipStream_t s, int kind, bool begin);
 
@@ -70,15 +71,16 @@ hipError_t lsd_r8_sort(int key_bytes, const void* keys_in, void* keys_out,
 struct LsdR16Layout {
     uint32_t rounds;    // 16-bit (last one narrower) digits
     uint32_t chunk;     // keys per chunk (a multiple of the tile)
-    uint32_t nchunks;   // <= 256 workgroups / count rows
-    size_t off_tmp_keys, off_tmp_vals, off_rows, off_tot;
+    uint32_t nchunks;   // workgroups / count rows (<= 4096)
+    size_t off_tmp_keys, off_tmp_vals, off_rows, off_win, off_tot;
+    size_t off_grp_keys, off_grp_vals, off_r8;   // grouped keys, grouping round
     size_t bytes;
 };
 LsdR16Layout lsd_r16_layout(int key_bytes, bool has_vals, size_t n, int begin_bit, int end_bit);
 hipError_t lsd_r16_sort(int key_bytes, const void* keys_in, void* keys_out,
                         const uint32_t* vals_in, uint32_t* vals_out, size_t n, int begin_bit,
-                        int end_bit, void* ws, const LsdR16Layout& L, hipStream_t stream,
-                        Profiler* prof);
+                        int end_bit, void* ws, const LsdR16Layout& L, uint32_t* dev_err,
+                        hipStream_t stream, Profiler* prof);
 
 // Digit histograms of every digit (8- or 16-bit) of [begin_bit, end_bit).
 size_t histogram_ws_bytes(int digit_bits, int begin_bit, int end_bit);

@@ -79,6 +79,7 @@ RSORT_KERNEL_HIST = 1
 RSORT_KERNEL_COUNT = 2
 RSORT_KERNEL_TILESCAN = 3
 RSORT_KERNEL_SMALL = 4
+RSORT_KERNEL_GROUP = 5
 
 
 class RsortError(RuntimeError):
