@@ -199,6 +199,114 @@ __device__ __forceinline__ uint32_t wave_inclusive_max(uint32_t x)
     return x;
 }
 
+// A tile whose keys share the digit's high byte (the usual case after the
+// grouping): one stable counting round on the low byte l, as in the radix-256
+// rounds, with the run of l going to row[g + l] (g: the tile's group times
+// 256).  The sorted tile is staged in LDS and leaves in sorted order,
+// consecutive threads taking consecutive positions.  Every thread must call.
+template <typename K, bool KV, int WG, int ITEMS>
+__device__ __forceinline__ void place_one_group(TileSmem<K, KV, WG, ITEMS, true>& sm, uint32_t* gofs,
+                                                K (&k)[ITEMS], uint32_t (&v)[ITEMS], uint32_t len,
+                                                uint32_t shift, uint32_t width, uint32_t mask,
+                                                uint32_t* row, uint32_t n, K first,
+                                                K* __restrict__ keys_out, uint32_t* __restrict__ vals_out)
+{
+    static_assert(WG == 256, "one thread per low-byte value");
+    constexpr int HW = WG / 32;
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t hw = tid >> 5, hl = tid & 31;
+    const uint32_t hofs = hw * ITEMS * 32 + hl;
+    const uint32_t lmask = width < 8 ? mask : 255u;
+    const uint32_t g = width > 8 ? (digit_of(first, shift, mask) & ~255u) : 0u;
+
+    for (uint32_t i = tid; i < HW * 256 / 2; i += WG)
+        ((uint4*)&sm.slot[0][0])[i] = make_uint4(0, 0, 0, 0);
+    __syncthreads();
+    uint2* sl = sm.slot[hw];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const bool ok = hofs + i * 32 < len;
+        const uint32_t d = digit_of(k[i], shift, lmask);
+        if (wave_one_digit(ok, d)) {
+            if (hl == 0) atomicAdd(&sl[d].y, 32u);
+            continue;
+        }
+        if (ok) atomicAdd(&sl[d].y, 1u);
+    }
+    __syncthreads();
+    {
+        // thread tid = low byte l: its run's start in the tile and in the output
+        uint32_t total = 0;
+#pragma unroll
+        for (int h = 0; h < HW; ++h) total += sm.slot[h][tid].y;
+        const uint32_t incl = wave_inclusive_sum(total);
+        if (lane == 63) sm.wsum[wave] = incl;
+        __syncthreads();
+        uint32_t run = incl - total;
+        for (uint32_t q = 0; q < wave; ++q) run += sm.wsum[q];
+        if (total) {
+            const uint32_t r = __hip_atomic_load(&row[g + tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            gofs[tid] = r - run;
+            __hip_atomic_store(&row[g + tid], r + total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+#pragma unroll
+        for (int h = 0; h < HW; ++h) {
+            const uint32_t c = sm.slot[h][tid].y;
+            sm.slot[h][tid].y = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    uint32_t pos[ITEMS];
+    {
+        const uint32_t bit = 1u << hl;
+        const uint32_t lowsel = lane < 32 ? ~0u : 0u;
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const bool ok = hofs + i * 32 < len;
+            const uint32_t d = digit_of(k[i], shift, lmask);
+            if (wave_one_digit(ok, d)) {
+                const uint32_t c = (uint32_t)(__hip_atomic_load((uint64_t*)&sl[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >> 32);
+                pos[i] = c + hl;
+                wave_lds_order();
+                if (hl == 0)
+                    __hip_atomic_store((uint64_t*)&sl[d], (uint64_t)(c + 32) << 32, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                wave_lds_order();
+                continue;
+            }
+            if (ok) __hip_atomic_fetch_or(&sl[d].x, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            wave_lds_order();
+            const uint64_t s = ok ? __hip_atomic_load((uint64_t*)&sl[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : 0ull;
+            const uint32_t m = (uint32_t)s, c = (uint32_t)(s >> 32);
+            pos[i] = __builtin_amdgcn_mbcnt_hi(m, __builtin_amdgcn_mbcnt_lo(m & lowsel, c));
+            wave_lds_order();
+            if (ok)
+                __hip_atomic_store((uint64_t*)&sl[d], (uint64_t)(c + __builtin_popcount(m)) << 32,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            wave_lds_order();
+        }
+    }
+    __syncthreads();   // every slot read before the keys overwrite them
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        if (hofs + i * 32 < len) {
+            sm.keys[pos[i]] = k[i];
+            if (KV) sm.vals[pos[i]] = v[i];
+        }
+    }
+    __syncthreads();
+    for (uint32_t p = tid; p < len; p += WG) {
+        const K key = sm.keys[p];
+        const uint32_t d = gofs[digit_of(key, shift, lmask)] + p;
+        if (d < n) {   // always true when the rows are consistent
+            keys_out[d] = key;
+            if (KV) vals_out[d] = sm.vals[p];
+        }
+    }
+    __syncthreads();   // before the next tile reuses the slots
+}
+
 // The placement of one round over chunk w (workgroup w), tile by tile in
 // order; row[v] = rows[256 w + v] is the output index of the chunk's next key
 // of digit v.  After the tile is sorted, each thread finds the digit runs in
@@ -218,6 +326,7 @@ __global__ __launch_bounds__(R16Config<K>::WG) void k_place16(
     static_assert(ITEMS * sizeof(K) % 16 == 0, "vector LDS reads of a thread's run");
     __shared__ alignas(16) TileSmem<K, KV, WG, ITEMS, true> sm;
     __shared__ uint32_t dest[TILE];
+    __shared__ uint32_t gofs[256];
     __shared__ uint32_t wmax[WG / 64];
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t hofs = (tid >> 5) * ITEMS * 32 + (tid & 31);
@@ -243,6 +352,11 @@ __global__ __launch_bounds__(R16Config<K>::WG) void k_place16(
         // keys agree on it needs only the first
         const bool one_group = width <= 8 || (digit_of(keys_in[t0], shift, mask) >> 8) ==
                                                  (digit_of(keys_in[t0 + len - 1], shift, mask) >> 8);
+        if (one_group) {
+            place_one_group<K, KV, WG, ITEMS>(sm, gofs, k, v, len, shift, width, mask, row, n,
+                                              keys_in[t0], keys_out, vals_out);
+            continue;
+        }
         // held: LDS holds the tile in its final order (a round that finds
         // itself the identity has overwritten LDS with its slots)
         bool held = tile_round<K, KV, WG, ITEMS, true>(sm, k, v, len, shift, (1u << w0) - 1u);
