@@ -233,13 +233,39 @@ int rsort_segmented_device_workspace_bytes(rsort_ctx* ctx, int key_type, int has
  * applies to later calls on ctx.  RSORT_EINVAL for other values. */
 int rsort_segmented_set_tile(rsort_ctx* ctx, int tile_threads);
 
+/*
+ * How the segmented sort with host offsets (rsort_segmented_sort) is launched:
+ *   RSORT_SEG_ROUNDS      the small segments' in-LDS sorts, then per round of
+ *                         the large segments a count, a per-segment scan and
+ *                         a scatter kernel (default);
+ *   RSORT_SEG_PERSISTENT  one persistent launch (after a fill kernel that
+ *                         clears its counters): a resident grid takes work
+ *                         items from one ticket counter -- per-tile
+ *                         histograms of the large segments, whole small
+ *                         segments (at most 8192 32-bit or 4096 64-bit keys,
+ *                         radix rounds), then round by round the large
+ *                         segments' tiles, each folding in the counts of the
+ *                         earlier tiles of its segment by decoupled look-back.
+ *                         Items wait only on items handed out before them, and
+ *                         every wait is bounded (a wait that gives up is
+ *                         reported by rsort_synchronize as RSORT_EDEVICE).
+ * Same result either way (Section 3.2's SR4 on every segment).  Chosen by the
+ * tuner; applies to later calls on ctx.  RSORT_EINVAL for other values.
+ * RSORT_SEG_PERSISTENT is currently switched off (RSORT_EUNSUPPORTED): its
+ * first run on the GPU faulted and the cause is not found yet.
+ */
+enum rsort_seg_launch { RSORT_SEG_ROUNDS = 0, RSORT_SEG_PERSISTENT = 1 };
+int rsort_segmented_set_launch(rsort_ctx* ctx, int launch);
+
 /* The segmented sort's current configuration on ctx: the small/large split,
- * the small-segment sorter, the tile workgroup size of the large path and
- * the radix width in bits of every count-sort round (8: the rounds of the
+ * the small-segment sorter, the tile workgroup size of the large path, the
+ * radix width in bits of every count-sort round (8: the rounds of the
  * segmented sort are the paper's radix-2^8 rounds; a wider radix has no tile
- * that fits LDS with per-group ranking slots).  Any output may be NULL. */
+ * that fits LDS with per-group ranking slots) and the launch mode
+ * (rsort_seg_launch; the persistent launch always reports the radix sorter
+ * and 512-thread tiles).  Any output may be NULL. */
 int rsort_segmented_get_config(rsort_ctx* ctx, uint32_t* small_max, int* small_sort,
-                               int* tile_threads, int* radix_bits);
+                               int* tile_threads, int* radix_bits, int* launch);
 
 /* Largest segment sorted whole in LDS (<= 8192; 0 sends every segment through
  * the tiled path).  Chosen by the tuner; applies to later calls on ctx. */
@@ -267,8 +293,9 @@ int rsort_segmented_get_small_sort(rsort_ctx* ctx, int* small_sort);
 /* Tuner for the segmented sort: sorts the given batch (into keys_out /
  * vals_out) reps times with each candidate split (0, 1024, 4096, 8192 keys),
  * each small-segment sorter and each tile workgroup of the large path (256,
- * 512, 1024 threads), keeps the fastest combination on ctx and returns its
- * split (the rest: rsort_segmented_get_config), with its time per sort in ms.
+ * 512, 1024 threads), and the persistent launch at each split, keeps the
+ * fastest combination on ctx and returns its split (the rest:
+ * rsort_segmented_get_config), with its time per sort in ms.
  * Synchronises the stream. */
 int rsort_segmented_tune(rsort_ctx* ctx, int key_type, const void* keys_in, void* keys_out,
                          const uint32_t* vals_in, uint32_t* vals_out,

@@ -116,6 +116,18 @@ hipError_t segmented_sort(int key_bytes, const void* keys_in, void* keys_out,
                           const SegPlan& P, const void* host_meta, void* ws, uint32_t* dev_err,
                           hipStream_t stream, Profiler* prof, int small_sort = 0);
 
+// The same sort in one persistent launch (seg_persist.hip): a resident grid
+// takes histogram, small-segment and round items from one ticket counter.
+// Small segments are those of at most persist_small_max keys (and at most the
+// plan's small_max); plan with segmented_plan(..., tile shape 1).
+uint32_t persist_small_max(int key_bytes);
+size_t persist_meta_bytes(const SegPlan& P, int key_bytes);
+size_t persist_ws_bytes(int key_bytes, bool has_vals, size_t total, const SegPlan& P);
+void persist_pack(const SegPlan& P, int key_bytes, void* host);
+hipError_t persist_sort(int key_bytes, const void* keys_in, void* keys_out, const uint32_t* vals_in,
+                        uint32_t* vals_out, size_t total, const SegPlan& P, const void* host_meta,
+                        void* ws, uint32_t* dev_err, hipStream_t stream, Profiler* prof);
+
 // Device-planned segmented sort: offsets (nseg + 1 u32, nondecreasing) live in
 // device memory.  ws must hold devseg_layout(...).bytes bytes.
 struct DevSegLayout {

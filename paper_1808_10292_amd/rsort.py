@@ -55,7 +55,7 @@ EXPORTED = ("rsort_create", "rsort_destroy", "rsort_status_string", "rsort_last_
             "rsort_segmented_workspace_bytes", "rsort_segmented_set_split",
             "rsort_segmented_tune", "rsort_segmented_set_small_sort",
             "rsort_segmented_get_small_sort", "rsort_segmented_set_tile",
-            "rsort_segmented_get_config", "rsort_sample_sort", "rsort_sample_sort_workspace_bytes",
+            "rsort_segmented_get_config", "rsort_segmented_set_launch", "rsort_sample_sort", "rsort_sample_sort_workspace_bytes",
             "rsort_sample_sort_stats", "rsort_sample_sort_random",
             "rsort_sample_sort_random_workspace_bytes", "rsort_sample_sort_gvr",
             "rsort_sample_sort_gvr_workspace_bytes", "rsort_segmented_sort_device",
@@ -128,9 +128,10 @@ def load_library():
         lib.rsort_segmented_set_small_sort.argtypes = [vp, i]
         lib.rsort_segmented_get_small_sort.argtypes = [vp, ctypes.POINTER(i)]
         lib.rsort_segmented_set_tile.argtypes = [vp, i]
+        lib.rsort_segmented_set_launch.argtypes = [vp, i]
         lib.rsort_segmented_get_config.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32),
                                                    ctypes.POINTER(i), ctypes.POINTER(i),
-                                                   ctypes.POINTER(i)]
+                                                   ctypes.POINTER(i), ctypes.POINTER(i)]
         lib.rsort_segmented_tune.argtypes = [vp, i, vp, vp, u32p, u32p, vp, sz, i, vp,
                                              ctypes.POINTER(ctypes.c_uint32),
                                              ctypes.POINTER(ctypes.c_double)]
@@ -500,16 +501,32 @@ def rsort_segmented_set_tile(tile_threads, device=None):
               "rsort_segmented_set_tile")
 
 
-def rsort_segmented_get_config(device=None):
-    """dict(split, small_sort, tile_threads, radix_bits) of the segmented sort."""
+SEG_LAUNCHES = {"rounds": 0, "persistent": 1}
+
+
+def rsort_segmented_set_launch(launch, device=None):
+    """Launch mode of the segmented sort with host offsets: "rounds" (kernels
+    per round, default) or "persistent" (one persistent launch)."""
     ctx = context(device)
-    sm, ss, tt, rb = ctypes.c_uint32(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    code = SEG_LAUNCHES[launch] if isinstance(launch, str) else int(launch)
+    ctx.check(ctx._lib.rsort_segmented_set_launch(ctx.handle, code), "rsort_segmented_set_launch")
+
+
+def rsort_segmented_get_config(device=None):
+    """dict(split, small_sort, tile_threads, radix_bits, launch) of the
+    segmented sort."""
+    ctx = context(device)
+    sm, ss, tt, rb, ln = (ctypes.c_uint32(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int(),
+                          ctypes.c_int())
     ctx.check(ctx._lib.rsort_segmented_get_config(ctx.handle, ctypes.byref(sm), ctypes.byref(ss),
-                                                  ctypes.byref(tt), ctypes.byref(rb)),
+                                                  ctypes.byref(tt), ctypes.byref(rb),
+                                                  ctypes.byref(ln)),
               "rsort_segmented_get_config")
     names = {v: k for k, v in SMALL_SORTS.items()}
+    launches = {v: k for k, v in SEG_LAUNCHES.items()}
     return {"split": sm.value, "small_sort": names.get(ss.value, ss.value),
-            "tile_threads": tt.value, "radix_bits": rb.value}
+            "tile_threads": tt.value, "radix_bits": rb.value,
+            "launch": launches.get(ln.value, ln.value)}
 
 
 def rsort_segmented_tune(keys_in, keys_out, seg_offsets, vals_in=None, vals_out=None, reps=3,

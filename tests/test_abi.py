@@ -51,3 +51,4 @@ def test_status_strings_without_gpu(lib_path):
     assert lib.rsort_destroy(None) == rsort.RSORT_EINVAL
     assert lib.rsort_sort(None, 0, None, None, None, None, 0, 0, 32, 0, None, 0, None) == rsort.RSORT_EINVAL
     assert lib.rsort_last_error(None) == b""
+

@@ -28,6 +28,7 @@ def rs():
     yield rsort
     rsort.rsort_segmented_set_split(8192)
     rsort.rsort_segmented_set_tile(0)
+    rsort.rsort_segmented_set_launch("rounds")
 
 
 def run_case(rs, keys, sizes, with_vals, in_place=False):
@@ -194,6 +195,7 @@ def test_tuner_picks_a_split_and_stays_exact(rs):
     rs.rsort_segmented_set_split(8192)
     rs.rsort_segmented_set_small_sort("radix")
     rs.rsort_segmented_set_tile(0)
+    rs.rsort_segmented_set_launch("rounds")
 
 
 @pytest.mark.parametrize("tile_threads", [256, 512, 1024])
