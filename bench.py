@@ -97,6 +97,41 @@ def time_steps(fn, steps, warmup, torch):
     return (time.perf_counter() - t0) / steps
 
 
+def bench_sample_only(rsort, torch, np, keygen, args):
+    """GSD (p = 256, r = 32), GER and GVR (p = 256, s = 2 w^2 lg n) on
+    2^kv-log2n uniform (uint32 key, uint32 payload = input index) pairs, one
+    JSON line per sort; for profiling the sample sorts' kernels alone."""
+    n = 1 << args.kv_log2n
+    keys = keygen.kv_keys("uniform", n)
+    dk = torch.from_numpy(keys).cuda()
+    dv = torch.arange(n, dtype=torch.int32, device="cuda")
+    ko = torch.empty_like(dk)
+    vo = torch.empty_like(dv)
+    fns = {"gsd": lambda: rsort.rsort_sample_sort(dk, ko, dv, vo, p=256, r=32),
+           "ger": lambda: rsort.rsort_sample_sort_random(dk, ko, dv, vo, p=256, s=0, seed=11),
+           "gvr": lambda: rsort.rsort_sample_sort_gvr(dk, ko, dv, vo, p=256, s=0, seed=12)}
+    for name, fn in fns.items():
+        sec = time_steps(fn, args.steps, args.warmup, torch)
+        got = ko.cpu().numpy()
+        print(json.dumps({"mode": "sample", "algo": name, "pairs": n, "ms": round(sec * 1e3, 4),
+                          "sorted": bool(np.all(got[1:] >= got[:-1]))}), flush=True)
+
+
+def bench_segmented_only(rsort, torch, np, keygen, args):
+    """The batched segmented sort of the 4096 lognormal arrays (median 2^12,
+    sigma 1.5, clipped to [16, 2^20]), uniform 32-bit keys, keys only, with the
+    default configuration; for profiling its kernels alone."""
+    sizes = keygen.lognormal_sizes(4096)
+    off = keygen.offsets_from_sizes(sizes)
+    keys = keygen.uniform_u32(int(off[-1]), keygen.SEED_SEGMENTS)
+    dk = torch.from_numpy(keys).cuda()
+    out = torch.empty_like(dk)
+    sec = time_steps(lambda: rsort.rsort_segmented_sort(dk, out, off), args.steps, args.warmup,
+                     torch)
+    print(json.dumps({"mode": "segmented", "arrays": int(sizes.size), "keys": int(off[-1]),
+                      "ms": round(sec * 1e3, 4)}), flush=True)
+
+
 def bench_batched(rsort, torch, np, keygen, args):
     """Batched segmented sort vs one plain sort per array: 4096 arrays with
     lognormal sizes (median 2^12, sigma 1.5, clipped to [16, 2^20]), uniform
@@ -440,10 +475,14 @@ def main():
     ap.add_argument("--kv-dists", default="uniform,low16,zipf,equal,presorted,reverse",
                     help="comma list of key distributions for the key-value leg "
                          "(uniform, low16, zipf, equal, presorted, reverse)")
-    ap.add_argument("--mode", choices=("sort", "copy", "pr2"), default="sort",
+    ap.add_argument("--mode", choices=("sort", "copy", "pr2", "sample", "segmented"),
+                    default="sort",
                     help="copy: time the library's plain device copy of the same bytes "
                          "(calibrates rocprofv3 byte counters against a known transfer); "
-                         "pr2: time only the radix-65536 sort of the same keys (for profiling)")
+                         "pr2: time only the radix-65536 sort of the same keys; "
+                         "sample: only GSD, GER and GVR on 2^kv-log2n uniform key-value pairs; "
+                         "segmented: only the batched segmented sort of the 4096 lognormal "
+                         "arrays (these three for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -458,6 +497,12 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     rsort.load_library()
+    if args.mode == "sample":
+        bench_sample_only(rsort, torch, np, keygen, args)
+        return
+    if args.mode == "segmented":
+        bench_segmented_only(rsort, torch, np, keygen, args)
+        return
     n = 1 << args.log2n
     log("generating %d keys" % n)
     keys = keygen.uniform_u32(n, keygen.SEED_LARGE)
