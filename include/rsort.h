@@ -484,7 +484,9 @@ enum rsort_kernel_kind {
     RSORT_KERNEL_ROUND = 0,     /* rank-and-scatter kernel of a count-sort round  */
     RSORT_KERNEL_HIST = 1,      /* all-rounds digit counting before the rounds    */
     RSORT_KERNEL_COUNT = 2,     /* per-tile digit counts of a round               */
-    RSORT_KERNEL_TILESCAN = 3,  /* exclusive scan of the tile counts of a round   */
+    RSORT_KERNEL_TILESCAN = 3,  /* exclusive scan of the tile counts of a round
+                                   (none in radix-2^8 sorts of at most 256 tiles,
+                                   whose scatter sums the tile counts itself)   */
     RSORT_KERNEL_SMALL = 4,     /* whole-segment in-LDS sorts (segmented sort)    */
     RSORT_KERNEL_GROUP = 5      /* high-byte grouping pass of a radix-2^16 round  */
 };

@@ -73,6 +73,11 @@ constexpr uint32_t kNoTile = 0xFFFFFFFFu;
 #ifndef LB_WINDOW
 #define LB_WINDOW 4
 #endif
+// Plain sorts of at most this many tiles skip the tile-scan kernel: each
+// scatter workgroup sums the tile counts of the round itself.
+#ifndef RSORT_INLINE_SCAN_TILES
+#define RSORT_INLINE_SCAN_TILES 256
+#endif
 
 // Count kernel workgroup size (same tile, ITEMS = tile / CWG) and whether full
 // tiles are read with 16-byte loads.
@@ -131,6 +136,9 @@ struct RoundArgs {
     const RoundPlan* seg_plan = nullptr;
     uint32_t* seg_or = nullptr;
     const uint4* lsegs = nullptr;
+    // Nonzero: there is no tile scan; counts[t][v] stay the tile counts and
+    // the scatter sums them itself (plain sorts of few tiles).
+    uint32_t inline_scan = 0;
 };
 
 // The plan of round a.round for tile t: the segment's plan in a segmented
@@ -623,6 +631,57 @@ __global__ __launch_bounds__(R) void k_tilescan(RoundArgs a)
 }
 
 // ---------------------------------------------------------------------------
+// Output start of each digit's run of tile `tile` without a tile scan: the
+// keys of digit v in the tiles before it plus the start of digit v (the keys
+// of smaller digits in all tiles), for thread v < 256; every thread calls.
+// The rows of tile counts are read as 16-byte vectors, WG / 64 rows per step;
+// scratch holds 2 x (WG / 64) x 256 words of LDS, wsum 4 words.  Each
+// workgroup reads every row, so this is for sorts of few tiles.
+template <int WG>
+__device__ __forceinline__ uint32_t inline_tile_offset(const RoundArgs& a, uint32_t tile,
+                                                       uint32_t* scratch, uint32_t* wsum)
+{
+    constexpr uint32_t RG = WG / 64;   // rows per step: 64 threads x 4 digits per row
+    constexpr int U = 4;               // steps in flight
+    static_assert(WG % 64 == 0 && WG >= 256, "whole rows and a thread per digit");
+    const uint32_t tid = threadIdx.x, c4 = tid & 63, rg = tid >> 6;
+    const uint32_t lane = tid & 63, wave = tid >> 6;
+    const uint4* rows = (const uint4*)a.counts;
+    uint4 bs = make_uint4(0, 0, 0, 0), ts = make_uint4(0, 0, 0, 0);
+    for (uint32_t t0 = rg; t0 < a.ntiles; t0 += RG * U) {
+        uint4 x[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t t = t0 + u * RG;
+            x[u] = t < a.ntiles ? rows[(size_t)t * (R / 4) + c4] : make_uint4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t f = t0 + u * RG < tile ? 1u : 0u;
+            ts.x += x[u].x; ts.y += x[u].y; ts.z += x[u].z; ts.w += x[u].w;
+            bs.x += f * x[u].x; bs.y += f * x[u].y; bs.z += f * x[u].z; bs.w += f * x[u].w;
+        }
+    }
+    ((uint4*)scratch)[rg * (R / 4) + c4] = bs;
+    ((uint4*)scratch)[(RG + rg) * (R / 4) + c4] = ts;
+    __syncthreads();
+    uint32_t before = 0, total = 0, incl = 0;
+    if (tid < R) {
+#pragma unroll
+        for (uint32_t g = 0; g < RG; ++g) {
+            before += scratch[g * R + tid];
+            total += scratch[(RG + g) * R + tid];
+        }
+        incl = wave_inclusive_sum(total);
+        if (lane == 63) wsum[wave] = incl;
+    }
+    __syncthreads();
+    if (tid < R)
+        for (uint32_t w = 0; w < wave; ++w) incl += wsum[w];
+    return incl - total + before;
+}
+
+// ---------------------------------------------------------------------------
 // k_scatter: one stable count-sort round of one tile.
 //
 // Layout: the tile is split among half-waves (32 lanes); half-wave h owns the
@@ -661,6 +720,7 @@ __global__ __launch_bounds__(WG, !KV ? RSORT_R8_WAVES_PER_EU : sizeof(K) == 4 ? 
     static_assert(G == 16 || G == 32, "ranking groups of 16 or 32 lanes");
     static_assert(G == 32 || (uint64_t)TILE < 65536, "16-bit slot counts");
     static_assert(TILE * sizeof(K) >= NG * R * (G == 32 ? 8 : 4), "staging must cover the slots");
+    static_assert(2 * NG * R >= 2 * (WG / 64) * R, "the inline tile scan's scratch fits the slot words");
     struct Smem {
         union {
             uint2 slot[NG][R];           // 32-lane groups: {lane set, count}, then {-, slot base}
@@ -765,13 +825,17 @@ __global__ __launch_bounds__(WG, !KV ? RSORT_R8_WAVES_PER_EU : sizeof(K) == 4 ? 
         // keys in this tile
         const uint32_t lim = decltype(full)::value ? TILE : tile_range(a, tile, TILE).y;
         constexpr uint32_t slot_u4 = NG * R * (G == 32 ? 8 : 4) / 16;
-        for (uint32_t i = tid; i < slot_u4; i += WG)
-            ((uint4*)&sm.u)[i] = make_uint4(0, 0, 0, 0);
         uint32_t toff = 0;
-        if (tid < R) {
+        if (a.inline_scan) {
+            // the LDS scratch is read before the barrier that ends the call
+            // and zeroed below only after it
+            toff = inline_tile_offset<WG>(a, tile, sm.u.words, sm.wsum);
+        } else if (tid < R) {
             toff = a.counts[(size_t)tile * R + tid];
             if (a.bases) toff += a.bases[a.round * R + tid];
         }
+        for (uint32_t i = tid; i < slot_u4; i += WG)
+            ((uint4*)&sm.u)[i] = make_uint4(0, 0, 0, 0);
         __syncthreads();
 
         // Rank row by row; a slot's count is advanced by the lanes of the row

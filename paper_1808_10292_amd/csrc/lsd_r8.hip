@@ -191,19 +191,24 @@ hipError_t run(const void* keys_in, void* keys_out, const uint32_t* vals_in, uin
         const uint32_t resident = persistent_blocks((const void*)k_scatter<K, KV, WG, ITEMS>, WG);
         sgrid = std::min<uint32_t>(L.ntiles, resident & ~7u ? resident & ~7u : resident);
     }
+    // few tiles: no tile-scan kernel, the scatter sums the tile counts itself
+    const bool inline_scan = L.ntiles <= RSORT_INLINE_SCAN_TILES && sgrid == L.ntiles;
     for (uint32_t d = 0; d < nr; ++d) {
-        const RoundArgs a = round_args(keys_in, keys_out, keys_tmp, vals_in, vals_out, vals_tmp, n,
-                                       begin_bit, end_bit, d, L, bases, plan, counts, blk_state,
-                                       tickets, dev_err);
+        RoundArgs a = round_args(keys_in, keys_out, keys_tmp, vals_in, vals_out, vals_tmp, n,
+                                 begin_bit, end_bit, d, L, bases, plan, counts, blk_state,
+                                 tickets, dev_err);
+        a.inline_scan = inline_scan ? 1u : 0u;
         if (d > 0) {   // round 0 was counted with the histograms
             if (prof) profiler_mark(prof, stream, kKindCount, true);
             hipLaunchKernelGGL((k_count<K, R8Config<K>::CWG, R8Config<K>::CITEMS, false>), dim3(L.ntiles), dim3(R8Config<K>::CWG), 0, stream,
                                a, nullptr);
             if (prof) profiler_mark(prof, stream, kKindCount, false);
         }
-        if (prof) profiler_mark(prof, stream, kKindTileScan, true);
-        hipLaunchKernelGGL(k_tilescan, dim3(nblk), dim3(R), 0, stream, a);
-        if (prof) profiler_mark(prof, stream, kKindTileScan, false);
+        if (!inline_scan) {
+            if (prof) profiler_mark(prof, stream, kKindTileScan, true);
+            hipLaunchKernelGGL(k_tilescan, dim3(nblk), dim3(R), 0, stream, a);
+            if (prof) profiler_mark(prof, stream, kKindTileScan, false);
+        }
         if (prof) profiler_mark(prof, stream, kKindRound, true);
         hipLaunchKernelGGL((k_scatter<K, KV, WG, ITEMS>), dim3(sgrid), dim3(WG), 0, stream, a);
         if (prof) profiler_mark(prof, stream, kKindRound, false);
