@@ -14,7 +14,9 @@ from tests.gpu_util import announce, check_kv_invariants, dev, host
 
 pytestmark = pytest.mark.gpu
 
-# One to a few hundred 8192-key tiles, ragged tails, powers of two.
+# One to a few hundred 8192-key tiles, ragged tails, powers of two; 2^21 keys
+# (256 tiles) is the largest sort whose scatter sums the tile counts itself,
+# 2^21 + 1 the smallest with the tile-scan kernel.
 SIZES = [1, 2, 63, 64, 65, 1000, 2047, 2048, 2049, 8191, 8192, 8193, 3 * 8192 + 17, 100003,
          1 << 20, 1 << 21, (1 << 21) + 1, 3 * (1 << 20) + 4097]
 
