@@ -136,9 +136,9 @@ struct RoundArgs {
     const RoundPlan* seg_plan = nullptr;
     uint32_t* seg_or = nullptr;
     const uint4* lsegs = nullptr;
-    // Nonzero: there is no tile scan; counts[t][v] stay the tile counts and
-    // the scatter sums them itself (plain sorts of few tiles).
-    uint32_t inline_scan = 0;
+    // Plain sorts of few tiles: round 0's count stores tile t's identity pair
+    // at mixed[2 t] (no atomics, so the words need no clearing beforehand).
+    uint32_t mix_dense = 0;
 };
 
 // The plan of round a.round for tile t: the segment's plan in a segmented
@@ -387,14 +387,24 @@ __device__ void plan_rounds(const int* identity, uint32_t nrounds, int alias, Ro
     plan[kMaxRounds] = pc;
 }
 
-// The round plan of the count-first path.  The OR of the kMixSlots pairs is
-// the OR over all keys of (key XOR first key): a round is the identity
-// exactly when its digit's bits are zero there.
+// The round plan of the count-first path.  The OR of the kMixSlots pairs (or,
+// with dense_pairs > 0, of the pairs mixed[2 i], i < dense_pairs, one per
+// tile) is the OR over all keys of (key XOR first key): a round is the
+// identity exactly when its digit's bits are zero there.
 __global__ void k_plan(const uint32_t* mixed, uint32_t nrounds, uint32_t begin_bit,
-                       uint32_t end_bit, int alias, RoundPlan* plan)
+                       uint32_t end_bit, int alias, RoundPlan* plan, uint32_t dense_pairs)
 {
-    const uint32_t t = threadIdx.x;   // 64 threads, one per pair
-    uint32_t mlo = mixed[t * kMixStride], mhi = mixed[t * kMixStride + 1];
+    const uint32_t t = threadIdx.x;   // 64 threads
+    uint32_t mlo = 0, mhi = 0;
+    if (dense_pairs) {
+        for (uint32_t i = t; i < dense_pairs; i += 64) {
+            mlo |= mixed[2 * i];
+            mhi |= mixed[2 * i + 1];
+        }
+    } else {
+        mlo = mixed[t * kMixStride];
+        mhi = mixed[t * kMixStride + 1];
+    }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
         mlo |= __shfl_xor(mlo, o, 64);
@@ -530,11 +540,15 @@ __global__ __launch_bounds__(WG) void k_count(RoundArgs a, uint32_t* mixed)
     }
     __syncthreads();
     if (ALL && tid < 2) {
-        // only bits the workgroup's pair lacks cost an atomic
-        uint32_t* mw = a.seg_or ? &a.seg_or[2 * a.tile_seg[tile] + tid]
-                                : &mixed[(blockIdx.x % kMixSlots) * kMixStride + tid];
-        const uint32_t mine = mix_s[tid];
-        if (mine & ~ld_agent(mw)) atomicOr(mw, mine);
+        if (!a.seg_or && a.mix_dense) {
+            mixed[2 * tile + tid] = mix_s[tid];
+        } else {
+            // only bits the workgroup's pair lacks cost an atomic
+            uint32_t* mw = a.seg_or ? &a.seg_or[2 * a.tile_seg[tile] + tid]
+                                    : &mixed[(blockIdx.x % kMixSlots) * kMixStride + tid];
+            const uint32_t mine = mix_s[tid];
+            if (mine & ~ld_agent(mw)) atomicOr(mw, mine);
+        }
     }
     for (uint32_t v = tid; v < R; v += WG) {
         const uint4* r4 = (const uint4*)&h[v * 32];
@@ -642,7 +656,7 @@ __device__ __forceinline__ uint32_t inline_tile_offset(const RoundArgs& a, uint3
                                                        uint32_t* scratch, uint32_t* wsum)
 {
     constexpr uint32_t RG = WG / 64;   // rows per step: 64 threads x 4 digits per row
-    constexpr int U = 4;               // steps in flight
+    constexpr int U = 8;               // steps in flight
     static_assert(WG % 64 == 0 && WG >= 256, "whole rows and a thread per digit");
     const uint32_t tid = threadIdx.x, c4 = tid & 63, rg = tid >> 6;
     const uint32_t lane = tid & 63, wave = tid >> 6;
@@ -704,8 +718,14 @@ __device__ __forceinline__ uint32_t inline_tile_offset(const RoundArgs& a, uint3
 //   stage  each key goes to LDS at base + rank, the tile now in digit order;
 //   scatter consecutive threads write consecutive slots of a digit's run; the
 //          payloads follow in a second staging pass through the same LDS.
-template <typename K, bool KV, int WG, int ITEMS>
-__global__ __launch_bounds__(WG, !KV ? RSORT_R8_WAVES_PER_EU : sizeof(K) == 4 ? RSORT_R8_WAVES_PER_EU_KV : RSORT_R8_WAVES_PER_EU_KV64) void k_scatter(RoundArgs a)
+//
+// INL (plain sorts of few tiles): there is no tile scan; counts[t][v] are the
+// tile counts and the workgroup sums them itself (inline_tile_offset).  A
+// separate instantiation, so that the registers of the usual one stay as
+// they are; with at most a few hundred tiles it needs no more than one
+// workgroup per CU, so it may use more registers.
+template <typename K, bool KV, int WG, int ITEMS, bool INL = false>
+__global__ __launch_bounds__(WG, INL ? WG / 256 : !KV ? RSORT_R8_WAVES_PER_EU : sizeof(K) == 4 ? RSORT_R8_WAVES_PER_EU_KV : RSORT_R8_WAVES_PER_EU_KV64) void k_scatter(RoundArgs a)
 {
     constexpr int G = RSORT_RANK_GROUP;         // lanes per ranking group
     constexpr int NG = WG / G;                  // ranking groups
@@ -826,7 +846,7 @@ __global__ __launch_bounds__(WG, !KV ? RSORT_R8_WAVES_PER_EU : sizeof(K) == 4 ? 
         const uint32_t lim = decltype(full)::value ? TILE : tile_range(a, tile, TILE).y;
         constexpr uint32_t slot_u4 = NG * R * (G == 32 ? 8 : 4) / 16;
         uint32_t toff = 0;
-        if (a.inline_scan) {
+        if constexpr (INL) {
             // the LDS scratch is read before the barrier that ends the call
             // and zeroed below only after it
             toff = inline_tile_offset<WG>(a, tile, sm.u.words, sm.wsum);

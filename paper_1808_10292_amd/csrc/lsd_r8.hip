@@ -165,25 +165,6 @@ hipError_t run(const void* keys_in, void* keys_out, const uint32_t* vals_in, uin
 
     uint32_t* mixed = hist;   // kMixWords words
     static_assert(kMixWords <= (size_t)kHistReplicas * kMaxRounds * R, "identity words fit");
-    hipLaunchKernelGGL(k_init, dim3(256), dim3(256), 0, stream, mixed, kMixWords, tickets, nr, blk_state,
-                       (size_t)nr * nblk * R);
-    // Round 0's tile counts and the identity test of every round in one read.
-    {
-        RoundArgs a0 = round_args(keys_in, keys_out, keys_tmp, vals_in, vals_out, vals_tmp, n,
-                                  begin_bit, end_bit, 0, L, bases, plan, counts, blk_state,
-                                  tickets, dev_err);
-        if (prof) profiler_mark(prof, stream, kKindHist, true);
-        hipLaunchKernelGGL((k_count<K, R8Config<K>::CWG, R8Config<K>::CITEMS, true>), dim3(L.ntiles), dim3(R8Config<K>::CWG), 0, stream, a0,
-                           mixed);
-        if (prof) profiler_mark(prof, stream, kKindHist, false);
-    }
-    hipLaunchKernelGGL(k_plan, dim3(1), dim3(64), 0, stream, (const uint32_t*)mixed, nr,
-                       (uint32_t)begin_bit, (uint32_t)end_bit, alias, plan);
-    if (in_place && (nr & 1)) {
-        const uint32_t g = (uint32_t)((n + 256 * kPrecopyItems - 1) / (256 * kPrecopyItems));
-        hipLaunchKernelGGL(k_precopy<K>, dim3(g), dim3(256), 0, stream, (const RoundPlan*)plan,
-                           (const K*)keys_in, keys_tmp, KV ? vals_in : nullptr, vals_tmp, (uint32_t)n);
-    }
     // Scatter grid: one workgroup per tile, or RSORT_SCATTER_WAVES resident
     // workgroups per CU looping over the tiles.
     uint32_t sgrid = L.ntiles;
@@ -191,13 +172,38 @@ hipError_t run(const void* keys_in, void* keys_out, const uint32_t* vals_in, uin
         const uint32_t resident = persistent_blocks((const void*)k_scatter<K, KV, WG, ITEMS>, WG);
         sgrid = std::min<uint32_t>(L.ntiles, resident & ~7u ? resident & ~7u : resident);
     }
-    // few tiles: no tile-scan kernel, the scatter sums the tile counts itself
+    // Few tiles: no tile-scan kernel (the scatter sums the tile counts
+    // itself) and one identity pair per tile, stored without atomics, so
+    // nothing needs clearing before round 0's count.
     const bool inline_scan = L.ntiles <= RSORT_INLINE_SCAN_TILES && sgrid == L.ntiles;
+    static_assert(2 * RSORT_INLINE_SCAN_TILES <= (size_t)kHistReplicas * kMaxRounds * R,
+                  "one identity pair per tile fits");
+    if (!inline_scan)
+        hipLaunchKernelGGL(k_init, dim3(256), dim3(256), 0, stream, mixed, kMixWords, tickets, nr,
+                           blk_state, (size_t)nr * nblk * R);
+    // Round 0's tile counts and the identity test of every round in one read.
+    {
+        RoundArgs a0 = round_args(keys_in, keys_out, keys_tmp, vals_in, vals_out, vals_tmp, n,
+                                  begin_bit, end_bit, 0, L, bases, plan, counts, blk_state,
+                                  tickets, dev_err);
+        a0.mix_dense = inline_scan ? 1u : 0u;
+        if (prof) profiler_mark(prof, stream, kKindHist, true);
+        hipLaunchKernelGGL((k_count<K, R8Config<K>::CWG, R8Config<K>::CITEMS, true>), dim3(L.ntiles), dim3(R8Config<K>::CWG), 0, stream, a0,
+                           mixed);
+        if (prof) profiler_mark(prof, stream, kKindHist, false);
+    }
+    hipLaunchKernelGGL(k_plan, dim3(1), dim3(64), 0, stream, (const uint32_t*)mixed, nr,
+                       (uint32_t)begin_bit, (uint32_t)end_bit, alias, plan,
+                       inline_scan ? L.ntiles : 0u);
+    if (in_place && (nr & 1)) {
+        const uint32_t g = (uint32_t)((n + 256 * kPrecopyItems - 1) / (256 * kPrecopyItems));
+        hipLaunchKernelGGL(k_precopy<K>, dim3(g), dim3(256), 0, stream, (const RoundPlan*)plan,
+                           (const K*)keys_in, keys_tmp, KV ? vals_in : nullptr, vals_tmp, (uint32_t)n);
+    }
     for (uint32_t d = 0; d < nr; ++d) {
-        RoundArgs a = round_args(keys_in, keys_out, keys_tmp, vals_in, vals_out, vals_tmp, n,
-                                 begin_bit, end_bit, d, L, bases, plan, counts, blk_state,
-                                 tickets, dev_err);
-        a.inline_scan = inline_scan ? 1u : 0u;
+        const RoundArgs a = round_args(keys_in, keys_out, keys_tmp, vals_in, vals_out, vals_tmp, n,
+                                       begin_bit, end_bit, d, L, bases, plan, counts, blk_state,
+                                       tickets, dev_err);
         if (d > 0) {   // round 0 was counted with the histograms
             if (prof) profiler_mark(prof, stream, kKindCount, true);
             hipLaunchKernelGGL((k_count<K, R8Config<K>::CWG, R8Config<K>::CITEMS, false>), dim3(L.ntiles), dim3(R8Config<K>::CWG), 0, stream,
@@ -210,7 +216,10 @@ hipError_t run(const void* keys_in, void* keys_out, const uint32_t* vals_in, uin
             if (prof) profiler_mark(prof, stream, kKindTileScan, false);
         }
         if (prof) profiler_mark(prof, stream, kKindRound, true);
-        hipLaunchKernelGGL((k_scatter<K, KV, WG, ITEMS>), dim3(sgrid), dim3(WG), 0, stream, a);
+        if (inline_scan)
+            hipLaunchKernelGGL((k_scatter<K, KV, WG, ITEMS, true>), dim3(sgrid), dim3(WG), 0, stream, a);
+        else
+            hipLaunchKernelGGL((k_scatter<K, KV, WG, ITEMS>), dim3(sgrid), dim3(WG), 0, stream, a);
         if (prof) profiler_mark(prof, stream, kKindRound, false);
     }
     return hipGetLastError();
