@@ -78,6 +78,14 @@ constexpr uint32_t kNoTile = 0xFFFFFFFFu;
 #ifndef RSORT_INLINE_SCAN_TILES
 #define RSORT_INLINE_SCAN_TILES 256
 #endif
+// Plain 32-bit sorts (counted rounds) of at most this many keys use tiles of
+// kSmallWG32 x kSmallItems32 keys.
+#ifndef RSORT_SMALL_TILE_MAXN
+#define RSORT_SMALL_TILE_MAXN (1u << 20)
+#endif
+constexpr int kSmallWG32 = 512;
+constexpr int kSmallItems32 = 8;
+constexpr uint32_t kSmallTile32 = kSmallWG32 * kSmallItems32;
 
 // Count kernel workgroup size (same tile, ITEMS = tile / CWG) and whether full
 // tiles are read with 16-byte loads.
@@ -739,7 +747,7 @@ __global__ __launch_bounds__(WG, INL ? WG / 256 : !KV ? RSORT_R8_WAVES_PER_EU : 
     constexpr bool split_counts = G == 32 && !rank_first;
     static_assert(G == 16 || G == 32, "ranking groups of 16 or 32 lanes");
     static_assert(G == 32 || (uint64_t)TILE < 65536, "16-bit slot counts");
-    static_assert(TILE * sizeof(K) >= NG * R * (G == 32 ? 8 : 4), "staging must cover the slots");
+    static_assert(INL || TILE * sizeof(K) >= NG * R * (G == 32 ? 8 : 4), "staging must cover the slots");
     static_assert(2 * NG * R >= 2 * (WG / 64) * R, "the inline tile scan's scratch fits the slot words");
     struct Smem {
         union {

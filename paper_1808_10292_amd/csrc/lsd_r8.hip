@@ -141,13 +141,13 @@ RoundArgs round_args(const void* keys_in, void* keys_out, void* keys_tmp, const 
     return a;
 }
 
-template <typename K, bool KV>
+template <typename K, bool KV, int WG = R8Config<K>::WG, int ITEMS = R8Config<K>::ITEMS>
 hipError_t run(const void* keys_in, void* keys_out, const uint32_t* vals_in, uint32_t* vals_out,
                size_t n, int begin_bit, int end_bit, void* ws, const LsdR8Layout& L,
                uint32_t* dev_err, hipStream_t stream, Profiler* prof)
 {
-    constexpr int WG = R8Config<K>::WG;
-    constexpr int ITEMS = R8Config<K>::ITEMS;
+    constexpr int CWG = R8Config<K>::CWG;          // count kernel: same tile
+    constexpr int CITEMS = WG * ITEMS / CWG;
     uint8_t* w = (uint8_t*)ws;
     uint32_t* hist = (uint32_t*)(w + L.off_hist);
     uint32_t* bases = (uint32_t*)(w + L.off_bases);
@@ -167,8 +167,12 @@ hipError_t run(const void* keys_in, void* keys_out, const uint32_t* vals_in, uin
     static_assert(kMixWords <= (size_t)kHistReplicas * kMaxRounds * R, "identity words fit");
     // Scatter grid: one workgroup per tile, or RSORT_SCATTER_WAVES resident
     // workgroups per CU looping over the tiles.
+    // The small-tile shape exists only for sorts of few tiles (inline scan).
+    constexpr bool kSmallShape = sizeof(K) == 4 && WG == kSmallWG32 && ITEMS == kSmallItems32;
+    static_assert((size_t)RSORT_SMALL_TILE_MAXN <= (size_t)RSORT_INLINE_SCAN_TILES * kSmallTile32,
+                  "small-tile sorts have few enough tiles for the inline scan");
     uint32_t sgrid = L.ntiles;
-    if (RSORT_SCATTER_PERSIST) {
+    if constexpr (RSORT_SCATTER_PERSIST && !kSmallShape) {
         const uint32_t resident = persistent_blocks((const void*)k_scatter<K, KV, WG, ITEMS>, WG);
         sgrid = std::min<uint32_t>(L.ntiles, resident & ~7u ? resident & ~7u : resident);
     }
@@ -188,7 +192,7 @@ hipError_t run(const void* keys_in, void* keys_out, const uint32_t* vals_in, uin
                                   tickets, dev_err);
         a0.mix_dense = inline_scan ? 1u : 0u;
         if (prof) profiler_mark(prof, stream, kKindHist, true);
-        hipLaunchKernelGGL((k_count<K, R8Config<K>::CWG, R8Config<K>::CITEMS, true>), dim3(L.ntiles), dim3(R8Config<K>::CWG), 0, stream, a0,
+        hipLaunchKernelGGL((k_count<K, CWG, CITEMS, true>), dim3(L.ntiles), dim3(R8Config<K>::CWG), 0, stream, a0,
                            mixed);
         if (prof) profiler_mark(prof, stream, kKindHist, false);
     }
@@ -206,7 +210,7 @@ hipError_t run(const void* keys_in, void* keys_out, const uint32_t* vals_in, uin
                                        tickets, dev_err);
         if (d > 0) {   // round 0 was counted with the histograms
             if (prof) profiler_mark(prof, stream, kKindCount, true);
-            hipLaunchKernelGGL((k_count<K, R8Config<K>::CWG, R8Config<K>::CITEMS, false>), dim3(L.ntiles), dim3(R8Config<K>::CWG), 0, stream,
+            hipLaunchKernelGGL((k_count<K, CWG, CITEMS, false>), dim3(L.ntiles), dim3(R8Config<K>::CWG), 0, stream,
                                a, nullptr);
             if (prof) profiler_mark(prof, stream, kKindCount, false);
         }
@@ -216,10 +220,14 @@ hipError_t run(const void* keys_in, void* keys_out, const uint32_t* vals_in, uin
             if (prof) profiler_mark(prof, stream, kKindTileScan, false);
         }
         if (prof) profiler_mark(prof, stream, kKindRound, true);
-        if (inline_scan)
+        if constexpr (kSmallShape) {
             hipLaunchKernelGGL((k_scatter<K, KV, WG, ITEMS, true>), dim3(sgrid), dim3(WG), 0, stream, a);
-        else
-            hipLaunchKernelGGL((k_scatter<K, KV, WG, ITEMS>), dim3(sgrid), dim3(WG), 0, stream, a);
+        } else {
+            if (inline_scan)
+                hipLaunchKernelGGL((k_scatter<K, KV, WG, ITEMS, true>), dim3(sgrid), dim3(WG), 0, stream, a);
+            else
+                hipLaunchKernelGGL((k_scatter<K, KV, WG, ITEMS>), dim3(sgrid), dim3(WG), 0, stream, a);
+        }
         if (prof) profiler_mark(prof, stream, kKindRound, false);
     }
     return hipGetLastError();
@@ -323,6 +331,10 @@ LsdR8Layout lsd_r8_layout(int key_bytes, bool has_vals, size_t n, int begin_bit,
     L.rounds = rounds_of(begin_bit, end_bit, 8);
     L.tile = key_bytes == 8 ? R8Config<uint64_t>::WG * R8Config<uint64_t>::ITEMS
                             : R8Config<uint32_t>::WG * R8Config<uint32_t>::ITEMS;
+    // small 32-bit sorts (counted rounds): tiles of half the keys, so that
+    // twice as many workgroups share the work of a round and each ranks half
+    // as many rows
+    if (key_bytes == 4 && !single_read && n <= (size_t)RSORT_SMALL_TILE_MAXN) L.tile = kSmallTile32;
     L.ntiles = (uint32_t)((n + L.tile - 1) / L.tile);
     const uint32_t nblk = nblocks_of(L.ntiles);
     size_t o = 0;
@@ -367,6 +379,9 @@ hipError_t lsd_r8_sort(int key_bytes, const void* keys_in, void* keys_out,
     if (L.onesweep)
         return kv ? run_os<true>(keys_in, keys_out, vals_in, vals_out, n, begin_bit, end_bit, ws, L, dev_err, stream, prof)
                   : run_os<false>(keys_in, keys_out, vals_in, vals_out, n, begin_bit, end_bit, ws, L, dev_err, stream, prof);
+    if (key_bytes == 4 && L.tile == kSmallTile32)
+        return kv ? run<uint32_t, true, kSmallWG32, kSmallItems32>(keys_in, keys_out, vals_in, vals_out, n, begin_bit, end_bit, ws, L, dev_err, stream, prof)
+                  : run<uint32_t, false, kSmallWG32, kSmallItems32>(keys_in, keys_out, vals_in, vals_out, n, begin_bit, end_bit, ws, L, dev_err, stream, prof);
     if (key_bytes == 4)
         return kv ? run<uint32_t, true>(keys_in, keys_out, vals_in, vals_out, n, begin_bit, end_bit, ws, L, dev_err, stream, prof)
                   : run<uint32_t, false>(keys_in, keys_out, vals_in, vals_out, n, begin_bit, end_bit, ws, L, dev_err, stream, prof);
