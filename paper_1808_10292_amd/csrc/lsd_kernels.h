@@ -147,6 +147,9 @@ struct RoundArgs {
     // Plain sorts of few tiles: round 0's count stores tile t's identity pair
     // at mixed[2 t] (no atomics, so the words need no clearing beforehand).
     uint32_t mix_dense = 0;
+    // ... and its counts stores the tile counts as 16-bit words (rows of 512
+    // bytes), which the scatter's inline tile scan reads.
+    uint32_t counts16 = 0;
 };
 
 // The plan of round a.round for tile t: the segment's plan in a segmented
@@ -566,7 +569,10 @@ __global__ __launch_bounds__(WG) void k_count(RoundArgs a, uint32_t* mixed)
             const uint4 x = r4[(q + v) & 7];   // rotate the start so threads spread over banks
             s += x.x + x.y + x.z + x.w;
         }
-        a.counts[(size_t)tile * R + v] = s;
+        if (a.counts16)
+            ((uint16_t*)a.counts)[(size_t)tile * R + v] = (uint16_t)s;
+        else
+            a.counts[(size_t)tile * R + v] = s;
     }
 }
 
@@ -656,36 +662,48 @@ __global__ __launch_bounds__(R) void k_tilescan(RoundArgs a)
 // Output start of each digit's run of tile `tile` without a tile scan: the
 // keys of digit v in the tiles before it plus the start of digit v (the keys
 // of smaller digits in all tiles), for thread v < 256; every thread calls.
-// The rows of tile counts are read as 16-byte vectors, WG / 64 rows per step;
-// scratch holds 2 x (WG / 64) x 256 words of LDS, wsum 4 words.  Each
+// The tile counts are 16-bit here (counts16: a tile holds fewer than 2^16
+// keys), 512-byte rows read as 16-byte vectors of 8 digits, WG / 32 rows per
+// step; scratch holds 2 x (WG / 32) x 256 words of LDS, wsum 4 words.  Each
 // workgroup reads every row, so this is for sorts of few tiles.
 template <int WG>
 __device__ __forceinline__ uint32_t inline_tile_offset(const RoundArgs& a, uint32_t tile,
                                                        uint32_t* scratch, uint32_t* wsum)
 {
-    constexpr uint32_t RG = WG / 64;   // rows per step: 64 threads x 4 digits per row
+    constexpr uint32_t RG = WG / 32;   // rows per step: 32 threads x 8 digits per row
+    constexpr uint32_t ROW = R / 8;    // 16-byte vectors per row
     constexpr int U = 8;               // steps in flight
     static_assert(WG % 64 == 0 && WG >= 256, "whole rows and a thread per digit");
-    const uint32_t tid = threadIdx.x, c4 = tid & 63, rg = tid >> 6;
+    const uint32_t tid = threadIdx.x, c8 = tid & 31, rg = tid >> 5;
     const uint32_t lane = tid & 63, wave = tid >> 6;
     const uint4* rows = (const uint4*)a.counts;
-    uint4 bs = make_uint4(0, 0, 0, 0), ts = make_uint4(0, 0, 0, 0);
+    uint32_t bs[8] = {0, 0, 0, 0, 0, 0, 0, 0}, ts[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (uint32_t t0 = rg; t0 < a.ntiles; t0 += RG * U) {
         uint4 x[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint32_t t = t0 + u * RG;
-            x[u] = t < a.ntiles ? rows[(size_t)t * (R / 4) + c4] : make_uint4(0, 0, 0, 0);
+            x[u] = t < a.ntiles ? rows[(size_t)t * ROW + c8] : make_uint4(0, 0, 0, 0);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const uint32_t f = t0 + u * RG < tile ? 1u : 0u;
-            ts.x += x[u].x; ts.y += x[u].y; ts.z += x[u].z; ts.w += x[u].w;
-            bs.x += f * x[u].x; bs.y += f * x[u].y; bs.z += f * x[u].z; bs.w += f * x[u].w;
+            const uint32_t f = t0 + u * RG < tile ? ~0u : 0u;
+            const uint32_t w[4] = {x[u].x, x[u].y, x[u].z, x[u].w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t lo = w[q] & 0xFFFFu, hi = w[q] >> 16;
+                ts[2 * q] += lo;
+                ts[2 * q + 1] += hi;
+                bs[2 * q] += lo & f;
+                bs[2 * q + 1] += hi & f;
+            }
         }
     }
-    ((uint4*)scratch)[rg * (R / 4) + c4] = bs;
-    ((uint4*)scratch)[(RG + rg) * (R / 4) + c4] = ts;
+    uint4* s4 = (uint4*)scratch;
+    s4[(rg * R + 8 * c8) / 4] = make_uint4(bs[0], bs[1], bs[2], bs[3]);
+    s4[(rg * R + 8 * c8) / 4 + 1] = make_uint4(bs[4], bs[5], bs[6], bs[7]);
+    s4[((RG + rg) * R + 8 * c8) / 4] = make_uint4(ts[0], ts[1], ts[2], ts[3]);
+    s4[((RG + rg) * R + 8 * c8) / 4 + 1] = make_uint4(ts[4], ts[5], ts[6], ts[7]);
     __syncthreads();
     uint32_t before = 0, total = 0, incl = 0;
     if (tid < R) {
@@ -748,7 +766,8 @@ __global__ __launch_bounds__(WG, INL ? WG / 256 : !KV ? RSORT_R8_WAVES_PER_EU : 
     static_assert(G == 16 || G == 32, "ranking groups of 16 or 32 lanes");
     static_assert(G == 32 || (uint64_t)TILE < 65536, "16-bit slot counts");
     static_assert(INL || TILE * sizeof(K) >= NG * R * (G == 32 ? 8 : 4), "staging must cover the slots");
-    static_assert(2 * NG * R >= 2 * (WG / 64) * R, "the inline tile scan's scratch fits the slot words");
+    static_assert(!INL || 2 * NG * R >= 2 * (WG / 32) * R, "the inline tile scan's scratch fits the slot words");
+    static_assert(!INL || TILE < 65536, "16-bit tile counts");
     struct Smem {
         union {
             uint2 slot[NG][R];           // 32-lane groups: {lane set, count}, then {-, slot base}

@@ -191,6 +191,7 @@ hipError_t run(const void* keys_in, void* keys_out, const uint32_t* vals_in, uin
                                   begin_bit, end_bit, 0, L, bases, plan, counts, blk_state,
                                   tickets, dev_err);
         a0.mix_dense = inline_scan ? 1u : 0u;
+        a0.counts16 = inline_scan ? 1u : 0u;
         if (prof) profiler_mark(prof, stream, kKindHist, true);
         hipLaunchKernelGGL((k_count<K, CWG, CITEMS, true>), dim3(L.ntiles), dim3(R8Config<K>::CWG), 0, stream, a0,
                            mixed);
@@ -205,9 +206,10 @@ hipError_t run(const void* keys_in, void* keys_out, const uint32_t* vals_in, uin
                            (const K*)keys_in, keys_tmp, KV ? vals_in : nullptr, vals_tmp, (uint32_t)n);
     }
     for (uint32_t d = 0; d < nr; ++d) {
-        const RoundArgs a = round_args(keys_in, keys_out, keys_tmp, vals_in, vals_out, vals_tmp, n,
-                                       begin_bit, end_bit, d, L, bases, plan, counts, blk_state,
-                                       tickets, dev_err);
+        RoundArgs a = round_args(keys_in, keys_out, keys_tmp, vals_in, vals_out, vals_tmp, n,
+                                 begin_bit, end_bit, d, L, bases, plan, counts, blk_state,
+                                 tickets, dev_err);
+        a.counts16 = inline_scan ? 1u : 0u;
         if (d > 0) {   // round 0 was counted with the histograms
             if (prof) profiler_mark(prof, stream, kKindCount, true);
             hipLaunchKernelGGL((k_count<K, CWG, CITEMS, false>), dim3(L.ntiles), dim3(R8Config<K>::CWG), 0, stream,
