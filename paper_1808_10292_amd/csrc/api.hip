@@ -130,6 +130,9 @@ struct rsort_ctx {
     size_t meta_bytes = 0;
     hipEvent_t meta_done = nullptr;
     bool meta_pending = false;
+    // second stream of the segmented sort (whole-segment sorts beside the
+    // large segments' rounds) and its fork / join events; made on first use
+    rsort::SegOverlap seg_ov;
     uint32_t small_max = rsort::kSmallMaxDefault;
     int small_sort = RSORT_SMALL_RADIX;   // sorter of the small segments
     int seg_tile_shape = rsort::kSegTileShapeDefault;   // tiles of the large segments
@@ -350,6 +353,9 @@ int rsort_destroy(rsort_ctx* ctx)
         delete ctx->prof;
         if (ctx->meta_host) (void)hipHostFree(ctx->meta_host);
         if (ctx->meta_done) (void)hipEventDestroy(ctx->meta_done);
+        if (ctx->seg_ov.fork) (void)hipEventDestroy(ctx->seg_ov.fork);
+        if (ctx->seg_ov.join) (void)hipEventDestroy(ctx->seg_ov.join);
+        if (ctx->seg_ov.aux) (void)hipStreamDestroy(ctx->seg_ov.aux);
         if (ctx->ws) (void)hipFree(ctx->ws);
         if (ctx->dev_err) (void)hipFree(ctx->dev_err);
         if (ctx->gsd_stats) (void)hipFree(ctx->gsd_stats);
@@ -818,6 +824,33 @@ size_t seg_plan_for(rsort_ctx* ctx, const uint64_t* seg_offsets, size_t num_segs
     return rsort::segmented_ws_bytes(kb, has_vals, total, P);
 }
 
+// The segmented sort's second stream and events (default priority, made on
+// first use); null when they cannot be made or RSORT_SEG_OVERLAP is 0, and
+// the sort then runs on the caller's stream alone.
+#ifndef RSORT_SEG_OVERLAP
+#define RSORT_SEG_OVERLAP 1
+#endif
+const rsort::SegOverlap* seg_overlap(rsort_ctx* ctx)
+{
+    if (!RSORT_SEG_OVERLAP) return nullptr;
+    rsort::SegOverlap& o = ctx->seg_ov;
+    if (!o.aux) {
+        hipStream_t st = nullptr;
+        hipEvent_t f = nullptr, j = nullptr;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return nullptr;
+        if (hipEventCreateWithFlags(&f, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&j, hipEventDisableTiming) != hipSuccess) {
+            if (f) (void)hipEventDestroy(f);
+            (void)hipStreamDestroy(st);
+            return nullptr;
+        }
+        o.aux = st;
+        o.fork = f;
+        o.join = j;
+    }
+    return &o;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1026,7 +1059,8 @@ int rsort_segmented_sort(rsort_ctx* ctx, int key_type, const void* keys_in, void
             ? rsort::persist_sort(kb, keys_in, keys_out, vals_in, vals_out, total, P, nullptr, ws,
                                   ctx->dev_err, s, nullptr)
             : rsort::segmented_sort(kb, keys_in, keys_out, vals_in, vals_out, total, P,
-                                    nullptr, ws, ctx->dev_err, s, nullptr, ctx->small_sort);
+                                    nullptr, ws, ctx->dev_err, s, nullptr, ctx->small_sort,
+                                    seg_overlap(ctx));
         return e == hipSuccess ? RSORT_OK : hip_fail(ctx, e, "segmented sort capture");
     }
     // pinned staging of the plan: wait until its previous upload has completed
@@ -1054,7 +1088,8 @@ int rsort_segmented_sort(rsort_ctx* ctx, int key_type, const void* keys_in, void
     } else {
         rsort::segmented_pack(P, kb, ctx->meta_host);
         e = rsort::segmented_sort(kb, keys_in, keys_out, vals_in, vals_out, total, P,
-                                  ctx->meta_host, ws, ctx->dev_err, s, ctx->prof, ctx->small_sort);
+                                  ctx->meta_host, ws, ctx->dev_err, s, ctx->prof, ctx->small_sort,
+                                  seg_overlap(ctx));
     }
     if (e != hipSuccess) return hip_fail(ctx, e, "segmented sort launch");
     if (hipEventRecord(ctx->meta_done, s) == hipSuccess) ctx->meta_pending = true;

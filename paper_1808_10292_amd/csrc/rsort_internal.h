@@ -111,10 +111,18 @@ size_t segmented_meta_bytes(const SegPlan& P);
 size_t segmented_ws_bytes(int key_bytes, bool has_vals, size_t total, const SegPlan& P);
 void segmented_pack(const SegPlan& P, int key_bytes, void* host);
 // small_sort: the sorter of the small segments (0 radix rounds, 1 BTN, 2 OET).
+// Overlap (optional): the whole-segment sorts run on `aux`, forked from and
+// joined back into `stream` with the two events, while the large segments'
+// rounds run on `stream` (the two touch disjoint key ranges).
+struct SegOverlap {
+    hipStream_t aux = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
 hipError_t segmented_sort(int key_bytes, const void* keys_in, void* keys_out,
                           const uint32_t* vals_in, uint32_t* vals_out, size_t total,
                           const SegPlan& P, const void* host_meta, void* ws, uint32_t* dev_err,
-                          hipStream_t stream, Profiler* prof, int small_sort = 0);
+                          hipStream_t stream, Profiler* prof, int small_sort = 0,
+                          const SegOverlap* ov = nullptr);
 
 // The same sort in one persistent launch (seg_persist.hip): a resident grid
 // takes histogram, small-segment and round items from one ticket counter.

@@ -488,7 +488,7 @@ template <typename K, bool KV>
 hipError_t run_segmented(const void* keys_in, void* keys_out, const uint32_t* vals_in,
                          uint32_t* vals_out, size_t total, const SegPlan& P, const void* host_meta,
                          void* ws, uint32_t* dev_err, hipStream_t stream, Profiler* prof,
-                         int small_sort)
+                         int small_sort, const SegOverlap* ov)
 {
     const uint32_t nrounds = sizeof(K);   // 8-bit digits over the whole key
     const size_t nt = P.tiles.size();
@@ -520,11 +520,28 @@ hipError_t run_segmented(const void* keys_in, void* keys_out, const uint32_t* va
     m += nls * sizeof(uint4);
     const uint32_t* tile_seg = (const uint32_t*)m;
 
-    if (prof) profiler_mark(prof, stream, kKindSmall, true);
+    // The whole-segment sorts and the large segments' rounds touch disjoint
+    // key ranges (and the workspace only for the plan, read by both): with an
+    // aux stream the small ones run beside the rounds.
+    const size_t nsmall = P.small[0].size() + P.small[1].size() + P.small[2].size();
+    const bool fork = ov && ov->aux && nsmall && nt;
+    hipStream_t ss = stream;
+    if (fork) {
+        e = hipEventRecord(ov->fork, stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(ov->aux, ov->fork, 0);
+        if (e != hipSuccess) return e;
+        ss = ov->aux;
+    }
+    if (prof) profiler_mark(prof, ss, kKindSmall, true);
     for (int c = 0; c < 3; ++c)
         launch_small<K, KV>(c, keys_in, keys_out, KV ? vals_in : nullptr, KV ? vals_out : nullptr,
-                            small[c], (uint32_t)P.small[c].size(), nrounds, stream, small_sort);
-    if (prof) profiler_mark(prof, stream, kKindSmall, false);
+                            small[c], (uint32_t)P.small[c].size(), nrounds, ss, small_sort);
+    if (prof) profiler_mark(prof, ss, kKindSmall, false);
+    if (fork) {
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipEventRecord(ov->join, ov->aux);
+        if (e != hipSuccess) return e;
+    }
     if (!nt) return hipGetLastError();
 
     const bool keys_alias = keys_in == keys_out, vals_alias = KV && vals_in == vals_out;
@@ -539,7 +556,9 @@ hipError_t run_segmented(const void* keys_in, void* keys_out, const uint32_t* va
     case 2: run_large<K, KV, 1024, IT>(la); break;
     default: run_large<K, KV, 512, IT>(la); break;
     }
-    return hipGetLastError();
+    e = hipGetLastError();
+    if (e == hipSuccess && fork) e = hipStreamWaitEvent(stream, ov->join, 0);
+    return e;
 }
 
 }  // namespace
@@ -547,14 +566,14 @@ hipError_t run_segmented(const void* keys_in, void* keys_out, const uint32_t* va
 hipError_t segmented_sort(int key_bytes, const void* keys_in, void* keys_out,
                           const uint32_t* vals_in, uint32_t* vals_out, size_t total,
                           const SegPlan& P, const void* host_meta, void* ws, uint32_t* dev_err,
-                          hipStream_t stream, Profiler* prof, int small_sort)
+                          hipStream_t stream, Profiler* prof, int small_sort, const SegOverlap* ov)
 {
     const bool kv = vals_in != nullptr;
     if (key_bytes == 4)
-        return kv ? run_segmented<uint32_t, true>(keys_in, keys_out, vals_in, vals_out, total, P, host_meta, ws, dev_err, stream, prof, small_sort)
-                  : run_segmented<uint32_t, false>(keys_in, keys_out, vals_in, vals_out, total, P, host_meta, ws, dev_err, stream, prof, small_sort);
-    return kv ? run_segmented<uint64_t, true>(keys_in, keys_out, vals_in, vals_out, total, P, host_meta, ws, dev_err, stream, prof, small_sort)
-              : run_segmented<uint64_t, false>(keys_in, keys_out, vals_in, vals_out, total, P, host_meta, ws, dev_err, stream, prof, small_sort);
+        return kv ? run_segmented<uint32_t, true>(keys_in, keys_out, vals_in, vals_out, total, P, host_meta, ws, dev_err, stream, prof, small_sort, ov)
+                  : run_segmented<uint32_t, false>(keys_in, keys_out, vals_in, vals_out, total, P, host_meta, ws, dev_err, stream, prof, small_sort, ov);
+    return kv ? run_segmented<uint64_t, true>(keys_in, keys_out, vals_in, vals_out, total, P, host_meta, ws, dev_err, stream, prof, small_sort, ov)
+              : run_segmented<uint64_t, false>(keys_in, keys_out, vals_in, vals_out, total, P, host_meta, ws, dev_err, stream, prof, small_sort, ov);
 }
 
 
