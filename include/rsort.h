@@ -239,20 +239,20 @@ int rsort_segmented_set_tile(rsort_ctx* ctx, int tile_threads);
  *                         the large segments a count, a per-segment scan and
  *                         a scatter kernel (default);
  *   RSORT_SEG_PERSISTENT  one persistent launch (after a fill kernel that
- *                         clears its counters): a resident grid takes work
- *                         items from one ticket counter -- per-tile
- *                         histograms of the large segments, whole small
- *                         segments (at most 8192 32-bit or 4096 64-bit keys,
- *                         radix rounds), then round by round the large
- *                         segments' tiles, each folding in the counts of the
- *                         earlier tiles of its segment by decoupled look-back.
- *                         Items wait only on items handed out before them, and
- *                         every wait is bounded (a wait that gives up is
- *                         reported by rsort_synchronize as RSORT_EDEVICE).
+ *                         clears its counters): a cooperative launch whose
+ *                         resident grid goes through phases separated by
+ *                         grid-wide barriers -- the whole small segments (at
+ *                         most 8192 32-bit or 4096 64-bit keys, radix rounds)
+ *                         beside round 0's tile counts of the large segments,
+ *                         then per round the tile counts, the per-segment
+ *                         output starts (and, first, the per-segment round
+ *                         plans) and the tiles' stable counting rounds.  Every
+ *                         barrier wait is bounded (a wait that gives up is
+ *                         reported by rsort_synchronize as RSORT_EDEVICE).  It
+ *                         is not captured into a graph (RSORT_EUNSUPPORTED
+ *                         inside a capture).
  * Same result either way (Section 3.2's SR4 on every segment).  Chosen by the
  * tuner; applies to later calls on ctx.  RSORT_EINVAL for other values.
- * RSORT_SEG_PERSISTENT is currently switched off (RSORT_EUNSUPPORTED): its
- * first run on the GPU faulted and the cause is not found yet.
  */
 enum rsort_seg_launch { RSORT_SEG_ROUNDS = 0, RSORT_SEG_PERSISTENT = 1 };
 int rsort_segmented_set_launch(rsort_ctx* ctx, int launch);

@@ -804,10 +804,9 @@ int check_offsets(rsort_ctx* ctx, const uint64_t* off, size_t num_segs, size_t* 
     return RSORT_OK;
 }
 
-// The persistent segmented launch (seg_persist.hip) faulted the GPU on its
-// first run; its kernel source is exact and in bounds in a CPU build, so the
-// cause is not known.  Until it is, the launch mode cannot be selected.
-constexpr bool kPersistentLaunch = false;
+// The persistent segmented launch (seg_persist.hip: one cooperative launch,
+// phases separated by grid-wide barriers) can be selected and tuned.
+constexpr bool kPersistentLaunch = true;
 
 // The host plan of a segmented sort on ctx and the workspace it needs, for
 // the context's launch mode (the persistent launch sorts segments of at most
@@ -817,7 +816,8 @@ size_t seg_plan_for(rsort_ctx* ctx, const uint64_t* seg_offsets, size_t num_segs
 {
     if (ctx->seg_launch == RSORT_SEG_PERSISTENT) {
         rsort::segmented_plan(seg_offsets, num_segs,
-                              std::min(ctx->small_max, rsort::persist_small_max(kb)), kb, P, 1);
+                              std::min(ctx->small_max, rsort::persist_small_max(kb)), kb, P,
+                              rsort::persist_tile_shape(kb));
         return rsort::persist_ws_bytes(kb, has_vals, total, P);
     }
     rsort::segmented_plan(seg_offsets, num_segs, ctx->small_max, kb, P, ctx->seg_tile_shape);
@@ -965,8 +965,7 @@ int rsort_segmented_set_launch(rsort_ctx* ctx, int launch)
     if (launch != RSORT_SEG_ROUNDS && launch != RSORT_SEG_PERSISTENT)
         return fail(ctx, RSORT_EINVAL, "unknown segmented launch mode %d", launch);
     if (launch == RSORT_SEG_PERSISTENT && !kPersistentLaunch)
-        return fail(ctx, RSORT_EUNSUPPORTED, "the persistent segmented launch is switched off: its "
-                                             "first GPU run faulted and the cause is not found yet");
+        return fail(ctx, RSORT_EUNSUPPORTED, "the persistent segmented launch is switched off");
     ctx->seg_launch = launch;
     return RSORT_OK;
 }
@@ -1050,6 +1049,9 @@ int rsort_segmented_sort(rsort_ctx* ctx, int key_type, const void* keys_in, void
     mix(num_segs);
     for (size_t i = 0; i <= num_segs; ++i) mix(seg_offsets[i]);
     if (cap == hipStreamCaptureStatusActive) {
+        if (persistent)
+            return fail(ctx, RSORT_EUNSUPPORTED, "the persistent segmented launch is a cooperative "
+                                                 "launch, which is not captured into a graph");
         // No host traffic inside a graph: the plan must already sit in this
         // workspace from an identical call made outside the capture.
         if (sig != ctx->upload_sig || ws != ctx->upload_ws)

@@ -1,13 +1,14 @@
-"""GPU parity of the segmented sort's persistent launch (RSORT_SEG_PERSISTENT)
-against the oracle's per-segment SR4, bit-exact.
+"""GPU parity of the segmented sort's persistent launch (RSORT_SEG_PERSISTENT:
+one cooperative launch, phases separated by grid-wide barriers) against the
+oracle's per-segment SR4, bit-exact.
 
-The cases reach every kind of work item: histogram tiles and round tiles of
-large segments (one tile, ragged last tiles, hundreds of tiles, so that the
-look-back inside a segment's chain of tiles runs), whole small segments of
-both in-LDS capacities, empty and one-key segments, segments whose rounds are
-skipped (per-segment plans, including all-equal segments that are copied),
-u32 / u64 keys, payloads, in place, the all-tiled split, the lognormal
-4096-segment batch, and the tuner choosing between the launch modes.
+The cases reach every phase: whole small segments of both in-LDS forms, tiles
+of large segments (one tile, ragged last tiles, hundreds of tiles per
+segment), empty and one-key segments, segments whose rounds are skipped
+(per-segment plans, including all-equal segments that are copied), u32 / u64
+keys, payloads, in place, the all-tiled split, the lognormal 4096-segment
+batch, repeated launches, the refusal inside a graph capture, and the tuner
+choosing between the launch modes.
 """
 import numpy as np
 import pytest
@@ -17,10 +18,7 @@ import oracle
 from tests.gpu_util import announce, dev, host
 from tests.test_gpu_segmented import BOUNDARY_SIZES, run_case, shaped_segments
 
-pytestmark = [pytest.mark.gpu, pytest.mark.skip(
-    reason="the persistent launch faulted the GPU on its first run (boundary sizes, u32 keys "
-           "only); its kernel source is exact and in bounds in a CPU build with 1 to 114 "
-           "concurrent workgroups, so the cause is unknown and the launch mode is switched off")]
+pytestmark = pytest.mark.gpu
 
 
 @pytest.fixture(scope="module")
@@ -101,9 +99,9 @@ def test_lognormal_batch(rs):
     run_case(rs, keys, sizes, False)
 
 
-def test_repeat_and_graph_capture(rs):
-    """Twenty launches in a row give the same result; replaying a captured
-    graph (the work list already uploaded by an identical call) too."""
+def test_repeat_and_capture_refused(rs):
+    """Twenty launches in a row give the same result; a graph capture of the
+    persistent launch is refused (it is a cooperative launch)."""
     import torch
     sizes = keygen.lognormal_sizes(300, seed=5)
     off = keygen.offsets_from_sizes(sizes)
@@ -123,14 +121,14 @@ def test_repeat_and_graph_capture(rs):
     rs.rsort_segmented_sort(dk, ko, off, workspace=ws)
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g):
-        rs.rsort_segmented_sort(dk, ko, off, workspace=ws)
-    for r in range(5):
-        ko.fill_(0)
-        torch.cuda.synchronize()
-        g.replay()
-        torch.cuda.synchronize()
-        assert np.array_equal(host(ko), want), ("replay", r)
+    with pytest.raises(rs.RsortError) as e:
+        with torch.cuda.graph(g):
+            rs.rsort_segmented_sort(dk, ko, off, workspace=ws)
+    assert e.value.status == rs.RSORT_EUNSUPPORTED
+    torch.cuda.synchronize()
+    rs.rsort_segmented_sort(dk, ko, off)
+    rs.rsort_synchronize()
+    assert np.array_equal(host(ko), want)
 
 
 def test_tuner_searches_launch_modes(rs):
