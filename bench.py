@@ -20,7 +20,8 @@ Printed as one JSON line:
   cpu_baseline the CPU oracle (serial SR4 in C, one thread) on the same keys
   variants     other algorithms on the same keys (reported, not in value)
   batched      4096 lognormal arrays: batched segmented sort vs one plain
-               sort per array, latency p50/p99, graph replay
+               sort per array, latency p50/p99, graph replay, the one-launch
+               persistent mode
   kv           2^28 key-value pairs per key distribution: PR4 vs the
                regular-oversampling sample sort (GSD, p = 256, r = 32)
   small        2^20 keys uniform in [0, 2^31): per-call latency p50/p99
@@ -154,6 +155,13 @@ def bench_batched(rsort, torch, np, keygen, args):
     split, tune_ms = rsort.rsort_segmented_tune(dk, out, off, reps=3)
     sorter = {v: k for k, v in rsort.SMALL_SORTS.items()}[rsort.rsort_segmented_get_small_sort()]
     tuned = rsort.rsort_segmented_get_config()
+    # the one-launch persistent mode on the same batch (the tuner's other launch mode)
+    rsort.rsort_segmented_set_launch("persistent")
+    persist_s = time_steps(lambda: rsort.rsort_segmented_sort(dk, out, off), reps, 1, torch)
+    rsort.rsort_synchronize()
+    gotp = out.cpu().numpy()
+    okp = all(np.array_equal(gotp[a:b], np.sort(keys[a:b])) for a, b in zip(off[:-1:97], off[1::97]))
+    rsort.rsort_segmented_set_launch(tuned["launch"])
     # per-call latency: submit -> completion, one call at a time
     lat = []
     for _ in range(reps):
@@ -165,7 +173,10 @@ def bench_batched(rsort, torch, np, keygen, args):
     got = out.cpu().numpy()
     ok = all(bool(np.all(got[a:b][1:] >= got[a:b][:-1])) for a, b in zip(off[:-1:97], off[1::97]))
     batched = time_steps(lambda: rsort.rsort_segmented_sort(dk, out, off), reps, 2, torch)
-    # the same call replayed from a HIP graph
+    # the same call replayed from a HIP graph (a cooperative launch is not
+    # captured: the rounds then stand in for a persistent pick)
+    if tuned["launch"] == "persistent":
+        rsort.rsort_segmented_set_launch("rounds")
     need = rsort.rsort_segmented_workspace_bytes(torch.uint32, False, off)
     ws = torch.empty(need, dtype=torch.uint8, device="cuda")
     rsort.rsort_segmented_sort(dk, out, off, workspace=ws)
@@ -174,6 +185,7 @@ def bench_batched(rsort, torch, np, keygen, args):
     with torch.cuda.graph(g):
         rsort.rsort_segmented_sort(dk, out, off, workspace=ws)
     graph = time_steps(g.replay, reps, 2, torch)
+    rsort.rsort_segmented_set_launch(tuned["launch"])
     # one plain sort call per array, same stream
     bounds = [(int(a), int(b)) for a, b in zip(off[:-1], off[1:])]
     views = [(dk[a:b], out[a:b]) for a, b in bounds]
@@ -188,7 +200,9 @@ def bench_batched(rsort, torch, np, keygen, args):
             "keys": total, "split_small_max": split, "small_sorter": sorter,
             "tuned": {"split": tuned["split"], "small_sorter": sorter,
                       "tile_threads": tuned["tile_threads"], "radix_bits": tuned["radix_bits"],
-                      "tune_ms": round(tune_ms, 3)},
+                      "launch": tuned["launch"], "tune_ms": round(tune_ms, 3)},
+            "persistent_launch_ms": round(persist_s * 1e3, 3),
+            "persistent_launch_check": "segments equal np.sort (sampled)" if okp else "FAILED",
             "small_sorter_ms_at_split_4096": sorter_ms,
             "batched_ms": round(batched * 1e3, 3), "batched_gkeys_per_s": round(total / batched / 1e9, 3),
             "graph_replay_ms": round(graph * 1e3, 3),
