@@ -978,7 +978,7 @@ int rsort_segmented_get_config(rsort_ctx* ctx, uint32_t* small_max, int* small_s
     const bool persistent = ctx->seg_launch == RSORT_SEG_PERSISTENT;
     if (small_max) *small_max = ctx->small_max;
     if (small_sort) *small_sort = persistent ? (int)RSORT_SMALL_RADIX : ctx->small_sort;
-    if (tile_threads) *tile_threads = persistent ? 512 : threads[ctx->seg_tile_shape];
+    if (tile_threads) *tile_threads = persistent ? rsort::persist_threads() : threads[ctx->seg_tile_shape];
     if (radix_bits) *radix_bits = 8;
     if (launch) *launch = ctx->seg_launch;
     return RSORT_OK;

@@ -130,6 +130,7 @@ hipError_t segmented_sort(int key_bytes, const void* keys_in, void* keys_out,
 // plan's small_max); plan with segmented_plan(..., persist_tile_shape(...)).
 uint32_t persist_small_max(int key_bytes);
 int persist_tile_shape(int key_bytes);   // the plan's tile shape: tiles of persist_small_max keys
+int persist_threads();                    // workgroup size of the persistent kernel
 size_t persist_meta_bytes(const SegPlan& P, int key_bytes);
 size_t persist_ws_bytes(int key_bytes, bool has_vals, size_t total, const SegPlan& P);
 void persist_pack(const SegPlan& P, int key_bytes, void* host);

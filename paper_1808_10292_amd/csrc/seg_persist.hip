@@ -44,12 +44,21 @@ namespace {
 #ifndef RSORT_PERSIST_WAVES
 #define RSORT_PERSIST_WAVES 4
 #endif
-constexpr int kPWG = 512;
+#ifndef RSORT_PERSIST_WG
+#define RSORT_PERSIST_WG 512
+#endif
+constexpr int kPWG = RSORT_PERSIST_WG;
 constexpr int kPSmallItems = 4;   // small segments of at most kPWG * 4 keys: the short form
 constexpr int kPCols = 8;         // LDS count replicas (spread the atomics of equal digits)
 template <typename K> struct PCfg;
 template <> struct PCfg<uint32_t> { static constexpr int ITEMS = RSORT_PERSIST_ITEMS32; };
 template <> struct PCfg<uint64_t> { static constexpr int ITEMS = RSORT_PERSIST_ITEMS32 / 2; };
+// The host plan cuts the large segments into tiles of one of the segmented
+// sort's tile shapes (256, 512 or 1024 threads x 16 keys, x 8 for 64-bit
+// keys); the persistent kernel's tile must be one of them.
+static_assert(kPWG * RSORT_PERSIST_ITEMS32 == 256 * 16 || kPWG * RSORT_PERSIST_ITEMS32 == 512 * 16 ||
+                  kPWG * RSORT_PERSIST_ITEMS32 == 1024 * 16,
+              "the persistent tile is a tile shape of the plan");
 
 struct PArgs {
     const void* keys_in;
@@ -115,6 +124,21 @@ __device__ __forceinline__ uint32_t* pick_vbuf(int which, const PArgs& a)
     return which == 0 ? (uint32_t*)a.vals_in : which == 1 ? a.vals_out : a.vals_tmp;
 }
 
+// Data written by other workgroups earlier in the launch (keys of the round
+// before, tile counts, run starts, plans) is read with agent-scope loads, which
+// the memory model makes coherent across the XCDs' L2 caches; the barrier
+// orders them after the writes.
+__device__ __forceinline__ RoundPlan load_plan(const RoundPlan* p)
+{
+    const int32_t* w = reinterpret_cast<const int32_t*>(p);
+    RoundPlan r;
+    r.exec = ld_agent(&w[0]);
+    r.ord = ld_agent(&w[1]);
+    r.src = ld_agent(&w[2]);
+    r.dst = ld_agent(&w[3]);
+    return r;
+}
+
 // Inclusive sum over the first 256 threads (4 waves); all threads call.
 __device__ __forceinline__ uint32_t sum256(uint32_t x, uint32_t* wsum)
 {
@@ -172,7 +196,7 @@ __device__ void count_item(const PArgs& a, unsigned char* raw, uint32_t r, uint3
     const uint32_t s = a.tile_seg[g];
     const K* src = (const K*)a.keys_in;
     if (r > 0) {
-        const RoundPlan pl = a.seg_plan[(size_t)s * (kMaxRounds + 1) + r];
+        const RoundPlan pl = load_plan(&a.seg_plan[(size_t)s * (kMaxRounds + 1) + r]);
         if (pl.exec != 1) return;   // uniform over the workgroup
         src = pick_buf<K>(pl.src, a);
     }
@@ -187,7 +211,7 @@ __device__ void count_item(const PArgs& a, unsigned char* raw, uint32_t r, uint3
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
         const uint32_t i = tr.x + j * kPWG + tid;
-        kk[j] = i < tr.y ? src[i] : K(0);
+        kk[j] = i < tr.y ? (r == 0 ? src[i] : ld_agent(&src[i])) : K(0);
     }
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
@@ -238,7 +262,7 @@ __device__ void scan_item(const PArgs& a, uint32_t* wsum, RoundPlan* plan_s, uin
             for (uint32_t d = 0; d < NR; ++d) identity[d] = ((mx >> (8u * d)) & 0xFFull) == 0;
             plan_rounds(identity, NR, a.alias, plan);
         }
-        *plan_s = plan[r];
+        *plan_s = load_plan(&plan[r]);
     }
     __syncthreads();
     const RoundPlan pl = *plan_s;
@@ -252,7 +276,7 @@ __device__ void scan_item(const PArgs& a, uint32_t* wsum, RoundPlan* plan_s, uin
         for (uint32_t t = sg.x; t < sg.y; t += B) {
             uint32_t c[B];
 #pragma unroll
-            for (uint32_t j = 0; j < B; ++j) c[j] = t + j < sg.y ? a.cnt[(size_t)(t + j) * R + tid] : 0u;
+            for (uint32_t j = 0; j < B; ++j) c[j] = t + j < sg.y ? ld_agent(&a.cnt[(size_t)(t + j) * R + tid]) : 0u;
 #pragma unroll
             for (uint32_t j = 0; j < B; ++j) total += c[j];
         }
@@ -263,7 +287,7 @@ __device__ void scan_item(const PArgs& a, uint32_t* wsum, RoundPlan* plan_s, uin
         for (uint32_t t = sg.x; t < sg.y; t += B) {
             uint32_t c[B];
 #pragma unroll
-            for (uint32_t j = 0; j < B; ++j) c[j] = t + j < sg.y ? a.cnt[(size_t)(t + j) * R + tid] : 0u;
+            for (uint32_t j = 0; j < B; ++j) c[j] = t + j < sg.y ? ld_agent(&a.cnt[(size_t)(t + j) * R + tid]) : 0u;
 #pragma unroll
             for (uint32_t j = 0; j < B; ++j)
                 if (t + j < sg.y) {
@@ -284,7 +308,7 @@ __device__ void scatter_item(const PArgs& a, unsigned char* raw, uint32_t* goff,
     auto& sm = *reinterpret_cast<TileSmem<K, KV, kPWG, ITEMS, true>*>(raw);
     const uint32_t tid = threadIdx.x;
     const uint32_t s = a.tile_seg[g];
-    const RoundPlan pl = a.seg_plan[(size_t)s * (kMaxRounds + 1) + r];
+    const RoundPlan pl = load_plan(&a.seg_plan[(size_t)s * (kMaxRounds + 1) + r]);
     if (pl.exec == 0) return;   // uniform over the workgroup
     const uint2 tr = a.tiles[g];
     const uint32_t len = tr.y - tr.x;
@@ -308,12 +332,12 @@ __device__ void scatter_item(const PArgs& a, unsigned char* raw, uint32_t* goff,
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const uint32_t o = hofs + i * 32;
-        k[i] = o < len ? src[tr.x + o] : K(0);
-        v[i] = KV && o < len ? vsrc[tr.x + o] : 0u;
+        k[i] = o < len ? ld_agent(&src[tr.x + o]) : K(0);
+        v[i] = KV && o < len ? ld_agent(&vsrc[tr.x + o]) : 0u;
     }
     // goff[v] = output index of sorted tile position 0 of digit v's run
-    const uint32_t c = tid < R ? a.cnt[(size_t)g * R + tid] : 0u;
-    const uint32_t st = tid < R ? a.start[(size_t)g * R + tid] : 0u;
+    const uint32_t c = tid < R ? ld_agent(&a.cnt[(size_t)g * R + tid]) : 0u;
+    const uint32_t st = tid < R ? ld_agent(&a.start[(size_t)g * R + tid]) : 0u;
     const uint32_t incl = sum256(c, wsum);
     if (tid < R) goff[tid] = st - (incl - c);
     const uint32_t shift = 8u * r;
@@ -393,6 +417,8 @@ uint32_t persist_small_max(int key_bytes)
 {
     return key_bytes == 8 ? kPWG * PCfg<uint64_t>::ITEMS : kPWG * PCfg<uint32_t>::ITEMS;
 }
+
+int persist_threads() { return kPWG; }
 
 int persist_tile_shape(int key_bytes)
 {
