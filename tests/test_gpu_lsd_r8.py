@@ -349,3 +349,30 @@ def test_full_size_kv_pr4(rs, dist):
     rs.rsort_synchronize()
     del dk, dv
     check_kv_invariants(keys, host(ko), host(vo).view(np.uint32))
+
+
+@pytest.mark.parametrize("dtype,n", [(np.uint32, 1 << 20), (np.uint32, (1 << 20) + 1),
+                                     (np.uint32, 1 << 21), (np.uint32, (1 << 21) + 1),
+                                     (np.uint64, 1 << 20), (np.uint64, (1 << 20) + 1)])
+@pytest.mark.parametrize("in_place", [False, True])
+def test_tile_shape_and_inline_scan_limits(rs, dtype, n, in_place):
+    """Both sides of each size limit of the few-tile forms: 32-bit sorts of at
+    most 2^20 keys (4096-key tiles), at most 256 tiles (no tile-scan kernel,
+    16-bit tile counts summed by every scatter workgroup), and the tile-scan
+    form beyond; with payloads, in and out of place, against the oracle."""
+    import torch
+    announce("tile limits", np.dtype(dtype).name, n, in_place)
+    keys = (keygen.uniform_u32(n, 300 + n) if dtype == np.uint32
+            else keygen.uniform_u64(n, 300 + n))
+    keys[::9] = keys[4]                       # runs of equal keys across tiles
+    vals = np.arange(n, dtype=np.uint32)
+    wk, wv = oracle.sr4(keys, vals)
+    dk, dv = dev(keys), dev(vals)
+    if in_place:
+        rs.rsort_sort(dk, dk, dv, dv)
+        ko, vo = dk, dv
+    else:
+        ko, vo = torch.empty_like(dk), torch.empty_like(dv)
+        rs.rsort_sort(dk, ko, dv, vo)
+    rs.rsort_synchronize()
+    assert np.array_equal(host(ko), wk) and np.array_equal(host(vo), wv)
