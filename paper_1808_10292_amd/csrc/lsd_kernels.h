@@ -150,6 +150,10 @@ struct RoundArgs {
     // ... and its counts stores the tile counts as 16-bit words (rows of 512
     // bytes), which the scatter's inline tile scan reads.
     uint32_t counts16 = 0;
+    // Device-planned segmented sorts given a device round count (the buckets
+    // of the sample sort): when it is 0 nothing is sorted, and round 0's
+    // count returns at once.
+    const uint32_t* dev_rounds = nullptr;
 };
 
 // The plan of round a.round for tile t: the segment's plan in a segmented
@@ -487,6 +491,7 @@ __global__ __launch_bounds__(WG) void k_count(RoundArgs a, uint32_t* mixed)
     if (a.ntiles_dev && tile >= *a.ntiles_dev) return;
     RoundPlan pl;
     if (ALL) {
+        if (a.dev_rounds && *a.dev_rounds == 0) return;
         pl = RoundPlan{1, 0, 0, 0};
     } else {
         pl = round_plan_of(a, tile);

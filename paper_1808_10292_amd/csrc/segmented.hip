@@ -112,12 +112,20 @@ __global__ void k_zero_words(uint32_t* words, uint32_t count)
 // difference from the segment's first key, from round 0's count) into its
 // round plan: a round whose digit bits are zero there is the identity for the
 // segment and is skipped, with the rounds that run alternating between the
-// temporary and the output so that the last one writes the output.
+// temporary and the output so that the last one writes the output.  With a
+// device round count of 0 (dev_rounds) the caller writes the output itself:
+// no round runs and nothing is copied.
 __global__ void k_seg_plans(const uint32_t* seg_or, uint32_t nseg, uint32_t nrounds, int alias,
-                            RoundPlan* seg_plan)
+                            RoundPlan* seg_plan, const uint32_t* dev_rounds)
 {
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= nseg) return;
+    if (dev_rounds && *dev_rounds == 0) {
+        RoundPlan* pl = seg_plan + (size_t)s * (kMaxRounds + 1);
+        for (uint32_t d = 0; d < nrounds; ++d) pl[d] = RoundPlan{0, -1, 0, -1};
+        pl[kMaxRounds] = RoundPlan{0, 0, 0, 2};
+        return;
+    }
     const uint64_t mx = (uint64_t)seg_or[2 * s] | ((uint64_t)seg_or[2 * s + 1] << 32);
     int identity[kMaxRounds];
     for (uint32_t d = 0; d < nrounds; ++d) identity[d] = ((mx >> (8u * d)) & 0xFFull) == 0;
@@ -470,7 +478,8 @@ void run_large(const LargeArgs& L)
             hipLaunchKernelGGL((k_count<K, WG, ITEMS, true>), dim3(L.nt), dim3(WG), 0, L.stream, a, nullptr);
             a.seg_or = nullptr;
             hipLaunchKernelGGL(k_seg_plans, dim3((L.nls + 255) / 256), dim3(256), 0, L.stream,
-                               (const uint32_t*)L.seg_or, L.nls, nrounds, L.alias, L.seg_plan);
+                               (const uint32_t*)L.seg_or, L.nls, nrounds, L.alias, L.seg_plan,
+                               (const uint32_t*)nullptr);
         } else {
             hipLaunchKernelGGL((k_count<K, WG, ITEMS, false>), dim3(L.nt), dim3(WG), 0, L.stream, a, nullptr);
         }
@@ -740,6 +749,7 @@ hipError_t run_devseg(const void* keys_in, void* keys_out, const uint32_t* vals_
         a.tile_seg = tile_seg;
         a.seg_plan = seg_plan;
         a.lsegs = lsegs;
+        a.dev_rounds = dev_rounds;
         if (prof) profiler_mark(prof, stream, kKindCount, true);
         if (d == 0) {
             // round 0's count also takes the segments' identity words, from
@@ -748,7 +758,7 @@ hipError_t run_devseg(const void* keys_in, void* keys_out, const uint32_t* vals_
             hipLaunchKernelGGL((k_count<K, R8Config<K>::CWG, R8Config<K>::CITEMS, true>), dim3(L.max_tiles), dim3(R8Config<K>::CWG), 0, stream, a, nullptr);
             a.seg_or = nullptr;
             hipLaunchKernelGGL(k_seg_plans, dim3((nseg + 255) / 256), dim3(256), 0, stream,
-                               (const uint32_t*)seg_or, nseg, rounds, alias, seg_plan);
+                               (const uint32_t*)seg_or, nseg, rounds, alias, seg_plan, dev_rounds);
         } else {
             hipLaunchKernelGGL((k_count<K, R8Config<K>::CWG, R8Config<K>::CITEMS, false>), dim3(L.max_tiles), dim3(R8Config<K>::CWG), 0, stream, a, nullptr);
         }
