@@ -986,19 +986,21 @@ union MergeAux {
     MergeDigits d;
 };
 
-// Registers <- piece positions [c0, c0 + nc) in the ranking layout (position
-// c0 + hofs + 32 i in register i).  The run of every position is found
-// through a map: run k + 1 is marked at its first position in the chunk, and
-// a running maximum fills the positions after it.
+// Registers <- piece positions [c0, c0 + nc) in the ranking layout with ni
+// registers per half-wave (position c0 + hofs + 32 i in register i < ni).
+// The run of every position is found through a map: run k + 1 is marked at
+// its first position in the chunk, and a running maximum fills the positions
+// after it.
 template <bool KV>
 __device__ __forceinline__ void merge_gather(const uint32_t* __restrict__ X,
                                              const uint32_t* __restrict__ XV, uint32_t p,
                                              const MergeRuns& runs, uint16_t* mark, uint32_t* wsc,
                                              uint32_t c0, uint32_t nc,
-                                             uint32_t (&k)[kMergeItems], uint32_t (&v)[kMergeItems])
+                                             uint32_t (&k)[kMergeItems], uint32_t (&v)[kMergeItems],
+                                             uint32_t ni = kMergeItems)
 {
     const uint32_t tid = threadIdx.x;
-    const uint32_t hofs = (tid >> 5) * kMergeItems * 32 + (tid & 31);
+    const uint32_t hofs = (tid >> 5) * ni * 32 + (tid & 31);
     for (uint32_t j = tid; j < kMarkLen / 2; j += kMergeWG) ((uint32_t*)mark)[j] = 0;
     __syncthreads();
     if (tid < p) {
@@ -1027,7 +1029,7 @@ __device__ __forceinline__ void merge_gather(const uint32_t* __restrict__ X,
         const uint32_t u = hofs + i * 32;
         k[i] = 0;
         v[i] = 0;
-        if (u < nc) {
+        if ((uint32_t)i < ni && u < nc) {
             const uint32_t r = mark[mark_idx(u)] - 1u;
             const uint32_t q = runs.src[r] + (c0 + u - runs.off[r]);
             k[i] = X[q];
@@ -1110,7 +1112,6 @@ __global__ __launch_bounds__(kMergeWG, 4) void k_gsd_merge(const uint32_t* __res
     __shared__ uint32_t wsc[4];
     __shared__ uint32_t tot[2];
     const uint32_t tid = threadIdx.x;
-    const uint32_t hofs = (tid >> 5) * ITEMS * 32 + (tid & 31);
     // Piece of this workgroup.  The grid (a multiple of 8) is dealt to the 8
     // XCDs in turn; XCD x takes the x-th eighth of the pieces, so neighbouring
     // pieces, whose runs and outputs share cache lines, meet in one L2.
@@ -1126,9 +1127,13 @@ __global__ __launch_bounds__(kMergeWG, 4) void k_gsd_merge(const uint32_t* __res
         if (tid == 0) large[1 + atomicAdd(&large[0], 1u)] = m;
         return;
     }
+    // the piece spread over all half-waves: ni registers each
+    constexpr uint32_t HW = kMergeWG / 32;
+    const uint32_t ni = (L + 32 * HW - 1) / (32 * HW);
+    const uint32_t hofs = (tid >> 5) * ni * 32 + (tid & 31);
     uint16_t* mark = (uint16_t*)&smu.t.slot[0][0];   // run map in the ranking slots
     uint32_t k[ITEMS], v[ITEMS];
-    merge_gather<KV>(X, XV, p, runs, mark, wsc, 0, L, k, v);
+    merge_gather<KV>(X, XV, p, runs, mark, wsc, 0, L, k, v, ni);
     // word = (key - klo) << 12 | position with payloads (range < 2^20), or
     // key - klo without; a keys-only stable sort on the range bits
     constexpr uint32_t low = KV ? 12u : 0u;
@@ -1136,20 +1141,20 @@ __global__ __launch_bounds__(kMergeWG, 4) void k_gsd_merge(const uint32_t* __res
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const uint32_t u = hofs + i * 32;
-        if (KV && u < L) smu.vst[u] = v[i];
+        if (KV && (uint32_t)i < ni && u < L) smu.vst[u] = v[i];
         k[i] = ((k[i] - klo) << low) | (KV ? u : 0u);
     }
     const uint32_t nb = range ? 32u - __builtin_clz(range) : 0u;
 #pragma unroll 1
     for (uint32_t sh = 0; sh < nb; sh += 8) {
         const uint32_t w = min(8u, nb - sh);
-        tile_round<uint32_t, false, kMergeWG, ITEMS>(smu.t, k, v, L, low + sh, (1u << w) - 1u);
+        tile_round<uint32_t, false, kMergeWG, ITEMS>(smu.t, k, v, L, low + sh, (1u << w) - 1u, ni);
     }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const uint32_t u = hofs + i * 32;
-        if (u < L) {
+        if ((uint32_t)i < ni && u < L) {
             out[base + u] = klo + (k[i] >> low);
             if (KV) vout[base + u] = smu.vst[k[i] & 0xFFFu];
         }

@@ -3,8 +3,10 @@
 // placement) on up to WG * ITEMS keys, with digits of at most 8 bits.
 //
 // Register layout ("ranking layout"): half-wave h (32 lanes) owns tile
-// positions [h * ITEMS * 32, (h + 1) * ITEMS * 32); its lane l holds, in
-// register i, position h * ITEMS * 32 + 32 i + l.  Positions >= len are empty.
+// positions [h * NI * 32, (h + 1) * NI * 32); its lane l holds, in register
+// i < NI, position h * NI * 32 + 32 i + l.  Positions >= len, and registers
+// i >= NI, are empty.  NI (at most ITEMS) is ITEMS unless the caller spreads
+// a short tile over every half-wave: NI = ceil(len / (32 * half-waves)).
 //
 // A round: every half-wave counts its digits into its own 256 slots, the
 // slots are turned into the first output position of (half-wave, digit) in
@@ -53,7 +55,7 @@ struct TileSmem<K, KV, WG, ITEMS, true> {
 // hold the tile in that order.  Every thread of the workgroup must call it.
 template <typename K, bool KV, int WG, int ITEMS, bool SHARED>
 __device__ __forceinline__ bool tile_round(TileSmem<K, KV, WG, ITEMS, SHARED>& sm, K (&k)[ITEMS], uint32_t (&v)[ITEMS],
-                           uint32_t len, uint32_t shift, uint32_t mask)
+                           uint32_t len, uint32_t shift, uint32_t mask, uint32_t ni = ITEMS)
 {
     constexpr int HW = WG / 32;
     constexpr uint32_t R = kTileRadix;
@@ -62,7 +64,7 @@ __device__ __forceinline__ bool tile_round(TileSmem<K, KV, WG, ITEMS, SHARED>& s
     const uint32_t wave = tid >> 6;
     const uint32_t hw = tid >> 5;
     const uint32_t hl = tid & 31;
-    const uint32_t hofs = hw * ITEMS * 32 + hl;
+    const uint32_t hofs = hw * ni * 32 + hl;
 
     for (uint32_t i = tid; i < HW * R / 2; i += WG)
         ((uint4*)&sm.slot[0][0])[i] = make_uint4(0, 0, 0, 0);
@@ -71,6 +73,7 @@ __device__ __forceinline__ bool tile_round(TileSmem<K, KV, WG, ITEMS, SHARED>& s
     uint2* sl = sm.slot[hw];
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
+        if ((uint32_t)i >= ni) break;   // ni is uniform over the workgroup
         const bool ok = hofs + i * 32 < len;
         const uint32_t d = digit_of(k[i], shift, mask);
         if (wave_one_digit(ok, d)) {   // whole wave one digit: one add per half-wave
@@ -108,6 +111,7 @@ __device__ __forceinline__ bool tile_round(TileSmem<K, KV, WG, ITEMS, SHARED>& s
         const uint32_t lowsel = lane < 32 ? ~0u : 0u;
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
+            if ((uint32_t)i >= ni) break;
             const bool ok = hofs + i * 32 < len;
             const uint32_t d = digit_of(k[i], shift, mask);
             if (wave_one_digit(ok, d)) {   // whole wave one digit: ranks in lane order
@@ -136,7 +140,7 @@ __device__ __forceinline__ bool tile_round(TileSmem<K, KV, WG, ITEMS, SHARED>& s
     if constexpr (SHARED) __syncthreads();   // every slot read before keys overwrite them
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
-        if (hofs + i * 32 < len) {
+        if ((uint32_t)i < ni && hofs + i * 32 < len) {
             sm.keys[pos[i]] = k[i];
             if (KV) sm.vals[pos[i]] = v[i];
         }
@@ -145,7 +149,7 @@ __device__ __forceinline__ bool tile_round(TileSmem<K, KV, WG, ITEMS, SHARED>& s
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const uint32_t o = hofs + i * 32;
-        if (o < len) {
+        if ((uint32_t)i < ni && o < len) {
             k[i] = sm.keys[o];
             if (KV) v[i] = sm.vals[o];
         }
