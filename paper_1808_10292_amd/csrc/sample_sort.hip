@@ -1085,13 +1085,10 @@ __device__ __forceinline__ uint2 merge_key_bounds(const uint32_t* Sk, uint32_t g
 // key range spans.  Pieces beyond one LDS tile, and with
 // payloads pieces of a wider key range, are only listed here (large[0] =
 // count, large[1..] = pieces) for k_gsd_merge_large.
-// The ranking slots share LDS with the key staging.  With payloads the run
-// map stays in LDS of its own through the rounds and each payload is read at
-// the end, from its position in the sorted blocks (cache lines the gather of
-// the keys brought into L2): about 27 KiB per workgroup, five 4-wave
-// workgroups per CU.
+// The ranking slots share LDS with the key staging: with payloads about
+// 35 KiB per workgroup, four 4-wave workgroups per CU.
 template <bool KV>
-__global__ __launch_bounds__(kMergeWG, 5) void k_gsd_merge(const uint32_t* __restrict__ X,
+__global__ __launch_bounds__(kMergeWG, 4) void k_gsd_merge(const uint32_t* __restrict__ X,
                                                            const uint32_t* __restrict__ XV,
                                                            const uint32_t* lo, uint32_t p,
                                                            uint32_t M, uint32_t g,
@@ -1102,13 +1099,13 @@ __global__ __launch_bounds__(kMergeWG, 5) void k_gsd_merge(const uint32_t* __res
     constexpr int ITEMS = kMergeItems;
     constexpr uint32_t C = kMergeCap;
     static_assert(kMarkLen * 2 <= sizeof(uint2) * (kMergeWG / 32) * kTileRadix,
-                  "the run map fits the ranking slots");
-    // LDS: the keys-only ranking tile (keys only: the run map lives in its
-    // slots during the gather), with payloads followed by the run map
+                  "the run map lives in the ranking slots");
+    // LDS: the keys-only ranking tile, with payloads followed by the payloads
+    // staged by piece position
     using SmK = TileSmem<uint32_t, false, kMergeWG, ITEMS, true>;
     struct Packed {
         SmK t;
-        uint16_t mk[KV ? kMarkLen : 2];
+        uint32_t vst[KV ? C : 1];
     };
     __shared__ Packed smu;
     __shared__ MergeRuns runs;
@@ -1134,9 +1131,9 @@ __global__ __launch_bounds__(kMergeWG, 5) void k_gsd_merge(const uint32_t* __res
     constexpr uint32_t HW = kMergeWG / 32;
     const uint32_t ni = (L + 32 * HW - 1) / (32 * HW);
     const uint32_t hofs = (tid >> 5) * ni * 32 + (tid & 31);
-    uint16_t* mark = KV ? smu.mk : (uint16_t*)&smu.t.slot[0][0];
+    uint16_t* mark = (uint16_t*)&smu.t.slot[0][0];   // run map in the ranking slots
     uint32_t k[ITEMS], v[ITEMS];
-    merge_gather<false>(X, nullptr, p, runs, mark, wsc, 0, L, k, v, ni);
+    merge_gather<KV>(X, XV, p, runs, mark, wsc, 0, L, k, v, ni);
     // word = (key - klo) << 12 | position with payloads (range < 2^20), or
     // key - klo without; a keys-only stable sort on the range bits
     constexpr uint32_t low = KV ? 12u : 0u;
@@ -1144,6 +1141,7 @@ __global__ __launch_bounds__(kMergeWG, 5) void k_gsd_merge(const uint32_t* __res
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const uint32_t u = hofs + i * 32;
+        if (KV && (uint32_t)i < ni && u < L) smu.vst[u] = v[i];
         k[i] = ((k[i] - klo) << low) | (KV ? u : 0u);
     }
     const uint32_t nb = range ? 32u - __builtin_clz(range) : 0u;
@@ -1158,11 +1156,7 @@ __global__ __launch_bounds__(kMergeWG, 5) void k_gsd_merge(const uint32_t* __res
         const uint32_t u = hofs + i * 32;
         if ((uint32_t)i < ni && u < L) {
             out[base + u] = klo + (k[i] >> low);
-            if (KV) {   // the payload of piece position u0, from its run
-                const uint32_t u0 = k[i] & 0xFFFu;
-                const uint32_t r = mark[mark_idx(u0)] - 1u;
-                vout[base + u] = XV[runs.src[r] + (u0 - runs.off[r])];
-            }
+            if (KV) vout[base + u] = smu.vst[k[i] & 0xFFFu];
         }
     }
 }
