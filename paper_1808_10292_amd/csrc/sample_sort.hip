@@ -821,7 +821,7 @@ constexpr uint32_t kMergeWG = 256;
 constexpr int kMergeItems = 16;
 constexpr uint32_t kMergeCap = kMergeWG * kMergeItems;   // piece merged whole in LDS
 constexpr uint32_t kMergeMaxP = 256;                     // one run per thread
-constexpr uint32_t kMarkLen = kMergeCap + kMergeCap / 8; // padded run map (u16 entries)
+constexpr uint32_t kMarkLen = kMergeCap / 16 * 24;       // padded run map (u16 entries)
 
 // F[k][m] for m = 0..M+1, block-major (M + 2 per block).  Chunk c (8192 keys)
 // of sorted block k handles the boundaries whose rank in the block falls in
@@ -966,10 +966,11 @@ __device__ __forceinline__ uint32_t wave_inclusive_max(uint32_t x)
     return x;
 }
 
-// Run map index of piece position u: blocks of 16 u16 entries padded by one
-// dword, so thread t's block (entries 16 t .. 16 t + 15) starts at dword 9 t
-// and the 64 lanes of a wave hit 64 different banks.
-__device__ __forceinline__ uint32_t mark_idx(uint32_t u) { return u + 2 * (u >> 4); }
+// Run map index of piece position u: blocks of 16 u16 entries (8 dwords)
+// padded to 12 dwords, so thread t's block (entries 16 t .. 16 t + 15) is two
+// 16-byte vectors at byte 48 t, and the vectors of 16 consecutive threads
+// cover the 64 LDS banks once.  The map must be 16-byte aligned.
+__device__ __forceinline__ uint32_t mark_idx(uint32_t u) { return u + 8 * (u >> 4); }
 
 // LDS of the piece merge outside the ranking tile.
 struct MergeRuns {
@@ -1001,7 +1002,8 @@ __device__ __forceinline__ void merge_gather(const uint32_t* __restrict__ X,
 {
     const uint32_t tid = threadIdx.x;
     const uint32_t hofs = (tid >> 5) * ni * 32 + (tid & 31);
-    for (uint32_t j = tid; j < kMarkLen / 2; j += kMergeWG) ((uint32_t*)mark)[j] = 0;
+    static_assert(kMergeWG * 16 == kMergeCap && kMarkLen % 8 == 0, "16 map entries a thread");
+    for (uint32_t j = tid; j < kMarkLen / 8; j += kMergeWG) ((uint4*)mark)[j] = make_uint4(0, 0, 0, 0);
     __syncthreads();
     if (tid < p) {
         const uint32_t a = runs.off[tid], e = runs.off[tid + 1];
@@ -1009,9 +1011,13 @@ __device__ __forceinline__ void merge_gather(const uint32_t* __restrict__ X,
         if (s0 < e0) mark[mark_idx(s0 - c0)] = (uint16_t)(tid + 1);
     }
     __syncthreads();
+    // this thread's 16 entries, two to a dword
+    uint4* mb = (uint4*)(mark + mark_idx(16 * tid));
+    const uint4 m0 = mb[0], m1 = mb[1];
+    uint32_t w[8] = {m0.x, m0.y, m0.z, m0.w, m1.x, m1.y, m1.z, m1.w};
     uint32_t run = 0;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) run = max(run, (uint32_t)mark[mark_idx(16 * tid + j)]);
+    for (int q = 0; q < 8; ++q) run = max(run, max(w[q] & 0xFFFFu, w[q] >> 16));
     const uint32_t wmax = wave_inclusive_max(run);
     if ((tid & 63) == 63) wsc[tid >> 6] = wmax;
     __syncthreads();
@@ -1019,10 +1025,13 @@ __device__ __forceinline__ void merge_gather(const uint32_t* __restrict__ X,
     if ((tid & 63) == 0) cur = 0;
     for (uint32_t w = 0; w < (tid >> 6); ++w) cur = max(cur, wsc[w]);
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        cur = max(cur, (uint32_t)mark[mark_idx(16 * tid + j)]);
-        mark[mark_idx(16 * tid + j)] = (uint16_t)cur;
+    for (int q = 0; q < 8; ++q) {
+        const uint32_t lo16 = max(cur, w[q] & 0xFFFFu);
+        cur = max(lo16, w[q] >> 16);
+        w[q] = lo16 | (cur << 16);
     }
+    mb[0] = make_uint4(w[0], w[1], w[2], w[3]);
+    mb[1] = make_uint4(w[4], w[5], w[6], w[7]);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < kMergeItems; ++i) {
@@ -1107,7 +1116,7 @@ __global__ __launch_bounds__(kMergeWG, 4) void k_gsd_merge(const uint32_t* __res
         SmK t;
         uint32_t vst[KV ? C : 1];
     };
-    __shared__ Packed smu;
+    __shared__ alignas(16) Packed smu;
     __shared__ MergeRuns runs;
     __shared__ uint32_t wsc[4];
     __shared__ uint32_t tot[2];
@@ -1186,7 +1195,9 @@ __global__ __launch_bounds__(kMergeWG) void k_gsd_merge_large(
     const uint32_t varying = kb.x ^ kb.y;
     const uint2 lb = merge_setup(lo, p, M, F, m, aux.r, wsc, tot);
     const uint32_t L = lb.x, base = lb.y;
-    uint16_t* mark = (uint16_t*)&sm.slot[0][0];
+    // run map in the ranking slots, from their first 16-byte boundary
+    static_assert(kMarkLen * 2 + 16 <= sizeof(sm.slot), "the run map fits the ranking slots");
+    uint16_t* mark = (uint16_t*)(((uintptr_t)&sm.slot[0][0] + 15) & ~(uintptr_t)15);
     uint32_t k[ITEMS], v[ITEMS];
     for (uint32_t c0 = 0; c0 < L; c0 += C) {
         const uint32_t nc = min(C, L - c0);

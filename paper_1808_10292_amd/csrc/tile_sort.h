@@ -73,7 +73,7 @@ __device__ __forceinline__ bool tile_round(TileSmem<K, KV, WG, ITEMS, SHARED>& s
     uint2* sl = sm.slot[hw];
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
-        if ((uint32_t)i >= ni) break;   // ni is uniform over the workgroup
+        if ((uint32_t)i >= ni) continue;   // ni is uniform over the workgroup
         const bool ok = hofs + i * 32 < len;
         const uint32_t d = digit_of(k[i], shift, mask);
         if (wave_one_digit(ok, d)) {   // whole wave one digit: one add per half-wave
@@ -111,7 +111,7 @@ __device__ __forceinline__ bool tile_round(TileSmem<K, KV, WG, ITEMS, SHARED>& s
         const uint32_t lowsel = lane < 32 ? ~0u : 0u;
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
-            if ((uint32_t)i >= ni) break;
+            if ((uint32_t)i >= ni) continue;
             const bool ok = hofs + i * 32 < len;
             const uint32_t d = digit_of(k[i], shift, mask);
             if (wave_one_digit(ok, d)) {   // whole wave one digit: ranks in lane order
