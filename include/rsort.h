@@ -303,6 +303,31 @@ int rsort_segmented_tune(rsort_ctx* ctx, int key_type, const void* keys_in, void
                          uint32_t* best_split, double* best_ms);
 
 /*
+ * Tune cache of ctx: a text file (path copied; NULL or "" for none) of one
+ * JSON object per line, each a choice of rsort_segmented_tune keyed by the GPU
+ * architecture (e.g. gfx950), the key type, whether payloads move and the
+ * batch's size class (ceil(log2) of its total keys and of its segment count).
+ * With a cache set, rsort_segmented_tune first looks the batch's key up: on a
+ * hit (the last line with that key wins) it applies that choice, sorts the
+ * batch once with it and returns the stored split and time instead of tuning;
+ * otherwise it tunes and appends the choice.  Lines that do not parse, or
+ * choices this build cannot apply, are ignored, and a file that cannot be
+ * written is not an error: tuning simply happens again.  A new context takes
+ * the path in the environment variable RSORT_TUNE_CACHE, if set.
+ */
+int rsort_set_tune_cache(rsort_ctx* ctx, const char* path);
+
+/*
+ * Test hook for the out-of-memory paths: the k-th device allocation the
+ * library makes from now on (workspaces, error words, descriptor buffers; any
+ * context or server in the process) fails as out of memory, and the call that
+ * needed it returns RSORT_ENOMEM; k = 0 disarms the hook.  RSORT_FAULT_ALLOC=k
+ * in the environment arms it when the library first allocates.  RSORT_EINVAL
+ * for k < 0.
+ */
+int rsort_debug_fail_alloc(int k);
+
+/*
  * Deterministic regular-oversampling sample sort, GSD (Section 3.3,
  * Algorithm 1), of n uint32 keys (key_type must be RSORT_U32), stable, with
  * an optional payload.

@@ -3,8 +3,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
+#include <cstring>
 #include <mutex>
 #include <new>
 #include <string>
@@ -12,6 +15,7 @@
 
 #include "../../include/rsort.h"
 #include "rsort_internal.h"
+#include "tune_cache.h"
 
 namespace rsort {
 
@@ -144,6 +148,7 @@ struct rsort_ctx {
     // split statistics of the last sample sort (device), sized for p = kMaxP
     uint32_t* gsd_stats = nullptr;
     uint32_t gsd_p = 0;
+    std::string tune_cache;   // the tuner's persisted choices (empty: none)
     std::string last_error;
 };
 
@@ -231,7 +236,7 @@ int ensure_workspace(rsort_ctx* ctx, size_t need, void** ws)
         ctx->ws_bytes = 0;
     }
     size_t grow = std::max(need, (size_t)1 << 20);
-    hipError_t e = hipMalloc(&ctx->ws, grow);
+    hipError_t e = rsort::dev_malloc(&ctx->ws, grow);
     if (e != hipSuccess) {
         ctx->ws = nullptr;
         return hip_fail(ctx, e, "hipMalloc(workspace)");
@@ -320,7 +325,54 @@ int check_gsd_params(rsort_ctx* ctx, int key_type, int p, int q, int kind = rsor
 
 }  // namespace
 
+namespace rsort {
+
+namespace {
+// Allocations left up to and including the one that fails; 0: none fails.
+std::atomic<long> g_fail_alloc{0};
+std::once_flag g_fail_alloc_env;
+
+void fail_alloc_from_env()
+{
+    std::call_once(g_fail_alloc_env, [] {
+        const char* s = getenv("RSORT_FAULT_ALLOC");
+        const long k = s ? strtol(s, nullptr, 10) : 0;
+        if (k > 0) g_fail_alloc.store(k);
+    });
+}
+}  // namespace
+
+hipError_t dev_malloc(void** p, size_t bytes)
+{
+    fail_alloc_from_env();
+    long k = g_fail_alloc.load();
+    while (k > 0 && !g_fail_alloc.compare_exchange_weak(k, k - 1)) {
+    }
+    if (k == 1) {   // this call is the k-th
+        *p = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    return hipMalloc(p, bytes);
+}
+
+}  // namespace rsort
+
 extern "C" {
+
+int rsort_debug_fail_alloc(int k)
+{
+    if (k < 0) return RSORT_EINVAL;
+    rsort::fail_alloc_from_env();
+    rsort::g_fail_alloc.store(k);
+    return RSORT_OK;
+}
+
+int rsort_set_tune_cache(rsort_ctx* ctx, const char* path)
+{
+    if (!ctx) return RSORT_EINVAL;
+    ctx->tune_cache = path ? path : "";
+    return RSORT_OK;
+}
 
 int rsort_create(int hip_device, rsort_ctx** out)
 {
@@ -333,13 +385,14 @@ int rsort_create(int hip_device, rsort_ctx** out)
     if (!ctx) return RSORT_ENOMEM;
     ctx->device = hip_device;
     DeviceGuard g(hip_device);
-    if (hipMalloc(&ctx->dev_err, 256) != hipSuccess ||
+    if (rsort::dev_malloc((void**)&ctx->dev_err, 256) != hipSuccess ||
         hipMemset(ctx->dev_err, 0, 256) != hipSuccess) {
         if (ctx->dev_err) (void)hipFree(ctx->dev_err);
         delete ctx;
         return RSORT_ENOMEM;
     }
     ctx->scratch = scratch_address(hip_device);
+    if (const char* tc = getenv("RSORT_TUNE_CACHE")) ctx->tune_cache = tc;
     *out = ctx;
     return RSORT_OK;
 }
@@ -500,7 +553,7 @@ int run_skeleton(rsort_ctx* ctx, int key_type, const void* keys_in, void* keys_o
         if (hipStreamIsCapturing(st, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone)
             return fail(ctx, RSORT_EINVAL,
                         "first sample sort on a context cannot be captured (it allocates)");
-        hipError_t e = hipMalloc(&ctx->gsd_stats, rsort::gsd_stats_words(kMaxP) * 4);
+        hipError_t e = rsort::dev_malloc((void**)&ctx->gsd_stats, rsort::gsd_stats_words(kMaxP) * 4);
         if (e != hipSuccess) {
             ctx->gsd_stats = nullptr;
             return hip_fail(ctx, e, "hipMalloc(sample sort statistics)");
@@ -1108,6 +1161,44 @@ int rsort_segmented_tune(rsort_ctx* ctx, int key_type, const void* keys_in, void
                          double* best_ms)
 {
     if (!ctx || !best_split) return RSORT_EINVAL;
+    // A choice persisted for this architecture, key type, payload and batch
+    // size class is applied (the batch is still sorted once) instead of tuning.
+    rsort::TuneKey tkey;
+    memset(&tkey, 0, sizeof tkey);
+    const bool use_cache = !ctx->tune_cache.empty() && seg_offsets;
+    if (use_cache) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, ctx->device) != hipSuccess)
+            return fail(ctx, RSORT_EDEVICE, "hipGetDeviceProperties");
+        rsort::set_tune_arch(&tkey, prop.gcnArchName);
+        tkey.key_type = key_type;
+        tkey.payload = vals_in != nullptr;
+        tkey.log2_keys = rsort::ceil_log2(num_segs ? seg_offsets[num_segs] - seg_offsets[0] : 0);
+        tkey.log2_segs = rsort::ceil_log2(num_segs);
+        rsort::TuneEntry te;
+        if (rsort::lookup_tune_entry(ctx->tune_cache.c_str(), tkey, &te)) {
+            const uint32_t s0 = ctx->small_max;
+            const int k0 = ctx->small_sort, t0 = ctx->seg_tile_shape, l0 = ctx->seg_launch;
+            if (rsort_segmented_set_launch(ctx, te.launch) == RSORT_OK &&
+                rsort_segmented_set_split(ctx, te.split) == RSORT_OK &&
+                rsort_segmented_set_small_sort(ctx, te.small_sort) == RSORT_OK &&
+                rsort_segmented_set_tile(ctx, te.tile_threads) == RSORT_OK) {
+                int rc = rsort_segmented_sort(ctx, key_type, keys_in, keys_out, vals_in, vals_out,
+                                              seg_offsets, num_segs, nullptr, 0, stream);
+                if (rc == RSORT_OK) rc = rsort_synchronize(ctx, stream);
+                if (rc) return rc;
+                *best_split = te.split;
+                if (best_ms) *best_ms = te.ms;
+                return RSORT_OK;
+            }
+            // an entry this build cannot apply: tune as if there were none
+            ctx->small_max = s0;
+            ctx->small_sort = k0;
+            ctx->seg_tile_shape = t0;
+            ctx->seg_launch = l0;
+            ctx->last_error.clear();
+        }
+    }
     static const uint32_t cands[] = {0, 1024, 4096, 8192};
     static const int sorters[] = {RSORT_SMALL_RADIX, RSORT_SMALL_BTN, RSORT_SMALL_OET};
     if (reps < 1) reps = 3;
@@ -1171,6 +1262,17 @@ int rsort_segmented_tune(rsort_ctx* ctx, int key_type, const void* keys_in, void
     if (rc) return rc;
     *best_split = pick;
     if (best_ms) *best_ms = best;
+    if (use_cache) {   // a file that cannot be written only means tuning again next time
+        static const int threads[rsort::kSegTileShapes] = {256, 512, 1024};
+        rsort::TuneEntry te;
+        te.key = tkey;
+        te.split = pick;
+        te.small_sort = pick_sort;
+        te.tile_threads = threads[pick_shape];
+        te.launch = pick_launch;
+        te.ms = best;
+        (void)rsort::append_tune_entry(ctx->tune_cache.c_str(), te);
+    }
     return RSORT_OK;
 }
 

@@ -207,4 +207,11 @@ hipError_t map_keys(int key_bytes, int kind, bool inverse, const void* in, void*
 // Plain device copy used when a sort moves nothing (empty bit range).
 hipError_t copy_bytes(void* dst, const void* src, size_t bytes, hipStream_t stream);
 
+// Device memory for the library's own buffers (workspaces, error words,
+// descriptors).  hipMalloc, except that a test hook can make one allocation
+// fail as out of memory: rsort_debug_fail_alloc(k), or RSORT_FAULT_ALLOC=k in
+// the environment when the library first allocates, fails the k-th call from
+// then on.
+hipError_t dev_malloc(void** p, size_t bytes);
+
 }  // namespace rsort

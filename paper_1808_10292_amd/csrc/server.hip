@@ -172,7 +172,7 @@ hipError_t grow(void** p, size_t* have, size_t need)
     if (*p) (void)hipFree(*p);
     *p = nullptr;
     *have = 0;
-    hipError_t e = hipMalloc(p, need);
+    hipError_t e = dev_malloc(p, need);
     if (e == hipSuccess) *have = need;
     return e;
 }
@@ -198,7 +198,7 @@ int launch_batch(rsort_server* sv, Slot& sl)
             sl.desc_cap = 0;
             const size_t cap = std::max<size_t>(cnt, 1024);
             e = hipHostMalloc((void**)&sl.desc_host, cap * sizeof(ServeDesc), hipHostMallocDefault);
-            if (e == hipSuccess) e = hipMalloc((void**)&sl.desc_dev, cap * sizeof(ServeDesc));
+            if (e == hipSuccess) e = dev_malloc((void**)&sl.desc_dev, cap * sizeof(ServeDesc));
             if (e != hipSuccess) return RSORT_ENOMEM;
             sl.desc_cap = cap;
         }
@@ -357,10 +357,10 @@ int rsort_server_create(int hip_device, size_t hbm_cap_bytes, int num_streams, r
             // error word and the descriptors of the largest small-request batch,
             // so that the scheduling thread never allocates for them
             const size_t dbytes = rsort::kServeMaxBatch * sizeof(rsort::ServeDesc);
-            if (hipMalloc((void**)&sl.err_dev, 256) != hipSuccess ||
+            if (rsort::dev_malloc((void**)&sl.err_dev, 256) != hipSuccess ||
                 hipHostMalloc((void**)&sl.err_host, 256, hipHostMallocDefault) != hipSuccess ||
                 hipHostMalloc((void**)&sl.desc_host, dbytes, hipHostMallocDefault) != hipSuccess ||
-                hipMalloc((void**)&sl.desc_dev, dbytes) != hipSuccess) {
+                rsort::dev_malloc((void**)&sl.desc_dev, dbytes) != hipSuccess) {
                 rc = RSORT_ENOMEM;
                 break;
             }

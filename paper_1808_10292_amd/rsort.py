@@ -55,7 +55,8 @@ EXPORTED = ("rsort_create", "rsort_destroy", "rsort_status_string", "rsort_last_
             "rsort_segmented_workspace_bytes", "rsort_segmented_set_split",
             "rsort_segmented_tune", "rsort_segmented_set_small_sort",
             "rsort_segmented_get_small_sort", "rsort_segmented_set_tile",
-            "rsort_segmented_get_config", "rsort_segmented_set_launch", "rsort_sample_sort", "rsort_sample_sort_workspace_bytes",
+            "rsort_segmented_get_config", "rsort_segmented_set_launch", "rsort_set_tune_cache",
+            "rsort_debug_fail_alloc", "rsort_sample_sort", "rsort_sample_sort_workspace_bytes",
             "rsort_sample_sort_stats", "rsort_sample_sort_random",
             "rsort_sample_sort_random_workspace_bytes", "rsort_sample_sort_gvr",
             "rsort_sample_sort_gvr_workspace_bytes", "rsort_segmented_sort_device",
@@ -135,6 +136,8 @@ def load_library():
         lib.rsort_segmented_tune.argtypes = [vp, i, vp, vp, u32p, u32p, vp, sz, i, vp,
                                              ctypes.POINTER(ctypes.c_uint32),
                                              ctypes.POINTER(ctypes.c_double)]
+        lib.rsort_set_tune_cache.argtypes = [vp, ctypes.c_char_p]
+        lib.rsort_debug_fail_alloc.argtypes = [i]
         lib.rsort_sample_sort.argtypes = [vp, i, vp, vp, u32p, u32p, sz, i, i, vp, sz, vp]
         lib.rsort_sample_sort_workspace_bytes.argtypes = [vp, i, i, sz, i, i, ctypes.POINTER(sz)]
         lib.rsort_sample_sort_stats.argtypes = [vp, i, ctypes.POINTER(i), vp, vp, vp, vp]
@@ -546,6 +549,22 @@ def rsort_segmented_tune(keys_in, keys_out, seg_offsets, vals_in=None, vals_out=
                                        ctypes.byref(ms))
     ctx.check(rc, "rsort_segmented_tune")
     return split.value, ms.value
+
+
+def rsort_set_tune_cache(path, device=None):
+    """Tune cache file of the device's context (None: none); see include/rsort.h."""
+    ctx = context(device)
+    arg = None if path is None else os.fsencode(path)
+    ctx.check(ctx._lib.rsort_set_tune_cache(ctx.handle, arg), "rsort_set_tune_cache")
+
+
+def rsort_debug_fail_alloc(k):
+    """Make the k-th device allocation of the library from now on fail as out
+    of memory (0 disarms); a test hook for the error paths."""
+    lib = load_library()
+    rc = lib.rsort_debug_fail_alloc(int(k))
+    if rc:
+        raise RsortError(rc, "rsort_debug_fail_alloc")
 
 
 def _check_kv(keys_in, keys_out, vals_in, vals_out):
