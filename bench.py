@@ -489,14 +489,15 @@ def main():
     ap.add_argument("--kv-dists", default="uniform,low16,zipf,equal,presorted,reverse",
                     help="comma list of key distributions for the key-value leg "
                          "(uniform, low16, zipf, equal, presorted, reverse)")
-    ap.add_argument("--mode", choices=("sort", "copy", "pr2", "sample", "segmented"),
+    ap.add_argument("--mode", choices=("sort", "copy", "pr2", "sample", "segmented", "small"),
                     default="sort",
                     help="copy: time the library's plain device copy of the same bytes "
                          "(calibrates rocprofv3 byte counters against a known transfer); "
                          "pr2: time only the radix-65536 sort of the same keys; "
                          "sample: only GSD, GER and GVR on 2^kv-log2n uniform key-value pairs; "
                          "segmented: only the batched segmented sort of the 4096 lognormal "
-                         "arrays (these three for profiling)")
+                         "arrays; small: only the 2^20-key latency leg (these four for "
+                         "profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -516,6 +517,10 @@ def main():
         return
     if args.mode == "segmented":
         bench_segmented_only(rsort, torch, np, keygen, args)
+        return
+    if args.mode == "small":
+        res = bench_small(rsort, torch, np, keygen, args)
+        print(json.dumps(dict(mode="small", **res)), flush=True)
         return
     n = 1 << args.log2n
     log("generating %d keys" % n)
