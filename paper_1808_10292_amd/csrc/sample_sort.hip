@@ -573,7 +573,10 @@ __global__ __launch_bounds__(kRangeWG) void k_gvr_range(const uint32_t* Sk, uint
 // {lanes of the current row, keys of earlier rows} per 32-lane group (rows in
 // order); the tile is staged in LDS in bucket order with its bucket bytes and
 // written run by run, the payloads in a second staging pass.  A key of bucket
-// v is stored as key - shift[v].
+// v is stored as key - shift[v].  When no bucket needs a round (*rounds == 0:
+// each bucket holds one key value) and the output is not the input
+// (direct_ok), the route is the whole sort: keys and payloads go unchanged
+// straight to out / vout instead of Y / YV.
 template <bool KV>
 __global__ __launch_bounds__(kGvrWG) void k_gvr_scatter(const uint32_t* __restrict__ X,
                                                         const uint32_t* __restrict__ XV,
@@ -582,8 +585,15 @@ __global__ __launch_bounds__(kGvrWG) void k_gvr_scatter(const uint32_t* __restri
                                                         const uint32_t* counts,
                                                         const uint32_t* bases,
                                                         const uint32_t* shift, uint32_t n,
-                                                        uint32_t* Y, uint32_t* YV)
+                                                        uint32_t* Y, uint32_t* YV,
+                                                        const uint32_t* rounds, uint32_t direct_ok,
+                                                        uint32_t* out, uint32_t* vout)
 {
+    if (direct_ok && *rounds == 0) {
+        Y = out;
+        YV = vout;
+        shift = nullptr;
+    }
     constexpr int ITEMS = kGvrItems;
     constexpr uint32_t TILE = kGvrTile;
     struct Smem {
@@ -621,7 +631,7 @@ __global__ __launch_bounds__(kGvrWG) void k_gvr_scatter(const uint32_t* __restri
     for (uint32_t i = tid; i < kGvrGroups * R / 2; i += kGvrWG)
         ((uint4*)&sm.u.slot[0][0])[i] = make_uint4(0, 0, 0, 0);
     const uint32_t toff = tid < R ? counts[(size_t)t * R + tid] + bases[tid] : 0u;
-    if (tid < R) sm.sub[tid] = shift[tid];
+    if (tid < R) sm.sub[tid] = shift ? shift[tid] : 0u;
     __syncthreads();
 
     // rank within the group, rows in order
@@ -751,12 +761,12 @@ __global__ __launch_bounds__(kUnshiftWG) void k_gvr_unshift(uint32_t* keys_out, 
                                                             const uint32_t* boff,
                                                             const uint32_t* shift,
                                                             const uint32_t* rounds, uint32_t p,
-                                                            uint32_t n)
+                                                            uint32_t n, uint32_t direct_ok)
 {
     __shared__ uint32_t sb[kGvrMaxP + 1];
     __shared__ uint32_t sh[kGvrMaxP];
     const uint32_t nr = *rounds;
-    if (nr >= 4) return;
+    if (nr >= 4 || (nr == 0 && direct_ok)) return;   // keys unchanged, or routed to the output
     const uint32_t tid = threadIdx.x;
     for (uint32_t j = tid; j <= p; j += kUnshiftWG) sb[j] = boff[j];
     if (tid < p) sh[tid] = shift[tid];
@@ -1455,12 +1465,18 @@ hipError_t gvr_sort(const uint32_t* keys_in, uint32_t* keys_out, const uint32_t*
     a.tickets = ticket;
     a.err = dev_err;
     hipLaunchKernelGGL(k_tilescan, dim3((uint32_t)nblocks), dim3(R), 0, stream, a);
+    // with no round to run the route may write the output itself, unless it
+    // would overwrite keys or payloads other workgroups have yet to read
+    const uint32_t direct_ok = (const void*)keys_out != (const void*)keys_in &&
+                               (!vals_in || (const void*)vals_out != (const void*)vals_in);
     if (vals_in)
         hipLaunchKernelGGL(k_gvr_scatter<true>, dim3(nt), dim3(kGvrWG), 0, stream, keys_in,
-                           vals_in, lo, tpb, bkt, counts, bases, shift, (uint32_t)n, Y, YV);
+                           vals_in, lo, tpb, bkt, counts, bases, shift, (uint32_t)n, Y, YV,
+                           (const uint32_t*)rounds, direct_ok, keys_out, vals_out);
     else
         hipLaunchKernelGGL(k_gvr_scatter<false>, dim3(nt), dim3(kGvrWG), 0, stream, keys_in,
-                           nullptr, lo, tpb, bkt, counts, bases, shift, (uint32_t)n, Y, nullptr);
+                           nullptr, lo, tpb, bkt, counts, bases, shift, (uint32_t)n, Y, nullptr,
+                           (const uint32_t*)rounds, direct_ok, keys_out, nullptr);
     hipLaunchKernelGGL(k_gvr_stats, dim3(p), dim3(R), 0, stream, counts, bases, (uint32_t)n, p, s,
                        tpb, Sk, Sg, boff, bnd, split_key, split_g);
     e = hipGetLastError();
@@ -1473,10 +1489,10 @@ hipError_t gvr_sort(const uint32_t* keys_in, uint32_t* keys_out, const uint32_t*
     const dim3 ug((uint32_t)((n + kUnshiftTile - 1) / kUnshiftTile));
     if (vals_in)
         hipLaunchKernelGGL(k_gvr_unshift<true>, ug, dim3(kUnshiftWG), 0, stream, keys_out,
-                           vals_out, Y, YV, boff, shift, rounds, p, (uint32_t)n);
+                           vals_out, Y, YV, boff, shift, rounds, p, (uint32_t)n, direct_ok);
     else
         hipLaunchKernelGGL(k_gvr_unshift<false>, ug, dim3(kUnshiftWG), 0, stream, keys_out,
-                           nullptr, Y, nullptr, boff, shift, rounds, p, (uint32_t)n);
+                           nullptr, Y, nullptr, boff, shift, rounds, p, (uint32_t)n, direct_ok);
     return hipGetLastError();
 }
 

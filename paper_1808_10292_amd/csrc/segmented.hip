@@ -646,8 +646,11 @@ __global__ __launch_bounds__(kPlanWG) void k_devseg_plan(const uint32_t* off, ui
         return;
     }
     // the large segments' rounds: the low digits the keys can differ in
-    // (dev_rounds, when given), so the last one still writes the output
+    // (dev_rounds, when given), so the last one still writes the output; with
+    // none the caller writes the output itself, so no segment is sorted whole
+    // either
     const uint32_t rounds = dev_rounds ? min(key_rounds, *dev_rounds) : key_rounds;
+    const bool none = dev_rounds && rounds == 0;
     if (tid <= (uint32_t)kMaxRounds) {
         RoundPlan r{0, -1, 0, -1};
         if (tid < rounds) {
@@ -670,7 +673,7 @@ __global__ __launch_bounds__(kPlanWG) void k_devseg_plan(const uint32_t* off, ui
             nt = len > small_max ? (len + tile - 1) / tile : 0u;
             // class c takes len in (cap[c-1], cap[c]]; other classes see an empty segment
             uint32_t cls = 3;
-            if (len && len <= small_max)
+            if (len && len <= small_max && !none)
                 for (uint32_t k = 0; k < 3; ++k)
                     if (len <= (uint32_t)(kSmallClasses[k].wg * kSmallClasses[k].items)) { cls = k; break; }
             for (uint32_t k = 0; k < 3; ++k)

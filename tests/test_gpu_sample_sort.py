@@ -355,6 +355,9 @@ def _span_keys(case, n, seed):
 @pytest.mark.parametrize("case,p,with_vals,in_place,offset", [
     ("one_value", 16, True, False, 0),
     ("one_value", 16, False, True, 0),
+    ("one_value", 256, True, False, 0),
+    ("one_value", 256, True, True, 0),
+    ("one_value", 256, False, False, 2),
     ("one_value_max", 7, True, False, 1),
     ("top_byte_span", 4, True, False, 0),
     ("top_byte_span", 1, False, False, 3),
@@ -369,8 +372,9 @@ def _span_keys(case, n, seed):
 ])
 def test_gvr_bucket_spans(rs, case, p, with_vals, in_place, offset):
     """The route stores key - lo_j and the bucket sort runs only the digits of
-    the widest bucket span: no round (one key value: the routed keys are
-    copied), one, two, three (keys below 2^24 in 4 buckets) or four (spread
+    the widest bucket span: no round (one key value: the route writes the
+    output itself, or in place the routed keys are copied; with p = 256 the
+    buckets are below the small-segment limit), one, two, three (keys below 2^24 in 4 buckets) or four (spread
     keys: the keys are routed unchanged), including the extreme keys 0 and 2^32 - 1, unaligned
     outputs (scalar path) and a ragged tail; buckets above the small-segment
     limit take the tiled rounds."""
