@@ -187,3 +187,63 @@ def test_forced_allocation_failure_in_server_create(rs):
         assert np.array_equal(host(ko), np.sort(keys, kind="stable"))
     finally:
         srv.destroy()
+
+
+def test_tune_cache_path_from_environment(rs, tmp_path, monkeypatch):
+    """A context made while RSORT_TUNE_CACHE is set writes its tuner's choice there."""
+    import torch
+    path = str(tmp_path / "env_tune.jsonl")
+    lib = rs.load_library()
+    sizes = [3000, 9000, 40000, 1, 0, 12345]
+    off = keygen.offsets_from_sizes(sizes)
+    n = int(off[-1])
+    keys = keygen.uniform_u64(n, 96)
+    want, _ = oracle.segmented(keys, None, off)
+    dk = dev(keys)
+    ko = torch.zeros_like(dk)
+    monkeypatch.setenv("RSORT_TUNE_CACHE", path)
+    h = ctypes.c_void_p()
+    assert lib.rsort_create(0, ctypes.byref(h)) == 0
+    try:
+        split, ms = ctypes.c_uint32(), ctypes.c_double()
+        offs = np.ascontiguousarray(off, dtype=np.uint64)
+        announce("tune cache from environment, u64", n)
+        rc = lib.rsort_segmented_tune(h, 1, ctypes.c_void_p(dk.data_ptr()),
+                                      ctypes.c_void_p(ko.data_ptr()), None, None,
+                                      ctypes.c_void_p(offs.ctypes.data), len(sizes), 1, None,
+                                      ctypes.byref(split), ctypes.byref(ms))
+        assert rc == 0
+        assert np.array_equal(host(ko), want)
+        got = lines(path)
+        assert len(got) == 1
+        e = json.loads(got[0])
+        assert (e["key_type"], e["payload"], e["split"]) == (1, 0, split.value)
+    finally:
+        lib.rsort_destroy(h)
+
+
+def test_fault_alloc_from_environment():
+    """RSORT_FAULT_ALLOC=1 in a fresh process: its first device allocation (the
+    context's error word) fails as out of memory, the next context works."""
+    import os
+    import subprocess
+    import sys
+    code = (
+        "from paper_1808_10292_amd import rsort\n"
+        "try:\n"
+        "    rsort.Context(0)\n"
+        "    print('created')\n"
+        "except rsort.RsortError as e:\n"
+        "    print('status', e.status)\n"
+        "c = rsort.Context(0)\n"
+        "print('second ok', bool(c.handle))\n"
+    )
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, RSORT_FAULT_ALLOC="1")
+    announce("fault alloc from environment (subprocess)")
+    p = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300,
+                       env=env, cwd=root)
+    assert p.returncode == 0, p.stderr[-2000:]
+    out = p.stdout.split()
+    assert "status" in out and out[out.index("status") + 1] == "-2", p.stdout
+    assert "second" in out and out[-1] == "True", p.stdout
