@@ -48,7 +48,7 @@ enum rsort_status {
     RSORT_ENOMEM = -2,        /* device allocation failed                          */
     RSORT_EDEVICE = -3,       /* a HIP call or a kernel failed                     */
     RSORT_EBUSY = -4,         /* resource in use                                   */
-    RSORT_EUNSUPPORTED = -5   /* valid request outside this build's limits         */
+    RSORT_EUNSUPPORTED = -5   /* valid request outside the library's limits        */
 };
 
 enum rsort_key_type {
@@ -311,7 +311,7 @@ int rsort_segmented_tune(rsort_ctx* ctx, int key_type, const void* keys_in, void
  * hit (the last line with that key wins) it applies that choice, sorts the
  * batch once with it and returns the stored split and time instead of tuning;
  * otherwise it tunes and appends the choice.  Lines that do not parse, or
- * choices this build cannot apply, are ignored, and a file that cannot be
+ * choices this library version cannot apply, are ignored, and a file that cannot be
  * written is not an error: tuning simply happens again.  A new context takes
  * the path in the environment variable RSORT_TUNE_CACHE, if set.
  */

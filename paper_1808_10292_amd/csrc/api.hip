@@ -1191,7 +1191,7 @@ int rsort_segmented_tune(rsort_ctx* ctx, int key_type, const void* keys_in, void
                 if (best_ms) *best_ms = te.ms;
                 return RSORT_OK;
             }
-            // an entry this build cannot apply: tune as if there were none
+            // an entry the library cannot apply (another version): tune as if there were none
             ctx->small_max = s0;
             ctx->small_sort = k0;
             ctx->seg_tile_shape = t0;

@@ -74,7 +74,7 @@ def test_tune_cache_miss_hit_and_bad_entries(rs, tmp_path):
         assert np.array_equal(host(ko), want)
         assert len(lines(path)) == 1
 
-        # a damaged line and a later entry this build cannot apply (a tile of
+        # a damaged line and a later entry the library cannot apply (a tile of
         # 300 threads): both ignored, so the batch is tuned again and appended
         bad = dict(e, tile_threads=300)
         with open(path, "a") as f:
