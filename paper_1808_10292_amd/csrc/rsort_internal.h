@@ -171,12 +171,12 @@ struct GsdLayout {
     DevSegLayout LS;            // local sort and bucket finish
     size_t off_lo, off_boff, off_bsize, off_coloff, off_Tk, off_Tg, off_Sk, off_Sg, off_lsd,
         off_Y, off_YV, off_seg;
-    // GSD step 5 as a merge (p <= 256): pieces cut at every g-th element of
-    // a sorted regular sample of the sorted blocks (GSD: its own sample; GER:
-    // a second one, s2 per block, sorted with LT2), M boundaries, F = (M + 2)
-    // x p run bounds
+    // GSD step 5 as a merge (p <= 256): pieces cut at a sorted regular sample
+    // of the sorted blocks (GSD: its own sample; GER: a second one, s2 per
+    // block, sorted with LT2; GSD's s2 is s), each of its p intervals of s2
+    // elements cut into q parts: M = p q boundaries, F = (M + 2) x p run bounds
     bool merge;
-    uint32_t g, M, s2;
+    uint32_t q, M, s2;
     size_t nT2;
     LsdR8Layout LT2;
     size_t off_F, off_BK, off_large, off_R;

@@ -41,6 +41,7 @@
 // into bucket order (X_{k,j} for k = 0..p-1 concatenated is bucket j).  The
 // finish sorts every bucket as above.  p <= 256: one 8-bit routing digit.
 #include <algorithm>
+#include <cmath>
 #include <type_traits>
 
 #include "lsd_kernels.h"
@@ -814,10 +815,13 @@ __global__ __launch_bounds__(kUnshiftWG) void k_gvr_unshift(uint32_t* keys_out, 
 
 // ---------------------------------------------------------------------------
 // GSD step 5 as a merge of the p sorted runs of every bucket (also GER's).
-// A sorted sample T of the sorted blocks gives boundaries B_m = T[m g - 1],
-// m = 1..M (M = |T| / g): GSD's own regular sample, with g dividing s so that
-// its splitters S_i = B_{i s / g} are among them; for GER the boundary sample
-// of k_merge_sample (its own random sample gives unevenly sized pieces).
+// A sorted sample T of the sorted blocks, p intervals of sT elements, gives
+// boundaries B_m = T[c(m) - 1], m = 1..M: each interval is cut into q
+// near-equal parts (M = p q, c(m) = (m / q) sT + (m mod q) sT / q), so that
+// B_{i q} = T[i sT - 1] ends interval i.  GSD uses its own regular sample
+// (sT = s), whose splitters S_i = T[i s - 1] = B_{i q} are thus among the
+// boundaries; GER the boundary sample of k_merge_sample (its own random
+// sample gives unevenly sized pieces).
 // Piece m (m = 0..M)
 // holds the elements whose composite lies in (B_m, B_{m+1}] (B_0 = -inf,
 // B_{M+1} = +inf): from every sorted block k the positions [F[k][m],
@@ -825,8 +829,8 @@ __global__ __launch_bounds__(kUnshiftWG) void k_gvr_unshift(uint32_t* keys_out, 
 // cover the output in order, piece m from sum_k F[k][m] on, and a piece is the
 // merge of its p sorted sub-runs; the buckets are unions of consecutive
 // pieces' sub-runs, so merging piece by piece merges every bucket.  By Lemma
-// 1's argument a piece holds at most (g + p - 1) x keys (x = block keys per
-// sample); g is chosen so that the average is about 2048.
+// 1's argument a piece holds at most (ceil(sT / q) + p - 1) x keys (x = block
+// keys per sample); q is chosen so that the average is about 2560.
 constexpr uint32_t kMergeWG = 256;
 constexpr int kMergeItems = 16;
 constexpr uint32_t kMergeCap = kMergeWG * kMergeItems;   // piece merged whole in LDS
@@ -839,12 +843,21 @@ constexpr uint32_t kMarkLen = kMergeCap / 16 * 24;       // padded run map (u16 
 // condition; last: no upper one); every block key is read once.
 constexpr uint32_t kFineChunk = 8192;
 
+// Sample elements up to and including boundary m (1 <= m <= p q, q <= sT).
+__device__ __forceinline__ size_t bound_count(uint32_t m, uint32_t sT, uint32_t q)
+{
+    return (size_t)(m / q) * sT + (size_t)(m % q) * sT / q;
+}
+
 // BK[m - 1] = B_m as one 64-bit composite (key << 32 | index), m = 1..M.
-__global__ void k_gsd_bounds(const uint32_t* Sk, const uint32_t* Sg, uint32_t g, uint32_t M,
-                             uint64_t* BK)
+__global__ void k_gsd_bounds(const uint32_t* Sk, const uint32_t* Sg, uint32_t sT, uint32_t q,
+                             uint32_t M, uint64_t* BK)
 {
     const uint32_t m = blockIdx.x * blockDim.x + threadIdx.x + 1;
-    if (m <= M) BK[m - 1] = ((uint64_t)Sk[(size_t)m * g - 1] << 32) | Sg[(size_t)m * g - 1];
+    if (m <= M) {
+        const size_t c = bound_count(m, sT, q) - 1;
+        BK[m - 1] = ((uint64_t)Sk[c] << 32) | Sg[c];
+    }
 }
 
 // Index (0..M) of the first boundary not below composite x: BK[i] >= x.
@@ -948,16 +961,16 @@ __global__ __launch_bounds__(256) void k_gsd_fine_split(const uint32_t* __restri
     }
 }
 
-// GSD: split bounds of the p buckets (bnd[k][i] = F[k][i s / g]: the
-// splitters are boundaries) and the splitters, for the statistics.
-__global__ void k_gsd_fine_bnd(const uint32_t* F, uint32_t p, uint32_t s, uint32_t g, uint32_t M,
+// GSD: split bounds of the p buckets (bnd[k][i] = F[k][i q]: the splitters
+// are boundaries) and the splitters, for the statistics.
+__global__ void k_gsd_fine_bnd(const uint32_t* F, uint32_t p, uint32_t s, uint32_t q, uint32_t M,
                                const uint32_t* Sk, const uint32_t* Sg, uint32_t* bnd,
                                uint32_t* split_key, uint32_t* split_g)
 {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= p * (p + 1)) return;
     const uint32_t k = t / (p + 1), i = t - k * (p + 1);
-    const uint32_t row = i == p ? M + 1 : i * (s / g);
+    const uint32_t row = i == p ? M + 1 : i * q;
     bnd[t] = F[(size_t)k * (M + 2) + row];
     if (k == 0 && i > 0 && i < p) {
         split_key[i - 1] = Sk[(size_t)i * s - 1];
@@ -1087,11 +1100,11 @@ __device__ __forceinline__ uint2 merge_setup(const uint32_t* lo, uint32_t p, uin
 }
 
 // Key bounds of piece m: its keys lie between the keys of its two boundaries.
-__device__ __forceinline__ uint2 merge_key_bounds(const uint32_t* Sk, uint32_t g, uint32_t M,
-                                                  uint32_t m)
+__device__ __forceinline__ uint2 merge_key_bounds(const uint32_t* Sk, uint32_t sT, uint32_t q,
+                                                  uint32_t M, uint32_t m)
 {
-    return make_uint2(m == 0 ? 0u : Sk[(size_t)m * g - 1],
-                      m == M ? 0xFFFFFFFFu : Sk[(size_t)(m + 1) * g - 1]);
+    return make_uint2(m == 0 ? 0u : Sk[bound_count(m, sT, q) - 1],
+                      m == M ? 0xFFFFFFFFu : Sk[bound_count(m + 1, sT, q) - 1]);
 }
 
 // One workgroup per piece: the p sub-runs are read in run order (block order,
@@ -1110,7 +1123,7 @@ template <bool KV>
 __global__ __launch_bounds__(kMergeWG, 4) void k_gsd_merge(const uint32_t* __restrict__ X,
                                                            const uint32_t* __restrict__ XV,
                                                            const uint32_t* lo, uint32_t p,
-                                                           uint32_t M, uint32_t g,
+                                                           uint32_t M, uint32_t sT, uint32_t q,
                                                            const uint32_t* Sk, const uint32_t* F,
                                                            uint32_t* out, uint32_t* vout,
                                                            uint32_t* large)
@@ -1137,7 +1150,7 @@ __global__ __launch_bounds__(kMergeWG, 4) void k_gsd_merge(const uint32_t* __res
     const uint32_t per = gridDim.x >> 3, x = blockIdx.x & 7, j = blockIdx.x >> 3;
     const uint32_t m = x * per + j;
     if (m > M) return;
-    const uint2 kb = merge_key_bounds(Sk, g, M, m);
+    const uint2 kb = merge_key_bounds(Sk, sT, q, M, m);
     const uint32_t klo = kb.x, khi = kb.y;
     const uint2 lb = merge_setup(lo, p, M, F, m, runs, wsc, tot);
     const uint32_t L = lb.x, base = lb.y;
@@ -1188,7 +1201,7 @@ __global__ __launch_bounds__(kMergeWG, 4) void k_gsd_merge(const uint32_t* __res
 template <bool KV>
 __global__ __launch_bounds__(kMergeWG) void k_gsd_merge_large(
     const uint32_t* __restrict__ X, const uint32_t* __restrict__ XV, const uint32_t* lo,
-    uint32_t p, uint32_t M, uint32_t g, const uint32_t* Sk, const uint32_t* F, uint32_t* out,
+    uint32_t p, uint32_t M, uint32_t sT, uint32_t q, const uint32_t* Sk, const uint32_t* F, uint32_t* out,
     uint32_t* vout, uint32_t* tmp, uint32_t* vtmp, const uint32_t* large)
 {
     constexpr int ITEMS = kMergeItems;
@@ -1201,7 +1214,7 @@ __global__ __launch_bounds__(kMergeWG) void k_gsd_merge_large(
     const uint32_t m = large[1 + blockIdx.x];
     const uint32_t tid = threadIdx.x;
     const uint32_t hofs = (tid >> 5) * ITEMS * 32 + (tid & 31);
-    const uint2 kb = merge_key_bounds(Sk, g, M, m);
+    const uint2 kb = merge_key_bounds(Sk, sT, q, M, m);
     const uint32_t varying = kb.x ^ kb.y;
     const uint2 lb = merge_setup(lo, p, M, F, m, aux.r, wsc, tot);
     const uint32_t L = lb.x, base = lb.y;
@@ -1347,22 +1360,16 @@ GsdLayout skeleton_layout(bool has_vals, size_t n, uint32_t p, uint32_t s, size_
     L.off_YV = o;    o = align_up(o + (has_vals ? n * 4 : 0));
     L.off_seg = o;   o = align_up(o + L.LS.bytes);
     if ((kind == kGSD || kind == kGER) && p <= kMergeMaxP && L.nT2 && n <= L.nT2 * 4096) {
-        // the merge finish: every g-th sample element, g n / nT2 at most about
-        // 2048 (GSD) or 2560 (GER) keys per piece (g >= 1), at least one
-        // boundary (g <= nT2), and for GSD g dividing s.  GER's boundary
-        // sample is its own, so its pieces need not match a splitter spacing:
-        // at 2^28 pairs its merge measured fastest with pieces of 2304 to 2816
-        // keys (4 % below 2048; 3072 slower again, more pieces above one tile)
+        // the merge finish: each interval of s2 sample elements cut into q
+        // parts (1 <= q <= s2) of about 2560 keys; at 2^28 pairs GER's merge
+        // measured fastest with pieces of 2304 to 2816 keys (4 % below 2048;
+        // 3072 slower again, more pieces above one tile)
         L.merge = true;
-        const uint64_t piece = kind == kGER ? 2560 : 2048;
-        const uint64_t want = std::max<uint64_t>(1, piece * L.nT2 / n);
-        uint32_t g = (uint32_t)std::min<uint64_t>(want, L.nT2);
-        if (kind == kGSD) {
-            g = std::min(g, s);
-            while (s % g) --g;
-        }
-        L.g = g;
-        L.M = (uint32_t)(L.nT2 / g);
+        // sample elements per piece for about 2560 keys, then parts per interval
+        const double per_piece = std::max(1.0, 2560.0 * (double)L.nT2 / (double)n);
+        const double parts = std::floor((double)L.s2 / per_piece + 0.5);
+        L.q = (uint32_t)std::min<double>(L.s2, std::max(1.0, parts));
+        L.M = p * L.q;
         L.off_F = o;       o = align_up(o + ((size_t)L.M + 2) * p * 4);
         L.off_BK = o;      o = align_up(o + (size_t)L.M * 8);
         L.off_large = o;   o = align_up(o + ((size_t)L.M + 2) * 4);
@@ -1510,7 +1517,7 @@ hipError_t gsd_merge_sort(const uint32_t* keys_in, uint32_t* keys_out, const uin
                           uint32_t* split_key, uint32_t* split_g, uint32_t* dev_err,
                           hipStream_t stream, Profiler* prof)
 {
-    const uint32_t p = L.p, s = L.s, g = L.g, M = L.M;
+    const uint32_t p = L.p, s = L.s, sT = L.s2, q = L.q, M = L.M;
     uint32_t* F = (uint32_t*)(w + L.off_F);
     uint8_t* seg_ws = w + L.off_seg;
     uint32_t* tmp = (uint32_t*)(seg_ws + L.LS.off_tmp_keys);
@@ -1542,7 +1549,7 @@ hipError_t gsd_merge_sort(const uint32_t* keys_in, uint32_t* keys_out, const uin
     if (e != hipSuccess) return e;
     // 4. splitters, the fine split, the buckets' split bounds
     uint64_t* BK = (uint64_t*)(w + L.off_BK);
-    hipLaunchKernelGGL(k_gsd_bounds, dim3((M + 255) / 256), dim3(256), 0, stream, Sk, Sg, g, M, BK);
+    hipLaunchKernelGGL(k_gsd_bounds, dim3((M + 255) / 256), dim3(256), 0, stream, Sk, Sg, sT, q, M, BK);
     const uint32_t chunks = (uint32_t)std::max<size_t>(1, ((n + p - 1) / p + kFineChunk - 1) / kFineChunk);
     uint32_t* R = (uint32_t*)(w + L.off_R);
     const uint32_t nr = p * (chunks + 2);
@@ -1551,7 +1558,7 @@ hipError_t gsd_merge_sort(const uint32_t* keys_in, uint32_t* keys_out, const uin
     hipLaunchKernelGGL(k_gsd_fine_split, dim3(chunks, p), dim3(256), 0, stream, Y, lo, p, M, chunks,
                        BK, R, F);
     if (L.kind == kGSD)
-        hipLaunchKernelGGL(k_gsd_fine_bnd, dim3((nb + 255) / 256), dim3(256), 0, stream, F, p, s, g,
+        hipLaunchKernelGGL(k_gsd_fine_bnd, dim3((nb + 255) / 256), dim3(256), 0, stream, F, p, s, q,
                            M, Sk, Sg, bnd, split_key, split_g);
     // 5. merge every piece into the output
     uint32_t* large = (uint32_t*)(w + L.off_large);
@@ -1559,15 +1566,15 @@ hipError_t gsd_merge_sort(const uint32_t* keys_in, uint32_t* keys_out, const uin
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, stream, large, 1u, 0u);
     const dim3 mg((M + 1 + 7) & ~7u);
     if (vals_in) {
-        hipLaunchKernelGGL(k_gsd_merge<true>, mg, dim3(kMergeWG), 0, stream, Y, YV, lo, p, M, g, Sk,
+        hipLaunchKernelGGL(k_gsd_merge<true>, mg, dim3(kMergeWG), 0, stream, Y, YV, lo, p, M, sT, q, Sk,
                            F, keys_out, vals_out, large);
         hipLaunchKernelGGL(k_gsd_merge_large<true>, dim3(max_large), dim3(kMergeWG), 0, stream, Y,
-                           YV, lo, p, M, g, Sk, F, keys_out, vals_out, tmp, vtmp, large);
+                           YV, lo, p, M, sT, q, Sk, F, keys_out, vals_out, tmp, vtmp, large);
     } else {
         hipLaunchKernelGGL(k_gsd_merge<false>, mg, dim3(kMergeWG), 0, stream, Y, nullptr, lo, p, M,
-                           g, Sk, F, keys_out, nullptr, large);
+                           sT, q, Sk, F, keys_out, nullptr, large);
         hipLaunchKernelGGL(k_gsd_merge_large<false>, dim3(max_large), dim3(kMergeWG), 0, stream, Y,
-                           nullptr, lo, p, M, g, Sk, F, keys_out, nullptr, tmp, nullptr, large);
+                           nullptr, lo, p, M, sT, q, Sk, F, keys_out, nullptr, tmp, nullptr, large);
     }
     return hipGetLastError();
 }
